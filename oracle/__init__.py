@@ -1,0 +1,230 @@
+"""FP64 CPU oracle for the ALI-FMM travel-time method (arXiv 2302.10988).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline leg of
+the benchmark may import this package; the GPU product path never does.  The C sources
+here share no code with the HIP kernels.
+
+Every function follows the paper section cited in its docstring.  Inputs are numpy
+arrays; orientations are symmetry-axis angles in radians (from +x toward +z), materials
+are dicts/tuples (c11, c13, c33, c55, c44, c66, rho) in Pa and kg/m^3.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SOURCES = ["velocity.c", "fmm.c", "dijkstra.c", "rays.c", "adjoint.c"]
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+class Material(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("c11", "c13", "c33", "c55", "c44", "c66", "rho")]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
+    hdr = os.path.join(_HERE, "ali_oracle.h")
+    if not force and os.path.exists(_LIB_PATH):
+        newest = max(os.path.getmtime(p) for p in srcs + [hdr])
+        if os.path.getmtime(_LIB_PATH) >= newest:
+            return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-std=c11", "-D_DEFAULT_SOURCE", "-O2", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    D, I, I64 = ctypes.c_double, ctypes.c_int, ctypes.c_int64
+    P = ctypes.c_void_p
+    M = ctypes.POINTER(Material)
+    lib.or_qp_phase_speed.argtypes = [M, D]
+    lib.or_qp_phase_speed.restype = D
+    lib.or_qp_group_from_phase.argtypes = [M, D, ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.or_qp_group_speed.argtypes = [M, D]
+    lib.or_qp_group_speed.restype = D
+    lib.or_qp_group_speed_support.argtypes = [M, D]
+    lib.or_qp_group_speed_support.restype = D
+    lib.or_stencil_offsets.argtypes = [I, ctypes.POINTER(I)]
+    lib.or_stencil_estimate.argtypes = [M, D, D, ctypes.POINTER(I), D, D, D]
+    lib.or_stencil_estimate.restype = D
+    lib.or_phi_d.argtypes = [I, I, D, M, P, P, P, P, I, I, ctypes.POINTER(I)]
+    lib.or_phi_d.restype = D
+    lib.or_source_box.argtypes = [I, I, D, M, P, P, I, I, I, P, P]
+    lib.or_solve_fmm.argtypes = [I, I, D, M, I, P, P, I, I, I, P, P, P]
+    lib.or_solve_fmm.restype = I64
+    lib.or_localfmm.argtypes = [I, I, D, M, P, P, P, I, I, ctypes.POINTER(I)]
+    lib.or_localfmm.restype = D
+    lib.or_sweep_solve.argtypes = [I, I, D, M, I, P, P, I, I, I, I, P]
+    lib.or_sweep_solve.restype = I
+    lib.or_dijkstra_dense.argtypes = [I, I, D, M, P, P, I, I, D, P]
+    lib.or_segment_time.argtypes = [I, I, D, M, P, P, D, D, D, D]
+    lib.or_segment_time.restype = D
+    if hasattr(lib, "or_trace_ray"):
+        lib.or_trace_ray.argtypes = [I, I, D, M, P, P, P, I, I, I, I, I, I, P, ctypes.POINTER(I), ctypes.POINTER(D)]
+        lib.or_trace_ray.restype = I
+    if hasattr(lib, "or_adjoint"):
+        lib.or_adjoint.argtypes = [I, I, D, M, I, P, P, I, I, I, P, P, P]
+        lib.or_adjoint.restype = I
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------------------
+def _mat_array(mats):
+    mats = list(mats)
+    arr = (Material * len(mats))()
+    for k, m in enumerate(mats):
+        if isinstance(m, dict):
+            vals = [m[n] for n in ("c11", "c13", "c33", "c55", "c44", "c66", "rho")]
+        else:
+            vals = list(m)
+        for n, v in zip(("c11", "c13", "c33", "c55", "c44", "c66", "rho"), vals):
+            setattr(arr[k], n, float(v))
+    return arr
+
+
+def _medium(mat_id, orient):
+    mat_id = np.ascontiguousarray(mat_id, dtype=np.uint8)
+    orient = np.ascontiguousarray(orient, dtype=np.float64)
+    assert mat_id.shape == orient.shape and mat_id.ndim == 2
+    return mat_id, orient
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------------------
+# Section 3: velocities
+# ---------------------------------------------------------------------------------------
+def qp_phase_speed(mat, th_p):
+    """qP phase speed at phase angle th_p (rad, from the c22 axis); Section 3.2."""
+    lib = _load()
+    return lib.or_qp_phase_speed(_mat_array([mat]), float(th_p))
+
+
+def qp_group_from_phase(mat, th_p):
+    """(group angle, group speed) for phase angle th_p; Section 3.1 group velocity."""
+    lib = _load()
+    ga, gs = ctypes.c_double(), ctypes.c_double()
+    lib.or_qp_group_from_phase(_mat_array([mat]), float(th_p), ctypes.byref(ga), ctypes.byref(gs))
+    return ga.value, gs.value
+
+
+def qp_group_speed(mat, phi):
+    """qP group speed along group angle phi (rad, from the c22 axis); Section 3.2."""
+    return _load().or_qp_group_speed(_mat_array([mat]), float(phi))
+
+
+def qp_group_speed_support(mat, phi):
+    """Group speed by the slowness-curve support function (independent route)."""
+    return _load().or_qp_group_speed_support(_mat_array([mat]), float(phi))
+
+
+# ---------------------------------------------------------------------------------------
+# Section 4: stencils and the update
+# ---------------------------------------------------------------------------------------
+def stencil_offsets(s):
+    """(di, dj) of A, B, C for stencil s = 0..31 (Tables 1-2, corrected)."""
+    out = (ctypes.c_int * 6)()
+    _load().or_stencil_offsets(int(s), out)
+    return [(out[0], out[1]), (out[2], out[3]), (out[4], out[5])]
+
+
+def stencil_estimate(mat, theta_ax, h, offsets, ta, tb, tc):
+    """Section 4.2 estimate tau_B + |FD| / v(theta') for one stencil."""
+    off = (ctypes.c_int * 6)(*[int(v) for p in offsets for v in p])
+    return _load().or_stencil_estimate(_mat_array([mat]), float(theta_ax), float(h), off,
+                                       float(ta), float(tb), float(tc))
+
+
+def phi_d(h, mats, mat_id, orient, T, known, i, j):
+    """Section 4.3 choice Phi_D(K); returns (value, choice)."""
+    mat_id, orient = _medium(mat_id, orient)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    known = np.ascontiguousarray(known, dtype=np.uint8)
+    nz, nx = mat_id.shape
+    ch = ctypes.c_int()
+    v = _load().or_phi_d(nx, nz, float(h), _mat_array(mats), _ptr(mat_id), _ptr(orient),
+                         _ptr(T), _ptr(known), int(i), int(j), ctypes.byref(ch))
+    return v, ch.value
+
+
+def source_box(h, mats, mat_id, orient, src, R):
+    mat_id, orient = _medium(mat_id, orient)
+    nz, nx = mat_id.shape
+    T = np.full((nz, nx), np.inf)
+    fixed = np.zeros((nz, nx), np.uint8)
+    _load().or_source_box(nx, nz, float(h), _mat_array(mats), _ptr(mat_id), _ptr(orient),
+                          int(src[0]), int(src[1]), int(R), _ptr(T), _ptr(fixed))
+    return T, fixed
+
+
+def solve_fmm(h, mats, mat_id, orient, src, R=2, return_pops=False):
+    """Heap Fast Marching with the ALI update (Section 2, Section 4).  src = (i, j)."""
+    mat_id, orient = _medium(mat_id, orient)
+    nz, nx = mat_id.shape
+    T = np.empty((nz, nx))
+    pops = np.empty(nx * nz, np.int64)
+    pvals = np.empty(nx * nz)
+    n = _load().or_solve_fmm(nx, nz, float(h), _mat_array(mats), len(list(mats)), _ptr(mat_id),
+                             _ptr(orient), int(src[0]), int(src[1]), int(R), _ptr(T),
+                             _ptr(pops), _ptr(pvals))
+    if n < 0:
+        raise ValueError("oracle: invalid input")
+    if return_pops:
+        return T, pops[:n], pvals[:n]
+    return T
+
+
+def localfmm(h, mats, mat_id, orient, T, i, j):
+    """The local operator at node (i, j) evaluated on field T; returns (value, choice)."""
+    mat_id, orient = _medium(mat_id, orient)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    nz, nx = mat_id.shape
+    ch = ctypes.c_int()
+    v = _load().or_localfmm(nx, nz, float(h), _mat_array(mats), _ptr(mat_id), _ptr(orient),
+                            _ptr(T), int(i), int(j), ctypes.byref(ch))
+    return v, ch.value
+
+
+def sweep_solve(h, mats, mat_id, orient, src, R=2, max_sweeps=1000):
+    """Gauss-Seidel sweeps of the local operator to a bitwise fixed point."""
+    mat_id, orient = _medium(mat_id, orient)
+    nz, nx = mat_id.shape
+    T = np.empty((nz, nx))
+    n = _load().or_sweep_solve(nx, nz, float(h), _mat_array(mats), len(list(mats)), _ptr(mat_id),
+                               _ptr(orient), int(src[0]), int(src[1]), int(R), int(max_sweeps), _ptr(T))
+    return T, n
+
+
+def dijkstra_dense(h, mats, mat_id, orient, src, rad):
+    mat_id, orient = _medium(mat_id, orient)
+    nz, nx = mat_id.shape
+    T = np.empty((nz, nx))
+    _load().or_dijkstra_dense(nx, nz, float(h), _mat_array(mats), _ptr(mat_id), _ptr(orient),
+                              int(src[0]), int(src[1]), float(rad), _ptr(T))
+    return T
+
+
+def segment_time(h, mats, mat_id, orient, p0, p1):
+    mat_id, orient = _medium(mat_id, orient)
+    nz, nx = mat_id.shape
+    return _load().or_segment_time(nx, nz, float(h), _mat_array(mats), _ptr(mat_id), _ptr(orient),
+                                   float(p0[0]), float(p0[1]), float(p1[0]), float(p1[1]))

@@ -1,0 +1,122 @@
+/*
+ * ali_oracle.h -- plain, slow, FP64 CPU oracle for the ALI-FMM travel-time method
+ * (Ludlam, Tant, Dolean, Curtis, "Travel times and ray paths for acoustic and elastic
+ * waves in generally anisotropic media", arXiv 2302.10988).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  The GPU product path shares no code with
+ * it and must never call it.
+ *
+ * Conventions (used by every function below):
+ *   - grid nodes (i, j): i = x column 0..nx-1, j = z row 0..nz-1 (z = depth); spacing h [m];
+ *     linear index idx = j*nx + i; arrays are row-major [nz][nx].
+ *   - orientation theta [rad] = angle of the transversely-isotropic symmetry axis measured
+ *     from +x toward +z.  The paper's velocity-curve angle is measured from the c22 axis
+ *     (perpendicular to the symmetry axis), i.e. the paper's theta_D = theta + 90 deg.
+ *   - material record: stiffness [Pa] in the axis frame ("1" = in-plane direction
+ *     perpendicular to the axis, "3" = the axis) and density [kg/m^3].  In the paper's
+ *     YZ-plane notation (Section 3.2): c22 <- c11, c23 <- c13, c33 <- c33, c44 <- c55.
+ *   - travel times in seconds, +INFINITY where a node is unreached.
+ *
+ * Functions marked "parity unpinned" in the comments implement readings of the paper that
+ * no printed value fixes; they are pinned only by invariants (see the test suite).
+ */
+#ifndef ALI_ORACLE_H
+#define ALI_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double c11, c13, c33, c55, c44, c66, rho;
+} or_material;
+
+/* ---- Section 3: velocities ------------------------------------------------------- */
+
+/* qP phase speed [m/s] at phase angle th_p [rad] measured from the c22 axis
+   (largest root of the in-plane Christoffel matrix, Section 3.2). */
+double or_qp_phase_speed(const or_material* m, double th_p);
+
+/* qP group velocity for phase angle th_p (Section 3.1, group velocity from the
+   polarisation vector and the stiffness tensor).  Outputs the group angle [rad] from the
+   c22 axis and the group speed [m/s]. */
+void or_qp_group_from_phase(const or_material* m, double th_p, double* g_angle, double* g_speed);
+
+/* qP group speed [m/s] along group angle phi [rad] from the c22 axis, by inverting the
+   phase->group angle map with bisection (exact to rounding). */
+double or_qp_group_speed(const or_material* m, double phi);
+
+/* Same quantity by a second, independent route: the support function of the slowness
+   curve, 1/V(phi) = max_psi cos(phi - psi) / v(psi). */
+double or_qp_group_speed_support(const or_material* m, double phi);
+
+/* ---- Section 4.1: stencil table --------------------------------------------------- */
+
+/* Offsets (di, dj) of A, B, C relative to D for stencil s = 0..31 (0 = "1-1", 1 = "1-2",
+   ..., 31 = "16-2"), with the two printing errors of Table 1 corrected. */
+void or_stencil_offsets(int s, int out[6]);
+
+/* ---- Section 4.2: one stencil's estimate ----------------------------------------- */
+
+/* Travel-time estimate at D from the stencil whose support has offsets (xa,ya),(xb,yb),
+   (xc,yc) relative to D (grid units), travel times ta < tb <= tc, material m, axis angle
+   theta_ax at D, spacing h.  Returns tau_B + |FD| / v(theta'). */
+double or_stencil_estimate(const or_material* m, double theta_ax, double h,
+                           const int off[6], double ta, double tb, double tc);
+
+/* ---- Section 4.3: stencil choice Phi_D(K) ----------------------------------------- */
+
+/* Estimate at node (i, j) from the set K of known diamond neighbours given by
+   known[] (nonzero = known; array over the whole grid).  Returns the value and, through
+   choice (nullable), the chosen candidate: 0..31 = stencil, 32 + k = straight-ray
+   fallback from the k-th 8-neighbour, -1 = none (value +inf).  parity unpinned (reading). */
+double or_phi_d(int nx, int nz, double h, const or_material* mats, const uint8_t* mat_id,
+                const double* orient, const double* T, const uint8_t* known,
+                int i, int j, int* choice);
+
+/* ---- Section 2 / 4.4: drivers ------------------------------------------------------ */
+
+/* Straight-ray source box (Section 4.4 first paragraph): for every node within Chebyshev
+   radius R of the source node (si, sj), T = |N - S| h / V_group(direction) with the
+   source node's material and orientation.  Writes T and sets fixed[] for those nodes. */
+void or_source_box(int nx, int nz, double h, const or_material* mats, const uint8_t* mat_id,
+                   const double* orient, int si, int sj, int R, double* T, uint8_t* fixed);
+
+/* Heap-based Fast Marching (Section 2) with the ALI update.  T[nz*nx] out.
+   pop_order (nullable, length nx*nz) receives the linear index of each popped node in
+   pop order; returns the number of pops (or -1 on invalid input). */
+int64_t or_solve_fmm(int nx, int nz, double h, const or_material* mats, int n_mats,
+                     const uint8_t* mat_id, const double* orient, int si, int sj, int R,
+                     double* T, int64_t* pop_order, double* pop_values);
+
+/* The local operator whose unique fixed point is the heap result: value at non-fixed
+   node (i, j) computed from the current field T only (neighbours sorted by (T, idx), the
+   known set grown in that order, stop once the estimate is below the next neighbour). */
+double or_localfmm(int nx, int nz, double h, const or_material* mats, const uint8_t* mat_id,
+                   const double* orient, const double* T, int i, int j, int* choice);
+
+/* Independent driver: Gauss-Seidel sweeps of or_localfmm to a bitwise fixed point.
+   Returns the number of sweeps, or -1 if max_sweeps was reached. */
+int or_sweep_solve(int nx, int nz, double h, const or_material* mats, int n_mats,
+                   const uint8_t* mat_id, const double* orient, int si, int sj, int R,
+                   int max_sweeps, double* T);
+
+/* Dense-stencil Dijkstra reference: edges to every node within Euclidean radius rad
+   (grid units); edge time = exact cell-walk of the straight segment through the
+   nearest-node cells at group speed.  Source at node (si, sj) with T = 0. */
+void or_dijkstra_dense(int nx, int nz, double h, const or_material* mats,
+                       const uint8_t* mat_id, const double* orient, int si, int sj,
+                       double rad, double* T);
+
+/* Straight-segment travel time from point p0 to p1 (grid coordinates) through the
+   nearest-node cells at group speed (the segment time used by the ray tracer). */
+double or_segment_time(int nx, int nz, double h, const or_material* mats,
+                       const uint8_t* mat_id, const double* orient,
+                       double x0, double z0, double x1, double z1);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,131 @@
+/*
+ * velocity.c -- oracle velocities (paper Section 3).  TEST INFRASTRUCTURE ONLY.
+ *
+ * The medium is orthotropic/TI and waves stay in the plane that contains the symmetry
+ * axis.  Following Section 3.2, the in-plane Christoffel matrix for phase direction
+ * (cos th, sin th) (th from the c22 axis) is
+ *     [ alpha beta ; beta gamma ],  alpha = cos^2 c22 + sin^2 c44,
+ *                                   beta  = cos sin (c23 + c44),
+ *                                   gamma = cos^2 c44 + sin^2 c33,
+ * and the qP eigenvalue is the largest root ((alpha+gamma) + sqrt((alpha-gamma)^2+4beta^2))/2
+ * (the eigenvalues of M divided by rho give v^2; Section 3.1).
+ *
+ * Group velocity (Section 3.1): differentiating rho w^2 = C_ijql k_j k_l p_q p_i (the
+ * Christoffel equation as derived in the paper) with respect to k_m gives
+ *     V_m = C_imql p_i p_q n_l / (rho v).
+ * The printed final formula divides by rho*omega and places the polarisation on the first
+ * two tensor indices; both are read as printing slips (omega -> v, and the index order
+ * that the derivation itself produces).
+ */
+#include <math.h>
+#include "ali_oracle.h"
+
+/* In-plane stiffness tensor C_ijkl, i,j,k,l in {0 = y (c22 axis), 1 = z (symmetry
+   axis)}, from the Voigt matrix with the paper's index map f(i,j) (Section 3.2):
+   f(y,y) = 2, f(z,z) = 3, f(y,z) = 4. */
+static double cvoigt(const or_material* m, int vi, int vj) {
+    /* Voigt entries that matter in the plane: c22, c33, c23, c44 (paper notation). */
+    if (vi > vj) { int t = vi; vi = vj; vj = t; }
+    if (vi == 2 && vj == 2) return m->c11;   /* c22 */
+    if (vi == 3 && vj == 3) return m->c33;   /* c33 */
+    if (vi == 2 && vj == 3) return m->c13;   /* c23 */
+    if (vi == 4 && vj == 4) return m->c55;   /* c44 (in-plane shear) */
+    return 0.0;
+}
+static int fmap(int i, int j) { return i == j ? (i == 0 ? 2 : 3) : 4; }
+static double cijkl(const or_material* m, int i, int j, int k, int l) {
+    return cvoigt(m, fmap(i, j), fmap(k, l));
+}
+
+static void christoffel(const or_material* m, double th, double* al, double* be, double* ga) {
+    double c = cos(th), s = sin(th);
+    *al = c * c * m->c11 + s * s * m->c55;
+    *be = c * s * (m->c13 + m->c55);
+    *ga = c * c * m->c55 + s * s * m->c33;
+}
+
+static double qp_lambda(double al, double be, double ga) {
+    return 0.5 * ((al + ga) + sqrt((al - ga) * (al - ga) + 4.0 * be * be));
+}
+
+double or_qp_phase_speed(const or_material* m, double th_p) {
+    double al, be, ga;
+    christoffel(m, th_p, &al, &be, &ga);
+    return sqrt(qp_lambda(al, be, ga) / m->rho);
+}
+
+void or_qp_group_from_phase(const or_material* m, double th_p, double* g_angle, double* g_speed) {
+    double al, be, ga;
+    christoffel(m, th_p, &al, &be, &ga);
+    double lam = qp_lambda(al, be, ga);
+    double v = sqrt(lam / m->rho);
+    /* unit eigenvector of [al be; be ga] for lam: take the better conditioned of the two
+       equivalent forms (be, lam-al) and (lam-ga, be). */
+    double p0a = be, p1a = lam - al;
+    double p0b = lam - ga, p1b = be;
+    double na = p0a * p0a + p1a * p1a, nb = p0b * p0b + p1b * p1b;
+    double p[2];
+    if (na >= nb) { double r = sqrt(na); p[0] = p0a / r; p[1] = p1a / r; }
+    else          { double r = sqrt(nb); p[0] = p0b / r; p[1] = p1b / r; }
+    if (na == 0.0 && nb == 0.0) {          /* degenerate (isotropic point): p = n */
+        p[0] = cos(th_p); p[1] = sin(th_p);
+    }
+    double n[2] = {cos(th_p), sin(th_p)};
+    double V[2] = {0.0, 0.0};
+    for (int mm = 0; mm < 2; ++mm)
+        for (int i = 0; i < 2; ++i)
+            for (int q = 0; q < 2; ++q)
+                for (int l = 0; l < 2; ++l)
+                    V[mm] += cijkl(m, i, mm, q, l) * p[i] * p[q] * n[l];
+    V[0] /= (m->rho * v);
+    V[1] /= (m->rho * v);
+    *g_angle = atan2(V[1], V[0]);
+    *g_speed = sqrt(V[0] * V[0] + V[1] * V[1]);
+}
+
+/* Reduce an angle to [0, pi/2] using the two mirror symmetries of an orthotropic
+   velocity curve (symmetric about the c22 axis and about the symmetry axis). */
+static double reduce_quadrant(double a) {
+    a = fmod(fabs(a), M_PI);
+    if (a > 0.5 * M_PI) a = M_PI - a;
+    return a;
+}
+
+double or_qp_group_speed(const or_material* m, double phi) {
+    double target = reduce_quadrant(phi);
+    double lo = 0.0, hi = 0.5 * M_PI, ga, gs;
+    /* the qP group angle increases monotonically with the phase angle on [0, pi/2]
+       (convex slowness curve; checked by the tests) -> plain bisection */
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        or_qp_group_from_phase(m, mid, &ga, &gs);
+        if (ga < target) lo = mid; else hi = mid;
+    }
+    or_qp_group_from_phase(m, 0.5 * (lo + hi), &ga, &gs);
+    return gs;
+}
+
+double or_qp_group_speed_support(const or_material* m, double phi) {
+    /* maximise f(psi) = cos(phi - psi) / v(psi) over psi in (phi - pi/2, phi + pi/2):
+       coarse scan, then golden-section refinement of the best bracket */
+    const int N = 7200;
+    double best = -1.0, bpsi = phi;
+    for (int k = 1; k < N; ++k) {
+        double psi = phi - 0.5 * M_PI + M_PI * (double)k / N;
+        double f = cos(phi - psi) / or_qp_phase_speed(m, psi);
+        if (f > best) { best = f; bpsi = psi; }
+    }
+    double a = bpsi - M_PI / N, b = bpsi + M_PI / N;
+    const double gr = 0.5 * (sqrt(5.0) - 1.0);
+    double c = b - gr * (b - a), d = a + gr * (b - a);
+    double fc = cos(phi - c) / or_qp_phase_speed(m, c);
+    double fd = cos(phi - d) / or_qp_phase_speed(m, d);
+    for (int it = 0; it < 200 && (b - a) > 1e-13; ++it) {
+        if (fc > fd) { b = d; d = c; fd = fc; c = b - gr * (b - a); fc = cos(phi - c) / or_qp_phase_speed(m, c); }
+        else         { a = c; c = d; fc = fd; d = a + gr * (b - a); fd = cos(phi - d) / or_qp_phase_speed(m, d); }
+    }
+    double f = fc > fd ? fc : fd;
+    if (best > f) f = best;
+    return 1.0 / f;
+}
