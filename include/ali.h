@@ -1,0 +1,129 @@
+/*
+ * ali.h -- C ABI of the MI355X travel-time solver for generally anisotropic media
+ * (ALI-FMM: Ludlam, Tant, Dolean, Curtis, arXiv 2302.10988).
+ *
+ * What it computes (paper Section 2, eq. 1): first-arrival qP travel times from a point
+ * source to every node of a square 2-D grid, in a medium given per node by a material
+ * (stiffness tensor and density, Section 3.2) and the orientation of its symmetry axis.
+ * Each node value is the paper's locally interpolated wavefront estimate (Sections
+ * 4.1-4.3) from already-known diamond neighbours; the GPU reaches the same discrete fixed
+ * point as the paper's heap-ordered Fast Marching by a tiled data-parallel relaxation.
+ *
+ * Conventions for every entry point:
+ *   - nodes (i, j): i = x column 0..nx-1, j = z row 0..nz-1 (z = depth, downward);
+ *     spacing h [m]; fields are row-major [nz][nx], float32 unless the name ends in _f64.
+ *   - orientation [rad]: angle of the symmetry axis measured from +x toward +z.  The
+ *     paper's velocity-curve angle is measured from the perpendicular (c22) axis; only the
+ *     difference matters and any multiple of pi is harmless (180-degree symmetry).
+ *   - material stiffness [Pa] is given in the axis frame: "3" = symmetry axis, "1" = the
+ *     in-plane direction across it.  The qP speed uses c11, c13, c33, c55 (the paper's
+ *     c22, c23, c33, c44 of its YZ plane); c44, c66 are carried for shear modes.
+ *   - travel times in seconds; +INFINITY marks a node the wave cannot reach.
+ *   - pointers named d_* are device pointers (caller-owned, on the handle's device);
+ *     the others are host pointers.  Calls are asynchronous on the handle's stream
+ *     unless stated; a stats struct is filled before the call returns.
+ *   - errors: every function returns ali_status; nothing throws across the ABI.  Invalid
+ *     arguments return ALI_EINVAL before any device work is queued; the message is
+ *     available from ali_last_error(handle).
+ */
+#ifndef ALI_H
+#define ALI_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ALI_OK = 0,
+    ALI_EINVAL = -1,        /* invalid argument (sizes, material, source, orientation)   */
+    ALI_ENOMEM = -2,        /* device allocation for the handle's scratch failed          */
+    ALI_EDEVICE = -3,       /* a HIP call failed                                           */
+    ALI_ENOCONV = -4,       /* relaxation hit max_sweeps; T holds the last iterate         */
+    ALI_EUNSUPPORTED = -5
+} ali_status;
+
+typedef struct { int32_t nx, nz; double h; } ali_grid;
+
+typedef struct { double c11, c13, c33, c55, c44, c66, rho; } ali_material;
+
+typedef struct { int32_t i, j; } ali_node;
+
+typedef struct {
+    int32_t src_box_radius;  /* straight-ray box half-width in nodes (Section 4.4); default 2   */
+    int32_t max_sweeps;      /* cap on outer relaxation passes; default 1000000                 */
+    int32_t inner_sweeps;    /* cap on sweeps inside one tile visit; default 64                 */
+    int32_t band_cells;      /* width of the relaxation time band in node spacings at the
+                                fastest phase speed; 0 = no band; default 4                   */
+    int32_t ray_window;      /* ray tracer: candidates tested either side of the straight-ahead
+                                intersection (Section 5.1 limits them, no value given); default 8 */
+    int32_t ray_max_pts;     /* ray tracer: maximum points per path; default 4096                */
+    int32_t arith;           /* float32 entry points: ALI_ARITH_MIXED (default), _F32 or _F64     */
+    int32_t reserved;
+} ali_options;
+
+/* Arithmetic of the float32 entry points.  MIXED keeps travel times, scores and every
+   comparison that decides a stencil in float64 and computes each stencil's wavefront /
+   phase-speed increment in float32; F32 does everything in float32 (fastest; stencil
+   choices near ties follow float32 rounding of the stored times); F64 does everything in
+   float64.  Output is float32 in all three. */
+enum { ALI_ARITH_MIXED = 0, ALI_ARITH_F32 = 1, ALI_ARITH_F64 = 2 };
+
+typedef struct {
+    int64_t node_updates;    /* evaluations of the local update at a non-fixed node          */
+    int64_t stencil_evals;   /* single-stencil estimates computed inside those updates        */
+    int64_t tile_visits;     /* tile passes of the relaxation                                */
+    int64_t nodes;           /* grid nodes times fields                                       */
+    int32_t outer_iters;     /* outer relaxation passes (= relaxation kernel launches)        */
+    int32_t converged;       /* 1 if every field reached a bitwise fixed point                */
+    double  ms;              /* time of the whole call on the stream (HIP events)             */
+    double  relax_ms;        /* summed duration of the relaxation kernel launches (HIP events) */
+} ali_solve_stats;
+
+typedef struct ali_handle ali_handle;
+
+/* Create a handle bound to HIP device `device` and stream `hip_stream` (a hipStream_t;
+   NULL = the default stream).  The handle owns its scratch memory (tile lists, flags,
+   per-node constants), grown on demand and freed by ali_destroy.  One handle must not be
+   used from two threads at once. */
+ali_status ali_create(ali_handle** out, int device, void* hip_stream);
+ali_status ali_destroy(ali_handle* h);
+ali_status ali_set_stream(ali_handle* h, void* hip_stream);
+void ali_default_options(ali_options* opt);
+const char* ali_status_string(ali_status s);
+const char* ali_last_error(const ali_handle* h);
+
+/* Travel-time fields for n_src point sources in one medium (paper Sections 2 and 4),
+   solved together in one batched relaxation.
+     grid           nx, nz >= 3, h > 0
+     mats[n_mats]   1 <= n_mats <= 256; each needs rho > 0, c11, c33, c55 > 0 and
+                    c11*c33 > c13^2 (in-plane positive definiteness)
+     d_mat_id       [nz][nx] uint8 material index (< n_mats)
+     d_orient       [nz][nx] float32 symmetry-axis angle [rad], finite
+     srcs[n_src]    source nodes (host array), inside the grid
+     d_T            [n_src][nz][nx] float32 output
+   Node values inside the source box come from straight rays at the group speed of the
+   source node's material (Section 4.4, first paragraph); every other value is the ALI
+   local estimate (Sections 4.1-4.3) at the unique fixed point of the update.
+   A NaN/inf orientation is reported as ALI_EINVAL after the device check.
+   If stats != NULL the call synchronises the stream and fills it. */
+ali_status ali_solve_traveltime(ali_handle* h, const ali_grid* grid,
+                                const ali_material* mats, int32_t n_mats,
+                                const uint8_t* d_mat_id, const float* d_orient,
+                                const ali_node* srcs, int32_t n_src,
+                                const ali_options* opt, float* d_T,
+                                ali_solve_stats* stats);
+
+/* Same computation in float64 (orientation and output in double): the logic-parity
+   mode used to compare with a double-precision reference. */
+ali_status ali_solve_traveltime_f64(ali_handle* h, const ali_grid* grid,
+                                    const ali_material* mats, int32_t n_mats,
+                                    const uint8_t* d_mat_id, const double* d_orient,
+                                    const ali_node* srcs, int32_t n_src,
+                                    const ali_options* opt, double* d_T,
+                                    ali_solve_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

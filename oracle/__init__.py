@@ -66,6 +66,8 @@ def _load():
     lib.or_source_box.argtypes = [I, I, D, M, P, P, I, I, I, P, P]
     lib.or_solve_fmm.argtypes = [I, I, D, M, I, P, P, I, I, I, P, P, P]
     lib.or_solve_fmm.restype = I64
+    lib.or_last_phi_evals.argtypes = []
+    lib.or_last_phi_evals.restype = I64
     lib.or_localfmm.argtypes = [I, I, D, M, P, P, P, I, I, ctypes.POINTER(I)]
     lib.or_localfmm.restype = D
     lib.or_sweep_solve.argtypes = [I, I, D, M, I, P, P, I, I, I, I, P]
@@ -191,6 +193,12 @@ def solve_fmm(h, mats, mat_id, orient, src, R=2, return_pops=False):
     if return_pops:
         return T, pops[:n], pvals[:n]
     return T
+
+
+def solve_fmm_counted(h, mats, mat_id, orient, src, R=2):
+    """solve_fmm plus the number of Phi_D evaluations the heap driver made."""
+    T = solve_fmm(h, mats, mat_id, orient, src, R)
+    return T, int(_load().or_last_phi_evals())
 
 
 def localfmm(h, mats, mat_id, orient, T, i, j):

@@ -91,6 +91,9 @@ int64_t or_solve_fmm(int nx, int nz, double h, const or_material* mats, int n_ma
                      const uint8_t* mat_id, const double* orient, int si, int sj, int R,
                      double* T, int64_t* pop_order, double* pop_values);
 
+/* Number of Phi_D evaluations made by the last or_solve_fmm call (statistics). */
+int64_t or_last_phi_evals(void);
+
 /* The local operator whose unique fixed point is the heap result: value at non-fixed
    node (i, j) computed from the current field T only (neighbours sorted by (T, idx), the
    known set grown in that order, stop once the estimate is below the next neighbour). */

@@ -198,6 +198,9 @@ void or_source_box(int nx, int nz, double h, const or_material* mats, const uint
 }
 
 /* ---- Section 2: heap Fast Marching -------------------------------------------------- */
+static int64_t g_phi_evals = 0;     /* evaluations of Phi_D in the last or_solve_fmm call */
+int64_t or_last_phi_evals(void) { return g_phi_evals; }
+
 typedef struct { double t; int64_t idx; int64_t ver; } hent;
 typedef struct { hent* a; int64_t n, cap; } heap_t;
 
@@ -259,6 +262,7 @@ int64_t or_solve_fmm(int nx, int nz, double h, const or_material* mats, int n_ma
         if (fixed[p]) hpush(&hp, (hent){T[p], p, 0});
     ctx_t c = {nx, nz, h, mats, mat_id, orient, T};
     int64_t npop = 0;
+    g_phi_evals = 0;
     while (hp.n > 0) {
         hent e = hpop(&hp);
         if (known[e.idx] || e.ver != ver[e.idx]) continue;   /* stale entry */
@@ -273,6 +277,7 @@ int64_t or_solve_fmm(int nx, int nz, double h, const or_material* mats, int n_ma
             int64_t d = (int64_t)dj * nx + di;
             if (known[d] || fixed[d]) continue;
             double u = phi_core(&c, di, dj, known12_from_grid(&c, known, di, dj), NULL);
+            ++g_phi_evals;
             if (u != T[d]) {                                  /* R4: recompute */
                 T[d] = u;
                 ++ver[d];

@@ -1,0 +1,136 @@
+"""MI355X travel-time solver for generally anisotropic media (ALI-FMM, arXiv 2302.10988).
+
+Thin Python binding over the C ABI of libali.so (include/ali.h).  torch provides device
+memory and the stream; every step of the computation runs in the HIP kernels.  There is
+no CPU fallback: without the built library or a GPU, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+
+__all__ = ["AliError", "Solver", "default_options"]
+
+_MAT_FIELDS = ("c11", "c13", "c33", "c55", "c44", "c66", "rho")
+
+
+class AliError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (status %d): %s" % (_status_string(status), status, message))
+        self.status = status
+
+
+def _status_string(status):
+    try:
+        return _lib.load().ali_status_string(status).decode()
+    except Exception:  # library not loadable: still report the code
+        return "status"
+
+
+def default_options(**overrides):
+    lib = _lib.load()
+    o = _lib.Options()
+    lib.ali_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        if v is not None:
+            setattr(o, k, int(v))
+    return o
+
+
+def _materials(mats):
+    mats = list(mats)
+    arr = (_lib.Material * len(mats))()
+    for k, m in enumerate(mats):
+        vals = [m[n] for n in _MAT_FIELDS] if isinstance(m, dict) else list(m)
+        for n, v in zip(_MAT_FIELDS, vals):
+            setattr(arr[k], n, float(v))
+    return arr, len(mats)
+
+
+def _nodes(nodes):
+    nodes = [tuple(int(v) for v in p) for p in nodes]
+    arr = (_lib.Node * max(len(nodes), 1))()
+    for k, (i, j) in enumerate(nodes):
+        arr[k].i, arr[k].j = i, j
+    return arr, len(nodes)
+
+
+def _dev_ptr(t, dtype, shape=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must have dtype %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One handle of the C ABI, bound to a device and to torch's current stream."""
+
+    def __init__(self, device=None):
+        import torch
+        self._lib = _lib.load()
+        dev = torch.cuda.current_device() if device is None else int(device)
+        self.device = dev
+        h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        st = self._lib.ali_create(ctypes.byref(h), dev, ctypes.c_void_p(stream))
+        if st != 0:
+            raise AliError(st, "ali_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ali_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        import torch
+        self._lib.ali_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _check(self, st):
+        if st != 0:
+            raise AliError(st, self._lib.ali_last_error(self._h).decode())
+
+    def solve(self, h, mats, mat_id, orient, sources, out=None, precision="f32",
+              src_box_radius=None, max_sweeps=None, inner_sweeps=None, band_cells=None,
+              arith="mixed"):
+        """Travel-time fields [n_src, nz, nx] for point sources in one medium.
+
+        h: grid spacing [m]; mats: list of stiffness records (dicts with c11, c13, c33,
+        c55, c44, c66 [Pa], rho [kg/m^3]); mat_id: uint8 [nz, nx] device tensor;
+        orient: symmetry-axis angle [rad], float32 (float64 for precision="f64") [nz, nx];
+        sources: [(i, j), ...]; arith (float32 output only): "mixed" (float64 times and
+        decisions, float32 wavefront math), "f32" or "f64".  Returns (T, stats dict)."""
+        import torch
+        nz, nx = mat_id.shape
+        fdt = torch.float32 if precision == "f32" else torch.float64
+        m_arr, nm = _materials(mats)
+        s_arr, ns = _nodes(sources)
+        g = _lib.Grid(int(nx), int(nz), float(h))
+        opt = default_options(src_box_radius=src_box_radius, max_sweeps=max_sweeps,
+                              inner_sweeps=inner_sweeps, band_cells=band_cells,
+                              arith=_lib.ARITH[arith])
+        if out is None:
+            out = torch.empty((ns, nz, nx), dtype=fdt, device=mat_id.device)
+        p_id = _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id")
+        p_or = _dev_ptr(orient, fdt, (nz, nx), "orient")
+        p_T = _dev_ptr(out, fdt, (ns, nz, nx), "out")
+        stats = _lib.SolveStats()
+        self._sync_stream()
+        fn = self._lib.ali_solve_traveltime if precision == "f32" else self._lib.ali_solve_traveltime_f64
+        st = fn(self._h, ctypes.byref(g), m_arr, nm, p_id, p_or, s_arr, ns, ctypes.byref(opt),
+                p_T, ctypes.byref(stats))
+        self._check(st)
+        return out, stats.as_dict()

@@ -1,0 +1,83 @@
+"""ctypes declarations of the C ABI in include/ali.h (argument marshalling only).
+
+The shared library is built in-tree by build.py.  There is no fallback: if libali.so is
+missing or a GPU is absent, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libali.so")
+
+ALI_OK, ALI_EINVAL, ALI_ENOMEM, ALI_EDEVICE, ALI_ENOCONV, ALI_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32), ("h", ctypes.c_double)]
+
+
+class Material(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("c11", "c13", "c33", "c55", "c44", "c66", "rho")]
+
+
+class Node(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_int32), ("j", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("src_box_radius", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("inner_sweeps", ctypes.c_int32), ("band_cells", ctypes.c_int32),
+                ("ray_window", ctypes.c_int32), ("ray_max_pts", ctypes.c_int32),
+                ("arith", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+ARITH = {"mixed": 0, "f32": 1, "f64": 2}
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("node_updates", ctypes.c_int64), ("stencil_evals", ctypes.c_int64),
+                ("tile_visits", ctypes.c_int64), ("nodes", ctypes.c_int64),
+                ("outer_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("relax_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol the header declares, with (restype, argtypes)
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+SIGNATURES = {
+    "ali_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P]),
+    "ali_destroy": (ctypes.c_int, [_P]),
+    "ali_set_stream": (ctypes.c_int, [_P, _P]),
+    "ali_default_options": (None, [ctypes.POINTER(Options)]),
+    "ali_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ali_last_error": (ctypes.c_char_p, [_P]),
+    "ali_solve_traveltime": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32,
+                                            _P, _P, ctypes.POINTER(Node), _I32,
+                                            ctypes.POINTER(Options), _P, ctypes.POINTER(SolveStats)]),
+    "ali_solve_traveltime_f64": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32,
+                                                _P, _P, ctypes.POINTER(Node), _I32,
+                                                ctypes.POINTER(Options), _P, ctypes.POINTER(SolveStats)]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libali.so and declare its entry points (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libali.so is not built (run paper_2302_10988_amd/build.py): "
+                           "the solver has no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

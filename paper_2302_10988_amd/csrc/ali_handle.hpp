@@ -1,0 +1,85 @@
+// ali_handle.hpp -- handle state shared by the C-ABI entry points: device, stream,
+// named scratch buffers grown on demand, timing events, last error message.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <map>
+#include <string>
+
+#include "../../include/ali.h"
+
+struct ali_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+    uint32_t* host_count = nullptr;           // pinned 4-byte readback slot
+    std::string err;
+    struct Buf { void* p = nullptr; size_t bytes = 0; };
+    std::map<std::string, Buf> bufs;
+
+    ali_status fail(ali_status s, const std::string& msg) {
+        err = msg;
+        return s;
+    }
+    // device buffer `name` of at least `bytes`; contents are not preserved on growth
+    bool scratch(const char* name, size_t bytes, void** out) {
+        Buf& b = bufs[name];
+        if (b.bytes < bytes) {
+            if (b.p) (void)hipFree(b.p);
+            b.p = nullptr;
+            b.bytes = 0;
+            size_t want = bytes < 256 ? 256 : bytes;
+            if (hipMalloc(&b.p, want) != hipSuccess) { b.p = nullptr; return false; }
+            b.bytes = want;
+        }
+        *out = b.p;
+        return true;
+    }
+};
+
+#define HIPCK(H, call)                                                                 \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return (H)->fail(ALI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace ali {
+
+inline ali_status set_device(ali_handle* H) {
+    HIPCK(H, hipSetDevice(H->device));
+    return ALI_OK;
+}
+
+// host-side validation shared by every entry point taking a medium
+template <typename oreal>
+inline ali_status validate_medium(ali_handle* H, const ali_grid* g, const ali_material* mats,
+                                  int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient,
+                                  const ali_node* srcs, int32_t n_src) {
+    if (!g) return H->fail(ALI_EINVAL, "grid is NULL");
+    if (g->nx < 3 || g->nz < 3) return H->fail(ALI_EINVAL, "grid needs nx, nz >= 3");
+    if ((int64_t)g->nx * g->nz > (int64_t)1 << 31) return H->fail(ALI_EINVAL, "grid too large");
+    if (!(g->h > 0.0) || !isfinite(g->h)) return H->fail(ALI_EINVAL, "grid spacing h must be finite and > 0");
+    if (!mats || n_mats < 1 || n_mats > 256) return H->fail(ALI_EINVAL, "need 1..256 materials");
+    for (int k = 0; k < n_mats; ++k) {
+        const ali_material& m = mats[k];
+        const double v[7] = {m.c11, m.c13, m.c33, m.c55, m.c44, m.c66, m.rho};
+        for (double x : v)
+            if (!isfinite(x)) return H->fail(ALI_EINVAL, "material " + std::to_string(k) + " has a non-finite entry");
+        if (!(m.rho > 0.0)) return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": rho must be > 0");
+        if (!(m.c11 > 0.0 && m.c33 > 0.0 && m.c55 > 0.0))
+            return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": c11, c33, c55 must be > 0");
+        if (!(m.c11 * m.c33 > m.c13 * m.c13))
+            return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": c11*c33 must exceed c13^2");
+    }
+    if (!d_mat_id || !d_orient) return H->fail(ALI_EINVAL, "medium arrays are NULL");
+    if (!srcs || n_src < 1) return H->fail(ALI_EINVAL, "need at least one source");
+    for (int k = 0; k < n_src; ++k)
+        if (srcs[k].i < 0 || srcs[k].j < 0 || srcs[k].i >= g->nx || srcs[k].j >= g->nz)
+            return H->fail(ALI_EINVAL, "source " + std::to_string(k) + " outside the grid");
+    return ALI_OK;
+}
+
+}  // namespace ali

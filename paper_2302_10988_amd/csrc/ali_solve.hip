@@ -1,0 +1,576 @@
+// ali_solve.hip -- travel-time fields by tiled relaxation of the ALI update (gfx950).
+//
+// The paper orders node updates with a binary heap (Section 2).  Its result is the unique
+// fixed point of a local operator: at node D, grow the known set in (tau, index) order
+// over the diamond and stop once D's estimate precedes the next neighbour.  Any schedule
+// that reaches a state where no node changes lands on that field, so the GPU relaxes
+// tiles in parallel instead:
+//   - each work-group owns a 16x16 tile plus a 2-node halo staged in LDS;
+//   - it sweeps the update over the tile in place until a block-wide OR reports no
+//     change (or the inner cap), skipping waves whose rows saw no change last sweep;
+//   - changed values go back to HBM; a change within 2 nodes of an edge flags the
+//     neighbouring tile(s), an unfinished tile flags itself;
+//   - a compaction kernel turns the flags into the next pass's work list.
+// Ordering: relaxing from +inf everywhere lets values computed from incomplete upstream
+// information race through the whole grid and be corrected over and over.  A per-field
+// time band limits that: an update whose value exceeds the field's threshold theta is
+// stored as +inf and its value remembered per tile (min_rejected).  theta advances by a
+// fixed step each pass (and jumps to the smallest rejected value when nothing is active);
+// a tile wakes up when theta passes its min_rejected.  This restricted operator has the
+// unrestricted field, cut at theta, as its unique fixed point, so the end state (nothing
+// active, nothing rejected) is the same discrete fixed point, reached with far fewer
+// corrections (a Dijkstra-like ordering at tile granularity).
+// Fields of one call (one per source) share the medium and are relaxed in the same launch.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+#include <new>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "ali_device.hpp"
+#include "ali_handle.hpp"
+#include "../../include/ali.h"
+
+namespace ali {
+
+constexpr int TX = 16, TZ = 16, HALO = 2;
+constexpr int LW = TX + 2 * HALO, LH = TZ + 2 * HALO;
+constexpr int LSTRIDE = LW + 1;
+constexpr int NTHREADS = TX * TZ;
+
+template <typename real> inline real dinf_host() { return (real)INFINITY; }
+
+// ---------------------------------------------------------------------------------------
+// Group speed along group angle phi measured from the symmetry axis (float64).
+// Phase speed squared F(psi) = v^2 with psi the phase angle from the axis; the group
+// direction is psi + atan(v'/v) and |V|^2 = v^2 + v'^2 (Section 3.1's |V| = |v|/cos).
+// Inverted on [0, pi/2] (two mirror symmetries) by a bracketed Illinois iteration.
+// ---------------------------------------------------------------------------------------
+struct MatA { double a11, a13, a33, a55; };
+
+__device__ inline void phase_F(const MatA& m, double psi, double& F, double& dF) {
+    const double P = m.a11 + m.a33 + 2.0 * m.a55, Q = m.a33 - m.a11;
+    const double R = m.a11 + m.a33 - 2.0 * m.a55, W = m.a13 + m.a55;
+    double s, c;
+    sincos(2.0 * psi, &s, &c);
+    const double lin = Q + R * c;
+    const double S = sqrt(lin * lin + 4.0 * W * W * s * s);
+    F = 0.25 * (P + Q * c + S);
+    const double dS = S > 0.0 ? (-2.0 * R * s * lin + 8.0 * W * W * s * c) / S : 0.0;
+    dF = 0.25 * (-2.0 * Q * s + dS);
+}
+
+__device__ inline double group_angle_of(const MatA& m, double psi, double* speed) {
+    double F, dF;
+    phase_F(m, psi, F, dF);
+    if (speed) *speed = sqrt(F + dF * dF / (4.0 * F));
+    return psi + atan(dF / (2.0 * F));
+}
+
+__device__ inline double group_speed(const MatA& m, double phi) {
+    const double half_pi = 1.57079632679489661923;
+    double a = fmod(fabs(phi), 2.0 * half_pi);
+    if (a > half_pi) a = 2.0 * half_pi - a;
+    double lo = 0.0, hi = half_pi;
+    double glo = -a, ghi = half_pi - a;
+    double spd;
+    if (glo == 0.0) { group_angle_of(m, 0.0, &spd); return spd; }
+    if (ghi == 0.0) { group_angle_of(m, half_pi, &spd); return spd; }
+    int side = 0;
+    double x = a;
+    for (int it = 0; it < 100; ++it) {
+        x = (lo * ghi - hi * glo) / (ghi - glo);
+        if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+        const double g = group_angle_of(m, x, nullptr) - a;
+        if (g == 0.0 || hi - lo < 1e-15) break;
+        if (g < 0.0) {
+            lo = x; glo = g;
+            if (side == -1) ghi *= 0.5;
+            side = -1;
+        } else {
+            hi = x; ghi = g;
+            if (side == 1) glo *= 0.5;
+            side = 1;
+        }
+    }
+    group_angle_of(m, x, &spd);
+    return spd;
+}
+
+// per-material constants on the device (phase-speed constants in the math type)
+template <typename mreal> struct MatDev {
+    mreal P, Q, R, K4;      // phase-speed constants / h^2
+    MatA A;
+};
+
+// ---------------------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------------------
+template <typename mreal, typename treal, typename oreal>
+__global__ void k_prep(int nx, int nz, double h, int n_mats, const MatDev<mreal>* __restrict__ mats,
+                       const uint8_t* __restrict__ mat_id, const oreal* __restrict__ orient,
+                       mreal* __restrict__ geo, treal* __restrict__ fbt, int* __restrict__ err) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)nx * nz) return;
+    const double th = (double)orient[p];
+    const int mid = mat_id[p];
+    if (!isfinite(th)) { atomicOr(err, 1); return; }
+    if (mid >= n_mats) { atomicOr(err, 2); return; }
+    const MatA m = mats[mid].A;
+    double s2, c2;
+    sincos(2.0 * th, &s2, &c2);
+    geo[2 * p + 0] = (mreal)c2;
+    geo[2 * p + 1] = (mreal)s2;
+    // straight-ray time to an 8-neighbour along x, (1,1), z, (1,-1)
+    const double quarter = 0.78539816339744830962;
+    const double len[4] = {1.0, 1.41421356237309504880, 1.0, 1.41421356237309504880};
+    const double ang[4] = {0.0, quarter, 2.0 * quarter, -quarter};
+#pragma unroll
+    for (int d = 0; d < 4; ++d) fbt[4 * p + d] = (treal)(len[d] * h / group_speed(m, ang[d] - th));
+}
+
+template <typename real, typename mreal, typename oreal>
+__global__ void k_init(int nx, int nz, int nf, double h, const MatDev<mreal>* __restrict__ mats,
+                       const uint8_t* __restrict__ mat_id, const oreal* __restrict__ orient,
+                       const int2* __restrict__ src, int R, real* __restrict__ T,
+                       uint8_t* __restrict__ flags, int ntx, int ntz) {
+    const int64_t N = (int64_t)nx * nz;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = blockIdx.y;
+    if (p >= N) return;
+    const int i = (int)(p % nx), j = (int)(p / nx);
+    const int2 s = src[f];
+    const int di = i - s.x, dj = j - s.y;
+    real v = dinf<real>();
+    if (abs(di) <= R && abs(dj) <= R) {
+        // straight ray at the group speed of the source node's material (Section 4.4)
+        const int64_t ps = (int64_t)s.y * nx + s.x;
+        if (di == 0 && dj == 0) {
+            v = real(0);
+        } else {
+            const double phi = atan2((double)dj, (double)di) - (double)orient[ps];
+            v = (real)(sqrt((double)(di * di + dj * dj)) * h / group_speed(mats[mat_id[ps]].A, phi));
+        }
+    }
+    T[(int64_t)f * N + p] = v;
+    // tiles that see the box (box radius + diamond radius) start active
+    if (abs(di) <= R + HALO && abs(dj) <= R + HALO) {
+        flags[(int64_t)f * ntx * ntz + (j / TZ) * ntx + (i / TX)] = 1;
+    }
+}
+
+template <typename real>
+__global__ void k_compact(uint8_t* __restrict__ flags, real* __restrict__ minrej, int64_t n,
+                          int ntiles, const real* __restrict__ theta, uint32_t* __restrict__ list,
+                          uint32_t* __restrict__ count) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    const int f = (int)(u / ntiles);
+    if (flags[u] || minrej[u] <= theta[f]) {
+        flags[u] = 0;
+        minrej[u] = dinf<real>();     // recomputed by the visit
+        const uint32_t pos = atomicAdd(count, 1u);
+        list[pos] = (uint32_t)u;
+    }
+}
+
+// nothing active: move each field's threshold up to its smallest rejected value
+template <typename real>
+__global__ void k_jump(const real* __restrict__ minrej, int ntiles, int nf, real* __restrict__ theta,
+                       uint32_t* __restrict__ jumped) {
+    const int f = blockIdx.x;
+    real m = dinf<real>();
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        const real v = minrej[(int64_t)f * ntiles + t];
+        m = v < m ? v : m;
+    }
+    __shared__ real red[256];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x + w] < red[threadIdx.x] ? red[threadIdx.x + w] : red[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] < dinf<real>()) {
+        if (red[0] > theta[f]) theta[f] = red[0];
+        atomicAdd(jumped, 1u);
+    }
+}
+
+template <typename real>
+__global__ void k_advance(real* __restrict__ theta, const real* __restrict__ step, int nf) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < nf) theta[f] += step[f];
+}
+
+__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
+
+// min of non-negative values in LDS through their integer bit patterns
+__device__ __forceinline__ void lds_min(float* p, float v) {
+    atomicMin(reinterpret_cast<unsigned*>(p), __float_as_uint(v));
+}
+__device__ __forceinline__ void lds_min(double* p, double v) {
+    atomicMin(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+template <typename dst, typename srcT>
+__global__ void k_convert(dst* __restrict__ out, const srcT* __restrict__ in, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (dst)in[i];
+}
+
+template <typename real>
+__global__ void k_fill(real* __restrict__ p, int64_t n, real v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <typename real, typename mreal>
+__global__ void __launch_bounds__(NTHREADS)
+k_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
+        const MatDev<mreal>* __restrict__ mats, const uint8_t* __restrict__ mat_id,
+        const mreal* __restrict__ geo, const real* __restrict__ fbt,
+        const int2* __restrict__ src, int R, int inner, const real* __restrict__ theta,
+        real* __restrict__ T, uint8_t* __restrict__ flags, real* __restrict__ minrej,
+        unsigned long long* __restrict__ counters) {
+    __shared__ real lt[LH * LSTRIDE];
+    __shared__ real blk_rej;
+    __shared__ unsigned rowmask[3];
+    __shared__ unsigned edge;
+    __shared__ unsigned blk_updates, blk_evals;
+
+    const uint32_t unit = list[blockIdx.x];
+    const int ntiles = ntx * ntz;
+    const int f = (int)(unit / (uint32_t)ntiles);
+    const int tile = (int)(unit % (uint32_t)ntiles);
+    const int tx = tile % ntx, tz = tile / ntx;
+    const int i0 = tx * TX, j0 = tz * TZ;
+    const int64_t N = (int64_t)nx * nz;
+    real* __restrict__ Tf = T + (int64_t)f * N;
+    const real inf = dinf<real>();
+
+    // stage tile + halo
+    for (int q = threadIdx.x; q < LW * LH; q += NTHREADS) {
+        const int li = q % LW, lj = q / LW;
+        const int gi = i0 - HALO + li, gj = j0 - HALO + lj;
+        real v = inf;
+        if (gi >= 0 && gj >= 0 && gi < nx && gj < nz) v = Tf[(int64_t)gj * nx + gi];
+        lt[lj * LSTRIDE + li] = v;
+    }
+    if (threadIdx.x < 3) rowmask[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) { edge = 0u; blk_updates = 0u; blk_evals = 0u; blk_rej = inf; }
+
+    const int lx = threadIdx.x % TX, lz = threadIdx.x / TX;
+    const int gi = i0 + lx, gj = j0 + lz;
+    const int2 s = src[f];
+    const real th = theta[f];
+    const bool valid = gi < nx && gj < nz;
+    const bool fixed = abs(gi - s.x) <= R && abs(gj - s.y) <= R;
+    const bool active = valid && !fixed;
+    NodeConst<mreal, real> nc;
+    if (active) {
+        const int64_t p = (int64_t)gj * nx + gi;
+        const MatDev<mreal> m = mats[mat_id[p]];
+        nc.P = m.P; nc.Q = m.Q; nc.R = m.R; nc.K4 = m.K4;
+        nc.c2t = geo[2 * p + 0];
+        nc.s2t = geo[2 * p + 1];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) nc.fb[d] = fbt[4 * p + d];
+    }
+    __syncthreads();
+
+    const int me = (lz + HALO) * LSTRIDE + (lx + HALO);
+    const real orig = lt[me];
+    const int wave = threadIdx.x / 64;
+    // rows whose changes reach this wave's rows through the diamond
+    const int rlo = wave * (64 / TX) - HALO, rhi = wave * (64 / TX) + (64 / TX) - 1 + HALO;
+    unsigned wrows = 0;
+    for (int r = rlo; r <= rhi; ++r)
+        if (r >= 0 && r < TZ) wrows |= 1u << r;
+
+    unsigned my_updates = 0, my_evals = 0;
+    real my_rej = inf;          // value this node last computed above the band, if any
+    bool done = false;
+    int it = 0;
+    for (; it < inner; ++it) {
+        if (threadIdx.x == 0) rowmask[(it + 1) % 3] = 0u;
+        bool ch = false;
+        const bool eval = it == 0 || (rowmask[(it + 2) % 3] & wrows) != 0u;
+        if (eval && active) {
+            real t[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) t[k] = lt[me + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]];
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) any |= t[k] < inf;
+            if (any) {
+                ++my_updates;
+                real u = local_update<mreal, real>(nc, t, my_evals);
+                my_rej = inf;
+                if (u > th && u < inf) { my_rej = u; u = inf; }
+                const real cur = lt[me];
+                if (!(u == cur || (u >= inf && cur >= inf))) {
+                    lt[me] = u;
+                    ch = true;
+                    atomicOr(&rowmask[it % 3], 1u << lz);
+                }
+            }
+        }
+        if (!__syncthreads_or(ch)) { done = true; break; }
+    }
+
+    const real fin = lt[me];
+    if (valid && !(fin == orig || (fin >= inf && orig >= inf))) {
+        Tf[(int64_t)gj * nx + gi] = fin;
+        unsigned e = 0;
+        if (lx < HALO) e |= 1u;                 // left
+        if (lx >= TX - HALO) e |= 2u;           // right
+        if (lz < HALO) e |= 4u;                 // up
+        if (lz >= TZ - HALO) e |= 8u;           // down
+        if (e) atomicOr(&edge, e);
+    }
+    // per-block update count
+    if (my_updates) { atomicAdd(&blk_updates, my_updates); atomicAdd(&blk_evals, my_evals); }
+    if (my_rej < inf) lds_min(&blk_rej, my_rej);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (blk_updates) {
+            atomicAdd(&counters[0], (unsigned long long)blk_updates);
+            atomicAdd(&counters[1], (unsigned long long)blk_evals);
+        }
+        uint8_t* fl = flags + (int64_t)f * ntiles;
+        minrej[(int64_t)f * ntiles + tile] = blk_rej;
+        const unsigned e = edge;
+        const bool L = e & 1u, Rr = e & 2u, U = e & 4u, D = e & 8u;
+        if (!done) fl[tile] = 1;
+        if (L && tx > 0) fl[tile - 1] = 1;
+        if (Rr && tx + 1 < ntx) fl[tile + 1] = 1;
+        if (U && tz > 0) fl[tile - ntx] = 1;
+        if (D && tz + 1 < ntz) fl[tile + ntx] = 1;
+        if (L && U && tx > 0 && tz > 0) fl[tile - ntx - 1] = 1;
+        if (Rr && U && tx + 1 < ntx && tz > 0) fl[tile - ntx + 1] = 1;
+        if (L && D && tx > 0 && tz + 1 < ntz) fl[tile + ntx - 1] = 1;
+        if (Rr && D && tx + 1 < ntx && tz + 1 < ntz) fl[tile + ntx + 1] = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------------------
+// real: travel-time type (storage, scores, decisions); mreal: wavefront / phase-speed
+// math; oreal: orientation input; outreal: output field.  When real != outreal the
+// relaxation runs on a scratch field that is converted into d_out at the end.
+template <typename real, typename mreal, typename oreal, typename outreal>
+static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats,
+                             int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient,
+                             const ali_node* srcs, int32_t n_src, const ali_options* opt_in,
+                             outreal* d_out, ali_solve_stats* stats) {
+    ali_options opt;
+    ali_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    ali_status st = validate_medium(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src);
+    if (st != ALI_OK) return st;
+    if (!d_out) return H->fail(ALI_EINVAL, "d_T is NULL");
+    if (opt.src_box_radius < 0 || opt.src_box_radius > 64) return H->fail(ALI_EINVAL, "src_box_radius out of range [0, 64]");
+    if (opt.max_sweeps < 1) return H->fail(ALI_EINVAL, "max_sweeps must be >= 1");
+    if (opt.inner_sweeps < 1 || opt.inner_sweeps > 4096) return H->fail(ALI_EINVAL, "inner_sweeps out of range [1, 4096]");
+    if (opt.band_cells < 0) return H->fail(ALI_EINVAL, "band_cells must be >= 0 (0 = no band)");
+
+    const int nx = grid->nx, nz = grid->nz;
+    const int64_t N = (int64_t)nx * nz;
+    const int ntx = (nx + TX - 1) / TX, ntz = (nz + TZ - 1) / TZ;
+    const int64_t nunits = (int64_t)ntx * ntz * n_src;
+    if (nunits >= (int64_t)UINT32_MAX) return H->fail(ALI_EINVAL, "too many tiles in one call");
+    if (set_device(H) != ALI_OK) return ALI_EDEVICE;
+    hipStream_t S = H->stream;
+
+    // device scratch
+    std::vector<MatDev<mreal>> hm(n_mats);
+    for (int k = 0; k < n_mats; ++k) {
+        const ali_material& m = mats[k];
+        const double a11 = m.c11 / m.rho, a13 = m.c13 / m.rho, a33 = m.c33 / m.rho, a55 = m.c55 / m.rho;
+        const double ih2 = 1.0 / (grid->h * grid->h);
+        hm[k].P = (mreal)((a11 + a33 + 2.0 * a55) * ih2);
+        hm[k].Q = (mreal)((a33 - a11) * ih2);
+        hm[k].R = (mreal)((a11 + a33 - 2.0 * a55) * ih2);
+        const double W = (a13 + a55) * ih2;
+        hm[k].K4 = (mreal)(4.0 * W * W);
+        hm[k].A = MatA{a11, a13, a33, a55};
+    }
+    // band step: band_cells node spacings at the fastest phase speed of the medium
+    double vmax = 0.0;
+    for (int k = 0; k < n_mats; ++k)
+        for (int q = 0; q <= 180; ++q) {
+            const double psi = q * (3.14159265358979323846 / 360.0);
+            const double a11 = mats[k].c11 / mats[k].rho, a13 = mats[k].c13 / mats[k].rho;
+            const double a33 = mats[k].c33 / mats[k].rho, a55 = mats[k].c55 / mats[k].rho;
+            const double c = cos(2.0 * psi), sn = sin(2.0 * psi);
+            const double lin = (a33 - a11) + (a11 + a33 - 2.0 * a55) * c;
+            const double v2 = 0.25 * ((a11 + a33 + 2.0 * a55) + (a33 - a11) * c +
+                                      sqrt(lin * lin + 4.0 * (a13 + a55) * (a13 + a55) * sn * sn));
+            if (v2 > vmax * vmax) vmax = sqrt(v2);
+        }
+    const real band = opt.band_cells > 0 ? (real)(opt.band_cells * grid->h / vmax) : dinf_host<real>();
+    std::vector<real> hstep(n_src, band), htheta(n_src, band);
+
+    void *d_mats, *d_geo, *d_fbt, *d_src, *d_flags, *d_list, *d_count, *d_upd, *d_err;
+    void *d_theta, *d_step, *d_minrej, *d_work = nullptr;
+    constexpr bool same_out = std::is_same<real, outreal>::value;
+    if (!same_out && !H->scratch("Twork", sizeof(real) * N * n_src, &d_work))
+        return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+    real* d_T = same_out ? (real*)d_out : (real*)d_work;
+    if (!H->scratch("mats", sizeof(MatDev<mreal>) * n_mats, &d_mats) ||
+        !H->scratch("theta", sizeof(real) * n_src, &d_theta) ||
+        !H->scratch("step", sizeof(real) * n_src, &d_step) ||
+        !H->scratch("minrej", sizeof(real) * nunits, &d_minrej) ||
+        !H->scratch("geo", sizeof(mreal) * 2 * N, &d_geo) ||
+        !H->scratch("fbt", sizeof(real) * 4 * N, &d_fbt) ||
+        !H->scratch("src", sizeof(int2) * n_src, &d_src) ||
+        !H->scratch("flags", (size_t)nunits, &d_flags) ||
+        !H->scratch("list", sizeof(uint32_t) * nunits, &d_list) ||
+        !H->scratch("count", sizeof(uint32_t), &d_count) ||
+        !H->scratch("upd", 2 * sizeof(unsigned long long), &d_upd) ||
+        !H->scratch("err", sizeof(int), &d_err))
+        return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+    std::vector<int2> hs(n_src);
+    for (int k = 0; k < n_src; ++k) hs[k] = make_int2(srcs[k].i, srcs[k].j);
+
+    hipEvent_t e0 = H->ev0, e1 = H->ev1;
+    HIPCK(H, hipEventRecord(e0, S));
+    HIPCK(H, hipMemcpyAsync(d_mats, hm.data(), sizeof(MatDev<mreal>) * n_mats, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemcpyAsync(d_src, hs.data(), sizeof(int2) * n_src, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemcpyAsync(d_theta, htheta.data(), sizeof(real) * n_src, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemcpyAsync(d_step, hstep.data(), sizeof(real) * n_src, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemsetAsync(d_flags, 0, (size_t)nunits, S));
+    HIPCK(H, hipMemsetAsync(d_upd, 0, 2 * sizeof(unsigned long long), S));
+    HIPCK(H, hipMemsetAsync(d_err, 0, sizeof(int), S));
+
+    const int B = 256;
+    hipLaunchKernelGGL((k_fill<real>), dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
+                       (real*)d_minrej, nunits, dinf_host<real>());
+    hipLaunchKernelGGL((k_prep<mreal, real, oreal>), dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S,
+                       nx, nz, grid->h, n_mats, (const MatDev<mreal>*)d_mats, d_mat_id, d_orient,
+                       (mreal*)d_geo, (real*)d_fbt, (int*)d_err);
+    HIPCK(H, hipGetLastError());
+    hipLaunchKernelGGL((k_init<real, mreal, oreal>), dim3((unsigned)((N + B - 1) / B), (unsigned)n_src), dim3(B), 0, S,
+                       nx, nz, n_src, grid->h, (const MatDev<mreal>*)d_mats, d_mat_id,
+                       d_orient, (const int2*)d_src, opt.src_box_radius, d_T,
+                       (uint8_t*)d_flags, ntx, ntz);
+    HIPCK(H, hipGetLastError());
+
+    int h_err = 0;
+    HIPCK(H, hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, S));
+    HIPCK(H, hipStreamSynchronize(S));
+    if (h_err & 1) return H->fail(ALI_EINVAL, "orientation contains NaN or Inf");
+    if (h_err & 2) return H->fail(ALI_EINVAL, "material id out of range");
+
+    int iters = 0;
+    int64_t visits = 0;
+    bool converged = false;
+    double relax_ms = 0.0;
+    bool pending_relax = false;
+    uint32_t* h_count = H->host_count;
+    const int ntiles = ntx * ntz;
+    for (;;) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, S, (uint32_t*)d_count);
+        hipLaunchKernelGGL((k_compact<real>), dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
+                           (uint8_t*)d_flags, (real*)d_minrej, nunits, ntiles, (const real*)d_theta,
+                           (uint32_t*)d_list, (uint32_t*)d_count);
+        HIPCK(H, hipGetLastError());
+        HIPCK(H, hipMemcpyAsync(h_count, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
+        HIPCK(H, hipStreamSynchronize(S));
+        if (pending_relax) {
+            float kms = 0.f;
+            HIPCK(H, hipEventElapsedTime(&kms, H->ev2, H->ev3));
+            relax_ms += kms;
+            pending_relax = false;
+        }
+        const uint32_t n = *h_count;
+        if (n == 0) {
+            // nothing active: jump thresholds to the smallest rejected values, if any
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, S, (uint32_t*)d_count);
+            hipLaunchKernelGGL((k_jump<real>), dim3((unsigned)n_src), dim3(256), 0, S,
+                               (const real*)d_minrej, ntiles, n_src, (real*)d_theta, (uint32_t*)d_count);
+            HIPCK(H, hipGetLastError());
+            HIPCK(H, hipMemcpyAsync(h_count, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
+            HIPCK(H, hipStreamSynchronize(S));
+            if (*h_count == 0) { converged = true; break; }
+            continue;
+        }
+        if (iters >= opt.max_sweeps) break;
+        HIPCK(H, hipEventRecord(H->ev2, S));
+        hipLaunchKernelGGL((k_relax<real, mreal>), dim3(n), dim3(NTHREADS), 0, S,
+                           nx, nz, ntx, ntz, (const uint32_t*)d_list, (const MatDev<mreal>*)d_mats,
+                           d_mat_id, (const mreal*)d_geo, (const real*)d_fbt, (const int2*)d_src,
+                           opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
+                           (uint8_t*)d_flags, (real*)d_minrej, (unsigned long long*)d_upd);
+        HIPCK(H, hipGetLastError());
+        HIPCK(H, hipEventRecord(H->ev3, S));
+        if (opt.band_cells > 0)
+            hipLaunchKernelGGL((k_advance<real>), dim3((unsigned)((n_src + 63) / 64)), dim3(64), 0, S,
+                               (real*)d_theta, (const real*)d_step, n_src);
+        pending_relax = true;
+        ++iters;
+        visits += n;
+    }
+    if (!same_out) {
+        const int64_t tot = N * n_src;
+        hipLaunchKernelGGL((k_convert<outreal, real>), dim3((unsigned)((tot + B - 1) / B)), dim3(B), 0, S,
+                           d_out, (const real*)d_T, tot);
+        HIPCK(H, hipGetLastError());
+    }
+    HIPCK(H, hipEventRecord(e1, S));
+    unsigned long long upd[2] = {0, 0};
+    HIPCK(H, hipMemcpyAsync(upd, d_upd, sizeof(upd), hipMemcpyDeviceToHost, S));
+    HIPCK(H, hipStreamSynchronize(S));
+    if (stats) {
+        float ms = 0.f;
+        HIPCK(H, hipEventElapsedTime(&ms, e0, e1));
+        stats->node_updates = (int64_t)upd[0];
+        stats->stencil_evals = (int64_t)upd[1];
+        stats->relax_ms = relax_ms;
+        stats->tile_visits = visits;
+        stats->nodes = N * n_src;
+        stats->outer_iters = iters;
+        stats->converged = converged ? 1 : 0;
+        stats->ms = ms;
+    }
+    if (!converged) return H->fail(ALI_ENOCONV, "relaxation reached max_sweeps");
+    return ALI_OK;
+}
+
+}  // namespace ali
+
+using namespace ali;
+
+extern "C" ali_status ali_solve_traveltime(ali_handle* h, const ali_grid* grid,
+                                           const ali_material* mats, int32_t n_mats,
+                                           const uint8_t* d_mat_id, const float* d_orient,
+                                           const ali_node* srcs, int32_t n_src,
+                                           const ali_options* opt, float* d_T,
+                                           ali_solve_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
+    switch (arith) {
+        case ALI_ARITH_MIXED:
+            return solve_impl<double, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt, d_T, stats);
+        case ALI_ARITH_F32:
+            return solve_impl<float, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt, d_T, stats);
+        case ALI_ARITH_F64:
+            return solve_impl<double, double, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt, d_T, stats);
+    }
+    return h->fail(ALI_EINVAL, "unknown arith mode");
+}
+
+extern "C" ali_status ali_solve_traveltime_f64(ali_handle* h, const ali_grid* grid,
+                                               const ali_material* mats, int32_t n_mats,
+                                               const uint8_t* d_mat_id, const double* d_orient,
+                                               const ali_node* srcs, int32_t n_src,
+                                               const ali_options* opt, double* d_T,
+                                               ali_solve_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    return solve_impl<double, double, double, double>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt, d_T, stats);
+}

@@ -1,0 +1,53 @@
+"""The C-ABI library loads and exports every symbol that include/*.h declares.
+No compute call is made (no GPU needed)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for hdr in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(hdr).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(ali_\w+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("ali_create", "ali_destroy", "ali_solve_traveltime", "ali_solve_traveltime_f64",
+              "ali_status_string", "ali_last_error", "ali_default_options"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2302_10988_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libali.so is not built")
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_2302_10988_amd import _lib
+    assert declared_functions() <= set(_lib.SIGNATURES)
+
+
+def test_host_only_entry_points():
+    from paper_2302_10988_amd import _lib
+    lib = _lib.load()
+    o = _lib.Options()
+    lib.ali_default_options(ctypes.byref(o))
+    assert o.src_box_radius == 2 and o.inner_sweeps > 0 and o.max_sweeps > 0
+    assert lib.ali_status_string(_lib.ALI_ENOCONV).decode().startswith("relaxation")
+    assert lib.ali_status_string(0).decode() == "ok"
+    assert lib.ali_destroy(None) == _lib.ALI_EINVAL
+    assert lib.ali_create(None, 0, None) == _lib.ALI_EINVAL
