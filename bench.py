@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--workload", default="weld512x64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 256 MiB device copy first (known bytes, to scale HBM counters)")
     return ap.parse_args()
 
 
@@ -71,6 +73,15 @@ def main():
     solver = Solver(0)
     print("bench: workload %s, %d fields of %dx%d, warmup %d, steps %d"
           % (args.workload, len(m.sources), m.nx, m.nz, args.warmup, args.steps), file=sys.stderr, flush=True)
+
+    if args.calib_copy:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print("bench: calibration copy of %d bytes done" % (a.numel() * 4), file=sys.stderr, flush=True)
+        del a, b
 
     for _ in range(args.warmup):
         solver.solve(m.h, m.mats, mid, ori, m.sources, out=out)

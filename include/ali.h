@@ -54,7 +54,7 @@ typedef struct {
     int32_t max_sweeps;      /* cap on outer relaxation passes; default 1000000                 */
     int32_t inner_sweeps;    /* cap on sweeps inside one tile visit; default 64                 */
     int32_t band_cells;      /* width of the relaxation time band in node spacings at the
-                                fastest phase speed; 0 = no band; default 4                   */
+                                fastest phase speed; 0 = no band; default 2                   */
     int32_t ray_window;      /* ray tracer: candidates tested either side of the straight-ahead
                                 intersection (Section 5.1 limits them, no value given); default 8 */
     int32_t ray_max_pts;     /* ray tracer: maximum points per path; default 4096                */

@@ -9,7 +9,7 @@ extern "C" void ali_default_options(ali_options* o) {
     o->src_box_radius = 2;
     o->max_sweeps = 1000000;
     o->inner_sweeps = 64;
-    o->band_cells = 4;
+    o->band_cells = 2;
     o->ray_window = 8;
     o->ray_max_pts = 4096;
     o->arith = ALI_ARITH_MIXED;

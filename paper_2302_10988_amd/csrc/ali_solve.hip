@@ -136,7 +136,7 @@ template <typename real, typename mreal, typename oreal>
 __global__ void k_init(int nx, int nz, int nf, double h, const MatDev<mreal>* __restrict__ mats,
                        const uint8_t* __restrict__ mat_id, const oreal* __restrict__ orient,
                        const int2* __restrict__ src, int R, real* __restrict__ T,
-                       uint8_t* __restrict__ flags, int ntx, int ntz) {
+                       uint32_t* __restrict__ flags, int ntx, int ntz) {
     const int64_t N = (int64_t)nx * nz;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int f = blockIdx.y;
@@ -158,22 +158,24 @@ __global__ void k_init(int nx, int nz, int nf, double h, const MatDev<mreal>* __
     T[(int64_t)f * N + p] = v;
     // tiles that see the box (box radius + diamond radius) start active
     if (abs(di) <= R + HALO && abs(dj) <= R + HALO) {
-        flags[(int64_t)f * ntx * ntz + (j / TZ) * ntx + (i / TX)] = 1;
+        flags[(int64_t)f * ntx * ntz + (j / TZ) * ntx + (i / TX)] = 1u;   // evaluate the whole tile
     }
 }
 
 template <typename real>
-__global__ void k_compact(uint8_t* __restrict__ flags, real* __restrict__ minrej, int64_t n,
+__global__ void k_compact(uint32_t* __restrict__ flags, real* __restrict__ minrej, int64_t n,
                           int ntiles, const real* __restrict__ theta, uint32_t* __restrict__ list,
-                          uint32_t* __restrict__ count) {
+                          uint32_t* __restrict__ lbits, uint32_t* __restrict__ count) {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
     const int f = (int)(u / ntiles);
-    if (flags[u] || minrej[u] <= theta[f]) {
+    const uint32_t b = flags[u];
+    if (b || minrej[u] <= theta[f]) {
         flags[u] = 0;
         minrej[u] = dinf<real>();     // recomputed by the visit
         const uint32_t pos = atomicAdd(count, 1u);
         list[pos] = (uint32_t)u;
+        lbits[pos] = b;
     }
 }
 
@@ -228,21 +230,54 @@ __global__ void k_fill(real* __restrict__ p, int64_t n, real v) {
     if (i < n) p[i] = v;
 }
 
+// flag bits of a tile: which parts of it need evaluation on its next visit
+enum : uint32_t {
+    TF_SELF = 1u,              // everything (first visit, or the previous visit hit the sweep cap)
+    TF_HALO_L = 2u, TF_HALO_R = 4u, TF_HALO_U = 8u, TF_HALO_D = 16u,       // a halo side changed
+    TF_HALO_UL = 32u, TF_HALO_UR = 64u, TF_HALO_DL = 128u, TF_HALO_DR = 256u  // a halo corner changed
+};
+
+template <typename real, typename mreal>
+__device__ __forceinline__ void load_node_const(NodeConst<mreal, real>& nc, int64_t p,
+                                                const MatDev<mreal>* __restrict__ mats,
+                                                const uint8_t* __restrict__ mat_id,
+                                                const mreal* __restrict__ geo,
+                                                const real* __restrict__ fbt) {
+    const MatDev<mreal>& m = mats[mat_id[p]];
+    nc.P = m.P; nc.Q = m.Q; nc.R = m.R; nc.K4 = m.K4;
+    nc.c2t = geo[2 * p + 0];
+    nc.s2t = geo[2 * p + 1];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) nc.fb[d] = fbt[4 * p + d];
+}
+
+// One tile visit.  The set of nodes to evaluate is tracked per node: a node whose value
+// changes marks its diamond neighbours inside the tile for the next sweep, and each sweep
+// packs the marked nodes into the first threads of the block so that idle waves skip the
+// update altogether.  The first sweep evaluates the band front (unreached nodes with a
+// reached neighbour: new arrivals and values rejected by an earlier band), nodes next to
+// a halo side that a neighbouring tile changed, or every node (TF_SELF).
 template <typename real, typename mreal>
 __global__ void __launch_bounds__(NTHREADS)
 k_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
+        const uint32_t* __restrict__ lbits,
         const MatDev<mreal>* __restrict__ mats, const uint8_t* __restrict__ mat_id,
         const mreal* __restrict__ geo, const real* __restrict__ fbt,
         const int2* __restrict__ src, int R, int inner, const real* __restrict__ theta,
-        real* __restrict__ T, uint8_t* __restrict__ flags, real* __restrict__ minrej,
+        real* __restrict__ T, uint32_t* __restrict__ flags, real* __restrict__ minrej,
         unsigned long long* __restrict__ counters) {
     __shared__ real lt[LH * LSTRIDE];
+    __shared__ real rej[NTHREADS];
+    __shared__ uint8_t dirty[2][NTHREADS];
+    __shared__ uint8_t act[NTHREADS];
+    __shared__ uint16_t clist[NTHREADS];
+    __shared__ unsigned wcount[NTHREADS / 64];
     __shared__ real blk_rej;
-    __shared__ unsigned rowmask[3];
-    __shared__ unsigned edge;
+    __shared__ unsigned edge_out;
     __shared__ unsigned blk_updates, blk_evals;
 
     const uint32_t unit = list[blockIdx.x];
+    const uint32_t bits = lbits[blockIdx.x];
     const int ntiles = ntx * ntz;
     const int f = (int)(unit / (uint32_t)ntiles);
     const int tile = (int)(unit % (uint32_t)ntiles);
@@ -251,109 +286,134 @@ k_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
     const int64_t N = (int64_t)nx * nz;
     real* __restrict__ Tf = T + (int64_t)f * N;
     const real inf = dinf<real>();
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
 
     // stage tile + halo
-    for (int q = threadIdx.x; q < LW * LH; q += NTHREADS) {
+    for (int q = tid; q < LW * LH; q += NTHREADS) {
         const int li = q % LW, lj = q / LW;
         const int gi = i0 - HALO + li, gj = j0 - HALO + lj;
         real v = inf;
         if (gi >= 0 && gj >= 0 && gi < nx && gj < nz) v = Tf[(int64_t)gj * nx + gi];
         lt[lj * LSTRIDE + li] = v;
     }
-    if (threadIdx.x < 3) rowmask[threadIdx.x] = 0u;
-    if (threadIdx.x == 0) { edge = 0u; blk_updates = 0u; blk_evals = 0u; blk_rej = inf; }
-
-    const int lx = threadIdx.x % TX, lz = threadIdx.x / TX;
-    const int gi = i0 + lx, gj = j0 + lz;
     const int2 s = src[f];
     const real th = theta[f];
+    // the node this thread owns for bookkeeping
+    const int lx = tid % TX, lz = tid / TX;
+    const int gi = i0 + lx, gj = j0 + lz;
     const bool valid = gi < nx && gj < nz;
-    const bool fixed = abs(gi - s.x) <= R && abs(gj - s.y) <= R;
-    const bool active = valid && !fixed;
-    NodeConst<mreal, real> nc;
-    if (active) {
-        const int64_t p = (int64_t)gj * nx + gi;
-        const MatDev<mreal> m = mats[mat_id[p]];
-        nc.P = m.P; nc.Q = m.Q; nc.R = m.R; nc.K4 = m.K4;
-        nc.c2t = geo[2 * p + 0];
-        nc.s2t = geo[2 * p + 1];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) nc.fb[d] = fbt[4 * p + d];
-    }
+    const bool active = valid && !(abs(gi - s.x) <= R && abs(gj - s.y) <= R);
+    act[tid] = active ? 1 : 0;
+    rej[tid] = inf;
+    if (tid == 0) { edge_out = 0u; blk_updates = 0u; blk_evals = 0u; blk_rej = inf; }
     __syncthreads();
 
     const int me = (lz + HALO) * LSTRIDE + (lx + HALO);
     const real orig = lt[me];
-    const int wave = threadIdx.x / 64;
-    // rows whose changes reach this wave's rows through the diamond
-    const int rlo = wave * (64 / TX) - HALO, rhi = wave * (64 / TX) + (64 / TX) - 1 + HALO;
-    unsigned wrows = 0;
-    for (int r = rlo; r <= rhi; ++r)
-        if (r >= 0 && r < TZ) wrows |= 1u << r;
+    {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) any |= lt[me + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]] < inf;
+        const bool d = (bits & TF_SELF) || !(orig < inf) ||
+                       ((bits & TF_HALO_L) && lx < HALO) || ((bits & TF_HALO_R) && lx >= TX - HALO) ||
+                       ((bits & TF_HALO_U) && lz < HALO) || ((bits & TF_HALO_D) && lz >= TZ - HALO) ||
+                       ((bits & TF_HALO_UL) && lx == 0 && lz == 0) ||
+                       ((bits & TF_HALO_UR) && lx == TX - 1 && lz == 0) ||
+                       ((bits & TF_HALO_DL) && lx == 0 && lz == TZ - 1) ||
+                       ((bits & TF_HALO_DR) && lx == TX - 1 && lz == TZ - 1);
+        dirty[0][tid] = (active && any && d) ? 1 : 0;
+        dirty[1][tid] = 0;
+    }
+    __syncthreads();
 
     unsigned my_updates = 0, my_evals = 0;
-    real my_rej = inf;          // value this node last computed above the band, if any
     bool done = false;
-    int it = 0;
-    for (; it < inner; ++it) {
-        if (threadIdx.x == 0) rowmask[(it + 1) % 3] = 0u;
-        bool ch = false;
-        const bool eval = it == 0 || (rowmask[(it + 2) % 3] & wrows) != 0u;
-        if (eval && active) {
+    for (int it = 0;; ++it) {
+        const int cur = it & 1;
+        // pack the marked nodes
+        const bool d = dirty[cur][tid] != 0;
+        dirty[cur][tid] = 0;
+        const unsigned long long m = __ballot(d);
+        const unsigned below = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wcount[wave] = (unsigned)__popcll(m);
+        __syncthreads();
+        unsigned base = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < NTHREADS / 64; ++w) {
+            const unsigned c = wcount[w];
+            base += w < wave ? c : 0u;
+            total += c;
+        }
+        if (d) clist[base + below] = (uint16_t)tid;
+        __syncthreads();
+        if (total == 0) { done = true; break; }
+        if (it == inner) break;
+        if ((unsigned)tid < total) {
+            const int node = clist[tid];
+            const int nlx = node % TX, nlz = node / TX;
+            const int nme = (nlz + HALO) * LSTRIDE + (nlx + HALO);
+            const int64_t p = (int64_t)(j0 + nlz) * nx + (i0 + nlx);
+            NodeConst<mreal, real> nc;
+            load_node_const<real, mreal>(nc, p, mats, mat_id, geo, fbt);
             real t[12];
 #pragma unroll
-            for (int k = 0; k < 12; ++k) t[k] = lt[me + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]];
-            bool any = false;
+            for (int k = 0; k < 12; ++k) t[k] = lt[nme + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]];
+            ++my_updates;
+            real u = local_update<mreal, real>(nc, t, my_evals);
+            real r = inf;
+            if (u > th && u < inf) { r = u; u = inf; }
+            rej[node] = r;
+            const real cv = lt[nme];
+            if (!(u == cv || (u >= inf && cv >= inf))) {
+                lt[nme] = u;
 #pragma unroll
-            for (int k = 0; k < 12; ++k) any |= t[k] < inf;
-            if (any) {
-                ++my_updates;
-                real u = local_update<mreal, real>(nc, t, my_evals);
-                my_rej = inf;
-                if (u > th && u < inf) { my_rej = u; u = inf; }
-                const real cur = lt[me];
-                if (!(u == cur || (u >= inf && cur >= inf))) {
-                    lt[me] = u;
-                    ch = true;
-                    atomicOr(&rowmask[it % 3], 1u << lz);
+                for (int k = 0; k < 12; ++k) {
+                    const int ax = nlx + SLOT_DI[k], az = nlz + SLOT_DJ[k];
+                    if (ax >= 0 && az >= 0 && ax < TX && az < TZ && act[az * TX + ax])
+                        dirty[cur ^ 1][az * TX + ax] = 1;
                 }
             }
         }
-        if (!__syncthreads_or(ch)) { done = true; break; }
+        __syncthreads();
     }
 
+    // write back, tell neighbouring tiles which of their halo sides changed
     const real fin = lt[me];
     if (valid && !(fin == orig || (fin >= inf && orig >= inf))) {
         Tf[(int64_t)gj * nx + gi] = fin;
         unsigned e = 0;
-        if (lx < HALO) e |= 1u;                 // left
-        if (lx >= TX - HALO) e |= 2u;           // right
-        if (lz < HALO) e |= 4u;                 // up
-        if (lz >= TZ - HALO) e |= 8u;           // down
-        if (e) atomicOr(&edge, e);
+        if (lx < HALO) e |= 1u;
+        if (lx >= TX - HALO) e |= 2u;
+        if (lz < HALO) e |= 4u;
+        if (lz >= TZ - HALO) e |= 8u;
+        if (lx == 0 && lz == 0) e |= 16u;
+        if (lx == TX - 1 && lz == 0) e |= 32u;
+        if (lx == 0 && lz == TZ - 1) e |= 64u;
+        if (lx == TX - 1 && lz == TZ - 1) e |= 128u;
+        if (e) atomicOr(&edge_out, e);
     }
-    // per-block update count
+    if (rej[tid] < inf) lds_min(&blk_rej, rej[tid]);
     if (my_updates) { atomicAdd(&blk_updates, my_updates); atomicAdd(&blk_evals, my_evals); }
-    if (my_rej < inf) lds_min(&blk_rej, my_rej);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         if (blk_updates) {
             atomicAdd(&counters[0], (unsigned long long)blk_updates);
             atomicAdd(&counters[1], (unsigned long long)blk_evals);
         }
-        uint8_t* fl = flags + (int64_t)f * ntiles;
+        uint32_t* fl = flags + (int64_t)f * ntiles;
         minrej[(int64_t)f * ntiles + tile] = blk_rej;
-        const unsigned e = edge;
-        const bool L = e & 1u, Rr = e & 2u, U = e & 4u, D = e & 8u;
-        if (!done) fl[tile] = 1;
-        if (L && tx > 0) fl[tile - 1] = 1;
-        if (Rr && tx + 1 < ntx) fl[tile + 1] = 1;
-        if (U && tz > 0) fl[tile - ntx] = 1;
-        if (D && tz + 1 < ntz) fl[tile + ntx] = 1;
-        if (L && U && tx > 0 && tz > 0) fl[tile - ntx - 1] = 1;
-        if (Rr && U && tx + 1 < ntx && tz > 0) fl[tile - ntx + 1] = 1;
-        if (L && D && tx > 0 && tz + 1 < ntz) fl[tile + ntx - 1] = 1;
-        if (Rr && D && tx + 1 < ntx && tz + 1 < ntz) fl[tile + ntx + 1] = 1;
+        const unsigned e = edge_out;
+        const bool hasL = tx > 0, hasR = tx + 1 < ntx, hasU = tz > 0, hasD = tz + 1 < ntz;
+        if (!done) atomicOr(&fl[tile], TF_SELF);
+        if ((e & 1u) && hasL) atomicOr(&fl[tile - 1], TF_HALO_R);
+        if ((e & 2u) && hasR) atomicOr(&fl[tile + 1], TF_HALO_L);
+        if ((e & 4u) && hasU) atomicOr(&fl[tile - ntx], TF_HALO_D);
+        if ((e & 8u) && hasD) atomicOr(&fl[tile + ntx], TF_HALO_U);
+        if ((e & 16u) && hasL && hasU) atomicOr(&fl[tile - ntx - 1], TF_HALO_DR);
+        if ((e & 32u) && hasR && hasU) atomicOr(&fl[tile - ntx + 1], TF_HALO_DL);
+        if ((e & 64u) && hasL && hasD) atomicOr(&fl[tile + ntx - 1], TF_HALO_UR);
+        if ((e & 128u) && hasR && hasD) atomicOr(&fl[tile + ntx + 1], TF_HALO_UL);
     }
 }
 
@@ -417,7 +477,7 @@ static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     std::vector<real> hstep(n_src, band), htheta(n_src, band);
 
     void *d_mats, *d_geo, *d_fbt, *d_src, *d_flags, *d_list, *d_count, *d_upd, *d_err;
-    void *d_theta, *d_step, *d_minrej, *d_work = nullptr;
+    void *d_theta, *d_step, *d_minrej, *d_lbits, *d_work = nullptr;
     constexpr bool same_out = std::is_same<real, outreal>::value;
     if (!same_out && !H->scratch("Twork", sizeof(real) * N * n_src, &d_work))
         return H->fail(ALI_ENOMEM, "device scratch allocation failed");
@@ -429,8 +489,9 @@ static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_mate
         !H->scratch("geo", sizeof(mreal) * 2 * N, &d_geo) ||
         !H->scratch("fbt", sizeof(real) * 4 * N, &d_fbt) ||
         !H->scratch("src", sizeof(int2) * n_src, &d_src) ||
-        !H->scratch("flags", (size_t)nunits, &d_flags) ||
+        !H->scratch("flags", sizeof(uint32_t) * nunits, &d_flags) ||
         !H->scratch("list", sizeof(uint32_t) * nunits, &d_list) ||
+        !H->scratch("lbits", sizeof(uint32_t) * nunits, &d_lbits) ||
         !H->scratch("count", sizeof(uint32_t), &d_count) ||
         !H->scratch("upd", 2 * sizeof(unsigned long long), &d_upd) ||
         !H->scratch("err", sizeof(int), &d_err))
@@ -444,7 +505,7 @@ static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     HIPCK(H, hipMemcpyAsync(d_src, hs.data(), sizeof(int2) * n_src, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemcpyAsync(d_theta, htheta.data(), sizeof(real) * n_src, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemcpyAsync(d_step, hstep.data(), sizeof(real) * n_src, hipMemcpyHostToDevice, S));
-    HIPCK(H, hipMemsetAsync(d_flags, 0, (size_t)nunits, S));
+    HIPCK(H, hipMemsetAsync(d_flags, 0, sizeof(uint32_t) * nunits, S));
     HIPCK(H, hipMemsetAsync(d_upd, 0, 2 * sizeof(unsigned long long), S));
     HIPCK(H, hipMemsetAsync(d_err, 0, sizeof(int), S));
 
@@ -458,7 +519,7 @@ static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     hipLaunchKernelGGL((k_init<real, mreal, oreal>), dim3((unsigned)((N + B - 1) / B), (unsigned)n_src), dim3(B), 0, S,
                        nx, nz, n_src, grid->h, (const MatDev<mreal>*)d_mats, d_mat_id,
                        d_orient, (const int2*)d_src, opt.src_box_radius, d_T,
-                       (uint8_t*)d_flags, ntx, ntz);
+                       (uint32_t*)d_flags, ntx, ntz);
     HIPCK(H, hipGetLastError());
 
     int h_err = 0;
@@ -477,8 +538,8 @@ static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     for (;;) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, S, (uint32_t*)d_count);
         hipLaunchKernelGGL((k_compact<real>), dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
-                           (uint8_t*)d_flags, (real*)d_minrej, nunits, ntiles, (const real*)d_theta,
-                           (uint32_t*)d_list, (uint32_t*)d_count);
+                           (uint32_t*)d_flags, (real*)d_minrej, nunits, ntiles, (const real*)d_theta,
+                           (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_count);
         HIPCK(H, hipGetLastError());
         HIPCK(H, hipMemcpyAsync(h_count, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
         HIPCK(H, hipStreamSynchronize(S));
@@ -503,10 +564,11 @@ static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_mate
         if (iters >= opt.max_sweeps) break;
         HIPCK(H, hipEventRecord(H->ev2, S));
         hipLaunchKernelGGL((k_relax<real, mreal>), dim3(n), dim3(NTHREADS), 0, S,
-                           nx, nz, ntx, ntz, (const uint32_t*)d_list, (const MatDev<mreal>*)d_mats,
+                           nx, nz, ntx, ntz, (const uint32_t*)d_list, (const uint32_t*)d_lbits,
+                           (const MatDev<mreal>*)d_mats,
                            d_mat_id, (const mreal*)d_geo, (const real*)d_fbt, (const int2*)d_src,
                            opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
-                           (uint8_t*)d_flags, (real*)d_minrej, (unsigned long long*)d_upd);
+                           (uint32_t*)d_flags, (real*)d_minrej, (unsigned long long*)d_upd);
         HIPCK(H, hipGetLastError());
         HIPCK(H, hipEventRecord(H->ev3, S));
         if (opt.band_cells > 0)
