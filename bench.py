@@ -31,6 +31,22 @@ OPS_PER_UPDATE = 138
 OPS_PER_ESTIMATE = 47
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published fp32 vector peak
 
+# HBM traffic of the relaxation kernel from two rocprofv3 --pmc runs (FETCH_SIZE, then
+# WRITE_SIZE; each scaled by the same counter on a 256 MiB device copy in the same program),
+# per launch, for the kernel sources with this hash.  Reported as null once the sources
+# differ (profiles/k_relax_weld512x64.md holds the command and the raw figures).
+TRAFFIC = {"sources_sha256_16": "2b281753796594bc", "fetch_bytes_per_launch": 32.863e6,
+           "write_bytes_per_launch": 2.029e6}
+
+
+def kernel_sources_hash():
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2302_10988_amd", "csrc")
+    data = b"".join(open(p, "rb").read() for p in sorted(glob.glob(os.path.join(csrc, "*.hip"))) +
+                    sorted(glob.glob(os.path.join(csrc, "*.hpp"))))
+    return hashlib.sha256(data).hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -125,7 +141,10 @@ def main():
         "relax_kernel_ms_per_step": tot["relax_ms"] / args.steps,
         "roofline": {"kernel": "k_relax<double,float>", "bound": "alu", "achieved": achieved,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": (TRAFFIC["fetch_bytes_per_launch"] + TRAFFIC["write_bytes_per_launch"]
+                                 if kernel_sources_hash() == TRAFFIC["sources_sha256_16"] else None),
+                     "traffic_unit": "bytes per launch",
                      "avg_launch_ms": tot["relax_ms"] / max(tot["outer_iters"], 1)},
     }
 

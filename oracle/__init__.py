@@ -75,9 +75,8 @@ def _load():
     lib.or_dijkstra_dense.argtypes = [I, I, D, M, P, P, I, I, D, P]
     lib.or_segment_time.argtypes = [I, I, D, M, P, P, D, D, D, D]
     lib.or_segment_time.restype = D
-    if hasattr(lib, "or_trace_ray"):
-        lib.or_trace_ray.argtypes = [I, I, D, M, P, P, P, I, I, I, I, I, I, P, ctypes.POINTER(I), ctypes.POINTER(D)]
-        lib.or_trace_ray.restype = I
+    lib.or_trace_ray.argtypes = [I, I, D, M, P, P, P, I, I, I, I, I, I, I, P, ctypes.POINTER(I), ctypes.POINTER(D)]
+    lib.or_trace_ray.restype = I
     if hasattr(lib, "or_adjoint"):
         lib.or_adjoint.argtypes = [I, I, D, M, I, P, P, I, I, I, P, P, P]
         lib.or_adjoint.restype = I
@@ -236,3 +235,21 @@ def segment_time(h, mats, mat_id, orient, p0, p1):
     nz, nx = mat_id.shape
     return _load().or_segment_time(nx, nz, float(h), _mat_array(mats), _ptr(mat_id), _ptr(orient),
                                    float(p0[0]), float(p0[1]), float(p1[0]), float(p1[1]))
+
+
+# ---------------------------------------------------------------------------------------
+# Section 5.1: ray tracing
+# ---------------------------------------------------------------------------------------
+def trace_ray(h, mats, mat_id, orient, T, src, start, window=4, sub=8, max_pts=4096):
+    """Ray from node `start` to the source `src` of field T.  Returns (points [n, 2] in
+    grid units (x, z), integrated time, reached flag)."""
+    mat_id, orient = _medium(mat_id, orient)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    nz, nx = mat_id.shape
+    pts = np.zeros((max_pts, 2))
+    n = ctypes.c_int()
+    t = ctypes.c_double()
+    st = _load().or_trace_ray(nx, nz, float(h), _mat_array(mats), _ptr(mat_id), _ptr(orient), _ptr(T),
+                              int(src[0]), int(src[1]), int(start[0]), int(start[1]), int(window),
+                              int(sub), int(max_pts), _ptr(pts), ctypes.byref(n), ctypes.byref(t))
+    return pts[: n.value].copy(), t.value, st == 0

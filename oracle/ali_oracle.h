@@ -119,6 +119,16 @@ double or_segment_time(int nx, int nz, double h, const or_material* mats,
                        const uint8_t* mat_id, const double* orient,
                        double x0, double z0, double x1, double z1);
 
+/* ---- Section 5.1: ray tracing ------------------------------------------------------ */
+
+/* Ray from node (ri, rj) to the source (si, sj) of field T (reciprocity).  Candidates
+   are spaced 1/sub node spacing within +-window nodes of the straight-ahead point.  Writes
+   up to max_pts points (x, z in grid units) to pts[2*max_pts], their number to *n_pts
+   and the integrated time to *t_ray.  Returns 0 on success, -1 if S was not reached. */
+int or_trace_ray(int nx, int nz, double h, const or_material* mats, const uint8_t* mat_id,
+                 const double* orient, const double* T, int si, int sj, int ri, int rj,
+                 int window, int sub, int max_pts, double* pts, int* n_pts, double* t_ray);
+
 #ifdef __cplusplus
 }
 #endif

@@ -262,9 +262,15 @@ __device__ __forceinline__ void slow_all(const NodeConst<mreal, real>& n, const 
     (slow_pair<mreal, real, P>(n, t, sb), ...);
 }
 
+// The slow path re-reads the diamond from the caller's staging buffer (LDS) and takes
+// the node constants by value, so the fast path never spills them to the stack.
 template <typename mreal, typename real>
-__device__ __noinline__ real slow_update(const NodeConst<mreal, real>& n, const real (&t)[12]) {
+__device__ __noinline__ real slow_update(const NodeConst<mreal, real> n, const real* __restrict__ lds,
+                                         int me, int stride) {
     const real inf = dinf<real>();
+    real t[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) t[k] = lds[me + SLOT_DJ[k] * stride + SLOT_DI[k]];
     SlotBest<real> sb;
 #pragma unroll
     for (int k = 0; k < 8; ++k) { sb.cls[k] = 3; sb.idx[k] = 99; sb.score[k] = inf; sb.U[k] = inf; }
@@ -310,8 +316,12 @@ __device__ __noinline__ real slow_update(const NodeConst<mreal, real>& n, const 
 // activation key.  If every candidate's value lies above kappa_B, no record activated
 // before B can satisfy the stopping rule, so the heap's answer is B's value.
 // ---------------------------------------------------------------------------------------
+// t: the 12 diamond values (copied from lds[me + dj*stride + di]); the slow path
+// reads them again from lds.
 template <typename mreal, typename real>
-__device__ __forceinline__ real local_update(const NodeConst<mreal, real>& n, const real (&t)[12], unsigned& evals) {
+__device__ __forceinline__ real local_update(const NodeConst<mreal, real>& n, const real (&t)[12],
+                                             const real* __restrict__ lds, int me, int stride,
+                                             unsigned& evals) {
     const real inf = dinf<real>();
     Best<real> best;
     best.cls = 3; best.score = inf; best.U = inf; best.kt = inf; best.ks = 0; best.evals = 0;
@@ -321,7 +331,7 @@ __device__ __forceinline__ real local_update(const NodeConst<mreal, real>& n, co
     evals += best.evals;
     if (best.cls == 3) return inf;
     if (key_after(minU, best.kt, best.ks)) return best.U;
-    return slow_update<mreal, real>(n, t);
+    return slow_update<mreal, real>(n, lds, me, stride);
 }
 
 }  // namespace ali

@@ -360,7 +360,7 @@ k_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
 #pragma unroll
             for (int k = 0; k < 12; ++k) t[k] = lt[nme + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]];
             ++my_updates;
-            real u = local_update<mreal, real>(nc, t, my_evals);
+            real u = local_update<mreal, real>(nc, t, lt, nme, LSTRIDE, my_evals);
             real r = inf;
             if (u > th && u < inf) { r = u; u = inf; }
             rej[node] = r;
