@@ -11,10 +11,11 @@
  *     direction towards S);
  *   - the next plane is the family's plane at the rounded index of the last point plus
  *     one step towards the direction of travel;
- *   - candidates: points of that plane spaced 1/sub of the node spacing, within +-window
- *     nodes of the straight-ahead intersection (the paper samples a finer subgrid and
- *     limits the candidates without giving a number); T at a candidate is linearly
- *     interpolated between the two grid nodes of the plane around it;
+ *   - candidates: points of that plane spaced 1/sub of the node spacing, at offsets
+ *     q/sub, |q| <= window*sub - 1, from the grid node nearest to the straight-ahead
+ *     intersection (the paper samples a finer subgrid and limits the candidates without
+ *     giving a number); T at a candidate is linearly interpolated between the two grid
+ *     nodes of the plane around it;
  *   - segment time: exact walk through the nearest-node cells at the group speed of each
  *     cell (equal to the paper's "orientation of the closest point" inside one cell);
  *   - a parabola through each local minimum of the candidate costs and its two
@@ -65,7 +66,8 @@ int or_trace_ray(int nx, int nz, double h, const or_material* mats, const uint8_
     double dx = si - px, dz = sj - pz;
     int n = 0;
     double tt = 0.0;
-    const int nc = 2 * window * sub + 1;
+    const int half = window * sub - 1;
+    const int nc = 2 * half + 1;
     double* cost = malloc(sizeof(double) * (size_t)nc);
     int* ok = malloc(sizeof(int) * (size_t)nc);
     pts[2 * n] = px; pts[2 * n + 1] = pz; ++n;
@@ -102,7 +104,7 @@ int or_trace_ray(int nx, int nz, double h, const or_material* mats, const uint8_
         fam_node(f, k, 0, &i00, &j00);
         int any = 0;
         for (int q = 0; q < nc; ++q) {
-            double u = m0 - window + (double)q / sub;
+            double u = m0 + (double)(q - half) / sub;
             ok[q] = 0;
             cost[q] = INFINITY;
             double tc = plane_T(nx, nz, T, f, k, u);
@@ -133,7 +135,7 @@ int or_trace_ray(int nx, int nz, double h, const or_material* mats, const uint8_
             if (v < bestv) { bestv = v; bestpos = pos; bestq = q; }
         }
         if (bestq < 0) break;
-        double ub = m0 - window + ((double)bestq + bestpos) / sub;
+        double ub = m0 + ((double)(bestq - half) + bestpos) / sub;
         double qx = i00 + ub * FAM_E[f][0], qz = j00 + ub * FAM_E[f][1];
         tt += or_segment_time(nx, nz, h, mats, mat_id, orient, px, pz, qx, qz);
         dx = qx - px; dz = qz - pz;
