@@ -2,7 +2,8 @@
 
 One step = one pass of the hot path over one batch: the 512x512 synthetic V-weld with 64
 top-surface sources solved in one batched relaxation (the paper's forward modeller,
-Sections 2-4), FP32, inputs resident in HBM.
+Sections 2-4), then the 64 x 64 ray paths from 64 bottom receivers to every source
+through those fields (Section 5.1); float32 output, inputs resident in HBM.
 
 Prints one JSON line.  `value` is node updates per second (one update = one evaluation
 of the local ALI update at one node).  Alongside: fields/s, solved nodes/s, redundancy,
@@ -86,6 +87,7 @@ def main():
     mid = torch.from_numpy(m.mat_id).to(dev)
     ori = torch.from_numpy(m.orient).to(torch.float32).to(dev)
     out = torch.empty((len(m.sources), m.nz, m.nx), dtype=torch.float32, device=dev)
+    rays = len(m.receivers) > 0
     solver = Solver(0)
     print("bench: workload %s, %d fields of %dx%d, warmup %d, steps %d"
           % (args.workload, len(m.sources), m.nx, m.nz, args.warmup, args.steps), file=sys.stderr, flush=True)
@@ -99,14 +101,21 @@ def main():
         print("bench: calibration copy of %d bytes done" % (a.numel() * 4), file=sys.stderr, flush=True)
         del a, b
 
+    def step():
+        _, st = solver.solve(m.h, m.mats, mid, ori, m.sources, out=out)
+        tr = None
+        if rays:
+            tr = solver.trace_rays(m.h, m.mats, mid, ori, out, m.sources, m.receivers)
+        return st, tr
+
     for _ in range(args.warmup):
-        solver.solve(m.h, m.mats, mid, ori, m.sources, out=out)
+        step()
     torch.cuda.synchronize()
 
     tot = dict(node_updates=0, stencil_evals=0, outer_iters=0, relax_ms=0.0, nodes=0, tile_visits=0)
     t0 = time.perf_counter()
     for k in range(args.steps):
-        _, st = solver.solve(m.h, m.mats, mid, ori, m.sources, out=out)
+        st, tr = step()
         for key in tot:
             tot[key] += st[key]
         print("bench: step %d done, %d passes, %.2f ms" % (k, st["outer_iters"], st["ms"]), file=sys.stderr, flush=True)
@@ -130,10 +139,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 wavefront math, f64 travel times",
         "data": "synthetic",
-        "config": {"workload": "V-weld %dx%d, h=%.1f mm, %d top sources, batched forward solve"
-                               % (m.nx, m.nz, m.h * 1e3, len(m.sources)),
+        "config": {"workload": "V-weld %dx%d, h=%.1f mm, %d top sources: batched forward solve + %d x %d ray paths"
+                               % (m.nx, m.nz, m.h * 1e3, len(m.sources), len(m.sources), len(m.receivers)),
                    "grid": [m.nz, m.nx], "fields_per_step": len(m.sources), "src_box_radius": 2},
         "fields_per_s": n_fields / el,
+        "rays_per_s": (len(m.sources) * len(m.receivers) * args.steps / el) if rays else None,
         "solved_nodes_per_s": tot["nodes"] / el,
         "redundancy_updates_per_node": tot["node_updates"] / max(tot["nodes"], 1),
         "stencil_estimates_per_update": tot["stencil_evals"] / max(tot["node_updates"], 1),

@@ -55,11 +55,13 @@ typedef struct {
     int32_t inner_sweeps;    /* cap on sweeps inside one tile visit; default 64                 */
     int32_t band_cells;      /* width of the relaxation time band in node spacings at the
                                 fastest phase speed; 0 = no band; default 2                   */
-    int32_t ray_window;      /* ray tracer: candidates tested either side of the straight-ahead
-                                intersection (Section 5.1 limits them, no value given); default 8 */
+    int32_t ray_window;      /* ray tracer: candidate window either side of the straight-ahead
+                                intersection, in node spacings (Section 5.1 limits the candidates,
+                                no value given); default 4                                      */
     int32_t ray_max_pts;     /* ray tracer: maximum points per path; default 4096                */
     int32_t arith;           /* float32 entry points: ALI_ARITH_MIXED (default), _F32 or _F64     */
-    int32_t reserved;
+    int32_t ray_sub;         /* ray tracer: candidates per node spacing along a plane (the paper's
+                                finer subgrid); ray_window * ray_sub <= 32; default 8             */
 } ali_options;
 
 /* Arithmetic of the float32 entry points.  MIXED keeps travel times, scores and every
@@ -122,6 +124,28 @@ ali_status ali_solve_traveltime_f64(ali_handle* h, const ali_grid* grid,
                                     const ali_node* srcs, int32_t n_src,
                                     const ali_options* opt, double* d_T,
                                     ali_solve_stats* stats);
+
+/* Ray paths through finished fields (paper Section 5.1): for every source s and receiver
+   r, the fastest path from r to s through field s (reciprocity), built plane by plane with
+   the adaptive plane family, Fermat's principle on sampled candidates and a parabola
+   through each local minimum; stops within 1.6 node spacings of the source.
+     d_T            [n_src][nz][nx] fields (float32; _f64: float64), e.g. from
+                    ali_solve_traveltime with the same sources
+     recv[n_recv]   receiver nodes (host), inside the grid
+     d_paths        [n_src][n_recv][ray_max_pts] (x, z) float pairs in grid units
+     d_npts         [n_src][n_recv] number of points; negative if the ray stopped before
+                    reaching the source (ray_max_pts or no usable candidate)
+     d_tray         [n_src][n_recv] travel time integrated along the path [s]
+   Segment times walk the nearest-node cells at the exact group speed of each cell's
+   material and orientation (tabulated at 2048 angles per material). */
+ali_status ali_trace_rays(ali_handle* h, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
+                          const uint8_t* d_mat_id, const float* d_orient, const float* d_T,
+                          const ali_node* srcs, int32_t n_src, const ali_node* recv, int32_t n_recv,
+                          const ali_options* opt, float* d_paths, int32_t* d_npts, float* d_tray);
+ali_status ali_trace_rays_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
+                              const uint8_t* d_mat_id, const float* d_orient, const double* d_T,
+                              const ali_node* srcs, int32_t n_src, const ali_node* recv, int32_t n_recv,
+                              const ali_options* opt, float* d_paths, int32_t* d_npts, float* d_tray);
 
 #ifdef __cplusplus
 }

@@ -134,3 +134,34 @@ class Solver:
                 p_T, ctypes.byref(stats))
         self._check(st)
         return out, stats.as_dict()
+
+    def trace_rays(self, h, mats, mat_id, orient, T, sources, receivers, window=None, sub=None,
+                   max_pts=None):
+        """Ray paths from every receiver to every source through the fields T
+        [n_src, nz, nx] (float32 or float64 device tensor).  Returns (paths [n_src, n_rec,
+        max_pts, 2] float32 grid coordinates, npts [n_src, n_rec] int32 (negative: source
+        not reached), tray [n_src, n_rec] float32 seconds)."""
+        import torch
+        nz, nx = mat_id.shape
+        m_arr, nm = _materials(mats)
+        s_arr, ns = _nodes(sources)
+        r_arr, nr = _nodes(receivers)
+        g = _lib.Grid(int(nx), int(nz), float(h))
+        opt = default_options(ray_window=window, ray_sub=sub, ray_max_pts=max_pts)
+        dev = mat_id.device
+        paths = torch.empty((ns, nr, opt.ray_max_pts, 2), dtype=torch.float32, device=dev)
+        npts = torch.empty((ns, nr), dtype=torch.int32, device=dev)
+        tray = torch.empty((ns, nr), dtype=torch.float32, device=dev)
+        p_id = _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id")
+        p_or = _dev_ptr(orient, torch.float32, (nz, nx), "orient")
+        if T.dtype == torch.float64:
+            fn, tdt = self._lib.ali_trace_rays_f64, torch.float64
+        else:
+            fn, tdt = self._lib.ali_trace_rays, torch.float32
+        p_T = _dev_ptr(T, tdt, (ns, nz, nx), "T")
+        self._sync_stream()
+        st = fn(self._h, ctypes.byref(g), m_arr, nm, p_id, p_or, p_T, s_arr, ns, r_arr, nr,
+                ctypes.byref(opt), _dev_ptr(paths, torch.float32), _dev_ptr(npts, torch.int32),
+                _dev_ptr(tray, torch.float32))
+        self._check(st)
+        return paths, npts, tray

@@ -30,7 +30,7 @@ class Options(ctypes.Structure):
     _fields_ = [("src_box_radius", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("inner_sweeps", ctypes.c_int32), ("band_cells", ctypes.c_int32),
                 ("ray_window", ctypes.c_int32), ("ray_max_pts", ctypes.c_int32),
-                ("arith", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("arith", ctypes.c_int32), ("ray_sub", ctypes.c_int32)]
 
 ARITH = {"mixed": 0, "f32": 1, "f64": 2}
 
@@ -61,6 +61,12 @@ SIGNATURES = {
     "ali_solve_traveltime_f64": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32,
                                                 _P, _P, ctypes.POINTER(Node), _I32,
                                                 ctypes.POINTER(Options), _P, ctypes.POINTER(SolveStats)]),
+    "ali_trace_rays": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P, _P, _P,
+                                      ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32,
+                                      ctypes.POINTER(Options), _P, _P, _P]),
+    "ali_trace_rays_f64": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P, _P, _P,
+                                          ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32,
+                                          ctypes.POINTER(Options), _P, _P, _P]),
 }
 
 _lib = None

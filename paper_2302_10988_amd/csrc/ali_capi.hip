@@ -10,10 +10,10 @@ extern "C" void ali_default_options(ali_options* o) {
     o->max_sweeps = 1000000;
     o->inner_sweeps = 64;
     o->band_cells = 2;
-    o->ray_window = 8;
+    o->ray_window = 4;
     o->ray_max_pts = 4096;
     o->arith = ALI_ARITH_MIXED;
-    o->reserved = 0;
+    o->ray_sub = 8;
 }
 
 extern "C" ali_status ali_create(ali_handle** out, int device, void* hip_stream) {

@@ -1,0 +1,307 @@
+// ali_rays.hip -- ray tracing through finished travel-time fields (paper Section 5.1).
+//
+// A ray runs from a receiver to the source of a field: by reciprocity the field value at
+// a point is the time from that point to the source.  Each step chooses the plane family
+// (x = k, z = k, x + z = k, x - z = k) that makes the largest angle with the last segment,
+// moves to the family's next plane through grid nodes, and picks the point of that plane
+// that minimises  straight-segment time + field time  (Fermat): a parabola through each
+// local minimum of the sampled costs and its two neighbours, the smallest vertex wins.
+// The ray stops within 1.6 node spacings of the source.
+//
+// GPU mapping: one wave per ray, one candidate per lane (2 * window * sub - 1 <= 63
+// candidates spaced 1/sub of a node, field linearly interpolated along the plane);
+// neighbours, local minima and the arg-min use wave shuffles, so a step costs one
+// segment walk per lane plus a few cross-lane reductions.  The segment walk crosses the
+// nearest-node cells and sums length / group speed; the group slowness comes from a
+// per-material table over the group angle (2048 intervals on [0, pi/2], linear
+// interpolation) built by exact inversion in float64.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <vector>
+
+#include "ali_handle.hpp"
+#include "ali_velocity.hpp"
+#include "../../include/ali.h"
+
+namespace ali {
+
+constexpr int GT_N = 2048;                 // table intervals over [0, pi/2]
+constexpr double HALF_PI = 1.57079632679489661923;
+
+__global__ void k_gtable(const MatA* __restrict__ mats, int n_mats, float* __restrict__ tab) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (q > GT_N || m >= n_mats) return;
+    const double phi = HALF_PI * (double)q / GT_N;
+    tab[(int64_t)m * (GT_N + 1) + q] = (float)(1.0 / group_speed(mats[m], phi));
+}
+
+struct RayMedium {
+    int nx, nz;
+    double h;
+    const uint8_t* mat_id;
+    const float* orient;
+    const float* tab;                      // [n_mats][GT_N + 1] group slowness [s/m]
+};
+
+__device__ __forceinline__ float group_slowness(const RayMedium& M, int64_t p, float ang) {
+    // reduce the angle against the cell's symmetry axis to [0, pi/2]
+    float a = fabsf(ang - M.orient[p]);
+    a = fmodf(a, 3.14159265358979f);
+    if (a > 1.57079632679490f) a = 3.14159265358979f - a;
+    const float x = a * (float)(GT_N / HALF_PI);
+    int i = (int)x;
+    i = i < 0 ? 0 : (i >= GT_N ? GT_N - 1 : i);
+    const float w = x - (float)i;
+    const float* t = M.tab + (int64_t)M.mat_id[p] * (GT_N + 1);
+    return t[i] + w * (t[i + 1] - t[i]);
+}
+
+// straight-segment time from (x0,z0) to (x1,z1) [grid units] through the nearest-node
+// cells: cut at the cell boundaries k + 1/2, each piece at its midpoint cell's speed
+__device__ double segment_time(const RayMedium& M, double x0, double z0, double x1, double z1) {
+    const double dx = x1 - x0, dz = z1 - z0;
+    const double len = sqrt(dx * dx + dz * dz);
+    if (len == 0.0) return 0.0;
+    const float ang = atan2f((float)dz, (float)dx);
+    // next boundary crossings along x and z
+    double tx = 2.0, tz = 2.0, sx = 0.0, sz = 0.0;
+    if (dx != 0.0) {
+        const double b = dx > 0.0 ? floor(x0 + 0.5) + 0.5 : floor(x0 + 0.5) - 0.5;
+        tx = (b - x0) / dx;
+        sx = 1.0 / fabs(dx);
+    }
+    if (dz != 0.0) {
+        const double b = dz > 0.0 ? floor(z0 + 0.5) + 0.5 : floor(z0 + 0.5) - 0.5;
+        tz = (b - z0) / dz;
+        sz = 1.0 / fabs(dz);
+    }
+    double t = 0.0, total = 0.0;
+    for (int guard = 0; guard < 4096 && t < 1.0; ++guard) {
+        double tn = tx < tz ? tx : tz;
+        if (tn > 1.0) tn = 1.0;
+        if (tn > t) {
+            const double tm = 0.5 * (t + tn);
+            int ci = (int)floor(x0 + tm * dx + 0.5), cj = (int)floor(z0 + tm * dz + 0.5);
+            ci = ci < 0 ? 0 : (ci >= M.nx ? M.nx - 1 : ci);
+            cj = cj < 0 ? 0 : (cj >= M.nz ? M.nz - 1 : cj);
+            total += (tn - t) * len * M.h * (double)group_slowness(M, (int64_t)cj * M.nx + ci, ang);
+        }
+        t = tn;
+        if (tx <= tn) tx += sx;
+        if (tz <= tn) tz += sz;
+    }
+    return total;
+}
+
+// plane families: normal N and step E between consecutive nodes of one plane
+__device__ __forceinline__ void fam(int f, int& nxf, int& nzf, int& ex, int& ez) {
+    switch (f) {
+        case 0: nxf = 1; nzf = 0; ex = 0; ez = 1; break;     // x = k
+        case 1: nxf = 0; nzf = 1; ex = 1; ez = 0; break;     // z = k
+        case 2: nxf = 1; nzf = 1; ex = 1; ez = -1; break;    // x + z = k
+        default: nxf = 1; nzf = -1; ex = 1; ez = 1; break;   // x - z = k
+    }
+}
+// grid node of parameter m on plane k of family f
+__device__ __forceinline__ void fam_node(int f, int k, int m, int& i, int& j) {
+    switch (f) {
+        case 0: i = k; j = m; break;
+        case 1: i = m; j = k; break;
+        case 2: i = m; j = k - m; break;
+        default: i = m; j = m - k; break;
+    }
+}
+
+template <typename treal>
+__device__ __forceinline__ double field_at(const treal* __restrict__ T, int nx, int nz, int i, int j) {
+    if (i < 0 || j < 0 || i >= nx || j >= nz) return INFINITY;
+    return (double)T[(int64_t)j * nx + i];
+}
+
+template <typename treal>
+__global__ void __launch_bounds__(64)
+k_trace(RayMedium M, const treal* __restrict__ Tall, const int2* __restrict__ srcs,
+        const int2* __restrict__ recv, int n_recv, int window, int sub, int max_pts,
+        float2* __restrict__ paths, int32_t* __restrict__ npts, float* __restrict__ tray) {
+    const int r = blockIdx.x;
+    const int s = r / n_recv, k = r % n_recv;
+    const int lane = threadIdx.x;
+    const int64_t N = (int64_t)M.nx * M.nz;
+    const treal* __restrict__ T = Tall + (int64_t)s * N;
+    float2* __restrict__ path = paths + (int64_t)r * max_pts;
+    const int2 S = srcs[s], R0 = recv[k];
+    const int half = window * sub - 1, nc = 2 * half + 1;
+    double px = R0.x, pz = R0.y;
+    double dx = S.x - px, dz = S.y - pz;
+    double tt = 0.0;
+    int n = 0;
+    if (lane == 0) path[0] = make_float2((float)px, (float)pz);
+    ++n;
+    bool reached = false;
+    for (int guard = 0; guard < max_pts; ++guard) {
+        if (hypot(px - S.x, pz - S.y) < 1.6) {
+            if (px != S.x || pz != S.y) {
+                tt += segment_time(M, px, pz, S.x, S.y);
+                if (lane == 0) path[n] = make_float2((float)S.x, (float)S.y);
+                ++n;
+            }
+            reached = true;
+            break;
+        }
+        if (n + 1 >= max_pts) break;
+        // family making the largest angle with the direction of travel (first wins ties)
+        int f = 0;
+        double best = 2.0;
+        const double dl = sqrt(dx * dx + dz * dz);
+        for (int q = 0; q < 4; ++q) {
+            int a, b, ex, ez;
+            fam(q, a, b, ex, ez);
+            const double c = fabs(dx * ex + dz * ez) / (dl * sqrt((double)(ex * ex + ez * ez)));
+            if (c < best) { best = c; f = q; }
+        }
+        int fnx, fnz, ex, ez;
+        fam(f, fnx, fnz, ex, ez);
+        const double dn = dx * fnx + dz * fnz;
+        const int sgn = dn > 0.0 ? 1 : -1;
+        const double ip = px * fnx + pz * fnz;
+        const int kk = (int)floor(ip + 0.5) + sgn;
+        const double st = (kk - ip) / dn;
+        const double xs = px + st * dx, zs = pz + st * dz;
+        const int m0 = (int)floor((f == 0 ? zs : xs) + 0.5);
+        int i00, j00;
+        fam_node(f, kk, 0, i00, j00);
+        // this lane's candidate
+        double cost = INFINITY;
+        const bool mine = lane < nc;
+        if (mine) {
+            const double u = m0 + (double)(lane - half) / sub;
+            const int mf = (int)floor(u);
+            const double w = u - mf;
+            int ia, ja, ib, jb;
+            fam_node(f, kk, mf, ia, ja);
+            fam_node(f, kk, mf + 1, ib, jb);
+            double tc = field_at<treal>(T, M.nx, M.nz, ia, ja);
+            if (w != 0.0) {
+                const double t1 = field_at<treal>(T, M.nx, M.nz, ib, jb);
+                tc = (1.0 - w) * tc + w * t1;
+            }
+            if (tc < INFINITY) cost = segment_time(M, px, pz, i00 + u * ex, j00 + u * ez) + tc;
+        }
+        // neighbours' costs
+        double cm = __shfl_up(cost, 1);
+        double cp = __shfl_down(cost, 1);
+        if (lane == 0) cm = INFINITY;
+        if (lane >= nc - 1) cp = INFINITY;
+        const bool ok = cost < INFINITY, lok = cm < INFINITY, rok = cp < INFINITY;
+        double v = INFINITY, pos = 0.0;
+        if (mine && ok && (!lok || cost < cm) && (!rok || cost <= cp)) {
+            v = cost;
+            if (lok && rok) {
+                const double den = cm - 2.0 * cost + cp;
+                if (den > 0.0) {
+                    pos = 0.5 * (cm - cp) / den;
+                    v = cost - 0.125 * (cp - cm) * (cp - cm) / den;
+                }
+            }
+        }
+        // arg-min over lanes: smallest value, then lowest lane
+        double bv = v;
+        int bl = lane;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off);
+            const int ol = __shfl_xor(bl, off);
+            if (ov < bv || (ov == bv && ol < bl)) { bv = ov; bl = ol; }
+        }
+        if (!(bv < INFINITY)) break;
+        const double bpos = __shfl(pos, bl);
+        const double ub = m0 + ((double)(bl - half) + bpos) / sub;
+        const double qx = i00 + ub * ex, qz = j00 + ub * ez;
+        tt += segment_time(M, px, pz, qx, qz);
+        dx = qx - px; dz = qz - pz;
+        px = qx; pz = qz;
+        if (lane == 0) path[n] = make_float2((float)px, (float)pz);
+        ++n;
+    }
+    if (lane == 0) {
+        npts[r] = reached ? n : -n;
+        tray[r] = (float)tt;
+    }
+}
+
+template <typename treal>
+static ali_status trace_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
+                             const uint8_t* d_mat_id, const float* d_orient, const treal* d_T,
+                             const ali_node* srcs, int32_t n_src, const ali_node* recv, int32_t n_recv,
+                             const ali_options* opt_in, float* d_paths, int32_t* d_npts, float* d_tray) {
+    ali_options opt;
+    ali_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    ali_status st = validate_medium(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src);
+    if (st != ALI_OK) return st;
+    if (!d_T || !d_paths || !d_npts || !d_tray) return H->fail(ALI_EINVAL, "ray output or field pointer is NULL");
+    if (!recv || n_recv < 1) return H->fail(ALI_EINVAL, "need at least one receiver");
+    for (int k = 0; k < n_recv; ++k)
+        if (recv[k].i < 0 || recv[k].j < 0 || recv[k].i >= grid->nx || recv[k].j >= grid->nz)
+            return H->fail(ALI_EINVAL, "receiver " + std::to_string(k) + " outside the grid");
+    if (opt.ray_window < 1 || opt.ray_sub < 1 || opt.ray_window * opt.ray_sub > 32)
+        return H->fail(ALI_EINVAL, "ray_window * ray_sub must be in [1, 32]");
+    if (opt.ray_max_pts < 2) return H->fail(ALI_EINVAL, "ray_max_pts must be >= 2");
+    if ((int64_t)n_src * n_recv > (int64_t)1 << 30) return H->fail(ALI_EINVAL, "too many rays");
+    if (set_device(H) != ALI_OK) return ALI_EDEVICE;
+    hipStream_t S = H->stream;
+
+    std::vector<MatA> hm(n_mats);
+    for (int k = 0; k < n_mats; ++k)
+        hm[k] = MatA{mats[k].c11 / mats[k].rho, mats[k].c13 / mats[k].rho, mats[k].c33 / mats[k].rho,
+                     mats[k].c55 / mats[k].rho};
+    std::vector<int2> hs(n_src), hr(n_recv);
+    for (int k = 0; k < n_src; ++k) hs[k] = make_int2(srcs[k].i, srcs[k].j);
+    for (int k = 0; k < n_recv; ++k) hr[k] = make_int2(recv[k].i, recv[k].j);
+    void *d_ma, *d_tab, *d_src, *d_rec;
+    if (!H->scratch("ray_mats", sizeof(MatA) * n_mats, &d_ma) ||
+        !H->scratch("ray_tab", sizeof(float) * (GT_N + 1) * n_mats, &d_tab) ||
+        !H->scratch("ray_src", sizeof(int2) * n_src, &d_src) ||
+        !H->scratch("ray_rec", sizeof(int2) * n_recv, &d_rec))
+        return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+    HIPCK(H, hipMemcpyAsync(d_ma, hm.data(), sizeof(MatA) * n_mats, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemcpyAsync(d_src, hs.data(), sizeof(int2) * n_src, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemcpyAsync(d_rec, hr.data(), sizeof(int2) * n_recv, hipMemcpyHostToDevice, S));
+    hipLaunchKernelGGL(k_gtable, dim3((GT_N + 1 + 255) / 256, (unsigned)n_mats), dim3(256), 0, S,
+                       (const MatA*)d_ma, n_mats, (float*)d_tab);
+    HIPCK(H, hipGetLastError());
+    RayMedium M{grid->nx, grid->nz, grid->h, d_mat_id, d_orient, (const float*)d_tab};
+    const int n_rays = n_src * n_recv;
+    hipLaunchKernelGGL((k_trace<treal>), dim3((unsigned)n_rays), dim3(64), 0, S, M, d_T,
+                       (const int2*)d_src, (const int2*)d_rec, n_recv, opt.ray_window, opt.ray_sub,
+                       opt.ray_max_pts, (float2*)d_paths, d_npts, d_tray);
+    HIPCK(H, hipGetLastError());
+    // the host arrays above must outlive the asynchronous copies
+    HIPCK(H, hipStreamSynchronize(S));
+    return ALI_OK;
+}
+
+}  // namespace ali
+
+using namespace ali;
+
+extern "C" ali_status ali_trace_rays(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                     int32_t n_mats, const uint8_t* d_mat_id, const float* d_orient,
+                                     const float* d_T, const ali_node* srcs, int32_t n_src,
+                                     const ali_node* recv, int32_t n_recv, const ali_options* opt,
+                                     float* d_paths, int32_t* d_npts, float* d_tray) {
+    if (!h) return ALI_EINVAL;
+    return trace_impl<float>(h, grid, mats, n_mats, d_mat_id, d_orient, d_T, srcs, n_src, recv, n_recv,
+                             opt, d_paths, d_npts, d_tray);
+}
+
+extern "C" ali_status ali_trace_rays_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                         int32_t n_mats, const uint8_t* d_mat_id, const float* d_orient,
+                                         const double* d_T, const ali_node* srcs, int32_t n_src,
+                                         const ali_node* recv, int32_t n_recv, const ali_options* opt,
+                                         float* d_paths, int32_t* d_npts, float* d_tray) {
+    if (!h) return ALI_EINVAL;
+    return trace_impl<double>(h, grid, mats, n_mats, d_mat_id, d_orient, d_T, srcs, n_src, recv, n_recv,
+                              opt, d_paths, d_npts, d_tray);
+}
