@@ -77,9 +77,15 @@ def _load():
     lib.or_segment_time.restype = D
     lib.or_trace_ray.argtypes = [I, I, D, M, P, P, P, I, I, I, I, I, I, I, P, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.or_trace_ray.restype = I
-    if hasattr(lib, "or_adjoint"):
-        lib.or_adjoint.argtypes = [I, I, D, M, I, P, P, I, I, I, P, P, P]
-        lib.or_adjoint.restype = I
+    lib.or_adjoint.argtypes = [I, I, D, M, I, P, P, I, I, I, P, P, P]
+    lib.or_adjoint.restype = I
+    lib.or_qp_phase_speed_deriv.argtypes = [M, D]
+    lib.or_qp_phase_speed_deriv.restype = D
+    lib.or_qp_group_speed_deriv.argtypes = [M, D]
+    lib.or_qp_group_speed_deriv.restype = D
+    lib.or_stencil_partials.argtypes = [M, D, D, ctypes.POINTER(I), D, D, D] + [ctypes.POINTER(D)] * 4
+    lib.or_field_choices.argtypes = [I, I, D, M, P, P, P, P, P]
+    lib.or_frozen_field.argtypes = [I, I, D, M, P, P, I, I, I, P, P, ctypes.c_int64, P]
     _lib = lib
     return lib
 
@@ -253,3 +259,58 @@ def trace_ray(h, mats, mat_id, orient, T, src, start, window=4, sub=8, max_pts=4
                               int(src[0]), int(src[1]), int(start[0]), int(start[1]), int(window),
                               int(sub), int(max_pts), _ptr(pts), ctypes.byref(n), ctypes.byref(t))
     return pts[: n.value].copy(), t.value, st == 0
+
+
+# ---------------------------------------------------------------------------------------
+# gradient with respect to orientation
+# ---------------------------------------------------------------------------------------
+def qp_phase_speed_deriv(mat, th_p):
+    return _load().or_qp_phase_speed_deriv(_mat_array([mat]), float(th_p))
+
+
+def qp_group_speed_deriv(mat, phi):
+    return _load().or_qp_group_speed_deriv(_mat_array([mat]), float(phi))
+
+
+def stencil_partials(mat, theta_ax, h, offsets, ta, tb, tc):
+    off = (ctypes.c_int * 6)(*[int(v) for p in offsets for v in p])
+    out = [ctypes.c_double() for _ in range(4)]
+    _load().or_stencil_partials(_mat_array([mat]), float(theta_ax), float(h), off, float(ta), float(tb),
+                                float(tc), *[ctypes.byref(o) for o in out])
+    return tuple(o.value for o in out)
+
+
+def adjoint(h, mats, mat_id, orient, src, g, R=2):
+    """(T, dL/dtheta) for one source given g = dL/dT [nz, nx]."""
+    mat_id, orient = _medium(mat_id, orient)
+    nz, nx = mat_id.shape
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    T = np.empty((nz, nx))
+    dth = np.empty((nz, nx))
+    st = _load().or_adjoint(nx, nz, float(h), _mat_array(mats), len(list(mats)), _ptr(mat_id), _ptr(orient),
+                            int(src[0]), int(src[1]), int(R), _ptr(g), _ptr(T), _ptr(dth))
+    if st != 0:
+        raise ValueError("oracle: invalid input")
+    return T, dth
+
+
+def frozen_setup(h, mats, mat_id, orient, src, R=2):
+    """Pop order and choices of the solution (for frozen-choice re-evaluation)."""
+    mat_id, orient = _medium(mat_id, orient)
+    nz, nx = mat_id.shape
+    T, pops, _ = solve_fmm(h, mats, mat_id, orient, src, R, return_pops=True)
+    _, fixed = source_box(h, mats, mat_id, orient, src, R)
+    choice = np.empty((nz, nx), np.int32)
+    _load().or_field_choices(nx, nz, float(h), _mat_array(mats), _ptr(mat_id), _ptr(orient), _ptr(T),
+                             _ptr(np.ascontiguousarray(fixed)), _ptr(choice))
+    return T, np.ascontiguousarray(pops), choice
+
+
+def frozen_field(h, mats, mat_id, orient, src, choice, pops, R=2):
+    mat_id, orient = _medium(mat_id, orient)
+    nz, nx = mat_id.shape
+    T = np.empty((nz, nx))
+    _load().or_frozen_field(nx, nz, float(h), _mat_array(mats), _ptr(mat_id), _ptr(orient), int(src[0]),
+                            int(src[1]), int(R), _ptr(np.ascontiguousarray(choice, dtype=np.int32)),
+                            _ptr(pops), len(pops), _ptr(T))
+    return T

@@ -44,6 +44,12 @@ double or_qp_phase_speed(const or_material* m, double th_p);
    c22 axis and the group speed [m/s]. */
 void or_qp_group_from_phase(const or_material* m, double th_p, double* g_angle, double* g_speed);
 
+/* derivative of the qP phase speed with respect to th_p (closed form). */
+double or_qp_phase_speed_deriv(const or_material* m, double th_p);
+
+/* derivative of the qP group speed with respect to the group angle (numerical). */
+double or_qp_group_speed_deriv(const or_material* m, double phi);
+
 /* qP group speed [m/s] along group angle phi [rad] from the c22 axis, by inverting the
    phase->group angle map with bisection (exact to rounding). */
 double or_qp_group_speed(const or_material* m, double phi);
@@ -128,6 +134,29 @@ double or_segment_time(int nx, int nz, double h, const or_material* mats,
 int or_trace_ray(int nx, int nz, double h, const or_material* mats, const uint8_t* mat_id,
                  const double* orient, const double* T, int si, int sj, int ri, int rj,
                  int window, int sub, int max_pts, double* pts, int* n_pts, double* t_ray);
+
+/* ---- gradient with respect to orientation (frozen choices) --------------------------- */
+
+/* partial derivatives of or_stencil_estimate with respect to ta, tb, tc and theta_ax */
+void or_stencil_partials(const or_material* m, double theta_ax, double h, const int off[6],
+                         double ta, double tb, double tc, double* dta, double* dtb, double* dtc,
+                         double* dth);
+
+/* choice of every node at the fixed point T: -2 fixed, -1 unreached, 0..31 stencil,
+   32 + k straight ray from the k-th 8-neighbour */
+void or_field_choices(int nx, int nz, double h, const or_material* mats, const uint8_t* mat_id,
+                      const double* orient, const double* T, const uint8_t* fixed, int* choice);
+
+/* field recomputed in pop order with frozen choices (orientation may be perturbed) */
+void or_frozen_field(int nx, int nz, double h, const or_material* mats, const uint8_t* mat_id,
+                     const double* orient, int si, int sj, int R, const int* choice,
+                     const int64_t* pop, int64_t npop, double* T);
+
+/* dL/dtheta for one source given g = dL/dT at every node; writes the field to T_out
+   (nullable).  Returns 0, or -1 on invalid input. */
+int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, const uint8_t* mat_id,
+               const double* orient, int si, int sj, int R, const double* g, double* T_out,
+               double* dtheta);
 
 #ifdef __cplusplus
 }

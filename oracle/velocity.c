@@ -54,6 +54,22 @@ double or_qp_phase_speed(const or_material* m, double th_p) {
     return sqrt(qp_lambda(al, be, ga) / m->rho);
 }
 
+/* d v / d th_p of the qP phase speed, by differentiating the closed-form root:
+   alpha' = 2 sin cos (c44 - c22), gamma' = 2 sin cos (c33 - c44),
+   beta' = (cos^2 - sin^2)(c23 + c44), lambda' from the root, v' = lambda' / (2 rho v). */
+double or_qp_phase_speed_deriv(const or_material* m, double th_p) {
+    double al, be, ga;
+    christoffel(m, th_p, &al, &be, &ga);
+    double c = cos(th_p), s = sin(th_p);
+    double dal = 2.0 * s * c * (m->c55 - m->c11);
+    double dga = 2.0 * s * c * (m->c33 - m->c55);
+    double dbe = (c * c - s * s) * (m->c13 + m->c55);
+    double root = sqrt((al - ga) * (al - ga) + 4.0 * be * be);
+    double dlam = 0.5 * ((dal + dga) + (root > 0.0 ? ((al - ga) * (dal - dga) + 4.0 * be * dbe) / root : 0.0));
+    double v = sqrt(qp_lambda(al, be, ga) / m->rho);
+    return dlam / (2.0 * m->rho * v);
+}
+
 void or_qp_group_from_phase(const or_material* m, double th_p, double* g_angle, double* g_speed) {
     double al, be, ga;
     christoffel(m, th_p, &al, &be, &ga);
@@ -128,4 +144,13 @@ double or_qp_group_speed_support(const or_material* m, double phi) {
     double f = fc > fd ? fc : fd;
     if (best > f) f = best;
     return 1.0 / f;
+}
+
+/* d V_group / d phi by Richardson-extrapolated central differences of the exact group
+   speed (step 1e-3 rad; truncation error far below the other tolerances). */
+double or_qp_group_speed_deriv(const or_material* m, double phi) {
+    const double h1 = 1e-3, h2 = 0.5e-3;
+    double d1 = (or_qp_group_speed(m, phi + h1) - or_qp_group_speed(m, phi - h1)) / (2.0 * h1);
+    double d2 = (or_qp_group_speed(m, phi + h2) - or_qp_group_speed(m, phi - h2)) / (2.0 * h2);
+    return (4.0 * d2 - d1) / 3.0;
 }
