@@ -147,6 +147,78 @@ ali_status ali_trace_rays_f64(ali_handle* h, const ali_grid* grid, const ali_mat
                               const ali_node* srcs, int32_t n_src, const ali_node* recv, int32_t n_recv,
                               const ali_options* opt, float* d_paths, int32_t* d_npts, float* d_tray);
 
+/* ---- gradient with respect to the orientation ---------------------------------------- */
+
+typedef struct {
+    ali_solve_stats forward;     /* the forward solve inside the call                        */
+    int64_t lambda_updates;      /* evaluations of the adjoint update at a node              */
+    int64_t tile_visits;         /* tile passes of the adjoint relaxation                    */
+    int64_t choice_mismatches;   /* nodes whose re-derived choice does not reproduce the
+                                    forward value (0 unless the forward did not converge)   */
+    int32_t outer_iters;         /* adjoint relaxation launches                              */
+    int32_t converged;           /* 1 if the adjoint reached its fixed point                 */
+    double  ms;                  /* whole call (forward + adjoint) on the stream             */
+    double  relax_ms;            /* summed duration of the adjoint relaxation launches       */
+} ali_adjoint_stats;
+
+/* Gradient of a loss of the receiver travel times with respect to the orientation at
+   every node (not in the paper; it differentiates the paper's update, Sections 4.2-4.4).
+   The call solves the forward fields (float64 travel times, same options and result as
+   ali_solve_traveltime), re-derives at every node the candidate its local update chose,
+   holds those choices fixed, and runs the reverse chain rule over the resulting DAG:
+       lambda(X) = dL/dT(X) + sum over nodes D whose candidate uses X of lambda(D) dU_D/dT(X)
+       dL/dtheta(D) = sum over sources of lambda(D) dU_D/dtheta(D)
+   plus, for the source box, lambda times the derivative of the straight-ray time with
+   respect to the source node's orientation.  The result is the exact derivative of the
+   discrete map wherever no stencil choice switches.
+     recv[n_recv]   receiver nodes (host), inside the grid
+     d_dLdT         [n_src][n_recv] dL/dT at the receivers (device)
+     d_T            [n_src][nz][nx] forward fields out (device, nullable)
+     d_dLdtheta     [nz][nx] output (device), summed over all sources
+   opt->arith must be ALI_ARITH_MIXED (float32 wavefront math in the forward, float64
+   derivatives) or ALI_ARITH_F64; ALI_ARITH_F32 returns ALI_EUNSUPPORTED.  Every receiver
+   must be reached by every source.  Scratch: about 58 bytes per node and source.
+   Synchronises the stream. */
+ali_status ali_adjoint(ali_handle* h, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
+                       const uint8_t* d_mat_id, const float* d_orient, const ali_node* srcs, int32_t n_src,
+                       const ali_node* recv, int32_t n_recv, const float* d_dLdT, const ali_options* opt,
+                       float* d_T, float* d_dLdtheta, ali_adjoint_stats* stats);
+ali_status ali_adjoint_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
+                           const uint8_t* d_mat_id, const double* d_orient, const ali_node* srcs, int32_t n_src,
+                           const ali_node* recv, int32_t n_recv, const double* d_dLdT, const ali_options* opt,
+                           double* d_T, double* d_dLdtheta, ali_adjoint_stats* stats);
+
+/* Forward + adjoint for the travel-time misfit L = 1/2 sum over (s, r) of
+   (T_s(r) - obs[s][r])^2 in one call (the tomography step).
+     d_obs          [n_src][n_recv] observed times (device)
+     d_Trec         [n_src][n_recv] modelled times at the receivers (device, nullable)
+     d_loss         one float64 on the device: L (nullable)
+     d_dLdtheta     [nz][nx] dL/dtheta (device)
+   Arithmetic, errors and synchronisation as ali_adjoint. */
+ali_status ali_misfit_gradient(ali_handle* h, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
+                               const uint8_t* d_mat_id, const float* d_orient, const ali_node* srcs,
+                               int32_t n_src, const ali_node* recv, int32_t n_recv, const float* d_obs,
+                               const ali_options* opt, float* d_Trec, double* d_loss, float* d_dLdtheta,
+                               ali_adjoint_stats* stats);
+ali_status ali_misfit_gradient_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                   int32_t n_mats, const uint8_t* d_mat_id, const double* d_orient,
+                                   const ali_node* srcs, int32_t n_src, const ali_node* recv, int32_t n_recv,
+                                   const double* d_obs, const ali_options* opt, double* d_Trec,
+                                   double* d_loss, double* d_dLdtheta, ali_adjoint_stats* stats);
+
+/* Orientation from an ncz x ncx grid of control values spanning the grid corner to corner
+   (node k sits at control coordinate k (nc-1)/(n-1); linear in each direction), and its
+   transpose, which maps dL/dtheta [nz][nx] to dL/dcontrol [ncz][ncx].  Needs nz, nx, ncz,
+   ncx >= 2 and ncz <= nz, ncx <= nx.  Device arrays; asynchronous. */
+ali_status ali_bilinear(ali_handle* h, int32_t nz, int32_t nx, int32_t ncz, int32_t ncx,
+                        const float* d_ctrl, float* d_orient);
+ali_status ali_bilinear_transpose(ali_handle* h, int32_t nz, int32_t nx, int32_t ncz, int32_t ncx,
+                                  const float* d_dLdtheta, float* d_dLdctrl);
+ali_status ali_bilinear_f64(ali_handle* h, int32_t nz, int32_t nx, int32_t ncz, int32_t ncx,
+                            const double* d_ctrl, double* d_orient);
+ali_status ali_bilinear_transpose_f64(ali_handle* h, int32_t nz, int32_t nx, int32_t ncz, int32_t ncx,
+                                      const double* d_dLdtheta, double* d_dLdctrl);
+
 #ifdef __cplusplus
 }
 #endif

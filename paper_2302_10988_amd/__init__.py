@@ -165,3 +165,85 @@ class Solver:
                 _dev_ptr(tray, torch.float32))
         self._check(st)
         return paths, npts, tray
+
+    def adjoint(self, h, mats, mat_id, orient, sources, receivers, dLdT, precision="f32",
+                return_T=False, src_box_radius=None, max_sweeps=None, inner_sweeps=None,
+                band_cells=None, arith="mixed"):
+        """dL/dtheta [nz, nx] (summed over sources) for dL/dT given at the receivers,
+        dLdT [n_src, n_rec] device tensor.  The forward fields are solved inside the call
+        (returned when return_T).  precision "f32" (arith "mixed" or "f64") or "f64".
+        Returns (dLdtheta, stats dict) or (dLdtheta, T, stats dict)."""
+        import torch
+        nz, nx = mat_id.shape
+        fdt = torch.float32 if precision == "f32" else torch.float64
+        m_arr, nm = _materials(mats)
+        s_arr, ns = _nodes(sources)
+        r_arr, nr = _nodes(receivers)
+        g = _lib.Grid(int(nx), int(nz), float(h))
+        opt = default_options(src_box_radius=src_box_radius, max_sweeps=max_sweeps,
+                              inner_sweeps=inner_sweeps, band_cells=band_cells,
+                              arith=_lib.ARITH[arith])
+        dev = mat_id.device
+        dth = torch.empty((nz, nx), dtype=fdt, device=dev)
+        T = torch.empty((ns, nz, nx), dtype=fdt, device=dev) if return_T else None
+        stats = _lib.AdjointStats()
+        self._sync_stream()
+        fn = self._lib.ali_adjoint if precision == "f32" else self._lib.ali_adjoint_f64
+        st = fn(self._h, ctypes.byref(g), m_arr, nm, _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id"),
+                _dev_ptr(orient, fdt, (nz, nx), "orient"), s_arr, ns, r_arr, nr,
+                _dev_ptr(dLdT, fdt, (ns, nr), "dLdT"), ctypes.byref(opt),
+                _dev_ptr(T, fdt) if T is not None else None, _dev_ptr(dth, fdt), ctypes.byref(stats))
+        self._check(st)
+        return (dth, T, stats.as_dict()) if return_T else (dth, stats.as_dict())
+
+    def misfit_gradient(self, h, mats, mat_id, orient, sources, receivers, obs, precision="f32",
+                        src_box_radius=None, max_sweeps=None, inner_sweeps=None, band_cells=None,
+                        arith="mixed"):
+        """Forward + adjoint of L = 1/2 sum (T_s(r) - obs[s, r])^2 in one call.
+        Returns (loss float64 device scalar, Trec [n_src, n_rec], dLdtheta [nz, nx], stats)."""
+        import torch
+        nz, nx = mat_id.shape
+        fdt = torch.float32 if precision == "f32" else torch.float64
+        m_arr, nm = _materials(mats)
+        s_arr, ns = _nodes(sources)
+        r_arr, nr = _nodes(receivers)
+        g = _lib.Grid(int(nx), int(nz), float(h))
+        opt = default_options(src_box_radius=src_box_radius, max_sweeps=max_sweeps,
+                              inner_sweeps=inner_sweeps, band_cells=band_cells,
+                              arith=_lib.ARITH[arith])
+        dev = mat_id.device
+        dth = torch.empty((nz, nx), dtype=fdt, device=dev)
+        trec = torch.empty((ns, nr), dtype=fdt, device=dev)
+        loss = torch.empty((), dtype=torch.float64, device=dev)
+        stats = _lib.AdjointStats()
+        self._sync_stream()
+        fn = self._lib.ali_misfit_gradient if precision == "f32" else self._lib.ali_misfit_gradient_f64
+        st = fn(self._h, ctypes.byref(g), m_arr, nm, _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id"),
+                _dev_ptr(orient, fdt, (nz, nx), "orient"), s_arr, ns, r_arr, nr,
+                _dev_ptr(obs, fdt, (ns, nr), "obs"), ctypes.byref(opt), _dev_ptr(trec, fdt),
+                _dev_ptr(loss, torch.float64), _dev_ptr(dth, fdt), ctypes.byref(stats))
+        self._check(st)
+        return loss, trec, dth, stats.as_dict()
+
+    def bilinear(self, ctrl, nz, nx):
+        """Orientation [nz, nx] from control values ctrl [ncz, ncx] (float32 or float64
+        device tensor) spanning the grid corner to corner, linear in each direction."""
+        import torch
+        ncz, ncx = ctrl.shape
+        out = torch.empty((nz, nx), dtype=ctrl.dtype, device=ctrl.device)
+        fn = self._lib.ali_bilinear if ctrl.dtype == torch.float32 else self._lib.ali_bilinear_f64
+        self._sync_stream()
+        self._check(fn(self._h, int(nz), int(nx), int(ncz), int(ncx), _dev_ptr(ctrl, ctrl.dtype, name="ctrl"),
+                       _dev_ptr(out, ctrl.dtype)))
+        return out
+
+    def bilinear_transpose(self, g, ncz, ncx):
+        """Transpose of bilinear: dL/dcontrol [ncz, ncx] from dL/dtheta [nz, nx]."""
+        import torch
+        nz, nx = g.shape
+        out = torch.empty((ncz, ncx), dtype=g.dtype, device=g.device)
+        fn = self._lib.ali_bilinear_transpose if g.dtype == torch.float32 else self._lib.ali_bilinear_transpose_f64
+        self._sync_stream()
+        self._check(fn(self._h, int(nz), int(nx), int(ncz), int(ncx), _dev_ptr(g, g.dtype, name="dLdtheta"),
+                       _dev_ptr(out, g.dtype)))
+        return out

@@ -45,6 +45,18 @@ class SolveStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class AdjointStats(ctypes.Structure):
+    _fields_ = [("forward", SolveStats), ("lambda_updates", ctypes.c_int64),
+                ("tile_visits", ctypes.c_int64), ("choice_mismatches", ctypes.c_int64),
+                ("outer_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("relax_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "forward"}
+        d["forward"] = self.forward.as_dict()
+        return d
+
+
 # every symbol the header declares, with (restype, argtypes)
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -67,6 +79,23 @@ SIGNATURES = {
     "ali_trace_rays_f64": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P, _P, _P,
                                           ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32,
                                           ctypes.POINTER(Options), _P, _P, _P]),
+    "ali_adjoint": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P, _P,
+                                   ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
+                                   ctypes.POINTER(Options), _P, _P, ctypes.POINTER(AdjointStats)]),
+    "ali_adjoint_f64": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P, _P,
+                                       ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
+                                       ctypes.POINTER(Options), _P, _P, ctypes.POINTER(AdjointStats)]),
+    "ali_misfit_gradient": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P, _P,
+                                           ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
+                                           ctypes.POINTER(Options), _P, _P, _P, ctypes.POINTER(AdjointStats)]),
+    "ali_misfit_gradient_f64": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P, _P,
+                                               ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
+                                               ctypes.POINTER(Options), _P, _P, _P,
+                                               ctypes.POINTER(AdjointStats)]),
+    "ali_bilinear": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),
+    "ali_bilinear_transpose": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),
+    "ali_bilinear_f64": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),
+    "ali_bilinear_transpose_f64": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),
 }
 
 _lib = None

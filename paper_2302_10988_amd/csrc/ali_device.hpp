@@ -99,6 +99,7 @@ template <typename real> struct Best {
     real U;
     real kt;                // tau of the activation point (kappa)
     int ks;                 // diamond slot of the activation point
+    int idx;                // table index 0..31, or 32 + neighbour order for a straight ray
     unsigned evals;         // single-stencil estimates computed (statistics only)
 };
 
@@ -155,6 +156,7 @@ __device__ __forceinline__ void eval_stencil(const NodeConst<mreal, real>& n, re
         best.U = U;
         best.kt = tc;
         best.ks = (tb == tc) ? St::tie_slot : St::sc;
+        best.idx = S;
     }
 }
 
@@ -190,6 +192,7 @@ __device__ __forceinline__ void eval_fallback(const NodeConst<mreal, real>& n, c
         best.U = U;
         best.kt = tn;
         best.ks = FB_SLOT[K];
+        best.idx = 32 + K;
     }
 }
 
@@ -266,7 +269,7 @@ __device__ __forceinline__ void slow_all(const NodeConst<mreal, real>& n, const 
 // the node constants by value, so the fast path never spills them to the stack.
 template <typename mreal, typename real>
 __device__ __noinline__ real slow_update(const NodeConst<mreal, real> n, const real* __restrict__ lds,
-                                         int me, int stride) {
+                                         int me, int stride, int* choice) {
     const real inf = dinf<real>();
     real t[12];
 #pragma unroll
@@ -282,7 +285,7 @@ __device__ __noinline__ real slow_update(const NodeConst<mreal, real> n, const r
         const real tn = t[FB_SLOT[k]];
         if (sb.cls[k] == 3 && tn < inf) {
             const real U = tn + n.fb[FB_DIR[k]];
-            if (U > tn) { sb.cls[k] = 2; sb.idx[k] = k; sb.score[k] = U; sb.U[k] = U; }
+            if (U > tn) { sb.cls[k] = 2; sb.idx[k] = 32 + k; sb.score[k] = U; sb.U[k] = U; }
         }
         if (sb.cls[k] < 3) rem |= 1u << k;
     }
@@ -304,10 +307,11 @@ __device__ __noinline__ real slow_update(const NodeConst<mreal, real> n, const r
         // rank = (class, score, table index / neighbour order)
         const bool better = ccls < rcls || (ccls == rcls && (cscore < rscore || (cscore == rscore && cidx < ridx)));
         if (better) {
-            if (rcls < 3 && !key_after(rU, tq, FB_SLOT[q])) return rU;   // record below next key
+            if (rcls < 3 && !key_after(rU, tq, FB_SLOT[q])) { *choice = ridx; return rU; }  // record below next key
             rcls = ccls; rscore = cscore; rU = cU; ridx = cidx;
         }
     }
+    *choice = rcls < 3 ? ridx : -1;
     return rcls < 3 ? rU : inf;
 }
 
@@ -318,20 +322,25 @@ __device__ __noinline__ real slow_update(const NodeConst<mreal, real> n, const r
 // ---------------------------------------------------------------------------------------
 // t: the 12 diamond values (copied from lds[me + dj*stride + di]); the slow path
 // reads them again from lds.
+// choice (nullable) receives the chosen candidate: table index 0..31, 32 + k for a
+// straight ray from the k-th 8-neighbour, -1 for none.
 template <typename mreal, typename real>
 __device__ __forceinline__ real local_update(const NodeConst<mreal, real>& n, const real (&t)[12],
                                              const real* __restrict__ lds, int me, int stride,
-                                             unsigned& evals) {
+                                             unsigned& evals, int* choice = nullptr) {
     const real inf = dinf<real>();
     Best<real> best;
-    best.cls = 3; best.score = inf; best.U = inf; best.kt = inf; best.ks = 0; best.evals = 0;
+    best.cls = 3; best.score = inf; best.U = inf; best.kt = inf; best.ks = 0; best.idx = -1; best.evals = 0;
     real minU = inf;
     eval_all<mreal, real>(n, t, best, minU, std::make_integer_sequence<int, 16>{});
     eval_fallbacks<mreal, real>(n, t, best, minU, std::make_integer_sequence<int, 8>{});
     evals += best.evals;
-    if (best.cls == 3) return inf;
-    if (key_after(minU, best.kt, best.ks)) return best.U;
-    return slow_update<mreal, real>(n, lds, me, stride);
+    if (best.cls == 3) { if (choice) *choice = -1; return inf; }
+    if (key_after(minU, best.kt, best.ks)) { if (choice) *choice = best.idx; return best.U; }
+    int ch = -1;
+    const real u = slow_update<mreal, real>(n, lds, me, stride, &ch);
+    if (choice) *choice = ch;
+    return u;
 }
 
 }  // namespace ali

@@ -30,25 +30,9 @@
 #include <string>
 #include <vector>
 
-#include "ali_device.hpp"
-#include "ali_velocity.hpp"
-#include "ali_handle.hpp"
-#include "../../include/ali.h"
+#include "ali_solve.hpp"
 
 namespace ali {
-
-constexpr int TX = 16, TZ = 16, HALO = 2;
-constexpr int LW = TX + 2 * HALO, LH = TZ + 2 * HALO;
-constexpr int LSTRIDE = LW + 1;
-constexpr int NTHREADS = TX * TZ;
-
-template <typename real> inline real dinf_host() { return (real)INFINITY; }
-
-// per-material constants on the device (phase-speed constants in the math type)
-template <typename mreal> struct MatDev {
-    mreal P, Q, R, K4;      // phase-speed constants / h^2
-    MatA A;
-};
 
 // ---------------------------------------------------------------------------------------
 // kernels
@@ -162,38 +146,6 @@ __device__ __forceinline__ void lds_min(double* p, double v) {
     atomicMin(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
 }
 
-template <typename dst, typename srcT>
-__global__ void k_convert(dst* __restrict__ out, const srcT* __restrict__ in, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = (dst)in[i];
-}
-
-template <typename real>
-__global__ void k_fill(real* __restrict__ p, int64_t n, real v) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
-// flag bits of a tile: which parts of it need evaluation on its next visit
-enum : uint32_t {
-    TF_SELF = 1u,              // everything (first visit, or the previous visit hit the sweep cap)
-    TF_HALO_L = 2u, TF_HALO_R = 4u, TF_HALO_U = 8u, TF_HALO_D = 16u,       // a halo side changed
-    TF_HALO_UL = 32u, TF_HALO_UR = 64u, TF_HALO_DL = 128u, TF_HALO_DR = 256u  // a halo corner changed
-};
-
-template <typename real, typename mreal>
-__device__ __forceinline__ void load_node_const(NodeConst<mreal, real>& nc, int64_t p,
-                                                const MatDev<mreal>* __restrict__ mats,
-                                                const uint8_t* __restrict__ mat_id,
-                                                const mreal* __restrict__ geo,
-                                                const real* __restrict__ fbt) {
-    const MatDev<mreal>& m = mats[mat_id[p]];
-    nc.P = m.P; nc.Q = m.Q; nc.R = m.R; nc.K4 = m.K4;
-    nc.c2t = geo[2 * p + 0];
-    nc.s2t = geo[2 * p + 1];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) nc.fb[d] = fbt[4 * p + d];
-}
 
 // One tile visit.  The set of nodes to evaluate is tracked per node: a node whose value
 // changes marks its diamond neighbours inside the tile for the next sweep, and each sweep
@@ -365,19 +317,15 @@ k_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
 // host driver
 // ---------------------------------------------------------------------------------------
 // real: travel-time type (storage, scores, decisions); mreal: wavefront / phase-speed
-// math; oreal: orientation input; outreal: output field.  When real != outreal the
-// relaxation runs on a scratch field that is converted into d_out at the end.
-template <typename real, typename mreal, typename oreal, typename outreal>
-static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats,
-                             int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient,
-                             const ali_node* srcs, int32_t n_src, const ali_options* opt_in,
-                             outreal* d_out, ali_solve_stats* stats) {
-    ali_options opt;
-    ali_default_options(&opt);
-    if (opt_in) opt = *opt_in;
+// math; oreal: orientation input.
+template <typename real, typename mreal, typename oreal>
+ali_status solve_core(ali_handle* H, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
+                      const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
+                      int32_t n_src, const ali_options& opt, real* d_T, ali_solve_stats* stats,
+                      ForwardState<real, mreal>* fs) {
     ali_status st = validate_medium(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src);
     if (st != ALI_OK) return st;
-    if (!d_out) return H->fail(ALI_EINVAL, "d_T is NULL");
+    if (!d_T) return H->fail(ALI_EINVAL, "d_T is NULL");
     if (opt.src_box_radius < 0 || opt.src_box_radius > 64) return H->fail(ALI_EINVAL, "src_box_radius out of range [0, 64]");
     if (opt.max_sweeps < 1) return H->fail(ALI_EINVAL, "max_sweeps must be >= 1");
     if (opt.inner_sweeps < 1 || opt.inner_sweeps > 4096) return H->fail(ALI_EINVAL, "inner_sweeps out of range [1, 4096]");
@@ -391,41 +339,24 @@ static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     if (set_device(H) != ALI_OK) return ALI_EDEVICE;
     hipStream_t S = H->stream;
 
-    // device scratch
-    std::vector<MatDev<mreal>> hm(n_mats);
-    for (int k = 0; k < n_mats; ++k) {
-        const ali_material& m = mats[k];
-        const double a11 = m.c11 / m.rho, a13 = m.c13 / m.rho, a33 = m.c33 / m.rho, a55 = m.c55 / m.rho;
-        const double ih2 = 1.0 / (grid->h * grid->h);
-        hm[k].P = (mreal)((a11 + a33 + 2.0 * a55) * ih2);
-        hm[k].Q = (mreal)((a33 - a11) * ih2);
-        hm[k].R = (mreal)((a11 + a33 - 2.0 * a55) * ih2);
-        const double W = (a13 + a55) * ih2;
-        hm[k].K4 = (mreal)(4.0 * W * W);
-        hm[k].A = MatA{a11, a13, a33, a55};
-    }
+    const std::vector<MatDev<mreal>> hm = make_matdev<mreal>(mats, n_mats, grid->h);
     // band step: band_cells node spacings at the fastest phase speed of the medium
     double vmax = 0.0;
     for (int k = 0; k < n_mats; ++k)
         for (int q = 0; q <= 180; ++q) {
             const double psi = q * (3.14159265358979323846 / 360.0);
-            const double a11 = mats[k].c11 / mats[k].rho, a13 = mats[k].c13 / mats[k].rho;
-            const double a33 = mats[k].c33 / mats[k].rho, a55 = mats[k].c55 / mats[k].rho;
+            const MatA& A = hm[k].A;
             const double c = cos(2.0 * psi), sn = sin(2.0 * psi);
-            const double lin = (a33 - a11) + (a11 + a33 - 2.0 * a55) * c;
-            const double v2 = 0.25 * ((a11 + a33 + 2.0 * a55) + (a33 - a11) * c +
-                                      sqrt(lin * lin + 4.0 * (a13 + a55) * (a13 + a55) * sn * sn));
+            const double lin = (A.a33 - A.a11) + (A.a11 + A.a33 - 2.0 * A.a55) * c;
+            const double v2 = 0.25 * ((A.a11 + A.a33 + 2.0 * A.a55) + (A.a33 - A.a11) * c +
+                                      sqrt(lin * lin + 4.0 * (A.a13 + A.a55) * (A.a13 + A.a55) * sn * sn));
             if (v2 > vmax * vmax) vmax = sqrt(v2);
         }
     const real band = opt.band_cells > 0 ? (real)(opt.band_cells * grid->h / vmax) : dinf_host<real>();
     std::vector<real> hstep(n_src, band), htheta(n_src, band);
 
     void *d_mats, *d_geo, *d_fbt, *d_src, *d_flags, *d_list, *d_count, *d_upd, *d_err;
-    void *d_theta, *d_step, *d_minrej, *d_lbits, *d_work = nullptr;
-    constexpr bool same_out = std::is_same<real, outreal>::value;
-    if (!same_out && !H->scratch("Twork", sizeof(real) * N * n_src, &d_work))
-        return H->fail(ALI_ENOMEM, "device scratch allocation failed");
-    real* d_T = same_out ? (real*)d_out : (real*)d_work;
+    void *d_theta, *d_step, *d_minrej, *d_lbits;
     if (!H->scratch("mats", sizeof(MatDev<mreal>) * n_mats, &d_mats) ||
         !H->scratch("theta", sizeof(real) * n_src, &d_theta) ||
         !H->scratch("step", sizeof(real) * n_src, &d_step) ||
@@ -443,8 +374,7 @@ static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     std::vector<int2> hs(n_src);
     for (int k = 0; k < n_src; ++k) hs[k] = make_int2(srcs[k].i, srcs[k].j);
 
-    hipEvent_t e0 = H->ev0, e1 = H->ev1;
-    HIPCK(H, hipEventRecord(e0, S));
+    HIPCK(H, hipEventRecord(H->ev0, S));
     HIPCK(H, hipMemcpyAsync(d_mats, hm.data(), sizeof(MatDev<mreal>) * n_mats, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemcpyAsync(d_src, hs.data(), sizeof(int2) * n_src, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemcpyAsync(d_theta, htheta.data(), sizeof(real) * n_src, hipMemcpyHostToDevice, S));
@@ -522,19 +452,10 @@ static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_mate
         ++iters;
         visits += n;
     }
-    if (!same_out) {
-        const int64_t tot = N * n_src;
-        hipLaunchKernelGGL((k_convert<outreal, real>), dim3((unsigned)((tot + B - 1) / B)), dim3(B), 0, S,
-                           d_out, (const real*)d_T, tot);
-        HIPCK(H, hipGetLastError());
-    }
-    HIPCK(H, hipEventRecord(e1, S));
     unsigned long long upd[2] = {0, 0};
     HIPCK(H, hipMemcpyAsync(upd, d_upd, sizeof(upd), hipMemcpyDeviceToHost, S));
     HIPCK(H, hipStreamSynchronize(S));
     if (stats) {
-        float ms = 0.f;
-        HIPCK(H, hipEventElapsedTime(&ms, e0, e1));
         stats->node_updates = (int64_t)upd[0];
         stats->stencil_evals = (int64_t)upd[1];
         stats->relax_ms = relax_ms;
@@ -542,10 +463,71 @@ static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_mate
         stats->nodes = N * n_src;
         stats->outer_iters = iters;
         stats->converged = converged ? 1 : 0;
-        stats->ms = ms;
+        stats->ms = 0.0;
+    }
+    if (fs) {
+        fs->mats = (const MatDev<mreal>*)d_mats;
+        fs->geo = (const mreal*)d_geo;
+        fs->fbt = (const real*)d_fbt;
+        fs->src = (const int2*)d_src;
+        fs->ntx = ntx;
+        fs->ntz = ntz;
     }
     if (!converged) return H->fail(ALI_ENOCONV, "relaxation reached max_sweeps");
     return ALI_OK;
+}
+
+template ali_status solve_core<double, float, float>(ali_handle*, const ali_grid*, const ali_material*, int32_t,
+    const uint8_t*, const float*, const ali_node*, int32_t, const ali_options&, double*, ali_solve_stats*,
+    ForwardState<double, float>*);
+template ali_status solve_core<float, float, float>(ali_handle*, const ali_grid*, const ali_material*, int32_t,
+    const uint8_t*, const float*, const ali_node*, int32_t, const ali_options&, float*, ali_solve_stats*,
+    ForwardState<float, float>*);
+template ali_status solve_core<double, double, float>(ali_handle*, const ali_grid*, const ali_material*, int32_t,
+    const uint8_t*, const float*, const ali_node*, int32_t, const ali_options&, double*, ali_solve_stats*,
+    ForwardState<double, double>*);
+template ali_status solve_core<double, double, double>(ali_handle*, const ali_grid*, const ali_material*, int32_t,
+    const uint8_t*, const double*, const ali_node*, int32_t, const ali_options&, double*, ali_solve_stats*,
+    ForwardState<double, double>*);
+
+// Entry-point body: relax in `real` (on a scratch field when it differs from the output
+// type), convert into d_out, time the whole call.
+template <typename real, typename mreal, typename oreal, typename outreal>
+static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats,
+                             int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient,
+                             const ali_node* srcs, int32_t n_src, const ali_options* opt_in,
+                             outreal* d_out, ali_solve_stats* stats) {
+    ali_options opt;
+    ali_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (!d_out) return H->fail(ALI_EINVAL, "d_T is NULL");
+    if (!grid) return H->fail(ALI_EINVAL, "grid is NULL");
+    constexpr bool same_out = std::is_same<real, outreal>::value;
+    const int64_t tot = (int64_t)grid->nx * grid->nz * (n_src > 0 ? n_src : 0);
+    void* d_work = nullptr;
+    if (!same_out && tot > 0 && !H->scratch("Twork", sizeof(real) * tot, &d_work))
+        return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+    real* d_T = same_out ? (real*)d_out : (real*)d_work;
+    ali_solve_stats local{};
+    ali_status st = solve_core<real, mreal, oreal>(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
+                                                   opt, d_T, &local, nullptr);
+    if (st != ALI_OK && st != ALI_ENOCONV) return st;
+    hipStream_t S = H->stream;
+    if (!same_out) {
+        const int B = 256;
+        hipLaunchKernelGGL((k_convert<outreal, real>), dim3((unsigned)((tot + B - 1) / B)), dim3(B), 0, S,
+                           d_out, (const real*)d_T, tot);
+        HIPCK(H, hipGetLastError());
+    }
+    HIPCK(H, hipEventRecord(H->ev1, S));
+    HIPCK(H, hipStreamSynchronize(S));
+    if (stats) {
+        float ms = 0.f;
+        HIPCK(H, hipEventElapsedTime(&ms, H->ev0, H->ev1));
+        *stats = local;
+        stats->ms = ms;
+    }
+    return st;
 }
 
 }  // namespace ali

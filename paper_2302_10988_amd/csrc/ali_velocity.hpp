@@ -33,35 +33,45 @@ __device__ inline double group_angle_of(const MatA& m, double psi, double* speed
     return psi + atan(dF / (2.0 * F));
 }
 
-__device__ inline double group_speed(const MatA& m, double phi) {
+// Group speed V and, if dV != nullptr, dV/dphi.  With psi the phase angle whose group
+// direction is phi, tan(phi - psi) = v'/v and dV/dphi = V v'/v (differentiate
+// V^2 = v^2 + v'^2 and phi = psi + atan(v'/v) in psi and divide).
+__device__ inline double group_speed(const MatA& m, double phi, double* dV = nullptr) {
     const double half_pi = 1.57079632679489661923;
+    // fold onto [0, pi/2]: V is even and pi-periodic in phi
     double a = fmod(fabs(phi), 2.0 * half_pi);
-    if (a > half_pi) a = 2.0 * half_pi - a;
+    double sgn = phi < 0.0 ? -1.0 : 1.0;
+    if (a > half_pi) { a = 2.0 * half_pi - a; sgn = -sgn; }
     double lo = 0.0, hi = half_pi;
     double glo = -a, ghi = half_pi - a;
-    double spd;
-    if (glo == 0.0) { group_angle_of(m, 0.0, &spd); return spd; }
-    if (ghi == 0.0) { group_angle_of(m, half_pi, &spd); return spd; }
-    int side = 0;
     double x = a;
-    for (int it = 0; it < 100; ++it) {
-        x = (lo * ghi - hi * glo) / (ghi - glo);
-        if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
-        const double g = group_angle_of(m, x, nullptr) - a;
-        if (g == 0.0 || hi - lo < 1e-15) break;
-        if (g < 0.0) {
-            lo = x; glo = g;
-            if (side == -1) ghi *= 0.5;
-            side = -1;
-        } else {
-            hi = x; ghi = g;
-            if (side == 1) glo *= 0.5;
-            side = 1;
+    if (glo == 0.0) {
+        x = 0.0;
+    } else if (ghi == 0.0) {
+        x = half_pi;
+    } else {
+        int side = 0;
+        for (int it = 0; it < 100; ++it) {
+            x = (lo * ghi - hi * glo) / (ghi - glo);
+            if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+            const double g = group_angle_of(m, x, nullptr) - a;
+            if (g == 0.0 || hi - lo < 1e-15) break;
+            if (g < 0.0) {
+                lo = x; glo = g;
+                if (side == -1) ghi *= 0.5;
+                side = -1;
+            } else {
+                hi = x; ghi = g;
+                if (side == 1) glo *= 0.5;
+                side = 1;
+            }
         }
     }
-    group_angle_of(m, x, &spd);
+    double F, dF;
+    phase_F(m, x, F, dF);
+    const double spd = sqrt(F + dF * dF / (4.0 * F));
+    if (dV) *dV = sgn * spd * dF / (2.0 * F);
     return spd;
 }
-
 
 }  // namespace ali

@@ -51,3 +51,28 @@ def test_host_only_entry_points():
     assert lib.ali_status_string(0).decode() == "ok"
     assert lib.ali_destroy(None) == _lib.ALI_EINVAL
     assert lib.ali_create(None, 0, None) == _lib.ALI_EINVAL
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # sizes and field offsets of every struct, from the header compiled by the C compiler
+    import subprocess
+    from paper_2302_10988_amd import _lib
+    structs = {"ali_grid": _lib.Grid, "ali_material": _lib.Material, "ali_node": _lib.Node,
+               "ali_options": _lib.Options, "ali_solve_stats": _lib.SolveStats,
+               "ali_adjoint_stats": _lib.AdjointStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ali.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
