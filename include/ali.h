@@ -150,7 +150,7 @@ ali_status ali_trace_rays_f64(ali_handle* h, const ali_grid* grid, const ali_mat
 /* ---- gradient with respect to the orientation ---------------------------------------- */
 
 typedef struct {
-    ali_solve_stats forward;     /* the forward solve inside the call                        */
+    ali_solve_stats forward;     /* the forward solve inside the call (ms: its share)        */
     int64_t lambda_updates;      /* evaluations of the adjoint update at a node              */
     int64_t tile_visits;         /* tile passes of the adjoint relaxation                    */
     int64_t choice_mismatches;   /* nodes whose re-derived choice does not reproduce the
@@ -191,6 +191,7 @@ ali_status ali_adjoint_f64(ali_handle* h, const ali_grid* grid, const ali_materi
 /* Forward + adjoint for the travel-time misfit L = 1/2 sum over (s, r) of
    (T_s(r) - obs[s][r])^2 in one call (the tomography step).
      d_obs          [n_src][n_recv] observed times (device)
+     d_T            [n_src][nz][nx] forward fields out (device, nullable)
      d_Trec         [n_src][n_recv] modelled times at the receivers (device, nullable)
      d_loss         one float64 on the device: L (nullable)
      d_dLdtheta     [nz][nx] dL/dtheta (device)
@@ -198,12 +199,12 @@ ali_status ali_adjoint_f64(ali_handle* h, const ali_grid* grid, const ali_materi
 ali_status ali_misfit_gradient(ali_handle* h, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
                                const uint8_t* d_mat_id, const float* d_orient, const ali_node* srcs,
                                int32_t n_src, const ali_node* recv, int32_t n_recv, const float* d_obs,
-                               const ali_options* opt, float* d_Trec, double* d_loss, float* d_dLdtheta,
-                               ali_adjoint_stats* stats);
+                               const ali_options* opt, float* d_T, float* d_Trec, double* d_loss,
+                               float* d_dLdtheta, ali_adjoint_stats* stats);
 ali_status ali_misfit_gradient_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats,
                                    int32_t n_mats, const uint8_t* d_mat_id, const double* d_orient,
                                    const ali_node* srcs, int32_t n_src, const ali_node* recv, int32_t n_recv,
-                                   const double* d_obs, const ali_options* opt, double* d_Trec,
+                                   const double* d_obs, const ali_options* opt, double* d_T, double* d_Trec,
                                    double* d_loss, double* d_dLdtheta, ali_adjoint_stats* stats);
 
 /* Orientation from an ncz x ncx grid of control values spanning the grid corner to corner

@@ -197,9 +197,10 @@ class Solver:
         return (dth, T, stats.as_dict()) if return_T else (dth, stats.as_dict())
 
     def misfit_gradient(self, h, mats, mat_id, orient, sources, receivers, obs, precision="f32",
-                        src_box_radius=None, max_sweeps=None, inner_sweeps=None, band_cells=None,
-                        arith="mixed"):
-        """Forward + adjoint of L = 1/2 sum (T_s(r) - obs[s, r])^2 in one call.
+                        T_out=None, src_box_radius=None, max_sweeps=None, inner_sweeps=None,
+                        band_cells=None, arith="mixed"):
+        """Forward + adjoint of L = 1/2 sum (T_s(r) - obs[s, r])^2 in one call; the forward
+        fields go to T_out [n_src, nz, nx] when given.
         Returns (loss float64 device scalar, Trec [n_src, n_rec], dLdtheta [nz, nx], stats)."""
         import torch
         nz, nx = mat_id.shape
@@ -220,7 +221,8 @@ class Solver:
         fn = self._lib.ali_misfit_gradient if precision == "f32" else self._lib.ali_misfit_gradient_f64
         st = fn(self._h, ctypes.byref(g), m_arr, nm, _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id"),
                 _dev_ptr(orient, fdt, (nz, nx), "orient"), s_arr, ns, r_arr, nr,
-                _dev_ptr(obs, fdt, (ns, nr), "obs"), ctypes.byref(opt), _dev_ptr(trec, fdt),
+                _dev_ptr(obs, fdt, (ns, nr), "obs"), ctypes.byref(opt),
+                _dev_ptr(T_out, fdt, (ns, nz, nx), "T_out") if T_out is not None else None, _dev_ptr(trec, fdt),
                 _dev_ptr(loss, torch.float64), _dev_ptr(dth, fdt), ctypes.byref(stats))
         self._check(st)
         return loss, trec, dth, stats.as_dict()

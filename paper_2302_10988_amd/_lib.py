@@ -87,10 +87,10 @@ SIGNATURES = {
                                        ctypes.POINTER(Options), _P, _P, ctypes.POINTER(AdjointStats)]),
     "ali_misfit_gradient": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P, _P,
                                            ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
-                                           ctypes.POINTER(Options), _P, _P, _P, ctypes.POINTER(AdjointStats)]),
+                                           ctypes.POINTER(Options), _P, _P, _P, _P, ctypes.POINTER(AdjointStats)]),
     "ali_misfit_gradient_f64": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P, _P,
                                                ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
-                                               ctypes.POINTER(Options), _P, _P, _P,
+                                               ctypes.POINTER(Options), _P, _P, _P, _P,
                                                ctypes.POINTER(AdjointStats)]),
     "ali_bilinear": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),
     "ali_bilinear_transpose": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),

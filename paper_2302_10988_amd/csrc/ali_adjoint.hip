@@ -223,15 +223,19 @@ __global__ void __launch_bounds__(NTHREADS)
 k_adj_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
             const uint32_t* __restrict__ lbits, const uint16_t* __restrict__ code,
             const double* __restrict__ wA, const double* __restrict__ wB, const double* __restrict__ wC,
-            const double* __restrict__ G, double* __restrict__ lam, uint32_t* __restrict__ flags,
-            int inner, unsigned long long* __restrict__ counters) {
+            const double* __restrict__ G, const double* __restrict__ T, const double* __restrict__ theta,
+            double* __restrict__ lam, uint8_t* __restrict__ pend, double* __restrict__ maxdef,
+            uint32_t* __restrict__ flags, int inner, unsigned long long* __restrict__ counters) {
     __shared__ double ll[LH * LSTRIDE];
     __shared__ double la[LH * LSTRIDE], lb[LH * LSTRIDE], lcw[LH * LSTRIDE];
     __shared__ uint16_t lc[LH * LSTRIDE];
+    __shared__ double ltau[NTHREADS];
+    __shared__ uint8_t lpend[NTHREADS];
     __shared__ uint8_t dirty[2][NTHREADS];
     __shared__ uint16_t clist[NTHREADS];
     __shared__ unsigned wcount[NTHREADS / 64];
     __shared__ unsigned edge_out, blk_updates;
+    __shared__ unsigned long long def_key;
 
     const uint32_t unit = list[blockIdx.x];
     const uint32_t bits = lbits[blockIdx.x];
@@ -263,7 +267,12 @@ k_adj_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
     const int lx = tid % TX, lz = tid / TX;
     const int gi = i0 + lx, gj = j0 + lz;
     const bool valid = gi < nx && gj < nz;
-    if (tid == 0) { edge_out = 0u; blk_updates = 0u; }
+    const int64_t pme = fo + (int64_t)gj * nx + gi;
+    const uint8_t pend0 = valid ? pend[pme] : 0;
+    ltau[tid] = valid ? T[pme] : 0.0;
+    lpend[tid] = pend0;
+    const double th = theta[f];
+    if (tid == 0) { edge_out = 0u; blk_updates = 0u; def_key = 0ull; }
     {
         const bool d = (bits & TF_SELF) ||
                        ((bits & TF_HALO_L) && lx < HALO) || ((bits & TF_HALO_R) && lx >= TX - HALO) ||
@@ -272,7 +281,7 @@ k_adj_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
                        ((bits & TF_HALO_UR) && lx == TX - 1 && lz == 0) ||
                        ((bits & TF_HALO_DL) && lx == 0 && lz == TZ - 1) ||
                        ((bits & TF_HALO_DR) && lx == TX - 1 && lz == TZ - 1);
-        dirty[0][tid] = (valid && d) ? 1 : 0;
+        dirty[0][tid] = (valid && (d || pend0)) ? 1 : 0;
         dirty[1][tid] = 0;
     }
     __syncthreads();
@@ -303,9 +312,15 @@ k_adj_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
             const int node = clist[tid];
             const int nlx = node % TX, nlz = node / TX;
             const int nme = (nlz + HALO) * LSTRIDE + (nlx + HALO);
-            const double gs = G[fo + (int64_t)(j0 + nlz) * nx + (i0 + nlx)];
-            ++my_updates;
-            const double v = pull_lambda(gs, nme, ll, lc, la, lb, lcw);
+            // time band: a node below the threshold waits (pending) until the band
+            // reaches it, by which time the nodes it pulls from are final or close to it
+            const bool ready = ltau[node] >= th;
+            lpend[node] = ready ? 0 : 1;
+            double v = ll[nme];
+            if (ready) {
+                ++my_updates;
+                v = pull_lambda(G[fo + (int64_t)(j0 + nlz) * nx + (i0 + nlx)], nme, ll, lc, la, lb, lcw);
+            }
             if (v != ll[nme]) {
                 ll[nme] = v;
                 // lambda flows into this node's supports: mark those inside the tile
@@ -346,10 +361,15 @@ k_adj_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
         if (lx == TX - 1 && lz == TZ - 1) e |= 128u;
         if (e) atomicOr(&edge_out, e);
     }
+    if (valid && lpend[tid] != pend0) pend[pme] = lpend[tid];
+    // largest time of a pending node (non-negative doubles order as their bit patterns)
+    if (valid && lpend[tid]) atomicMax(&def_key, (unsigned long long)__double_as_longlong(ltau[tid]) + 1ull);
     if (my_updates) atomicAdd(&blk_updates, my_updates);
     __syncthreads();
     if (tid == 0) {
         if (blk_updates) atomicAdd(&counters[0], (unsigned long long)blk_updates);
+        const unsigned long long dk = def_key;
+        maxdef[(int64_t)f * ntiles + tile] = dk ? __longlong_as_double((long long)(dk - 1ull)) : -dinf<double>();
         uint32_t* fl = flags + (int64_t)f * ntiles;
         const unsigned e = edge_out;
         const bool hasL = tx > 0, hasR = tx + 1 < ntx, hasU = tz > 0, hasD = tz + 1 < ntz;
@@ -365,12 +385,14 @@ k_adj_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
     }
 }
 
-__global__ void k_adj_compact(uint32_t* __restrict__ flags, int64_t n, uint32_t* __restrict__ list,
+__global__ void k_adj_compact(uint32_t* __restrict__ flags, const double* __restrict__ maxdef, int64_t n,
+                              int ntiles, const double* __restrict__ theta, uint32_t* __restrict__ list,
                               uint32_t* __restrict__ lbits, uint32_t* __restrict__ count) {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
     const uint32_t b = flags[u];
-    if (b) {
+    const double md = maxdef[u];
+    if (b || (md > -dinf<double>() && md >= theta[u / ntiles])) {
         flags[u] = 0;
         const uint32_t pos = atomicAdd(count, 1u);
         list[pos] = (uint32_t)u;
@@ -379,6 +401,33 @@ __global__ void k_adj_compact(uint32_t* __restrict__ flags, int64_t n, uint32_t*
 }
 
 __global__ void k_adj_zero(uint32_t* p) { *p = 0u; }
+
+// nothing active: lower each field's threshold to its largest pending time, if any
+__global__ void k_adj_jump(const double* __restrict__ maxdef, int ntiles, double* __restrict__ theta,
+                           uint32_t* __restrict__ jumped) {
+    const int f = blockIdx.x;
+    double m = -dinf<double>();
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        const double v = maxdef[(int64_t)f * ntiles + t];
+        m = v > m ? v : m;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x + w] > red[threadIdx.x] ? red[threadIdx.x + w] : red[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] > -dinf<double>()) {
+        if (red[0] < theta[f]) theta[f] = red[0];
+        atomicAdd(jumped, 1u);
+    }
+}
+
+__global__ void k_adj_advance(double* __restrict__ theta, double step, int nf) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < nf) theta[f] -= step;
+}
 
 // ---------------------------------------------------------------------------------------
 // right-hand side: g = dL/dT at the receivers, one thread per field (receivers in order)
@@ -390,10 +439,12 @@ __global__ void k_adj_rhs(int mode, int nf, int nrec, int nx, int64_t N, int ntx
                           const int2* __restrict__ rec, const greal* __restrict__ in,
                           const double* __restrict__ T, double* __restrict__ G,
                           outreal* __restrict__ trec, double* __restrict__ lossf,
-                          uint32_t* __restrict__ flags, int ntiles) {
+                          uint32_t* __restrict__ flags, int ntiles, double* __restrict__ theta,
+                          int banded) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     double L = 0.0;
+    double tmax = -dinf<double>();
     for (int r = 0; r < nrec; ++r) {
         const int2 x = rec[r];
         const int64_t p = (int64_t)f * N + (int64_t)x.y * nx + x.x;
@@ -405,9 +456,12 @@ __global__ void k_adj_rhs(int mode, int nf, int nrec, int nx, int64_t N, int ntx
             if (trec) trec[(int64_t)f * nrec + r] = (outreal)t;
         }
         G[p] += g;
+        tmax = T[p] > tmax ? T[p] : tmax;
         flags[(int64_t)f * ntiles + (x.y / TZ) * ntx + (x.x / TX)] |= TF_SELF;
     }
     if (lossf) lossf[f] = L;
+    // nodes later than every receiver carry no sensitivity: the band starts there
+    theta[f] = banded ? tmax : -dinf<double>();
 }
 
 __global__ void k_adj_loss(const double* __restrict__ lossf, int nf, double* __restrict__ out) {
@@ -501,20 +555,24 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     st = solve_core<double, mreal, oreal>(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
                                                      opt, T, &fst, &fs);
     if (st != ALI_OK) return st;
+    hipStream_t S = H->stream;
+    HIPCK(H, hipEventRecord(H->ev4, S));
     const int ntx = fs.ntx, ntz = fs.ntz, ntiles = ntx * ntz;
     const int64_t nunits = (int64_t)ntiles * n_src;
-    hipStream_t S = H->stream;
 
     void *d_code, *d_wA, *d_wB, *d_wC, *d_wT, *d_lam, *d_G, *d_dacc, *d_box, *d_lossf, *d_rec;
-    void *d_flags, *d_list, *d_lbits, *d_count, *d_cnt;
+    void *d_flags, *d_list, *d_lbits, *d_count, *d_cnt, *d_pend, *d_maxdef, *d_theta;
     if (!H->scratch("a_code", sizeof(uint16_t) * NF, &d_code) ||
         !H->scratch("a_wA", sizeof(double) * NF, &d_wA) || !H->scratch("a_wB", sizeof(double) * NF, &d_wB) ||
         !H->scratch("a_wC", sizeof(double) * NF, &d_wC) || !H->scratch("a_wT", sizeof(double) * NF, &d_wT) ||
         !H->scratch("a_lam", sizeof(double) * NF, &d_lam) || !H->scratch("a_G", sizeof(double) * NF, &d_G) ||
+        !H->scratch("a_pend", sizeof(uint8_t) * NF, &d_pend) ||
         !H->scratch("a_dth", sizeof(double) * N, &d_dacc) || !H->scratch("a_box", sizeof(double) * n_src, &d_box) ||
         !H->scratch("a_lossf", sizeof(double) * n_src, &d_lossf) ||
+        !H->scratch("a_theta", sizeof(double) * n_src, &d_theta) ||
         !H->scratch("a_rec", sizeof(int2) * n_recv, &d_rec) ||
         !H->scratch("a_flags", sizeof(uint32_t) * nunits, &d_flags) ||
+        !H->scratch("a_maxdef", sizeof(double) * nunits, &d_maxdef) ||
         !H->scratch("a_list", sizeof(uint32_t) * nunits, &d_list) ||
         !H->scratch("a_lbits", sizeof(uint32_t) * nunits, &d_lbits) ||
         !H->scratch("a_count", sizeof(uint32_t), &d_count) ||
@@ -525,6 +583,9 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     HIPCK(H, hipMemcpyAsync(d_rec, hr.data(), sizeof(int2) * n_recv, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemsetAsync(d_flags, 0, sizeof(uint32_t) * nunits, S));
     HIPCK(H, hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), S));
+    // descending time band: band_cells node spacings at the fastest phase speed
+    const bool banded = opt.band_cells > 0;
+    const double band = banded ? opt.band_cells * grid->h / max_phase_speed(mats, n_mats) : 0.0;
 
     const int B = 256;
     const unsigned gNF = (unsigned)((NF + B - 1) / B);
@@ -535,9 +596,13 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     HIPCK(H, hipGetLastError());
     hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_G, NF, 0.0);
     hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_lam, NF, 0.0);
+    hipLaunchKernelGGL((k_fill<uint8_t>), dim3(gNF), dim3(B), 0, S, (uint8_t*)d_pend, NF, (uint8_t)0);
+    hipLaunchKernelGGL((k_fill<double>), dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S, (double*)d_maxdef,
+                       nunits, -dinf_host<double>());
     hipLaunchKernelGGL((k_adj_rhs<greal, outreal>), dim3((unsigned)((n_src + 63) / 64)), dim3(64), 0, S,
                        mode, n_src, n_recv, nx, N, ntx, (const int2*)d_rec, d_in, (const double*)T,
-                       (double*)d_G, d_trec, (double*)d_lossf, (uint32_t*)d_flags, ntiles);
+                       (double*)d_G, d_trec, (double*)d_lossf, (uint32_t*)d_flags, ntiles, (double*)d_theta,
+                       banded ? 1 : 0);
     HIPCK(H, hipGetLastError());
     if (mode == 1 && d_loss)
         hipLaunchKernelGGL(k_adj_loss, dim3(1), dim3(64), 0, S, (const double*)d_lossf, n_src, d_loss);
@@ -551,7 +616,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     for (;;) {
         hipLaunchKernelGGL(k_adj_zero, dim3(1), dim3(1), 0, S, (uint32_t*)d_count);
         hipLaunchKernelGGL(k_adj_compact, dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
-                           (uint32_t*)d_flags, nunits, (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_count);
+                           (uint32_t*)d_flags, (const double*)d_maxdef, nunits, ntiles, (const double*)d_theta,
+                           (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_count);
         HIPCK(H, hipGetLastError());
         HIPCK(H, hipMemcpyAsync(h_count, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
         HIPCK(H, hipStreamSynchronize(S));
@@ -562,16 +628,30 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
             pending = false;
         }
         const uint32_t n = *h_count;
-        if (n == 0) { converged = true; break; }
+        if (n == 0) {
+            // nothing active: lower the thresholds to the largest pending times, if any
+            hipLaunchKernelGGL(k_adj_zero, dim3(1), dim3(1), 0, S, (uint32_t*)d_count);
+            hipLaunchKernelGGL(k_adj_jump, dim3((unsigned)n_src), dim3(256), 0, S, (const double*)d_maxdef,
+                               ntiles, (double*)d_theta, (uint32_t*)d_count);
+            HIPCK(H, hipGetLastError());
+            HIPCK(H, hipMemcpyAsync(h_count, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
+            HIPCK(H, hipStreamSynchronize(S));
+            if (*h_count == 0) { converged = true; break; }
+            continue;
+        }
         if (iters >= opt.max_sweeps) break;
         HIPCK(H, hipEventRecord(H->ev2, S));
         hipLaunchKernelGGL(k_adj_relax, dim3(n), dim3(NTHREADS), 0, S, nx, nz, ntx, ntz,
                            (const uint32_t*)d_list, (const uint32_t*)d_lbits, (const uint16_t*)d_code,
                            (const double*)d_wA, (const double*)d_wB, (const double*)d_wC,
-                           (const double*)d_G, (double*)d_lam, (uint32_t*)d_flags, opt.inner_sweeps,
+                           (const double*)d_G, (const double*)T, (const double*)d_theta, (double*)d_lam,
+                           (uint8_t*)d_pend, (double*)d_maxdef, (uint32_t*)d_flags, opt.inner_sweeps,
                            (unsigned long long*)d_cnt);
         HIPCK(H, hipGetLastError());
         HIPCK(H, hipEventRecord(H->ev3, S));
+        if (banded)
+            hipLaunchKernelGGL(k_adj_advance, dim3((unsigned)((n_src + 63) / 64)), dim3(64), 0, S,
+                               (double*)d_theta, band, n_src);
         pending = true;
         ++iters;
         visits += n;
@@ -596,7 +676,10 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     if (stats) {
         float ms = 0.f;
         HIPCK(H, hipEventElapsedTime(&ms, H->ev0, H->ev1));
+        float fms = 0.f;
+        HIPCK(H, hipEventElapsedTime(&fms, H->ev0, H->ev4));
         stats->forward = fst;
+        stats->forward.ms = fms;
         stats->lambda_updates = (int64_t)cnt[0];
         stats->choice_mismatches = (int64_t)cnt[1];
         stats->tile_visits = visits;
@@ -716,16 +799,16 @@ extern "C" ali_status ali_misfit_gradient(ali_handle* h, const ali_grid* grid, c
                                           int32_t n_mats, const uint8_t* d_mat_id, const float* d_orient,
                                           const ali_node* srcs, int32_t n_src, const ali_node* recv,
                                           int32_t n_recv, const float* d_obs, const ali_options* opt,
-                                          float* d_Trec, double* d_loss, float* d_dLdtheta,
+                                          float* d_T, float* d_Trec, double* d_loss, float* d_dLdtheta,
                                           ali_adjoint_stats* stats) {
     if (!h) return ALI_EINVAL;
     const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
     if (arith == ALI_ARITH_MIXED)
         return adjoint_impl<float, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, recv,
-                                                        n_recv, 1, d_obs, opt, nullptr, d_Trec, d_loss, d_dLdtheta, stats);
+                                                        n_recv, 1, d_obs, opt, d_T, d_Trec, d_loss, d_dLdtheta, stats);
     if (arith == ALI_ARITH_F64)
         return adjoint_impl<double, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, recv,
-                                                         n_recv, 1, d_obs, opt, nullptr, d_Trec, d_loss, d_dLdtheta, stats);
+                                                         n_recv, 1, d_obs, opt, d_T, d_Trec, d_loss, d_dLdtheta, stats);
     return h->fail(ALI_EUNSUPPORTED, "the adjoint needs float64 travel times: use ALI_ARITH_MIXED or ALI_ARITH_F64");
 }
 
@@ -733,11 +816,11 @@ extern "C" ali_status ali_misfit_gradient_f64(ali_handle* h, const ali_grid* gri
                                               int32_t n_mats, const uint8_t* d_mat_id, const double* d_orient,
                                               const ali_node* srcs, int32_t n_src, const ali_node* recv,
                                               int32_t n_recv, const double* d_obs, const ali_options* opt,
-                                              double* d_Trec, double* d_loss, double* d_dLdtheta,
+                                              double* d_T, double* d_Trec, double* d_loss, double* d_dLdtheta,
                                               ali_adjoint_stats* stats) {
     if (!h) return ALI_EINVAL;
     return adjoint_impl<double, double, double, double>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, recv,
-                                                        n_recv, 1, d_obs, opt, nullptr, d_Trec, d_loss, d_dLdtheta, stats);
+                                                        n_recv, 1, d_obs, opt, d_T, d_Trec, d_loss, d_dLdtheta, stats);
 }
 
 extern "C" ali_status ali_bilinear(ali_handle* h, int32_t nz, int32_t nx, int32_t ncz, int32_t ncx,

@@ -27,7 +27,7 @@ extern "C" ali_status ali_create(ali_handle** out, int device, void* hip_stream)
     h->stream = (hipStream_t)hip_stream;
     if (hipSetDevice(device) != hipSuccess || hipEventCreate(&h->ev0) != hipSuccess ||
         hipEventCreate(&h->ev1) != hipSuccess || hipEventCreate(&h->ev2) != hipSuccess ||
-        hipEventCreate(&h->ev3) != hipSuccess ||
+        hipEventCreate(&h->ev3) != hipSuccess || hipEventCreate(&h->ev4) != hipSuccess ||
         hipHostMalloc((void**)&h->host_count, sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess) {
         ali_destroy(h);
         return ALI_EDEVICE;
@@ -47,6 +47,7 @@ extern "C" ali_status ali_destroy(ali_handle* h) {
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     if (h->ev2) (void)hipEventDestroy(h->ev2);
     if (h->ev3) (void)hipEventDestroy(h->ev3);
+    if (h->ev4) (void)hipEventDestroy(h->ev4);
     if (h->host_count) (void)hipHostFree(h->host_count);
     delete h;
     return ALI_OK;

@@ -13,7 +13,7 @@
 struct ali_handle {
     int device = 0;
     hipStream_t stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr;
     uint32_t* host_count = nullptr;           // pinned 4-byte readback slot
     std::string err;
     struct Buf { void* p = nullptr; size_t bytes = 0; };

@@ -341,17 +341,7 @@ ali_status solve_core(ali_handle* H, const ali_grid* grid, const ali_material* m
 
     const std::vector<MatDev<mreal>> hm = make_matdev<mreal>(mats, n_mats, grid->h);
     // band step: band_cells node spacings at the fastest phase speed of the medium
-    double vmax = 0.0;
-    for (int k = 0; k < n_mats; ++k)
-        for (int q = 0; q <= 180; ++q) {
-            const double psi = q * (3.14159265358979323846 / 360.0);
-            const MatA& A = hm[k].A;
-            const double c = cos(2.0 * psi), sn = sin(2.0 * psi);
-            const double lin = (A.a33 - A.a11) + (A.a11 + A.a33 - 2.0 * A.a55) * c;
-            const double v2 = 0.25 * ((A.a11 + A.a33 + 2.0 * A.a55) + (A.a33 - A.a11) * c +
-                                      sqrt(lin * lin + 4.0 * (A.a13 + A.a55) * (A.a13 + A.a55) * sn * sn));
-            if (v2 > vmax * vmax) vmax = sqrt(v2);
-        }
+    const double vmax = max_phase_speed(mats, n_mats);
     const real band = opt.band_cells > 0 ? (real)(opt.band_cells * grid->h / vmax) : dinf_host<real>();
     std::vector<real> hstep(n_src, band), htheta(n_src, band);
 

@@ -45,6 +45,25 @@ inline std::vector<MatDev<mreal>> make_matdev(const ali_material* mats, int n_ma
     return hm;
 }
 
+// fastest qP phase speed over the materials (sampled every half degree): the time band
+// of the relaxations is a number of node spacings at this speed
+inline double max_phase_speed(const ali_material* mats, int n_mats) {
+    double vmax = 0.0;
+    for (int k = 0; k < n_mats; ++k) {
+        const ali_material& m = mats[k];
+        const double a11 = m.c11 / m.rho, a13 = m.c13 / m.rho, a33 = m.c33 / m.rho, a55 = m.c55 / m.rho;
+        for (int q = 0; q <= 180; ++q) {
+            const double psi = q * (3.14159265358979323846 / 360.0);
+            const double c = cos(2.0 * psi), sn = sin(2.0 * psi);
+            const double lin = (a33 - a11) + (a11 + a33 - 2.0 * a55) * c;
+            const double v2 = 0.25 * ((a11 + a33 + 2.0 * a55) + (a33 - a11) * c +
+                                      sqrt(lin * lin + 4.0 * (a13 + a55) * (a13 + a55) * sn * sn));
+            if (v2 > vmax * vmax) vmax = sqrt(v2);
+        }
+    }
+    return vmax;
+}
+
 template <typename dst, typename srcT>
 __global__ void k_convert(dst* __restrict__ out, const srcT* __restrict__ in, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
