@@ -52,9 +52,10 @@ typedef struct { int32_t i, j; } ali_node;
 typedef struct {
     int32_t src_box_radius;  /* straight-ray box half-width in nodes (Section 4.4); default 2   */
     int32_t max_sweeps;      /* cap on outer relaxation passes; default 1000000                 */
-    int32_t inner_sweeps;    /* cap on sweeps inside one tile visit; default 64                 */
+    int32_t inner_sweeps;    /* cap on sweeps inside one tile visit (unfinished nodes carry over
+                                to the next pass); default 2                                    */
     int32_t band_cells;      /* width of the relaxation time band in node spacings at the
-                                fastest phase speed; 0 = no band; default 2                   */
+                                fastest phase speed; 0 = no band; default 1                   */
     int32_t ray_window;      /* ray tracer: candidate window either side of the straight-ahead
                                 intersection, in node spacings (Section 5.1 limits the candidates,
                                 no value given); default 4                                      */

@@ -13,6 +13,9 @@ SOURCES = ["ali_capi.hip", "ali_solve.hip", "ali_rays.hip", "ali_adjoint.hip", "
 
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # no implicit multiply-add contraction: the same estimate must round identically in
+    # every kernel that evaluates it (fused operations are written out where wanted)
+    "-ffp-contract=off",
     # never emit packed fp32 arithmetic (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

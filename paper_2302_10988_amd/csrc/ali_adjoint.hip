@@ -54,16 +54,6 @@ __device__ __forceinline__ StGeo stencil_geo(int s, std::integer_sequence<int, S
     return g;
 }
 
-// diamond slot and grid direction of the k-th 8-neighbour (straight-ray candidates)
-__device__ __forceinline__ int fb_slot(int k) {
-    switch (k) { case 0: return 1; case 1: return 2; case 2: return 3; case 3: return 5;
-                 case 4: return 6; case 5: return 8; case 6: return 9; default: return 10; }
-}
-__device__ __forceinline__ int fb_dir(int k) {
-    switch (k) { case 0: return 1; case 1: return 2; case 2: return 3; case 3: return 0;
-                 case 4: return 0; case 5: return 3; case 6: return 2; default: return 1; }
-}
-
 // Float64 node constants for the derivatives (the phase-speed constants / h^2 and the
 // double angle of the axis).
 struct NodeD { double c2t, s2t, P, Q, R, K4; };
@@ -184,7 +174,7 @@ k_adj_prep(int nx, int nz, int ntx, int ntz, double h, const MatDev<mreal>* __re
             cd = make_code(K_STENCIL, (unsigned)g.sa, (unsigned)g.sb, (unsigned)g.sc);
         } else if (ch >= 32) {
             const int k = ch - 32;
-            const int d = fb_dir(k);
+            const int d = fb_dir_rt(k);
             const double quarter = 0.78539816339744830962;
             const double ang = d == 0 ? 0.0 : d == 1 ? quarter : d == 2 ? 2.0 * quarter : -quarter;
             const double len = (d & 1) ? 1.41421356237309504880 : 1.0;
@@ -192,7 +182,7 @@ k_adj_prep(int nx, int nz, int ntx, int ntz, double h, const MatDev<mreal>* __re
             const double V = group_speed(A, ang - th, &dV);
             a = 1.0;
             t = len * h * dV / (V * V);
-            cd = make_code(K_FALLBACK, (unsigned)fb_slot(k), NO_SLOT, NO_SLOT);
+            cd = make_code(K_FALLBACK, (unsigned)fb_slot_rt(k), NO_SLOT, NO_SLOT);
         }
     }
     code[q] = cd;

@@ -8,8 +8,8 @@ extern "C" void ali_default_options(ali_options* o) {
     if (!o) return;
     o->src_box_radius = 2;
     o->max_sweeps = 1000000;
-    o->inner_sweeps = 64;
-    o->band_cells = 2;
+    o->inner_sweeps = 2;
+    o->band_cells = 1;
     o->ray_window = 4;
     o->ray_max_pts = 4096;
     o->arith = ALI_ARITH_MIXED;
@@ -28,10 +28,16 @@ extern "C" ali_status ali_create(ali_handle** out, int device, void* hip_stream)
     if (hipSetDevice(device) != hipSuccess || hipEventCreate(&h->ev0) != hipSuccess ||
         hipEventCreate(&h->ev1) != hipSuccess || hipEventCreate(&h->ev2) != hipSuccess ||
         hipEventCreate(&h->ev3) != hipSuccess || hipEventCreate(&h->ev4) != hipSuccess ||
-        hipHostMalloc((void**)&h->host_count, sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&h->host_count, sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess ||
+        hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
         ali_destroy(h);
         return ALI_EDEVICE;
     }
+    for (int k = 0; k < 2 * ALI_PASS_BATCH; ++k)
+        if (hipEventCreate(&h->pev[k]) != hipSuccess) {
+            ali_destroy(h);
+            return ALI_EDEVICE;
+        }
     *out = h;
     return ALI_OK;
 }
@@ -48,6 +54,8 @@ extern "C" ali_status ali_destroy(ali_handle* h) {
     if (h->ev2) (void)hipEventDestroy(h->ev2);
     if (h->ev3) (void)hipEventDestroy(h->ev3);
     if (h->ev4) (void)hipEventDestroy(h->ev4);
+    for (int k = 0; k < 2 * ALI_PASS_BATCH; ++k)
+        if (h->pev[k]) (void)hipEventDestroy(h->pev[k]);
     if (h->host_count) (void)hipHostFree(h->host_count);
     delete h;
     return ALI_OK;

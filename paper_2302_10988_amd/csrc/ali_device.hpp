@@ -45,6 +45,11 @@ template <> __device__ __forceinline__ double dinf<double>() { return __builtin_
 // ---------------------------------------------------------------------------------------
 constexpr int SLOT_DI[12] = {0, -1, 0, 1, -2, -1, 1, 2, -1, 0, 1, 0};
 constexpr int SLOT_DJ[12] = {-2, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 2};
+// the same offsets for a slot number known only at run time
+__host__ __device__ constexpr int SLOT_DI_RT(int k) {
+    return (k == 1 || k == 5 || k == 8) ? -1 : (k == 3 || k == 6 || k == 10) ? 1 : k == 4 ? -2 : k == 7 ? 2 : 0;
+}
+__host__ __device__ constexpr int SLOT_DJ_RT(int k) { return k == 0 ? -2 : k <= 3 ? -1 : k <= 7 ? 0 : k <= 10 ? 1 : 2; }
 
 // Tables 1-2 as 16 pairs (A, P, Q): member 1 has B = P, C = Q; member 2 swaps B and C.
 // Pairs 1-4 are the unit squares, 5-8 the sqrt(2) squares, 9-16 the triangles (member 1:
@@ -57,10 +62,6 @@ constexpr int PAIR_Q[16] = {5, 5, 9, 6, 8, 8, 1, 3, 10, 3, 1, 8, 8, 10, 3, 1};
 // the grid direction of each (0: x axis, 1: (1,1) diagonal, 2: z axis, 3: (1,-1) diagonal)
 constexpr int FB_SLOT[8] = {1, 2, 3, 5, 6, 8, 9, 10};
 constexpr int FB_DIR[8] = {1, 2, 3, 0, 0, 3, 2, 1};
-__host__ __device__ constexpr int fb_local(int slot) {
-    return slot == 1 ? 0 : slot == 2 ? 1 : slot == 3 ? 2 : slot == 5 ? 3 : slot == 6 ? 4
-         : slot == 8 ? 5 : slot == 9 ? 6 : slot == 10 ? 7 : -1;
-}
 
 // stencil s = 2*pair + member (0-based member), table order 1-1, 1-2, 2-1, ..., 16-2
 template <int S> struct Stencil {
@@ -103,21 +104,26 @@ template <typename real> struct Best {
     unsigned evals;         // single-stencil estimates computed (statistics only)
 };
 
-// travel time from the wavefront EB to D (|FD| / v) in the math type
+__device__ __forceinline__ float dfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double dfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// travel time from the wavefront EB to D (|FD| / v) in the math type.  The multiply-adds
+// are explicit fused operations and the build forbids implicit contraction, so every
+// kernel that evaluates an estimate rounds it the same way.
 template <typename real, typename treal>
 __device__ __forceinline__ real stencil_incr(const NodeConst<real, treal>& n, real a, int bx, int bz,
                                              int cx, int cz, int k1, int k2) {
     // w = (B - A) - a (C - A)
-    const real wx = real(bx) - a * real(cx);
-    const real wz = real(bz) - a * real(cz);
-    const real cr = real(k1) - a * real(k2);
-    const real w2 = wx * wx + wz * wz;
-    const real dd = wz * wz - wx * wx;            // |w|^2 cos 2phi_n
-    const real xz = real(-2) * wx * wz;           // |w|^2 sin 2phi_n
-    const real c = dd * n.c2t + xz * n.s2t;       // |w|^2 cos 2psi
-    const real s2 = w2 * w2 - c * c;              // (|w|^2 sin 2psi)^2
-    const real lin = n.Q * w2 + n.R * c;
-    const real G4 = n.P * w2 + n.Q * c + dsqrt(lin * lin + n.K4 * s2);   // 4 G
+    const real wx = dfma(-a, real(cx), real(bx));
+    const real wz = dfma(-a, real(cz), real(bz));
+    const real cr = dfma(-a, real(k2), real(k1));
+    const real w2 = dfma(wx, wx, wz * wz);
+    const real dd = dfma(wz, wz, -(wx * wx));        // |w|^2 cos 2phi_n
+    const real xz = real(-2) * wx * wz;               // |w|^2 sin 2phi_n
+    const real c = dfma(dd, n.c2t, xz * n.s2t);       // |w|^2 cos 2psi
+    const real s2 = dfma(w2, w2, -(c * c));           // (|w|^2 sin 2psi)^2
+    const real lin = dfma(n.Q, w2, n.R * c);
+    const real G4 = dfma(n.P, w2, dfma(n.Q, c, dsqrt(dfma(lin, lin, n.K4 * s2))));   // 4 G
     // |FD|/v = |cr| / sqrt(G) = 2 |cr| / sqrt(4G)
     return real(2) * __builtin_fabs(cr) * drsqrt(G4);
 }
@@ -129,51 +135,83 @@ __device__ __forceinline__ mreal interp_weight(treal ta, treal tb, treal tc) {
     return dratio((mreal)(tb - ta), (mreal)(tc - ta));
 }
 
-template <typename mreal, typename real, int S>
-__device__ __forceinline__ void eval_stencil(const NodeConst<mreal, real>& n, real ta, real tb, real tc,
-                                             Best<real>& best, real& minU) {
-    using St = Stencil<S>;
-    ++best.evals;
-    const mreal a = interp_weight<mreal, real>(ta, tb, tc);
-    const real U = tb + (real)stencil_incr<mreal, real>(n, a, St::bx, St::bz, St::cx, St::cz, St::k1, St::k2);
-    if (!(U > tc)) return;                        // causality
-    real score;
-    if (St::cls == 0) {
-        score = tc - tb;
-    } else {
-        // triangles: distance of the diagonal point's time from the isosceles interpolant
-        const real r2m1 = real(0.41421356237309504880);   // sqrt(2) - 1
-        const real tm = real(0.58578643762690495120);     // 2 - sqrt(2)
-        if (St::second) score = __builtin_fabs(tb - (r2m1 * ta + tm * tc));
-        else            score = __builtin_fabs(tc - (r2m1 * ta + tm * tb));
-    }
-    minU = U < minU ? U : minU;
+// One stencil pair of Tables 1-2 as data: the diamond slots of A, P, Q, the class, the
+// activation slot of a tie, and the geometry (B - A, C - A, k1, k2) of both members.
+struct PairTab {
+    int8_t a, p, q;          // diamond slots
+    int8_t cls;              // 0 square, 1 triangle
+    int8_t tie;              // activation slot when tau_B == tau_C
+    int8_t g1[6], g2[6];     // bx, bz, cx, cz, k1, k2 of member 1 and member 2
+};
+template <int PAIR> constexpr PairTab make_pair_tab() {
+    using S1 = Stencil<2 * PAIR>;
+    using S2 = Stencil<2 * PAIR + 1>;
+    return PairTab{(int8_t)PAIR_A[PAIR], (int8_t)PAIR_P[PAIR], (int8_t)PAIR_Q[PAIR], (int8_t)S1::cls,
+                   (int8_t)S1::tie_slot,
+                   {(int8_t)S1::bx, (int8_t)S1::bz, (int8_t)S1::cx, (int8_t)S1::cz, (int8_t)S1::k1, (int8_t)S1::k2},
+                   {(int8_t)S2::bx, (int8_t)S2::bz, (int8_t)S2::cx, (int8_t)S2::cz, (int8_t)S2::k1, (int8_t)S2::k2}};
+}
+static __constant__ PairTab PAIRS[16] = {
+    make_pair_tab<0>(), make_pair_tab<1>(), make_pair_tab<2>(), make_pair_tab<3>(),
+    make_pair_tab<4>(), make_pair_tab<5>(), make_pair_tab<6>(), make_pair_tab<7>(),
+    make_pair_tab<8>(), make_pair_tab<9>(), make_pair_tab<10>(), make_pair_tab<11>(),
+    make_pair_tab<12>(), make_pair_tab<13>(), make_pair_tab<14>(), make_pair_tab<15>()};
+
+// Candidate of one member: estimate, causality, rank against the best so far.  Every lane
+// runs the same instructions (selects, no branches).
+template <typename mreal, typename real>
+__device__ __forceinline__ void member_candidate(const NodeConst<mreal, real>& n, const int8_t (&g)[6],
+                                                 real tA, real tB, real tC, real score, bool ok, int cls,
+                                                 int ks, int idx, Best<real>& best, real& minU) {
+    best.evals += ok ? 1u : 0u;
+    const mreal a = interp_weight<mreal, real>(tA, tB, tC);
+    const real U = tB + (real)stencil_incr<mreal, real>(n, a, g[0], g[1], g[2], g[3], g[4], g[5]);
+    const bool cand = ok && U > tC;                // causality
+    minU = (cand && U < minU) ? U : minU;
     // table order is the evaluation order, so an equal score never displaces the best
-    const bool better = St::cls < best.cls || (St::cls == best.cls && score < best.score);
-    if (better) {
-        best.cls = St::cls;
-        best.score = score;
-        best.U = U;
-        best.kt = tc;
-        best.ks = (tb == tc) ? St::tie_slot : St::sc;
-        best.idx = S;
-    }
+    const bool better = cand && (cls < best.cls || (cls == best.cls && score < best.score));
+    best.cls = better ? cls : best.cls;
+    best.score = better ? score : best.score;
+    best.U = better ? U : best.U;
+    best.kt = better ? tC : best.kt;
+    best.ks = better ? ks : best.ks;
+    best.idx = better ? idx : best.idx;
 }
 
+// One stencil pair with compile-time geometry.  The two members order the same three
+// points (member 1: B = P, C = Q; member 2: B = Q, C = P), so only one of them can satisfy
+// tau_A < tau_B <= tau_C unless tau_P == tau_Q; the admissible member's geometry is picked
+// by selects, so every lane runs the same instructions.  A tie evaluates member 2 as well,
+// after member 1 (table order).
 template <typename mreal, typename real, int PAIR>
 __device__ __forceinline__ void eval_pair(const NodeConst<mreal, real>& n, const real (&t)[12],
                                           Best<real>& best, real& minU) {
+    using S1 = Stencil<2 * PAIR>;
+    using S2 = Stencil<2 * PAIR + 1>;
     const real inf = dinf<real>();
     const real tA = t[PAIR_A[PAIR]], tP = t[PAIR_P[PAIR]], tQ = t[PAIR_Q[PAIR]];
-    // ordering tau_A < tau_B <= tau_C with both B, C known (finite)
-    if (tA < tP && tP <= tQ && tQ < inf) eval_stencil<mreal, real, 2 * PAIR>(n, tA, tP, tQ, best, minU);
-    if (tA < tQ && tQ <= tP && tP < inf) eval_stencil<mreal, real, 2 * PAIR + 1>(n, tA, tQ, tP, best, minU);
+    const bool m1 = tP <= tQ;
+    const real tB = m1 ? tP : tQ, tC = m1 ? tQ : tP;
+    const bool ok = tA < tB && tC < inf;
+    // score: squares by tau_C - tau_B; triangles (P axial, Q diagonal) by the distance of
+    // the diagonal point's time from the isosceles interpolant (same for both members)
+    const real r2m1 = real(0.41421356237309504880);   // sqrt(2) - 1
+    const real tm = real(0.58578643762690495120);     // 2 - sqrt(2)
+    const real score = S1::cls == 0 ? tC - tB : __builtin_fabs(tQ - (r2m1 * tA + tm * tP));
+    const int ks = (tB == tC) ? S1::tie_slot : (m1 ? S1::sc : S2::sc);
+    const int8_t g[6] = {(int8_t)(m1 ? S1::bx : S2::bx), (int8_t)(m1 ? S1::bz : S2::bz),
+                         (int8_t)(m1 ? S1::cx : S2::cx), (int8_t)(m1 ? S1::cz : S2::cz),
+                         (int8_t)(m1 ? S1::k1 : S2::k1), (int8_t)(m1 ? S1::k2 : S2::k2)};
+    member_candidate<mreal, real>(n, g, tA, tB, tC, score, ok, S1::cls, ks, m1 ? 2 * PAIR : 2 * PAIR + 1, best, minU);
+    if (tP == tQ && ok) {
+        const int8_t g2[6] = {(int8_t)S2::bx, (int8_t)S2::bz, (int8_t)S2::cx, (int8_t)S2::cz, (int8_t)S2::k1, (int8_t)S2::k2};
+        member_candidate<mreal, real>(n, g2, tA, tQ, tP, score, true, S1::cls, S1::tie_slot, 2 * PAIR + 1, best, minU);
+    }
 }
 
 template <typename mreal, typename real, int... P>
-__device__ __forceinline__ void eval_all(const NodeConst<mreal, real>& n, const real (&t)[12],
-                                         Best<real>& best, real& minU,
-                                         std::integer_sequence<int, P...>) {
+__device__ __forceinline__ void eval_pairs(const NodeConst<mreal, real>& n, const real (&t)[12],
+                                           Best<real>& best, real& minU, std::integer_sequence<int, P...>) {
     (eval_pair<mreal, real, P>(n, t, best, minU), ...);
 }
 
@@ -181,19 +219,17 @@ template <typename mreal, typename real, int K>
 __device__ __forceinline__ void eval_fallback(const NodeConst<mreal, real>& n, const real (&t)[12],
                                               Best<real>& best, real& minU) {
     const real tn = t[FB_SLOT[K]];
-    if (!(tn < dinf<real>())) return;
     const real U = tn + n.fb[FB_DIR[K]];
-    if (!(U > tn)) return;
-    minU = U < minU ? U : minU;
+    const bool cand = tn < dinf<real>() && U > tn;
+    minU = (cand && U < minU) ? U : minU;
     // class 2 ranks by value, then neighbour order (evaluated in that order)
-    if (best.cls > 2 || (best.cls == 2 && U < best.score)) {
-        best.cls = 2;
-        best.score = U;
-        best.U = U;
-        best.kt = tn;
-        best.ks = FB_SLOT[K];
-        best.idx = 32 + K;
-    }
+    const bool better = cand && (best.cls > 2 || (best.cls == 2 && U < best.score));
+    best.cls = better ? 2 : best.cls;
+    best.score = better ? U : best.score;
+    best.U = better ? U : best.U;
+    best.kt = better ? tn : best.kt;
+    best.ks = better ? FB_SLOT[K] : best.ks;
+    best.idx = better ? 32 + K : best.idx;
 }
 
 template <typename mreal, typename real, int... K>
@@ -208,108 +244,106 @@ __device__ __forceinline__ bool key_after(float u, float tk, int ks) { return u 
 __device__ __forceinline__ bool key_after(double u, double tk, int ks) { return u > tk || (u == tk && ks <= 5); }
 
 // ---------------------------------------------------------------------------------------
-// Exact slow path: walk the activation points in key order.  For each of the eight
-// possible activation points keep the best candidate activated there; the answer is the
-// first record (a candidate better than all activated before it) whose value lies below
-// the key of the next record.  Used only when the fast test below is inconclusive.
+// Exact slow path: walk the activation points (8-neighbours with a finite time) in key
+// order.  At each one, the candidate activated there is the best stencil (by class,
+// score, table order) whose activation point it is, or else the straight ray from it.
+// The answer is the first record (a candidate better than all activated before it) whose
+// value lies below the key of the next record's activation point.  Used only when the
+// fast test is inconclusive (rare), so it is written for few registers: everything is
+// recomputed per activation point from the staging buffer.
 // ---------------------------------------------------------------------------------------
-template <typename real> struct SlotBest {
-    int cls[8];
-    int idx[8];             // table index of a stencil, neighbour order of a straight ray
-    real score[8];
-    real U[8];
+__host__ __device__ constexpr int fb_slot_rt(int k) {
+    return k == 0 ? 1 : k == 1 ? 2 : k == 2 ? 3 : k == 3 ? 5 : k == 4 ? 6 : k == 5 ? 8 : k == 6 ? 9 : 10;
+}
+__host__ __device__ constexpr int fb_dir_rt(int k) {
+    return k == 0 ? 1 : k == 1 ? 2 : k == 2 ? 3 : k == 3 ? 0 : k == 4 ? 0 : k == 5 ? 3 : k == 6 ? 2 : 1;
+}
+
+// For each 8-neighbour k: the stencil members (2 * pair + member, table order) that can
+// be activated there (k is their C point, or the later of B and C when tau_B == tau_C).
+struct ActTab {
+    int8_t n[8];
+    int8_t m[8][8];
 };
-
-template <typename mreal, typename real, int S>
-__device__ __forceinline__ void slow_stencil(const NodeConst<mreal, real>& n, real ta, real tb, real tc,
-                                             SlotBest<real>& sb) {
-    using St = Stencil<S>;
-    const mreal a = interp_weight<mreal, real>(ta, tb, tc);
-    const real U = tb + (real)stencil_incr<mreal, real>(n, a, St::bx, St::bz, St::cx, St::cz, St::k1, St::k2);
-    if (!(U > tc)) return;
-    real score;
-    if (St::cls == 0) {
-        score = tc - tb;
-    } else {
-        const real r2m1 = real(0.41421356237309504880);
-        const real tm = real(0.58578643762690495120);
-        if (St::second) score = __builtin_fabs(tb - (r2m1 * ta + tm * tc));
-        else            score = __builtin_fabs(tc - (r2m1 * ta + tm * tb));
-    }
-    constexpr int kc = fb_local(St::sc);
-    constexpr int kt = fb_local(St::tie_slot);
-    static_assert(kc >= 0 && kt >= 0, "activation point outside the 8-neighbourhood");
-    // two static slots; the tie case files the candidate under the later point
-    if (tb == tc) {
-        if (St::cls < sb.cls[kt] || (St::cls == sb.cls[kt] && score < sb.score[kt])) {
-            sb.cls[kt] = St::cls; sb.idx[kt] = S; sb.score[kt] = score; sb.U[kt] = U;
+constexpr ActTab make_act_tab() {
+    ActTab t{};
+    for (int pr = 0; pr < 16; ++pr)
+        for (int mem = 0; mem < 2; ++mem) {
+            const int sb = mem == 0 ? PAIR_P[pr] : PAIR_Q[pr];
+            const int sc = mem == 0 ? PAIR_Q[pr] : PAIR_P[pr];
+            const int tie = sb > sc ? sb : sc;
+            for (int k = 0; k < 8; ++k)
+                if (FB_SLOT[k] == sc || FB_SLOT[k] == tie) t.m[k][t.n[k]++] = (int8_t)(2 * pr + mem);
         }
-    } else {
-        if (St::cls < sb.cls[kc] || (St::cls == sb.cls[kc] && score < sb.score[kc])) {
-            sb.cls[kc] = St::cls; sb.idx[kc] = S; sb.score[kc] = score; sb.U[kc] = U;
-        }
-    }
+    return t;
 }
+static __constant__ ActTab ACT = make_act_tab();
 
-template <typename mreal, typename real, int PAIR>
-__device__ __forceinline__ void slow_pair(const NodeConst<mreal, real>& n, const real (&t)[12], SlotBest<real>& sb) {
-    const real inf = dinf<real>();
-    const real tA = t[PAIR_A[PAIR]], tP = t[PAIR_P[PAIR]], tQ = t[PAIR_Q[PAIR]];
-    if (tA < tP && tP <= tQ && tQ < inf) slow_stencil<mreal, real, 2 * PAIR>(n, tA, tP, tQ, sb);
-    if (tA < tQ && tQ <= tP && tP < inf) slow_stencil<mreal, real, 2 * PAIR + 1>(n, tA, tQ, tP, sb);
-}
-
-template <typename mreal, typename real, int... P>
-__device__ __forceinline__ void slow_all(const NodeConst<mreal, real>& n, const real (&t)[12], SlotBest<real>& sb,
-                                         std::integer_sequence<int, P...>) {
-    (slow_pair<mreal, real, P>(n, t, sb), ...);
-}
-
-// The slow path re-reads the diamond from the caller's staging buffer (LDS) and takes
-// the node constants by value, so the fast path never spills them to the stack.
 template <typename mreal, typename real>
 __device__ __noinline__ real slow_update(const NodeConst<mreal, real> n, const real* __restrict__ lds,
                                          int me, int stride, int* choice) {
     const real inf = dinf<real>();
-    real t[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) t[k] = lds[me + SLOT_DJ[k] * stride + SLOT_DI[k]];
-    SlotBest<real> sb;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) { sb.cls[k] = 3; sb.idx[k] = 99; sb.score[k] = inf; sb.U[k] = inf; }
-    slow_all<mreal, real>(n, t, sb, std::make_integer_sequence<int, 16>{});
-    // straight-ray candidates fill activation points without a stencil candidate
-    unsigned rem = 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const real tn = t[FB_SLOT[k]];
-        if (sb.cls[k] == 3 && tn < inf) {
-            const real U = tn + n.fb[FB_DIR[k]];
-            if (U > tn) { sb.cls[k] = 2; sb.idx[k] = 32 + k; sb.score[k] = U; sb.U[k] = U; }
-        }
-        if (sb.cls[k] < 3) rem |= 1u << k;
-    }
-    // records in key order
-    int rcls = 3, ridx = 99;
+    const real r2m1 = real(0.41421356237309504880);
+    const real tm = real(0.58578643762690495120);
+    int rcls = 3, ridx = -1;
     real rscore = inf, rU = inf;
-    for (int it = 0; it < 8 && rem; ++it) {
-        int q = -1, ccls = 3, cidx = 99;
-        real tq = inf, cscore = inf, cU = inf;
-#pragma unroll
+    real prev_t = -inf;
+    int prev_slot = -1;
+#pragma unroll 1
+    for (int step = 0; step < 8; ++step) {
+        // next activation point in key order (time, then slot = linear-index order)
+        int q = -1;
+        real tq = inf;
+#pragma unroll 1
         for (int k = 0; k < 8; ++k) {
-            const real tk = t[FB_SLOT[k]];
-            // strict < scanning in index order keeps the smaller index on equal times
-            if (((rem >> k) & 1u) && (q < 0 || tk < tq)) {
-                q = k; tq = tk; ccls = sb.cls[k]; cscore = sb.score[k]; cU = sb.U[k]; cidx = sb.idx[k];
+            const int sl = fb_slot_rt(k);
+            const real tk = lds[me + SLOT_DJ_RT(sl) * stride + SLOT_DI_RT(sl)];
+            const bool after = tk > prev_t || (tk == prev_t && sl > prev_slot);
+            if (tk < inf && after && (q < 0 || tk < tq)) { q = k; tq = tk; }
+        }
+        if (q < 0) break;
+        const int qs = fb_slot_rt(q);
+        // best stencil activated at this point (only the members listed for it)
+        int ccls = 3, cidx = -1;
+        real cscore = inf, cU = inf;
+        const int ne = ACT.n[q];
+#pragma unroll 1
+        for (int e = 0; e < ne; ++e) {
+            const int sm = ACT.m[q][e];
+            const int pr = sm >> 1, mem = sm & 1;
+            const PairTab& pt = PAIRS[pr];
+            const real tA = lds[me + SLOT_DJ_RT(pt.a) * stride + SLOT_DI_RT(pt.a)];
+            const real tP = lds[me + SLOT_DJ_RT(pt.p) * stride + SLOT_DI_RT(pt.p)];
+            const real tQ = lds[me + SLOT_DJ_RT(pt.q) * stride + SLOT_DI_RT(pt.q)];
+            const real tB = mem == 0 ? tP : tQ, tC = mem == 0 ? tQ : tP;
+            if (!(tA < tB && tB <= tC && tC < inf)) continue;
+            const int ks = (tB == tC) ? pt.tie : (mem == 0 ? pt.q : pt.p);
+            if (ks != qs) continue;
+            const int8_t* g = mem == 0 ? pt.g1 : pt.g2;
+            const mreal a = interp_weight<mreal, real>(tA, tB, tC);
+            const real U = tB + (real)stencil_incr<mreal, real>(n, a, g[0], g[1], g[2], g[3], g[4], g[5]);
+            if (!(U > tC)) continue;
+            const real score = pt.cls == 0 ? tC - tB : __builtin_fabs(tQ - (r2m1 * tA + tm * tP));
+            if (pt.cls < ccls || (pt.cls == ccls && score < cscore)) {
+                ccls = pt.cls; cscore = score; cU = U; cidx = sm;
             }
         }
-        rem &= ~(1u << q);
-        // rank = (class, score, table index / neighbour order)
-        const bool better = ccls < rcls || (ccls == rcls && (cscore < rscore || (cscore == rscore && cidx < ridx)));
-        if (better) {
-            if (rcls < 3 && !key_after(rU, tq, FB_SLOT[q])) { *choice = ridx; return rU; }  // record below next key
-            rcls = ccls; rscore = cscore; rU = cU; ridx = cidx;
+        if (ccls == 3) {
+            const int d = fb_dir_rt(q);
+            const real fbt = d == 0 ? n.fb[0] : d == 1 ? n.fb[1] : d == 2 ? n.fb[2] : n.fb[3];
+            const real U = tq + fbt;
+            if (U > tq) { ccls = 2; cscore = U; cU = U; cidx = 32 + q; }
         }
+        // rank = (class, score, table index / neighbour order)
+        if (ccls < 3) {
+            const bool better = ccls < rcls || (ccls == rcls && (cscore < rscore || (cscore == rscore && cidx < ridx)));
+            if (better) {
+                if (rcls < 3 && !key_after(rU, tq, qs)) { *choice = ridx; return rU; }   // record below next key
+                rcls = ccls; rscore = cscore; rU = cU; ridx = cidx;
+            }
+        }
+        prev_t = tq;
+        prev_slot = qs;
     }
     *choice = rcls < 3 ? ridx : -1;
     return rcls < 3 ? rU : inf;
@@ -332,7 +366,7 @@ __device__ __forceinline__ real local_update(const NodeConst<mreal, real>& n, co
     Best<real> best;
     best.cls = 3; best.score = inf; best.U = inf; best.kt = inf; best.ks = 0; best.idx = -1; best.evals = 0;
     real minU = inf;
-    eval_all<mreal, real>(n, t, best, minU, std::make_integer_sequence<int, 16>{});
+    eval_pairs<mreal, real>(n, t, best, minU, std::make_integer_sequence<int, 16>{});
     eval_fallbacks<mreal, real>(n, t, best, minU, std::make_integer_sequence<int, 8>{});
     evals += best.evals;
     if (best.cls == 3) { if (choice) *choice = -1; return inf; }

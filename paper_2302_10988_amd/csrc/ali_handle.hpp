@@ -10,11 +10,17 @@
 
 #include "../../include/ali.h"
 
+// relaxation passes queued between two host checks
+constexpr int ALI_PASS_BATCH = 16;
+
 struct ali_handle {
     int device = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr;
     uint32_t* host_count = nullptr;           // pinned 4-byte readback slot
+    hipEvent_t pev[2 * ALI_PASS_BATCH] = {};  // per-pass timing events of one batch
+    int n_cu = 0;                             // compute units of the device
+    std::map<const void*, int> grids;         // resident work-groups per kernel (grid-stride launches)
     std::string err;
     struct Buf { void* p = nullptr; size_t bytes = 0; };
     std::map<std::string, Buf> bufs;
@@ -47,6 +53,19 @@ struct ali_handle {
     } while (0)
 
 namespace ali {
+
+constexpr int PASS_BATCH = ALI_PASS_BATCH;
+
+// work-groups of `kernel` (one wave each) that fit on the device at once
+inline int relax_grid(ali_handle* H, const void* kernel) {
+    auto it = H->grids.find(kernel);
+    if (it != H->grids.end()) return it->second;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess || per_cu < 1) return -1;
+    const int g = per_cu * H->n_cu;
+    H->grids[kernel] = g;
+    return g;
+}
 
 inline ali_status set_device(ali_handle* H) {
     HIPCK(H, hipSetDevice(H->device));

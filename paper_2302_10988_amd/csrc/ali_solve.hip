@@ -90,53 +90,82 @@ __global__ void k_init(int nx, int nz, int nf, double h, const MatDev<mreal>* __
     }
 }
 
+// Scheduler of one relaxation pass, one work-group per field: advance the field's
+// threshold by its step (not before the first pass); if none of its tiles is flagged or
+// holds a rejected value at or below the threshold, raise the threshold to its smallest
+// rejected value; then append the field's active tiles to the pass list.  cnt_cur counts
+// this pass's list; cnt_next (the next pass's counter) is cleared here.
 template <typename real>
-__global__ void k_compact(uint32_t* __restrict__ flags, real* __restrict__ minrej, int64_t n,
-                          int ntiles, const real* __restrict__ theta, uint32_t* __restrict__ list,
-                          uint32_t* __restrict__ lbits, uint32_t* __restrict__ count) {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    const int f = (int)(u / ntiles);
-    const uint32_t b = flags[u];
-    if (b || minrej[u] <= theta[f]) {
-        flags[u] = 0;
-        minrej[u] = dinf<real>();     // recomputed by the visit
-        const uint32_t pos = atomicAdd(count, 1u);
-        list[pos] = (uint32_t)u;
-        lbits[pos] = b;
-    }
-}
-
-// nothing active: move each field's threshold up to its smallest rejected value
-template <typename real>
-__global__ void k_jump(const real* __restrict__ minrej, int ntiles, int nf, real* __restrict__ theta,
-                       uint32_t* __restrict__ jumped) {
+__global__ void __launch_bounds__(256)
+k_sched(int ntiles, int advance, uint32_t* __restrict__ flags, real* __restrict__ minrej,
+        real* __restrict__ theta, const real* __restrict__ step, uint32_t* __restrict__ list,
+        uint32_t* __restrict__ lbits, uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next) {
     const int f = blockIdx.x;
-    real m = dinf<real>();
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-        const real v = minrej[(int64_t)f * ntiles + t];
+    const int tid = threadIdx.x;
+    const real inf = dinf<real>();
+    __shared__ real red_m[256];
+    __shared__ unsigned red_c[256];
+    __shared__ real th_s;
+    __shared__ uint32_t base_s;
+    if (f == 0 && tid == 0) *cnt_next = 0u;
+    uint32_t* fl = flags + (int64_t)f * ntiles;
+    real* mr = minrej + (int64_t)f * ntiles;
+    real th = theta[f];
+    if (advance) th += step[f];
+    // is anything active at this threshold, and what is the smallest rejected value?
+    unsigned act = 0;
+    real m = inf;
+    for (int t = tid; t < ntiles; t += 256) {
+        const real v = mr[t];
+        act |= (fl[t] != 0u || v <= th) ? 1u : 0u;
         m = v < m ? v : m;
     }
-    __shared__ real red[256];
-    red[threadIdx.x] = m;
+    red_m[tid] = m;
+    red_c[tid] = act;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x + w] < red[threadIdx.x] ? red[threadIdx.x + w] : red[threadIdx.x];
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+            red_m[tid] = red_m[tid + w] < red_m[tid] ? red_m[tid + w] : red_m[tid];
+            red_c[tid] |= red_c[tid + w];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0 && red[0] < dinf<real>()) {
-        if (red[0] > theta[f]) theta[f] = red[0];
-        atomicAdd(jumped, 1u);
+    if (tid == 0) {
+        if (!red_c[0] && red_m[0] < inf && red_m[0] > th) th = red_m[0];   // idle: jump
+        th_s = th;
+        theta[f] = th;
+    }
+    __syncthreads();
+    th = th_s;
+    // this work-item's active tiles (at most ceil(ntiles / 256) of them), then one slot
+    // range of the pass list for the whole group
+    unsigned mine = 0;
+    for (int t = tid; t < ntiles; t += 256) mine += (fl[t] != 0u || mr[t] <= th) ? 1u : 0u;
+    __syncthreads();
+    red_c[tid] = mine;
+    __syncthreads();
+    // inclusive scan (Hillis-Steele) of the per-item counts
+    for (int o = 1; o < 256; o <<= 1) {
+        const unsigned v = tid >= o ? red_c[tid - o] : 0u;
+        __syncthreads();
+        red_c[tid] += v;
+        __syncthreads();
+    }
+    if (tid == 255) base_s = red_c[255] ? atomicAdd(cnt_cur, red_c[255]) : 0u;
+    __syncthreads();
+    uint32_t pos = base_s + red_c[tid] - mine;
+    for (int t = tid; t < ntiles; t += 256) {
+        const uint32_t b = fl[t];
+        if (b != 0u || mr[t] <= th) {
+            fl[t] = 0u;
+            mr[t] = inf;          // recomputed by the visit
+            list[pos] = (uint32_t)((int64_t)f * ntiles + t);
+            lbits[pos] = b;
+            ++pos;
+        }
     }
 }
 
-template <typename real>
-__global__ void k_advance(real* __restrict__ theta, const real* __restrict__ step, int nf) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < nf) theta[f] += step[f];
-}
-
-__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
 
 // min of non-negative values in LDS through their integer bit patterns
 __device__ __forceinline__ void lds_min(float* p, float v) {
@@ -147,33 +176,45 @@ __device__ __forceinline__ void lds_min(double* p, double v) {
 }
 
 
-// One tile visit.  The set of nodes to evaluate is tracked per node: a node whose value
-// changes marks its diamond neighbours inside the tile for the next sweep, and each sweep
-// packs the marked nodes into the first threads of the block so that idle waves skip the
-// update altogether.  The first sweep evaluates the band front (unreached nodes with a
-// reached neighbour: new arrivals and values rejected by an earlier band), nodes next to
-// a halo side that a neighbouring tile changed, or every node (TF_SELF).
+// One tile visit by one wave (64 lanes, 4 nodes per lane; tile + halo staged in LDS).
+// The nodes to evaluate are tracked per node.  The first sweep takes every node (TF_SELF),
+// the band front (unreached nodes with a reached neighbour: new arrivals and values an
+// earlier band rejected) and the nodes a neighbouring tile marked; each later sweep takes
+// the nodes marked by changes inside the tile.  A change of node X marks a diamond
+// neighbour D in the tile only if min(old, new) <= tau_D: the update at D reads only
+// neighbours that precede D's own value in key order, so a neighbour that stays behind D
+// cannot change it.  Across tiles the marks are unconditional (the other tile may be
+// working on an older copy of X) and go to the neighbouring tile's node mask for the next
+// pass.  Each sweep packs the marked nodes into the first lanes.
 template <typename real, typename mreal>
-__global__ void __launch_bounds__(NTHREADS)
+__global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
 k_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
         const uint32_t* __restrict__ lbits,
         const MatDev<mreal>* __restrict__ mats, const uint8_t* __restrict__ mat_id,
         const mreal* __restrict__ geo, const real* __restrict__ fbt,
         const int2* __restrict__ src, int R, int inner, const real* __restrict__ theta,
         real* __restrict__ T, uint32_t* __restrict__ flags, real* __restrict__ minrej,
+        uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
+        const uint32_t* __restrict__ count, uint32_t* __restrict__ idle,
         unsigned long long* __restrict__ counters) {
     __shared__ real lt[LH * LSTRIDE];
-    __shared__ real rej[NTHREADS];
-    __shared__ uint8_t dirty[2][NTHREADS];
-    __shared__ uint8_t act[NTHREADS];
+    __shared__ uint8_t dnext[NTHREADS];
     __shared__ uint16_t clist[NTHREADS];
-    __shared__ unsigned wcount[NTHREADS / 64];
-    __shared__ real blk_rej;
-    __shared__ unsigned edge_out;
-    __shared__ unsigned blk_updates, blk_evals;
+    __shared__ uint32_t omask[9][NODE_WORDS];     // marks for the 3x3 tile neighbourhood
 
-    const uint32_t unit = list[blockIdx.x];
-    const uint32_t bits = lbits[blockIdx.x];
+    const uint32_t n_units = *count;
+    if (n_units == 0u) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *idle = 1u;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd(&counters[2], 1ull);                  // passes with work
+        atomicAdd(&counters[3], (unsigned long long)n_units);   // tile visits
+    }
+    // the work-groups walk the pass list with a grid stride
+    for (uint32_t item = blockIdx.x; item < n_units; item += gridDim.x) {
+    const uint32_t unit = list[item];
+    const uint32_t bits = lbits[item];
     const int ntiles = ntx * ntz;
     const int f = (int)(unit / (uint32_t)ntiles);
     const int tile = (int)(unit % (uint32_t)ntiles);
@@ -182,134 +223,184 @@ k_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
     const int64_t N = (int64_t)nx * nz;
     real* __restrict__ Tf = T + (int64_t)f * N;
     const real inf = dinf<real>();
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = threadIdx.x;
 
-    // stage tile + halo
-    for (int q = tid; q < LW * LH; q += NTHREADS) {
+    for (int q = lane; q < LW * LH; q += RW) {
         const int li = q % LW, lj = q / LW;
         const int gi = i0 - HALO + li, gj = j0 - HALO + lj;
         real v = inf;
         if (gi >= 0 && gj >= 0 && gi < nx && gj < nz) v = Tf[(int64_t)gj * nx + gi];
         lt[lj * LSTRIDE + li] = v;
     }
+    for (int q = lane; q < 9 * NODE_WORDS; q += RW) omask[q / NODE_WORDS][q % NODE_WORDS] = 0u;
+    for (int q = lane; q < NTHREADS; q += RW) dnext[q] = 0;
+    // incoming marks of this tile (read and cleared; this pass writes the other buffer)
+    uint32_t mk = 0u;
+    if (lane < NODE_WORDS) {
+        mk = marks_in[(int64_t)unit * NODE_WORDS + lane];
+        if (mk) marks_in[(int64_t)unit * NODE_WORDS + lane] = 0u;
+    }
     const int2 s = src[f];
     const real th = theta[f];
-    // the node this thread owns for bookkeeping
-    const int lx = tid % TX, lz = tid / TX;
-    const int gi = i0 + lx, gj = j0 + lz;
-    const bool valid = gi < nx && gj < nz;
-    const bool active = valid && !(abs(gi - s.x) <= R && abs(gj - s.y) <= R);
-    act[tid] = active ? 1 : 0;
-    rej[tid] = inf;
-    if (tid == 0) { edge_out = 0u; blk_updates = 0u; blk_evals = 0u; blk_rej = inf; }
     __syncthreads();
 
-    const int me = (lz + HALO) * LSTRIDE + (lx + HALO);
-    const real orig = lt[me];
-    {
+    // the four nodes of this lane: node = lane + 64 q (rows 4q .. 4q + 3 of the tile).
+    // Loops over them stay rolled, and nothing per node is kept in registers across the
+    // phases (the original values are re-read from global memory at the end).
+    unsigned dmask = 0u;              // bit q: node q of this lane is marked for this sweep
+    unsigned amask = 0u;              // bit q: node q of this lane is evaluated at all
+#pragma unroll 1
+    for (int q = 0; q < NPL; ++q) {
+        const int node = lane + RW * q;
+        const int lx = node % TX, lz = node / TX;
+        const int gi = i0 + lx, gj = j0 + lz;
+        const int me = (lz + HALO) * LSTRIDE + (lx + HALO);
+        const bool act = gi < nx && gj < nz && !(abs(gi - s.x) <= R && abs(gj - s.y) <= R);
+        amask |= act ? 1u << q : 0u;
+        const real cur = lt[me];
         bool any = false;
 #pragma unroll
         for (int k = 0; k < 12; ++k) any |= lt[me + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]] < inf;
-        const bool d = (bits & TF_SELF) || !(orig < inf) ||
-                       ((bits & TF_HALO_L) && lx < HALO) || ((bits & TF_HALO_R) && lx >= TX - HALO) ||
-                       ((bits & TF_HALO_U) && lz < HALO) || ((bits & TF_HALO_D) && lz >= TZ - HALO) ||
-                       ((bits & TF_HALO_UL) && lx == 0 && lz == 0) ||
-                       ((bits & TF_HALO_UR) && lx == TX - 1 && lz == 0) ||
-                       ((bits & TF_HALO_DL) && lx == 0 && lz == TZ - 1) ||
-                       ((bits & TF_HALO_DR) && lx == TX - 1 && lz == TZ - 1);
-        dirty[0][tid] = (active && any && d) ? 1 : 0;
-        dirty[1][tid] = 0;
+        const bool marked = (__shfl(mk, (node >> 5)) >> (node & 31)) & 1u;
+        // a finite node with no finite neighbour left is evaluated too (it must turn +inf)
+        if (act && (any || cur < inf) && ((bits & TF_SELF) || !(cur < inf) || marked)) dmask |= 1u << q;
     }
-    __syncthreads();
 
+    real rej = inf;                   // smallest value this lane's updates rejected
     unsigned my_updates = 0, my_evals = 0;
     bool done = false;
     for (int it = 0;; ++it) {
-        const int cur = it & 1;
         // pack the marked nodes
-        const bool d = dirty[cur][tid] != 0;
-        dirty[cur][tid] = 0;
-        const unsigned long long m = __ballot(d);
-        const unsigned below = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) wcount[wave] = (unsigned)__popcll(m);
-        __syncthreads();
-        unsigned base = 0, total = 0;
+        unsigned total = 0;
 #pragma unroll
-        for (int w = 0; w < NTHREADS / 64; ++w) {
-            const unsigned c = wcount[w];
-            base += w < wave ? c : 0u;
-            total += c;
+        for (int q = 0; q < NPL; ++q) {
+            const unsigned long long m = __ballot((dmask >> q) & 1u);
+            if ((dmask >> q) & 1u) clist[total + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)(lane + RW * q);
+            total += (unsigned)__popcll(m);
         }
-        if (d) clist[base + below] = (uint16_t)tid;
         __syncthreads();
         if (total == 0) { done = true; break; }
-        if (it == inner) break;
-        if ((unsigned)tid < total) {
-            const int node = clist[tid];
-            const int nlx = node % TX, nlz = node / TX;
-            const int nme = (nlz + HALO) * LSTRIDE + (nlx + HALO);
-            const int64_t p = (int64_t)(j0 + nlz) * nx + (i0 + nlx);
-            NodeConst<mreal, real> nc;
-            load_node_const<real, mreal>(nc, p, mats, mat_id, geo, fbt);
-            real t[12];
+        if (it == inner) break;     // sweep cap: the marked nodes carry over to the next pass
+        dmask = 0u;
+        for (unsigned c = 0; c < total; c += RW) {
+            bool chg = false;
+            real lo = real(0);
+            int node = 0;
+            if (c + lane < total) {
+                node = clist[c + lane];
+                const int nlx = node % TX, nlz = node / TX;
+                const int nme = (nlz + HALO) * LSTRIDE + (nlx + HALO);
+                const int64_t p = (int64_t)(j0 + nlz) * nx + (i0 + nlx);
+                NodeConst<mreal, real> nc;
+                load_node_const<real, mreal>(nc, p, mats, mat_id, geo, fbt);
+                real t[12];
 #pragma unroll
-            for (int k = 0; k < 12; ++k) t[k] = lt[nme + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]];
-            ++my_updates;
-            real u = local_update<mreal, real>(nc, t, lt, nme, LSTRIDE, my_evals);
-            real r = inf;
-            if (u > th && u < inf) { r = u; u = inf; }
-            rej[node] = r;
-            const real cv = lt[nme];
-            if (!(u == cv || (u >= inf && cv >= inf))) {
-                lt[nme] = u;
+                for (int k = 0; k < 12; ++k) t[k] = lt[nme + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]];
+                ++my_updates;
+                real u = local_update<mreal, real>(nc, t, lt, nme, LSTRIDE, my_evals);
+                if (u > th && u < inf) { rej = u < rej ? u : rej; u = inf; }
+                const real cv = lt[nme];
+                if (!(u == cv || (u >= inf && cv >= inf))) {
+                    lt[nme] = u;
+                    chg = true;
+                    lo = u < cv ? u : cv;
+                }
+            }
+            // every value of the chunk is stored before any neighbour is compared (the
+            // comparisons must see the neighbours' new values)
+            __syncthreads();
+            if (chg) {
+                const int nlx = node % TX, nlz = node / TX;
+                const int nme = (nlz + HALO) * LSTRIDE + (nlx + HALO);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) {
                     const int ax = nlx + SLOT_DI[k], az = nlz + SLOT_DJ[k];
-                    if (ax >= 0 && az >= 0 && ax < TX && az < TZ && act[az * TX + ax])
-                        dirty[cur ^ 1][az * TX + ax] = 1;
+                    if (ax >= 0 && az >= 0 && ax < TX && az < TZ &&
+                        lo <= lt[nme + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]])
+                        dnext[az * TX + ax] = 1;
                 }
+            }
+            __syncthreads();
+        }
+        // collect the marks for the next sweep
+#pragma unroll
+        for (int q = 0; q < NPL; ++q) {
+            const int node = lane + RW * q;
+            if (dnext[node]) {
+                dnext[node] = 0;
+                dmask |= amask & (1u << q);
             }
         }
         __syncthreads();
     }
 
-    // write back, tell neighbouring tiles which of their halo sides changed
-    const real fin = lt[me];
-    if (valid && !(fin == orig || (fin >= inf && orig >= inf))) {
-        Tf[(int64_t)gj * nx + gi] = fin;
-        unsigned e = 0;
-        if (lx < HALO) e |= 1u;
-        if (lx >= TX - HALO) e |= 2u;
-        if (lz < HALO) e |= 4u;
-        if (lz >= TZ - HALO) e |= 8u;
-        if (lx == 0 && lz == 0) e |= 16u;
-        if (lx == TX - 1 && lz == 0) e |= 32u;
-        if (lx == 0 && lz == TZ - 1) e |= 64u;
-        if (lx == TX - 1 && lz == TZ - 1) e |= 128u;
-        if (e) atomicOr(&edge_out, e);
+    // write back; mark the diamond neighbours of changed nodes in the neighbouring tiles
+    // (and, after the sweep cap, this tile's own unfinished nodes)
+    bool any_out = false;
+    if (!done) {
+#pragma unroll 1
+        for (int q = 0; q < NPL; ++q)
+            if ((dmask >> q) & 1u) {
+                const int node = lane + RW * q;
+                atomicOr(&omask[4][node >> 5], 1u << (node & 31));
+                any_out = true;
+            }
     }
-    if (rej[tid] < inf) lds_min(&blk_rej, rej[tid]);
-    if (my_updates) { atomicAdd(&blk_updates, my_updates); atomicAdd(&blk_evals, my_evals); }
-    __syncthreads();
-    if (tid == 0) {
-        if (blk_updates) {
-            atomicAdd(&counters[0], (unsigned long long)blk_updates);
-            atomicAdd(&counters[1], (unsigned long long)blk_evals);
+#pragma unroll 1
+    for (int q = 0; q < NPL; ++q) {
+        const int node = lane + RW * q;
+        const int lx = node % TX, lz = node / TX;
+        const int gi = i0 + lx, gj = j0 + lz;
+        if (gi >= nx || gj >= nz) continue;
+        const real fin = lt[(lz + HALO) * LSTRIDE + (lx + HALO)];
+        const real org = Tf[(int64_t)gj * nx + gi];     // only this visit writes the tile's nodes
+        if (fin == org || (fin >= inf && org >= inf)) continue;
+        Tf[(int64_t)gj * nx + gi] = fin;
+        if (lx >= HALO && lx < TX - HALO && lz >= HALO && lz < TZ - HALO) continue;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const int ax = lx + SLOT_DI[k], az = lz + SLOT_DJ[k];
+            if (ax >= 0 && az >= 0 && ax < TX && az < TZ) continue;
+            const int ngi = gi + SLOT_DI[k], ngj = gj + SLOT_DJ[k];
+            if (ngi < 0 || ngj < 0 || ngi >= nx || ngj >= nz) continue;
+            const int ox = ax < 0 ? 0 : (ax < TX ? 1 : 2), oz = az < 0 ? 0 : (az < TZ ? 1 : 2);
+            const int nn = (az - (oz - 1) * TZ) * TX + (ax - (ox - 1) * TX);
+            atomicOr(&omask[oz * 3 + ox][nn >> 5], 1u << (nn & 31));
+            any_out = true;
         }
-        uint32_t* fl = flags + (int64_t)f * ntiles;
-        minrej[(int64_t)f * ntiles + tile] = blk_rej;
-        const unsigned e = edge_out;
-        const bool hasL = tx > 0, hasR = tx + 1 < ntx, hasU = tz > 0, hasD = tz + 1 < ntz;
-        if (!done) atomicOr(&fl[tile], TF_SELF);
-        if ((e & 1u) && hasL) atomicOr(&fl[tile - 1], TF_HALO_R);
-        if ((e & 2u) && hasR) atomicOr(&fl[tile + 1], TF_HALO_L);
-        if ((e & 4u) && hasU) atomicOr(&fl[tile - ntx], TF_HALO_D);
-        if ((e & 8u) && hasD) atomicOr(&fl[tile + ntx], TF_HALO_U);
-        if ((e & 16u) && hasL && hasU) atomicOr(&fl[tile - ntx - 1], TF_HALO_DR);
-        if ((e & 32u) && hasR && hasU) atomicOr(&fl[tile - ntx + 1], TF_HALO_DL);
-        if ((e & 64u) && hasL && hasD) atomicOr(&fl[tile + ntx - 1], TF_HALO_UR);
-        if ((e & 128u) && hasR && hasD) atomicOr(&fl[tile + ntx + 1], TF_HALO_UL);
+    }
+    // wave-wide reductions
+    for (int o = 32; o > 0; o >>= 1) {
+        const real r2 = __shfl_xor(rej, o);
+        rej = r2 < rej ? r2 : rej;
+        my_updates += __shfl_xor(my_updates, o);
+        my_evals += __shfl_xor(my_evals, o);
+    }
+    const bool out = __ballot(any_out) != 0ull;
+    __syncthreads();
+    if (out) {
+        // one lane per (neighbour tile, word): push the node marks and flag the tile
+        for (int q = lane; q < 9 * NODE_WORDS; q += RW) {
+            const uint32_t w = omask[q / NODE_WORDS][q % NODE_WORDS];
+            if (!w) continue;
+            const int o = q / NODE_WORDS;
+            const int ntx2 = tx + o % 3 - 1, ntz2 = tz + o / 3 - 1;
+            const int64_t u2 = (int64_t)f * ntiles + (int64_t)ntz2 * ntx + ntx2;
+            atomicOr(&marks_out[u2 * NODE_WORDS + q % NODE_WORDS], w);
+            atomicOr(&flags[u2], TF_MARK);
+        }
+    }
+    if (lane == 0) {
+        // statistics spread over STAT_SLOTS counter pairs (one address for all visits
+        // would serialise every tile visit of a pass)
+        if (my_updates) {
+            unsigned long long* sc = counters + 4 + 2 * (blockIdx.x % STAT_SLOTS);
+            atomicAdd(&sc[0], (unsigned long long)my_updates);
+            atomicAdd(&sc[1], (unsigned long long)my_evals);
+        }
+        minrej[unit] = rej;
+    }
+    __syncthreads();     // LDS is reused by the next item
     }
 }
 
@@ -346,7 +437,7 @@ ali_status solve_core(ali_handle* H, const ali_grid* grid, const ali_material* m
     std::vector<real> hstep(n_src, band), htheta(n_src, band);
 
     void *d_mats, *d_geo, *d_fbt, *d_src, *d_flags, *d_list, *d_count, *d_upd, *d_err;
-    void *d_theta, *d_step, *d_minrej, *d_lbits;
+    void *d_theta, *d_step, *d_minrej, *d_lbits, *d_marks, *d_idle;
     if (!H->scratch("mats", sizeof(MatDev<mreal>) * n_mats, &d_mats) ||
         !H->scratch("theta", sizeof(real) * n_src, &d_theta) ||
         !H->scratch("step", sizeof(real) * n_src, &d_step) ||
@@ -357,8 +448,10 @@ ali_status solve_core(ali_handle* H, const ali_grid* grid, const ali_material* m
         !H->scratch("flags", sizeof(uint32_t) * nunits, &d_flags) ||
         !H->scratch("list", sizeof(uint32_t) * nunits, &d_list) ||
         !H->scratch("lbits", sizeof(uint32_t) * nunits, &d_lbits) ||
-        !H->scratch("count", sizeof(uint32_t), &d_count) ||
-        !H->scratch("upd", 2 * sizeof(unsigned long long), &d_upd) ||
+        !H->scratch("marks", sizeof(uint32_t) * 2 * NODE_WORDS * nunits, &d_marks) ||
+        !H->scratch("count", 2 * sizeof(uint32_t), &d_count) ||
+        !H->scratch("idle", sizeof(uint32_t), &d_idle) ||
+        !H->scratch("upd", (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), &d_upd) ||
         !H->scratch("err", sizeof(int), &d_err))
         return H->fail(ALI_ENOMEM, "device scratch allocation failed");
     std::vector<int2> hs(n_src);
@@ -370,7 +463,10 @@ ali_status solve_core(ali_handle* H, const ali_grid* grid, const ali_material* m
     HIPCK(H, hipMemcpyAsync(d_theta, htheta.data(), sizeof(real) * n_src, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemcpyAsync(d_step, hstep.data(), sizeof(real) * n_src, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemsetAsync(d_flags, 0, sizeof(uint32_t) * nunits, S));
-    HIPCK(H, hipMemsetAsync(d_upd, 0, 2 * sizeof(unsigned long long), S));
+    HIPCK(H, hipMemsetAsync(d_marks, 0, sizeof(uint32_t) * 2 * NODE_WORDS * nunits, S));
+    HIPCK(H, hipMemsetAsync(d_upd, 0, (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), S));
+    HIPCK(H, hipMemsetAsync(d_count, 0, 2 * sizeof(uint32_t), S));
+    HIPCK(H, hipMemsetAsync(d_idle, 0, sizeof(uint32_t), S));
     HIPCK(H, hipMemsetAsync(d_err, 0, sizeof(int), S));
 
     const int B = 256;
@@ -392,66 +488,59 @@ ali_status solve_core(ali_handle* H, const ali_grid* grid, const ali_material* m
     if (h_err & 1) return H->fail(ALI_EINVAL, "orientation contains NaN or Inf");
     if (h_err & 2) return H->fail(ALI_EINVAL, "material id out of range");
 
+    // passes are queued in batches without host round trips; each batch ends with one
+    // read of the idle flag (set by a relax launch that found an empty pass list: from
+    // then on nothing changes)
     int iters = 0;
-    int64_t visits = 0;
     bool converged = false;
     double relax_ms = 0.0;
-    bool pending_relax = false;
-    uint32_t* h_count = H->host_count;
+    // a fixed grid (the pass size is known only on the device); work-groups beyond the
+    // pass list exit at once
+    const int grid_relax = (int)(nunits < (int64_t)32 * H->n_cu ? nunits : (int64_t)32 * H->n_cu);
+    uint32_t* cnt = (uint32_t*)d_count;
     const int ntiles = ntx * ntz;
-    for (;;) {
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, S, (uint32_t*)d_count);
-        hipLaunchKernelGGL((k_compact<real>), dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
-                           (uint32_t*)d_flags, (real*)d_minrej, nunits, ntiles, (const real*)d_theta,
-                           (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_count);
+    while (iters < opt.max_sweeps) {
+        const int batch = opt.max_sweeps - iters < PASS_BATCH ? opt.max_sweeps - iters : PASS_BATCH;
+        for (int b = 0; b < batch; ++b) {
+            const int p = iters + b;
+            hipLaunchKernelGGL((k_sched<real>), dim3((unsigned)n_src), dim3(256), 0, S, ntiles, p > 0 ? 1 : 0,
+                               (uint32_t*)d_flags, (real*)d_minrej, (real*)d_theta, (const real*)d_step,
+                               (uint32_t*)d_list, (uint32_t*)d_lbits, cnt + (p & 1), cnt + ((p + 1) & 1));
+            uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
+            uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
+            HIPCK(H, hipEventRecord(H->pev[2 * b], S));
+            hipLaunchKernelGGL((k_relax<real, mreal>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
+                               nx, nz, ntx, ntz, (const uint32_t*)d_list, (const uint32_t*)d_lbits,
+                               (const MatDev<mreal>*)d_mats,
+                               d_mat_id, (const mreal*)d_geo, (const real*)d_fbt, (const int2*)d_src,
+                               opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
+                               (uint32_t*)d_flags, (real*)d_minrej, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)),
+                               (uint32_t*)d_idle, (unsigned long long*)d_upd);
+            HIPCK(H, hipEventRecord(H->pev[2 * b + 1], S));
+        }
         HIPCK(H, hipGetLastError());
-        HIPCK(H, hipMemcpyAsync(h_count, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
+        HIPCK(H, hipMemcpyAsync(H->host_count, d_idle, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
         HIPCK(H, hipStreamSynchronize(S));
-        if (pending_relax) {
+        for (int b = 0; b < batch; ++b) {
             float kms = 0.f;
-            HIPCK(H, hipEventElapsedTime(&kms, H->ev2, H->ev3));
+            HIPCK(H, hipEventElapsedTime(&kms, H->pev[2 * b], H->pev[2 * b + 1]));
             relax_ms += kms;
-            pending_relax = false;
         }
-        const uint32_t n = *h_count;
-        if (n == 0) {
-            // nothing active: jump thresholds to the smallest rejected values, if any
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, S, (uint32_t*)d_count);
-            hipLaunchKernelGGL((k_jump<real>), dim3((unsigned)n_src), dim3(256), 0, S,
-                               (const real*)d_minrej, ntiles, n_src, (real*)d_theta, (uint32_t*)d_count);
-            HIPCK(H, hipGetLastError());
-            HIPCK(H, hipMemcpyAsync(h_count, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
-            HIPCK(H, hipStreamSynchronize(S));
-            if (*h_count == 0) { converged = true; break; }
-            continue;
-        }
-        if (iters >= opt.max_sweeps) break;
-        HIPCK(H, hipEventRecord(H->ev2, S));
-        hipLaunchKernelGGL((k_relax<real, mreal>), dim3(n), dim3(NTHREADS), 0, S,
-                           nx, nz, ntx, ntz, (const uint32_t*)d_list, (const uint32_t*)d_lbits,
-                           (const MatDev<mreal>*)d_mats,
-                           d_mat_id, (const mreal*)d_geo, (const real*)d_fbt, (const int2*)d_src,
-                           opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
-                           (uint32_t*)d_flags, (real*)d_minrej, (unsigned long long*)d_upd);
-        HIPCK(H, hipGetLastError());
-        HIPCK(H, hipEventRecord(H->ev3, S));
-        if (opt.band_cells > 0)
-            hipLaunchKernelGGL((k_advance<real>), dim3((unsigned)((n_src + 63) / 64)), dim3(64), 0, S,
-                               (real*)d_theta, (const real*)d_step, n_src);
-        pending_relax = true;
-        ++iters;
-        visits += n;
+        iters += batch;
+        if (*H->host_count) { converged = true; break; }
     }
-    unsigned long long upd[2] = {0, 0};
-    HIPCK(H, hipMemcpyAsync(upd, d_upd, sizeof(upd), hipMemcpyDeviceToHost, S));
+    std::vector<unsigned long long> cnt_h(4 + 2 * STAT_SLOTS);
+    HIPCK(H, hipMemcpyAsync(cnt_h.data(), d_upd, sizeof(unsigned long long) * cnt_h.size(), hipMemcpyDeviceToHost, S));
     HIPCK(H, hipStreamSynchronize(S));
+    unsigned long long upd[4] = {0, 0, cnt_h[2], cnt_h[3]};
+    for (int k = 0; k < STAT_SLOTS; ++k) { upd[0] += cnt_h[4 + 2 * k]; upd[1] += cnt_h[5 + 2 * k]; }
     if (stats) {
         stats->node_updates = (int64_t)upd[0];
         stats->stencil_evals = (int64_t)upd[1];
         stats->relax_ms = relax_ms;
-        stats->tile_visits = visits;
+        stats->tile_visits = (int64_t)upd[3];
         stats->nodes = N * n_src;
-        stats->outer_iters = iters;
+        stats->outer_iters = (int32_t)upd[2];
         stats->converged = converged ? 1 : 0;
         stats->ms = 0.0;
     }

@@ -18,7 +18,11 @@ namespace ali {
 constexpr int TX = 16, TZ = 16, HALO = 2;
 constexpr int LW = TX + 2 * HALO, LH = TZ + 2 * HALO;
 constexpr int LSTRIDE = LW + 1;
-constexpr int NTHREADS = TX * TZ;
+constexpr int NTHREADS = TX * TZ;             // nodes of a tile
+constexpr int RW = 64;                        // one wave per tile visit
+constexpr int NPL = NTHREADS / RW;            // nodes per lane
+constexpr int NODE_WORDS = NTHREADS / 32;     // 32-bit words of a per-tile node mask
+constexpr int STAT_SLOTS = 256;               // spread of the statistics counters
 
 template <typename real> inline real dinf_host() { return (real)INFINITY; }
 
@@ -80,7 +84,8 @@ __global__ void k_fill(real* __restrict__ p, int64_t n, real v) {
 enum : uint32_t {
     TF_SELF = 1u,              // everything (first visit, or the previous visit hit the sweep cap)
     TF_HALO_L = 2u, TF_HALO_R = 4u, TF_HALO_U = 8u, TF_HALO_D = 16u,       // a halo side changed
-    TF_HALO_UL = 32u, TF_HALO_UR = 64u, TF_HALO_DL = 128u, TF_HALO_DR = 256u  // a halo corner changed
+    TF_HALO_UL = 32u, TF_HALO_UR = 64u, TF_HALO_DL = 128u, TF_HALO_DR = 256u, // a halo corner changed
+    TF_MARK = 512u             // a neighbouring tile marked nodes of this tile (node mask)
 };
 
 template <typename real, typename mreal>
