@@ -209,37 +209,51 @@ __device__ __forceinline__ double pull_lambda(double gsum, int me, const double*
     return s;
 }
 
-__global__ void __launch_bounds__(NTHREADS)
+// Tile visit of the lambda relaxation, one wave per tile (4 nodes per lane), laid out as
+// the forward relaxation.  A node is evaluated only once the descending threshold has
+// reached its travel time (ready); a marked node below the threshold is left pending and
+// the tile remembers its largest pending time.  A changed lambda marks the node's
+// supports: inside the tile for the next sweep, in a neighbouring tile through that
+// tile's node mask for the next pass.
+__global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
 k_adj_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
             const uint32_t* __restrict__ lbits, const uint16_t* __restrict__ code,
             const double* __restrict__ wA, const double* __restrict__ wB, const double* __restrict__ wC,
             const double* __restrict__ G, const double* __restrict__ T, const double* __restrict__ theta,
             double* __restrict__ lam, uint8_t* __restrict__ pend, double* __restrict__ maxdef,
-            uint32_t* __restrict__ flags, int inner, unsigned long long* __restrict__ counters) {
+            uint32_t* __restrict__ flags, uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
+            const uint32_t* __restrict__ count, uint32_t* __restrict__ idle, int inner,
+            unsigned long long* __restrict__ counters) {
     __shared__ double ll[LH * LSTRIDE];
     __shared__ double la[LH * LSTRIDE], lb[LH * LSTRIDE], lcw[LH * LSTRIDE];
     __shared__ uint16_t lc[LH * LSTRIDE];
-    __shared__ double ltau[NTHREADS];
+    __shared__ uint8_t dnext[NTHREADS];
     __shared__ uint8_t lpend[NTHREADS];
-    __shared__ uint8_t dirty[2][NTHREADS];
     __shared__ uint16_t clist[NTHREADS];
-    __shared__ unsigned wcount[NTHREADS / 64];
-    __shared__ unsigned edge_out, blk_updates;
-    __shared__ unsigned long long def_key;
+    __shared__ uint32_t omask[9][NODE_WORDS];
 
-    const uint32_t unit = list[blockIdx.x];
-    const uint32_t bits = lbits[blockIdx.x];
+    const uint32_t n_units = *count;
+    if (n_units == 0u) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *idle = 1u;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd(&counters[2], 1ull);
+        atomicAdd(&counters[3], (unsigned long long)n_units);
+    }
     const int ntiles = ntx * ntz;
+    const int64_t N = (int64_t)nx * nz;
+    const int lane = threadIdx.x;
+    for (uint32_t item = blockIdx.x; item < n_units; item += gridDim.x) {
+    const uint32_t unit = list[item];
+    const uint32_t bits = lbits[item];
     const int f = (int)(unit / (uint32_t)ntiles);
     const int tile = (int)(unit % (uint32_t)ntiles);
     const int tx = tile % ntx, tz = tile / ntx;
     const int i0 = tx * TX, j0 = tz * TZ;
-    const int64_t N = (int64_t)nx * nz;
     const int64_t fo = (int64_t)f * N;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
 
-    for (int q = tid; q < LW * LH; q += NTHREADS) {
+    for (int q = lane; q < LW * LH; q += RW) {
         const int li = q % LW, lj = q / LW;
         const int gi = i0 - HALO + li, gj = j0 - HALO + lj;
         const int o = lj * LSTRIDE + li;
@@ -254,169 +268,211 @@ k_adj_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
             la[o] = 0.0; lb[o] = 0.0; lcw[o] = 0.0;
         }
     }
-    const int lx = tid % TX, lz = tid / TX;
-    const int gi = i0 + lx, gj = j0 + lz;
-    const bool valid = gi < nx && gj < nz;
-    const int64_t pme = fo + (int64_t)gj * nx + gi;
-    const uint8_t pend0 = valid ? pend[pme] : 0;
-    ltau[tid] = valid ? T[pme] : 0.0;
-    lpend[tid] = pend0;
+    for (int q = lane; q < 9 * NODE_WORDS; q += RW) omask[q / NODE_WORDS][q % NODE_WORDS] = 0u;
+    for (int q = lane; q < NTHREADS; q += RW) dnext[q] = 0;
+    uint32_t mk = 0u;
+    if (lane < NODE_WORDS) {
+        mk = marks_in[(int64_t)unit * NODE_WORDS + lane];
+        if (mk) marks_in[(int64_t)unit * NODE_WORDS + lane] = 0u;
+    }
     const double th = theta[f];
-    if (tid == 0) { edge_out = 0u; blk_updates = 0u; def_key = 0ull; }
-    {
-        const bool d = (bits & TF_SELF) ||
-                       ((bits & TF_HALO_L) && lx < HALO) || ((bits & TF_HALO_R) && lx >= TX - HALO) ||
-                       ((bits & TF_HALO_U) && lz < HALO) || ((bits & TF_HALO_D) && lz >= TZ - HALO) ||
-                       ((bits & TF_HALO_UL) && lx == 0 && lz == 0) ||
-                       ((bits & TF_HALO_UR) && lx == TX - 1 && lz == 0) ||
-                       ((bits & TF_HALO_DL) && lx == 0 && lz == TZ - 1) ||
-                       ((bits & TF_HALO_DR) && lx == TX - 1 && lz == TZ - 1);
-        dirty[0][tid] = (valid && (d || pend0)) ? 1 : 0;
-        dirty[1][tid] = 0;
+    unsigned dmask = 0u, vmask = 0u;
+#pragma unroll 1
+    for (int q = 0; q < NPL; ++q) {
+        const int node = lane + RW * q;
+        const int gi = i0 + node % TX, gj = j0 + node / TX;
+        const bool valid = gi < nx && gj < nz;
+        const uint8_t pd = valid ? pend[fo + (int64_t)gj * nx + gi] : 0;
+        lpend[node] = pd;
+        const bool marked = (__shfl(mk, (node >> 5)) >> (node & 31)) & 1u;
+        vmask |= valid ? 1u << q : 0u;
+        if (valid && ((bits & TF_SELF) || marked || pd)) dmask |= 1u << q;
     }
     __syncthreads();
-    const int me = (lz + HALO) * LSTRIDE + (lx + HALO);
-    const double orig = ll[me];
+
     unsigned my_updates = 0;
     bool done = false;
+    bool any_out = false;
     for (int it = 0;; ++it) {
-        const int cur = it & 1;
-        const bool d = dirty[cur][tid] != 0;
-        dirty[cur][tid] = 0;
-        const unsigned long long m = __ballot(d);
-        const unsigned below = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) wcount[wave] = (unsigned)__popcll(m);
-        __syncthreads();
-        unsigned base = 0, total = 0;
+        unsigned total = 0;
 #pragma unroll
-        for (int w = 0; w < NTHREADS / 64; ++w) {
-            const unsigned c = wcount[w];
-            base += w < wave ? c : 0u;
-            total += c;
+        for (int q = 0; q < NPL; ++q) {
+            const unsigned long long m = __ballot((dmask >> q) & 1u);
+            if ((dmask >> q) & 1u) clist[total + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)(lane + RW * q);
+            total += (unsigned)__popcll(m);
         }
-        if (d) clist[base + below] = (uint16_t)tid;
         __syncthreads();
         if (total == 0) { done = true; break; }
-        if (it == inner) break;
-        if ((unsigned)tid < total) {
-            const int node = clist[tid];
-            const int nlx = node % TX, nlz = node / TX;
-            const int nme = (nlz + HALO) * LSTRIDE + (nlx + HALO);
-            // time band: a node below the threshold waits (pending) until the band
-            // reaches it, by which time the nodes it pulls from are final or close to it
-            const bool ready = ltau[node] >= th;
-            lpend[node] = ready ? 0 : 1;
-            double v = ll[nme];
-            if (ready) {
-                ++my_updates;
-                v = pull_lambda(G[fo + (int64_t)(j0 + nlz) * nx + (i0 + nlx)], nme, ll, lc, la, lb, lcw);
-            }
-            if (v != ll[nme]) {
-                ll[nme] = v;
-                // lambda flows into this node's supports: mark those inside the tile
-                const unsigned cd = lc[nme];
+        if (it == inner) break;     // sweep cap: the marked nodes carry over to the next pass
+        dmask = 0u;
+        for (unsigned c = 0; c < total; c += RW) {
+            if (c + lane < total) {
+                const int node = clist[c + lane];
+                const int nlx = node % TX, nlz = node / TX;
+                const int nme = (nlz + HALO) * LSTRIDE + (nlx + HALO);
+                const int64_t p = fo + (int64_t)(j0 + nlz) * nx + (i0 + nlx);
+                // time band: a node below the threshold waits until the band reaches it,
+                // by which time the nodes it pulls from are final or close to it
+                const bool ready = T[p] >= th;
+                lpend[node] = ready ? 0 : 1;
+                if (ready) {
+                    ++my_updates;
+                    const double v = pull_lambda(G[p], nme, ll, lc, la, lb, lcw);
+                    if (v != ll[nme]) {
+                        ll[nme] = v;
+                        // lambda flows into this node's supports
+                        const unsigned cd = lc[nme];
 #pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const unsigned sl = (cd >> (4 * r)) & 0xFu;
-                    if (sl < 12u) {
-                        int ax = nlx, az = nlz;
-                        switch (sl) {
-                            case 0: az -= 2; break;            case 1: ax -= 1; az -= 1; break;
-                            case 2: az -= 1; break;            case 3: ax += 1; az -= 1; break;
-                            case 4: ax -= 2; break;            case 5: ax -= 1; break;
-                            case 6: ax += 1; break;            case 7: ax += 2; break;
-                            case 8: ax -= 1; az += 1; break;   case 9: az += 1; break;
-                            case 10: ax += 1; az += 1; break;  default: az += 2; break;
+                        for (int r = 0; r < 3; ++r) {
+                            const unsigned sl = (cd >> (4 * r)) & 0xFu;
+                            if (sl >= 12u) continue;
+                            const int ax = nlx + SLOT_DI_RT((int)sl), az = nlz + SLOT_DJ_RT((int)sl);
+                            if (ax >= 0 && az >= 0 && ax < TX && az < TZ) {
+                                dnext[az * TX + ax] = 1;
+                            } else {
+                                const int ngi = i0 + ax, ngj = j0 + az;
+                                if (ngi < 0 || ngj < 0 || ngi >= nx || ngj >= nz) continue;
+                                const int ox = ax < 0 ? 0 : (ax < TX ? 1 : 2), oz = az < 0 ? 0 : (az < TZ ? 1 : 2);
+                                const int nn = (az - (oz - 1) * TZ) * TX + (ax - (ox - 1) * TX);
+                                atomicOr(&omask[oz * 3 + ox][nn >> 5], 1u << (nn & 31));
+                                any_out = true;
+                            }
                         }
-                        if (ax >= 0 && az >= 0 && ax < TX && az < TZ && i0 + ax < nx && j0 + az < nz)
-                            dirty[cur ^ 1][az * TX + ax] = 1;
                     }
                 }
             }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < NPL; ++q) {
+            const int node = lane + RW * q;
+            if (dnext[node]) {
+                dnext[node] = 0;
+                dmask |= vmask & (1u << q);
+            }
         }
         __syncthreads();
     }
 
-    const double fin = ll[me];
-    if (valid && fin != orig) {
-        lam[fo + (int64_t)gj * nx + gi] = fin;
-        unsigned e = 0;
-        if (lx < HALO) e |= 1u;
-        if (lx >= TX - HALO) e |= 2u;
-        if (lz < HALO) e |= 4u;
-        if (lz >= TZ - HALO) e |= 8u;
-        if (lx == 0 && lz == 0) e |= 16u;
-        if (lx == TX - 1 && lz == 0) e |= 32u;
-        if (lx == 0 && lz == TZ - 1) e |= 64u;
-        if (lx == TX - 1 && lz == TZ - 1) e |= 128u;
-        if (e) atomicOr(&edge_out, e);
+    // write back, carry unfinished nodes, record the largest pending time
+    if (!done) {
+#pragma unroll 1
+        for (int q = 0; q < NPL; ++q)
+            if ((dmask >> q) & 1u) {
+                const int node = lane + RW * q;
+                atomicOr(&omask[4][node >> 5], 1u << (node & 31));
+                any_out = true;
+            }
     }
-    if (valid && lpend[tid] != pend0) pend[pme] = lpend[tid];
-    // largest time of a pending node (non-negative doubles order as their bit patterns)
-    if (valid && lpend[tid]) atomicMax(&def_key, (unsigned long long)__double_as_longlong(ltau[tid]) + 1ull);
-    if (my_updates) atomicAdd(&blk_updates, my_updates);
+    double dk = -dinf<double>();
+#pragma unroll 1
+    for (int q = 0; q < NPL; ++q) {
+        const int node = lane + RW * q;
+        const int lx = node % TX, lz = node / TX;
+        const int gi = i0 + lx, gj = j0 + lz;
+        if (gi >= nx || gj >= nz) continue;
+        const int64_t p = fo + (int64_t)gj * nx + gi;
+        const double fin = ll[(lz + HALO) * LSTRIDE + (lx + HALO)];
+        if (fin != lam[p]) lam[p] = fin;          // only this visit writes the tile's nodes
+        const uint8_t pd = lpend[node];
+        if (pd != pend[p]) pend[p] = pd;
+        if (pd) { const double tp = T[p]; dk = tp > dk ? tp : dk; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double d2 = __shfl_xor(dk, o);
+        dk = d2 > dk ? d2 : dk;
+        my_updates += __shfl_xor(my_updates, o);
+    }
+    const bool out = __ballot(any_out) != 0ull;
     __syncthreads();
-    if (tid == 0) {
-        if (blk_updates) atomicAdd(&counters[0], (unsigned long long)blk_updates);
-        const unsigned long long dk = def_key;
-        maxdef[(int64_t)f * ntiles + tile] = dk ? __longlong_as_double((long long)(dk - 1ull)) : -dinf<double>();
-        uint32_t* fl = flags + (int64_t)f * ntiles;
-        const unsigned e = edge_out;
-        const bool hasL = tx > 0, hasR = tx + 1 < ntx, hasU = tz > 0, hasD = tz + 1 < ntz;
-        if (!done) atomicOr(&fl[tile], TF_SELF);
-        if ((e & 1u) && hasL) atomicOr(&fl[tile - 1], TF_HALO_R);
-        if ((e & 2u) && hasR) atomicOr(&fl[tile + 1], TF_HALO_L);
-        if ((e & 4u) && hasU) atomicOr(&fl[tile - ntx], TF_HALO_D);
-        if ((e & 8u) && hasD) atomicOr(&fl[tile + ntx], TF_HALO_U);
-        if ((e & 16u) && hasL && hasU) atomicOr(&fl[tile - ntx - 1], TF_HALO_DR);
-        if ((e & 32u) && hasR && hasU) atomicOr(&fl[tile - ntx + 1], TF_HALO_DL);
-        if ((e & 64u) && hasL && hasD) atomicOr(&fl[tile + ntx - 1], TF_HALO_UR);
-        if ((e & 128u) && hasR && hasD) atomicOr(&fl[tile + ntx + 1], TF_HALO_UL);
+    if (out) {
+        for (int q = lane; q < 9 * NODE_WORDS; q += RW) {
+            const uint32_t w = omask[q / NODE_WORDS][q % NODE_WORDS];
+            if (!w) continue;
+            const int o = q / NODE_WORDS;
+            const int64_t u2 = (int64_t)f * ntiles + (int64_t)(tz + o / 3 - 1) * ntx + (tx + o % 3 - 1);
+            atomicOr(&marks_out[u2 * NODE_WORDS + q % NODE_WORDS], w);
+            atomicOr(&flags[u2], TF_MARK);
+        }
+    }
+    if (lane == 0) {
+        if (my_updates) atomicAdd(&counters[4 + 2 * (blockIdx.x % STAT_SLOTS)], (unsigned long long)my_updates);
+        maxdef[unit] = dk;
+    }
+    __syncthreads();
     }
 }
 
-__global__ void k_adj_compact(uint32_t* __restrict__ flags, const double* __restrict__ maxdef, int64_t n,
-                              int ntiles, const double* __restrict__ theta, uint32_t* __restrict__ list,
-                              uint32_t* __restrict__ lbits, uint32_t* __restrict__ count) {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    const uint32_t b = flags[u];
-    const double md = maxdef[u];
-    if (b || (md > -dinf<double>() && md >= theta[u / ntiles])) {
-        flags[u] = 0;
-        const uint32_t pos = atomicAdd(count, 1u);
-        list[pos] = (uint32_t)u;
-        lbits[pos] = b;
-    }
-}
-
-__global__ void k_adj_zero(uint32_t* p) { *p = 0u; }
-
-// nothing active: lower each field's threshold to its largest pending time, if any
-__global__ void k_adj_jump(const double* __restrict__ maxdef, int ntiles, double* __restrict__ theta,
-                           uint32_t* __restrict__ jumped) {
+// Scheduler of one adjoint pass, one work-group per field: lower the threshold by its
+// step (not before the first pass); if no tile is flagged or holds a pending node at or
+// above the threshold, lower it to the largest pending time; then list the active tiles.
+__global__ void __launch_bounds__(256)
+k_adj_sched(int ntiles, int advance, double step, uint32_t* __restrict__ flags,
+            const double* __restrict__ maxdef, double* __restrict__ theta, uint32_t* __restrict__ list,
+            uint32_t* __restrict__ lbits, uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next) {
     const int f = blockIdx.x;
-    double m = -dinf<double>();
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-        const double v = maxdef[(int64_t)f * ntiles + t];
+    const int tid = threadIdx.x;
+    const double ninf = -dinf<double>();
+    __shared__ double red_m[256];
+    __shared__ unsigned red_c[256];
+    __shared__ double th_s;
+    __shared__ uint32_t base_s;
+    if (f == 0 && tid == 0) *cnt_next = 0u;
+    uint32_t* fl = flags + (int64_t)f * ntiles;
+    const double* md = maxdef + (int64_t)f * ntiles;
+    double th = theta[f];
+    if (advance) th -= step;
+    unsigned act = 0;
+    double m = ninf;
+    for (int t = tid; t < ntiles; t += 256) {
+        const double v = md[t];
+        act |= (fl[t] != 0u || (v > ninf && v >= th)) ? 1u : 0u;
         m = v > m ? v : m;
     }
-    __shared__ double red[256];
-    red[threadIdx.x] = m;
+    red_m[tid] = m;
+    red_c[tid] = act;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x + w] > red[threadIdx.x] ? red[threadIdx.x + w] : red[threadIdx.x];
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+            red_m[tid] = red_m[tid + w] > red_m[tid] ? red_m[tid + w] : red_m[tid];
+            red_c[tid] |= red_c[tid + w];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0 && red[0] > -dinf<double>()) {
-        if (red[0] < theta[f]) theta[f] = red[0];
-        atomicAdd(jumped, 1u);
+    if (tid == 0) {
+        if (!red_c[0] && red_m[0] > ninf && red_m[0] < th) th = red_m[0];   // idle: jump
+        th_s = th;
+        theta[f] = th;
     }
-}
-
-__global__ void k_adj_advance(double* __restrict__ theta, double step, int nf) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < nf) theta[f] -= step;
+    __syncthreads();
+    th = th_s;
+    unsigned mine = 0;
+    for (int t = tid; t < ntiles; t += 256) {
+        const double v = md[t];
+        mine += (fl[t] != 0u || (v > ninf && v >= th)) ? 1u : 0u;
+    }
+    __syncthreads();
+    red_c[tid] = mine;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const unsigned v = tid >= o ? red_c[tid - o] : 0u;
+        __syncthreads();
+        red_c[tid] += v;
+        __syncthreads();
+    }
+    if (tid == 255) base_s = red_c[255] ? atomicAdd(cnt_cur, red_c[255]) : 0u;
+    __syncthreads();
+    uint32_t pos = base_s + red_c[tid] - mine;
+    for (int t = tid; t < ntiles; t += 256) {
+        const uint32_t b = fl[t];
+        const double v = md[t];
+        if (b != 0u || (v > ninf && v >= th)) {
+            fl[t] = 0u;
+            list[pos] = (uint32_t)((int64_t)f * ntiles + t);
+            lbits[pos] = b;
+            ++pos;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -551,7 +607,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     const int64_t nunits = (int64_t)ntiles * n_src;
 
     void *d_code, *d_wA, *d_wB, *d_wC, *d_wT, *d_lam, *d_G, *d_dacc, *d_box, *d_lossf, *d_rec;
-    void *d_flags, *d_list, *d_lbits, *d_count, *d_cnt, *d_pend, *d_maxdef, *d_theta;
+    void *d_flags, *d_list, *d_lbits, *d_count, *d_cnt, *d_pend, *d_maxdef, *d_theta, *d_idle, *d_marks;
     if (!H->scratch("a_code", sizeof(uint16_t) * NF, &d_code) ||
         !H->scratch("a_wA", sizeof(double) * NF, &d_wA) || !H->scratch("a_wB", sizeof(double) * NF, &d_wB) ||
         !H->scratch("a_wC", sizeof(double) * NF, &d_wC) || !H->scratch("a_wT", sizeof(double) * NF, &d_wT) ||
@@ -565,14 +621,19 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
         !H->scratch("a_maxdef", sizeof(double) * nunits, &d_maxdef) ||
         !H->scratch("a_list", sizeof(uint32_t) * nunits, &d_list) ||
         !H->scratch("a_lbits", sizeof(uint32_t) * nunits, &d_lbits) ||
-        !H->scratch("a_count", sizeof(uint32_t), &d_count) ||
-        !H->scratch("a_cnt", 2 * sizeof(unsigned long long), &d_cnt))
+        !H->scratch("a_count", 2 * sizeof(uint32_t), &d_count) ||
+        !H->scratch("a_idle", sizeof(uint32_t), &d_idle) ||
+        !H->scratch("a_marks", sizeof(uint32_t) * 2 * NODE_WORDS * nunits, &d_marks) ||
+        !H->scratch("a_cnt", (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), &d_cnt))
         return H->fail(ALI_ENOMEM, "device scratch allocation failed");
     std::vector<int2> hr(n_recv);
     for (int r = 0; r < n_recv; ++r) hr[r] = make_int2(recv[r].i, recv[r].j);
     HIPCK(H, hipMemcpyAsync(d_rec, hr.data(), sizeof(int2) * n_recv, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemsetAsync(d_flags, 0, sizeof(uint32_t) * nunits, S));
-    HIPCK(H, hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), S));
+    HIPCK(H, hipMemsetAsync(d_marks, 0, sizeof(uint32_t) * 2 * NODE_WORDS * nunits, S));
+    HIPCK(H, hipMemsetAsync(d_count, 0, 2 * sizeof(uint32_t), S));
+    HIPCK(H, hipMemsetAsync(d_idle, 0, sizeof(uint32_t), S));
+    HIPCK(H, hipMemsetAsync(d_cnt, 0, (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), S));
     // descending time band: band_cells node spacings at the fastest phase speed
     const bool banded = opt.band_cells > 0;
     const double band = banded ? opt.band_cells * grid->h / max_phase_speed(mats, n_mats) : 0.0;
@@ -597,54 +658,41 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     if (mode == 1 && d_loss)
         hipLaunchKernelGGL(k_adj_loss, dim3(1), dim3(64), 0, S, (const double*)d_lossf, n_src, d_loss);
 
+    // passes queued in batches; the idle flag ends the loop (see the forward driver)
     int iters = 0;
-    int64_t visits = 0;
     bool converged = false;
     double relax_ms = 0.0;
-    bool pending = false;
-    uint32_t* h_count = H->host_count;
-    for (;;) {
-        hipLaunchKernelGGL(k_adj_zero, dim3(1), dim3(1), 0, S, (uint32_t*)d_count);
-        hipLaunchKernelGGL(k_adj_compact, dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
-                           (uint32_t*)d_flags, (const double*)d_maxdef, nunits, ntiles, (const double*)d_theta,
-                           (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_count);
+    const int grid_relax = (int)(nunits < (int64_t)32 * H->n_cu ? nunits : (int64_t)32 * H->n_cu);
+    uint32_t* cnt = (uint32_t*)d_count;
+    while (iters < opt.max_sweeps) {
+        const int batch = opt.max_sweeps - iters < PASS_BATCH ? opt.max_sweeps - iters : PASS_BATCH;
+        for (int bb = 0; bb < batch; ++bb) {
+            const int p = iters + bb;
+            hipLaunchKernelGGL(k_adj_sched, dim3((unsigned)n_src), dim3(256), 0, S, ntiles, p > 0 ? 1 : 0, band,
+                               (uint32_t*)d_flags, (const double*)d_maxdef, (double*)d_theta, (uint32_t*)d_list,
+                               (uint32_t*)d_lbits, cnt + (p & 1), cnt + ((p + 1) & 1));
+            uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
+            uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
+            HIPCK(H, hipEventRecord(H->pev[2 * bb], S));
+            hipLaunchKernelGGL(k_adj_relax, dim3((unsigned)grid_relax), dim3(RW), 0, S, nx, nz, ntx, ntz,
+                               (const uint32_t*)d_list, (const uint32_t*)d_lbits, (const uint16_t*)d_code,
+                               (const double*)d_wA, (const double*)d_wB, (const double*)d_wC,
+                               (const double*)d_G, (const double*)T, (const double*)d_theta, (double*)d_lam,
+                               (uint8_t*)d_pend, (double*)d_maxdef, (uint32_t*)d_flags, mk_in, mk_out,
+                               (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle, opt.inner_sweeps,
+                               (unsigned long long*)d_cnt);
+            HIPCK(H, hipEventRecord(H->pev[2 * bb + 1], S));
+        }
         HIPCK(H, hipGetLastError());
-        HIPCK(H, hipMemcpyAsync(h_count, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
+        HIPCK(H, hipMemcpyAsync(H->host_count, d_idle, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
         HIPCK(H, hipStreamSynchronize(S));
-        if (pending) {
+        for (int bb = 0; bb < batch; ++bb) {
             float kms = 0.f;
-            HIPCK(H, hipEventElapsedTime(&kms, H->ev2, H->ev3));
+            HIPCK(H, hipEventElapsedTime(&kms, H->pev[2 * bb], H->pev[2 * bb + 1]));
             relax_ms += kms;
-            pending = false;
         }
-        const uint32_t n = *h_count;
-        if (n == 0) {
-            // nothing active: lower the thresholds to the largest pending times, if any
-            hipLaunchKernelGGL(k_adj_zero, dim3(1), dim3(1), 0, S, (uint32_t*)d_count);
-            hipLaunchKernelGGL(k_adj_jump, dim3((unsigned)n_src), dim3(256), 0, S, (const double*)d_maxdef,
-                               ntiles, (double*)d_theta, (uint32_t*)d_count);
-            HIPCK(H, hipGetLastError());
-            HIPCK(H, hipMemcpyAsync(h_count, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
-            HIPCK(H, hipStreamSynchronize(S));
-            if (*h_count == 0) { converged = true; break; }
-            continue;
-        }
-        if (iters >= opt.max_sweeps) break;
-        HIPCK(H, hipEventRecord(H->ev2, S));
-        hipLaunchKernelGGL(k_adj_relax, dim3(n), dim3(NTHREADS), 0, S, nx, nz, ntx, ntz,
-                           (const uint32_t*)d_list, (const uint32_t*)d_lbits, (const uint16_t*)d_code,
-                           (const double*)d_wA, (const double*)d_wB, (const double*)d_wC,
-                           (const double*)d_G, (const double*)T, (const double*)d_theta, (double*)d_lam,
-                           (uint8_t*)d_pend, (double*)d_maxdef, (uint32_t*)d_flags, opt.inner_sweeps,
-                           (unsigned long long*)d_cnt);
-        HIPCK(H, hipGetLastError());
-        HIPCK(H, hipEventRecord(H->ev3, S));
-        if (banded)
-            hipLaunchKernelGGL(k_adj_advance, dim3((unsigned)((n_src + 63) / 64)), dim3(64), 0, S,
-                               (double*)d_theta, band, n_src);
-        pending = true;
-        ++iters;
-        visits += n;
+        iters += batch;
+        if (*H->host_count) { converged = true; break; }
     }
 
     hipLaunchKernelGGL(k_adj_grad, dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S, N, n_src,
@@ -660,9 +708,11 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
         hipLaunchKernelGGL((k_convert<outreal, double>), dim3(gNF), dim3(B), 0, S, d_T, (const double*)T, NF);
     HIPCK(H, hipGetLastError());
     HIPCK(H, hipEventRecord(H->ev1, S));
-    unsigned long long cnt[2] = {0, 0};
-    HIPCK(H, hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, S));
+    std::vector<unsigned long long> cnt_h(4 + 2 * STAT_SLOTS);
+    HIPCK(H, hipMemcpyAsync(cnt_h.data(), d_cnt, sizeof(unsigned long long) * cnt_h.size(), hipMemcpyDeviceToHost, S));
     HIPCK(H, hipStreamSynchronize(S));
+    unsigned long long lam_updates = 0;
+    for (int k = 0; k < STAT_SLOTS; ++k) lam_updates += cnt_h[4 + 2 * k];
     if (stats) {
         float ms = 0.f;
         HIPCK(H, hipEventElapsedTime(&ms, H->ev0, H->ev1));
@@ -670,10 +720,10 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
         HIPCK(H, hipEventElapsedTime(&fms, H->ev0, H->ev4));
         stats->forward = fst;
         stats->forward.ms = fms;
-        stats->lambda_updates = (int64_t)cnt[0];
-        stats->choice_mismatches = (int64_t)cnt[1];
-        stats->tile_visits = visits;
-        stats->outer_iters = iters;
+        stats->lambda_updates = (int64_t)lam_updates;
+        stats->choice_mismatches = (int64_t)cnt_h[1];
+        stats->tile_visits = (int64_t)cnt_h[3];
+        stats->outer_iters = (int32_t)cnt_h[2];
         stats->converged = converged ? 1 : 0;
         stats->ms = ms;
         stats->relax_ms = relax_ms;
