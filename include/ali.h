@@ -83,6 +83,18 @@ typedef struct {
     double  relax_ms;        /* summed duration of the relaxation kernel launches (HIP events) */
 } ali_solve_stats;
 
+/* One medium of a batch.  Offsets count elements of the arrays the batch calls take. */
+typedef struct {
+    ali_grid grid;
+    int32_t mat_offset, n_mats;   /* this medium's materials: mats[mat_offset .. + n_mats); its
+                                     material ids index this range                            */
+    int64_t node_offset;          /* first node of this medium's [nz][nx] arrays (material ids,
+                                     orientation, gradient)                                    */
+    int32_t src_offset, n_src;    /* this medium's sources: srcs[src_offset .. + n_src)          */
+    int32_t rec_offset, n_rec;    /* this medium's receivers: recv[rec_offset .. + n_rec)
+                                     (gradient calls; ignored by ali_solve_batch)             */
+} ali_medium;
+
 typedef struct ali_handle ali_handle;
 
 /* Create a handle bound to HIP device `device` and stream `hip_stream` (a hipStream_t;
@@ -125,6 +137,20 @@ ali_status ali_solve_traveltime_f64(ali_handle* h, const ali_grid* grid,
                                     const ali_node* srcs, int32_t n_src,
                                     const ali_options* opt, double* d_T,
                                     ali_solve_stats* stats);
+
+/* Fields of many media in one call: every source of every medium, relaxed together with
+   one time threshold per field (media of different sizes progress independently).
+     media[n_media]  the media (see ali_medium); 1 <= n_media
+     mats[n_mats]    material table; medium m uses mats[mat_offset ..]
+     d_mat_id, d_orient  per-node arrays of all media, medium m at node_offset
+     srcs            sources of all media, medium m at src_offset
+     d_T             output: the fields in medium order, for each medium its n_src fields of
+                     [nz][nx] one after the other (float32)
+   Options, arithmetic and errors as ali_solve_traveltime; stats cover the whole batch. */
+ali_status ali_solve_batch(ali_handle* h, const ali_medium* media, int32_t n_media,
+                           const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
+                           const float* d_orient, const ali_node* srcs, const ali_options* opt,
+                           float* d_T, ali_solve_stats* stats);
 
 /* Ray paths through finished fields (paper Section 5.1): for every source s and receiver
    r, the fastest path from r to s through field s (reciprocity), built plane by plane with
@@ -207,6 +233,22 @@ ali_status ali_misfit_gradient_f64(ali_handle* h, const ali_grid* grid, const al
                                    const ali_node* srcs, int32_t n_src, const ali_node* recv, int32_t n_recv,
                                    const double* d_obs, const ali_options* opt, double* d_T, double* d_Trec,
                                    double* d_loss, double* d_dLdtheta, ali_adjoint_stats* stats);
+
+/* Forward + adjoint of the travel-time misfit for many media in one call (the batched
+   tomography step): for each medium m, L_m = 1/2 sum over its sources s and receivers r of
+   (T_s(r) - obs)^2.
+     recv            receivers of all media, medium m at rec_offset (n_rec of them)
+     d_obs           observed times: for each field (medium order, then source order) its
+                     medium's n_rec values
+     d_Trec          modelled times, same layout (device, nullable)
+     d_loss          [n_media] float64 misfits (device, nullable)
+     d_dLdtheta      dL_m/dtheta per node, laid out as d_orient (device)
+   Arithmetic, errors and synchronisation as ali_misfit_gradient. */
+ali_status ali_misfit_gradient_batch(ali_handle* h, const ali_medium* media, int32_t n_media,
+                                     const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
+                                     const float* d_orient, const ali_node* srcs, const ali_node* recv,
+                                     const float* d_obs, const ali_options* opt, float* d_Trec,
+                                     double* d_loss, float* d_dLdtheta, ali_adjoint_stats* stats);
 
 /* Orientation from an ncz x ncx grid of control values spanning the grid corner to corner
    (node k sits at control coordinate k (nc-1)/(n-1); linear in each direction), and its

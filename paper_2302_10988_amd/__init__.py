@@ -10,7 +10,7 @@ import ctypes
 
 from . import _lib
 
-__all__ = ["AliError", "Solver", "default_options"]
+__all__ = ["AliError", "Batch", "Solver", "default_options"]
 
 _MAT_FIELDS = ("c11", "c13", "c33", "c55", "c44", "c66", "rho")
 
@@ -67,6 +67,62 @@ def _dev_ptr(t, dtype, shape=None, name="tensor"):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
     return ctypes.c_void_p(t.data_ptr())
+
+
+class Batch:
+    """Media packed for the batch entry points: one material table, per-node arrays of all
+    media concatenated on the device, sources and receivers concatenated on the host.
+
+    media: sequence of objects with attributes nx, nz, h, mats, mat_id [nz, nx] (uint8
+    array), orient [nz, nx] (radians), sources [(i, j)], receivers [(i, j)]."""
+
+    def __init__(self, media, device="cuda"):
+        import numpy as np
+        import torch
+        descs, mats, srcs, recs, ids, oris = [], [], [], [], [], []
+        node = 0
+        for m in media:
+            d = _lib.Medium()
+            d.grid = _lib.Grid(int(m.nx), int(m.nz), float(m.h))
+            d.mat_offset, d.n_mats = len(mats), len(m.mats)
+            d.node_offset = node
+            d.src_offset, d.n_src = len(srcs), len(m.sources)
+            d.rec_offset, d.n_rec = len(recs), len(getattr(m, "receivers", []) or [])
+            mats.extend(m.mats)
+            srcs.extend(m.sources)
+            recs.extend(getattr(m, "receivers", []) or [])
+            ids.append(np.ascontiguousarray(m.mat_id, dtype=np.uint8).ravel())
+            oris.append(np.ascontiguousarray(m.orient, dtype=np.float32).ravel())
+            node += int(m.nx) * int(m.nz)
+            descs.append(d)
+        self.n_media = len(descs)
+        self.media = (_lib.Medium * self.n_media)(*descs)
+        self.mats, self.n_mats = _materials(mats)
+        self.srcs, self.n_src = _nodes(srcs)
+        self.recs, self.n_rec = _nodes(recs) if recs else (None, 0)
+        self.mat_id = torch.from_numpy(np.concatenate(ids)).to(device)
+        self.orient = torch.from_numpy(np.concatenate(oris)).to(device)
+        self.shapes = [(int(d.grid.nz), int(d.grid.nx)) for d in descs]
+        self.n_fields = sum(int(d.n_src) for d in descs)
+        self.field_nodes = sum(int(d.n_src) * int(d.grid.nx) * int(d.grid.nz) for d in descs)
+        self.n_obs = sum(int(d.n_src) * int(d.n_rec) for d in descs)
+
+    def fields(self, T):
+        """Split a batch output [field_nodes] into per-medium [n_src, nz, nx] views."""
+        out, off = [], 0
+        for d, (nz, nx) in zip(self.media, self.shapes):
+            n = int(d.n_src) * nz * nx
+            out.append(T[off:off + n].view(int(d.n_src), nz, nx))
+            off += n
+        return out
+
+    def per_node(self, a):
+        """Split a per-node array (orientation layout) into per-medium [nz, nx] views."""
+        out = []
+        for d, (nz, nx) in zip(self.media, self.shapes):
+            off = int(d.node_offset)
+            out.append(a[off:off + nz * nx].view(nz, nx))
+        return out
 
 
 class Solver:
@@ -249,3 +305,45 @@ class Solver:
         self._check(fn(self._h, int(nz), int(nx), int(ncz), int(ncx), _dev_ptr(g, g.dtype, name="dLdtheta"),
                        _dev_ptr(out, g.dtype)))
         return out
+
+
+    def solve_batch(self, batch, out=None, arith="mixed", **opts):
+        """Fields of every source of every medium of `batch` in one call.  Returns (T
+        [field_nodes] float32 in medium order, stats dict)."""
+        import torch
+        opt = default_options(arith=_lib.ARITH[arith], **opts)
+        if out is None:
+            out = torch.empty(batch.field_nodes, dtype=torch.float32, device=batch.mat_id.device)
+        stats = _lib.SolveStats()
+        self._sync_stream()
+        st = self._lib.ali_solve_batch(self._h, batch.media, batch.n_media, batch.mats, batch.n_mats,
+                                       _dev_ptr(batch.mat_id, torch.uint8, name="mat_id"),
+                                       _dev_ptr(batch.orient, torch.float32, name="orient"), batch.srcs,
+                                       ctypes.byref(opt), _dev_ptr(out, torch.float32, (batch.field_nodes,), "out"),
+                                       ctypes.byref(stats))
+        self._check(st)
+        return out, stats.as_dict()
+
+    def misfit_gradient_batch(self, batch, obs, orient=None, arith="mixed", **opts):
+        """Forward + adjoint of the receiver misfit for every medium of `batch` in one call.
+        obs: [n_obs] float32 device tensor (per field, its medium's receivers); orient: optional
+        replacement of the batch's orientation (same layout).  Returns (loss [n_media] float64,
+        Trec [n_obs], dLdtheta [nodes] float32, stats)."""
+        import torch
+        opt = default_options(arith=_lib.ARITH[arith], **opts)
+        dev = batch.mat_id.device
+        ori = batch.orient if orient is None else orient
+        dth = torch.empty_like(batch.orient)
+        trec = torch.empty(batch.n_obs, dtype=torch.float32, device=dev)
+        loss = torch.empty(batch.n_media, dtype=torch.float64, device=dev)
+        stats = _lib.AdjointStats()
+        self._sync_stream()
+        st = self._lib.ali_misfit_gradient_batch(self._h, batch.media, batch.n_media, batch.mats, batch.n_mats,
+                                                 _dev_ptr(batch.mat_id, torch.uint8, name="mat_id"),
+                                                 _dev_ptr(ori, torch.float32, tuple(batch.orient.shape), "orient"),
+                                                 batch.srcs, batch.recs, _dev_ptr(obs, torch.float32, (batch.n_obs,), "obs"),
+                                                 ctypes.byref(opt), _dev_ptr(trec, torch.float32),
+                                                 _dev_ptr(loss, torch.float64), _dev_ptr(dth, torch.float32),
+                                                 ctypes.byref(stats))
+        self._check(st)
+        return loss, trec, dth, stats.as_dict()

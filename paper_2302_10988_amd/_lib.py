@@ -26,6 +26,12 @@ class Node(ctypes.Structure):
     _fields_ = [("i", ctypes.c_int32), ("j", ctypes.c_int32)]
 
 
+class Medium(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("mat_offset", ctypes.c_int32), ("n_mats", ctypes.c_int32),
+                ("node_offset", ctypes.c_int64), ("src_offset", ctypes.c_int32), ("n_src", ctypes.c_int32),
+                ("rec_offset", ctypes.c_int32), ("n_rec", ctypes.c_int32)]
+
+
 class Options(ctypes.Structure):
     _fields_ = [("src_box_radius", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("inner_sweeps", ctypes.c_int32), ("band_cells", ctypes.c_int32),
@@ -92,6 +98,11 @@ SIGNATURES = {
                                                ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
                                                ctypes.POINTER(Options), _P, _P, _P, _P,
                                                ctypes.POINTER(AdjointStats)]),
+    "ali_solve_batch": (ctypes.c_int, [_P, ctypes.POINTER(Medium), _I32, ctypes.POINTER(Material), _I32, _P, _P,
+                                       ctypes.POINTER(Node), ctypes.POINTER(Options), _P, ctypes.POINTER(SolveStats)]),
+    "ali_misfit_gradient_batch": (ctypes.c_int, [_P, ctypes.POINTER(Medium), _I32, ctypes.POINTER(Material), _I32,
+                                                 _P, _P, ctypes.POINTER(Node), ctypes.POINTER(Node), _P,
+                                                 ctypes.POINTER(Options), _P, _P, _P, ctypes.POINTER(AdjointStats)]),
     "ali_bilinear": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),
     "ali_bilinear_transpose": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),
     "ali_bilinear_f64": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),

@@ -103,20 +103,25 @@ __device__ void stencil_partials(const NodeD& n, const StGeo& g, double ta, doub
 // ---------------------------------------------------------------------------------------
 template <typename mreal, typename oreal>
 __global__ void __launch_bounds__(NTHREADS)
-k_adj_prep(int nx, int nz, int ntx, int ntz, double h, const MatDev<mreal>* __restrict__ mats,
-           const uint8_t* __restrict__ mat_id, const oreal* __restrict__ orient,
-           const mreal* __restrict__ geo, const double* __restrict__ fbt,
-           const int2* __restrict__ src, int R, const double* __restrict__ T,
-           uint16_t* __restrict__ code, double* __restrict__ wA, double* __restrict__ wB,
-           double* __restrict__ wC, double* __restrict__ wT,
+k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal>* __restrict__ mats_all,
+           const uint8_t* __restrict__ mat_id_all, const oreal* __restrict__ orient_all,
+           const mreal* __restrict__ geo_all, const double* __restrict__ fbt_all, int R,
+           const double* __restrict__ T, uint16_t* __restrict__ code, double* __restrict__ wA,
+           double* __restrict__ wB, double* __restrict__ wC, double* __restrict__ wT,
            unsigned long long* __restrict__ mismatches) {
     __shared__ double lt[LH * LSTRIDE];
-    const int ntiles = ntx * ntz;
-    const int f = blockIdx.x / ntiles;
-    const int tile = blockIdx.x % ntiles;
-    const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TZ;
-    const int64_t N = (int64_t)nx * nz;
-    const double* __restrict__ Tf = T + (int64_t)f * N;
+    const uint32_t unit = blockIdx.x;
+    const FieldDev fd = fields[field_of_unit(fields, n_fields, unit)];
+    const int nx = fd.nx, nz = fd.nz;
+    const double h = fd.h;
+    const int tile = (int)(unit - fd.unit_off);
+    const int i0 = (tile % fd.ntx) * TX, j0 = (tile / fd.ntx) * TZ;
+    const double* __restrict__ Tf = T + fd.t_off;
+    const MatDev<mreal>* __restrict__ mats = mats_all + fd.mat_off;
+    const uint8_t* __restrict__ mat_id = mat_id_all + fd.node_off;
+    const oreal* __restrict__ orient = orient_all + fd.node_off;
+    const mreal* __restrict__ geo = geo_all + 2 * fd.node_off;
+    const double* __restrict__ fbt = fbt_all + 4 * fd.node_off;
     const double inf = dinf<double>();
     const int tid = threadIdx.x;
     for (int q = tid; q < LW * LH; q += NTHREADS) {
@@ -131,8 +136,8 @@ k_adj_prep(int nx, int nz, int ntx, int ntz, double h, const MatDev<mreal>* __re
     const int gi = i0 + lx, gj = j0 + lz;
     if (gi >= nx || gj >= nz) return;
     const int64_t p = (int64_t)gj * nx + gi;
-    const int64_t q = (int64_t)f * N + p;
-    const int2 s = src[f];
+    const int64_t q = fd.t_off + p;
+    const int2 s = fd.src;
     const int me = (lz + HALO) * LSTRIDE + (lx + HALO);
     const double tD = lt[me];
     uint16_t cd = CODE_NONE;
@@ -216,8 +221,8 @@ __device__ __forceinline__ double pull_lambda(double gsum, int me, const double*
 // supports: inside the tile for the next sweep, in a neighbouring tile through that
 // tile's node mask for the next pass.
 __global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
-k_adj_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
-            const uint32_t* __restrict__ lbits, const uint16_t* __restrict__ code,
+k_adj_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ list,
+            const uint32_t* __restrict__ lbits, const uint32_t* __restrict__ lfld, const uint16_t* __restrict__ code,
             const double* __restrict__ wA, const double* __restrict__ wB, const double* __restrict__ wC,
             const double* __restrict__ G, const double* __restrict__ T, const double* __restrict__ theta,
             double* __restrict__ lam, uint8_t* __restrict__ pend, double* __restrict__ maxdef,
@@ -241,17 +246,17 @@ k_adj_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
         atomicAdd(&counters[2], 1ull);
         atomicAdd(&counters[3], (unsigned long long)n_units);
     }
-    const int ntiles = ntx * ntz;
-    const int64_t N = (int64_t)nx * nz;
     const int lane = threadIdx.x;
     for (uint32_t item = blockIdx.x; item < n_units; item += gridDim.x) {
     const uint32_t unit = list[item];
     const uint32_t bits = lbits[item];
-    const int f = (int)(unit / (uint32_t)ntiles);
-    const int tile = (int)(unit % (uint32_t)ntiles);
+    const int f = (int)lfld[item];
+    const FieldDev fd = fields[f];
+    const int nx = fd.nx, nz = fd.nz, ntx = fd.ntx;
+    const int tile = (int)(unit - fd.unit_off);
     const int tx = tile % ntx, tz = tile / ntx;
     const int i0 = tx * TX, j0 = tz * TZ;
-    const int64_t fo = (int64_t)f * N;
+    const int64_t fo = fd.t_off;
 
     for (int q = lane; q < LW * LH; q += RW) {
         const int li = q % LW, lj = q / LW;
@@ -390,7 +395,7 @@ k_adj_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
             const uint32_t w = omask[q / NODE_WORDS][q % NODE_WORDS];
             if (!w) continue;
             const int o = q / NODE_WORDS;
-            const int64_t u2 = (int64_t)f * ntiles + (int64_t)(tz + o / 3 - 1) * ntx + (tx + o % 3 - 1);
+            const int64_t u2 = (int64_t)fd.unit_off + (int64_t)(tz + o / 3 - 1) * ntx + (tx + o % 3 - 1);
             atomicOr(&marks_out[u2 * NODE_WORDS + q % NODE_WORDS], w);
             atomicOr(&flags[u2], TF_MARK);
         }
@@ -407,10 +412,13 @@ k_adj_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
 // step (not before the first pass); if no tile is flagged or holds a pending node at or
 // above the threshold, lower it to the largest pending time; then list the active tiles.
 __global__ void __launch_bounds__(256)
-k_adj_sched(int ntiles, int advance, double step, uint32_t* __restrict__ flags,
-            const double* __restrict__ maxdef, double* __restrict__ theta, uint32_t* __restrict__ list,
-            uint32_t* __restrict__ lbits, uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next) {
+k_adj_sched(const FieldDev* __restrict__ fields, int advance, const double* __restrict__ step,
+            uint32_t* __restrict__ flags, const double* __restrict__ maxdef, double* __restrict__ theta,
+            uint32_t* __restrict__ list, uint32_t* __restrict__ lbits, uint32_t* __restrict__ lfld,
+            uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next) {
     const int f = blockIdx.x;
+    const uint32_t uoff = fields[f].unit_off;
+    const int ntiles = fields[f].ntx * fields[f].ntz;
     const int tid = threadIdx.x;
     const double ninf = -dinf<double>();
     __shared__ double red_m[256];
@@ -418,10 +426,10 @@ k_adj_sched(int ntiles, int advance, double step, uint32_t* __restrict__ flags,
     __shared__ double th_s;
     __shared__ uint32_t base_s;
     if (f == 0 && tid == 0) *cnt_next = 0u;
-    uint32_t* fl = flags + (int64_t)f * ntiles;
-    const double* md = maxdef + (int64_t)f * ntiles;
+    uint32_t* fl = flags + uoff;
+    const double* md = maxdef + uoff;
     double th = theta[f];
-    if (advance) th -= step;
+    if (advance) th -= step[f];
     unsigned act = 0;
     double m = ninf;
     for (int t = tid; t < ntiles; t += 256) {
@@ -468,66 +476,71 @@ k_adj_sched(int ntiles, int advance, double step, uint32_t* __restrict__ flags,
         const double v = md[t];
         if (b != 0u || (v > ninf && v >= th)) {
             fl[t] = 0u;
-            list[pos] = (uint32_t)((int64_t)f * ntiles + t);
+            list[pos] = uoff + (uint32_t)t;
             lbits[pos] = b;
+            lfld[pos] = (uint32_t)f;
             ++pos;
         }
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// right-hand side: g = dL/dT at the receivers, one thread per field (receivers in order)
+// right-hand side: g = dL/dT at the receivers, one work-item per field (receivers in order)
 // ---------------------------------------------------------------------------------------
 // mode 0: g given per (field, receiver).  mode 1: misfit L = 1/2 sum (T - obs)^2, so
-// g = T - obs; also writes T at the receivers and the per-field misfit.
+// g = T - obs; also writes T at the receivers and the per-field misfit.  The field's
+// threshold starts at its latest receiver time (nodes later than every receiver carry no
+// sensitivity), or -inf without a band.
 template <typename greal, typename outreal>
-__global__ void k_adj_rhs(int mode, int nf, int nrec, int nx, int64_t N, int ntx,
-                          const int2* __restrict__ rec, const greal* __restrict__ in,
-                          const double* __restrict__ T, double* __restrict__ G,
-                          outreal* __restrict__ trec, double* __restrict__ lossf,
-                          uint32_t* __restrict__ flags, int ntiles, double* __restrict__ theta,
-                          int banded) {
+__global__ void k_adj_rhs(int mode, int n_fields, const FieldDev* __restrict__ fields, const int2* __restrict__ rec,
+                          const greal* __restrict__ in, const double* __restrict__ T, double* __restrict__ G,
+                          outreal* __restrict__ trec, double* __restrict__ lossf, uint32_t* __restrict__ flags,
+                          double* __restrict__ theta, int banded) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
+    if (f >= n_fields) return;
+    const FieldDev fd = fields[f];
     double L = 0.0;
     double tmax = -dinf<double>();
-    for (int r = 0; r < nrec; ++r) {
-        const int2 x = rec[r];
-        const int64_t p = (int64_t)f * N + (int64_t)x.y * nx + x.x;
-        double g = (double)in[(int64_t)f * nrec + r];
+    for (int r = 0; r < fd.n_rec; ++r) {
+        const int2 x = rec[fd.rec_off + r];
+        const int64_t p = fd.t_off + (int64_t)x.y * fd.nx + x.x;
+        double g = (double)in[fd.obs_off + r];
         if (mode == 1) {
             const double t = T[p];
             g = t - g;
             L += 0.5 * g * g;
-            if (trec) trec[(int64_t)f * nrec + r] = (outreal)t;
+            if (trec) trec[fd.obs_off + r] = (outreal)t;
         }
         G[p] += g;
         tmax = T[p] > tmax ? T[p] : tmax;
-        flags[(int64_t)f * ntiles + (x.y / TZ) * ntx + (x.x / TX)] |= TF_SELF;
+        flags[fd.unit_off + (x.y / TZ) * fd.ntx + (x.x / TX)] |= TF_SELF;
     }
     if (lossf) lossf[f] = L;
-    // nodes later than every receiver carry no sensitivity: the band starts there
     theta[f] = banded ? tmax : -dinf<double>();
 }
 
-__global__ void k_adj_loss(const double* __restrict__ lossf, int nf, double* __restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int f = 0; f < nf; ++f) s += lossf[f];
-        *out = s;
-    }
+// misfit of each medium: its fields' misfits in field order
+__global__ void k_adj_loss(const double* __restrict__ lossf, const int* __restrict__ first, int n_media,
+                           double* __restrict__ out) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n_media) return;
+    double s = 0.0;
+    for (int f = first[m]; f < first[m + 1]; ++f) s += lossf[f];
+    out[m] = s;
 }
 
 // ---------------------------------------------------------------------------------------
 // step 4: gradient
 // ---------------------------------------------------------------------------------------
-__global__ void k_adj_grad(int64_t N, int nf, const uint16_t* __restrict__ code, const double* __restrict__ wT,
+// nodes of one medium, summed over its fields f0 .. f1 - 1 in field order
+__global__ void k_adj_grad(int64_t N, int f0, int f1, const FieldDev* __restrict__ fields,
+                           const uint16_t* __restrict__ code, const double* __restrict__ wT,
                            const double* __restrict__ lam, double* __restrict__ dth) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     double s = 0.0;
-    for (int f = 0; f < nf; ++f) {
-        const int64_t q = (int64_t)f * N + p;
+    for (int f = f0; f < f1; ++f) {
+        const int64_t q = fields[f].t_off + p;
         const int kind = code[q] >> 12;
         if (kind == K_STENCIL || kind == K_FALLBACK) s += lam[q] * wT[q];
     }
@@ -535,17 +548,17 @@ __global__ void k_adj_grad(int64_t N, int nf, const uint16_t* __restrict__ code,
 }
 
 // source-box terms of field f, reduced in a fixed order
-__global__ void k_adj_box(int nx, int nz, int64_t N, int R, const int2* __restrict__ src,
-                          const double* __restrict__ wT, const double* __restrict__ lam,
-                          double* __restrict__ boxsum) {
+__global__ void k_adj_box(const FieldDev* __restrict__ fields, int R, const double* __restrict__ wT,
+                          const double* __restrict__ lam, double* __restrict__ boxsum) {
     const int f = blockIdx.x;
-    const int2 s = src[f];
+    const FieldDev fd = fields[f];
+    const int2 s = fd.src;
     const int w = 2 * R + 1;
     double acc = 0.0;
     for (int k = threadIdx.x; k < w * w; k += blockDim.x) {
         const int i = s.x - R + k % w, j = s.y - R + k / w;
-        if (i < 0 || j < 0 || i >= nx || j >= nz) continue;
-        const int64_t q = (int64_t)f * N + (int64_t)j * nx + i;
+        if (i < 0 || j < 0 || i >= fd.nx || j >= fd.nz) continue;
+        const int64_t q = fd.t_off + (int64_t)j * fd.nx + i;
         acc += lam[q] * wT[q];
     }
     __shared__ double red[256];
@@ -559,37 +572,43 @@ __global__ void k_adj_box(int nx, int nz, int64_t N, int R, const int2* __restri
 }
 
 // one work-item adds the box terms at the source nodes in field order
-__global__ void k_adj_box_add(int nf, int nx, const int2* __restrict__ src, const double* __restrict__ boxsum,
+__global__ void k_adj_box_add(int n_fields, const FieldDev* __restrict__ fields, const double* __restrict__ boxsum,
                               double* __restrict__ dth) {
     if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (int f = 0; f < nf; ++f) dth[(int64_t)src[f].y * nx + src[f].x] += boxsum[f];
+        for (int f = 0; f < n_fields; ++f) {
+            const FieldDev& fd = fields[f];
+            dth[fd.node_off + (int64_t)fd.src.y * fd.nx + fd.src.x] += boxsum[f];
+        }
 }
 
 // ---------------------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------------------
 template <typename mreal, typename oreal, typename greal, typename outreal>
-static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats,
+static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n_media, const ali_material* mats,
                                int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient,
-                               const ali_node* srcs, int32_t n_src, const ali_node* recv, int32_t n_recv,
-                               int mode, const greal* d_in, const ali_options* opt_in, outreal* d_T,
-                               outreal* d_trec, double* d_loss, outreal* d_dth, ali_adjoint_stats* stats) {
+                               const ali_node* srcs, const ali_node* recv, int mode, const greal* d_in,
+                               const ali_options* opt_in, outreal* d_T, outreal* d_trec, double* d_loss,
+                               outreal* d_dth, ali_adjoint_stats* stats) {
     ali_options opt;
     ali_default_options(&opt);
     if (opt_in) opt = *opt_in;
-    ali_status st = validate_medium(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src);
+    if (!recv) return H->fail(ALI_EINVAL, "receivers are NULL");
+    ali_status st = validate_batch(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, recv);
     if (st != ALI_OK) return st;
-    if (!recv || n_recv < 1) return H->fail(ALI_EINVAL, "need at least one receiver");
-    for (int r = 0; r < n_recv; ++r)
-        if (recv[r].i < 0 || recv[r].j < 0 || recv[r].i >= grid->nx || recv[r].j >= grid->nz)
-            return H->fail(ALI_EINVAL, "receiver " + std::to_string(r) + " outside the grid");
     if (!d_in) return H->fail(ALI_EINVAL, mode == 1 ? "d_obs is NULL" : "d_dLdT is NULL");
     if (!d_dth) return H->fail(ALI_EINVAL, "d_dLdtheta is NULL");
-    const int nx = grid->nx, nz = grid->nz;
-    const int64_t N = (int64_t)nx * nz;
-    const int64_t NF = N * n_src;
+    int64_t n_fields64 = 0, NF = 0;
+    batch_sizes(media, n_media, &n_fields64, &NF);
+    const int n_fields = (int)n_fields64;
+    int64_t med_nodes = 0;
+    int n_recv_total = 0;
+    for (int m = 0; m < n_media; ++m) {
+        med_nodes = std::max(med_nodes, media[m].node_offset + (int64_t)media[m].grid.nx * media[m].grid.nz);
+        n_recv_total = std::max(n_recv_total, media[m].rec_offset + media[m].n_rec);
+    }
 
-    // forward field in float64: the caller's buffer when it is float64, else scratch
+    // forward fields in float64: the caller's buffer when it is float64, else scratch
     constexpr bool out64 = std::is_same<outreal, double>::value;
     void* d_work = nullptr;
     if (!(out64 && d_T) && !H->scratch("adjT", sizeof(double) * NF, &d_work))
@@ -598,65 +617,74 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
 
     ali_solve_stats fst{};
     ForwardState<double, mreal> fs;
-    st = solve_core<double, mreal, oreal>(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
-                                                     opt, T, &fst, &fs);
+    st = solve_fields<double, mreal, oreal>(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, recv, opt, T,
+                                            &fst, &fs);
     if (st != ALI_OK) return st;
     hipStream_t S = H->stream;
     HIPCK(H, hipEventRecord(H->ev4, S));
-    const int ntx = fs.ntx, ntz = fs.ntz, ntiles = ntx * ntz;
-    const int64_t nunits = (int64_t)ntiles * n_src;
+    const int64_t nunits = fs.n_units;
 
-    void *d_code, *d_wA, *d_wB, *d_wC, *d_wT, *d_lam, *d_G, *d_dacc, *d_box, *d_lossf, *d_rec;
-    void *d_flags, *d_list, *d_lbits, *d_count, *d_cnt, *d_pend, *d_maxdef, *d_theta, *d_idle, *d_marks;
+    void *d_code, *d_wA, *d_wB, *d_wC, *d_wT, *d_lam, *d_G, *d_dacc, *d_box, *d_lossf, *d_rec, *d_first;
+    void *d_flags, *d_list, *d_lbits, *d_lfld, *d_count, *d_cnt, *d_pend, *d_maxdef, *d_theta, *d_step, *d_idle, *d_marks;
     if (!H->scratch("a_code", sizeof(uint16_t) * NF, &d_code) ||
         !H->scratch("a_wA", sizeof(double) * NF, &d_wA) || !H->scratch("a_wB", sizeof(double) * NF, &d_wB) ||
         !H->scratch("a_wC", sizeof(double) * NF, &d_wC) || !H->scratch("a_wT", sizeof(double) * NF, &d_wT) ||
         !H->scratch("a_lam", sizeof(double) * NF, &d_lam) || !H->scratch("a_G", sizeof(double) * NF, &d_G) ||
         !H->scratch("a_pend", sizeof(uint8_t) * NF, &d_pend) ||
-        !H->scratch("a_dth", sizeof(double) * N, &d_dacc) || !H->scratch("a_box", sizeof(double) * n_src, &d_box) ||
-        !H->scratch("a_lossf", sizeof(double) * n_src, &d_lossf) ||
-        !H->scratch("a_theta", sizeof(double) * n_src, &d_theta) ||
-        !H->scratch("a_rec", sizeof(int2) * n_recv, &d_rec) ||
+        !H->scratch("a_dth", sizeof(double) * med_nodes, &d_dacc) ||
+        !H->scratch("a_box", sizeof(double) * n_fields, &d_box) ||
+        !H->scratch("a_lossf", sizeof(double) * n_fields, &d_lossf) ||
+        !H->scratch("a_theta", sizeof(double) * n_fields, &d_theta) ||
+        !H->scratch("a_step", sizeof(double) * n_fields, &d_step) ||
+        !H->scratch("a_first", sizeof(int) * (n_media + 1), &d_first) ||
+        !H->scratch("a_rec", sizeof(int2) * n_recv_total, &d_rec) ||
         !H->scratch("a_flags", sizeof(uint32_t) * nunits, &d_flags) ||
         !H->scratch("a_maxdef", sizeof(double) * nunits, &d_maxdef) ||
         !H->scratch("a_list", sizeof(uint32_t) * nunits, &d_list) ||
         !H->scratch("a_lbits", sizeof(uint32_t) * nunits, &d_lbits) ||
+        !H->scratch("a_lfld", sizeof(uint32_t) * nunits, &d_lfld) ||
         !H->scratch("a_count", 2 * sizeof(uint32_t), &d_count) ||
         !H->scratch("a_idle", sizeof(uint32_t), &d_idle) ||
         !H->scratch("a_marks", sizeof(uint32_t) * 2 * NODE_WORDS * nunits, &d_marks) ||
         !H->scratch("a_cnt", (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), &d_cnt))
         return H->fail(ALI_ENOMEM, "device scratch allocation failed");
-    std::vector<int2> hr(n_recv);
-    for (int r = 0; r < n_recv; ++r) hr[r] = make_int2(recv[r].i, recv[r].j);
-    HIPCK(H, hipMemcpyAsync(d_rec, hr.data(), sizeof(int2) * n_recv, hipMemcpyHostToDevice, S));
+    // descending time band: band_cells node spacings at each medium's fastest phase speed
+    const bool banded = opt.band_cells > 0;
+    std::vector<double> hstep(n_fields);
+    for (int f = 0; f < n_fields; ++f) {
+        const int m = fs.hfields[f].medium;
+        hstep[f] = banded ? opt.band_cells * media[m].grid.h / fs.vmax[m] : 0.0;
+    }
+    std::vector<int2> hr(n_recv_total);
+    for (int r = 0; r < n_recv_total; ++r) hr[r] = make_int2(recv[r].i, recv[r].j);
+    HIPCK(H, hipMemcpyAsync(d_rec, hr.data(), sizeof(int2) * n_recv_total, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemcpyAsync(d_step, hstep.data(), sizeof(double) * n_fields, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemcpyAsync(d_first, fs.medium_first_field.data(), sizeof(int) * (n_media + 1), hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemsetAsync(d_flags, 0, sizeof(uint32_t) * nunits, S));
     HIPCK(H, hipMemsetAsync(d_marks, 0, sizeof(uint32_t) * 2 * NODE_WORDS * nunits, S));
     HIPCK(H, hipMemsetAsync(d_count, 0, 2 * sizeof(uint32_t), S));
     HIPCK(H, hipMemsetAsync(d_idle, 0, sizeof(uint32_t), S));
     HIPCK(H, hipMemsetAsync(d_cnt, 0, (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), S));
-    // descending time band: band_cells node spacings at the fastest phase speed
-    const bool banded = opt.band_cells > 0;
-    const double band = banded ? opt.band_cells * grid->h / max_phase_speed(mats, n_mats) : 0.0;
 
     const int B = 256;
     const unsigned gNF = (unsigned)((NF + B - 1) / B);
     hipLaunchKernelGGL((k_adj_prep<mreal, oreal>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
-                       nx, nz, ntx, ntz, grid->h, fs.mats, d_mat_id, d_orient, fs.geo, fs.fbt, fs.src,
-                       opt.src_box_radius, (const double*)T, (uint16_t*)d_code, (double*)d_wA, (double*)d_wB,
-                       (double*)d_wC, (double*)d_wT, (unsigned long long*)d_cnt + 1);
+                       fs.fields, n_fields, fs.mats, d_mat_id, d_orient, fs.geo, fs.fbt, opt.src_box_radius,
+                       (const double*)T, (uint16_t*)d_code, (double*)d_wA, (double*)d_wB, (double*)d_wC,
+                       (double*)d_wT, (unsigned long long*)d_cnt + 1);
     HIPCK(H, hipGetLastError());
     hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_G, NF, 0.0);
     hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_lam, NF, 0.0);
     hipLaunchKernelGGL((k_fill<uint8_t>), dim3(gNF), dim3(B), 0, S, (uint8_t*)d_pend, NF, (uint8_t)0);
     hipLaunchKernelGGL((k_fill<double>), dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S, (double*)d_maxdef,
                        nunits, -dinf_host<double>());
-    hipLaunchKernelGGL((k_adj_rhs<greal, outreal>), dim3((unsigned)((n_src + 63) / 64)), dim3(64), 0, S,
-                       mode, n_src, n_recv, nx, N, ntx, (const int2*)d_rec, d_in, (const double*)T,
-                       (double*)d_G, d_trec, (double*)d_lossf, (uint32_t*)d_flags, ntiles, (double*)d_theta,
-                       banded ? 1 : 0);
+    hipLaunchKernelGGL((k_adj_rhs<greal, outreal>), dim3((unsigned)((n_fields + 63) / 64)), dim3(64), 0, S,
+                       mode, n_fields, fs.fields, (const int2*)d_rec, d_in, (const double*)T, (double*)d_G, d_trec,
+                       (double*)d_lossf, (uint32_t*)d_flags, (double*)d_theta, banded ? 1 : 0);
     HIPCK(H, hipGetLastError());
     if (mode == 1 && d_loss)
-        hipLaunchKernelGGL(k_adj_loss, dim3(1), dim3(64), 0, S, (const double*)d_lossf, n_src, d_loss);
+        hipLaunchKernelGGL(k_adj_loss, dim3((unsigned)((n_media + 63) / 64)), dim3(64), 0, S, (const double*)d_lossf,
+                           (const int*)d_first, n_media, d_loss);
 
     // passes queued in batches; the idle flag ends the loop (see the forward driver)
     int iters = 0;
@@ -668,15 +696,15 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
         const int batch = opt.max_sweeps - iters < PASS_BATCH ? opt.max_sweeps - iters : PASS_BATCH;
         for (int bb = 0; bb < batch; ++bb) {
             const int p = iters + bb;
-            hipLaunchKernelGGL(k_adj_sched, dim3((unsigned)n_src), dim3(256), 0, S, ntiles, p > 0 ? 1 : 0, band,
-                               (uint32_t*)d_flags, (const double*)d_maxdef, (double*)d_theta, (uint32_t*)d_list,
-                               (uint32_t*)d_lbits, cnt + (p & 1), cnt + ((p + 1) & 1));
+            hipLaunchKernelGGL(k_adj_sched, dim3((unsigned)n_fields), dim3(256), 0, S, fs.fields, p > 0 ? 1 : 0,
+                               (const double*)d_step, (uint32_t*)d_flags, (const double*)d_maxdef, (double*)d_theta,
+                               (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_lfld, cnt + (p & 1), cnt + ((p + 1) & 1));
             uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
             uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
             HIPCK(H, hipEventRecord(H->pev[2 * bb], S));
-            hipLaunchKernelGGL(k_adj_relax, dim3((unsigned)grid_relax), dim3(RW), 0, S, nx, nz, ntx, ntz,
-                               (const uint32_t*)d_list, (const uint32_t*)d_lbits, (const uint16_t*)d_code,
-                               (const double*)d_wA, (const double*)d_wB, (const double*)d_wC,
+            hipLaunchKernelGGL(k_adj_relax, dim3((unsigned)grid_relax), dim3(RW), 0, S, fs.fields,
+                               (const uint32_t*)d_list, (const uint32_t*)d_lbits, (const uint32_t*)d_lfld,
+                               (const uint16_t*)d_code, (const double*)d_wA, (const double*)d_wB, (const double*)d_wC,
                                (const double*)d_G, (const double*)T, (const double*)d_theta, (double*)d_lam,
                                (uint8_t*)d_pend, (double*)d_maxdef, (uint32_t*)d_flags, mk_in, mk_out,
                                (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle, opt.inner_sweeps,
@@ -695,14 +723,22 @@ static ali_status adjoint_impl(ali_handle* H, const ali_grid* grid, const ali_ma
         if (*H->host_count) { converged = true; break; }
     }
 
-    hipLaunchKernelGGL(k_adj_grad, dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S, N, n_src,
-                       (const uint16_t*)d_code, (const double*)d_wT, (const double*)d_lam, (double*)d_dacc);
-    hipLaunchKernelGGL(k_adj_box, dim3((unsigned)n_src), dim3(256), 0, S, nx, nz, N, opt.src_box_radius,
-                       fs.src, (const double*)d_wT, (const double*)d_lam, (double*)d_box);
-    hipLaunchKernelGGL(k_adj_box_add, dim3(1), dim3(64), 0, S, n_src, nx, fs.src, (const double*)d_box,
+    for (int m = 0; m < n_media; ++m) {
+        const int64_t N = (int64_t)media[m].grid.nx * media[m].grid.nz;
+        hipLaunchKernelGGL(k_adj_grad, dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S, N,
+                           fs.medium_first_field[m], fs.medium_first_field[m + 1], fs.fields,
+                           (const uint16_t*)d_code, (const double*)d_wT, (const double*)d_lam,
+                           (double*)d_dacc + media[m].node_offset);
+    }
+    hipLaunchKernelGGL(k_adj_box, dim3((unsigned)n_fields), dim3(256), 0, S, fs.fields, opt.src_box_radius,
+                       (const double*)d_wT, (const double*)d_lam, (double*)d_box);
+    hipLaunchKernelGGL(k_adj_box_add, dim3(1), dim3(64), 0, S, n_fields, fs.fields, (const double*)d_box,
                        (double*)d_dacc);
-    hipLaunchKernelGGL((k_convert<outreal, double>), dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S,
-                       d_dth, (const double*)d_dacc, N);
+    for (int m = 0; m < n_media; ++m) {
+        const int64_t N = (int64_t)media[m].grid.nx * media[m].grid.nz;
+        hipLaunchKernelGGL((k_convert<outreal, double>), dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S,
+                           d_dth + media[m].node_offset, (const double*)d_dacc + media[m].node_offset, N);
+    }
     HIPCK(H, hipGetLastError());
     if (d_T && !out64)
         hipLaunchKernelGGL((k_convert<outreal, double>), dim3(gNF), dim3(B), 0, S, d_T, (const double*)T, NF);
@@ -809,20 +845,32 @@ static ali_status bilinear_impl(ali_handle* H, int32_t nz, int32_t nx, int32_t n
 
 using namespace ali;
 
+template <typename oreal, typename greal, typename outreal>
+static ali_status adjoint_dispatch(ali_handle* h, const ali_medium* media, int32_t n_media, const ali_material* mats,
+                                   int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
+                                   const ali_node* recv, int mode, const greal* d_in, const ali_options* opt,
+                                   outreal* d_T, outreal* d_trec, double* d_loss, outreal* d_dth,
+                                   ali_adjoint_stats* stats) {
+    const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
+    if (arith == ALI_ARITH_MIXED)
+        return adjoint_impl<float, oreal, greal, outreal>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs,
+                                                          recv, mode, d_in, opt, d_T, d_trec, d_loss, d_dth, stats);
+    if (arith == ALI_ARITH_F64)
+        return adjoint_impl<double, oreal, greal, outreal>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs,
+                                                           recv, mode, d_in, opt, d_T, d_trec, d_loss, d_dth, stats);
+    return h->fail(ALI_EUNSUPPORTED, "the adjoint needs float64 travel times: use ALI_ARITH_MIXED or ALI_ARITH_F64");
+}
+
 extern "C" ali_status ali_adjoint(ali_handle* h, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
                                   const uint8_t* d_mat_id, const float* d_orient, const ali_node* srcs,
                                   int32_t n_src, const ali_node* recv, int32_t n_recv, const float* d_dLdT,
                                   const ali_options* opt, float* d_T, float* d_dLdtheta,
                                   ali_adjoint_stats* stats) {
     if (!h) return ALI_EINVAL;
-    const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
-    if (arith == ALI_ARITH_MIXED)
-        return adjoint_impl<float, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, recv,
-                                                        n_recv, 0, d_dLdT, opt, d_T, nullptr, nullptr, d_dLdtheta, stats);
-    if (arith == ALI_ARITH_F64)
-        return adjoint_impl<double, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, recv,
-                                                         n_recv, 0, d_dLdT, opt, d_T, nullptr, nullptr, d_dLdtheta, stats);
-    return h->fail(ALI_EUNSUPPORTED, "the adjoint needs float64 travel times: use ALI_ARITH_MIXED or ALI_ARITH_F64");
+    if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
+    const ali_medium md = single_medium(grid, n_mats, n_src, n_recv);
+    return adjoint_dispatch<float, float, float>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, 0, d_dLdT,
+                                                 opt, d_T, (float*)nullptr, nullptr, d_dLdtheta, stats);
 }
 
 extern "C" ali_status ali_adjoint_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
@@ -831,8 +879,10 @@ extern "C" ali_status ali_adjoint_f64(ali_handle* h, const ali_grid* grid, const
                                       const ali_options* opt, double* d_T, double* d_dLdtheta,
                                       ali_adjoint_stats* stats) {
     if (!h) return ALI_EINVAL;
-    return adjoint_impl<double, double, double, double>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, recv,
-                                                        n_recv, 0, d_dLdT, opt, d_T, nullptr, nullptr, d_dLdtheta, stats);
+    if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
+    const ali_medium md = single_medium(grid, n_mats, n_src, n_recv);
+    return adjoint_impl<double, double, double, double>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, 0,
+                                                        d_dLdT, opt, d_T, (double*)nullptr, nullptr, d_dLdtheta, stats);
 }
 
 extern "C" ali_status ali_misfit_gradient(ali_handle* h, const ali_grid* grid, const ali_material* mats,
@@ -842,14 +892,10 @@ extern "C" ali_status ali_misfit_gradient(ali_handle* h, const ali_grid* grid, c
                                           float* d_T, float* d_Trec, double* d_loss, float* d_dLdtheta,
                                           ali_adjoint_stats* stats) {
     if (!h) return ALI_EINVAL;
-    const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
-    if (arith == ALI_ARITH_MIXED)
-        return adjoint_impl<float, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, recv,
-                                                        n_recv, 1, d_obs, opt, d_T, d_Trec, d_loss, d_dLdtheta, stats);
-    if (arith == ALI_ARITH_F64)
-        return adjoint_impl<double, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, recv,
-                                                         n_recv, 1, d_obs, opt, d_T, d_Trec, d_loss, d_dLdtheta, stats);
-    return h->fail(ALI_EUNSUPPORTED, "the adjoint needs float64 travel times: use ALI_ARITH_MIXED or ALI_ARITH_F64");
+    if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
+    const ali_medium md = single_medium(grid, n_mats, n_src, n_recv);
+    return adjoint_dispatch<float, float, float>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, 1, d_obs,
+                                                 opt, d_T, d_Trec, d_loss, d_dLdtheta, stats);
 }
 
 extern "C" ali_status ali_misfit_gradient_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats,
@@ -859,8 +905,20 @@ extern "C" ali_status ali_misfit_gradient_f64(ali_handle* h, const ali_grid* gri
                                               double* d_T, double* d_Trec, double* d_loss, double* d_dLdtheta,
                                               ali_adjoint_stats* stats) {
     if (!h) return ALI_EINVAL;
-    return adjoint_impl<double, double, double, double>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, recv,
-                                                        n_recv, 1, d_obs, opt, d_T, d_Trec, d_loss, d_dLdtheta, stats);
+    if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
+    const ali_medium md = single_medium(grid, n_mats, n_src, n_recv);
+    return adjoint_impl<double, double, double, double>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, 1,
+                                                        d_obs, opt, d_T, d_Trec, d_loss, d_dLdtheta, stats);
+}
+
+extern "C" ali_status ali_misfit_gradient_batch(ali_handle* h, const ali_medium* media, int32_t n_media,
+                                                const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
+                                                const float* d_orient, const ali_node* srcs, const ali_node* recv,
+                                                const float* d_obs, const ali_options* opt, float* d_Trec,
+                                                double* d_loss, float* d_dLdtheta, ali_adjoint_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    return adjoint_dispatch<float, float, float>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, recv, 1,
+                                                 d_obs, opt, (float*)nullptr, d_Trec, d_loss, d_dLdtheta, stats);
 }
 
 extern "C" ali_status ali_bilinear(ali_handle* h, int32_t nz, int32_t nx, int32_t ncz, int32_t ncx,

@@ -60,17 +60,18 @@ __global__ void k_prep(int nx, int nz, double h, int n_mats, const MatDev<mreal>
     for (int d = 0; d < 4; ++d) fbt[4 * p + d] = (treal)(len[d] * h / group_speed(m, ang[d] - th));
 }
 
+// initial values of the fields f0 .. f0 + gridDim.y - 1 (all in one medium)
 template <typename real, typename mreal, typename oreal>
-__global__ void k_init(int nx, int nz, int nf, double h, const MatDev<mreal>* __restrict__ mats,
-                       const uint8_t* __restrict__ mat_id, const oreal* __restrict__ orient,
-                       const int2* __restrict__ src, int R, real* __restrict__ T,
-                       uint32_t* __restrict__ flags, int ntx, int ntz) {
-    const int64_t N = (int64_t)nx * nz;
+__global__ void k_init(const FieldDev* __restrict__ fields, int f0, double h, const MatDev<mreal>* __restrict__ mats,
+                       const uint8_t* __restrict__ mat_id, const oreal* __restrict__ orient, int R,
+                       real* __restrict__ T, uint32_t* __restrict__ flags) {
+    const FieldDev fd = fields[f0 + blockIdx.y];
+    const int nx = fd.nx;
+    const int64_t N = (int64_t)nx * fd.nz;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int f = blockIdx.y;
     if (p >= N) return;
     const int i = (int)(p % nx), j = (int)(p / nx);
-    const int2 s = src[f];
+    const int2 s = fd.src;
     const int di = i - s.x, dj = j - s.y;
     real v = dinf<real>();
     if (abs(di) <= R && abs(dj) <= R) {
@@ -83,11 +84,10 @@ __global__ void k_init(int nx, int nz, int nf, double h, const MatDev<mreal>* __
             v = (real)(sqrt((double)(di * di + dj * dj)) * h / group_speed(mats[mat_id[ps]].A, phi));
         }
     }
-    T[(int64_t)f * N + p] = v;
+    T[fd.t_off + p] = v;
     // tiles that see the box (box radius + diamond radius) start active
-    if (abs(di) <= R + HALO && abs(dj) <= R + HALO) {
-        flags[(int64_t)f * ntx * ntz + (j / TZ) * ntx + (i / TX)] = 1u;   // evaluate the whole tile
-    }
+    if (abs(di) <= R + HALO && abs(dj) <= R + HALO)
+        flags[fd.unit_off + (j / TZ) * fd.ntx + (i / TX)] = TF_SELF;   // evaluate the whole tile
 }
 
 // Scheduler of one relaxation pass, one work-group per field: advance the field's
@@ -97,10 +97,13 @@ __global__ void k_init(int nx, int nz, int nf, double h, const MatDev<mreal>* __
 // this pass's list; cnt_next (the next pass's counter) is cleared here.
 template <typename real>
 __global__ void __launch_bounds__(256)
-k_sched(int ntiles, int advance, uint32_t* __restrict__ flags, real* __restrict__ minrej,
+k_sched(const FieldDev* __restrict__ fields, int advance, uint32_t* __restrict__ flags, real* __restrict__ minrej,
         real* __restrict__ theta, const real* __restrict__ step, uint32_t* __restrict__ list,
-        uint32_t* __restrict__ lbits, uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next) {
+        uint32_t* __restrict__ lbits, uint32_t* __restrict__ lfld, uint32_t* __restrict__ cnt_cur,
+        uint32_t* __restrict__ cnt_next) {
     const int f = blockIdx.x;
+    const uint32_t uoff = fields[f].unit_off;
+    const int ntiles = fields[f].ntx * fields[f].ntz;
     const int tid = threadIdx.x;
     const real inf = dinf<real>();
     __shared__ real red_m[256];
@@ -108,8 +111,8 @@ k_sched(int ntiles, int advance, uint32_t* __restrict__ flags, real* __restrict_
     __shared__ real th_s;
     __shared__ uint32_t base_s;
     if (f == 0 && tid == 0) *cnt_next = 0u;
-    uint32_t* fl = flags + (int64_t)f * ntiles;
-    real* mr = minrej + (int64_t)f * ntiles;
+    uint32_t* fl = flags + uoff;
+    real* mr = minrej + uoff;
     real th = theta[f];
     if (advance) th += step[f];
     // is anything active at this threshold, and what is the smallest rejected value?
@@ -159,8 +162,9 @@ k_sched(int ntiles, int advance, uint32_t* __restrict__ flags, real* __restrict_
         if (b != 0u || mr[t] <= th) {
             fl[t] = 0u;
             mr[t] = inf;          // recomputed by the visit
-            list[pos] = (uint32_t)((int64_t)f * ntiles + t);
+            list[pos] = uoff + (uint32_t)t;
             lbits[pos] = b;
+            lfld[pos] = (uint32_t)f;
             ++pos;
         }
     }
@@ -188,11 +192,11 @@ __device__ __forceinline__ void lds_min(double* p, double v) {
 // pass.  Each sweep packs the marked nodes into the first lanes.
 template <typename real, typename mreal>
 __global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
-k_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
-        const uint32_t* __restrict__ lbits,
-        const MatDev<mreal>* __restrict__ mats, const uint8_t* __restrict__ mat_id,
-        const mreal* __restrict__ geo, const real* __restrict__ fbt,
-        const int2* __restrict__ src, int R, int inner, const real* __restrict__ theta,
+k_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ list,
+        const uint32_t* __restrict__ lbits, const uint32_t* __restrict__ lfld,
+        const MatDev<mreal>* __restrict__ mats_all, const uint8_t* __restrict__ mat_id_all,
+        const mreal* __restrict__ geo_all, const real* __restrict__ fbt_all,
+        int R, int inner, const real* __restrict__ theta,
         real* __restrict__ T, uint32_t* __restrict__ flags, real* __restrict__ minrej,
         uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
         const uint32_t* __restrict__ count, uint32_t* __restrict__ idle,
@@ -215,13 +219,17 @@ k_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
     for (uint32_t item = blockIdx.x; item < n_units; item += gridDim.x) {
     const uint32_t unit = list[item];
     const uint32_t bits = lbits[item];
-    const int ntiles = ntx * ntz;
-    const int f = (int)(unit / (uint32_t)ntiles);
-    const int tile = (int)(unit % (uint32_t)ntiles);
+    const int f = (int)lfld[item];
+    const FieldDev fd = fields[f];
+    const int nx = fd.nx, nz = fd.nz, ntx = fd.ntx;
+    const int tile = (int)(unit - fd.unit_off);
     const int tx = tile % ntx, tz = tile / ntx;
     const int i0 = tx * TX, j0 = tz * TZ;
-    const int64_t N = (int64_t)nx * nz;
-    real* __restrict__ Tf = T + (int64_t)f * N;
+    real* __restrict__ Tf = T + fd.t_off;
+    const MatDev<mreal>* __restrict__ mats = mats_all + fd.mat_off;
+    const uint8_t* __restrict__ mat_id = mat_id_all + fd.node_off;
+    const mreal* __restrict__ geo = geo_all + 2 * fd.node_off;
+    const real* __restrict__ fbt = fbt_all + 4 * fd.node_off;
     const real inf = dinf<real>();
     const int lane = threadIdx.x;
 
@@ -240,7 +248,7 @@ k_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
         mk = marks_in[(int64_t)unit * NODE_WORDS + lane];
         if (mk) marks_in[(int64_t)unit * NODE_WORDS + lane] = 0u;
     }
-    const int2 s = src[f];
+    const int2 s = fd.src;
     const real th = theta[f];
     __syncthreads();
 
@@ -385,7 +393,7 @@ k_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
             if (!w) continue;
             const int o = q / NODE_WORDS;
             const int ntx2 = tx + o % 3 - 1, ntz2 = tz + o / 3 - 1;
-            const int64_t u2 = (int64_t)f * ntiles + (int64_t)ntz2 * ntx + ntx2;
+            const int64_t u2 = (int64_t)fd.unit_off + (int64_t)ntz2 * ntx + ntx2;
             atomicOr(&marks_out[u2 * NODE_WORDS + q % NODE_WORDS], w);
             atomicOr(&flags[u2], TF_MARK);
         }
@@ -407,61 +415,151 @@ k_relax(int nx, int nz, int ntx, int ntz, const uint32_t* __restrict__ list,
 // ---------------------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------------------
+ali_status validate_batch(ali_handle* H, const ali_medium* media, int32_t n_media, const ali_material* mats,
+                          int32_t n_mats, const void* d_mat_id, const void* d_orient, const ali_node* srcs,
+                          const ali_node* recv) {
+    if (!media || n_media < 1) return H->fail(ALI_EINVAL, "need at least one medium");
+    if (!mats || n_mats < 1) return H->fail(ALI_EINVAL, "need at least one material");
+    for (int k = 0; k < n_mats; ++k) {
+        const ali_material& m = mats[k];
+        const double v[7] = {m.c11, m.c13, m.c33, m.c55, m.c44, m.c66, m.rho};
+        for (double x : v)
+            if (!isfinite(x)) return H->fail(ALI_EINVAL, "material " + std::to_string(k) + " has a non-finite entry");
+        if (!(m.rho > 0.0)) return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": rho must be > 0");
+        if (!(m.c11 > 0.0 && m.c33 > 0.0 && m.c55 > 0.0))
+            return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": c11, c33, c55 must be > 0");
+        if (!(m.c11 * m.c33 > m.c13 * m.c13))
+            return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": c11*c33 must exceed c13^2");
+    }
+    if (!d_mat_id || !d_orient) return H->fail(ALI_EINVAL, "medium arrays are NULL");
+    if (!srcs) return H->fail(ALI_EINVAL, "sources are NULL");
+    int64_t units = 0;
+    for (int m = 0; m < n_media; ++m) {
+        const ali_medium& md = media[m];
+        const std::string tag = "medium " + std::to_string(m) + ": ";
+        const ali_grid& g = md.grid;
+        if (g.nx < 3 || g.nz < 3) return H->fail(ALI_EINVAL, tag + "grid needs nx, nz >= 3");
+        if ((int64_t)g.nx * g.nz > (int64_t)1 << 31) return H->fail(ALI_EINVAL, tag + "grid too large");
+        if (!(g.h > 0.0) || !isfinite(g.h)) return H->fail(ALI_EINVAL, tag + "grid spacing h must be finite and > 0");
+        if (md.n_mats < 1 || md.n_mats > 256 || md.mat_offset < 0 || md.mat_offset + md.n_mats > n_mats)
+            return H->fail(ALI_EINVAL, tag + "materials outside the table (1..256 per medium)");
+        if (md.node_offset < 0) return H->fail(ALI_EINVAL, tag + "negative node offset");
+        if (md.n_src < 1 || md.src_offset < 0) return H->fail(ALI_EINVAL, tag + "need at least one source");
+        for (int k = 0; k < md.n_src; ++k) {
+            const ali_node& sn = srcs[md.src_offset + k];
+            if (sn.i < 0 || sn.j < 0 || sn.i >= g.nx || sn.j >= g.nz)
+                return H->fail(ALI_EINVAL, tag + "source " + std::to_string(k) + " outside the grid");
+        }
+        if (recv) {
+            if (md.n_rec < 1 || md.rec_offset < 0) return H->fail(ALI_EINVAL, tag + "need at least one receiver");
+            for (int k = 0; k < md.n_rec; ++k) {
+                const ali_node& r = recv[md.rec_offset + k];
+                if (r.i < 0 || r.j < 0 || r.i >= g.nx || r.j >= g.nz)
+                    return H->fail(ALI_EINVAL, tag + "receiver " + std::to_string(k) + " outside the grid");
+            }
+        }
+        units += (int64_t)((g.nx + TX - 1) / TX) * ((g.nz + TZ - 1) / TZ) * md.n_src;
+    }
+    if (units >= (int64_t)INT32_MAX) return H->fail(ALI_EINVAL, "too many tiles in one call");
+    return ALI_OK;
+}
+
 // real: travel-time type (storage, scores, decisions); mreal: wavefront / phase-speed
 // math; oreal: orientation input.
 template <typename real, typename mreal, typename oreal>
-ali_status solve_core(ali_handle* H, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
-                      const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
-                      int32_t n_src, const ali_options& opt, real* d_T, ali_solve_stats* stats,
-                      ForwardState<real, mreal>* fs) {
-    ali_status st = validate_medium(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src);
+ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media, const ali_material* mats,
+                        int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
+                        const ali_node* recv, const ali_options& opt, real* d_T, ali_solve_stats* stats,
+                        ForwardState<real, mreal>* fs) {
+    ali_status st = validate_batch(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, recv);
     if (st != ALI_OK) return st;
     if (!d_T) return H->fail(ALI_EINVAL, "d_T is NULL");
     if (opt.src_box_radius < 0 || opt.src_box_radius > 64) return H->fail(ALI_EINVAL, "src_box_radius out of range [0, 64]");
     if (opt.max_sweeps < 1) return H->fail(ALI_EINVAL, "max_sweeps must be >= 1");
     if (opt.inner_sweeps < 1 || opt.inner_sweeps > 4096) return H->fail(ALI_EINVAL, "inner_sweeps out of range [1, 4096]");
     if (opt.band_cells < 0) return H->fail(ALI_EINVAL, "band_cells must be >= 0 (0 = no band)");
-
-    const int nx = grid->nx, nz = grid->nz;
-    const int64_t N = (int64_t)nx * nz;
-    const int ntx = (nx + TX - 1) / TX, ntz = (nz + TZ - 1) / TZ;
-    const int64_t nunits = (int64_t)ntx * ntz * n_src;
-    if (nunits >= (int64_t)UINT32_MAX) return H->fail(ALI_EINVAL, "too many tiles in one call");
     if (set_device(H) != ALI_OK) return ALI_EDEVICE;
     hipStream_t S = H->stream;
 
-    const std::vector<MatDev<mreal>> hm = make_matdev<mreal>(mats, n_mats, grid->h);
-    // band step: band_cells node spacings at the fastest phase speed of the medium
-    const double vmax = max_phase_speed(mats, n_mats);
-    const real band = opt.band_cells > 0 ? (real)(opt.band_cells * grid->h / vmax) : dinf_host<real>();
-    std::vector<real> hstep(n_src, band), htheta(n_src, band);
+    // field table, per-medium material constants (they carry 1/h^2) and band steps
+    ForwardState<real, mreal> local;
+    ForwardState<real, mreal>& F = fs ? *fs : local;
+    F.hfields.clear();
+    F.medium_first_field.clear();
+    F.vmax.clear();
+    std::vector<MatDev<mreal>> hm;
+    std::vector<int> dev_mat_off(n_media);
+    std::vector<real> hstep, htheta;
+    int64_t units = 0, fnodes = 0, med_nodes = 0;
+    int obs = 0;
+    for (int m = 0; m < n_media; ++m) {
+        const ali_medium& md = media[m];
+        dev_mat_off[m] = (int)hm.size();
+        const std::vector<MatDev<mreal>> mm = make_matdev<mreal>(mats + md.mat_offset, md.n_mats, md.grid.h);
+        hm.insert(hm.end(), mm.begin(), mm.end());
+        const double vmax = max_phase_speed(mats + md.mat_offset, md.n_mats);
+        F.vmax.push_back(vmax);
+        const real band = opt.band_cells > 0 ? (real)(opt.band_cells * md.grid.h / vmax) : dinf_host<real>();
+        F.medium_first_field.push_back((int)F.hfields.size());
+        const int nx = md.grid.nx, nz = md.grid.nz;
+        const int ntx = (nx + TX - 1) / TX, ntz = (nz + TZ - 1) / TZ;
+        med_nodes = std::max(med_nodes, md.node_offset + (int64_t)nx * nz);
+        for (int k = 0; k < md.n_src; ++k) {
+            FieldDev fd;
+            fd.nx = nx; fd.nz = nz; fd.ntx = ntx; fd.ntz = ntz;
+            fd.h = md.grid.h;
+            fd.node_off = md.node_offset;
+            fd.t_off = fnodes;
+            fd.unit_off = (uint32_t)units;
+            fd.mat_off = dev_mat_off[m];
+            fd.medium = m;
+            fd.rec_off = md.rec_offset;
+            fd.n_rec = recv ? md.n_rec : 0;
+            fd.obs_off = obs;
+            fd.src = make_int2(srcs[md.src_offset + k].i, srcs[md.src_offset + k].j);
+            F.hfields.push_back(fd);
+            units += (int64_t)ntx * ntz;
+            fnodes += (int64_t)nx * nz;
+            obs += fd.n_rec;
+            hstep.push_back(band);
+            htheta.push_back(band);
+        }
+    }
+    F.medium_first_field.push_back((int)F.hfields.size());
+    const int n_fields = (int)F.hfields.size();
+    const int64_t nunits = units;
+    F.n_units = nunits;
+    F.field_nodes = fnodes;
 
-    void *d_mats, *d_geo, *d_fbt, *d_src, *d_flags, *d_list, *d_count, *d_upd, *d_err;
+    void *d_mats, *d_geo, *d_fbt, *d_fields, *d_flags, *d_list, *d_lfld, *d_count, *d_upd, *d_err;
     void *d_theta, *d_step, *d_minrej, *d_lbits, *d_marks, *d_idle;
-    if (!H->scratch("mats", sizeof(MatDev<mreal>) * n_mats, &d_mats) ||
-        !H->scratch("theta", sizeof(real) * n_src, &d_theta) ||
-        !H->scratch("step", sizeof(real) * n_src, &d_step) ||
+    if (!H->scratch("mats", sizeof(MatDev<mreal>) * hm.size(), &d_mats) ||
+        !H->scratch("fields", sizeof(FieldDev) * n_fields, &d_fields) ||
+        !H->scratch("theta", sizeof(real) * n_fields, &d_theta) ||
+        !H->scratch("step", sizeof(real) * n_fields, &d_step) ||
         !H->scratch("minrej", sizeof(real) * nunits, &d_minrej) ||
-        !H->scratch("geo", sizeof(mreal) * 2 * N, &d_geo) ||
-        !H->scratch("fbt", sizeof(real) * 4 * N, &d_fbt) ||
-        !H->scratch("src", sizeof(int2) * n_src, &d_src) ||
+        !H->scratch("geo", sizeof(mreal) * 2 * med_nodes, &d_geo) ||
+        !H->scratch("fbt", sizeof(real) * 4 * med_nodes, &d_fbt) ||
         !H->scratch("flags", sizeof(uint32_t) * nunits, &d_flags) ||
         !H->scratch("list", sizeof(uint32_t) * nunits, &d_list) ||
         !H->scratch("lbits", sizeof(uint32_t) * nunits, &d_lbits) ||
+        !H->scratch("lfld", sizeof(uint32_t) * nunits, &d_lfld) ||
         !H->scratch("marks", sizeof(uint32_t) * 2 * NODE_WORDS * nunits, &d_marks) ||
         !H->scratch("count", 2 * sizeof(uint32_t), &d_count) ||
         !H->scratch("idle", sizeof(uint32_t), &d_idle) ||
         !H->scratch("upd", (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), &d_upd) ||
         !H->scratch("err", sizeof(int), &d_err))
         return H->fail(ALI_ENOMEM, "device scratch allocation failed");
-    std::vector<int2> hs(n_src);
-    for (int k = 0; k < n_src; ++k) hs[k] = make_int2(srcs[k].i, srcs[k].j);
+    F.mats = (const MatDev<mreal>*)d_mats;
+    F.geo = (const mreal*)d_geo;
+    F.fbt = (const real*)d_fbt;
+    F.fields = (const FieldDev*)d_fields;
 
     HIPCK(H, hipEventRecord(H->ev0, S));
-    HIPCK(H, hipMemcpyAsync(d_mats, hm.data(), sizeof(MatDev<mreal>) * n_mats, hipMemcpyHostToDevice, S));
-    HIPCK(H, hipMemcpyAsync(d_src, hs.data(), sizeof(int2) * n_src, hipMemcpyHostToDevice, S));
-    HIPCK(H, hipMemcpyAsync(d_theta, htheta.data(), sizeof(real) * n_src, hipMemcpyHostToDevice, S));
-    HIPCK(H, hipMemcpyAsync(d_step, hstep.data(), sizeof(real) * n_src, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemcpyAsync(d_mats, hm.data(), sizeof(MatDev<mreal>) * hm.size(), hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemcpyAsync(d_fields, F.hfields.data(), sizeof(FieldDev) * n_fields, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemcpyAsync(d_theta, htheta.data(), sizeof(real) * n_fields, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemcpyAsync(d_step, hstep.data(), sizeof(real) * n_fields, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemsetAsync(d_flags, 0, sizeof(uint32_t) * nunits, S));
     HIPCK(H, hipMemsetAsync(d_marks, 0, sizeof(uint32_t) * 2 * NODE_WORDS * nunits, S));
     HIPCK(H, hipMemsetAsync(d_upd, 0, (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), S));
@@ -472,14 +570,18 @@ ali_status solve_core(ali_handle* H, const ali_grid* grid, const ali_material* m
     const int B = 256;
     hipLaunchKernelGGL((k_fill<real>), dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
                        (real*)d_minrej, nunits, dinf_host<real>());
-    hipLaunchKernelGGL((k_prep<mreal, real, oreal>), dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S,
-                       nx, nz, grid->h, n_mats, (const MatDev<mreal>*)d_mats, d_mat_id, d_orient,
-                       (mreal*)d_geo, (real*)d_fbt, (int*)d_err);
-    HIPCK(H, hipGetLastError());
-    hipLaunchKernelGGL((k_init<real, mreal, oreal>), dim3((unsigned)((N + B - 1) / B), (unsigned)n_src), dim3(B), 0, S,
-                       nx, nz, n_src, grid->h, (const MatDev<mreal>*)d_mats, d_mat_id,
-                       d_orient, (const int2*)d_src, opt.src_box_radius, d_T,
-                       (uint32_t*)d_flags, ntx, ntz);
+    for (int m = 0; m < n_media; ++m) {
+        const ali_medium& md = media[m];
+        const int64_t N = (int64_t)md.grid.nx * md.grid.nz;
+        hipLaunchKernelGGL((k_prep<mreal, real, oreal>), dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S,
+                           md.grid.nx, md.grid.nz, md.grid.h, md.n_mats, (const MatDev<mreal>*)d_mats + dev_mat_off[m],
+                           d_mat_id + md.node_offset, d_orient + md.node_offset,
+                           (mreal*)d_geo + 2 * md.node_offset, (real*)d_fbt + 4 * md.node_offset, (int*)d_err);
+        hipLaunchKernelGGL((k_init<real, mreal, oreal>), dim3((unsigned)((N + B - 1) / B), (unsigned)md.n_src), dim3(B), 0, S,
+                           (const FieldDev*)d_fields, F.medium_first_field[m], md.grid.h,
+                           (const MatDev<mreal>*)d_mats + dev_mat_off[m], d_mat_id + md.node_offset,
+                           d_orient + md.node_offset, opt.src_box_radius, d_T, (uint32_t*)d_flags);
+    }
     HIPCK(H, hipGetLastError());
 
     int h_err = 0;
@@ -498,22 +600,21 @@ ali_status solve_core(ali_handle* H, const ali_grid* grid, const ali_material* m
     // pass list exit at once
     const int grid_relax = (int)(nunits < (int64_t)32 * H->n_cu ? nunits : (int64_t)32 * H->n_cu);
     uint32_t* cnt = (uint32_t*)d_count;
-    const int ntiles = ntx * ntz;
     while (iters < opt.max_sweeps) {
         const int batch = opt.max_sweeps - iters < PASS_BATCH ? opt.max_sweeps - iters : PASS_BATCH;
         for (int b = 0; b < batch; ++b) {
             const int p = iters + b;
-            hipLaunchKernelGGL((k_sched<real>), dim3((unsigned)n_src), dim3(256), 0, S, ntiles, p > 0 ? 1 : 0,
+            hipLaunchKernelGGL((k_sched<real>), dim3((unsigned)n_fields), dim3(256), 0, S,
+                               (const FieldDev*)d_fields, p > 0 ? 1 : 0,
                                (uint32_t*)d_flags, (real*)d_minrej, (real*)d_theta, (const real*)d_step,
-                               (uint32_t*)d_list, (uint32_t*)d_lbits, cnt + (p & 1), cnt + ((p + 1) & 1));
+                               (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_lfld, cnt + (p & 1), cnt + ((p + 1) & 1));
             uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
             uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
             HIPCK(H, hipEventRecord(H->pev[2 * b], S));
             hipLaunchKernelGGL((k_relax<real, mreal>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
-                               nx, nz, ntx, ntz, (const uint32_t*)d_list, (const uint32_t*)d_lbits,
-                               (const MatDev<mreal>*)d_mats,
-                               d_mat_id, (const mreal*)d_geo, (const real*)d_fbt, (const int2*)d_src,
-                               opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
+                               (const FieldDev*)d_fields, (const uint32_t*)d_list, (const uint32_t*)d_lbits,
+                               (const uint32_t*)d_lfld, (const MatDev<mreal>*)d_mats, d_mat_id, (const mreal*)d_geo,
+                               (const real*)d_fbt, opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
                                (uint32_t*)d_flags, (real*)d_minrej, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)),
                                (uint32_t*)d_idle, (unsigned long long*)d_upd);
             HIPCK(H, hipEventRecord(H->pev[2 * b + 1], S));
@@ -539,57 +640,49 @@ ali_status solve_core(ali_handle* H, const ali_grid* grid, const ali_material* m
         stats->stencil_evals = (int64_t)upd[1];
         stats->relax_ms = relax_ms;
         stats->tile_visits = (int64_t)upd[3];
-        stats->nodes = N * n_src;
+        stats->nodes = fnodes;
         stats->outer_iters = (int32_t)upd[2];
         stats->converged = converged ? 1 : 0;
         stats->ms = 0.0;
-    }
-    if (fs) {
-        fs->mats = (const MatDev<mreal>*)d_mats;
-        fs->geo = (const mreal*)d_geo;
-        fs->fbt = (const real*)d_fbt;
-        fs->src = (const int2*)d_src;
-        fs->ntx = ntx;
-        fs->ntz = ntz;
     }
     if (!converged) return H->fail(ALI_ENOCONV, "relaxation reached max_sweeps");
     return ALI_OK;
 }
 
-template ali_status solve_core<double, float, float>(ali_handle*, const ali_grid*, const ali_material*, int32_t,
-    const uint8_t*, const float*, const ali_node*, int32_t, const ali_options&, double*, ali_solve_stats*,
-    ForwardState<double, float>*);
-template ali_status solve_core<float, float, float>(ali_handle*, const ali_grid*, const ali_material*, int32_t,
-    const uint8_t*, const float*, const ali_node*, int32_t, const ali_options&, float*, ali_solve_stats*,
-    ForwardState<float, float>*);
-template ali_status solve_core<double, double, float>(ali_handle*, const ali_grid*, const ali_material*, int32_t,
-    const uint8_t*, const float*, const ali_node*, int32_t, const ali_options&, double*, ali_solve_stats*,
-    ForwardState<double, double>*);
-template ali_status solve_core<double, double, double>(ali_handle*, const ali_grid*, const ali_material*, int32_t,
-    const uint8_t*, const double*, const ali_node*, int32_t, const ali_options&, double*, ali_solve_stats*,
-    ForwardState<double, double>*);
+#define ALI_SOLVE_FIELDS(R, M, O)                                                                            \
+    template ali_status solve_fields<R, M, O>(ali_handle*, const ali_medium*, int32_t, const ali_material*,  \
+                                              int32_t, const uint8_t*, const O*, const ali_node*,            \
+                                              const ali_node*, const ali_options&, R*, ali_solve_stats*,     \
+                                              ForwardState<R, M>*);
+ALI_SOLVE_FIELDS(double, float, float)
+ALI_SOLVE_FIELDS(float, float, float)
+ALI_SOLVE_FIELDS(double, double, float)
+ALI_SOLVE_FIELDS(double, double, double)
+#undef ALI_SOLVE_FIELDS
 
 // Entry-point body: relax in `real` (on a scratch field when it differs from the output
 // type), convert into d_out, time the whole call.
 template <typename real, typename mreal, typename oreal, typename outreal>
-static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats,
+static ali_status solve_impl(ali_handle* H, const ali_medium* media, int32_t n_media, const ali_material* mats,
                              int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient,
-                             const ali_node* srcs, int32_t n_src, const ali_options* opt_in,
-                             outreal* d_out, ali_solve_stats* stats) {
+                             const ali_node* srcs, const ali_options* opt_in, outreal* d_out,
+                             ali_solve_stats* stats) {
     ali_options opt;
     ali_default_options(&opt);
     if (opt_in) opt = *opt_in;
     if (!d_out) return H->fail(ALI_EINVAL, "d_T is NULL");
-    if (!grid) return H->fail(ALI_EINVAL, "grid is NULL");
+    ali_status st = validate_batch(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, nullptr);
+    if (st != ALI_OK) return st;
+    int64_t n_fields = 0, tot = 0;
+    batch_sizes(media, n_media, &n_fields, &tot);
     constexpr bool same_out = std::is_same<real, outreal>::value;
-    const int64_t tot = (int64_t)grid->nx * grid->nz * (n_src > 0 ? n_src : 0);
     void* d_work = nullptr;
-    if (!same_out && tot > 0 && !H->scratch("Twork", sizeof(real) * tot, &d_work))
+    if (!same_out && !H->scratch("Twork", sizeof(real) * tot, &d_work))
         return H->fail(ALI_ENOMEM, "device scratch allocation failed");
     real* d_T = same_out ? (real*)d_out : (real*)d_work;
     ali_solve_stats local{};
-    ali_status st = solve_core<real, mreal, oreal>(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
-                                                   opt, d_T, &local, nullptr);
+    st = solve_fields<real, mreal, oreal>(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, nullptr, opt,
+                                          d_T, &local, nullptr);
     if (st != ALI_OK && st != ALI_ENOCONV) return st;
     hipStream_t S = H->stream;
     if (!same_out) {
@@ -613,6 +706,22 @@ static ali_status solve_impl(ali_handle* H, const ali_grid* grid, const ali_mate
 
 using namespace ali;
 
+template <typename oreal, typename outreal>
+static ali_status solve_dispatch(ali_handle* h, const ali_medium* media, int32_t n_media, const ali_material* mats,
+                                 int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
+                                 const ali_options* opt, outreal* d_T, ali_solve_stats* stats) {
+    const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
+    switch (arith) {
+        case ALI_ARITH_MIXED:
+            return solve_impl<double, float, oreal, outreal>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, opt, d_T, stats);
+        case ALI_ARITH_F32:
+            return solve_impl<float, float, oreal, outreal>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, opt, d_T, stats);
+        case ALI_ARITH_F64:
+            return solve_impl<double, double, oreal, outreal>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, opt, d_T, stats);
+    }
+    return h->fail(ALI_EINVAL, "unknown arith mode");
+}
+
 extern "C" ali_status ali_solve_traveltime(ali_handle* h, const ali_grid* grid,
                                            const ali_material* mats, int32_t n_mats,
                                            const uint8_t* d_mat_id, const float* d_orient,
@@ -620,16 +729,9 @@ extern "C" ali_status ali_solve_traveltime(ali_handle* h, const ali_grid* grid,
                                            const ali_options* opt, float* d_T,
                                            ali_solve_stats* stats) {
     if (!h) return ALI_EINVAL;
-    const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
-    switch (arith) {
-        case ALI_ARITH_MIXED:
-            return solve_impl<double, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt, d_T, stats);
-        case ALI_ARITH_F32:
-            return solve_impl<float, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt, d_T, stats);
-        case ALI_ARITH_F64:
-            return solve_impl<double, double, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt, d_T, stats);
-    }
-    return h->fail(ALI_EINVAL, "unknown arith mode");
+    if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
+    const ali_medium md = single_medium(grid, n_mats, n_src, 0);
+    return solve_dispatch<float, float>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, opt, d_T, stats);
 }
 
 extern "C" ali_status ali_solve_traveltime_f64(ali_handle* h, const ali_grid* grid,
@@ -639,5 +741,15 @@ extern "C" ali_status ali_solve_traveltime_f64(ali_handle* h, const ali_grid* gr
                                                const ali_options* opt, double* d_T,
                                                ali_solve_stats* stats) {
     if (!h) return ALI_EINVAL;
-    return solve_impl<double, double, double, double>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt, d_T, stats);
+    if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
+    const ali_medium md = single_medium(grid, n_mats, n_src, 0);
+    return solve_impl<double, double, double, double>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, opt, d_T, stats);
+}
+
+extern "C" ali_status ali_solve_batch(ali_handle* h, const ali_medium* media, int32_t n_media,
+                                      const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
+                                      const float* d_orient, const ali_node* srcs, const ali_options* opt,
+                                      float* d_T, ali_solve_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    return solve_dispatch<float, float>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, opt, d_T, stats);
 }

@@ -102,25 +102,82 @@ __device__ __forceinline__ void load_node_const(NodeConst<mreal, real>& nc, int6
     for (int d = 0; d < 4; ++d) nc.fb[d] = fbt[4 * p + d];
 }
 
-// What the forward driver leaves on the device for a following adjoint on the same
-// stream: per-material and per-node constants of the medium and the source list.
-template <typename real, typename mreal> struct ForwardState {
-    const MatDev<mreal>* mats = nullptr;
-    const mreal* geo = nullptr;      // [N][2] cos 2theta, sin 2theta
-    const real* fbt = nullptr;       // [N][4] straight-ray times to 8-neighbours
-    const int2* src = nullptr;       // [n_src]
-    int ntx = 0, ntz = 0;
+// One field of a batch: a source in a medium.  Offsets count elements.
+struct FieldDev {
+    int nx, nz, ntx, ntz;
+    double h;             // node spacing of the medium
+    int64_t node_off;     // the medium's first node in the per-node arrays (materials, orientation)
+    int64_t t_off;        // the field's first node in the per-field arrays (travel times)
+    uint32_t unit_off;    // the field's first tile unit (flags, thresholds, node marks)
+    int mat_off;          // the medium's first entry in the device material table
+    int medium;
+    int rec_off, n_rec;   // the medium's receivers (gradient calls)
+    int obs_off;          // the field's first entry in per-receiver arrays
+    int2 src;
 };
 
-// Forward solve of n_src fields into the working field d_T ([n_src][nz][nx], type real).
-// Validates its arguments, records H->ev0 at its start, synchronises the stream before
-// returning and fills every stats field except `ms`.  Instantiated for
-// <double, float, float>, <float, float, float>, <double, double, float> and
-// <double, double, double>.
+// field f owning tile unit u (fields are stored in unit order)
+__device__ __forceinline__ int field_of_unit(const FieldDev* __restrict__ fields, int n_fields, uint32_t u) {
+    int lo = 0, hi = n_fields - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (fields[mid].unit_off <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// What the forward driver leaves on the device for a following adjoint on the same
+// stream: the field table, per-material and per-node constants, and their host copies.
+template <typename real, typename mreal> struct ForwardState {
+    const MatDev<mreal>* mats = nullptr;
+    const mreal* geo = nullptr;      // [medium nodes][2] cos 2theta, sin 2theta
+    const real* fbt = nullptr;       // [medium nodes][4] straight-ray times to 8-neighbours
+    const FieldDev* fields = nullptr;
+    std::vector<FieldDev> hfields;
+    std::vector<int> medium_first_field;   // per medium, then the total
+    std::vector<double> vmax;        // fastest phase speed per medium
+    int64_t n_units = 0, field_nodes = 0;
+};
+
+// Validates a batch (media, materials, sources and, when recv != NULL, receivers).
+ali_status validate_batch(ali_handle* H, const ali_medium* media, int32_t n_media, const ali_material* mats,
+                          int32_t n_mats, const void* d_mat_id, const void* d_orient, const ali_node* srcs,
+                          const ali_node* recv);
+
+// Forward solve of every field of a batch into the working field d_T (fields in medium
+// order, each [nz][nx]; type real).  Validates its arguments, records H->ev0 at its start,
+// synchronises the stream before returning and fills every stats field except `ms`.
+// Instantiated for <double, float, float>, <float, float, float>, <double, double, float>
+// and <double, double, double>.
 template <typename real, typename mreal, typename oreal>
-ali_status solve_core(ali_handle* H, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
-                      const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
-                      int32_t n_src, const ali_options& opt, real* d_T, ali_solve_stats* stats,
-                      ForwardState<real, mreal>* fs);
+ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media, const ali_material* mats,
+                        int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
+                        const ali_node* recv, const ali_options& opt, real* d_T, ali_solve_stats* stats,
+                        ForwardState<real, mreal>* fs);
+
+// number of fields and field nodes of a batch (after validation)
+inline void batch_sizes(const ali_medium* media, int32_t n_media, int64_t* n_fields, int64_t* field_nodes) {
+    int64_t f = 0, n = 0;
+    for (int m = 0; m < n_media; ++m) {
+        f += media[m].n_src;
+        n += (int64_t)media[m].n_src * media[m].grid.nx * media[m].grid.nz;
+    }
+    *n_fields = f;
+    *field_nodes = n;
+}
+
+// the single-medium entry points as a batch of one
+inline ali_medium single_medium(const ali_grid* g, int32_t n_mats, int32_t n_src, int32_t n_rec) {
+    ali_medium m;
+    m.grid = *g;
+    m.mat_offset = 0;
+    m.n_mats = n_mats;
+    m.node_offset = 0;
+    m.src_offset = 0;
+    m.n_src = n_src;
+    m.rec_offset = 0;
+    m.n_rec = n_rec;
+    return m;
+}
 
 }  // namespace ali

@@ -58,7 +58,7 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     from paper_2302_10988_amd import _lib
     structs = {"ali_grid": _lib.Grid, "ali_material": _lib.Material, "ali_node": _lib.Node,
-               "ali_options": _lib.Options, "ali_solve_stats": _lib.SolveStats,
+               "ali_options": _lib.Options, "ali_solve_stats": _lib.SolveStats, "ali_medium": _lib.Medium,
                "ali_adjoint_stats": _lib.AdjointStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ali.h"', "int main(void) {"]
     for cname, py in structs.items():
