@@ -63,6 +63,9 @@ typedef struct {
     int32_t arith;           /* float32 entry points: ALI_ARITH_MIXED (default), _F32 or _F64     */
     int32_t ray_sub;         /* ray tracer: candidates per node spacing along a plane (the paper's
                                 finer subgrid); ray_window * ray_sub <= 32; default 8             */
+    int32_t graph;           /* 1: relaxation passes are replayed from captured HIP graphs (one
+                                per argument signature, kept by the handle); 0: launched one by
+                                one; default 1                                                 */
 } ali_options;
 
 /* Arithmetic of the float32 entry points.  MIXED keeps travel times, scores and every
@@ -151,6 +154,18 @@ ali_status ali_solve_batch(ali_handle* h, const ali_medium* media, int32_t n_med
                            const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
                            const float* d_orient, const ali_node* srcs, const ali_options* opt,
                            float* d_T, ali_solve_stats* stats);
+
+/* Schedule autotuner: times the forward batch solve (the fields go to d_T, [field nodes]
+   float32, device) under each of ALI_TUNE_CANDIDATES (band_cells, inner_sweeps) settings
+   -- (1,1) (1,2) (1,4) (2,2) (2,4) (3,4) -- and writes the fastest into *opt (the other
+   fields of *opt are kept and used for every run).  ms_out (host, nullable) receives the
+   time of each candidate.  Every candidate reaches the same fields (the fixed point does
+   not depend on the schedule); only the time differs.  Synchronises the stream. */
+#define ALI_TUNE_CANDIDATES 6
+ali_status ali_autotune_batch(ali_handle* h, const ali_medium* media, int32_t n_media,
+                              const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
+                              const float* d_orient, const ali_node* srcs, ali_options* opt,
+                              float* d_T, double* ms_out);
 
 /* Ray paths through finished fields (paper Section 5.1): for every source s and receiver
    r, the fastest path from r to s through field s (reciprocity), built plane by plane with

@@ -161,7 +161,7 @@ class Solver:
 
     def solve(self, h, mats, mat_id, orient, sources, out=None, precision="f32",
               src_box_radius=None, max_sweeps=None, inner_sweeps=None, band_cells=None,
-              arith="mixed"):
+              arith="mixed", **extra):
         """Travel-time fields [n_src, nz, nx] for point sources in one medium.
 
         h: grid spacing [m]; mats: list of stiffness records (dicts with c11, c13, c33,
@@ -177,7 +177,7 @@ class Solver:
         g = _lib.Grid(int(nx), int(nz), float(h))
         opt = default_options(src_box_radius=src_box_radius, max_sweeps=max_sweeps,
                               inner_sweeps=inner_sweeps, band_cells=band_cells,
-                              arith=_lib.ARITH[arith])
+                              arith=_lib.ARITH[arith], **extra)
         if out is None:
             out = torch.empty((ns, nz, nx), dtype=fdt, device=mat_id.device)
         p_id = _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id")
@@ -224,7 +224,7 @@ class Solver:
 
     def adjoint(self, h, mats, mat_id, orient, sources, receivers, dLdT, precision="f32",
                 return_T=False, src_box_radius=None, max_sweeps=None, inner_sweeps=None,
-                band_cells=None, arith="mixed"):
+                band_cells=None, arith="mixed", **extra):
         """dL/dtheta [nz, nx] (summed over sources) for dL/dT given at the receivers,
         dLdT [n_src, n_rec] device tensor.  The forward fields are solved inside the call
         (returned when return_T).  precision "f32" (arith "mixed" or "f64") or "f64".
@@ -238,7 +238,7 @@ class Solver:
         g = _lib.Grid(int(nx), int(nz), float(h))
         opt = default_options(src_box_radius=src_box_radius, max_sweeps=max_sweeps,
                               inner_sweeps=inner_sweeps, band_cells=band_cells,
-                              arith=_lib.ARITH[arith])
+                              arith=_lib.ARITH[arith], **extra)
         dev = mat_id.device
         dth = torch.empty((nz, nx), dtype=fdt, device=dev)
         T = torch.empty((ns, nz, nx), dtype=fdt, device=dev) if return_T else None
@@ -254,7 +254,7 @@ class Solver:
 
     def misfit_gradient(self, h, mats, mat_id, orient, sources, receivers, obs, precision="f32",
                         T_out=None, src_box_radius=None, max_sweeps=None, inner_sweeps=None,
-                        band_cells=None, arith="mixed"):
+                        band_cells=None, arith="mixed", **extra):
         """Forward + adjoint of L = 1/2 sum (T_s(r) - obs[s, r])^2 in one call; the forward
         fields go to T_out [n_src, nz, nx] when given.
         Returns (loss float64 device scalar, Trec [n_src, n_rec], dLdtheta [nz, nx], stats)."""
@@ -267,7 +267,7 @@ class Solver:
         g = _lib.Grid(int(nx), int(nz), float(h))
         opt = default_options(src_box_radius=src_box_radius, max_sweeps=max_sweeps,
                               inner_sweeps=inner_sweeps, band_cells=band_cells,
-                              arith=_lib.ARITH[arith])
+                              arith=_lib.ARITH[arith], **extra)
         dev = mat_id.device
         dth = torch.empty((nz, nx), dtype=fdt, device=dev)
         trec = torch.empty((ns, nr), dtype=fdt, device=dev)
@@ -347,3 +347,19 @@ class Solver:
                                                  ctypes.byref(stats))
         self._check(st)
         return loss, trec, dth, stats.as_dict()
+
+    def autotune_batch(self, batch, arith="mixed", **opts):
+        """Time the forward batch solve under each candidate schedule and return (the
+        fastest options as a dict, {(band_cells, inner_sweeps): ms})."""
+        import torch
+        opt = default_options(arith=_lib.ARITH[arith], **opts)
+        out = torch.empty(batch.field_nodes, dtype=torch.float32, device=batch.mat_id.device)
+        ms = (ctypes.c_double * len(_lib.TUNE_CANDIDATES))()
+        self._sync_stream()
+        st = self._lib.ali_autotune_batch(self._h, batch.media, batch.n_media, batch.mats, batch.n_mats,
+                                          _dev_ptr(batch.mat_id, torch.uint8, name="mat_id"),
+                                          _dev_ptr(batch.orient, torch.float32, name="orient"), batch.srcs,
+                                          ctypes.byref(opt), _dev_ptr(out, torch.float32), ms)
+        self._check(st)
+        best = {k: getattr(opt, k) for k, _ in opt._fields_}
+        return best, {c: ms[k] for k, c in enumerate(_lib.TUNE_CANDIDATES)}

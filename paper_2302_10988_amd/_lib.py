@@ -36,9 +36,10 @@ class Options(ctypes.Structure):
     _fields_ = [("src_box_radius", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("inner_sweeps", ctypes.c_int32), ("band_cells", ctypes.c_int32),
                 ("ray_window", ctypes.c_int32), ("ray_max_pts", ctypes.c_int32),
-                ("arith", ctypes.c_int32), ("ray_sub", ctypes.c_int32)]
+                ("arith", ctypes.c_int32), ("ray_sub", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 ARITH = {"mixed": 0, "f32": 1, "f64": 2}
+TUNE_CANDIDATES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4), (3, 4)]   # (band_cells, inner_sweeps)
 
 
 class SolveStats(ctypes.Structure):
@@ -103,6 +104,9 @@ SIGNATURES = {
     "ali_misfit_gradient_batch": (ctypes.c_int, [_P, ctypes.POINTER(Medium), _I32, ctypes.POINTER(Material), _I32,
                                                  _P, _P, ctypes.POINTER(Node), ctypes.POINTER(Node), _P,
                                                  ctypes.POINTER(Options), _P, _P, _P, ctypes.POINTER(AdjointStats)]),
+    "ali_autotune_batch": (ctypes.c_int, [_P, ctypes.POINTER(Medium), _I32, ctypes.POINTER(Material), _I32, _P, _P,
+                                          ctypes.POINTER(Node), ctypes.POINTER(Options), _P,
+                                          ctypes.POINTER(ctypes.c_double)]),
     "ali_bilinear": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),
     "ali_bilinear_transpose": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),
     "ali_bilinear_f64": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),

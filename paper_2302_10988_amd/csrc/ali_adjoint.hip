@@ -692,32 +692,51 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     double relax_ms = 0.0;
     const int grid_relax = (int)(nunits < (int64_t)32 * H->n_cu ? nunits : (int64_t)32 * H->n_cu);
     uint32_t* cnt = (uint32_t*)d_count;
+    auto enqueue = [&](int p, bool timed, hipStream_t S) {
+        hipLaunchKernelGGL(k_adj_sched, dim3((unsigned)n_fields), dim3(256), 0, S, fs.fields, p > 0 ? 1 : 0,
+                           (const double*)d_step, (uint32_t*)d_flags, (const double*)d_maxdef, (double*)d_theta,
+                           (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_lfld, cnt + (p & 1), cnt + ((p + 1) & 1));
+        uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
+        uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
+        if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);
+        hipLaunchKernelGGL(k_adj_relax, dim3((unsigned)grid_relax), dim3(RW), 0, S, fs.fields,
+                           (const uint32_t*)d_list, (const uint32_t*)d_lbits, (const uint32_t*)d_lfld,
+                           (const uint16_t*)d_code, (const double*)d_wA, (const double*)d_wB, (const double*)d_wC,
+                           (const double*)d_G, (const double*)T, (const double*)d_theta, (double*)d_lam,
+                           (uint8_t*)d_pend, (double*)d_maxdef, (uint32_t*)d_flags, mk_in, mk_out,
+                           (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle, opt.inner_sweeps,
+                           (unsigned long long*)d_cnt);
+        if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH) + 1], S);
+    };
     while (iters < opt.max_sweeps) {
         const int batch = opt.max_sweeps - iters < PASS_BATCH ? opt.max_sweeps - iters : PASS_BATCH;
-        for (int bb = 0; bb < batch; ++bb) {
-            const int p = iters + bb;
-            hipLaunchKernelGGL(k_adj_sched, dim3((unsigned)n_fields), dim3(256), 0, S, fs.fields, p > 0 ? 1 : 0,
-                               (const double*)d_step, (uint32_t*)d_flags, (const double*)d_maxdef, (double*)d_theta,
-                               (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_lfld, cnt + (p & 1), cnt + ((p + 1) & 1));
-            uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
-            uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
-            HIPCK(H, hipEventRecord(H->pev[2 * bb], S));
-            hipLaunchKernelGGL(k_adj_relax, dim3((unsigned)grid_relax), dim3(RW), 0, S, fs.fields,
-                               (const uint32_t*)d_list, (const uint32_t*)d_lbits, (const uint32_t*)d_lfld,
-                               (const uint16_t*)d_code, (const double*)d_wA, (const double*)d_wB, (const double*)d_wC,
-                               (const double*)d_G, (const double*)T, (const double*)d_theta, (double*)d_lam,
-                               (uint8_t*)d_pend, (double*)d_maxdef, (uint32_t*)d_flags, mk_in, mk_out,
-                               (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle, opt.inner_sweeps,
-                               (unsigned long long*)d_cnt);
-            HIPCK(H, hipEventRecord(H->pev[2 * bb + 1], S));
+        const bool graph = opt.graph && batch == PASS_BATCH;
+        if (graph) {
+            const int first = iters == 0 ? 1 : 0;
+            const std::string key = graph_key("adj", first, fs.fields, n_fields, d_step, d_flags, d_maxdef, d_theta,
+                                              d_list, d_lbits, d_lfld, d_count, d_marks, nunits, d_code, d_wA, d_wB,
+                                              d_wC, d_G, T, d_lam, d_pend, d_idle, opt.inner_sweeps, d_cnt, grid_relax);
+            HIPCK(H, hipEventRecord(H->ev2, S));
+            st = launch_captured(H, key, [&](int b, hipStream_t cs) { enqueue(first ? b : PASS_BATCH + b, false, cs); });
+            if (st != ALI_OK) return st;
+            HIPCK(H, hipEventRecord(H->ev3, S));
+        } else {
+            for (int bb = 0; bb < batch; ++bb) enqueue(iters + bb, true, S);
         }
         HIPCK(H, hipGetLastError());
         HIPCK(H, hipMemcpyAsync(H->host_count, d_idle, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
         HIPCK(H, hipStreamSynchronize(S));
-        for (int bb = 0; bb < batch; ++bb) {
+        if (graph) {
             float kms = 0.f;
-            HIPCK(H, hipEventElapsedTime(&kms, H->pev[2 * bb], H->pev[2 * bb + 1]));
+            HIPCK(H, hipEventElapsedTime(&kms, H->ev2, H->ev3));
             relax_ms += kms;
+        } else {
+            for (int bb = 0; bb < batch; ++bb) {
+                float kms = 0.f;
+                HIPCK(H, hipEventElapsedTime(&kms, H->pev[2 * ((iters + bb) % PASS_BATCH)],
+                                             H->pev[2 * ((iters + bb) % PASS_BATCH) + 1]));
+                relax_ms += kms;
+            }
         }
         iters += batch;
         if (*H->host_count) { converged = true; break; }

@@ -14,6 +14,7 @@ extern "C" void ali_default_options(ali_options* o) {
     o->ray_max_pts = 4096;
     o->arith = ALI_ARITH_MIXED;
     o->ray_sub = 8;
+    o->graph = 1;
 }
 
 extern "C" ali_status ali_create(ali_handle** out, int device, void* hip_stream) {
@@ -28,6 +29,7 @@ extern "C" ali_status ali_create(ali_handle** out, int device, void* hip_stream)
     if (hipSetDevice(device) != hipSuccess || hipEventCreate(&h->ev0) != hipSuccess ||
         hipEventCreate(&h->ev1) != hipSuccess || hipEventCreate(&h->ev2) != hipSuccess ||
         hipEventCreate(&h->ev3) != hipSuccess || hipEventCreate(&h->ev4) != hipSuccess ||
+        hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         hipHostMalloc((void**)&h->host_count, sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess ||
         hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
         ali_destroy(h);
@@ -47,6 +49,7 @@ extern "C" ali_status ali_destroy(ali_handle* h) {
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto& kv : h->bufs)
         if (kv.second.p) (void)hipFree(kv.second.p);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -54,6 +57,7 @@ extern "C" ali_status ali_destroy(ali_handle* h) {
     if (h->ev2) (void)hipEventDestroy(h->ev2);
     if (h->ev3) (void)hipEventDestroy(h->ev3);
     if (h->ev4) (void)hipEventDestroy(h->ev4);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (int k = 0; k < 2 * ALI_PASS_BATCH; ++k)
         if (h->pev[k]) (void)hipEventDestroy(h->pev[k]);
     if (h->host_count) (void)hipHostFree(h->host_count);

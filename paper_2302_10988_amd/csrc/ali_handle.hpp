@@ -16,11 +16,13 @@ constexpr int ALI_PASS_BATCH = 16;
 struct ali_handle {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;         // only records pass batches into graphs
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr;
     uint32_t* host_count = nullptr;           // pinned 4-byte readback slot
     hipEvent_t pev[2 * ALI_PASS_BATCH] = {};  // per-pass timing events of one batch
     int n_cu = 0;                             // compute units of the device
     std::map<const void*, int> grids;         // resident work-groups per kernel (grid-stride launches)
+    std::map<std::string, hipGraphExec_t> graphs;   // captured pass batches by argument signature
     std::string err;
     struct Buf { void* p = nullptr; size_t bytes = 0; };
     std::map<std::string, Buf> bufs;
@@ -65,6 +67,46 @@ inline int relax_grid(ali_handle* H, const void* kernel) {
     const int g = per_cu * H->n_cu;
     H->grids[kernel] = g;
     return g;
+}
+
+// Enqueue `enqueue(b)` for b = 0 .. PASS_BATCH-1 on the handle's stream as one captured
+// graph, instantiated once per signature `key` (every argument the kernels receive) and
+// replayed afterwards.
+// The batch is recorded on the handle's own capture stream (the caller's stream may be the
+// legacy default stream, which cannot be captured) and replayed on the caller's stream.
+template <class F>
+inline ali_status launch_captured(ali_handle* H, const std::string& key, F&& enqueue) {
+    hipGraphExec_t exec = nullptr;
+    auto it = H->graphs.find(key);
+    if (it != H->graphs.end()) {
+        exec = it->second;
+    } else {
+        hipGraph_t graph = nullptr;
+        HIPCK(H, hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int b = 0; b < PASS_BATCH; ++b) enqueue(b, H->cap_stream);
+        const hipError_t le = hipGetLastError();
+        HIPCK(H, hipStreamEndCapture(H->cap_stream, &graph));
+        if (le != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return H->fail(ALI_EDEVICE, std::string("launch during capture: ") + hipGetErrorString(le));
+        }
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return H->fail(ALI_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        H->graphs[key] = exec;
+    }
+    HIPCK(H, hipGraphLaunch(exec, H->stream));
+    return ALI_OK;
+}
+
+// signature of a pass batch: the pointer and scalar arguments, printed
+template <typename... A>
+inline std::string graph_key(const char* tag, A... a) {
+    std::string k(tag);
+    const unsigned long long v[] = {(unsigned long long)a...};
+    char buf[24];
+    for (unsigned long long x : v) { snprintf(buf, sizeof(buf), ":%llx", x); k += buf; }
+    return k;
 }
 
 inline ali_status set_device(ali_handle* H) {

@@ -600,32 +600,54 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     // pass list exit at once
     const int grid_relax = (int)(nunits < (int64_t)32 * H->n_cu ? nunits : (int64_t)32 * H->n_cu);
     uint32_t* cnt = (uint32_t*)d_count;
+    // one pass: schedule, then relax (events around the relax launch when timed)
+    auto enqueue = [&](int p, bool timed, hipStream_t S) {
+        hipLaunchKernelGGL((k_sched<real>), dim3((unsigned)n_fields), dim3(256), 0, S,
+                           (const FieldDev*)d_fields, p > 0 ? 1 : 0,
+                           (uint32_t*)d_flags, (real*)d_minrej, (real*)d_theta, (const real*)d_step,
+                           (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_lfld, cnt + (p & 1), cnt + ((p + 1) & 1));
+        uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
+        uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
+        if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);
+        hipLaunchKernelGGL((k_relax<real, mreal>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
+                           (const FieldDev*)d_fields, (const uint32_t*)d_list, (const uint32_t*)d_lbits,
+                           (const uint32_t*)d_lfld, (const MatDev<mreal>*)d_mats, d_mat_id, (const mreal*)d_geo,
+                           (const real*)d_fbt, opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
+                           (uint32_t*)d_flags, (real*)d_minrej, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)),
+                           (uint32_t*)d_idle, (unsigned long long*)d_upd);
+        if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH) + 1], S);
+    };
     while (iters < opt.max_sweeps) {
         const int batch = opt.max_sweeps - iters < PASS_BATCH ? opt.max_sweeps - iters : PASS_BATCH;
-        for (int b = 0; b < batch; ++b) {
-            const int p = iters + b;
-            hipLaunchKernelGGL((k_sched<real>), dim3((unsigned)n_fields), dim3(256), 0, S,
-                               (const FieldDev*)d_fields, p > 0 ? 1 : 0,
-                               (uint32_t*)d_flags, (real*)d_minrej, (real*)d_theta, (const real*)d_step,
-                               (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_lfld, cnt + (p & 1), cnt + ((p + 1) & 1));
-            uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
-            uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
-            HIPCK(H, hipEventRecord(H->pev[2 * b], S));
-            hipLaunchKernelGGL((k_relax<real, mreal>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
-                               (const FieldDev*)d_fields, (const uint32_t*)d_list, (const uint32_t*)d_lbits,
-                               (const uint32_t*)d_lfld, (const MatDev<mreal>*)d_mats, d_mat_id, (const mreal*)d_geo,
-                               (const real*)d_fbt, opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
-                               (uint32_t*)d_flags, (real*)d_minrej, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)),
-                               (uint32_t*)d_idle, (unsigned long long*)d_upd);
-            HIPCK(H, hipEventRecord(H->pev[2 * b + 1], S));
+        const bool graph = opt.graph && batch == PASS_BATCH;
+        if (graph) {
+            // the first batch differs from the others only in the first pass (no advance)
+            const int first = iters == 0 ? 1 : 0;
+            const std::string key = graph_key("relax", first, (const void*)&k_relax<real, mreal>, d_fields, n_fields,
+                                              d_flags, d_minrej, d_theta, d_step, d_list, d_lbits, d_lfld, d_count,
+                                              d_marks, nunits, d_mats, d_mat_id, d_geo, d_fbt, opt.src_box_radius,
+                                              opt.inner_sweeps, d_T, d_idle, d_upd, grid_relax);
+            HIPCK(H, hipEventRecord(H->ev2, S));
+            st = launch_captured(H, key, [&](int b, hipStream_t cs) { enqueue(first ? b : PASS_BATCH + b, false, cs); });
+            if (st != ALI_OK) return st;
+            HIPCK(H, hipEventRecord(H->ev3, S));
+        } else {
+            for (int b = 0; b < batch; ++b) enqueue(iters + b, true, S);
         }
         HIPCK(H, hipGetLastError());
         HIPCK(H, hipMemcpyAsync(H->host_count, d_idle, sizeof(uint32_t), hipMemcpyDeviceToHost, S));
         HIPCK(H, hipStreamSynchronize(S));
-        for (int b = 0; b < batch; ++b) {
+        if (graph) {
             float kms = 0.f;
-            HIPCK(H, hipEventElapsedTime(&kms, H->pev[2 * b], H->pev[2 * b + 1]));
+            HIPCK(H, hipEventElapsedTime(&kms, H->ev2, H->ev3));
             relax_ms += kms;
+        } else {
+            for (int b = 0; b < batch; ++b) {
+                float kms = 0.f;
+                HIPCK(H, hipEventElapsedTime(&kms, H->pev[2 * ((iters + b) % PASS_BATCH)],
+                                             H->pev[2 * ((iters + b) % PASS_BATCH) + 1]));
+                relax_ms += kms;
+            }
         }
         iters += batch;
         if (*H->host_count) { converged = true; break; }
@@ -752,4 +774,36 @@ extern "C" ali_status ali_solve_batch(ali_handle* h, const ali_medium* media, in
                                       float* d_T, ali_solve_stats* stats) {
     if (!h) return ALI_EINVAL;
     return solve_dispatch<float, float>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, opt, d_T, stats);
+}
+
+// candidate schedules of the autotuner: (band_cells, inner_sweeps)
+static const int TUNE_BAND[ALI_TUNE_CANDIDATES] = {1, 1, 1, 2, 2, 3};
+static const int TUNE_INNER[ALI_TUNE_CANDIDATES] = {1, 2, 4, 2, 4, 4};
+
+extern "C" ali_status ali_autotune_batch(ali_handle* h, const ali_medium* media, int32_t n_media,
+                                         const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
+                                         const float* d_orient, const ali_node* srcs, ali_options* opt,
+                                         float* d_T, double* ms_out) {
+    if (!h) return ALI_EINVAL;
+    if (!opt) return h->fail(ALI_EINVAL, "opt is NULL");
+    ali_options best = *opt;
+    double best_ms = INFINITY;
+    for (int c = 0; c < ALI_TUNE_CANDIDATES; ++c) {
+        ali_options o = *opt;
+        o.band_cells = TUNE_BAND[c];
+        o.inner_sweeps = TUNE_INNER[c];
+        double ms = INFINITY;
+        // two runs: the first may build the candidate's graphs
+        for (int rep = 0; rep < 2; ++rep) {
+            ali_solve_stats st{};
+            const ali_status s = solve_dispatch<float, float>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs,
+                                                              &o, d_T, &st);
+            if (s != ALI_OK) return s;
+            ms = st.ms;
+        }
+        if (ms_out) ms_out[c] = ms;
+        if (ms < best_ms) { best_ms = ms; best = o; }
+    }
+    *opt = best;
+    return ALI_OK;
 }
