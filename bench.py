@@ -47,7 +47,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector
 # WRITE_SIZE; each scaled by the same counter on a 256 MiB device copy in the same
 # program), per launch, for the kernel sources with this hash.  Reported as null once the
 # sources differ.
-TRAFFIC = {"sources_sha256_16": None, "fetch_bytes_per_launch": None, "write_bytes_per_launch": None}
+TRAFFIC = {"sources_sha256_16": "b1cd6a0ee573931b", "fetch_bytes_per_launch": 13.727e6,
+           "write_bytes_per_launch": 1.355e6}
 
 
 def kernel_sources_hash():
