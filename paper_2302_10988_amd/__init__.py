@@ -363,3 +363,66 @@ class Solver:
         self._check(st)
         best = {k: getattr(opt, k) for k, _ in opt._fields_}
         return best, {c: ms[k] for k, c in enumerate(_lib.TUNE_CANDIDATES)}
+
+
+def receiver_times(solver, h, mats, mat_id, orient, sources, receivers, **opts):
+    """Travel times [n_src, n_rec] (float32) at the receivers as a differentiable function
+    of the orientation [nz, nx] (float32 device tensor).  The backward pass runs the
+    adjoint kernels (the forward fields are solved again inside it, not stored)."""
+    return _ReceiverTimes.apply(orient, solver, h, mats, mat_id, tuple(map(tuple, sources)),
+                                tuple(map(tuple, receivers)), opts)
+
+
+def bilinear_orientation(solver, ctrl, nz, nx):
+    """Orientation [nz, nx] from control values ctrl [ncz, ncx] spanning the grid corner to
+    corner (linear in each direction), differentiable in ctrl (backward: the transpose)."""
+    return _Bilinear.apply(ctrl, solver, int(nz), int(nx))
+
+
+def _autograd():
+    import torch
+
+    class ReceiverTimes(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, orient, solver, h, mats, mat_id, sources, receivers, opts):
+            T, _ = solver.solve(h, mats, mat_id, orient, sources, **opts)
+            rows = torch.tensor([r[1] for r in receivers], device=T.device)
+            cols = torch.tensor([r[0] for r in receivers], device=T.device)
+            ctx.save_for_backward(orient)
+            ctx.args = (solver, h, mats, mat_id, sources, receivers, opts)
+            return T[:, rows, cols].contiguous()
+
+        @staticmethod
+        def backward(ctx, grad):
+            (orient,) = ctx.saved_tensors
+            solver, h, mats, mat_id, sources, receivers, opts = ctx.args
+            dth, _ = solver.adjoint(h, mats, mat_id, orient, sources, receivers,
+                                    grad.to(torch.float32).contiguous(), **opts)
+            return dth, None, None, None, None, None, None, None
+
+    class Bilinear(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, ctrl, solver, nz, nx):
+            ctx.args = (solver, ctrl.shape[0], ctrl.shape[1])
+            return solver.bilinear(ctrl.contiguous(), nz, nx)
+
+        @staticmethod
+        def backward(ctx, grad):
+            solver, ncz, ncx = ctx.args
+            return solver.bilinear_transpose(grad.contiguous(), ncz, ncx), None, None, None
+
+    return ReceiverTimes, Bilinear
+
+
+class _Lazy:
+    """Defer importing torch until a differentiable function is first used."""
+
+    def __init__(self, k):
+        self.k = k
+
+    def apply(self, *a):
+        return _autograd()[self.k].apply(*a)
+
+
+_ReceiverTimes, _Bilinear = _Lazy(0), _Lazy(1)
+__all__ += ["receiver_times", "bilinear_orientation"]

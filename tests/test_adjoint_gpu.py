@@ -242,3 +242,30 @@ def test_forward_is_exact_fixed_point_under_every_schedule(solver, band, inner):
                                    band_cells=band, inner_sweeps=inner)
             assert st["forward"]["converged"] == 1 and st["converged"] == 1
             assert st["choice_mismatches"] == 0
+
+
+def test_autograd_matches_misfit_gradient(solver):
+    # loss built with torch ops on the differentiable receiver times and control grid:
+    # its gradient must equal the fused misfit entry point's (same kernels, same sums)
+    import torch
+    from paper_2302_10988_amd import bilinear_orientation, receiver_times
+    m = sm.adjoint_grid(seed=2, n_src=8, n_rec=8)
+    mid = torch.from_numpy(m.mat_id).cuda()
+    ctrl = torch.from_numpy(m.controls).float().cuda().requires_grad_(True)
+    obs = torch.full((8, 8), 2e-6, device="cuda")
+    ori = bilinear_orientation(solver, ctrl, m.nz, m.nx)
+    Tr = receiver_times(solver, m.h, m.mats, mid, ori, m.sources, m.receivers)
+    loss = 0.5 * ((Tr.double() - obs.double()) ** 2).sum()
+    loss.backward()
+    with torch.no_grad():
+        ori2 = solver.bilinear(ctrl.detach(), m.nz, m.nx)
+        l2, tr2, dth, _ = solver.misfit_gradient(m.h, m.mats, mid, ori2, m.sources, m.receivers, obs)
+        g2 = solver.bilinear_transpose(dth, 32, 32)
+    gd = (ctrl.grad - g2).abs().max().item() / g2.abs().max().item()
+    print("autograd: loss %.9e fused %.9e, control gradient max diff / max %.3g"
+          % (loss.item(), l2.item(), gd))
+    assert torch.equal(Tr.detach(), tr2)
+    # the fused call forms the residuals from float64 times, the autograd graph from the
+    # float32 receiver times: the losses differ by the rounding of T (~1e-7 relative)
+    assert abs(loss.item() - l2.item()) <= 1e-5 * abs(l2.item())
+    assert gd <= 1e-5
