@@ -130,7 +130,7 @@ def main():
     line = {"metric": "node-updates/s & batched forward+adjoint field solves/s at ≤1e-4 rel err",
             "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32 wavefront math, f64 travel times and derivatives", "data": "synthetic"}
+            "dtype": "f32 wavefront math and adjoint pull weights; f64 travel times, lambda and gradient sums", "data": "synthetic"}
 
     if args.workload == "weld512x64":
         m = sm.weld_multi()

@@ -43,6 +43,16 @@ constexpr uint16_t CODE_NONE = make_code(K_NONE, NO_SLOT, NO_SLOT, NO_SLOT);
 
 struct StGeo { int sa, sb, sc, bx, bz, cx, cz, k1, k2; };
 
+// What the relaxation of lambda reads of a node D: dU_D/dtau at its A, B and C supports
+// and its code, in one aligned record.  The weights are stored in the math type: float32
+// under mixed arithmetic (whose travel times, and so the weights derived from them, carry
+// float32-level error already), float64 otherwise.
+template <typename wreal> struct alignas(4 * sizeof(wreal)) AdjW {
+    wreal a, b, c;
+    uint32_t code;
+};
+static_assert(sizeof(AdjW<float>) == 16 && sizeof(AdjW<double>) == 32, "pull records are whole vectors");
+
 template <int S> __device__ __forceinline__ StGeo geo_of() {
     using St = Stencil<S>;
     return StGeo{St::sa, St::sb, St::sc, St::bx, St::bz, St::cx, St::cz, St::k1, St::k2};
@@ -106,8 +116,7 @@ __global__ void __launch_bounds__(NTHREADS)
 k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal>* __restrict__ mats_all,
            const uint8_t* __restrict__ mat_id_all, const oreal* __restrict__ orient_all,
            const mreal* __restrict__ geo_all, const double* __restrict__ fbt_all, int R,
-           const double* __restrict__ T, uint16_t* __restrict__ code, double* __restrict__ wA,
-           double* __restrict__ wB, double* __restrict__ wC, double* __restrict__ wT,
+           const double* __restrict__ T, AdjW<mreal>* __restrict__ W, double* __restrict__ wT,
            unsigned long long* __restrict__ mismatches) {
     __shared__ double lt[LH * LSTRIDE];
     const uint32_t unit = blockIdx.x;
@@ -120,7 +129,7 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
     const MatDev<mreal>* __restrict__ mats = mats_all + fd.mat_off;
     const uint8_t* __restrict__ mat_id = mat_id_all + fd.node_off;
     const oreal* __restrict__ orient = orient_all + fd.node_off;
-    const mreal* __restrict__ geo = geo_all + 2 * fd.node_off;
+    const mreal* __restrict__ geo = geo_all + GEO_N * fd.node_off;
     const double* __restrict__ fbt = fbt_all + 4 * fd.node_off;
     const double inf = dinf<double>();
     const int tid = threadIdx.x;
@@ -155,7 +164,7 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
         }
     } else if (tD < inf) {
         NodeConst<mreal, double> nc;
-        load_node_const<double, mreal>(nc, p, mats, mat_id, geo, fbt);
+        load_node_const<double, mreal>(nc, p, geo, fbt);
         double tt[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) tt[k] = lt[me + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]];
@@ -190,26 +199,30 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
             cd = make_code(K_FALLBACK, (unsigned)fb_slot_rt(k), NO_SLOT, NO_SLOT);
         }
     }
-    code[q] = cd;
-    wA[q] = a; wB[q] = b; wC[q] = c; wT[q] = t;
+    AdjW<mreal> w;
+    w.a = (mreal)a; w.b = (mreal)b; w.c = (mreal)c;
+    w.code = cd;
+    W[q] = w;
+    wT[q] = t;
 }
 
 // ---------------------------------------------------------------------------------------
 // step 3: relaxation of lambda, one work-group per active (tile, field)
 // ---------------------------------------------------------------------------------------
 // contribution to lambda at the node in LDS slot `me` from its 12 diamond neighbours
+template <typename wreal>
 __device__ __forceinline__ double pull_lambda(double gsum, int me, const double* __restrict__ ll,
-                                              const uint16_t* __restrict__ lc, const double* __restrict__ la,
-                                              const double* __restrict__ lb, const double* __restrict__ lcw) {
+                                              const uint16_t* __restrict__ lc, const wreal* __restrict__ la,
+                                              const wreal* __restrict__ lb, const wreal* __restrict__ lcw) {
     double s = gsum;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
         const int o = me + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k];
         const unsigned cd = lc[o];
         const unsigned tgt = 11u - (unsigned)k;       // this node seen from the neighbour
-        if ((cd & 0xFu) == tgt) s += ll[o] * la[o];
-        else if (((cd >> 4) & 0xFu) == tgt) s += ll[o] * lb[o];
-        else if (((cd >> 8) & 0xFu) == tgt) s += ll[o] * lcw[o];
+        if ((cd & 0xFu) == tgt) s += ll[o] * (double)la[o];
+        else if (((cd >> 4) & 0xFu) == tgt) s += ll[o] * (double)lb[o];
+        else if (((cd >> 8) & 0xFu) == tgt) s += ll[o] * (double)lcw[o];
     }
     return s;
 }
@@ -220,23 +233,26 @@ __device__ __forceinline__ double pull_lambda(double gsum, int me, const double*
 // the tile remembers its largest pending time.  A changed lambda marks the node's
 // supports: inside the tile for the next sweep, in a neighbouring tile through that
 // tile's node mask for the next pass.
+template <typename wreal>
 __global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
-k_adj_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ list,
-            const uint32_t* __restrict__ lbits, const uint32_t* __restrict__ lfld, const uint16_t* __restrict__ code,
-            const double* __restrict__ wA, const double* __restrict__ wB, const double* __restrict__ wC,
+k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W,
             const double* __restrict__ G, const double* __restrict__ T, const double* __restrict__ theta,
             double* __restrict__ lam, uint8_t* __restrict__ pend, double* __restrict__ maxdef,
             uint32_t* __restrict__ flags, uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
             const uint32_t* __restrict__ count, uint32_t* __restrict__ idle, int inner,
             unsigned long long* __restrict__ counters) {
     __shared__ double ll[LH * LSTRIDE];
-    __shared__ double la[LH * LSTRIDE], lb[LH * LSTRIDE], lcw[LH * LSTRIDE];
+    __shared__ wreal la[LH * LSTRIDE], lb[LH * LSTRIDE], lcw[LH * LSTRIDE];
     __shared__ uint16_t lc[LH * LSTRIDE];
     __shared__ uint8_t dnext[NTHREADS];
     __shared__ uint8_t lpend[NTHREADS];
     __shared__ uint16_t clist[NTHREADS];
     __shared__ uint32_t omask[9][NODE_WORDS];
+    __shared__ uint32_t touched[NODE_WORDS];      // nodes whose lambda changed in this visit
 
+    // the first entry is read together with the list length (in bounds: the grid never
+    // exceeds the list's capacity; the entry is used only if it is live)
+    PassItem pi = list[blockIdx.x];
     const uint32_t n_units = *count;
     if (n_units == 0u) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *idle = 1u;
@@ -246,49 +262,71 @@ k_adj_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ li
         atomicAdd(&counters[2], 1ull);
         atomicAdd(&counters[3], (unsigned long long)n_units);
     }
-    const int lane = threadIdx.x;
     for (uint32_t item = blockIdx.x; item < n_units; item += gridDim.x) {
-    const uint32_t unit = list[item];
-    const uint32_t bits = lbits[item];
-    const int f = (int)lfld[item];
-    const FieldDev fd = fields[f];
-    const int nx = fd.nx, nz = fd.nz, ntx = fd.ntx;
-    const int tile = (int)(unit - fd.unit_off);
-    const int tx = tile % ntx, tz = tile / ntx;
+    if (item != blockIdx.x) pi = list[item];
+    // opaque inside the item loop, so that per-lane staging offsets are not hoisted out of
+    // it and held in registers through the sweeps
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));
+    const uint32_t unit = pi.unit;
+    const uint32_t bits = pi.bits;
+    const int f = pi.f;
+    const int nx = pi.nx, nz = pi.nz, tx = pi.tx, tz = pi.tz;
+    const int ntx = (nx + TX - 1) / TX;
     const int i0 = tx * TX, j0 = tz * TZ;
-    const int64_t fo = fd.t_off;
+    const int64_t fo = pi.t_off;
 
-    for (int q = lane; q < LW * LH; q += RW) {
+    // stage the tile and its halo: every load is issued before the first store to LDS
+    constexpr int SQ = (LW * LH + RW - 1) / RW;
+    double sl[SQ];
+    AdjW<wreal> sw[SQ];
+#pragma unroll
+    for (int k = 0; k < SQ; ++k) {
+        const int q = lane + RW * k;
         const int li = q % LW, lj = q / LW;
         const int gi = i0 - HALO + li, gj = j0 - HALO + lj;
-        const int o = lj * LSTRIDE + li;
-        if (gi >= 0 && gj >= 0 && gi < nx && gj < nz) {
+        sl[k] = 0.0;
+        sw[k].a = wreal(0); sw[k].b = wreal(0); sw[k].c = wreal(0);
+        sw[k].code = CODE_NONE;
+        if (q < LW * LH && gi >= 0 && gj >= 0 && gi < nx && gj < nz) {
             const int64_t p = fo + (int64_t)gj * nx + gi;
-            ll[o] = lam[p];
-            lc[o] = code[p];
-            la[o] = wA[p]; lb[o] = wB[p]; lcw[o] = wC[p];
-        } else {
-            ll[o] = 0.0;
-            lc[o] = CODE_NONE;
-            la[o] = 0.0; lb[o] = 0.0; lcw[o] = 0.0;
+            sl[k] = lam[p];
+            sw[k] = W[p];
         }
     }
-    for (int q = lane; q < 9 * NODE_WORDS; q += RW) omask[q / NODE_WORDS][q % NODE_WORDS] = 0u;
-    for (int q = lane; q < NTHREADS; q += RW) dnext[q] = 0;
     uint32_t mk = 0u;
     if (lane < NODE_WORDS) {
         mk = marks_in[(int64_t)unit * NODE_WORDS + lane];
         if (mk) marks_in[(int64_t)unit * NODE_WORDS + lane] = 0u;
     }
     const double th = theta[f];
-    unsigned dmask = 0u, vmask = 0u;
-#pragma unroll 1
+    uint8_t pdv[NPL];
+#pragma unroll
+    for (int q = 0; q < NPL; ++q) {
+        const int node = lane + RW * q;
+        const int gi = i0 + node % TX, gj = j0 + node / TX;
+        pdv[q] = (gi < nx && gj < nz) ? pend[fo + (int64_t)gj * nx + gi] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < SQ; ++k) {
+        const int q = lane + RW * k;
+        if (q < LW * LH) {
+            const int o = (q / LW) * LSTRIDE + q % LW;
+            ll[o] = sl[k]; lc[o] = (uint16_t)sw[k].code; la[o] = sw[k].a; lb[o] = sw[k].b; lcw[o] = sw[k].c;
+        }
+    }
+    for (int q = lane; q < 9 * NODE_WORDS; q += RW) omask[q / NODE_WORDS][q % NODE_WORDS] = 0u;
+    for (int q = lane; q < NTHREADS; q += RW) dnext[q] = 0;
+    if (lane < NODE_WORDS) touched[lane] = 0u;
+    unsigned dmask = 0u, vmask = 0u, pmask = 0u;   // pmask: pending on entry
+#pragma unroll
     for (int q = 0; q < NPL; ++q) {
         const int node = lane + RW * q;
         const int gi = i0 + node % TX, gj = j0 + node / TX;
         const bool valid = gi < nx && gj < nz;
-        const uint8_t pd = valid ? pend[fo + (int64_t)gj * nx + gi] : 0;
+        const uint8_t pd = pdv[q];
         lpend[node] = pd;
+        pmask |= pd ? 1u << q : 0u;
         const bool marked = (__shfl(mk, (node >> 5)) >> (node & 31)) & 1u;
         vmask |= valid ? 1u << q : 0u;
         if (valid && ((bits & TF_SELF) || marked || pd)) dmask |= 1u << q;
@@ -325,6 +363,7 @@ k_adj_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ li
                     const double v = pull_lambda(G[p], nme, ll, lc, la, lb, lcw);
                     if (v != ll[nme]) {
                         ll[nme] = v;
+                        atomicOr(&touched[node >> 5], 1u << (node & 31));
                         // lambda flows into this node's supports
                         const unsigned cd = lc[nme];
 #pragma unroll
@@ -377,10 +416,10 @@ k_adj_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ li
         const int gi = i0 + lx, gj = j0 + lz;
         if (gi >= nx || gj >= nz) continue;
         const int64_t p = fo + (int64_t)gj * nx + gi;
-        const double fin = ll[(lz + HALO) * LSTRIDE + (lx + HALO)];
-        if (fin != lam[p]) lam[p] = fin;          // only this visit writes the tile's nodes
+        // only this visit writes the tile's nodes: changed values and pending states
+        if ((touched[node >> 5] >> (node & 31)) & 1u) lam[p] = ll[(lz + HALO) * LSTRIDE + (lx + HALO)];
         const uint8_t pd = lpend[node];
-        if (pd != pend[p]) pend[p] = pd;
+        if ((pd != 0) != (((pmask >> q) & 1u) != 0u)) pend[p] = pd;
         if (pd) { const double tp = T[p]; dk = tp > dk ? tp : dk; }
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -395,7 +434,7 @@ k_adj_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ li
             const uint32_t w = omask[q / NODE_WORDS][q % NODE_WORDS];
             if (!w) continue;
             const int o = q / NODE_WORDS;
-            const int64_t u2 = (int64_t)fd.unit_off + (int64_t)(tz + o / 3 - 1) * ntx + (tx + o % 3 - 1);
+            const int64_t u2 = (int64_t)unit + (int64_t)(o / 3 - 1) * ntx + (o % 3 - 1);
             atomicOr(&marks_out[u2 * NODE_WORDS + q % NODE_WORDS], w);
             atomicOr(&flags[u2], TF_MARK);
         }
@@ -408,80 +447,13 @@ k_adj_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ li
     }
 }
 
-// Scheduler of one adjoint pass, one work-group per field: lower the threshold by its
-// step (not before the first pass); if no tile is flagged or holds a pending node at or
-// above the threshold, lower it to the largest pending time; then list the active tiles.
-__global__ void __launch_bounds__(256)
+// Scheduler of one adjoint pass (descending thresholds), one work-group per field; the
+// tile keys are the largest pending times (the relaxation rewrites them).
+__global__ void __launch_bounds__(SCHED_T)
 k_adj_sched(const FieldDev* __restrict__ fields, int advance, const double* __restrict__ step,
-            uint32_t* __restrict__ flags, const double* __restrict__ maxdef, double* __restrict__ theta,
-            uint32_t* __restrict__ list, uint32_t* __restrict__ lbits, uint32_t* __restrict__ lfld,
-            uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next) {
-    const int f = blockIdx.x;
-    const uint32_t uoff = fields[f].unit_off;
-    const int ntiles = fields[f].ntx * fields[f].ntz;
-    const int tid = threadIdx.x;
-    const double ninf = -dinf<double>();
-    __shared__ double red_m[256];
-    __shared__ unsigned red_c[256];
-    __shared__ double th_s;
-    __shared__ uint32_t base_s;
-    if (f == 0 && tid == 0) *cnt_next = 0u;
-    uint32_t* fl = flags + uoff;
-    const double* md = maxdef + uoff;
-    double th = theta[f];
-    if (advance) th -= step[f];
-    unsigned act = 0;
-    double m = ninf;
-    for (int t = tid; t < ntiles; t += 256) {
-        const double v = md[t];
-        act |= (fl[t] != 0u || (v > ninf && v >= th)) ? 1u : 0u;
-        m = v > m ? v : m;
-    }
-    red_m[tid] = m;
-    red_c[tid] = act;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) {
-            red_m[tid] = red_m[tid + w] > red_m[tid] ? red_m[tid + w] : red_m[tid];
-            red_c[tid] |= red_c[tid + w];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        if (!red_c[0] && red_m[0] > ninf && red_m[0] < th) th = red_m[0];   // idle: jump
-        th_s = th;
-        theta[f] = th;
-    }
-    __syncthreads();
-    th = th_s;
-    unsigned mine = 0;
-    for (int t = tid; t < ntiles; t += 256) {
-        const double v = md[t];
-        mine += (fl[t] != 0u || (v > ninf && v >= th)) ? 1u : 0u;
-    }
-    __syncthreads();
-    red_c[tid] = mine;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const unsigned v = tid >= o ? red_c[tid - o] : 0u;
-        __syncthreads();
-        red_c[tid] += v;
-        __syncthreads();
-    }
-    if (tid == 255) base_s = red_c[255] ? atomicAdd(cnt_cur, red_c[255]) : 0u;
-    __syncthreads();
-    uint32_t pos = base_s + red_c[tid] - mine;
-    for (int t = tid; t < ntiles; t += 256) {
-        const uint32_t b = fl[t];
-        const double v = md[t];
-        if (b != 0u || (v > ninf && v >= th)) {
-            fl[t] = 0u;
-            list[pos] = uoff + (uint32_t)t;
-            lbits[pos] = b;
-            lfld[pos] = (uint32_t)f;
-            ++pos;
-        }
-    }
+            uint32_t* __restrict__ flags, double* __restrict__ maxdef, double* __restrict__ theta,
+            PassItem* __restrict__ list, uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next) {
+    schedule_field<true, double>(fields, advance, step, flags, maxdef, theta, list, cnt_cur, cnt_next);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -533,15 +505,16 @@ __global__ void k_adj_loss(const double* __restrict__ lossf, const int* __restri
 // step 4: gradient
 // ---------------------------------------------------------------------------------------
 // nodes of one medium, summed over its fields f0 .. f1 - 1 in field order
+template <typename wreal>
 __global__ void k_adj_grad(int64_t N, int f0, int f1, const FieldDev* __restrict__ fields,
-                           const uint16_t* __restrict__ code, const double* __restrict__ wT,
+                           const AdjW<wreal>* __restrict__ W, const double* __restrict__ wT,
                            const double* __restrict__ lam, double* __restrict__ dth) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     double s = 0.0;
     for (int f = f0; f < f1; ++f) {
         const int64_t q = fields[f].t_off + p;
-        const int kind = code[q] >> 12;
+        const int kind = (int)(W[q].code >> 12);
         if (kind == K_STENCIL || kind == K_FALLBACK) s += lam[q] * wT[q];
     }
     dth[p] = s;
@@ -624,11 +597,9 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     HIPCK(H, hipEventRecord(H->ev4, S));
     const int64_t nunits = fs.n_units;
 
-    void *d_code, *d_wA, *d_wB, *d_wC, *d_wT, *d_lam, *d_G, *d_dacc, *d_box, *d_lossf, *d_rec, *d_first;
-    void *d_flags, *d_list, *d_lbits, *d_lfld, *d_count, *d_cnt, *d_pend, *d_maxdef, *d_theta, *d_step, *d_idle, *d_marks;
-    if (!H->scratch("a_code", sizeof(uint16_t) * NF, &d_code) ||
-        !H->scratch("a_wA", sizeof(double) * NF, &d_wA) || !H->scratch("a_wB", sizeof(double) * NF, &d_wB) ||
-        !H->scratch("a_wC", sizeof(double) * NF, &d_wC) || !H->scratch("a_wT", sizeof(double) * NF, &d_wT) ||
+    void *d_W, *d_wT, *d_lam, *d_G, *d_dacc, *d_box, *d_lossf, *d_rec, *d_first;
+    void *d_flags, *d_list, *d_count, *d_cnt, *d_pend, *d_maxdef, *d_theta, *d_step, *d_idle, *d_marks;
+    if (!H->scratch("a_w", sizeof(AdjW<mreal>) * NF, &d_W) || !H->scratch("a_wT", sizeof(double) * NF, &d_wT) ||
         !H->scratch("a_lam", sizeof(double) * NF, &d_lam) || !H->scratch("a_G", sizeof(double) * NF, &d_G) ||
         !H->scratch("a_pend", sizeof(uint8_t) * NF, &d_pend) ||
         !H->scratch("a_dth", sizeof(double) * med_nodes, &d_dacc) ||
@@ -640,9 +611,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
         !H->scratch("a_rec", sizeof(int2) * n_recv_total, &d_rec) ||
         !H->scratch("a_flags", sizeof(uint32_t) * nunits, &d_flags) ||
         !H->scratch("a_maxdef", sizeof(double) * nunits, &d_maxdef) ||
-        !H->scratch("a_list", sizeof(uint32_t) * nunits, &d_list) ||
-        !H->scratch("a_lbits", sizeof(uint32_t) * nunits, &d_lbits) ||
-        !H->scratch("a_lfld", sizeof(uint32_t) * nunits, &d_lfld) ||
+        !H->scratch("a_list", sizeof(PassItem) * nunits, &d_list) ||
         !H->scratch("a_count", 2 * sizeof(uint32_t), &d_count) ||
         !H->scratch("a_idle", sizeof(uint32_t), &d_idle) ||
         !H->scratch("a_marks", sizeof(uint32_t) * 2 * NODE_WORDS * nunits, &d_marks) ||
@@ -670,8 +639,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     const unsigned gNF = (unsigned)((NF + B - 1) / B);
     hipLaunchKernelGGL((k_adj_prep<mreal, oreal>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
                        fs.fields, n_fields, fs.mats, d_mat_id, d_orient, fs.geo, fs.fbt, opt.src_box_radius,
-                       (const double*)T, (uint16_t*)d_code, (double*)d_wA, (double*)d_wB, (double*)d_wC,
-                       (double*)d_wT, (unsigned long long*)d_cnt + 1);
+                       (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (unsigned long long*)d_cnt + 1);
     HIPCK(H, hipGetLastError());
     hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_G, NF, 0.0);
     hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_lam, NF, 0.0);
@@ -693,15 +661,14 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     const int grid_relax = (int)(nunits < (int64_t)32 * H->n_cu ? nunits : (int64_t)32 * H->n_cu);
     uint32_t* cnt = (uint32_t*)d_count;
     auto enqueue = [&](int p, bool timed, hipStream_t S) {
-        hipLaunchKernelGGL(k_adj_sched, dim3((unsigned)n_fields), dim3(256), 0, S, fs.fields, p > 0 ? 1 : 0,
-                           (const double*)d_step, (uint32_t*)d_flags, (const double*)d_maxdef, (double*)d_theta,
-                           (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_lfld, cnt + (p & 1), cnt + ((p + 1) & 1));
+        hipLaunchKernelGGL(k_adj_sched, dim3((unsigned)n_fields), dim3(SCHED_T), 0, S, fs.fields, p > 0 ? 1 : 0,
+                           (const double*)d_step, (uint32_t*)d_flags, (double*)d_maxdef, (double*)d_theta,
+                           (PassItem*)d_list, cnt + (p & 1), cnt + ((p + 1) & 1));
         uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
         uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);
-        hipLaunchKernelGGL(k_adj_relax, dim3((unsigned)grid_relax), dim3(RW), 0, S, fs.fields,
-                           (const uint32_t*)d_list, (const uint32_t*)d_lbits, (const uint32_t*)d_lfld,
-                           (const uint16_t*)d_code, (const double*)d_wA, (const double*)d_wB, (const double*)d_wC,
+        hipLaunchKernelGGL(k_adj_relax<mreal>, dim3((unsigned)grid_relax), dim3(RW), 0, S,
+                           (const PassItem*)d_list, (const AdjW<mreal>*)d_W,
                            (const double*)d_G, (const double*)T, (const double*)d_theta, (double*)d_lam,
                            (uint8_t*)d_pend, (double*)d_maxdef, (uint32_t*)d_flags, mk_in, mk_out,
                            (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle, opt.inner_sweeps,
@@ -713,9 +680,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
         const bool graph = opt.graph && batch == PASS_BATCH;
         if (graph) {
             const int first = iters == 0 ? 1 : 0;
-            const std::string key = graph_key("adj", first, fs.fields, n_fields, d_step, d_flags, d_maxdef, d_theta,
-                                              d_list, d_lbits, d_lfld, d_count, d_marks, nunits, d_code, d_wA, d_wB,
-                                              d_wC, d_G, T, d_lam, d_pend, d_idle, opt.inner_sweeps, d_cnt, grid_relax);
+            const std::string key = graph_key("adj", first, (const void*)&k_adj_relax<mreal>, fs.fields, n_fields, d_step, d_flags, d_maxdef, d_theta,
+                                              d_list, d_count, d_marks, nunits, d_W, d_G, T, d_lam, d_pend, d_idle, opt.inner_sweeps, d_cnt, grid_relax);
             HIPCK(H, hipEventRecord(H->ev2, S));
             st = launch_captured(H, key, [&](int b, hipStream_t cs) { enqueue(first ? b : PASS_BATCH + b, false, cs); });
             if (st != ALI_OK) return st;
@@ -744,9 +710,9 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
 
     for (int m = 0; m < n_media; ++m) {
         const int64_t N = (int64_t)media[m].grid.nx * media[m].grid.nz;
-        hipLaunchKernelGGL(k_adj_grad, dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S, N,
+        hipLaunchKernelGGL(k_adj_grad<mreal>, dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S, N,
                            fs.medium_first_field[m], fs.medium_first_field[m + 1], fs.fields,
-                           (const uint16_t*)d_code, (const double*)d_wT, (const double*)d_lam,
+                           (const AdjW<mreal>*)d_W, (const double*)d_wT, (const double*)d_lam,
                            (double*)d_dacc + media[m].node_offset);
     }
     hipLaunchKernelGGL(k_adj_box, dim3((unsigned)n_fields), dim3(256), 0, S, fs.fields, opt.src_box_radius,

@@ -181,8 +181,8 @@ __device__ __forceinline__ void member_candidate(const NodeConst<mreal, real>& n
 // One stencil pair with compile-time geometry.  The two members order the same three
 // points (member 1: B = P, C = Q; member 2: B = Q, C = P), so only one of them can satisfy
 // tau_A < tau_B <= tau_C unless tau_P == tau_Q; the admissible member's geometry is picked
-// by selects, so every lane runs the same instructions.  A tie evaluates member 2 as well,
-// after member 1 (table order).
+// by selects, so the lanes of a wave run the same instructions.  A tie evaluates member 2
+// as well, after member 1 (table order).
 template <typename mreal, typename real, int PAIR>
 __device__ __forceinline__ void eval_pair(const NodeConst<mreal, real>& n, const real (&t)[12],
                                           Best<real>& best, real& minU) {
@@ -202,6 +202,9 @@ __device__ __forceinline__ void eval_pair(const NodeConst<mreal, real>& n, const
     const int8_t g[6] = {(int8_t)(m1 ? S1::bx : S2::bx), (int8_t)(m1 ? S1::bz : S2::bz),
                          (int8_t)(m1 ? S1::cx : S2::cx), (int8_t)(m1 ? S1::cz : S2::cz),
                          (int8_t)(m1 ? S1::k1 : S2::k1), (int8_t)(m1 ? S1::k2 : S2::k2)};
+    // a pair that no lane of the wave can use is skipped as a whole (wave-uniform branch;
+    // lanes with ok == false contribute nothing through the selects either way)
+    if (__ballot(ok) == 0ull) return;
     member_candidate<mreal, real>(n, g, tA, tB, tC, score, ok, S1::cls, ks, m1 ? 2 * PAIR : 2 * PAIR + 1, best, minU);
     if (tP == tQ && ok) {
         const int8_t g2[6] = {(int8_t)S2::bx, (int8_t)S2::bz, (int8_t)S2::cx, (int8_t)S2::cz, (int8_t)S2::k1, (int8_t)S2::k2};

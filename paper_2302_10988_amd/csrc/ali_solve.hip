@@ -50,8 +50,15 @@ __global__ void k_prep(int nx, int nz, double h, int n_mats, const MatDev<mreal>
     const MatA m = mats[mid].A;
     double s2, c2;
     sincos(2.0 * th, &s2, &c2);
-    geo[2 * p + 0] = (mreal)c2;
-    geo[2 * p + 1] = (mreal)s2;
+    mreal* g = geo + GEO_N * p;
+    g[0] = (mreal)c2;
+    g[1] = (mreal)s2;
+    g[2] = mats[mid].P;
+    g[3] = mats[mid].Q;
+    g[4] = mats[mid].R;
+    g[5] = mats[mid].K4;
+    g[6] = mreal(0);
+    g[7] = mreal(0);
     // straight-ray time to an 8-neighbour along x, (1,1), z, (1,-1)
     const double quarter = 0.78539816339744830962;
     const double len[4] = {1.0, 1.41421356237309504880, 1.0, 1.41421356237309504880};
@@ -90,84 +97,13 @@ __global__ void k_init(const FieldDev* __restrict__ fields, int f0, double h, co
         flags[fd.unit_off + (j / TZ) * fd.ntx + (i / TX)] = TF_SELF;   // evaluate the whole tile
 }
 
-// Scheduler of one relaxation pass, one work-group per field: advance the field's
-// threshold by its step (not before the first pass); if none of its tiles is flagged or
-// holds a rejected value at or below the threshold, raise the threshold to its smallest
-// rejected value; then append the field's active tiles to the pass list.  cnt_cur counts
-// this pass's list; cnt_next (the next pass's counter) is cleared here.
+// Scheduler of one relaxation pass (ascending thresholds), one work-group per field.
 template <typename real>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(SCHED_T)
 k_sched(const FieldDev* __restrict__ fields, int advance, uint32_t* __restrict__ flags, real* __restrict__ minrej,
-        real* __restrict__ theta, const real* __restrict__ step, uint32_t* __restrict__ list,
-        uint32_t* __restrict__ lbits, uint32_t* __restrict__ lfld, uint32_t* __restrict__ cnt_cur,
-        uint32_t* __restrict__ cnt_next) {
-    const int f = blockIdx.x;
-    const uint32_t uoff = fields[f].unit_off;
-    const int ntiles = fields[f].ntx * fields[f].ntz;
-    const int tid = threadIdx.x;
-    const real inf = dinf<real>();
-    __shared__ real red_m[256];
-    __shared__ unsigned red_c[256];
-    __shared__ real th_s;
-    __shared__ uint32_t base_s;
-    if (f == 0 && tid == 0) *cnt_next = 0u;
-    uint32_t* fl = flags + uoff;
-    real* mr = minrej + uoff;
-    real th = theta[f];
-    if (advance) th += step[f];
-    // is anything active at this threshold, and what is the smallest rejected value?
-    unsigned act = 0;
-    real m = inf;
-    for (int t = tid; t < ntiles; t += 256) {
-        const real v = mr[t];
-        act |= (fl[t] != 0u || v <= th) ? 1u : 0u;
-        m = v < m ? v : m;
-    }
-    red_m[tid] = m;
-    red_c[tid] = act;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) {
-            red_m[tid] = red_m[tid + w] < red_m[tid] ? red_m[tid + w] : red_m[tid];
-            red_c[tid] |= red_c[tid + w];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        if (!red_c[0] && red_m[0] < inf && red_m[0] > th) th = red_m[0];   // idle: jump
-        th_s = th;
-        theta[f] = th;
-    }
-    __syncthreads();
-    th = th_s;
-    // this work-item's active tiles (at most ceil(ntiles / 256) of them), then one slot
-    // range of the pass list for the whole group
-    unsigned mine = 0;
-    for (int t = tid; t < ntiles; t += 256) mine += (fl[t] != 0u || mr[t] <= th) ? 1u : 0u;
-    __syncthreads();
-    red_c[tid] = mine;
-    __syncthreads();
-    // inclusive scan (Hillis-Steele) of the per-item counts
-    for (int o = 1; o < 256; o <<= 1) {
-        const unsigned v = tid >= o ? red_c[tid - o] : 0u;
-        __syncthreads();
-        red_c[tid] += v;
-        __syncthreads();
-    }
-    if (tid == 255) base_s = red_c[255] ? atomicAdd(cnt_cur, red_c[255]) : 0u;
-    __syncthreads();
-    uint32_t pos = base_s + red_c[tid] - mine;
-    for (int t = tid; t < ntiles; t += 256) {
-        const uint32_t b = fl[t];
-        if (b != 0u || mr[t] <= th) {
-            fl[t] = 0u;
-            mr[t] = inf;          // recomputed by the visit
-            list[pos] = uoff + (uint32_t)t;
-            lbits[pos] = b;
-            lfld[pos] = (uint32_t)f;
-            ++pos;
-        }
-    }
+        real* __restrict__ theta, const real* __restrict__ step, PassItem* __restrict__ list,
+        uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next) {
+    schedule_field<false, real>(fields, advance, step, flags, minrej, theta, list, cnt_cur, cnt_next);
 }
 
 
@@ -192,10 +128,7 @@ __device__ __forceinline__ void lds_min(double* p, double v) {
 // pass.  Each sweep packs the marked nodes into the first lanes.
 template <typename real, typename mreal>
 __global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
-k_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ list,
-        const uint32_t* __restrict__ lbits, const uint32_t* __restrict__ lfld,
-        const MatDev<mreal>* __restrict__ mats_all, const uint8_t* __restrict__ mat_id_all,
-        const mreal* __restrict__ geo_all, const real* __restrict__ fbt_all,
+k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, const real* __restrict__ fbt_all,
         int R, int inner, const real* __restrict__ theta,
         real* __restrict__ T, uint32_t* __restrict__ flags, real* __restrict__ minrej,
         uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
@@ -205,7 +138,11 @@ k_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ list,
     __shared__ uint8_t dnext[NTHREADS];
     __shared__ uint16_t clist[NTHREADS];
     __shared__ uint32_t omask[9][NODE_WORDS];     // marks for the 3x3 tile neighbourhood
+    __shared__ uint32_t touched[NODE_WORDS];      // nodes whose value changed in this visit
 
+    // the first entry is read together with the list length (the grid never exceeds the
+    // list's capacity, so the read is in bounds; the entry is used only if it is live)
+    PassItem pi = list[blockIdx.x];
     const uint32_t n_units = *count;
     if (n_units == 0u) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *idle = 1u;
@@ -217,39 +154,48 @@ k_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ list,
     }
     // the work-groups walk the pass list with a grid stride
     for (uint32_t item = blockIdx.x; item < n_units; item += gridDim.x) {
-    const uint32_t unit = list[item];
-    const uint32_t bits = lbits[item];
-    const int f = (int)lfld[item];
-    const FieldDev fd = fields[f];
-    const int nx = fd.nx, nz = fd.nz, ntx = fd.ntx;
-    const int tile = (int)(unit - fd.unit_off);
-    const int tx = tile % ntx, tz = tile / ntx;
+    if (item != blockIdx.x) pi = list[item];
+    const uint32_t unit = pi.unit;
+    const uint32_t bits = pi.bits;
+    const int f = pi.f;
+    const int nx = pi.nx, nz = pi.nz, tx = pi.tx, tz = pi.tz;
+    const int ntx = (nx + TX - 1) / TX;
     const int i0 = tx * TX, j0 = tz * TZ;
-    real* __restrict__ Tf = T + fd.t_off;
-    const MatDev<mreal>* __restrict__ mats = mats_all + fd.mat_off;
-    const uint8_t* __restrict__ mat_id = mat_id_all + fd.node_off;
-    const mreal* __restrict__ geo = geo_all + 2 * fd.node_off;
-    const real* __restrict__ fbt = fbt_all + 4 * fd.node_off;
+    real* __restrict__ Tf = T + pi.t_off;
+    const mreal* __restrict__ geo = geo_all + GEO_N * pi.node_off;
+    const real* __restrict__ fbt = fbt_all + 4 * pi.node_off;
     const real inf = dinf<real>();
-    const int lane = threadIdx.x;
+    // the lane index is made opaque inside the item loop: otherwise the per-lane staging
+    // offsets are hoisted out of the loop and held in registers through the sweeps
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));
 
-    for (int q = lane; q < LW * LH; q += RW) {
+    // stage the tile and its halo: every load is issued before the first store to LDS
+    constexpr int SQ = (LW * LH + RW - 1) / RW;
+    real sv[SQ];
+#pragma unroll
+    for (int k = 0; k < SQ; ++k) {
+        const int q = lane + RW * k;
         const int li = q % LW, lj = q / LW;
         const int gi = i0 - HALO + li, gj = j0 - HALO + lj;
-        real v = inf;
-        if (gi >= 0 && gj >= 0 && gi < nx && gj < nz) v = Tf[(int64_t)gj * nx + gi];
-        lt[lj * LSTRIDE + li] = v;
+        sv[k] = (q < LW * LH && gi >= 0 && gj >= 0 && gi < nx && gj < nz) ? Tf[(int64_t)gj * nx + gi] : inf;
     }
-    for (int q = lane; q < 9 * NODE_WORDS; q += RW) omask[q / NODE_WORDS][q % NODE_WORDS] = 0u;
-    for (int q = lane; q < NTHREADS; q += RW) dnext[q] = 0;
     // incoming marks of this tile (read and cleared; this pass writes the other buffer)
     uint32_t mk = 0u;
     if (lane < NODE_WORDS) {
         mk = marks_in[(int64_t)unit * NODE_WORDS + lane];
         if (mk) marks_in[(int64_t)unit * NODE_WORDS + lane] = 0u;
     }
-    const int2 s = fd.src;
     const real th = theta[f];
+#pragma unroll
+    for (int k = 0; k < SQ; ++k) {
+        const int q = lane + RW * k;
+        if (q < LW * LH) lt[(q / LW) * LSTRIDE + q % LW] = sv[k];
+    }
+    for (int q = lane; q < 9 * NODE_WORDS; q += RW) omask[q / NODE_WORDS][q % NODE_WORDS] = 0u;
+    for (int q = lane; q < NTHREADS; q += RW) dnext[q] = 0;
+    if (lane < NODE_WORDS) touched[lane] = 0u;
+    const int2 s = pi.src;
     __syncthreads();
 
     // the four nodes of this lane: node = lane + 64 q (rows 4q .. 4q + 3 of the tile).
@@ -300,7 +246,7 @@ k_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ list,
                 const int nme = (nlz + HALO) * LSTRIDE + (nlx + HALO);
                 const int64_t p = (int64_t)(j0 + nlz) * nx + (i0 + nlx);
                 NodeConst<mreal, real> nc;
-                load_node_const<real, mreal>(nc, p, mats, mat_id, geo, fbt);
+                load_node_const<real, mreal>(nc, p, geo, fbt);
                 real t[12];
 #pragma unroll
                 for (int k = 0; k < 12; ++k) t[k] = lt[nme + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]];
@@ -312,6 +258,7 @@ k_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ list,
                     lt[nme] = u;
                     chg = true;
                     lo = u < cv ? u : cv;
+                    atomicOr(&touched[node >> 5], 1u << (node & 31));
                 }
             }
             // every value of the chunk is stored before any neighbour is compared (the
@@ -360,10 +307,9 @@ k_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ list,
         const int lx = node % TX, lz = node / TX;
         const int gi = i0 + lx, gj = j0 + lz;
         if (gi >= nx || gj >= nz) continue;
-        const real fin = lt[(lz + HALO) * LSTRIDE + (lx + HALO)];
-        const real org = Tf[(int64_t)gj * nx + gi];     // only this visit writes the tile's nodes
-        if (fin == org || (fin >= inf && org >= inf)) continue;
-        Tf[(int64_t)gj * nx + gi] = fin;
+        // a node whose value changed (possibly back to where it started) is written back
+        if (!((touched[node >> 5] >> (node & 31)) & 1u)) continue;
+        Tf[(int64_t)gj * nx + gi] = lt[(lz + HALO) * LSTRIDE + (lx + HALO)];
         if (lx >= HALO && lx < TX - HALO && lz >= HALO && lz < TZ - HALO) continue;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
@@ -393,7 +339,7 @@ k_relax(const FieldDev* __restrict__ fields, const uint32_t* __restrict__ list,
             if (!w) continue;
             const int o = q / NODE_WORDS;
             const int ntx2 = tx + o % 3 - 1, ntz2 = tz + o / 3 - 1;
-            const int64_t u2 = (int64_t)fd.unit_off + (int64_t)ntz2 * ntx + ntx2;
+            const int64_t u2 = (int64_t)unit + (int64_t)(ntz2 - tz) * ntx + (ntx2 - tx);
             atomicOr(&marks_out[u2 * NODE_WORDS + q % NODE_WORDS], w);
             atomicOr(&flags[u2], TF_MARK);
         }
@@ -531,19 +477,17 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     F.n_units = nunits;
     F.field_nodes = fnodes;
 
-    void *d_mats, *d_geo, *d_fbt, *d_fields, *d_flags, *d_list, *d_lfld, *d_count, *d_upd, *d_err;
-    void *d_theta, *d_step, *d_minrej, *d_lbits, *d_marks, *d_idle;
+    void *d_mats, *d_geo, *d_fbt, *d_fields, *d_flags, *d_list, *d_count, *d_upd, *d_err;
+    void *d_theta, *d_step, *d_minrej, *d_marks, *d_idle;
     if (!H->scratch("mats", sizeof(MatDev<mreal>) * hm.size(), &d_mats) ||
         !H->scratch("fields", sizeof(FieldDev) * n_fields, &d_fields) ||
         !H->scratch("theta", sizeof(real) * n_fields, &d_theta) ||
         !H->scratch("step", sizeof(real) * n_fields, &d_step) ||
         !H->scratch("minrej", sizeof(real) * nunits, &d_minrej) ||
-        !H->scratch("geo", sizeof(mreal) * 2 * med_nodes, &d_geo) ||
+        !H->scratch("geo", sizeof(mreal) * GEO_N * med_nodes, &d_geo) ||
         !H->scratch("fbt", sizeof(real) * 4 * med_nodes, &d_fbt) ||
         !H->scratch("flags", sizeof(uint32_t) * nunits, &d_flags) ||
-        !H->scratch("list", sizeof(uint32_t) * nunits, &d_list) ||
-        !H->scratch("lbits", sizeof(uint32_t) * nunits, &d_lbits) ||
-        !H->scratch("lfld", sizeof(uint32_t) * nunits, &d_lfld) ||
+        !H->scratch("list", sizeof(PassItem) * nunits, &d_list) ||
         !H->scratch("marks", sizeof(uint32_t) * 2 * NODE_WORDS * nunits, &d_marks) ||
         !H->scratch("count", 2 * sizeof(uint32_t), &d_count) ||
         !H->scratch("idle", sizeof(uint32_t), &d_idle) ||
@@ -576,7 +520,7 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
         hipLaunchKernelGGL((k_prep<mreal, real, oreal>), dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S,
                            md.grid.nx, md.grid.nz, md.grid.h, md.n_mats, (const MatDev<mreal>*)d_mats + dev_mat_off[m],
                            d_mat_id + md.node_offset, d_orient + md.node_offset,
-                           (mreal*)d_geo + 2 * md.node_offset, (real*)d_fbt + 4 * md.node_offset, (int*)d_err);
+                           (mreal*)d_geo + GEO_N * md.node_offset, (real*)d_fbt + 4 * md.node_offset, (int*)d_err);
         hipLaunchKernelGGL((k_init<real, mreal, oreal>), dim3((unsigned)((N + B - 1) / B), (unsigned)md.n_src), dim3(B), 0, S,
                            (const FieldDev*)d_fields, F.medium_first_field[m], md.grid.h,
                            (const MatDev<mreal>*)d_mats + dev_mat_off[m], d_mat_id + md.node_offset,
@@ -602,17 +546,15 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     uint32_t* cnt = (uint32_t*)d_count;
     // one pass: schedule, then relax (events around the relax launch when timed)
     auto enqueue = [&](int p, bool timed, hipStream_t S) {
-        hipLaunchKernelGGL((k_sched<real>), dim3((unsigned)n_fields), dim3(256), 0, S,
+        hipLaunchKernelGGL((k_sched<real>), dim3((unsigned)n_fields), dim3(SCHED_T), 0, S,
                            (const FieldDev*)d_fields, p > 0 ? 1 : 0,
                            (uint32_t*)d_flags, (real*)d_minrej, (real*)d_theta, (const real*)d_step,
-                           (uint32_t*)d_list, (uint32_t*)d_lbits, (uint32_t*)d_lfld, cnt + (p & 1), cnt + ((p + 1) & 1));
+                           (PassItem*)d_list, cnt + (p & 1), cnt + ((p + 1) & 1));
         uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
         uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);
         hipLaunchKernelGGL((k_relax<real, mreal>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
-                           (const FieldDev*)d_fields, (const uint32_t*)d_list, (const uint32_t*)d_lbits,
-                           (const uint32_t*)d_lfld, (const MatDev<mreal>*)d_mats, d_mat_id, (const mreal*)d_geo,
-                           (const real*)d_fbt, opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
+                           (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
                            (uint32_t*)d_flags, (real*)d_minrej, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)),
                            (uint32_t*)d_idle, (unsigned long long*)d_upd);
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH) + 1], S);
@@ -624,8 +566,8 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
             // the first batch differs from the others only in the first pass (no advance)
             const int first = iters == 0 ? 1 : 0;
             const std::string key = graph_key("relax", first, (const void*)&k_relax<real, mreal>, d_fields, n_fields,
-                                              d_flags, d_minrej, d_theta, d_step, d_list, d_lbits, d_lfld, d_count,
-                                              d_marks, nunits, d_mats, d_mat_id, d_geo, d_fbt, opt.src_box_radius,
+                                              d_flags, d_minrej, d_theta, d_step, d_list, d_count,
+                                              d_marks, nunits, d_geo, d_fbt, opt.src_box_radius,
                                               opt.inner_sweeps, d_T, d_idle, d_upd, grid_relax);
             HIPCK(H, hipEventRecord(H->ev2, S));
             st = launch_captured(H, key, [&](int b, hipStream_t cs) { enqueue(first ? b : PASS_BATCH + b, false, cs); });

@@ -24,6 +24,12 @@ constexpr int NPL = NTHREADS / RW;            // nodes per lane
 constexpr int NODE_WORDS = NTHREADS / 32;     // 32-bit words of a per-tile node mask
 constexpr int STAT_SLOTS = 256;               // spread of the statistics counters
 
+// per-node constants of the relaxation: GEO_N values of the math type per node, namely
+// cos 2theta, sin 2theta of the symmetry axis and P, Q, R, K4 of the node's material (two
+// unused), so that a node's constants come in two aligned vector loads with no table
+// lookup behind them
+constexpr int GEO_N = 8;
+
 template <typename real> inline real dinf_host() { return (real)INFINITY; }
 
 // per-material constants on the device (phase-speed constants in the math type)
@@ -90,16 +96,19 @@ enum : uint32_t {
 
 template <typename real, typename mreal>
 __device__ __forceinline__ void load_node_const(NodeConst<mreal, real>& nc, int64_t p,
-                                                const MatDev<mreal>* __restrict__ mats,
-                                                const uint8_t* __restrict__ mat_id,
                                                 const mreal* __restrict__ geo,
                                                 const real* __restrict__ fbt) {
-    const MatDev<mreal>& m = mats[mat_id[p]];
-    nc.P = m.P; nc.Q = m.Q; nc.R = m.R; nc.K4 = m.K4;
-    nc.c2t = geo[2 * p + 0];
-    nc.s2t = geo[2 * p + 1];
+    // both arrays come from the device allocator (256-byte aligned) and hold whole
+    // per-node records of 8 and 4 values
+    const mreal* g = static_cast<const mreal*>(__builtin_assume_aligned(geo, 32)) + GEO_N * p;
+    const real* b = static_cast<const real*>(__builtin_assume_aligned(fbt, 32)) + 4 * p;
+    mreal gv[6];
 #pragma unroll
-    for (int d = 0; d < 4; ++d) nc.fb[d] = fbt[4 * p + d];
+    for (int k = 0; k < 6; ++k) gv[k] = g[k];
+    nc.c2t = gv[0]; nc.s2t = gv[1];
+    nc.P = gv[2]; nc.Q = gv[3]; nc.R = gv[4]; nc.K4 = gv[5];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) nc.fb[d] = b[d];
 }
 
 // One field of a batch: a source in a medium.  Offsets count elements.
@@ -115,6 +124,145 @@ struct FieldDev {
     int obs_off;          // the field's first entry in per-receiver arrays
     int2 src;
 };
+
+// One entry of a pass list: what a tile visit needs before its first load of field
+// values, written by the scheduler so that the visit reads it in one round trip.
+struct alignas(16) PassItem {
+    uint32_t unit, bits;      // tile unit; the flag bits it was scheduled with
+    int f, tx;                // field; tile column
+    int tz, nx, nz, pad0;     // tile row; the field's grid
+    int2 src;                 // the field's source node
+    int64_t t_off;            // the field's first node in the per-field arrays
+    int64_t node_off;         // the medium's first node in the per-node arrays
+    int64_t pad1;
+};
+static_assert(sizeof(PassItem) == 64, "pass-list entries are four 16-byte vectors");
+
+constexpr int SCHED_T = 256;  // work-items of a scheduler work-group (one group per field)
+constexpr int SCHED_K = 8;    // tiles per work-item held in registers
+
+// Pass scheduler of field blockIdx.x, run by one work-group of SCHED_T work-items.
+// Ascending (DESC = false, travel times): key[t] is the smallest value tile t rejected
+// (+inf: none); the threshold rises by step each pass, a tile is due when it is flagged
+// or its key is at or below the threshold, and a due tile's key is reset to +inf (its
+// visit recomputes it).  Descending (DESC = true, adjoint): key[t] is the largest key
+// still pending in tile t (-inf: none); the threshold falls by step, and a tile is due
+// when flagged or its key is at or above the threshold.  When no tile is due the
+// threshold jumps to the nearest key.  Due tiles have their flags cleared and are
+// appended to the pass list, counted by cnt_cur; cnt_next (the next pass's counter) is
+// cleared here.  Fields of up to SCHED_T * SCHED_K tiles are read once.
+template <bool DESC, typename real>
+__device__ __forceinline__ void schedule_field(const FieldDev* __restrict__ fields, int advance,
+                                               const real* __restrict__ step, uint32_t* __restrict__ flags,
+                                               real* __restrict__ key, real* __restrict__ theta,
+                                               PassItem* __restrict__ list, uint32_t* __restrict__ cnt_cur,
+                                               uint32_t* __restrict__ cnt_next) {
+    constexpr int NW = SCHED_T / 64;
+    constexpr int SPAN = SCHED_T * SCHED_K;
+    __shared__ real s_key[NW];
+    __shared__ unsigned s_act[NW], s_cnt[NW];
+    __shared__ uint32_t s_base;
+    const int f = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const FieldDev fd = fields[f];
+    const int ntiles = fd.ntx * fd.ntz;
+    uint32_t* __restrict__ fl = flags + fd.unit_off;
+    real* __restrict__ ky = key + fd.unit_off;
+    const real inf = dinf<real>();
+    const real none = DESC ? -inf : inf;
+    if (f == 0 && tid == 0) *cnt_next = 0u;
+    real th = theta[f];
+    if (advance) th = DESC ? th - step[f] : th + step[f];
+
+    // is any tile due at this threshold, and which key is nearest?
+    uint32_t fv[SCHED_K];
+    real kv[SCHED_K];
+    bool act = false;
+    real near = none;
+    for (int b0 = 0; b0 < ntiles; b0 += SPAN) {
+#pragma unroll
+        for (int k = 0; k < SCHED_K; ++k) {
+            const int t = b0 + tid + SCHED_T * k;
+            fv[k] = t < ntiles ? fl[t] : 0u;
+            kv[k] = t < ntiles ? ky[t] : none;
+        }
+#pragma unroll
+        for (int k = 0; k < SCHED_K; ++k) {
+            act |= fv[k] != 0u || (kv[k] != none && (DESC ? kv[k] >= th : kv[k] <= th));
+            near = DESC ? (kv[k] > near ? kv[k] : near) : (kv[k] < near ? kv[k] : near);
+        }
+    }
+    const bool wact = __ballot(act) != 0ull;
+    for (int o = 32; o > 0; o >>= 1) {
+        const real r = __shfl_xor(near, o);
+        near = DESC ? (r > near ? r : near) : (r < near ? r : near);
+    }
+    if (lane == 0) { s_key[wv] = near; s_act[wv] = wact ? 1u : 0u; }
+    __syncthreads();
+    bool any = false;
+    near = none;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        any |= s_act[w] != 0u;
+        near = DESC ? (s_key[w] > near ? s_key[w] : near) : (s_key[w] < near ? s_key[w] : near);
+    }
+    if (!any && near != none && (DESC ? near < th : near > th)) th = near;   // idle: jump
+    if (tid == 0) theta[f] = th;
+
+    // append the due tiles: a prefix sum of the per-work-item counts gives the slots
+    for (int b0 = 0; b0 < ntiles; b0 += SPAN) {
+        if (ntiles > SPAN) {
+#pragma unroll
+            for (int k = 0; k < SCHED_K; ++k) {
+                const int t = b0 + tid + SCHED_T * k;
+                fv[k] = t < ntiles ? fl[t] : 0u;
+                kv[k] = t < ntiles ? ky[t] : none;
+            }
+        }
+        unsigned dmask = 0u;
+#pragma unroll
+        for (int k = 0; k < SCHED_K; ++k)
+            if (fv[k] != 0u || (kv[k] != none && (DESC ? kv[k] >= th : kv[k] <= th))) dmask |= 1u << k;
+        const unsigned mine = (unsigned)__popc(dmask);
+        unsigned incl = mine;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        if (lane == 63) s_cnt[wv] = incl;
+        __syncthreads();
+        unsigned wbase = 0u, total = 0u;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            wbase += w < wv ? s_cnt[w] : 0u;
+            total += s_cnt[w];
+        }
+        if (tid == 0) s_base = total ? atomicAdd(cnt_cur, total) : 0u;
+        __syncthreads();
+        uint32_t pos = s_base + wbase + incl - mine;
+#pragma unroll
+        for (int k = 0; k < SCHED_K; ++k) {
+            if (!((dmask >> k) & 1u)) continue;
+            const int t = b0 + tid + SCHED_T * k;
+            fl[t] = 0u;
+            if (!DESC) ky[t] = inf;
+            PassItem it;
+            it.unit = fd.unit_off + (uint32_t)t;
+            it.bits = fv[k];
+            it.f = f;
+            it.tx = t % fd.ntx;
+            it.tz = t / fd.ntx;
+            it.nx = fd.nx;
+            it.nz = fd.nz;
+            it.pad0 = 0;
+            it.src = fd.src;
+            it.t_off = fd.t_off;
+            it.node_off = fd.node_off;
+            it.pad1 = 0;
+            list[pos++] = it;
+        }
+        __syncthreads();     // s_cnt and s_base are reused by the next span of tiles
+    }
+}
 
 // field f owning tile unit u (fields are stored in unit order)
 __device__ __forceinline__ int field_of_unit(const FieldDev* __restrict__ fields, int n_fields, uint32_t u) {
