@@ -45,10 +45,11 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector
 
 # HBM traffic of the relaxation kernel from two rocprofv3 --pmc runs (FETCH_SIZE, then
 # WRITE_SIZE; each scaled by the same counter on a 256 MiB device copy in the same
-# program), per launch, for the kernel sources with this hash.  Reported as null once the
+# program), per launch of the 64-field weld forward (grid 8192 x 64; the counters are split
+# by grid size), for the kernel sources with this hash.  Reported as null once the
 # sources differ.
-TRAFFIC = {"sources_sha256_16": "b1cd6a0ee573931b", "fetch_bytes_per_launch": 13.727e6,
-           "write_bytes_per_launch": 1.355e6}
+TRAFFIC = {"sources_sha256_16": "412971c5dab06fd7", "fetch_bytes_per_launch": 24.72e6,
+           "write_bytes_per_launch": 1.327e6}
 
 
 def kernel_sources_hash():

@@ -46,9 +46,14 @@ struct RayMedium {
 };
 
 __device__ __forceinline__ float group_slowness(const RayMedium& M, int64_t p, float ang) {
-    // reduce the angle against the cell's symmetry axis to [0, pi/2]
+    // reduce the angle against the cell's symmetry axis to [0, pi/2].  Below 3 pi (the
+    // usual case) one or two exact subtractions give fmodf's exact remainder (Sterbenz:
+    // a - k pi is exact for k pi <= a <= 2 k pi); beyond that, fmodf itself.
+    constexpr float PI_F = 3.14159265358979f;
     float a = fabsf(ang - M.orient[p]);
-    a = fmodf(a, 3.14159265358979f);
+    if (a >= 3.0f * PI_F) a = fmodf(a, PI_F);
+    else if (a >= 2.0f * PI_F) a -= 2.0f * PI_F;
+    else if (a >= PI_F) a -= PI_F;
     if (a > 1.57079632679490f) a = 3.14159265358979f - a;
     const float x = a * (float)(GT_N / HALF_PI);
     int i = (int)x;
@@ -59,7 +64,12 @@ __device__ __forceinline__ float group_slowness(const RayMedium& M, int64_t p, f
 }
 
 // straight-segment time from (x0,z0) to (x1,z1) [grid units] through the nearest-node
-// cells: cut at the cell boundaries k + 1/2, each piece at its midpoint cell's speed
+// cells: cut at the cell boundaries k + 1/2, each piece at its midpoint cell's speed.
+// The pieces are enumerated SEG_BATCH at a time with arithmetic only and their cells'
+// data loaded together, so a walk costs two dependent memory round trips per batch
+// rather than two per cell.  A step that crosses no boundary adds a zero-length piece
+// (+0, which leaves the sum unchanged); the pieces are summed in walk order.
+constexpr int SEG_BATCH = 4;
 __device__ double segment_time(const RayMedium& M, double x0, double z0, double x1, double z1) {
     const double dx = x1 - x0, dz = z1 - z0;
     const double len = sqrt(dx * dx + dz * dz);
@@ -78,19 +88,31 @@ __device__ double segment_time(const RayMedium& M, double x0, double z0, double 
         sz = 1.0 / fabs(dz);
     }
     double t = 0.0, total = 0.0;
-    for (int guard = 0; guard < 4096 && t < 1.0; ++guard) {
-        double tn = tx < tz ? tx : tz;
-        if (tn > 1.0) tn = 1.0;
-        if (tn > t) {
+    for (int guard = 0; guard < 4096 && t < 1.0; guard += SEG_BATCH) {
+        double wgt[SEG_BATCH];
+        uint32_t cell[SEG_BATCH];
+#pragma unroll
+        for (int k = 0; k < SEG_BATCH; ++k) {
+            double tn = tx < tz ? tx : tz;
+            if (tn > 1.0) tn = 1.0;
+            const bool live = t < 1.0;
             const double tm = 0.5 * (t + tn);
             int ci = (int)floor(x0 + tm * dx + 0.5), cj = (int)floor(z0 + tm * dz + 0.5);
             ci = ci < 0 ? 0 : (ci >= M.nx ? M.nx - 1 : ci);
             cj = cj < 0 ? 0 : (cj >= M.nz ? M.nz - 1 : cj);
-            total += (tn - t) * len * M.h * (double)group_slowness(M, (int64_t)cj * M.nx + ci, ang);
+            wgt[k] = (live && tn > t) ? tn - t : 0.0;
+            cell[k] = (uint32_t)cj * (uint32_t)M.nx + (uint32_t)ci;
+            if (live) {
+                t = tn;
+                if (tx <= tn) tx += sx;
+                if (tz <= tn) tz += sz;
+            }
         }
-        t = tn;
-        if (tx <= tn) tx += sx;
-        if (tz <= tn) tz += sz;
+        float sl[SEG_BATCH];
+#pragma unroll
+        for (int k = 0; k < SEG_BATCH; ++k) sl[k] = group_slowness(M, (int64_t)cell[k], ang);
+#pragma unroll
+        for (int k = 0; k < SEG_BATCH; ++k) total += wgt[k] * len * M.h * (double)sl[k];
     }
     return total;
 }
@@ -135,7 +157,21 @@ k_trace(RayMedium M, const treal* __restrict__ Tall, const int2* __restrict__ sr
     const int half = window * sub - 1, nc = 2 * half + 1;
     double px = R0.x, pz = R0.y;
     double dx = S.x - px, dz = S.y - pz;
-    double tt = 0.0;
+    // The path's time is off the step's critical path: segment number g is kept by lane
+    // g mod 64, and every 64 segments the lanes walk their segments together.  Each lane
+    // sums its segments in order; the lanes' sums are combined by a fixed butterfly.
+    double part = 0.0;
+    double hx0 = 0.0, hz0 = 0.0, hx1 = 0.0, hz1 = 0.0;
+    bool held = false;
+    int nseg = 0;
+    auto keep = [&](double ax, double az, double bx, double bz) {
+        if (lane == (nseg & 63)) { hx0 = ax; hz0 = az; hx1 = bx; hz1 = bz; held = true; }
+        if ((nseg & 63) == 63) {
+            if (held) part += segment_time(M, hx0, hz0, hx1, hz1);
+            held = false;
+        }
+        ++nseg;
+    };
     int n = 0;
     if (lane == 0) path[0] = make_float2((float)px, (float)pz);
     ++n;
@@ -143,7 +179,7 @@ k_trace(RayMedium M, const treal* __restrict__ Tall, const int2* __restrict__ sr
     for (int guard = 0; guard < max_pts; ++guard) {
         if (hypot(px - S.x, pz - S.y) < 1.6) {
             if (px != S.x || pz != S.y) {
-                tt += segment_time(M, px, pz, S.x, S.y);
+                keep(px, pz, (double)S.x, (double)S.y);
                 if (lane == 0) path[n] = make_float2((float)S.x, (float)S.y);
                 ++n;
             }
@@ -172,7 +208,7 @@ k_trace(RayMedium M, const treal* __restrict__ Tall, const int2* __restrict__ sr
         const int m0 = (int)floor((f == 0 ? zs : xs) + 0.5);
         int i00, j00;
         fam_node(f, kk, 0, i00, j00);
-        // this lane's candidate
+        // this lane's candidate (the segment walk does not wait for the field values)
         double cost = INFINITY;
         const bool mine = lane < nc;
         if (mine) {
@@ -183,11 +219,10 @@ k_trace(RayMedium M, const treal* __restrict__ Tall, const int2* __restrict__ sr
             fam_node(f, kk, mf, ia, ja);
             fam_node(f, kk, mf + 1, ib, jb);
             double tc = field_at<treal>(T, M.nx, M.nz, ia, ja);
-            if (w != 0.0) {
-                const double t1 = field_at<treal>(T, M.nx, M.nz, ib, jb);
-                tc = (1.0 - w) * tc + w * t1;
-            }
-            if (tc < INFINITY) cost = segment_time(M, px, pz, i00 + u * ex, j00 + u * ez) + tc;
+            const double t1 = w != 0.0 ? field_at<treal>(T, M.nx, M.nz, ib, jb) : 0.0;
+            const double seg = segment_time(M, px, pz, i00 + u * ex, j00 + u * ez);
+            if (w != 0.0) tc = (1.0 - w) * tc + w * t1;
+            if (tc < INFINITY) cost = seg + tc;
         }
         // neighbours' costs
         double cm = __shfl_up(cost, 1);
@@ -218,15 +253,17 @@ k_trace(RayMedium M, const treal* __restrict__ Tall, const int2* __restrict__ sr
         const double bpos = __shfl(pos, bl);
         const double ub = m0 + ((double)(bl - half) + bpos) / sub;
         const double qx = i00 + ub * ex, qz = j00 + ub * ez;
-        tt += segment_time(M, px, pz, qx, qz);
+        keep(px, pz, qx, qz);
         dx = qx - px; dz = qz - pz;
         px = qx; pz = qz;
         if (lane == 0) path[n] = make_float2((float)px, (float)pz);
         ++n;
     }
+    if (held) part += segment_time(M, hx0, hz0, hx1, hz1);
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
     if (lane == 0) {
         npts[r] = reached ? n : -n;
-        tray[r] = (float)tt;
+        tray[r] = (float)part;
     }
 }
 
