@@ -135,28 +135,6 @@ __device__ __forceinline__ mreal interp_weight(treal ta, treal tb, treal tc) {
     return dratio((mreal)(tb - ta), (mreal)(tc - ta));
 }
 
-// One stencil pair of Tables 1-2 as data: the diamond slots of A, P, Q, the class, the
-// activation slot of a tie, and the geometry (B - A, C - A, k1, k2) of both members.
-struct PairTab {
-    int8_t a, p, q;          // diamond slots
-    int8_t cls;              // 0 square, 1 triangle
-    int8_t tie;              // activation slot when tau_B == tau_C
-    int8_t g1[6], g2[6];     // bx, bz, cx, cz, k1, k2 of member 1 and member 2
-};
-template <int PAIR> constexpr PairTab make_pair_tab() {
-    using S1 = Stencil<2 * PAIR>;
-    using S2 = Stencil<2 * PAIR + 1>;
-    return PairTab{(int8_t)PAIR_A[PAIR], (int8_t)PAIR_P[PAIR], (int8_t)PAIR_Q[PAIR], (int8_t)S1::cls,
-                   (int8_t)S1::tie_slot,
-                   {(int8_t)S1::bx, (int8_t)S1::bz, (int8_t)S1::cx, (int8_t)S1::cz, (int8_t)S1::k1, (int8_t)S1::k2},
-                   {(int8_t)S2::bx, (int8_t)S2::bz, (int8_t)S2::cx, (int8_t)S2::cz, (int8_t)S2::k1, (int8_t)S2::k2}};
-}
-static __constant__ PairTab PAIRS[16] = {
-    make_pair_tab<0>(), make_pair_tab<1>(), make_pair_tab<2>(), make_pair_tab<3>(),
-    make_pair_tab<4>(), make_pair_tab<5>(), make_pair_tab<6>(), make_pair_tab<7>(),
-    make_pair_tab<8>(), make_pair_tab<9>(), make_pair_tab<10>(), make_pair_tab<11>(),
-    make_pair_tab<12>(), make_pair_tab<13>(), make_pair_tab<14>(), make_pair_tab<15>()};
-
 // Candidate of one member: estimate, causality, rank against the best so far.  Every lane
 // runs the same instructions (selects, no branches).
 template <typename mreal, typename real>
@@ -252,8 +230,10 @@ __device__ __forceinline__ bool key_after(double u, double tk, int ks) { return 
 // score, table order) whose activation point it is, or else the straight ray from it.
 // The answer is the first record (a candidate better than all activated before it) whose
 // value lies below the key of the next record's activation point.  Used only when the
-// fast test is inconclusive (rare), so it is written for few registers: everything is
-// recomputed per activation point from the staging buffer.
+// fast test is inconclusive (rare).  First every pair is evaluated again with the fast
+// path's arithmetic and wave-level skip, keeping per activation point the best member
+// activated there; then the walk finds each next point by a scan over registers.  No
+// table or memory access happens inside the walk.
 // ---------------------------------------------------------------------------------------
 __host__ __device__ constexpr int fb_slot_rt(int k) {
     return k == 0 ? 1 : k == 1 ? 2 : k == 2 ? 3 : k == 3 ? 5 : k == 4 ? 6 : k == 5 ? 8 : k == 6 ? 9 : 10;
@@ -262,94 +242,122 @@ __host__ __device__ constexpr int fb_dir_rt(int k) {
     return k == 0 ? 1 : k == 1 ? 2 : k == 2 ? 3 : k == 3 ? 0 : k == 4 ? 0 : k == 5 ? 3 : k == 6 ? 2 : 1;
 }
 
-// For each 8-neighbour k: the stencil members (2 * pair + member, table order) that can
-// be activated there (k is their C point, or the later of B and C when tau_B == tau_C).
-struct ActTab {
-    int8_t n[8];
-    int8_t m[8][8];
+// best stencil member activated at each 8-neighbour k (FB_SLOT[k])
+template <typename real> struct ActBest {
+    int ci[8];              // class * 64 + table index; 3 * 64: none
+    real score[8];
+    real U[8];
 };
-constexpr ActTab make_act_tab() {
-    ActTab t{};
-    for (int pr = 0; pr < 16; ++pr)
-        for (int mem = 0; mem < 2; ++mem) {
-            const int sb = mem == 0 ? PAIR_P[pr] : PAIR_Q[pr];
-            const int sc = mem == 0 ? PAIR_Q[pr] : PAIR_P[pr];
-            const int tie = sb > sc ? sb : sc;
-            for (int k = 0; k < 8; ++k)
-                if (FB_SLOT[k] == sc || FB_SLOT[k] == tie) t.m[k][t.n[k]++] = (int8_t)(2 * pr + mem);
-        }
-    return t;
+
+template <typename real>
+__device__ __forceinline__ void act_member(int ks, int cls, int idx, real score, real U, bool cand,
+                                           ActBest<real>& ab) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int c = ab.ci[k] >> 6;
+        // members arrive in table order, so an equal score keeps the earlier one
+        const bool upd = cand && ks == FB_SLOT[k] && (cls < c || (cls == c && score < ab.score[k]));
+        ab.ci[k] = upd ? cls * 64 + idx : ab.ci[k];
+        ab.score[k] = upd ? score : ab.score[k];
+        ab.U[k] = upd ? U : ab.U[k];
+    }
 }
-static __constant__ ActTab ACT = make_act_tab();
+
+template <typename mreal, typename real, int PAIR>
+__device__ __forceinline__ void act_pair(const NodeConst<mreal, real>& n, const real (&t)[12], ActBest<real>& ab) {
+    using S1 = Stencil<2 * PAIR>;
+    using S2 = Stencil<2 * PAIR + 1>;
+    const real inf = dinf<real>();
+    const real tA = t[PAIR_A[PAIR]], tP = t[PAIR_P[PAIR]], tQ = t[PAIR_Q[PAIR]];
+    const bool m1 = tP <= tQ;
+    const real tB = m1 ? tP : tQ, tC = m1 ? tQ : tP;
+    const bool ok = tA < tB && tC < inf;
+    if (__ballot(ok) == 0ull) return;
+    const real r2m1 = real(0.41421356237309504880);
+    const real tm = real(0.58578643762690495120);
+    const real score = S1::cls == 0 ? tC - tB : __builtin_fabs(tQ - (r2m1 * tA + tm * tP));
+    const int ks = (tB == tC) ? S1::tie_slot : (m1 ? S1::sc : S2::sc);
+    const mreal a = interp_weight<mreal, real>(tA, tB, tC);
+    const real U = tB + (real)stencil_incr<mreal, real>(n, a, m1 ? S1::bx : S2::bx, m1 ? S1::bz : S2::bz,
+                                                        m1 ? S1::cx : S2::cx, m1 ? S1::cz : S2::cz,
+                                                        m1 ? S1::k1 : S2::k1, m1 ? S1::k2 : S2::k2);
+    act_member<real>(ks, S1::cls, m1 ? 2 * PAIR : 2 * PAIR + 1, score, U, ok && U > tC, ab);
+    if (tP == tQ && ok) {
+        // tie: member 2 as well (B = Q, C = P), after member 1
+        const mreal a2 = interp_weight<mreal, real>(tA, tQ, tP);
+        const real U2 = tQ + (real)stencil_incr<mreal, real>(n, a2, S2::bx, S2::bz, S2::cx, S2::cz, S2::k1, S2::k2);
+        act_member<real>(S1::tie_slot, S1::cls, 2 * PAIR + 1, score, U2, U2 > tP, ab);
+    }
+}
+
+template <typename mreal, typename real, int... P>
+__device__ __forceinline__ void act_pairs(const NodeConst<mreal, real>& n, const real (&t)[12], ActBest<real>& ab,
+                                          std::integer_sequence<int, P...>) {
+    (act_pair<mreal, real, P>(n, t, ab), ...);
+}
+
+// v[q] for a run-time q: a switch (a chain of selects is folded back into an indexed
+// load, which puts the array in scratch memory)
+template <typename T> __device__ __forceinline__ T pick8(const T (&v)[8], int q) {
+    switch (q) {
+        case 1: return v[1]; case 2: return v[2]; case 3: return v[3]; case 4: return v[4];
+        case 5: return v[5]; case 6: return v[6]; case 7: return v[7]; default: return v[0];
+    }
+}
 
 template <typename mreal, typename real>
 __device__ __noinline__ real slow_update(const NodeConst<mreal, real> n, const real* __restrict__ lds,
                                          int me, int stride, int* choice) {
     const real inf = dinf<real>();
-    const real r2m1 = real(0.41421356237309504880);
-    const real tm = real(0.58578643762690495120);
-    int rcls = 3, ridx = -1;
+    real t[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) t[k] = lds[me + SLOT_DJ[k] * stride + SLOT_DI[k]];
+    ActBest<real> ab;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { ab.ci[k] = 3 * 64; ab.score[k] = inf; ab.U[k] = inf; }
+    act_pairs<mreal, real>(n, t, ab, std::make_integer_sequence<int, 16>{});
+
+    int rci = 3 * 64;                 // record: class * 64 + index
     real rscore = inf, rU = inf;
     real prev_t = -inf;
-    int prev_slot = -1;
+    int prev_k = -1;
 #pragma unroll 1
     for (int step = 0; step < 8; ++step) {
-        // next activation point in key order (time, then slot = linear-index order)
+        // next activation point in key order (time, then linear-index order = k order)
         int q = -1;
         real tq = inf;
-#pragma unroll 1
+#pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int sl = fb_slot_rt(k);
-            const real tk = lds[me + SLOT_DJ_RT(sl) * stride + SLOT_DI_RT(sl)];
-            const bool after = tk > prev_t || (tk == prev_t && sl > prev_slot);
-            if (tk < inf && after && (q < 0 || tk < tq)) { q = k; tq = tk; }
+            const real tk = t[FB_SLOT[k]];
+            const bool after = tk > prev_t || (tk == prev_t && k > prev_k);
+            const bool take = tk < inf && after && (q < 0 || tk < tq);
+            q = take ? k : q;
+            tq = take ? tk : tq;
         }
         if (q < 0) break;
-        const int qs = fb_slot_rt(q);
-        // best stencil activated at this point (only the members listed for it)
-        int ccls = 3, cidx = -1;
-        real cscore = inf, cU = inf;
-        const int ne = ACT.n[q];
-#pragma unroll 1
-        for (int e = 0; e < ne; ++e) {
-            const int sm = ACT.m[q][e];
-            const int pr = sm >> 1, mem = sm & 1;
-            const PairTab& pt = PAIRS[pr];
-            const real tA = lds[me + SLOT_DJ_RT(pt.a) * stride + SLOT_DI_RT(pt.a)];
-            const real tP = lds[me + SLOT_DJ_RT(pt.p) * stride + SLOT_DI_RT(pt.p)];
-            const real tQ = lds[me + SLOT_DJ_RT(pt.q) * stride + SLOT_DI_RT(pt.q)];
-            const real tB = mem == 0 ? tP : tQ, tC = mem == 0 ? tQ : tP;
-            if (!(tA < tB && tB <= tC && tC < inf)) continue;
-            const int ks = (tB == tC) ? pt.tie : (mem == 0 ? pt.q : pt.p);
-            if (ks != qs) continue;
-            const int8_t* g = mem == 0 ? pt.g1 : pt.g2;
-            const mreal a = interp_weight<mreal, real>(tA, tB, tC);
-            const real U = tB + (real)stencil_incr<mreal, real>(n, a, g[0], g[1], g[2], g[3], g[4], g[5]);
-            if (!(U > tC)) continue;
-            const real score = pt.cls == 0 ? tC - tB : __builtin_fabs(tQ - (r2m1 * tA + tm * tP));
-            if (pt.cls < ccls || (pt.cls == ccls && score < cscore)) {
-                ccls = pt.cls; cscore = score; cU = U; cidx = sm;
-            }
-        }
-        if (ccls == 3) {
+        int ci = pick8(ab.ci, q);
+        real cs = pick8(ab.score, q), cu = pick8(ab.U, q);
+        if ((ci >> 6) == 3) {
+            // no stencil activated here: the straight ray from this neighbour
             const int d = fb_dir_rt(q);
             const real fbt = d == 0 ? n.fb[0] : d == 1 ? n.fb[1] : d == 2 ? n.fb[2] : n.fb[3];
             const real U = tq + fbt;
-            if (U > tq) { ccls = 2; cscore = U; cU = U; cidx = 32 + q; }
+            if (U > tq) { ci = 2 * 64 + 32 + q; cs = U; cu = U; }
         }
-        // rank = (class, score, table index / neighbour order)
+        const int ccls = ci >> 6, cidx = ci & 63;
         if (ccls < 3) {
-            const bool better = ccls < rcls || (ccls == rcls && (cscore < rscore || (cscore == rscore && cidx < ridx)));
+            const int rcls = rci >> 6, ridx = rci & 63;
+            const bool better = ccls < rcls || (ccls == rcls && (cs < rscore || (cs == rscore && cidx < ridx)));
             if (better) {
-                if (rcls < 3 && !key_after(rU, tq, qs)) { *choice = ridx; return rU; }   // record below next key
-                rcls = ccls; rscore = cscore; rU = cU; ridx = cidx;
+                if (rcls < 3 && !key_after(rU, tq, fb_slot_rt(q))) { *choice = ridx; return rU; }   // record below next key
+                rci = ci; rscore = cs; rU = cu;
             }
         }
         prev_t = tq;
-        prev_slot = qs;
+        prev_k = q;
     }
-    *choice = rcls < 3 ? ridx : -1;
-    return rcls < 3 ? rU : inf;
+    *choice = (rci >> 6) < 3 ? (rci & 63) : -1;
+    return (rci >> 6) < 3 ? rU : inf;
 }
 
 // ---------------------------------------------------------------------------------------
