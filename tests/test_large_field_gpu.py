@@ -1,0 +1,61 @@
+"""Fields larger than one scheduler span.
+
+The pass scheduler holds up to 2048 tiles of a field in registers and re-reads the flags
+and keys span by span beyond that.  A 1100 x 600 field has 69 x 38 = 2622 tiles of 16 x 16
+nodes, so both the ascending (travel times) and the descending (adjoint) schedules take
+the multi-span path; the results are checked against the FP64 oracle and the adjoint's
+re-derivation of every node's candidate on the final field.
+"""
+import numpy as np
+import pytest
+
+import synthmedia as sm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+    from paper_2302_10988_amd import Solver
+    assert torch.cuda.is_available()
+    return Solver(0)
+
+
+def big_medium():
+    m = sm.random_medium(1100, 600, 0.2e-3, seed=41, n_mats=3)
+    m.sources = [(17, 3), (1090, 590)]
+    m.receivers = [(5, 599), (550, 599), (1099, 0), (600, 300)]
+    return m
+
+
+def test_multi_span_forward_vs_oracle(solver, orc):
+    import torch
+    m = big_medium()
+    assert ((m.nx + 15) // 16) * ((m.nz + 15) // 16) > 2048
+    mid = torch.from_numpy(m.mat_id).cuda()
+    ori = torch.from_numpy(m.orient).float().cuda()
+    print("multi-span forward: %d x %d, %d sources" % (m.nx, m.nz, len(m.sources)), flush=True)
+    T, st = solver.solve(m.h, m.mats, mid, ori, m.sources)
+    assert st["converged"] == 1
+    Tref = orc.solve_fmm(m.h, m.mats, m.mat_id, m.orient, m.sources[1], 2)
+    Tg = T[1].cpu().numpy().astype(np.float64)
+    mask = Tref > 0
+    rel = np.abs(Tg - Tref)[mask] / Tref[mask]
+    print("max rel err vs oracle %.3g" % rel.max(), flush=True)
+    assert np.isfinite(Tg).all()
+    assert rel.max() <= 1e-4
+
+
+def test_multi_span_schedules_reach_the_exact_fixed_point(solver):
+    import torch
+    m = big_medium()
+    mid = torch.from_numpy(m.mat_id).cuda()
+    ori = torch.from_numpy(m.orient).float().cuda()
+    g = torch.ones((len(m.sources), len(m.receivers)), device="cuda")
+    for band in (1, 0):
+        print("multi-span adjoint, band", band, flush=True)
+        _, st = solver.adjoint(m.h, m.mats, mid, ori, m.sources, m.receivers, g, band_cells=band,
+                               max_sweeps=40000)
+        assert st["forward"]["converged"] == 1 and st["converged"] == 1
+        assert st["choice_mismatches"] == 0
