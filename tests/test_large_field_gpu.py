@@ -1,10 +1,10 @@
 """Fields larger than one scheduler span.
 
 The pass scheduler holds up to 2048 tiles of a field in registers and re-reads the flags
-and keys span by span beyond that.  A 1100 x 600 field has 69 x 38 = 2622 tiles of 16 x 16
-nodes, so both the ascending (travel times) and the descending (adjoint) schedules take
-the multi-span path; the results are checked against the FP64 oracle and the adjoint's
-re-derivation of every node's candidate on the final field.
+and keys span by span beyond that.  A 1100 x 600 field has 69 x 75 = 5175 tiles of 16 x 8
+nodes (2622 of 16 x 16), so both the ascending (travel times) and the descending (adjoint)
+schedules take the multi-span path; the results are checked against the FP64 oracle and
+the adjoint's re-derivation of every node's candidate on the final field.
 """
 import numpy as np
 import pytest
@@ -32,7 +32,7 @@ def big_medium():
 def test_multi_span_forward_vs_oracle(solver, orc):
     import torch
     m = big_medium()
-    assert ((m.nx + 15) // 16) * ((m.nz + 15) // 16) > 2048
+    assert ((m.nx + 15) // 16) * ((m.nz + 15) // 16) > 2048     # also true of 16 x 8 tiles
     mid = torch.from_numpy(m.mat_id).cuda()
     ori = torch.from_numpy(m.orient).float().cuda()
     print("multi-span forward: %d x %d, %d sources" % (m.nx, m.nz, len(m.sources)), flush=True)
