@@ -246,6 +246,7 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
     __shared__ uint16_t lc[LH * LSTRIDE];
     __shared__ uint8_t dnext[NTHREADS];
     __shared__ uint8_t lpend[NTHREADS];
+    __shared__ double ltn[NTHREADS], lgn[NTHREADS];   // own nodes: travel time, right-hand side
     __shared__ uint16_t clist[NTHREADS];
     __shared__ uint32_t omask[9][NODE_WORDS];
     __shared__ uint32_t touched[NODE_WORDS];      // nodes whose lambda changed in this visit
@@ -300,12 +301,19 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
         if (mk) marks_in[(int64_t)unit * NODE_WORDS + lane] = 0u;
     }
     const double th = theta[f];
+    // the tile's own nodes: pending state, travel time (band test) and right-hand side,
+    // read with the halo instead of at every evaluation
     uint8_t pdv[NPL];
+    double tv[NPL], gv[NPL];
 #pragma unroll
     for (int q = 0; q < NPL; ++q) {
         const int node = lane + RW * q;
         const int gi = i0 + node % TX, gj = j0 + node / TX;
-        pdv[q] = (gi < nx && gj < nz) ? pend[fo + (int64_t)gj * nx + gi] : 0;
+        const bool in = gi < nx && gj < nz;
+        const int64_t p = fo + (int64_t)gj * nx + gi;
+        pdv[q] = in ? pend[p] : 0;
+        tv[q] = in ? T[p] : 0.0;
+        gv[q] = in ? G[p] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < SQ; ++k) {
@@ -326,6 +334,8 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
         const bool valid = gi < nx && gj < nz;
         const uint8_t pd = pdv[q];
         lpend[node] = pd;
+        ltn[node] = tv[q];
+        lgn[node] = gv[q];
         pmask |= pd ? 1u << q : 0u;
         const bool marked = (__shfl(mk, (node >> 5)) >> (node & 31)) & 1u;
         vmask |= valid ? 1u << q : 0u;
@@ -353,14 +363,13 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
                 const int node = clist[c + lane];
                 const int nlx = node % TX, nlz = node / TX;
                 const int nme = (nlz + HALO) * LSTRIDE + (nlx + HALO);
-                const int64_t p = fo + (int64_t)(j0 + nlz) * nx + (i0 + nlx);
                 // time band: a node below the threshold waits until the band reaches it,
                 // by which time the nodes it pulls from are final or close to it
-                const bool ready = T[p] >= th;
+                const bool ready = ltn[node] >= th;
                 lpend[node] = ready ? 0 : 1;
                 if (ready) {
                     ++my_updates;
-                    const double v = pull_lambda(G[p], nme, ll, lc, la, lb, lcw);
+                    const double v = pull_lambda(lgn[node], nme, ll, lc, la, lb, lcw);
                     if (v != ll[nme]) {
                         ll[nme] = v;
                         atomicOr(&touched[node >> 5], 1u << (node & 31));
@@ -420,7 +429,7 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
         if ((touched[node >> 5] >> (node & 31)) & 1u) lam[p] = ll[(lz + HALO) * LSTRIDE + (lx + HALO)];
         const uint8_t pd = lpend[node];
         if ((pd != 0) != (((pmask >> q) & 1u) != 0u)) pend[p] = pd;
-        if (pd) { const double tp = T[p]; dk = tp > dk ? tp : dk; }
+        if (pd) { const double tp = ltn[node]; dk = tp > dk ? tp : dk; }
     }
     for (int o = 32; o > 0; o >>= 1) {
         const double d2 = __shfl_xor(dk, o);

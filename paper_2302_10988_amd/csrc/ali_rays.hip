@@ -45,7 +45,8 @@ struct RayMedium {
     const float* tab;                      // [n_mats][GT_N + 1] group slowness [s/m]
 };
 
-__device__ __forceinline__ float group_slowness(const RayMedium& M, int64_t p, float ang) {
+__device__ __forceinline__ float group_slowness(const RayMedium& M, const float* __restrict__ tab, int64_t p,
+                                                float ang) {
     // reduce the angle against the cell's symmetry axis to [0, pi/2].  Below 3 pi (the
     // usual case) one or two exact subtractions give fmodf's exact remainder (Sterbenz:
     // a - k pi is exact for k pi <= a <= 2 k pi); beyond that, fmodf itself.
@@ -59,7 +60,7 @@ __device__ __forceinline__ float group_slowness(const RayMedium& M, int64_t p, f
     int i = (int)x;
     i = i < 0 ? 0 : (i >= GT_N ? GT_N - 1 : i);
     const float w = x - (float)i;
-    const float* t = M.tab + (int64_t)M.mat_id[p] * (GT_N + 1);
+    const float* t = tab + (int64_t)M.mat_id[p] * (GT_N + 1);
     return t[i] + w * (t[i + 1] - t[i]);
 }
 
@@ -70,7 +71,8 @@ __device__ __forceinline__ float group_slowness(const RayMedium& M, int64_t p, f
 // rather than two per cell.  A step that crosses no boundary adds a zero-length piece
 // (+0, which leaves the sum unchanged); the pieces are summed in walk order.
 constexpr int SEG_BATCH = 4;
-__device__ double segment_time(const RayMedium& M, double x0, double z0, double x1, double z1) {
+__device__ __forceinline__ double segment_time(const RayMedium& M, const float* __restrict__ tab, double x0,
+                                               double z0, double x1, double z1) {
     const double dx = x1 - x0, dz = z1 - z0;
     const double len = sqrt(dx * dx + dz * dz);
     if (len == 0.0) return 0.0;
@@ -110,7 +112,7 @@ __device__ double segment_time(const RayMedium& M, double x0, double z0, double 
         }
         float sl[SEG_BATCH];
 #pragma unroll
-        for (int k = 0; k < SEG_BATCH; ++k) sl[k] = group_slowness(M, (int64_t)cell[k], ang);
+        for (int k = 0; k < SEG_BATCH; ++k) sl[k] = group_slowness(M, tab, (int64_t)cell[k], ang);
 #pragma unroll
         for (int k = 0; k < SEG_BATCH; ++k) total += wgt[k] * len * M.h * (double)sl[k];
     }
@@ -142,14 +144,26 @@ __device__ __forceinline__ double field_at(const treal* __restrict__ T, int nx, 
     return (double)T[(int64_t)j * nx + i];
 }
 
-template <typename treal>
-__global__ void __launch_bounds__(64)
-k_trace(RayMedium M, const treal* __restrict__ Tall, const int2* __restrict__ srcs,
+// rays per work-group (one wave each); media of up to RAY_LDS_MATS materials keep the
+// slowness tables in LDS, shared by the work-group's rays
+constexpr int RAYS_PER_GROUP = 4;
+constexpr int RAY_LDS_MATS = 4;
+
+template <typename treal, bool LDS_TAB>
+__global__ void __launch_bounds__(RAYS_PER_GROUP * 64)
+k_trace(RayMedium M, int n_mats, int n_rays, const treal* __restrict__ Tall, const int2* __restrict__ srcs,
         const int2* __restrict__ recv, int n_recv, int window, int sub, int max_pts,
         float2* __restrict__ paths, int32_t* __restrict__ npts, float* __restrict__ tray) {
-    const int r = blockIdx.x;
+    __shared__ float s_tab[LDS_TAB ? RAY_LDS_MATS * (GT_N + 1) : 1];
+    if (LDS_TAB) {
+        for (int i = threadIdx.x; i < n_mats * (GT_N + 1); i += RAYS_PER_GROUP * 64) s_tab[i] = M.tab[i];
+        __syncthreads();
+    }
+    const float* __restrict__ tab = LDS_TAB ? s_tab : M.tab;
+    const int r = blockIdx.x * RAYS_PER_GROUP + (int)(threadIdx.x >> 6);
+    if (r >= n_rays) return;
     const int s = r / n_recv, k = r % n_recv;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int64_t N = (int64_t)M.nx * M.nz;
     const treal* __restrict__ T = Tall + (int64_t)s * N;
     float2* __restrict__ path = paths + (int64_t)r * max_pts;
@@ -167,7 +181,7 @@ k_trace(RayMedium M, const treal* __restrict__ Tall, const int2* __restrict__ sr
     auto keep = [&](double ax, double az, double bx, double bz) {
         if (lane == (nseg & 63)) { hx0 = ax; hz0 = az; hx1 = bx; hz1 = bz; held = true; }
         if ((nseg & 63) == 63) {
-            if (held) part += segment_time(M, hx0, hz0, hx1, hz1);
+            if (held) part += segment_time(M, tab, hx0, hz0, hx1, hz1);
             held = false;
         }
         ++nseg;
@@ -220,7 +234,7 @@ k_trace(RayMedium M, const treal* __restrict__ Tall, const int2* __restrict__ sr
             fam_node(f, kk, mf + 1, ib, jb);
             double tc = field_at<treal>(T, M.nx, M.nz, ia, ja);
             const double t1 = w != 0.0 ? field_at<treal>(T, M.nx, M.nz, ib, jb) : 0.0;
-            const double seg = segment_time(M, px, pz, i00 + u * ex, j00 + u * ez);
+            const double seg = segment_time(M, tab, px, pz, i00 + u * ex, j00 + u * ez);
             if (w != 0.0) tc = (1.0 - w) * tc + w * t1;
             if (tc < INFINITY) cost = seg + tc;
         }
@@ -259,7 +273,7 @@ k_trace(RayMedium M, const treal* __restrict__ Tall, const int2* __restrict__ sr
         if (lane == 0) path[n] = make_float2((float)px, (float)pz);
         ++n;
     }
-    if (held) part += segment_time(M, hx0, hz0, hx1, hz1);
+    if (held) part += segment_time(M, tab, hx0, hz0, hx1, hz1);
     for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
     if (lane == 0) {
         npts[r] = reached ? n : -n;
@@ -310,9 +324,15 @@ static ali_status trace_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     HIPCK(H, hipGetLastError());
     RayMedium M{grid->nx, grid->nz, grid->h, d_mat_id, d_orient, (const float*)d_tab};
     const int n_rays = n_src * n_recv;
-    hipLaunchKernelGGL((k_trace<treal>), dim3((unsigned)n_rays), dim3(64), 0, S, M, d_T,
-                       (const int2*)d_src, (const int2*)d_rec, n_recv, opt.ray_window, opt.ray_sub,
-                       opt.ray_max_pts, (float2*)d_paths, d_npts, d_tray);
+    const unsigned groups = (unsigned)((n_rays + RAYS_PER_GROUP - 1) / RAYS_PER_GROUP);
+    if (n_mats <= RAY_LDS_MATS)
+        hipLaunchKernelGGL((k_trace<treal, true>), dim3(groups), dim3(RAYS_PER_GROUP * 64), 0, S, M, n_mats, n_rays, d_T,
+                           (const int2*)d_src, (const int2*)d_rec, n_recv, opt.ray_window, opt.ray_sub,
+                           opt.ray_max_pts, (float2*)d_paths, d_npts, d_tray);
+    else
+        hipLaunchKernelGGL((k_trace<treal, false>), dim3(groups), dim3(RAYS_PER_GROUP * 64), 0, S, M, n_mats, n_rays, d_T,
+                           (const int2*)d_src, (const int2*)d_rec, n_recv, opt.ray_window, opt.ray_sub,
+                           opt.ray_max_pts, (float2*)d_paths, d_npts, d_tray);
     HIPCK(H, hipGetLastError());
     // the host arrays above must outlive the asynchronous copies
     HIPCK(H, hipStreamSynchronize(S));
