@@ -12,6 +12,9 @@
 
 // relaxation passes queued between two host checks
 constexpr int ALI_PASS_BATCH = 16;
+// captured pass batches kept per handle (each signature includes the output pointer, so a
+// caller that passes new buffers every call would otherwise grow the cache without bound)
+constexpr size_t ALI_MAX_GRAPHS = 32;
 
 struct ali_handle {
     int device = 0;
@@ -74,6 +77,8 @@ inline int relax_grid(ali_handle* H, const void* kernel) {
 // replayed afterwards.
 // The batch is recorded on the handle's own capture stream (the caller's stream may be the
 // legacy default stream, which cannot be captured) and replayed on the caller's stream.
+// Callers synchronise the stream after every batch, so when the cache is full its graphs
+// are idle and are all released before the next capture.
 template <class F>
 inline ali_status launch_captured(ali_handle* H, const std::string& key, F&& enqueue) {
     hipGraphExec_t exec = nullptr;
@@ -81,6 +86,10 @@ inline ali_status launch_captured(ali_handle* H, const std::string& key, F&& enq
     if (it != H->graphs.end()) {
         exec = it->second;
     } else {
+        if (H->graphs.size() >= ALI_MAX_GRAPHS) {
+            for (auto& kv : H->graphs) (void)hipGraphExecDestroy(kv.second);
+            H->graphs.clear();
+        }
         hipGraph_t graph = nullptr;
         HIPCK(H, hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
         for (int b = 0; b < PASS_BATCH; ++b) enqueue(b, H->cap_stream);

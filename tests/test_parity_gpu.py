@@ -132,6 +132,27 @@ def test_schedule_invariance(solver):
     assert sb["outer_iters"] > sa["outer_iters"]
 
 
+def test_graph_cache_bounded_and_exact(solver):
+    # in float32 arithmetic the relaxation works in the output buffer itself, so every
+    # output buffer is part of a captured batch's signature; 40 solves into fresh buffers
+    # overflow the handle's cache (32 graphs) and must release and recapture without
+    # changing a bit, graph replay or not
+    import torch
+    m = sm.weld(96, 0.3e-3)
+    mid = torch.from_numpy(m.mat_id).cuda()
+    ori = torch.from_numpy(m.orient).float().cuda()
+    srcs = m.sources
+    ref, st = solver.solve(m.h, m.mats, mid, ori, srcs, arith="f32", graph=0)
+    assert st["outer_iters"] > 32      # long enough for whole captured batches
+    keep = []
+    for k in range(40):
+        out = torch.full((len(srcs), m.nz, m.nx), -1.0, device="cuda")
+        keep.append(out)               # distinct live buffers, distinct signatures
+        T, _ = solver.solve(m.h, m.mats, mid, ori, srcs, out=out, arith="f32")
+        assert torch.equal(T, ref), k
+    print("graph cache: 40 captured signatures, all equal to the one-by-one launches", flush=True)
+
+
 # Exact ties of the discrete solution are resolved by rounding, so two correct
 # implementations may choose different stencils there.  Homogeneous cubic media whose
 # axis makes the x and z grid directions mirror images (e.g. 33 deg: 33 and 57 deg from
