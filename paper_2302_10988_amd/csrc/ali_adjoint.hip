@@ -227,7 +227,7 @@ __device__ __forceinline__ double pull_lambda(double gsum, int me, const double*
     return s;
 }
 
-// Tile visit of the lambda relaxation, one wave per tile (4 nodes per lane), laid out as
+// Tile visit of the lambda relaxation, one wave per tile (NPL nodes per lane), laid out as
 // the forward relaxation.  A node is evaluated only once the descending threshold has
 // reached its travel time (ready); a marked node below the threshold is left pending and
 // the tile remembers its largest pending time.  A changed lambda marks the node's

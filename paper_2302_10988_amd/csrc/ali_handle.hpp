@@ -24,7 +24,6 @@ struct ali_handle {
     uint32_t* host_count = nullptr;           // pinned 4-byte readback slot
     hipEvent_t pev[2 * ALI_PASS_BATCH] = {};  // per-pass timing events of one batch
     int n_cu = 0;                             // compute units of the device
-    std::map<const void*, int> grids;         // resident work-groups per kernel (grid-stride launches)
     std::map<std::string, hipGraphExec_t> graphs;   // captured pass batches by argument signature
     std::string err;
     struct Buf { void* p = nullptr; size_t bytes = 0; };
@@ -60,17 +59,6 @@ struct ali_handle {
 namespace ali {
 
 constexpr int PASS_BATCH = ALI_PASS_BATCH;
-
-// work-groups of `kernel` (one wave each) that fit on the device at once
-inline int relax_grid(ali_handle* H, const void* kernel) {
-    auto it = H->grids.find(kernel);
-    if (it != H->grids.end()) return it->second;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess || per_cu < 1) return -1;
-    const int g = per_cu * H->n_cu;
-    H->grids[kernel] = g;
-    return g;
-}
 
 // Enqueue `enqueue(b)` for b = 0 .. PASS_BATCH-1 on the handle's stream as one captured
 // graph, instantiated once per signature `key` (every argument the kernels receive) and

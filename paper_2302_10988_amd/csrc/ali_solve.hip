@@ -4,13 +4,13 @@
 // fixed point of a local operator: at node D, grow the known set in (tau, index) order
 // over the diamond and stop once D's estimate precedes the next neighbour.  Any schedule
 // that reaches a state where no node changes lands on that field, so the GPU relaxes
-// tiles in parallel instead:
-//   - each work-group owns a 16x16 tile plus a 2-node halo staged in LDS;
-//   - it sweeps the update over the tile in place until a block-wide OR reports no
-//     change (or the inner cap), skipping waves whose rows saw no change last sweep;
-//   - changed values go back to HBM; a change within 2 nodes of an edge flags the
-//     neighbouring tile(s), an unfinished tile flags itself;
-//   - a compaction kernel turns the flags into the next pass's work list.
+// tiles in parallel instead.  Each pass is two launches:
+//   - k_sched (one work-group per field) advances the field's threshold and lists the
+//     tiles that are due, each entry carrying what a visit needs to start staging;
+//   - k_relax (one wave per tile visit) stages a 16 x 8 tile and its 2-node halo in LDS,
+//     sweeps the marked nodes (packed into the lanes) until nothing changes or the inner
+//     cap is reached, writes changed values back and marks the diamond neighbours of
+//     changed nodes in the neighbouring tiles (unfinished nodes mark their own tile).
 // Ordering: relaxing from +inf everywhere lets values computed from incomplete upstream
 // information race through the whole grid and be corrected over and over.  A per-field
 // time band limits that: an update whose value exceeds the field's threshold theta is
@@ -116,7 +116,7 @@ __device__ __forceinline__ void lds_min(double* p, double v) {
 }
 
 
-// One tile visit by one wave (64 lanes, 4 nodes per lane; tile + halo staged in LDS).
+// One tile visit by one wave (64 lanes, NPL nodes per lane; tile + halo staged in LDS).
 // The nodes to evaluate are tracked per node.  The first sweep takes every node (TF_SELF),
 // the band front (unreached nodes with a reached neighbour: new arrivals and values an
 // earlier band rejected) and the nodes a neighbouring tile marked; each later sweep takes
@@ -198,9 +198,9 @@ k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, co
     const int2 s = pi.src;
     __syncthreads();
 
-    // the four nodes of this lane: node = lane + 64 q (rows 4q .. 4q + 3 of the tile).
+    // the NPL nodes of this lane: node = lane + 64 q.
     // Loops over them stay rolled, and nothing per node is kept in registers across the
-    // phases (the original values are re-read from global memory at the end).
+    // phases (the write-back finds changed nodes in the LDS change mask).
     unsigned dmask = 0u;              // bit q: node q of this lane is marked for this sweep
     unsigned amask = 0u;              // bit q: node q of this lane is evaluated at all
 #pragma unroll 1
