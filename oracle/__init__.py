@@ -77,13 +77,15 @@ def _load():
     lib.or_segment_time.restype = D
     lib.or_trace_ray.argtypes = [I, I, D, M, P, P, P, I, I, I, I, I, I, I, P, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.or_trace_ray.restype = I
-    lib.or_adjoint.argtypes = [I, I, D, M, I, P, P, I, I, I, P, P, P]
+    lib.or_adjoint.argtypes = [I, I, D, M, I, P, P, I, I, I, P, P, P, P]
     lib.or_adjoint.restype = I
     lib.or_qp_phase_speed_deriv.argtypes = [M, D]
     lib.or_qp_phase_speed_deriv.restype = D
     lib.or_qp_group_speed_deriv.argtypes = [M, D]
     lib.or_qp_group_speed_deriv.restype = D
-    lib.or_stencil_partials.argtypes = [M, D, D, ctypes.POINTER(I), D, D, D] + [ctypes.POINTER(D)] * 4
+    lib.or_stencil_partials.argtypes = [M, D, D, ctypes.POINTER(I), D, D, D] + [ctypes.POINTER(D)] * 4 + [P]
+    lib.or_qp_phase_speed_dA.argtypes = [M, D, ctypes.POINTER(D)]
+    lib.or_qp_group_speed_dA.argtypes = [M, D, ctypes.POINTER(D)]
     lib.or_field_choices.argtypes = [I, I, D, M, P, P, P, P, P]
     lib.or_frozen_field.argtypes = [I, I, D, M, P, P, I, I, I, P, P, ctypes.c_int64, P]
     _lib = lib
@@ -272,26 +274,46 @@ def qp_group_speed_deriv(mat, phi):
     return _load().or_qp_group_speed_deriv(_mat_array([mat]), float(phi))
 
 
-def stencil_partials(mat, theta_ax, h, offsets, ta, tb, tc):
+def qp_phase_speed_dA(mat, th_p):
+    """d v / d (A11, A13, A33, A55) of the qP phase speed, A = C / rho."""
+    out = (ctypes.c_double * 4)()
+    _load().or_qp_phase_speed_dA(_mat_array([mat]), float(th_p), out)
+    return np.array(out[:])
+
+
+def qp_group_speed_dA(mat, phi):
+    """d V / d (A11, A13, A33, A55) of the qP group speed at fixed group angle."""
+    out = (ctypes.c_double * 4)()
+    _load().or_qp_group_speed_dA(_mat_array([mat]), float(phi), out)
+    return np.array(out[:])
+
+
+def stencil_partials(mat, theta_ax, h, offsets, ta, tb, tc, with_A=False):
+    """(dU/dta, dU/dtb, dU/dtc, dU/dtheta), plus dU/dA [4] when with_A."""
     off = (ctypes.c_int * 6)(*[int(v) for p in offsets for v in p])
     out = [ctypes.c_double() for _ in range(4)]
+    dA = np.zeros(4)
     _load().or_stencil_partials(_mat_array([mat]), float(theta_ax), float(h), off, float(ta), float(tb),
-                                float(tc), *[ctypes.byref(o) for o in out])
-    return tuple(o.value for o in out)
+                                float(tc), *[ctypes.byref(o) for o in out], _ptr(dA))
+    res = tuple(o.value for o in out)
+    return res + (dA,) if with_A else res
 
 
-def adjoint(h, mats, mat_id, orient, src, g, R=2):
-    """(T, dL/dtheta) for one source given g = dL/dT [nz, nx]."""
+def adjoint(h, mats, mat_id, orient, src, g, R=2, with_A=False):
+    """(T, dL/dtheta) for one source given g = dL/dT [nz, nx]; with_A adds dL/dA
+    [nz, nx, 4] (A11, A13, A33, A55 of every node, A = C / rho)."""
     mat_id, orient = _medium(mat_id, orient)
     nz, nx = mat_id.shape
     g = np.ascontiguousarray(g, dtype=np.float64)
     T = np.empty((nz, nx))
     dth = np.empty((nz, nx))
+    dA = np.empty((nz, nx, 4)) if with_A else None
     st = _load().or_adjoint(nx, nz, float(h), _mat_array(mats), len(list(mats)), _ptr(mat_id), _ptr(orient),
-                            int(src[0]), int(src[1]), int(R), _ptr(g), _ptr(T), _ptr(dth))
+                            int(src[0]), int(src[1]), int(R), _ptr(g), _ptr(T), _ptr(dth),
+                            _ptr(dA) if with_A else None)
     if st != 0:
         raise ValueError("oracle: invalid input")
-    return T, dth
+    return (T, dth, dA) if with_A else (T, dth)
 
 
 def frozen_setup(h, mats, mat_id, orient, src, R=2):

@@ -13,6 +13,11 @@
  * The local partials differentiate the paper's geometric formulas (point E, foot point F,
  * |FD|, normal direction, phase speed at theta') by hand; the group-speed derivative used
  * by straight rays is a Richardson-extrapolated central difference.
+ *
+ * The same reverse pass also gives dL/dA for the density-normalised stiffness A = C / rho
+ * of every node (A11, A13, A33, A55): a stencil estimate depends on A_D through the phase
+ * speed v(theta') only, a straight ray through the group speed of its node (for the source
+ * box, the source node's), so dL/dA_D = lambda(D) dU_D/dA_D (+ box terms at the source).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -22,7 +27,7 @@
 /* partial derivatives of one stencil estimate (same arguments as or_stencil_estimate) */
 void or_stencil_partials(const or_material* m, double theta_ax, double h, const int off[6],
                          double ta, double tb, double tc, double* dta, double* dtb, double* dtc,
-                         double* dth) {
+                         double* dth, double* dA) {
     double xA = off[0], yA = off[1], xB = off[2], yB = off[3], xC = off[4], yC = off[5];
     double Dl = tc - ta;
     double a = (tb - ta) / Dl;
@@ -50,6 +55,12 @@ void or_stencil_partials(const or_material* m, double theta_ax, double h, const 
     *dtb = 1.0 + dU_da * da_tb;
     *dtc = dU_da * da_tc;
     *dth = -fd * dv / (v * v);
+    if (dA) {
+        /* |FD| depends on the times only; the stiffness enters through v(theta') */
+        double dvA[4];
+        or_qp_phase_speed_dA(m, thp, dvA);
+        for (int k = 0; k < 4; ++k) dA[k] = -fd * dvA[k] / (v * v);
+    }
 }
 
 static const int NEIGH8[8][2] = {
@@ -104,9 +115,17 @@ void or_frozen_field(int nx, int nz, double h, const or_material* mats, const ui
     free(fixed);
 }
 
+/* lambda times the stiffness derivative of a straight-ray time L / V(phi) */
+static void add_ray_dA(const or_material* m, double phi, double L, double l, double* out) {
+    double V = or_qp_group_speed(m, phi);
+    double dV[4];
+    or_qp_group_speed_dA(m, phi, dV);
+    for (int k = 0; k < 4; ++k) out[k] -= l * L * dV[k] / (V * V);
+}
+
 int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, const uint8_t* mat_id,
                const double* orient, int si, int sj, int R, const double* g, double* T_out,
-               double* dtheta) {
+               double* dtheta, double* dA) {
     int64_t N = (int64_t)nx * nz;
     double* T = T_out ? T_out : malloc(sizeof(double) * (size_t)N);
     int64_t* pop = malloc(sizeof(int64_t) * (size_t)N);
@@ -121,6 +140,8 @@ int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, co
     double* lam = malloc(sizeof(double) * (size_t)N);
     memcpy(lam, g, sizeof(double) * (size_t)N);
     for (int64_t p = 0; p < N; ++p) dtheta[p] = 0.0;
+    if (dA)
+        for (int64_t p = 0; p < 4 * N; ++p) dA[p] = 0.0;
     int64_t ps = (int64_t)sj * nx + si;
     const or_material* msrc = &mats[mat_id[ps]];
     for (int64_t q = npop - 1; q >= 0; --q) {
@@ -137,6 +158,7 @@ int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, co
             double V = or_qp_group_speed(msrc, phi);
             double r = sqrt((double)(di * di + dj * dj)) * h;
             dtheta[ps] += l * r * or_qp_group_speed_deriv(msrc, phi) / (V * V);
+            if (dA) add_ray_dA(msrc, phi, r, l, dA + 4 * ps);
             continue;
         }
         int ch = choice[p];
@@ -147,12 +169,14 @@ int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, co
             int64_t pa = (int64_t)(j + off[1]) * nx + i + off[0];
             int64_t pb = (int64_t)(j + off[3]) * nx + i + off[2];
             int64_t pc = (int64_t)(j + off[5]) * nx + i + off[4];
-            double da, db, dc, dth;
-            or_stencil_partials(m, orient[p], h, off, T[pa], T[pb], T[pc], &da, &db, &dc, &dth);
+            double da, db, dc, dth, dUA[4];
+            or_stencil_partials(m, orient[p], h, off, T[pa], T[pb], T[pc], &da, &db, &dc, &dth, dUA);
             lam[pa] += l * da;
             lam[pb] += l * db;
             lam[pc] += l * dc;
             dtheta[p] += l * dth;
+            if (dA)
+                for (int k = 0; k < 4; ++k) dA[4 * p + k] += l * dUA[k];
         } else {
             int di = NEIGH8[ch - 32][0], dj = NEIGH8[ch - 32][1];
             int64_t pn = (int64_t)(j + dj) * nx + i + di;
@@ -161,6 +185,7 @@ int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, co
             double L = sqrt((double)(di * di + dj * dj)) * h;
             lam[pn] += l;
             dtheta[p] += l * L * or_qp_group_speed_deriv(m, phi) / (V * V);
+            if (dA) add_ray_dA(m, phi, L, l, dA + 4 * p);
         }
     }
     free(lam); free(choice); free(fixed); free(Tbox); free(pop);

@@ -137,10 +137,19 @@ int or_trace_ray(int nx, int nz, double h, const or_material* mats, const uint8_
 
 /* ---- gradient with respect to orientation (frozen choices) --------------------------- */
 
-/* partial derivatives of or_stencil_estimate with respect to ta, tb, tc and theta_ax */
+/* partial derivatives of or_stencil_estimate with respect to ta, tb, tc and theta_ax, and
+   (dA nullable, 4 values) with respect to A11, A13, A33, A55 of the node's material, where
+   A = C / rho is the density-normalised stiffness */
 void or_stencil_partials(const or_material* m, double theta_ax, double h, const int off[6],
                          double ta, double tb, double tc, double* dta, double* dtb, double* dtc,
-                         double* dth);
+                         double* dth, double* dA);
+
+/* d v / d (A11, A13, A33, A55) of the qP phase speed at phase angle th_p (closed form,
+   eigenvalue perturbation of the Christoffel matrix) */
+void or_qp_phase_speed_dA(const or_material* m, double th_p, double dv[4]);
+
+/* d V / d (A11, A13, A33, A55) of the qP group speed at fixed group angle phi (numerical) */
+void or_qp_group_speed_dA(const or_material* m, double phi, double dV[4]);
 
 /* choice of every node at the fixed point T: -2 fixed, -1 unreached, 0..31 stencil,
    32 + k straight ray from the k-th 8-neighbour */
@@ -153,10 +162,11 @@ void or_frozen_field(int nx, int nz, double h, const or_material* mats, const ui
                      const int64_t* pop, int64_t npop, double* T);
 
 /* dL/dtheta for one source given g = dL/dT at every node; writes the field to T_out
-   (nullable).  Returns 0, or -1 on invalid input. */
+   (nullable) and dL/dA [nz][nx][4] (A11, A13, A33, A55 of every node, A = C / rho; nullable)
+   to dA.  Returns 0, or -1 on invalid input. */
 int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, const uint8_t* mat_id,
                const double* orient, int si, int sj, int R, const double* g, double* T_out,
-               double* dtheta);
+               double* dtheta, double* dA);
 
 #ifdef __cplusplus
 }

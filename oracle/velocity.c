@@ -70,22 +70,28 @@ double or_qp_phase_speed_deriv(const or_material* m, double th_p) {
     return dlam / (2.0 * m->rho * v);
 }
 
-void or_qp_group_from_phase(const or_material* m, double th_p, double* g_angle, double* g_speed) {
+/* qP eigenvalue (rho v^2) and unit polarisation p at phase angle th_p */
+static double qp_polarisation(const or_material* m, double th_p, double p[2]) {
     double al, be, ga;
     christoffel(m, th_p, &al, &be, &ga);
     double lam = qp_lambda(al, be, ga);
-    double v = sqrt(lam / m->rho);
     /* unit eigenvector of [al be; be ga] for lam: take the better conditioned of the two
        equivalent forms (be, lam-al) and (lam-ga, be). */
     double p0a = be, p1a = lam - al;
     double p0b = lam - ga, p1b = be;
     double na = p0a * p0a + p1a * p1a, nb = p0b * p0b + p1b * p1b;
-    double p[2];
     if (na >= nb) { double r = sqrt(na); p[0] = p0a / r; p[1] = p1a / r; }
     else          { double r = sqrt(nb); p[0] = p0b / r; p[1] = p1b / r; }
     if (na == 0.0 && nb == 0.0) {          /* degenerate (isotropic point): p = n */
         p[0] = cos(th_p); p[1] = sin(th_p);
     }
+    return lam;
+}
+
+void or_qp_group_from_phase(const or_material* m, double th_p, double* g_angle, double* g_speed) {
+    double p[2];
+    double lam = qp_polarisation(m, th_p, p);
+    double v = sqrt(lam / m->rho);
     double n[2] = {cos(th_p), sin(th_p)};
     double V[2] = {0.0, 0.0};
     for (int mm = 0; mm < 2; ++mm)
@@ -153,4 +159,46 @@ double or_qp_group_speed_deriv(const or_material* m, double phi) {
     double d1 = (or_qp_group_speed(m, phi + h1) - or_qp_group_speed(m, phi - h1)) / (2.0 * h1);
     double d2 = (or_qp_group_speed(m, phi + h2) - or_qp_group_speed(m, phi - h2)) / (2.0 * h2);
     return (4.0 * d2 - d1) / 3.0;
+}
+
+/* d v / d A of the qP phase speed at phase angle th_p, A = C / rho (order A11, A13, A33,
+   A55).  First-order eigenvalue perturbation of the symmetric Christoffel matrix: the
+   change of the qP eigenvalue is p^T dGamma p for the unit polarisation p, and
+   v^2 = lambda / rho, so dv/dA_k = rho (p^T dGamma/dc_k p) / (2 rho v). */
+void or_qp_phase_speed_dA(const or_material* m, double th_p, double dv[4]) {
+    double p[2];
+    double lam = qp_polarisation(m, th_p, p);
+    double v = sqrt(lam / m->rho);
+    double c = cos(th_p), s = sin(th_p);
+    /* dGamma/dc11 = [c^2 0; 0 0], dGamma/dc13 = [0 cs; cs 0], dGamma/dc33 = [0 0; 0 s^2],
+       dGamma/dc55 = [s^2 cs; cs c^2] */
+    double g11 = p[0] * p[0] * c * c;
+    double g13 = 2.0 * p[0] * p[1] * c * s;
+    double g33 = p[1] * p[1] * s * s;
+    double g55 = p[0] * p[0] * s * s + 2.0 * p[0] * p[1] * c * s + p[1] * p[1] * c * c;
+    double k = 1.0 / (2.0 * v);
+    dv[0] = g11 * k;
+    dv[1] = g13 * k;
+    dv[2] = g33 * k;
+    dv[3] = g55 * k;
+}
+
+/* d V / d A of the exact qP group speed at fixed group angle phi (order A11, A13, A33, A55)
+   by Richardson-extrapolated central differences of or_qp_group_speed, steps of 1e-3 and
+   5e-4 times (A11 + A33) / 2. */
+void or_qp_group_speed_dA(const or_material* m, double phi, double dV[4]) {
+    const double scale = 0.5 * (m->c11 + m->c33) / m->rho;
+    for (int k = 0; k < 4; ++k) {
+        double d[2];
+        for (int r = 0; r < 2; ++r) {
+            const double st = (r == 0 ? 1e-3 : 0.5e-3) * scale;
+            or_material mp = *m, mm = *m;
+            double* cp = k == 0 ? &mp.c11 : k == 1 ? &mp.c13 : k == 2 ? &mp.c33 : &mp.c55;
+            double* cm = k == 0 ? &mm.c11 : k == 1 ? &mm.c13 : k == 2 ? &mm.c33 : &mm.c55;
+            *cp += st * m->rho;
+            *cm -= st * m->rho;
+            d[r] = (or_qp_group_speed(&mp, phi) - or_qp_group_speed(&mm, phi)) / (2.0 * st);
+        }
+        dV[k] = (4.0 * d[1] - d[0]) / 3.0;
+    }
 }
