@@ -230,6 +230,30 @@ ali_status ali_adjoint_f64(ali_handle* h, const ali_grid* grid, const ali_materi
                            const ali_node* recv, int32_t n_recv, const double* d_dLdT, const ali_options* opt,
                            double* d_T, double* d_dLdtheta, ali_adjoint_stats* stats);
 
+/* ali_adjoint plus the gradient with respect to the stiffness of every node (not in the
+   paper; it differentiates the same updates, Sections 3.2 and 4.2-4.4).  The parameters are
+   the density-normalised stiffnesses A = C / rho of each node's material, in the order
+   A11, A13, A33, A55 [m^2/s^2] (the in-plane qP speeds depend on these only), each node
+   treated as a parameter of its own.  A stencil estimate depends on its node's A through the
+   phase speed at the wavefront normal; a straight-ray time (fallback or source box) through
+   the exact group speed at a fixed group angle, whose derivative is (V / v) dv/dA at the
+   phase angle that carries that group angle (envelope theorem); source-box terms go to the
+   source node.
+     d_dLdA         [nz][nx][4] output (device), summed over all sources; NULL is an error
+   Gradients w.r.t. C and rho follow by the chain rule: dL/dC = dL/dA / rho and
+   dL/drho = -sum_k A_k dL/dA_k / rho.  Every other argument, the arithmetic, errors and
+   synchronisation as ali_adjoint.  Scratch: 40 more bytes per node and source. */
+ali_status ali_adjoint_stiffness(ali_handle* h, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
+                                 const uint8_t* d_mat_id, const float* d_orient, const ali_node* srcs,
+                                 int32_t n_src, const ali_node* recv, int32_t n_recv, const float* d_dLdT,
+                                 const ali_options* opt, float* d_T, float* d_dLdtheta, float* d_dLdA,
+                                 ali_adjoint_stats* stats);
+ali_status ali_adjoint_stiffness_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                     int32_t n_mats, const uint8_t* d_mat_id, const double* d_orient,
+                                     const ali_node* srcs, int32_t n_src, const ali_node* recv, int32_t n_recv,
+                                     const double* d_dLdT, const ali_options* opt, double* d_T,
+                                     double* d_dLdtheta, double* d_dLdA, ali_adjoint_stats* stats);
+
 /* Forward + adjoint for the travel-time misfit L = 1/2 sum over (s, r) of
    (T_s(r) - obs[s][r])^2 in one call (the tomography step).
      d_obs          [n_src][n_recv] observed times (device)

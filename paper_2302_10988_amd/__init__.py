@@ -224,10 +224,12 @@ class Solver:
 
     def adjoint(self, h, mats, mat_id, orient, sources, receivers, dLdT, precision="f32",
                 return_T=False, src_box_radius=None, max_sweeps=None, inner_sweeps=None,
-                band_cells=None, arith="mixed", **extra):
+                band_cells=None, arith="mixed", stiffness=False, **extra):
         """dL/dtheta [nz, nx] (summed over sources) for dL/dT given at the receivers,
         dLdT [n_src, n_rec] device tensor.  The forward fields are solved inside the call
         (returned when return_T).  precision "f32" (arith "mixed" or "f64") or "f64".
+        stiffness=True also returns dL/dA [nz, nx, 4] (A11, A13, A33, A55 of every node,
+        A = C / rho), as a tuple (dLdtheta, dLdA) in place of dLdtheta.
         Returns (dLdtheta, stats dict) or (dLdtheta, T, stats dict)."""
         import torch
         nz, nx = mat_id.shape
@@ -244,13 +246,21 @@ class Solver:
         T = torch.empty((ns, nz, nx), dtype=fdt, device=dev) if return_T else None
         stats = _lib.AdjointStats()
         self._sync_stream()
-        fn = self._lib.ali_adjoint if precision == "f32" else self._lib.ali_adjoint_f64
-        st = fn(self._h, ctypes.byref(g), m_arr, nm, _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id"),
+        args = [self._h, ctypes.byref(g), m_arr, nm, _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id"),
                 _dev_ptr(orient, fdt, (nz, nx), "orient"), s_arr, ns, r_arr, nr,
                 _dev_ptr(dLdT, fdt, (ns, nr), "dLdT"), ctypes.byref(opt),
-                _dev_ptr(T, fdt) if T is not None else None, _dev_ptr(dth, fdt), ctypes.byref(stats))
+                _dev_ptr(T, fdt) if T is not None else None, _dev_ptr(dth, fdt)]
+        if stiffness:
+            dA = torch.empty((nz, nx, 4), dtype=fdt, device=dev)
+            fn = self._lib.ali_adjoint_stiffness if precision == "f32" else self._lib.ali_adjoint_stiffness_f64
+            st = fn(*args, _dev_ptr(dA, fdt), ctypes.byref(stats))
+            grad = (dth, dA)
+        else:
+            fn = self._lib.ali_adjoint if precision == "f32" else self._lib.ali_adjoint_f64
+            st = fn(*args, ctypes.byref(stats))
+            grad = dth
         self._check(st)
-        return (dth, T, stats.as_dict()) if return_T else (dth, stats.as_dict())
+        return (grad, T, stats.as_dict()) if return_T else (grad, stats.as_dict())
 
     def misfit_gradient(self, h, mats, mat_id, orient, sources, receivers, obs, precision="f32",
                         T_out=None, src_box_radius=None, max_sweeps=None, inner_sweeps=None,

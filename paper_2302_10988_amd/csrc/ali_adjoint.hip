@@ -1,5 +1,5 @@
 // ali_adjoint.hip -- gradient of receiver travel times with respect to the orientation of
-// the symmetry axis at every node (gfx950).
+// the symmetry axis at every node and, on request, to its stiffness A = C / rho (gfx950).
 //
 // At the fixed point every non-fixed node D holds the value of one candidate of its
 // local update (paper Sections 4.2-4.3): a stencil estimate U(tau_A, tau_B, tau_C,
@@ -19,7 +19,8 @@
 //      changes) is the exact solution and independent of the schedule; on a DAG the
 //      relaxation ends after at most its depth in sweeps;
 //   4. k_adj_grad / k_adj_box: per-node gradient summed over fields in field order
-//      (deterministic), plus the source-box terms.
+//      (deterministic), plus the source-box terms; k_adj_grad_a / k_adj_box_a do the same
+//      for dL/dA = lambda(D) dU_D/dA_D, whose partials k_adj_prep writes when asked.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -64,9 +65,9 @@ __device__ __forceinline__ StGeo stencil_geo(int s, std::integer_sequence<int, S
     return g;
 }
 
-// Float64 node constants for the derivatives (the phase-speed constants / h^2 and the
-// double angle of the axis).
-struct NodeD { double c2t, s2t, P, Q, R, K4; };
+// Float64 node constants for the derivatives (the phase-speed constants / h^2, with
+// K4 = 4 W^2, and the double angle of the axis).
+struct NodeD { double c2t, s2t, P, Q, R, W, K4; };
 
 // Partial derivatives of U = tau_B + 2|cr| / sqrt(G4) (the estimate of ali_device.hpp:
 // a = (tau_B - tau_A) / (tau_C - tau_A), w = (B - A) - a (C - A), cr = k1 - a k2) with
@@ -108,16 +109,46 @@ __device__ void stencil_partials(const NodeD& n, const StGeo& g, double ta, doub
     dT = -0.5 * inc * dG4_t / G4;
 }
 
+// Partial derivatives of the same estimate with respect to the node's stiffness A = C / rho
+// (a11, a13, a33, a55).  The increment 2|cr| / sqrt(G4) depends on A through G4 only, with
+// G4 = P w2 + Q c + sqrt(lin^2 + K4 s2), lin = Q w2 + R c, and P = (a11 + a33 + 2 a55)/h^2,
+// Q = (a33 - a11)/h^2, R = (a11 + a33 - 2 a55)/h^2, K4 = 4 W^2 with W = (a13 + a55)/h^2.
+__device__ void stencil_partials_A(const NodeD& n, const StGeo& g, double ta, double tb, double tc, double ih2,
+                                   double d[4]) {
+    const double Dl = tc - ta;
+    const double a = (tb - ta) / Dl;
+    const double wx = g.bx - a * g.cx, wz = g.bz - a * g.cz;
+    const double cr = g.k1 - a * g.k2;
+    const double w2 = wx * wx + wz * wz;
+    const double c = (wz * wz - wx * wx) * n.c2t + (-2.0 * wx * wz) * n.s2t;
+    const double s2 = w2 * w2 - c * c;
+    const double lin = n.Q * w2 + n.R * c;
+    const double rt = sqrt(lin * lin + n.K4 * s2);
+    const double G4 = n.P * w2 + n.Q * c + rt;
+    const double inc = 2.0 * fabs(cr) / sqrt(G4);
+    const double irt = rt > 0.0 ? 1.0 / rt : 0.0;
+    // dG4 / d(P, Q, R, K4)
+    const double gP = w2, gQ = c + lin * w2 * irt, gR = lin * c * irt, gK = 0.5 * s2 * irt;
+    const double gW = 8.0 * n.W * gK;      // dG4/dK4 dK4/dW
+    const double k = -0.5 * inc / G4 * ih2;
+    d[0] = k * (gP - gQ + gR);
+    d[1] = k * gW;
+    d[2] = k * (gP + gQ + gR);
+    d[3] = k * (2.0 * (gP - gR) + gW);
+}
+
 // ---------------------------------------------------------------------------------------
 // step 2: choices and partial derivatives, one work-group per (tile, field)
 // ---------------------------------------------------------------------------------------
-template <typename mreal, typename oreal>
+// WA: also write dU/dA of every node (4 float64 per node and field, wA[4 q + k]); for a
+// source-box node that is the derivative with respect to the source node's stiffness.
+template <typename mreal, typename oreal, bool WA>
 __global__ void __launch_bounds__(NTHREADS)
 k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal>* __restrict__ mats_all,
            const uint8_t* __restrict__ mat_id_all, const oreal* __restrict__ orient_all,
            const mreal* __restrict__ geo_all, const double* __restrict__ fbt_all, int R,
            const double* __restrict__ T, AdjW<mreal>* __restrict__ W, double* __restrict__ wT,
-           unsigned long long* __restrict__ mismatches) {
+           double* __restrict__ wA, unsigned long long* __restrict__ mismatches) {
     __shared__ double lt[LH * LSTRIDE];
     const uint32_t unit = blockIdx.x;
     const FieldDev fd = fields[field_of_unit(fields, n_fields, unit)];
@@ -151,6 +182,7 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
     const double tD = lt[me];
     uint16_t cd = CODE_NONE;
     double a = 0.0, b = 0.0, c = 0.0, t = 0.0;
+    double dA[4] = {0.0, 0.0, 0.0, 0.0};
     const int di = gi - s.x, dj = gj - s.y;
     if (abs(di) <= R && abs(dj) <= R) {
         // straight ray from the source at the source node's orientation and material
@@ -158,9 +190,15 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
         if (di != 0 || dj != 0) {
             const int64_t ps = (int64_t)s.y * nx + s.x;
             const double phi = atan2((double)dj, (double)di) - (double)orient[ps];
+            const double L = sqrt((double)(di * di + dj * dj)) * h;
             double dV;
             const double V = group_speed(mats[mat_id[ps]].A, phi, &dV);
-            t = sqrt((double)(di * di + dj * dj)) * h * dV / (V * V);
+            t = L * dV / (V * V);
+            if constexpr (WA) {
+                group_speed_dA(mats[mat_id[ps]].A, phi, dA);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dA[k] *= -L / (V * V);
+            }
         }
     } else if (tD < inf) {
         NodeConst<mreal, double> nc;
@@ -182,9 +220,10 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
             nd.P = (A.a11 + A.a33 + 2.0 * A.a55) * ih2;
             nd.Q = (A.a33 - A.a11) * ih2;
             nd.R = (A.a11 + A.a33 - 2.0 * A.a55) * ih2;
-            const double W = (A.a13 + A.a55) * ih2;
-            nd.K4 = 4.0 * W * W;
+            nd.W = (A.a13 + A.a55) * ih2;
+            nd.K4 = 4.0 * nd.W * nd.W;
             stencil_partials(nd, g, tt[g.sa], tt[g.sb], tt[g.sc], a, b, c, t);
+            if constexpr (WA) stencil_partials_A(nd, g, tt[g.sa], tt[g.sb], tt[g.sc], ih2, dA);
             cd = make_code(K_STENCIL, (unsigned)g.sa, (unsigned)g.sb, (unsigned)g.sc);
         } else if (ch >= 32) {
             const int k = ch - 32;
@@ -196,6 +235,11 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
             const double V = group_speed(A, ang - th, &dV);
             a = 1.0;
             t = len * h * dV / (V * V);
+            if constexpr (WA) {
+                group_speed_dA(A, ang - th, dA);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dA[k] *= -len * h / (V * V);
+            }
             cd = make_code(K_FALLBACK, (unsigned)fb_slot_rt(k), NO_SLOT, NO_SLOT);
         }
     }
@@ -204,6 +248,10 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
     w.code = cd;
     W[q] = w;
     wT[q] = t;
+    if constexpr (WA) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) wA[4 * q + k] = dA[k];
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -529,6 +577,31 @@ __global__ void k_adj_grad(int64_t N, int f0, int f1, const FieldDev* __restrict
     dth[p] = s;
 }
 
+// dL/dA of the nodes of one medium (4 per node), summed over its fields in field order
+template <typename wreal>
+__global__ void k_adj_grad_a(int64_t N, int f0, int f1, const FieldDev* __restrict__ fields,
+                             const AdjW<wreal>* __restrict__ W, const double* __restrict__ wA,
+                             const double* __restrict__ lam, double* __restrict__ dA) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int f = f0; f < f1; ++f) {
+        const int64_t q = fields[f].t_off + p;
+        const int kind = (int)(W[q].code >> 12);
+        if (kind == K_STENCIL || kind == K_FALLBACK) {
+            const double l = lam[q];
+            s0 += l * wA[4 * q + 0];
+            s1 += l * wA[4 * q + 1];
+            s2 += l * wA[4 * q + 2];
+            s3 += l * wA[4 * q + 3];
+        }
+    }
+    dA[4 * p + 0] = s0;
+    dA[4 * p + 1] = s1;
+    dA[4 * p + 2] = s2;
+    dA[4 * p + 3] = s3;
+}
+
 // source-box terms of field f, reduced in a fixed order
 __global__ void k_adj_box(const FieldDev* __restrict__ fields, int R, const double* __restrict__ wT,
                           const double* __restrict__ lam, double* __restrict__ boxsum) {
@@ -553,6 +626,45 @@ __global__ void k_adj_box(const FieldDev* __restrict__ fields, int R, const doub
     if (threadIdx.x == 0) boxsum[f] = red[0];
 }
 
+// source-box terms of field f with respect to the source node's stiffness (4 values)
+__global__ void k_adj_box_a(const FieldDev* __restrict__ fields, int R, const double* __restrict__ wA,
+                            const double* __restrict__ lam, double* __restrict__ boxsum) {
+    const int f = blockIdx.x;
+    const FieldDev fd = fields[f];
+    const int2 s = fd.src;
+    const int w = 2 * R + 1;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < w * w; k += blockDim.x) {
+        const int i = s.x - R + k % w, j = s.y - R + k / w;
+        if (i < 0 || j < 0 || i >= fd.nx || j >= fd.nz) continue;
+        const int64_t q = fd.t_off + (int64_t)j * fd.nx + i;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += lam[q] * wA[4 * q + c];
+    }
+    __shared__ double red[4][256];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int m = blockDim.x / 2; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) boxsum[4 * f + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// one work-item adds the stiffness box terms at the source nodes in field order
+__global__ void k_adj_box_add_a(int n_fields, const FieldDev* __restrict__ fields,
+                                const double* __restrict__ boxsum, double* __restrict__ dA) {
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int f = 0; f < n_fields; ++f) {
+            const FieldDev& fd = fields[f];
+            const int64_t p = fd.node_off + (int64_t)fd.src.y * fd.nx + fd.src.x;
+            for (int c = 0; c < 4; ++c) dA[4 * p + c] += boxsum[4 * f + c];
+        }
+}
+
 // one work-item adds the box terms at the source nodes in field order
 __global__ void k_adj_box_add(int n_fields, const FieldDev* __restrict__ fields, const double* __restrict__ boxsum,
                               double* __restrict__ dth) {
@@ -571,7 +683,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
                                int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient,
                                const ali_node* srcs, const ali_node* recv, int mode, const greal* d_in,
                                const ali_options* opt_in, outreal* d_T, outreal* d_trec, double* d_loss,
-                               outreal* d_dth, ali_adjoint_stats* stats) {
+                               outreal* d_dth, outreal* d_dA, ali_adjoint_stats* stats) {
     ali_options opt;
     ali_default_options(&opt);
     if (opt_in) opt = *opt_in;
@@ -626,6 +738,12 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
         !H->scratch("a_marks", sizeof(uint32_t) * 2 * NODE_WORDS * nunits, &d_marks) ||
         !H->scratch("a_cnt", (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), &d_cnt))
         return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+    // stiffness gradient (on request): dU/dA per node and field, its sums, box terms
+    void *d_wA = nullptr, *d_aacc = nullptr, *d_boxa = nullptr;
+    if (d_dA && (!H->scratch("a_wA", 4 * sizeof(double) * NF, &d_wA) ||
+                 !H->scratch("a_dA", 4 * sizeof(double) * med_nodes, &d_aacc) ||
+                 !H->scratch("a_boxA", 4 * sizeof(double) * n_fields, &d_boxa)))
+        return H->fail(ALI_ENOMEM, "device scratch allocation failed");
     // descending time band: band_cells node spacings at each medium's fastest phase speed
     const bool banded = opt.band_cells > 0;
     std::vector<double> hstep(n_fields);
@@ -646,9 +764,16 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
 
     const int B = 256;
     const unsigned gNF = (unsigned)((NF + B - 1) / B);
-    hipLaunchKernelGGL((k_adj_prep<mreal, oreal>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
-                       fs.fields, n_fields, fs.mats, d_mat_id, d_orient, fs.geo, fs.fbt, opt.src_box_radius,
-                       (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (unsigned long long*)d_cnt + 1);
+    if (d_dA)
+        hipLaunchKernelGGL((k_adj_prep<mreal, oreal, true>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
+                           fs.fields, n_fields, fs.mats, d_mat_id, d_orient, fs.geo, fs.fbt, opt.src_box_radius,
+                           (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (double*)d_wA,
+                           (unsigned long long*)d_cnt + 1);
+    else
+        hipLaunchKernelGGL((k_adj_prep<mreal, oreal, false>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
+                           fs.fields, n_fields, fs.mats, d_mat_id, d_orient, fs.geo, fs.fbt, opt.src_box_radius,
+                           (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (double*)nullptr,
+                           (unsigned long long*)d_cnt + 1);
     HIPCK(H, hipGetLastError());
     hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_G, NF, 0.0);
     hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_lam, NF, 0.0);
@@ -734,6 +859,26 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
                            d_dth + media[m].node_offset, (const double*)d_dacc + media[m].node_offset, N);
     }
     HIPCK(H, hipGetLastError());
+    if (d_dA) {
+        for (int m = 0; m < n_media; ++m) {
+            const int64_t N = (int64_t)media[m].grid.nx * media[m].grid.nz;
+            hipLaunchKernelGGL(k_adj_grad_a<mreal>, dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S, N,
+                               fs.medium_first_field[m], fs.medium_first_field[m + 1], fs.fields,
+                               (const AdjW<mreal>*)d_W, (const double*)d_wA, (const double*)d_lam,
+                               (double*)d_aacc + 4 * media[m].node_offset);
+        }
+        hipLaunchKernelGGL(k_adj_box_a, dim3((unsigned)n_fields), dim3(256), 0, S, fs.fields, opt.src_box_radius,
+                           (const double*)d_wA, (const double*)d_lam, (double*)d_boxa);
+        hipLaunchKernelGGL(k_adj_box_add_a, dim3(1), dim3(64), 0, S, n_fields, fs.fields, (const double*)d_boxa,
+                           (double*)d_aacc);
+        for (int m = 0; m < n_media; ++m) {
+            const int64_t N4 = 4 * (int64_t)media[m].grid.nx * media[m].grid.nz;
+            hipLaunchKernelGGL((k_convert<outreal, double>), dim3((unsigned)((N4 + B - 1) / B)), dim3(B), 0, S,
+                               d_dA + 4 * media[m].node_offset, (const double*)d_aacc + 4 * media[m].node_offset,
+                               N4);
+        }
+        HIPCK(H, hipGetLastError());
+    }
     if (d_T && !out64)
         hipLaunchKernelGGL((k_convert<outreal, double>), dim3(gNF), dim3(B), 0, S, d_T, (const double*)T, NF);
     HIPCK(H, hipGetLastError());
@@ -844,14 +989,16 @@ static ali_status adjoint_dispatch(ali_handle* h, const ali_medium* media, int32
                                    int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
                                    const ali_node* recv, int mode, const greal* d_in, const ali_options* opt,
                                    outreal* d_T, outreal* d_trec, double* d_loss, outreal* d_dth,
-                                   ali_adjoint_stats* stats) {
+                                   outreal* d_dA, ali_adjoint_stats* stats) {
     const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
     if (arith == ALI_ARITH_MIXED)
         return adjoint_impl<float, oreal, greal, outreal>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs,
-                                                          recv, mode, d_in, opt, d_T, d_trec, d_loss, d_dth, stats);
+                                                          recv, mode, d_in, opt, d_T, d_trec, d_loss, d_dth, d_dA,
+                                                          stats);
     if (arith == ALI_ARITH_F64)
         return adjoint_impl<double, oreal, greal, outreal>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs,
-                                                           recv, mode, d_in, opt, d_T, d_trec, d_loss, d_dth, stats);
+                                                           recv, mode, d_in, opt, d_T, d_trec, d_loss, d_dth, d_dA,
+                                                           stats);
     return h->fail(ALI_EUNSUPPORTED, "the adjoint needs float64 travel times: use ALI_ARITH_MIXED or ALI_ARITH_F64");
 }
 
@@ -864,7 +1011,8 @@ extern "C" ali_status ali_adjoint(ali_handle* h, const ali_grid* grid, const ali
     if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
     const ali_medium md = single_medium(grid, n_mats, n_src, n_recv);
     return adjoint_dispatch<float, float, float>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, 0, d_dLdT,
-                                                 opt, d_T, (float*)nullptr, nullptr, d_dLdtheta, stats);
+                                                 opt, d_T, (float*)nullptr, nullptr, d_dLdtheta,
+                                                 (float*)nullptr, stats);
 }
 
 extern "C" ali_status ali_adjoint_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
@@ -876,7 +1024,37 @@ extern "C" ali_status ali_adjoint_f64(ali_handle* h, const ali_grid* grid, const
     if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
     const ali_medium md = single_medium(grid, n_mats, n_src, n_recv);
     return adjoint_impl<double, double, double, double>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, 0,
-                                                        d_dLdT, opt, d_T, (double*)nullptr, nullptr, d_dLdtheta, stats);
+                                                        d_dLdT, opt, d_T, (double*)nullptr, nullptr, d_dLdtheta,
+                                                        (double*)nullptr, stats);
+}
+
+extern "C" ali_status ali_adjoint_stiffness(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                            int32_t n_mats, const uint8_t* d_mat_id, const float* d_orient,
+                                            const ali_node* srcs, int32_t n_src, const ali_node* recv,
+                                            int32_t n_recv, const float* d_dLdT, const ali_options* opt,
+                                            float* d_T, float* d_dLdtheta, float* d_dLdA,
+                                            ali_adjoint_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
+    if (!d_dLdA) return h->fail(ALI_EINVAL, "d_dLdA is NULL");
+    const ali_medium md = single_medium(grid, n_mats, n_src, n_recv);
+    return adjoint_dispatch<float, float, float>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, 0, d_dLdT,
+                                                 opt, d_T, (float*)nullptr, nullptr, d_dLdtheta, d_dLdA, stats);
+}
+
+extern "C" ali_status ali_adjoint_stiffness_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                                int32_t n_mats, const uint8_t* d_mat_id, const double* d_orient,
+                                                const ali_node* srcs, int32_t n_src, const ali_node* recv,
+                                                int32_t n_recv, const double* d_dLdT, const ali_options* opt,
+                                                double* d_T, double* d_dLdtheta, double* d_dLdA,
+                                                ali_adjoint_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
+    if (!d_dLdA) return h->fail(ALI_EINVAL, "d_dLdA is NULL");
+    const ali_medium md = single_medium(grid, n_mats, n_src, n_recv);
+    return adjoint_impl<double, double, double, double>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, 0,
+                                                        d_dLdT, opt, d_T, (double*)nullptr, nullptr, d_dLdtheta,
+                                                        d_dLdA, stats);
 }
 
 extern "C" ali_status ali_misfit_gradient(ali_handle* h, const ali_grid* grid, const ali_material* mats,
@@ -889,7 +1067,7 @@ extern "C" ali_status ali_misfit_gradient(ali_handle* h, const ali_grid* grid, c
     if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
     const ali_medium md = single_medium(grid, n_mats, n_src, n_recv);
     return adjoint_dispatch<float, float, float>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, 1, d_obs,
-                                                 opt, d_T, d_Trec, d_loss, d_dLdtheta, stats);
+                                                 opt, d_T, d_Trec, d_loss, d_dLdtheta, (float*)nullptr, stats);
 }
 
 extern "C" ali_status ali_misfit_gradient_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats,
@@ -902,7 +1080,8 @@ extern "C" ali_status ali_misfit_gradient_f64(ali_handle* h, const ali_grid* gri
     if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
     const ali_medium md = single_medium(grid, n_mats, n_src, n_recv);
     return adjoint_impl<double, double, double, double>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, 1,
-                                                        d_obs, opt, d_T, d_Trec, d_loss, d_dLdtheta, stats);
+                                                        d_obs, opt, d_T, d_Trec, d_loss, d_dLdtheta, (double*)nullptr,
+                                                        stats);
 }
 
 extern "C" ali_status ali_misfit_gradient_batch(ali_handle* h, const ali_medium* media, int32_t n_media,
@@ -912,7 +1091,8 @@ extern "C" ali_status ali_misfit_gradient_batch(ali_handle* h, const ali_medium*
                                                 double* d_loss, float* d_dLdtheta, ali_adjoint_stats* stats) {
     if (!h) return ALI_EINVAL;
     return adjoint_dispatch<float, float, float>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, recv, 1,
-                                                 d_obs, opt, (float*)nullptr, d_Trec, d_loss, d_dLdtheta, stats);
+                                                 d_obs, opt, (float*)nullptr, d_Trec, d_loss, d_dLdtheta,
+                                                 (float*)nullptr, stats);
 }
 
 extern "C" ali_status ali_bilinear(ali_handle* h, int32_t nz, int32_t nx, int32_t ncz, int32_t ncx,

@@ -33,10 +33,9 @@ __device__ inline double group_angle_of(const MatA& m, double psi, double* speed
     return psi + atan(dF / (2.0 * F));
 }
 
-// Group speed V and, if dV != nullptr, dV/dphi.  With psi the phase angle whose group
-// direction is phi, tan(phi - psi) = v'/v and dV/dphi = V v'/v (differentiate
-// V^2 = v^2 + v'^2 and phi = psi + atan(v'/v) in psi and divide).
-__device__ inline double group_speed(const MatA& m, double phi, double* dV = nullptr) {
+// Phase angle x in [0, pi/2] whose group direction is phi folded onto [0, pi/2] (V is even
+// and pi-periodic in phi); sgn is the sign that d/dphi takes through the fold.
+__device__ inline double phase_of_group(const MatA& m, double phi, double& sgn_out) {
     const double half_pi = 1.57079632679489661923;
     // fold onto [0, pi/2]: V is even and pi-periodic in phi
     double a = fmod(fabs(phi), 2.0 * half_pi);
@@ -67,10 +66,53 @@ __device__ inline double group_speed(const MatA& m, double phi, double* dV = nul
             }
         }
     }
+    sgn_out = sgn;
+    return x;
+}
+
+// Group speed V and, if dV != nullptr, dV/dphi.  With psi the phase angle whose group
+// direction is phi, tan(phi - psi) = v'/v and dV/dphi = V v'/v (differentiate
+// V^2 = v^2 + v'^2 and phi = psi + atan(v'/v) in psi and divide).
+__device__ inline double group_speed(const MatA& m, double phi, double* dV = nullptr) {
+    double sgn;
+    const double x = phase_of_group(m, phi, sgn);
     double F, dF;
     phase_F(m, x, F, dF);
     const double spd = sqrt(F + dF * dF / (4.0 * F));
     if (dV) *dV = sgn * spd * dF / (2.0 * F);
+    return spd;
+}
+
+// dF/dA of the phase speed squared at phase angle psi, A in the order a11, a13, a33, a55.
+// F = (P + Q c + S) / 4 with S = sqrt((Q + R c)^2 + 4 W^2 s^2) (c, s of 2 psi) and P, Q, R,
+// W linear in A.
+__device__ inline void phase_F_dA(const MatA& m, double psi, double d[4]) {
+    const double Q = m.a33 - m.a11, R = m.a11 + m.a33 - 2.0 * m.a55, W = m.a13 + m.a55;
+    double s, c;
+    sincos(2.0 * psi, &s, &c);
+    const double lin = Q + R * c;
+    const double S = sqrt(lin * lin + 4.0 * W * W * s * s);
+    const double iS = S > 0.0 ? 1.0 / S : 0.0;
+    const double fP = 0.25, fQ = 0.25 * (c + lin * iS), fR = 0.25 * lin * c * iS, fW = W * s * s * iS;
+    d[0] = fP - fQ + fR;
+    d[1] = fW;
+    d[2] = fP + fQ + fR;
+    d[3] = 2.0 * (fP - fR) + fW;
+}
+
+// Group speed V and dV/dA at a fixed group angle phi.  1/V(phi) is the largest value of
+// cos(phi - psi) / v(psi) over phase angles psi, so by the envelope theorem only v moves:
+// dV/dA = (V / v) dv/dA = V / (2 F) dF/dA at the phase angle that carries phi.
+__device__ inline double group_speed_dA(const MatA& m, double phi, double d[4]) {
+    double sgn;
+    const double x = phase_of_group(m, phi, sgn);
+    double F, dF;
+    phase_F(m, x, F, dF);
+    const double spd = sqrt(F + dF * dF / (4.0 * F));
+    phase_F_dA(m, x, d);
+    const double k = spd / (2.0 * F);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d[i] *= k;
     return spd;
 }
 

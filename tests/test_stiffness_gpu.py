@@ -1,0 +1,183 @@
+"""GPU gradient with respect to every node's stiffness (through the C ABI) against the oracle.
+
+The parameters are A = C / rho of each node (A11, A13, A33, A55).  Bars:
+  - float64 mode: both sides freeze the same choices on the same field; the GPU
+    differentiates its rsqrt form of the estimate and takes the group-speed derivative
+    from the envelope theorem, the oracle differentiates the phase speed through the
+    Christoffel eigenvector and the group speed by Richardson differences (~1e-12).  Bar:
+    1e-9 relative (see "Ties" for what is compared where).
+  - mixed mode (float32 wavefront math): as for the orientation gradient, cosine
+    similarity >= 0.99999 per component and every entry within 1e-4 of the largest.
+  - Euler's identity on the GPU's own output: travel times are homogeneous of degree
+    -1/2 in the stiffnesses of all nodes together, so sum over nodes of A . dL/dA equals
+    -1/2 sum over (s, r) of dL/dT(s, r) T_s(r); checked at 1e-10 (float64) and 1e-5
+    (mixed), the latter at the full tomography size (256 x 256, 32 sources, 32 receivers).
+  - the orientation gradient returned alongside is bitwise that of the plain adjoint.
+
+Ties.  In an isotropic material around a source the source-box times are mirror
+symmetric, so mirrored stencils give the same value at nodes on the symmetry lines.  The
+value does not depend on which one is taken, but its derivative with respect to A does
+(the two wavefront normals make different angles with the symmetry axis), so T is not
+differentiable there and each side keeps the candidate its own rounding prefers; lambda
+then reaches the nodes between those lines and the source along different paths.  The
+element-wise bars therefore cover the nodes of anisotropic materials (where such ties
+are not generic); every material is also checked through the derivatives along changes
+that keep every tie a tie, which are unique: the per-material sums of all four
+components for an anisotropic material, and of A11 + A13 + A33 and A55 - 2 A13 (the
+changes that keep an isotropic material isotropic) for an isotropic one.
+"""
+import numpy as np
+import pytest
+
+import synthmedia as sm
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("c11", "c13", "c33", "c55")
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+    from paper_2302_10988_amd import Solver
+    assert torch.cuda.is_available()
+    return Solver(0)
+
+
+def _dev(m, dtype):
+    import torch
+    return torch.from_numpy(m.mat_id).cuda(), torch.from_numpy(np.ascontiguousarray(m.orient)).to(dtype).cuda()
+
+
+def _A_nodes(m):
+    tab = np.array([[mat[k] / mat["rho"] for k in KEYS] for mat in m.mats])
+    return tab[m.mat_id]
+
+
+def oracle_grad_A(orc, m, sources, receivers, dLdT):
+    tot = np.zeros((m.nz, m.nx, 4))
+    for s, src in enumerate(sources):
+        g = np.zeros((m.nz, m.nx))
+        for r, rec in enumerate(receivers):
+            g[rec[1], rec[0]] += dLdT[s, r]
+        tot += orc.adjoint(m.h, m.mats, m.mat_id, m.orient, src, g, with_A=True)[2]
+    return tot
+
+
+def _isotropic(mat):
+    c11, c13, c33, c55 = (mat[k] for k in KEYS)
+    return abs(c11 - c33) <= 1e-9 * c11 and abs(c13 - (c11 - 2.0 * c55)) <= 1e-9 * c11
+
+
+def _check_materials(m, got, ref, bar):
+    """Element-wise on anisotropic nodes, tie-invariant material sums everywhere."""
+    aniso = np.zeros(m.mat_id.shape, bool)
+    for mi, mat in enumerate(m.mats):
+        sel = m.mat_id == mi
+        if not sel.any():
+            continue
+        a, b = got[sel].sum(0), ref[sel].sum(0)
+        if _isotropic(mat):
+            a = np.array([a[0] + a[1] + a[2], a[3] - 2.0 * a[1]])
+            b = np.array([b[0] + b[1] + b[2], b[3] - 2.0 * b[1]])
+        else:
+            aniso |= sel
+        err = np.abs(a - b).max() / np.abs(b).max()
+        print("  material %d sums: rel err %.3g" % (mi, err), flush=True)
+        assert err <= bar
+    for k in range(4):
+        scale = np.abs(ref[..., k][aniso]).max()
+        err = np.abs(got[..., k] - ref[..., k])[aniso].max() / scale
+        print("  A%s on anisotropic nodes: max |diff| / max |ref| = %.3g"
+              % (("11", "13", "33", "55")[k], err), flush=True)
+        assert err <= bar
+    return aniso
+
+
+def _euler(m, T, receivers, dLdT, dA):
+    lhs = float((_A_nodes(m) * dA).sum())
+    terms = np.array([[dLdT[s, r] * T[s, rec[1], rec[0]] for r, rec in enumerate(receivers)]
+                      for s in range(T.shape[0])])
+    return lhs, -0.5 * float(terms.sum()), float(np.abs(terms).sum())
+
+
+def _cos(a, b):
+    return float((a * b).sum() / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+@pytest.mark.parametrize("seed,aniso_only", [(5, False), (8, False), (8, True)])
+def test_stiffness_f64_vs_oracle(solver, orc, seed, aniso_only):
+    import torch
+    m = sm.random_medium(53, 41, 0.2e-3, seed=seed, n_mats=3)
+    if aniso_only:
+        m.mats = [sm.TI_STEEL, sm.elliptic(3.6e7, 2.2e7, 1.1e7), sm.CUBIC_STEEL]
+    rng = np.random.default_rng(seed)
+    sources = [m.sources[0], (3, 2), (50, 38)]
+    receivers = [(52, 40), (0, 40), (26, 0), (10, 20), (45, 5)]
+    dLdT = rng.normal(size=(len(sources), len(receivers)))
+    mid, ori = _dev(m, torch.float64)
+    g = torch.from_numpy(dLdT).cuda()
+    print("stiffness f64 vs oracle: seed", seed, flush=True)
+    (dth, dA), T, st = solver.adjoint(m.h, m.mats, mid, ori, sources, receivers, g, precision="f64",
+                                      return_T=True, stiffness=True)
+    assert st["converged"] == 1 and st["choice_mismatches"] == 0
+    dth0, _ = solver.adjoint(m.h, m.mats, mid, ori, sources, receivers, g, precision="f64")
+    assert torch.equal(dth, dth0)
+    ref = oracle_grad_A(orc, m, sources, receivers, dLdT)
+    got = dA.cpu().numpy()
+    _check_materials(m, got, ref, 1e-9)
+    lhs, rhs, mag = _euler(m, T.cpu().numpy(), receivers, dLdT, got)
+    assert abs(lhs - rhs) <= 1e-10 * mag, (lhs, rhs)
+
+
+def test_stiffness_mixed_vs_oracle(solver, orc):
+    import torch
+    m = sm.weld(n=128, h=0.4e-3, seed=0)
+    sources = [(20, 0), (64, 0), (110, 0)]
+    receivers = [(8 * k + 4, 127) for k in range(16)]
+    rng = np.random.default_rng(1)
+    dLdT = rng.normal(size=(len(sources), len(receivers)))
+    mid, ori = _dev(m, torch.float32)
+    print("stiffness mixed vs oracle: weld 128", flush=True)
+    (dth, dA), st = solver.adjoint(m.h, m.mats, mid, ori, sources, receivers,
+                                   torch.from_numpy(dLdT).float().cuda(), stiffness=True)
+    assert st["converged"] == 1 and st["choice_mismatches"] == 0
+    ref = oracle_grad_A(orc, m, sources, receivers, dLdT)
+    got = dA.cpu().numpy().astype(np.float64)
+    aniso = _check_materials(m, got, ref, 1e-4)
+    for k in range(4):
+        c = _cos(got[..., k][aniso], ref[..., k][aniso])
+        print("  component %d on anisotropic nodes: cos %.9f" % (k, c), flush=True)
+        assert c >= 0.99999
+
+
+def test_stiffness_euler_identity_full_size(solver):
+    # the tomography configuration: 256 x 256 nodes, 32 sources on top, 32 receivers below
+    import torch
+    m = sm.adjoint_grid()
+    mid, ori = _dev(m, torch.float32)
+    rng = np.random.default_rng(4)
+    dLdT = rng.normal(size=(len(m.sources), len(m.receivers)))
+    print("stiffness Euler identity: %d x %d, %d x %d" % (m.nx, m.nz, len(m.sources), len(m.receivers)),
+          flush=True)
+    (dth, dA), T, st = solver.adjoint(m.h, m.mats, mid, ori, m.sources, m.receivers,
+                                      torch.from_numpy(dLdT).float().cuda(), return_T=True, stiffness=True)
+    assert st["converged"] == 1 and st["choice_mismatches"] == 0
+    got = dA.cpu().numpy().astype(np.float64)
+    assert np.isfinite(got).all()
+    lhs, rhs, mag = _euler(m, T.cpu().numpy().astype(np.float64), m.receivers, dLdT, got)
+    print("  sum A.dL/dA = %.9g, -1/2 sum g T = %.9g" % (lhs, rhs), flush=True)
+    assert abs(lhs - rhs) <= 1e-5 * mag
+
+
+def test_stiffness_deterministic(solver):
+    import torch
+    m = sm.random_medium(70, 66, 0.2e-3, seed=3, n_mats=2)
+    sources = [m.sources[0], (0, 0)]
+    receivers = [(69, 65), (0, 65), (35, 30)]
+    dLdT = torch.ones((2, 3), dtype=torch.float32, device="cuda")
+    mid, ori = _dev(m, torch.float32)
+    (a, ga), _ = solver.adjoint(m.h, m.mats, mid, ori, sources, receivers, dLdT, stiffness=True)
+    (b, gb), _ = solver.adjoint(m.h, m.mats, mid, ori, sources, receivers, dLdT, stiffness=True,
+                                inner_sweeps=3)
+    assert torch.equal(a, b) and torch.equal(ga, gb)
