@@ -17,7 +17,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SOURCES = ["velocity.c", "fmm.c", "dijkstra.c", "rays.c", "adjoint.c"]
+_SOURCES = ["velocity.c", "fmm.c", "dijkstra.c", "rays.c", "adjoint.c", "nested.c"]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -87,6 +87,10 @@ def _load():
     lib.or_qp_phase_speed_dA.argtypes = [M, D, ctypes.POINTER(D)]
     lib.or_qp_group_speed_dA.argtypes = [M, D, ctypes.POINTER(D)]
     lib.or_field_choices.argtypes = [I, I, D, M, P, P, P, P, P]
+    lib.or_fmm_seeded.argtypes = [I, I, D, M, I, P, P, P, P, I, I, I, P, ctypes.POINTER(D)]
+    lib.or_fmm_seeded.restype = I64
+    lib.or_solve_refined.argtypes = [I, I, D, M, I, P, P, I, I, I, ctypes.POINTER(I), ctypes.POINTER(I), D, P]
+    lib.or_solve_refined.restype = I
     lib.or_frozen_field.argtypes = [I, I, D, M, P, P, I, I, I, P, P, ctypes.c_int64, P]
     _lib = lib
     return lib
@@ -336,3 +340,51 @@ def frozen_field(h, mats, mat_id, orient, src, choice, pops, R=2):
                             int(src[1]), int(R), _ptr(np.ascontiguousarray(choice, dtype=np.int32)),
                             _ptr(pops), len(pops), _ptr(T))
     return T
+
+
+# ---------------------------------------------------------------------------------------
+# Section 4.4: nested fine grids around the source; whole-grid refinement
+# ---------------------------------------------------------------------------------------
+PAPER_LEVELS = ((27, 1), (9, 6), (3, 13))
+
+
+def fmm_seeded(h, mats, mat_id, orient, fixed, T0, centre, stop_r=-1):
+    """Heap march from the nodes marked in fixed (times T0).  Returns (T, known, t_stop)."""
+    mat_id, orient = _medium(mat_id, orient)
+    nz, nx = mat_id.shape
+    fixed = np.ascontiguousarray(fixed, dtype=np.uint8)
+    T = np.ascontiguousarray(T0, dtype=np.float64).copy()
+    known = np.zeros((nz, nx), np.uint8)
+    ts = ctypes.c_double()
+    n = _load().or_fmm_seeded(nx, nz, float(h), _mat_array(mats), len(list(mats)), _ptr(mat_id), _ptr(orient),
+                              _ptr(fixed), _ptr(T), int(centre[0]), int(centre[1]), int(stop_r), _ptr(known),
+                              ctypes.byref(ts))
+    if n < 0:
+        raise ValueError("oracle: invalid input")
+    return T, known.astype(bool), ts.value
+
+
+def solve_refined(h, mats, mat_id, orient, src, levels=PAPER_LEVELS, vor_half=0.5):
+    """Travel times with nested fine grids around the source: levels = ((density, radius),
+    ...) from the finest; straight rays within vor_half cells of the source (Section 4.4)."""
+    mat_id, orient = _medium(mat_id, orient)
+    nz, nx = mat_id.shape
+    T = np.empty((nz, nx))
+    dens = (ctypes.c_int * max(len(levels), 1))(*[int(d) for d, _ in levels])
+    rads = (ctypes.c_int * max(len(levels), 1))(*[int(r) for _, r in levels])
+    st = _load().or_solve_refined(nx, nz, float(h), _mat_array(mats), len(list(mats)), _ptr(mat_id), _ptr(orient),
+                                  int(src[0]), int(src[1]), len(levels), dens, rads, float(vor_half), _ptr(T))
+    if st != 0:
+        raise ValueError("oracle: invalid input")
+    return T
+
+
+def refine_medium(mat_id, orient, s):
+    """The medium on an s-times finer grid (s odd): every node takes the material and
+    orientation of the nearest original node."""
+    assert s >= 1 and s % 2 == 1
+    nz, nx = np.shape(mat_id)
+    jz = (np.arange((nz - 1) * s + 1) + s // 2) // s
+    ix = (np.arange((nx - 1) * s + 1) + s // 2) // s
+    return (np.ascontiguousarray(np.asarray(mat_id)[np.ix_(jz, ix)]),
+            np.ascontiguousarray(np.asarray(orient)[np.ix_(jz, ix)]))

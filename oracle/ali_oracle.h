@@ -97,6 +97,24 @@ int64_t or_solve_fmm(int nx, int nz, double h, const or_material* mats, int n_ma
                      const uint8_t* mat_id, const double* orient, int si, int sj, int R,
                      double* T, int64_t* pop_order, double* pop_values);
 
+/* Heap Fast Marching from a seeded set: fixed[] marks the nodes whose T is given (all
+   other T are overwritten).  With stop_r >= 0 the march ends at the first accepted node
+   farther than stop_r (Chebyshev) from (ci, cj); its time goes to *t_stop (+inf if the
+   march ran to the end).  known[] receives the accepted nodes.  Returns the number of
+   accepted nodes, or -1 on invalid input. */
+int64_t or_fmm_seeded(int nx, int nz, double h, const or_material* mats, int n_mats, const uint8_t* mat_id,
+                      const double* orient, const uint8_t* fixed, double* T, int ci, int cj, int stop_r,
+                      uint8_t* known, double* t_stop);
+
+/* Nested fine grids around the source (Section 4.4): n_levels grids of density[l] nodes
+   per spacing (odd, each divisible by the next) used out to radius[l] cells (Chebyshev,
+   increasing), then the grid itself; straight rays in the square of half-width vor_half
+   cells around the source on the finest grid.  T[nz*nx] out.  Returns 0 or -1.
+   parity unpinned beyond the accuracy pins (readings). */
+int or_solve_refined(int nx, int nz, double h, const or_material* mats, int n_mats, const uint8_t* mat_id,
+                     const double* orient, int si, int sj, int n_levels, const int* density,
+                     const int* radius, double vor_half, double* T);
+
 /* Number of Phi_D evaluations made by the last or_solve_fmm call (statistics). */
 int64_t or_last_phi_evals(void);
 

@@ -247,30 +247,36 @@ static int valid_inputs(int nx, int nz, double h, const or_material* mats, int n
     return 1;
 }
 
-int64_t or_solve_fmm(int nx, int nz, double h, const or_material* mats, int n_mats,
-                     const uint8_t* mat_id, const double* orient, int si, int sj, int R,
-                     double* T, int64_t* pop_order, double* pop_values) {
-    if (!valid_inputs(nx, nz, h, mats, n_mats, mat_id, orient, si, sj)) return -1;
+/* The march from a set of fixed nodes (their T given).  Nodes are accepted in (tau, index)
+   order; with stop_r >= 0 the march ends at the first accepted node farther than stop_r
+   (Chebyshev) from (ci, cj), which is not marked known and whose time goes to *t_stop. */
+static int64_t fmm_core(int nx, int nz, double h, const or_material* mats, const uint8_t* mat_id,
+                        const double* orient, const uint8_t* fixed, double* T, int ci, int cj, int stop_r,
+                        uint8_t* known, int64_t* pop_order, double* pop_values, double* t_stop) {
     int64_t N = (int64_t)nx * nz;
-    uint8_t* fixed = calloc(N, 1);
-    uint8_t* known = calloc(N, 1);
     int64_t* ver = calloc(N, sizeof(int64_t));
-    for (int64_t p = 0; p < N; ++p) T[p] = INFINITY;
-    or_source_box(nx, nz, h, mats, mat_id, orient, si, sj, R, T, fixed);
     heap_t hp = {0, 0, 0};
-    for (int64_t p = 0; p < N; ++p)
+    for (int64_t p = 0; p < N; ++p) {
+        known[p] = 0;
         if (fixed[p]) hpush(&hp, (hent){T[p], p, 0});
+        else T[p] = INFINITY;
+    }
     ctx_t c = {nx, nz, h, mats, mat_id, orient, T};
     int64_t npop = 0;
     g_phi_evals = 0;
+    if (t_stop) *t_stop = INFINITY;
     while (hp.n > 0) {
         hent e = hpop(&hp);
         if (known[e.idx] || e.ver != ver[e.idx]) continue;   /* stale entry */
+        int pi = (int)(e.idx % nx), pj = (int)(e.idx / nx);
+        if (stop_r >= 0 && (abs(pi - ci) > stop_r || abs(pj - cj) > stop_r)) {
+            if (t_stop) *t_stop = e.t;
+            break;
+        }
         known[e.idx] = 1;
         if (pop_order) pop_order[npop] = e.idx;
         if (pop_values) pop_values[npop] = e.t;
         ++npop;
-        int pi = (int)(e.idx % nx), pj = (int)(e.idx / nx);
         for (int k = 0; k < 12; ++k) {
             int di = pi + DIAMOND[k][0], dj = pj + DIAMOND[k][1];
             if (!in_grid(&c, di, dj)) continue;
@@ -285,8 +291,30 @@ int64_t or_solve_fmm(int nx, int nz, double h, const or_material* mats, int n_ma
             }
         }
     }
-    free(hp.a); free(fixed); free(known); free(ver);
+    free(hp.a); free(ver);
     return npop;
+}
+
+int64_t or_solve_fmm(int nx, int nz, double h, const or_material* mats, int n_mats,
+                     const uint8_t* mat_id, const double* orient, int si, int sj, int R,
+                     double* T, int64_t* pop_order, double* pop_values) {
+    if (!valid_inputs(nx, nz, h, mats, n_mats, mat_id, orient, si, sj)) return -1;
+    int64_t N = (int64_t)nx * nz;
+    uint8_t* fixed = calloc(N, 1);
+    uint8_t* known = calloc(N, 1);
+    for (int64_t p = 0; p < N; ++p) T[p] = INFINITY;
+    or_source_box(nx, nz, h, mats, mat_id, orient, si, sj, R, T, fixed);
+    int64_t npop = fmm_core(nx, nz, h, mats, mat_id, orient, fixed, T, si, sj, -1, known, pop_order,
+                            pop_values, NULL);
+    free(fixed); free(known);
+    return npop;
+}
+
+int64_t or_fmm_seeded(int nx, int nz, double h, const or_material* mats, int n_mats, const uint8_t* mat_id,
+                      const double* orient, const uint8_t* fixed, double* T, int ci, int cj, int stop_r,
+                      uint8_t* known, double* t_stop) {
+    if (!valid_inputs(nx, nz, h, mats, n_mats, mat_id, orient, ci, cj)) return -1;
+    return fmm_core(nx, nz, h, mats, mat_id, orient, fixed, T, ci, cj, stop_r, known, NULL, NULL, t_stop);
 }
 
 /* ---- The local operator and an independent sweeping driver -------------------------- */
