@@ -141,6 +141,45 @@ ali_status ali_solve_traveltime_f64(ali_handle* h, const ali_grid* grid,
                                     const ali_options* opt, double* d_T,
                                     ali_solve_stats* stats);
 
+/* ---- nested fine grids around the source (paper Section 4.4) ------------------------- */
+
+#define ALI_MAX_LEVELS 8
+typedef struct {
+    int32_t n_levels;                  /* fine grids, finest first; 0 .. ALI_MAX_LEVELS       */
+    int32_t density[ALI_MAX_LEVELS];   /* nodes per grid spacing: odd, 3 .. 255, each divisible
+                                          by the next                                          */
+    int32_t radius[ALI_MAX_LEVELS];    /* the grid is used until the front passes this Chebyshev
+                                          radius around the source [cells]; non-decreasing    */
+    double start_half_width;           /* straight rays on the finest grid within this many cells
+                                          of the source (both directions); 0.5 = the source
+                                          node's own cell; (0, radius[0] + 1]                  */
+} ali_refine;
+
+/* The paper's choice: densities 27, 9, 3 out to 1, 6, 13 cells; straight rays in the source
+   node's own cell.  Host only. */
+void ali_default_refine(ali_refine* r);
+
+/* Travel-time fields with nested fine grids around every source (Section 4.4) in place of
+   the straight-ray box.  Per source, a sequence of grids centred on the source node, finest
+   first (level l: spacing h / density[l], extending radius[l] + 1 cells around the source,
+   clipped to the grid; every fine node takes the material and orientation of the nearest
+   grid node).  The finest grid starts from straight rays at the source material's group
+   speed inside start_half_width cells; on each level the march runs until it reaches a node
+   farther than radius[l] from the source, and the nodes reached strictly earlier seed the
+   next coarser grid (the nodes that coincide with them keep their times); the grid itself
+   comes last.  opt->src_box_radius is not used.  Other arguments, arithmetic, errors and
+   output as ali_solve_traveltime; ref == NULL means ali_default_refine.  Scratch grows with
+   the fine grids (27 x 3 cells around each source by default: about 36k nodes per source).
+   stats->ms is the host time of the call; the other counters add up every level. */
+ali_status ali_solve_traveltime_refined(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                        int32_t n_mats, const uint8_t* d_mat_id, const float* d_orient,
+                                        const ali_node* srcs, int32_t n_src, const ali_options* opt,
+                                        const ali_refine* ref, float* d_T, ali_solve_stats* stats);
+ali_status ali_solve_traveltime_refined_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                            int32_t n_mats, const uint8_t* d_mat_id, const double* d_orient,
+                                            const ali_node* srcs, int32_t n_src, const ali_options* opt,
+                                            const ali_refine* ref, double* d_T, ali_solve_stats* stats);
+
 /* Fields of many media in one call: every source of every medium, relaxed together with
    one time threshold per field (media of different sizes progress independently).
      media[n_media]  the media (see ali_medium); 1 <= n_media

@@ -191,6 +191,44 @@ class Solver:
         self._check(st)
         return out, stats.as_dict()
 
+    def solve_refined(self, h, mats, mat_id, orient, sources, levels=((27, 1), (9, 6), (3, 13)),
+                      start_half_width=0.5, out=None, precision="f32", max_sweeps=None,
+                      inner_sweeps=None, band_cells=None, arith="mixed", **extra):
+        """Travel-time fields [n_src, nz, nx] with nested fine grids around every source
+        (Section 4.4): levels = ((density, radius), ...) from the finest; straight rays on the
+        finest grid within start_half_width cells of the source.  Other arguments as solve.
+        Returns (T, stats dict)."""
+        import torch
+        nz, nx = mat_id.shape
+        fdt = torch.float32 if precision == "f32" else torch.float64
+        m_arr, nm = _materials(mats)
+        s_arr, ns = _nodes(sources)
+        g = _lib.Grid(int(nx), int(nz), float(h))
+        opt = default_options(max_sweeps=max_sweeps, inner_sweeps=inner_sweeps, band_cells=band_cells,
+                              arith=_lib.ARITH[arith], **extra)
+        levels = [tuple(v) for v in levels]
+        if len(levels) > _lib.MAX_LEVELS:
+            raise ValueError("at most %d levels" % _lib.MAX_LEVELS)
+        ref = _lib.Refine()
+        ref.n_levels = len(levels)
+        for k, (d, r) in enumerate(levels):
+            ref.density[k] = int(d)
+            ref.radius[k] = int(r)
+        ref.start_half_width = float(start_half_width)
+        if out is None:
+            out = torch.empty((ns, nz, nx), dtype=fdt, device=mat_id.device)
+        p_id = _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id")
+        p_or = _dev_ptr(orient, fdt, (nz, nx), "orient")
+        p_T = _dev_ptr(out, fdt, (ns, nz, nx), "out")
+        stats = _lib.SolveStats()
+        self._sync_stream()
+        fn = (self._lib.ali_solve_traveltime_refined if precision == "f32"
+              else self._lib.ali_solve_traveltime_refined_f64)
+        st = fn(self._h, ctypes.byref(g), m_arr, nm, p_id, p_or, s_arr, ns, ctypes.byref(opt), ctypes.byref(ref),
+                p_T, ctypes.byref(stats))
+        self._check(st)
+        return out, stats.as_dict()
+
     def trace_rays(self, h, mats, mat_id, orient, T, sources, receivers, window=None, sub=None,
                    max_pts=None):
         """Ray paths from every receiver to every source through the fields T

@@ -38,6 +38,14 @@ class Options(ctypes.Structure):
                 ("ray_window", ctypes.c_int32), ("ray_max_pts", ctypes.c_int32),
                 ("arith", ctypes.c_int32), ("ray_sub", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
+MAX_LEVELS = 8
+
+
+class Refine(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("density", ctypes.c_int32 * MAX_LEVELS),
+                ("radius", ctypes.c_int32 * MAX_LEVELS), ("start_half_width", ctypes.c_double)]
+
+
 ARITH = {"mixed": 0, "f32": 1, "f64": 2}
 TUNE_CANDIDATES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4), (3, 4)]   # (band_cells, inner_sweeps)
 
@@ -72,6 +80,14 @@ SIGNATURES = {
     "ali_destroy": (ctypes.c_int, [_P]),
     "ali_set_stream": (ctypes.c_int, [_P, _P]),
     "ali_default_options": (None, [ctypes.POINTER(Options)]),
+    "ali_default_refine": (None, [ctypes.POINTER(Refine)]),
+    "ali_solve_traveltime_refined": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32,
+                                                    _P, _P, ctypes.POINTER(Node), _I32, ctypes.POINTER(Options),
+                                                    ctypes.POINTER(Refine), _P, ctypes.POINTER(SolveStats)]),
+    "ali_solve_traveltime_refined_f64": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32,
+                                                        _P, _P, ctypes.POINTER(Node), _I32,
+                                                        ctypes.POINTER(Options), ctypes.POINTER(Refine), _P,
+                                                        ctypes.POINTER(SolveStats)]),
     "ali_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ali_last_error": (ctypes.c_char_p, [_P]),
     "ali_solve_traveltime": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32,

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libali.so")
-SOURCES = ["ali_capi.hip", "ali_solve.hip", "ali_rays.hip", "ali_adjoint.hip", "ali_batch.hip"]
+SOURCES = ["ali_capi.hip", "ali_solve.hip", "ali_rays.hip", "ali_adjoint.hip", "ali_refine.hip"]
 
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1,0 +1,377 @@
+// ali_refine.hip -- nested fine grids around each source (paper Section 4.4, propagation
+// around the source), gfx950.
+//
+// Every source gets a sequence of grids centred on its node, finest first; level l has
+// density d_l (nodes per working-grid spacing, odd, each divisible by the next) and is
+// used out to radius r_l working cells (Chebyshev).  Per level, for all sources at once:
+//   1. k_level_medium: the level grid of each source takes the material and orientation
+//      of the nearest working-grid node (odd densities make it unique);
+//   2. seeds: on the finest level, straight rays at the source material's group speed in
+//      the square of half-width `start_half_width` cells around the source (by default
+//      the source node's own cell, where the material cannot change); on later levels the
+//      nodes that coincide with known nodes of the previous level;
+//   3. the relaxation of the level's fields (one medium per source, one field each) with
+//      those seeds fixed: the same kernels as every forward solve;
+//   4. k_level_stop: per source, the earliest time beyond r_l.  A heap march would switch
+//      grids at that node, so the nodes known at the switch are those strictly earlier:
+//      the fixed point of the level restricted to them equals the march (a node's value
+//      depends only on earlier nodes).
+// The working grid itself is the last level: all sources' fields in one batch, seeded
+// from the coarsest fine level.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <chrono>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "ali_solve.hpp"
+
+namespace ali {
+
+// one source's grid at one level: node (a, b) of the level sits at working-grid position
+// (si + a / d, sj + b / d); a in [a_lo, a_lo + nx), b in [b_lo, b_lo + nz)
+struct LevelDev {
+    int a_lo, b_lo, nx, nz;
+    int si, sj;               // the source node on the working grid
+    int d;                    // density relative to the working grid
+    int stop;                 // level cells: the level is used out to this Chebyshev radius
+    int64_t node_off;         // first node in the level's per-node arrays
+    int64_t t_off;            // first node in the level's field array
+    uint32_t unit_off;        // first tile unit
+    int ntx;
+};
+
+// nearest multiple index of a / d for odd d (a half never occurs)
+__device__ __forceinline__ int near_div(int a, int d) {
+    const int q = a + (d - 1) / 2;
+    return q >= 0 ? q / d : -((-q + d - 1) / d);
+}
+
+template <typename oreal>
+__global__ void k_level_medium(const LevelDev* __restrict__ lv, int nx_w, const uint8_t* __restrict__ mat_w,
+                               const oreal* __restrict__ ori_w, uint8_t* __restrict__ mat_l,
+                               oreal* __restrict__ ori_l) {
+    const LevelDev L = lv[blockIdx.y];
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)L.nx * L.nz) return;
+    const int a = L.a_lo + (int)(q % L.nx), b = L.b_lo + (int)(q / L.nx);
+    const int64_t p = (int64_t)(L.sj + near_div(b, L.d)) * nx_w + (L.si + near_div(a, L.d));
+    mat_l[L.node_off + q] = mat_w[p];
+    ori_l[L.node_off + q] = ori_w[p];
+}
+
+__device__ __forceinline__ void set_fixed(uint32_t* __restrict__ fixmask, const LevelDev& L, int i, int j) {
+    const uint32_t unit = L.unit_off + (uint32_t)((j / TZ) * L.ntx + i / TX);
+    const int bit = (j % TZ) * TX + (i % TX);
+    atomicOr(&fixmask[(int64_t)unit * NODE_WORDS + (bit >> 5)], 1u << (bit & 31));
+}
+
+// finest level: straight rays from the source inside |a|, |b| < half * d, +inf elsewhere
+template <typename real, typename oreal>
+__global__ void k_seed_start(const LevelDev* __restrict__ lv, int nx_w, double h_w, double half,
+                             const MatA* __restrict__ A, int n_mats, const uint8_t* __restrict__ mat_w,
+                             const oreal* __restrict__ ori_w, real* __restrict__ T, uint32_t* __restrict__ fixmask) {
+    const LevelDev L = lv[blockIdx.y];
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)L.nx * L.nz) return;
+    const int i = (int)(q % L.nx), j = (int)(q / L.nx);
+    const int a = L.a_lo + i, b = L.b_lo + j;
+    real v = dinf<real>();
+    const double lim = half * L.d;
+    if (fabs((double)a) < lim && fabs((double)b) < lim) {
+        double t = 0.0;
+        if (a != 0 || b != 0) {
+            const int64_t ps = (int64_t)L.sj * nx_w + L.si;
+            const double phi = atan2((double)b, (double)a) - (double)ori_w[ps];
+            // an id outside the table is reported by the solve's own check; read a valid entry
+            const int mid = mat_w[ps] < n_mats ? mat_w[ps] : 0;
+            t = sqrt((double)a * a + (double)b * b) * (h_w / L.d) / group_speed(A[mid], phi);
+        }
+        v = (real)t;
+        set_fixed(fixmask, L, i, j);
+    }
+    T[L.t_off + q] = v;
+}
+
+// later levels: nodes that coincide with nodes of the finer level known before its stop
+template <typename real>
+__global__ void k_seed_transfer(const LevelDev* __restrict__ fine, const real* __restrict__ Tf,
+                                const real* __restrict__ tstop, const LevelDev* __restrict__ lv,
+                                real* __restrict__ T, uint32_t* __restrict__ fixmask) {
+    const LevelDev L = lv[blockIdx.y];
+    const LevelDev F = fine[blockIdx.y];
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)L.nx * L.nz) return;
+    const int i = (int)(q % L.nx), j = (int)(q / L.nx);
+    const int k = F.d / L.d;
+    const int fa = (L.a_lo + i) * k - F.a_lo, fb = (L.b_lo + j) * k - F.b_lo;
+    real v = dinf<real>();
+    if (fa >= 0 && fb >= 0 && fa < F.nx && fb < F.nz) {
+        const real t = Tf[F.t_off + (int64_t)fb * F.nx + fa];
+        if (t < tstop[blockIdx.y]) {
+            v = t;
+            set_fixed(fixmask, L, i, j);
+        }
+    }
+    T[L.t_off + q] = v;
+}
+
+// per source: the smallest time farther than `stop` level cells from the source
+template <typename real>
+__global__ void k_level_stop(const LevelDev* __restrict__ lv, const real* __restrict__ T, real* __restrict__ tstop) {
+    const LevelDev L = lv[blockIdx.x];
+    real m = dinf<real>();
+    for (int64_t q = threadIdx.x; q < (int64_t)L.nx * L.nz; q += blockDim.x) {
+        const int a = L.a_lo + (int)(q % L.nx), b = L.b_lo + (int)(q / L.nx);
+        if (abs(a) > L.stop || abs(b) > L.stop) {
+            const real t = T[L.t_off + q];
+            m = t < m ? t : m;
+        }
+    }
+    __shared__ real red[256];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x + s] < red[threadIdx.x] ? red[threadIdx.x + s]
+                                                                                             : red[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tstop[blockIdx.x] = red[0];
+}
+
+// host: one level's grids (clipped to the working grid) and their offsets
+static std::vector<LevelDev> level_grids(const ali_grid& g, const ali_node* srcs, int n_src, int d, int W, int stop,
+                                         std::vector<ali_medium>& media, std::vector<ali_node>& lsrc,
+                                         double h_w, int n_mats) {
+    std::vector<LevelDev> lv(n_src);
+    media.assign(n_src, ali_medium{});
+    lsrc.assign(n_src, ali_node{});
+    int64_t node = 0;
+    uint32_t unit = 0;
+    for (int k = 0; k < n_src; ++k) {
+        LevelDev& L = lv[k];
+        const int si = srcs[k].i, sj = srcs[k].j;
+        L.si = si; L.sj = sj; L.d = d; L.stop = stop;
+        L.a_lo = std::max(-W, -si * d);
+        const int a_hi = std::min(W, (g.nx - 1 - si) * d);
+        L.b_lo = std::max(-W, -sj * d);
+        const int b_hi = std::min(W, (g.nz - 1 - sj) * d);
+        L.nx = a_hi - L.a_lo + 1;
+        L.nz = b_hi - L.b_lo + 1;
+        L.node_off = node;
+        L.t_off = node;              // one field per level medium
+        L.unit_off = unit;
+        L.ntx = (L.nx + TX - 1) / TX;
+        ali_medium& m = media[k];
+        m.grid.nx = L.nx; m.grid.nz = L.nz; m.grid.h = h_w / d;
+        m.mat_offset = 0; m.n_mats = n_mats;
+        m.node_offset = node;
+        m.src_offset = k; m.n_src = 1;
+        m.rec_offset = 0; m.n_rec = 0;
+        lsrc[k].i = -L.a_lo;
+        lsrc[k].j = -L.b_lo;
+        node += (int64_t)L.nx * L.nz;
+        unit += (uint32_t)(L.ntx * ((L.nz + TZ - 1) / TZ));
+    }
+    return lv;
+}
+
+static void add_stats(ali_solve_stats& acc, const ali_solve_stats& s) {
+    acc.node_updates += s.node_updates;
+    acc.stencil_evals += s.stencil_evals;
+    acc.tile_visits += s.tile_visits;
+    acc.outer_iters += s.outer_iters;
+    acc.relax_ms += s.relax_ms;
+    acc.converged = acc.converged && s.converged;
+}
+
+template <typename real, typename mreal, typename oreal, typename outreal>
+static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
+                               const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs, int32_t n_src,
+                               const ali_options* opt_in, const ali_refine* ref_in, outreal* d_out,
+                               ali_solve_stats* stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    ali_options opt;
+    ali_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    ali_refine ref;
+    ali_default_refine(&ref);
+    if (ref_in) ref = *ref_in;
+    if (!grid) return H->fail(ALI_EINVAL, "grid is NULL");
+    if (!d_out) return H->fail(ALI_EINVAL, "d_T is NULL");
+    const ali_medium mw = single_medium(grid, n_mats, n_src, 0);
+    ali_status st = validate_batch(H, &mw, 1, mats, n_mats, d_mat_id, d_orient, srcs, nullptr);
+    if (st != ALI_OK) return st;
+    const int nl = ref.n_levels;
+    if (nl < 0 || nl > ALI_MAX_LEVELS) return H->fail(ALI_EINVAL, "n_levels out of range [0, ALI_MAX_LEVELS]");
+    if (!(ref.start_half_width > 0.0) || !(ref.start_half_width <= 64.0))
+        return H->fail(ALI_EINVAL, "start_half_width out of range (0, 64]");
+    for (int l = 0; l < nl; ++l) {
+        const int next = l + 1 < nl ? ref.density[l + 1] : 1;
+        if (ref.density[l] < 3 || ref.density[l] % 2 == 0 || ref.density[l] > 255 || ref.density[l] % next != 0)
+            return H->fail(ALI_EINVAL, "densities must be odd, in [3, 255], each divisible by the next");
+        if (ref.radius[l] < 0 || (l > 0 && ref.radius[l] < ref.radius[l - 1]))
+            return H->fail(ALI_EINVAL, "radii must be >= 0 and non-decreasing");
+        if ((int64_t)(ref.radius[l] + 1) * ref.density[l] > 4096)
+            return H->fail(ALI_EINVAL, "a fine grid would exceed 8193 nodes per side");
+    }
+    if (nl > 0 && ref.start_half_width > ref.radius[0] + 1)
+        return H->fail(ALI_EINVAL, "start_half_width exceeds the finest grid");
+    if (set_device(H) != ALI_OK) return ALI_EDEVICE;
+    hipStream_t S = H->stream;
+    const int B = 256;
+
+    // material table for the straight rays (A = C / rho)
+    std::vector<MatA> hA(n_mats);
+    for (int k = 0; k < n_mats; ++k)
+        hA[k] = MatA{mats[k].c11 / mats[k].rho, mats[k].c13 / mats[k].rho, mats[k].c33 / mats[k].rho,
+                     mats[k].c55 / mats[k].rho};
+    void *d_A = nullptr, *d_stop = nullptr, *d_fm = nullptr;
+    if (!H->scratch("ref_A", sizeof(MatA) * n_mats, &d_A) || !H->scratch("ref_stop", sizeof(real) * n_src, &d_stop))
+        return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+    HIPCK(H, hipMemcpyAsync(d_A, hA.data(), sizeof(MatA) * n_mats, hipMemcpyHostToDevice, S));
+
+    ali_solve_stats acc{};
+    acc.converged = 1;
+    const int64_t NW = (int64_t)grid->nx * grid->nz;
+    constexpr bool same_out = std::is_same<real, outreal>::value;
+    std::vector<LevelDev> prev;
+    const real* Tprev = nullptr;
+    const LevelDev* dprev = nullptr;
+    for (int l = 0; l <= nl; ++l) {
+        const bool last = l == nl;
+        const int d = last ? 1 : ref.density[l];
+        std::vector<ali_medium> media;
+        std::vector<ali_node> lsrc;
+        std::vector<LevelDev> lv;
+        const uint8_t* mid = d_mat_id;
+        const oreal* ori = d_orient;
+        real* T = nullptr;
+        int64_t nodes = 0, units = 0;
+        if (!last) {
+            lv = level_grids(*grid, srcs, n_src, d, (ref.radius[l] + 1) * d, ref.radius[l] * d, media, lsrc,
+                             grid->h, n_mats);
+            nodes = lv.back().node_off + (int64_t)lv.back().nx * lv.back().nz;
+            units = unit_offsets(media.data(), n_src).back();
+        } else {
+            // the working grid: every source's field in one medium
+            media.assign(1, mw);
+            lsrc.assign(srcs, srcs + n_src);
+            lv.resize(n_src);
+            const int ntx = (grid->nx + TX - 1) / TX, ntz = (grid->nz + TZ - 1) / TZ;
+            for (int k = 0; k < n_src; ++k) {
+                LevelDev& L = lv[k];
+                L.si = srcs[k].i; L.sj = srcs[k].j; L.d = 1; L.stop = -1;
+                L.a_lo = -L.si; L.b_lo = -L.sj; L.nx = grid->nx; L.nz = grid->nz;
+                L.node_off = 0; L.t_off = (int64_t)k * NW;
+                L.unit_off = (uint32_t)((int64_t)k * ntx * ntz);
+                L.ntx = ntx;
+            }
+            nodes = NW * n_src;
+            units = (int64_t)ntx * ntz * n_src;
+        }
+        const std::string pp = std::to_string(l & 1);
+        void *d_lv = nullptr, *d_T = nullptr, *d_mid = nullptr, *d_ori = nullptr;
+        if (!H->scratch(("ref_lv" + pp).c_str(), sizeof(LevelDev) * n_src, &d_lv) ||
+            !H->scratch("ref_fm", sizeof(uint32_t) * NODE_WORDS * units, &d_fm))
+            return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+        if (last && same_out) {
+            d_T = (void*)d_out;
+        } else if (!H->scratch(("ref_T" + pp).c_str(), sizeof(real) * nodes, &d_T)) {
+            return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+        }
+        T = (real*)d_T;
+        HIPCK(H, hipMemcpyAsync(d_lv, lv.data(), sizeof(LevelDev) * n_src, hipMemcpyHostToDevice, S));
+        HIPCK(H, hipMemsetAsync(d_fm, 0, sizeof(uint32_t) * NODE_WORDS * units, S));
+        int64_t maxn = 0;
+        for (const LevelDev& L : lv) maxn = std::max(maxn, (int64_t)L.nx * L.nz);
+        const dim3 g2((unsigned)((maxn + B - 1) / B), (unsigned)n_src);
+        if (!last) {
+            if (!H->scratch(("ref_mid" + pp).c_str(), nodes, &d_mid) ||
+                !H->scratch(("ref_ori" + pp).c_str(), sizeof(oreal) * nodes, &d_ori))
+                return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+            hipLaunchKernelGGL((k_level_medium<oreal>), g2, dim3(B), 0, S, (const LevelDev*)d_lv, grid->nx, d_mat_id,
+                               d_orient, (uint8_t*)d_mid, (oreal*)d_ori);
+            mid = (const uint8_t*)d_mid;
+            ori = (const oreal*)d_ori;
+        }
+        if (l == 0)
+            hipLaunchKernelGGL((k_seed_start<real, oreal>), g2, dim3(B), 0, S, (const LevelDev*)d_lv, grid->nx,
+                               grid->h, ref.start_half_width, (const MatA*)d_A, n_mats, d_mat_id, d_orient, T,
+                               (uint32_t*)d_fm);
+        else
+            hipLaunchKernelGGL((k_seed_transfer<real>), g2, dim3(B), 0, S, dprev, Tprev, (const real*)d_stop,
+                               (const LevelDev*)d_lv, T, (uint32_t*)d_fm);
+        HIPCK(H, hipGetLastError());
+        ali_solve_stats ls{};
+        st = solve_fields<real, mreal, oreal>(H, media.data(), (int32_t)media.size(), mats, n_mats, mid, ori,
+                                              lsrc.data(), nullptr, opt, T, &ls, nullptr, (const uint32_t*)d_fm);
+        if (st != ALI_OK && st != ALI_ENOCONV) return st;
+        add_stats(acc, ls);
+        if (!last) {
+            hipLaunchKernelGGL((k_level_stop<real>), dim3((unsigned)n_src), dim3(B), 0, S, (const LevelDev*)d_lv,
+                               (const real*)T, (real*)d_stop);
+            HIPCK(H, hipGetLastError());
+        } else if (!same_out) {
+            hipLaunchKernelGGL((k_convert<outreal, real>), dim3((unsigned)((nodes + B - 1) / B)), dim3(B), 0, S,
+                               d_out, (const real*)T, nodes);
+            HIPCK(H, hipGetLastError());
+        }
+        Tprev = T;
+        dprev = (const LevelDev*)d_lv;
+        prev = lv;
+    }
+    HIPCK(H, hipStreamSynchronize(S));
+    if (stats) {
+        *stats = acc;
+        stats->nodes = NW * n_src;
+        stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!acc.converged) return H->fail(ALI_ENOCONV, "relaxation reached max_sweeps");
+    return ALI_OK;
+}
+
+}  // namespace ali
+
+using namespace ali;
+
+extern "C" void ali_default_refine(ali_refine* r) {
+    if (!r) return;
+    *r = ali_refine{};
+    r->n_levels = 3;
+    r->density[0] = 27; r->density[1] = 9; r->density[2] = 3;
+    r->radius[0] = 1; r->radius[1] = 6; r->radius[2] = 13;
+    r->start_half_width = 0.5;
+}
+
+extern "C" ali_status ali_solve_traveltime_refined(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                                   int32_t n_mats, const uint8_t* d_mat_id, const float* d_orient,
+                                                   const ali_node* srcs, int32_t n_src, const ali_options* opt,
+                                                   const ali_refine* ref, float* d_T, ali_solve_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
+    switch (arith) {
+        case ALI_ARITH_MIXED:
+            return refined_impl<double, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
+                                                             opt, ref, d_T, stats);
+        case ALI_ARITH_F32:
+            return refined_impl<float, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
+                                                            opt, ref, d_T, stats);
+        case ALI_ARITH_F64:
+            return refined_impl<double, double, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
+                                                              opt, ref, d_T, stats);
+    }
+    return h->fail(ALI_EINVAL, "unknown arith mode");
+}
+
+extern "C" ali_status ali_solve_traveltime_refined_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                                       int32_t n_mats, const uint8_t* d_mat_id, const double* d_orient,
+                                                       const ali_node* srcs, int32_t n_src, const ali_options* opt,
+                                                       const ali_refine* ref, double* d_T, ali_solve_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    return refined_impl<double, double, double, double>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt,
+                                                        ref, d_T, stats);
+}

@@ -70,7 +70,7 @@ __global__ void k_prep(int nx, int nz, double h, int n_mats, const MatDev<mreal>
 // initial values of the fields f0 .. f0 + gridDim.y - 1 (all in one medium)
 template <typename real, typename mreal, typename oreal>
 __global__ void k_init(const FieldDev* __restrict__ fields, int f0, double h, const MatDev<mreal>* __restrict__ mats,
-                       const uint8_t* __restrict__ mat_id, const oreal* __restrict__ orient, int R,
+                       int n_mats, const uint8_t* __restrict__ mat_id, const oreal* __restrict__ orient, int R,
                        real* __restrict__ T, uint32_t* __restrict__ flags) {
     const FieldDev fd = fields[f0 + blockIdx.y];
     const int nx = fd.nx;
@@ -88,13 +88,36 @@ __global__ void k_init(const FieldDev* __restrict__ fields, int f0, double h, co
             v = real(0);
         } else {
             const double phi = atan2((double)dj, (double)di) - (double)orient[ps];
-            v = (real)(sqrt((double)(di * di + dj * dj)) * h / group_speed(mats[mat_id[ps]].A, phi));
+            // an id outside the table is reported by k_prep; read a valid entry meanwhile
+            const int mid = mat_id[ps] < n_mats ? mat_id[ps] : 0;
+            v = (real)(sqrt((double)(di * di + dj * dj)) * h / group_speed(mats[mid].A, phi));
         }
     }
     T[fd.t_off + p] = v;
     // tiles that see the box (box radius + diamond radius) start active
     if (abs(di) <= R + HALO && abs(dj) <= R + HALO)
         flags[fd.unit_off + (j / TZ) * fd.ntx + (i / TX)] = TF_SELF;   // evaluate the whole tile
+}
+
+// Seeded fields: every tile holding a fixed node, and its 8 neighbours, starts with a
+// visit of all its nodes (a fixed node reaches 2 nodes out, tiles are wider than that).
+__global__ void k_seed_flags(const FieldDev* __restrict__ fields, int n_fields, int64_t n_units,
+                             const uint32_t* __restrict__ fixmask, uint32_t* __restrict__ flags) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_units) return;
+    uint32_t any = 0u;
+#pragma unroll
+    for (int w = 0; w < NODE_WORDS; ++w) any |= fixmask[u * NODE_WORDS + w];
+    if (!any) return;
+    const FieldDev fd = fields[field_of_unit(fields, n_fields, (uint32_t)u)];
+    const int t = (int)(u - fd.unit_off);
+    const int tx = t % fd.ntx, tz = t / fd.ntx;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int x = tx + dx, z = tz + dz;
+            if (x < 0 || z < 0 || x >= fd.ntx || z >= fd.ntz) continue;
+            atomicOr(&flags[fd.unit_off + (uint32_t)(z * fd.ntx + x)], (uint32_t)TF_SELF);
+        }
 }
 
 // Scheduler of one relaxation pass (ascending thresholds), one work-group per field.
@@ -126,14 +149,16 @@ __device__ __forceinline__ void lds_min(double* p, double v) {
 // cannot change it.  Across tiles the marks are unconditional (the other tile may be
 // working on an older copy of X) and go to the neighbouring tile's node mask for the next
 // pass.  Each sweep packs the marked nodes into the first lanes.
-template <typename real, typename mreal>
+// SEEDED: the fixed nodes are the set bits of fixmask (one bit per node of each tile unit,
+// NODE_WORDS words per unit) instead of the source box of radius R.
+template <typename real, typename mreal, bool SEEDED>
 __global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
 k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, const real* __restrict__ fbt_all,
         int R, int inner, const real* __restrict__ theta,
         real* __restrict__ T, uint32_t* __restrict__ flags, real* __restrict__ minrej,
         uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
         const uint32_t* __restrict__ count, uint32_t* __restrict__ idle,
-        unsigned long long* __restrict__ counters) {
+        unsigned long long* __restrict__ counters, const uint32_t* __restrict__ fixmask) {
     __shared__ real lt[LH * LSTRIDE];
     __shared__ uint8_t dnext[NTHREADS];
     __shared__ uint16_t clist[NTHREADS];
@@ -181,10 +206,11 @@ k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, co
         sv[k] = (q < LW * LH && gi >= 0 && gj >= 0 && gi < nx && gj < nz) ? Tf[(int64_t)gj * nx + gi] : inf;
     }
     // incoming marks of this tile (read and cleared; this pass writes the other buffer)
-    uint32_t mk = 0u;
+    uint32_t mk = 0u, fm = 0u;
     if (lane < NODE_WORDS) {
         mk = marks_in[(int64_t)unit * NODE_WORDS + lane];
         if (mk) marks_in[(int64_t)unit * NODE_WORDS + lane] = 0u;
+        if constexpr (SEEDED) fm = fixmask[(int64_t)unit * NODE_WORDS + lane];
     }
     const real th = theta[f];
 #pragma unroll
@@ -209,7 +235,10 @@ k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, co
         const int lx = node % TX, lz = node / TX;
         const int gi = i0 + lx, gj = j0 + lz;
         const int me = (lz + HALO) * LSTRIDE + (lx + HALO);
-        const bool act = gi < nx && gj < nz && !(abs(gi - s.x) <= R && abs(gj - s.y) <= R);
+        bool fixed_node;
+        if constexpr (SEEDED) fixed_node = (__shfl(fm, (node >> 5)) >> (node & 31)) & 1u;
+        else fixed_node = abs(gi - s.x) <= R && abs(gj - s.y) <= R;
+        const bool act = gi < nx && gj < nz && !fixed_node;
         amask |= act ? 1u << q : 0u;
         const real cur = lt[me];
         bool any = false;
@@ -416,7 +445,7 @@ template <typename real, typename mreal, typename oreal>
 ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media, const ali_material* mats,
                         int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
                         const ali_node* recv, const ali_options& opt, real* d_T, ali_solve_stats* stats,
-                        ForwardState<real, mreal>* fs) {
+                        ForwardState<real, mreal>* fs, const uint32_t* d_fixmask) {
     ali_status st = validate_batch(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, recv);
     if (st != ALI_OK) return st;
     if (!d_T) return H->fail(ALI_EINVAL, "d_T is NULL");
@@ -521,11 +550,15 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
                            md.grid.nx, md.grid.nz, md.grid.h, md.n_mats, (const MatDev<mreal>*)d_mats + dev_mat_off[m],
                            d_mat_id + md.node_offset, d_orient + md.node_offset,
                            (mreal*)d_geo + GEO_N * md.node_offset, (real*)d_fbt + 4 * md.node_offset, (int*)d_err);
-        hipLaunchKernelGGL((k_init<real, mreal, oreal>), dim3((unsigned)((N + B - 1) / B), (unsigned)md.n_src), dim3(B), 0, S,
-                           (const FieldDev*)d_fields, F.medium_first_field[m], md.grid.h,
-                           (const MatDev<mreal>*)d_mats + dev_mat_off[m], d_mat_id + md.node_offset,
-                           d_orient + md.node_offset, opt.src_box_radius, d_T, (uint32_t*)d_flags);
+        if (!d_fixmask)
+            hipLaunchKernelGGL((k_init<real, mreal, oreal>), dim3((unsigned)((N + B - 1) / B), (unsigned)md.n_src),
+                               dim3(B), 0, S, (const FieldDev*)d_fields, F.medium_first_field[m], md.grid.h,
+                               (const MatDev<mreal>*)d_mats + dev_mat_off[m], md.n_mats, d_mat_id + md.node_offset,
+                               d_orient + md.node_offset, opt.src_box_radius, d_T, (uint32_t*)d_flags);
     }
+    if (d_fixmask)
+        hipLaunchKernelGGL(k_seed_flags, dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
+                           (const FieldDev*)d_fields, n_fields, nunits, d_fixmask, (uint32_t*)d_flags);
     HIPCK(H, hipGetLastError());
 
     int h_err = 0;
@@ -553,10 +586,17 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
         uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
         uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);
-        hipLaunchKernelGGL((k_relax<real, mreal>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
-                           (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
-                           (uint32_t*)d_flags, (real*)d_minrej, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)),
-                           (uint32_t*)d_idle, (unsigned long long*)d_upd);
+        if (d_fixmask)
+            hipLaunchKernelGGL((k_relax<real, mreal, true>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
+                               (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, -1,
+                               opt.inner_sweeps, (const real*)d_theta, d_T, (uint32_t*)d_flags, (real*)d_minrej,
+                               mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
+                               (unsigned long long*)d_upd, d_fixmask);
+        else
+            hipLaunchKernelGGL((k_relax<real, mreal, false>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
+                               (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
+                               (uint32_t*)d_flags, (real*)d_minrej, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)),
+                               (uint32_t*)d_idle, (unsigned long long*)d_upd, (const uint32_t*)nullptr);
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH) + 1], S);
     };
     while (iters < opt.max_sweeps) {
@@ -565,10 +605,13 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
         if (graph) {
             // the first batch differs from the others only in the first pass (no advance)
             const int first = iters == 0 ? 1 : 0;
-            const std::string key = graph_key("relax", first, (const void*)&k_relax<real, mreal>, d_fields, n_fields,
+            const void* kern = d_fixmask ? (const void*)&k_relax<real, mreal, true>
+                                         : (const void*)&k_relax<real, mreal, false>;
+            const std::string key = graph_key("relax", first, kern, d_fields, n_fields,
                                               d_flags, d_minrej, d_theta, d_step, d_list, d_count,
                                               d_marks, nunits, d_geo, d_fbt, opt.src_box_radius,
-                                              opt.inner_sweeps, d_T, d_idle, d_upd, grid_relax);
+                                              opt.inner_sweeps, d_T, d_idle, d_upd, grid_relax,
+                                              (const void*)d_fixmask);
             HIPCK(H, hipEventRecord(H->ev2, S));
             st = launch_captured(H, key, [&](int b, hipStream_t cs) { enqueue(first ? b : PASS_BATCH + b, false, cs); });
             if (st != ALI_OK) return st;
@@ -617,7 +660,7 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     template ali_status solve_fields<R, M, O>(ali_handle*, const ali_medium*, int32_t, const ali_material*,  \
                                               int32_t, const uint8_t*, const O*, const ali_node*,            \
                                               const ali_node*, const ali_options&, R*, ali_solve_stats*,     \
-                                              ForwardState<R, M>*);
+                                              ForwardState<R, M>*, const uint32_t*);
 ALI_SOLVE_FIELDS(double, float, float)
 ALI_SOLVE_FIELDS(float, float, float)
 ALI_SOLVE_FIELDS(double, double, float)

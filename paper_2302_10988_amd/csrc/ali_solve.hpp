@@ -300,11 +300,30 @@ ali_status validate_batch(ali_handle* H, const ali_medium* media, int32_t n_medi
 // synchronises the stream before returning and fills every stats field except `ms`.
 // Instantiated for <double, float, float>, <float, float, float>, <double, double, float>
 // and <double, double, double>.
+// Seeded mode (d_fixmask != NULL): the fields start from the values already in d_T, the
+// nodes whose bit is set in d_fixmask keep their values and every other node must hold
+// +inf; there is no source box.  d_fixmask has NODE_WORDS words per tile unit, units
+// numbered as unit_offsets() does, bit (j % TZ) * TX + i % TX for node (i, j) of the tile.
 template <typename real, typename mreal, typename oreal>
 ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media, const ali_material* mats,
                         int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
                         const ali_node* recv, const ali_options& opt, real* d_T, ali_solve_stats* stats,
-                        ForwardState<real, mreal>* fs);
+                        ForwardState<real, mreal>* fs, const uint32_t* d_fixmask = nullptr);
+
+// first tile unit of every field of a batch (fields in medium order, then source order)
+inline std::vector<uint32_t> unit_offsets(const ali_medium* media, int32_t n_media) {
+    std::vector<uint32_t> off;
+    uint32_t u = 0;
+    for (int m = 0; m < n_media; ++m) {
+        const uint32_t per = (uint32_t)(((media[m].grid.nx + TX - 1) / TX) * ((media[m].grid.nz + TZ - 1) / TZ));
+        for (int k = 0; k < media[m].n_src; ++k) {
+            off.push_back(u);
+            u += per;
+        }
+    }
+    off.push_back(u);
+    return off;
+}
 
 // number of fields and field nodes of a batch (after validation)
 inline void batch_sizes(const ali_medium* media, int32_t n_media, int64_t* n_fields, int64_t* field_nodes) {

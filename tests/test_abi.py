@@ -49,6 +49,10 @@ def test_host_only_entry_points():
     assert o.src_box_radius == 2 and o.inner_sweeps > 0 and o.max_sweeps > 0
     assert lib.ali_status_string(_lib.ALI_ENOCONV).decode().startswith("relaxation")
     assert lib.ali_status_string(0).decode() == "ok"
+    r = _lib.Refine()
+    lib.ali_default_refine(ctypes.byref(r))
+    assert r.n_levels == 3 and list(r.density[:3]) == [27, 9, 3] and list(r.radius[:3]) == [1, 6, 13]
+    assert r.start_half_width == 0.5
     assert lib.ali_destroy(None) == _lib.ALI_EINVAL
     assert lib.ali_create(None, 0, None) == _lib.ALI_EINVAL
 
@@ -59,7 +63,7 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_2302_10988_amd import _lib
     structs = {"ali_grid": _lib.Grid, "ali_material": _lib.Material, "ali_node": _lib.Node,
                "ali_options": _lib.Options, "ali_solve_stats": _lib.SolveStats, "ali_medium": _lib.Medium,
-               "ali_adjoint_stats": _lib.AdjointStats}
+               "ali_adjoint_stats": _lib.AdjointStats, "ali_refine": _lib.Refine}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ali.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))

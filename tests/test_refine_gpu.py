@@ -1,0 +1,153 @@
+"""Nested fine grids around the source (Section 4.4) on the GPU, through the C ABI, against
+the FP64 oracle.
+
+  - float64 entry point: every node within 1e-12 relative of the oracle (both sides take
+    the same decisions; their group speeds differ by rounding only), for the paper's levels
+    and for a second level set, sources in the interior and at the edges (clipped fine
+    grids), heterogeneous media;
+  - without fine grids the seeded path reproduces the straight-ray box solve bitwise;
+  - mixed arithmetic: within 1e-4 relative (the float32 contract) on the 128 x 128 weld; on
+    the 512 x 512 weld a float32 near-tie flip is measured, so the bar there is on the bulk;
+  - Table 3's set-up (cubic steel, 21 x 21, orientation 0, subgrid sizes 1 and 3): the GPU
+    field equals the oracle's and its error is the oracle's;
+  - the 512 x 512 weld with 64 sources: two whole fields against the oracle (float64
+    element-wise, mixed on the bulk).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthmedia as sm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+    from paper_2302_10988_amd import Solver
+    assert torch.cuda.is_available()
+    return Solver(0)
+
+
+def _dev(m, dtype):
+    import torch
+    return torch.from_numpy(m.mat_id).cuda(), torch.from_numpy(np.ascontiguousarray(m.orient)).to(dtype).cuda()
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    assert np.array_equal(np.isfinite(a), np.isfinite(b))
+    fin = np.isfinite(b) & (b > 0)
+    return float((np.abs(a - b)[fin] / b[fin]).max())
+
+
+LEVELS = [((27, 1), (9, 6), (3, 13)), ((9, 2), (3, 5))]
+
+
+@pytest.mark.parametrize("levels", LEVELS)
+@pytest.mark.parametrize("seed", [3, 10])
+def test_refined_f64_vs_oracle(solver, orc, levels, seed):
+    import torch
+    m = sm.random_medium(41, 37, 0.2e-3, seed=seed, n_mats=3)
+    sources = [m.sources[0], (0, 0), (40, 20), (20, 36), (1, 35)]
+    mid, ori = _dev(m, torch.float64)
+    print("refined f64: seed %d levels %s" % (seed, levels), flush=True)
+    T, st = solver.solve_refined(m.h, m.mats, mid, ori, sources, levels=levels, precision="f64")
+    assert st["converged"] == 1
+    for k, src in enumerate(sources):
+        ref = orc.solve_refined(m.h, m.mats, m.mat_id, m.orient, src, levels)
+        err = _rel(T[k].cpu().numpy(), ref)
+        print("  source %s: max rel err %.3g" % (src, err), flush=True)
+        assert err <= 1e-12
+
+
+def test_no_levels_is_the_box_solve(solver):
+    import torch
+    m = sm.random_medium(60, 44, 0.2e-3, seed=4, n_mats=3)
+    sources = [m.sources[0], (2, 40)]
+    mid, ori = _dev(m, torch.float32)
+    for R in (0, 2):
+        a, _ = solver.solve_refined(m.h, m.mats, mid, ori, sources, levels=(), start_half_width=R + 0.5)
+        b, _ = solver.solve(m.h, m.mats, mid, ori, sources, src_box_radius=R)
+        assert torch.equal(a, b), R
+
+
+def test_refined_mixed_vs_oracle(solver, orc):
+    import torch
+    m = sm.weld(n=128, h=0.4e-3, seed=0)
+    sources = [(20, 0), (64, 0), (110, 5)]
+    mid, ori = _dev(m, torch.float32)
+    print("refined mixed: weld 128", flush=True)
+    T, st = solver.solve_refined(m.h, m.mats, mid, ori, sources)
+    assert st["converged"] == 1
+    for k, src in enumerate(sources):
+        ref = orc.solve_refined(m.h, m.mats, m.mat_id, m.orient, src)
+        err = _rel(T[k].cpu().numpy(), ref)
+        print("  source %s: max rel err %.3g" % (src, err), flush=True)
+        assert err <= 1e-4
+
+
+@pytest.mark.parametrize("s", [1, 3])
+def test_table3_setup(solver, orc, s):
+    import torch
+    n, h, mat = 21, 1e-3, sm.CUBIC_STEEL
+    mid, ori = orc.refine_medium(np.zeros((n, n), np.uint8), np.zeros((n, n)), s)
+    levels = ((27, 1), (9, 6), (3, 13)) if s == 1 else ((9, 2 * s), (3, 5 * s))
+    half = 0.5 * s
+    src = (n // 2 * s, n // 2 * s)
+    T, st = solver.solve_refined(h / s, [mat], torch.from_numpy(mid).cuda(), torch.from_numpy(ori).cuda(), [src],
+                                 levels=levels, start_half_width=half, precision="f64")
+    got = T[0].cpu().numpy()
+    ref = orc.solve_refined(h / s, [mat], mid, ori, src, levels, half)
+    assert _rel(got, ref) <= 1e-12
+    c = n // 2
+    err = []
+    for j in range(n):
+        for i in range(n):
+            if i == c and j == c:
+                continue
+            t = math.hypot(i - c, j - c) * h / orc.qp_group_speed(mat, math.atan2(j - c, i - c) - 0.5 * math.pi)
+            err.append(abs(got[j * s, i * s] - t) / t)
+    print("Table 3 set-up, subgrid %d: %.3f %%" % (s, 100 * np.mean(err)), flush=True)
+    assert 100 * np.mean(err) < (1.083 if s == 1 else 1.073)
+
+
+def test_refined_weld_full_size(solver, orc):
+    # float64: element-wise parity.  Mixed arithmetic: the stencil choice ranks squares by
+    # the score tau_C - tau_B, not by value, so a near tie in score between two stencils
+    # whose estimates differ by ~1e-6 goes either way with float32 increments.  For the
+    # last source one such flip on the top surface inside the weld, 254 cells from the
+    # source, moves the nodes behind it by up to 4.5e-4 (4.5 % of the nodes above 1e-5).
+    # The bar is therefore on the bulk: median within 1e-6, 90 % within 1e-5, all 1e-3.
+    import torch
+    m = sm.weld_multi()
+    mid, ori = _dev(m, torch.float64)
+    print("refined weld %d x %d, %d sources" % (m.nx, m.nz, len(m.sources)), flush=True)
+    T64, st = solver.solve_refined(m.h, m.mats, mid, ori, m.sources, precision="f64")
+    assert st["converged"] == 1
+    T32, st = solver.solve_refined(m.h, m.mats, mid, ori.float(), m.sources)
+    assert st["converged"] == 1 and torch.isfinite(T32).all()
+    for k in (0, len(m.sources) - 1):
+        ref = orc.solve_refined(m.h, m.mats, m.mat_id, m.orient, m.sources[k])
+        err = _rel(T64[k].cpu().numpy(), ref)
+        got = T32[k].cpu().numpy().astype(np.float64)
+        fin = ref > 0
+        rel = np.abs(got - ref)[fin] / ref[fin]
+        print("  source %s: f64 max rel err %.3g; mixed max %.3g, median %.3g, above 1e-5: %.2f %%"
+              % (m.sources[k], err, rel.max(), np.median(rel), 100 * (rel > 1e-5).mean()), flush=True)
+        assert err <= 1e-12
+        assert np.median(rel) <= 1e-6 and (rel > 1e-5).mean() <= 0.1 and rel.max() <= 1e-3
+
+
+def test_refined_errors(solver):
+    import torch
+    from paper_2302_10988_amd import AliError
+    m = sm.random_medium(20, 20, 0.2e-3, seed=1)
+    mid, ori = _dev(m, torch.float32)
+    for bad in (((4, 1),), ((27, 1), (5, 2)), ((9, 3), (3, 1))):
+        with pytest.raises(AliError):
+            solver.solve_refined(m.h, m.mats, mid, ori, m.sources, levels=bad)
+    with pytest.raises(AliError):
+        solver.solve_refined(m.h, m.mats, mid, ori, m.sources, start_half_width=3.0)
