@@ -161,15 +161,15 @@ void ali_default_refine(ali_refine* r);
 
 /* Travel-time fields with nested fine grids around every source (Section 4.4) in place of
    the straight-ray box.  Per source, a sequence of grids centred on the source node, finest
-   first (level l: spacing h / density[l], extending radius[l] + 1 cells around the source,
-   clipped to the grid; every fine node takes the material and orientation of the nearest
-   grid node).  The finest grid starts from straight rays at the source material's group
+   first (level l: spacing h / density[l], extending radius[l] cells and 2 fine cells around
+   the source, clipped to the grid; every fine node takes the material and orientation of
+   the nearest grid node).  The finest grid starts from straight rays at the source material's group
    speed inside start_half_width cells; on each level the march runs until it reaches a node
    farther than radius[l] from the source, and the nodes reached strictly earlier seed the
    next coarser grid (the nodes that coincide with them keep their times); the grid itself
    comes last.  opt->src_box_radius is not used.  Other arguments, arithmetic, errors and
    output as ali_solve_traveltime; ref == NULL means ali_default_refine.  Scratch grows with
-   the fine grids (27 x 3 cells around each source by default: about 36k nodes per source).
+   the fine grids (about 23k nodes per source by default).
    stats->ms is the host time of the call; the other counters add up every level. */
 ali_status ali_solve_traveltime_refined(ali_handle* h, const ali_grid* grid, const ali_material* mats,
                                         int32_t n_mats, const uint8_t* d_mat_id, const float* d_orient,

@@ -16,11 +16,15 @@
  *   - on the next grid the nodes that coincide with known nodes keep those times and are
  *     fixed (the integer density ratio makes them coincide); the march resumes from them,
  *     which is the paper's re-seeding of known nodes with unknown neighbours.
- * Readings (where the paper is silent): each fine grid spans r_l + 1 working cells around
- * the source (clipped to the domain), which contains every node accepted before the
- * switch and their stencils; "known" at a switch is {tau < tau of the first node beyond
- * r_l}; the straight-ray region is a square of half-width vor_half working cells (1/2 for
- * the working grid's own cell).
+ * Readings (where the paper is silent): "known" at a switch is {tau < tau of the first node
+ * beyond r_l}; the straight-ray region is a square of half-width vor_half working cells
+ * (1/2 for the working grid's own cell).  Each fine grid spans r_l d_l + 2 of its own
+ * cells around the source (clipped to the domain).  That is enough for an exact switch:
+ * a node earlier than the first node beyond r_l has all its earlier neighbours inside the
+ * radius, and that first node lies within 2 cells of the radius (its earlier neighbours
+ * are inside the radius and the update reaches 2 cells); an update reads only earlier
+ * neighbours, so cutting the grid there changes none of these values, and no node beyond
+ * the radius can fall below the first one.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -87,7 +91,7 @@ int or_solve_refined(int nx, int nz, double h, const or_material* mats, int n_ma
     const or_material* msrc = &mats[mat_id[ps]];
     for (int l = 0; l <= n_levels; ++l) {
         level_t* L = &lv[l];
-        if (l < n_levels) level_alloc(L, density[l], (radius[l] + 1) * density[l], nx, nz, si, sj, mat_id, orient);
+        if (l < n_levels) level_alloc(L, density[l], radius[l] * density[l] + 2, nx, nz, si, sj, mat_id, orient);
         else level_alloc(L, 1, nx > nz ? nx : nz, nx, nz, si, sj, mat_id, orient);
         const double hl = h / L->d;
         if (l == 0) {

@@ -16,6 +16,10 @@
 //      grids at that node, so the nodes known at the switch are those strictly earlier:
 //      the fixed point of the level restricted to them equals the march (a node's value
 //      depends only on earlier nodes).
+// A level grid spans r_l d_l + 2 of its cells around the source: nodes earlier than the
+// switch have all their earlier neighbours inside the radius, the switching node lies
+// within 2 cells of it, and an update reads only earlier neighbours, so a larger grid
+// would change none of the values that are handed on.
 // The working grid itself is the last level: all sources' fields in one batch, seeded
 // from the coarsest fine level.
 #include <hip/hip_runtime.h>
@@ -215,7 +219,7 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
             return H->fail(ALI_EINVAL, "densities must be odd, in [3, 255], each divisible by the next");
         if (ref.radius[l] < 0 || (l > 0 && ref.radius[l] < ref.radius[l - 1]))
             return H->fail(ALI_EINVAL, "radii must be >= 0 and non-decreasing");
-        if ((int64_t)(ref.radius[l] + 1) * ref.density[l] > 4096)
+        if ((int64_t)ref.radius[l] * ref.density[l] + 2 > 4096)
             return H->fail(ALI_EINVAL, "a fine grid would exceed 8193 nodes per side");
     }
     if (nl > 0 && ref.start_half_width > ref.radius[0] + 1)
@@ -252,7 +256,7 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
         real* T = nullptr;
         int64_t nodes = 0, units = 0;
         if (!last) {
-            lv = level_grids(*grid, srcs, n_src, d, (ref.radius[l] + 1) * d, ref.radius[l] * d, media, lsrc,
+            lv = level_grids(*grid, srcs, n_src, d, ref.radius[l] * d + 2, ref.radius[l] * d, media, lsrc,
                              grid->h, n_mats);
             nodes = lv.back().node_off + (int64_t)lv.back().nx * lv.back().nz;
             units = unit_offsets(media.data(), n_src).back();

@@ -37,16 +37,32 @@ namespace ali {
 // ---------------------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------------------
+// per-node constants of media m0 .. m0 + gridDim.y - 1 (one medium per grid row, so a batch
+// of many small media takes one launch)
+struct PrepDev {
+    int64_t node_off;
+    int nx, nz;
+    double h;
+    int n_mats, mat_off;
+};
+
 template <typename mreal, typename treal, typename oreal>
-__global__ void k_prep(int nx, int nz, double h, int n_mats, const MatDev<mreal>* __restrict__ mats,
-                       const uint8_t* __restrict__ mat_id, const oreal* __restrict__ orient,
-                       mreal* __restrict__ geo, treal* __restrict__ fbt, int* __restrict__ err) {
+__global__ void k_prep(const PrepDev* __restrict__ media, int m0, const MatDev<mreal>* __restrict__ mats_all,
+                       const uint8_t* __restrict__ mat_id_all, const oreal* __restrict__ orient_all,
+                       mreal* __restrict__ geo_all, treal* __restrict__ fbt_all, int* __restrict__ err) {
+    const PrepDev md = media[m0 + blockIdx.y];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (int64_t)nx * nz) return;
+    if (p >= (int64_t)md.nx * md.nz) return;
+    const MatDev<mreal>* __restrict__ mats = mats_all + md.mat_off;
+    const uint8_t* __restrict__ mat_id = mat_id_all + md.node_off;
+    const oreal* __restrict__ orient = orient_all + md.node_off;
+    mreal* __restrict__ geo = geo_all + GEO_N * md.node_off;
+    treal* __restrict__ fbt = fbt_all + 4 * md.node_off;
+    const double h = md.h;
     const double th = (double)orient[p];
     const int mid = mat_id[p];
     if (!isfinite(th)) { atomicOr(err, 1); return; }
-    if (mid >= n_mats) { atomicOr(err, 2); return; }
+    if (mid >= md.n_mats) { atomicOr(err, 2); return; }
     const MatA m = mats[mid].A;
     double s2, c2;
     sincos(2.0 * th, &s2, &c2);
@@ -543,13 +559,27 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     const int B = 256;
     hipLaunchKernelGGL((k_fill<real>), dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
                        (real*)d_minrej, nunits, dinf_host<real>());
+    // per-node constants of every medium: one launch per 65535 media
+    std::vector<PrepDev> hp(n_media);
+    int64_t max_nodes = 0;
+    for (int m = 0; m < n_media; ++m) {
+        const ali_medium& md = media[m];
+        hp[m] = PrepDev{md.node_offset, md.grid.nx, md.grid.nz, md.grid.h, md.n_mats, dev_mat_off[m]};
+        max_nodes = std::max(max_nodes, (int64_t)md.grid.nx * md.grid.nz);
+    }
+    void* d_prep = nullptr;
+    if (!H->scratch("prep", sizeof(PrepDev) * n_media, &d_prep))
+        return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+    HIPCK(H, hipMemcpyAsync(d_prep, hp.data(), sizeof(PrepDev) * n_media, hipMemcpyHostToDevice, S));
+    for (int m0 = 0; m0 < n_media; m0 += 65535) {
+        const int nm = std::min(n_media - m0, 65535);
+        hipLaunchKernelGGL((k_prep<mreal, real, oreal>), dim3((unsigned)((max_nodes + B - 1) / B), (unsigned)nm),
+                           dim3(B), 0, S, (const PrepDev*)d_prep, m0, (const MatDev<mreal>*)d_mats, d_mat_id,
+                           d_orient, (mreal*)d_geo, (real*)d_fbt, (int*)d_err);
+    }
     for (int m = 0; m < n_media; ++m) {
         const ali_medium& md = media[m];
         const int64_t N = (int64_t)md.grid.nx * md.grid.nz;
-        hipLaunchKernelGGL((k_prep<mreal, real, oreal>), dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S,
-                           md.grid.nx, md.grid.nz, md.grid.h, md.n_mats, (const MatDev<mreal>*)d_mats + dev_mat_off[m],
-                           d_mat_id + md.node_offset, d_orient + md.node_offset,
-                           (mreal*)d_geo + GEO_N * md.node_offset, (real*)d_fbt + 4 * md.node_offset, (int*)d_err);
         if (!d_fixmask)
             hipLaunchKernelGGL((k_init<real, mreal, oreal>), dim3((unsigned)((N + B - 1) / B), (unsigned)md.n_src),
                                dim3(B), 0, S, (const FieldDev*)d_fields, F.medium_first_field[m], md.grid.h,
