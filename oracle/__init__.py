@@ -23,7 +23,16 @@ _lib = None
 
 
 class Material(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_double) for n in ("c11", "c13", "c33", "c55", "c44", "c66", "rho")]
+    _fields_ = [(n, ctypes.c_double) for n in ("c11", "c13", "c33", "c55", "c44", "c66", "rho")] + \
+               [("wave", ctypes.c_int32)]
+
+
+WAVE_QP, WAVE_SH = 0, 1
+
+
+def as_sh(mats):
+    """The same materials for the SH wave (every solver then uses the SH speeds)."""
+    return [dict(m, wave=WAVE_SH) for m in mats]
 
 
 def build(force: bool = False) -> str:
@@ -85,6 +94,11 @@ def _load():
     lib.or_qp_group_speed_deriv.restype = D
     lib.or_stencil_partials.argtypes = [M, D, D, ctypes.POINTER(I), D, D, D] + [ctypes.POINTER(D)] * 4 + [P]
     lib.or_qp_phase_speed_dA.argtypes = [M, D, ctypes.POINTER(D)]
+    for name in ("or_sh_phase_speed", "or_sh_phase_speed_deriv", "or_sh_group_speed", "or_sh_group_speed_deriv",
+                 "or_phase_speed", "or_phase_speed_deriv", "or_group_speed", "or_group_speed_deriv",
+                 "or_group_speed_support"):
+        getattr(lib, name).argtypes = [M, D]
+        getattr(lib, name).restype = D
     lib.or_qp_group_speed_dA.argtypes = [M, D, ctypes.POINTER(D)]
     lib.or_field_choices.argtypes = [I, I, D, M, P, P, P, P, P]
     lib.or_fmm_seeded.argtypes = [I, I, D, M, I, P, P, P, P, I, I, I, P, ctypes.POINTER(D)]
@@ -105,10 +119,13 @@ def _mat_array(mats):
     for k, m in enumerate(mats):
         if isinstance(m, dict):
             vals = [m[n] for n in ("c11", "c13", "c33", "c55", "c44", "c66", "rho")]
+            wave = int(m.get("wave", WAVE_QP))
         else:
-            vals = list(m)
+            vals = list(m)[:7]
+            wave = int(list(m)[7]) if len(list(m)) > 7 else WAVE_QP
         for n, v in zip(("c11", "c13", "c33", "c55", "c44", "c66", "rho"), vals):
             setattr(arr[k], n, float(v))
+        arr[k].wave = wave
     return arr
 
 
@@ -143,6 +160,29 @@ def qp_group_from_phase(mat, th_p):
 def qp_group_speed(mat, phi):
     """qP group speed along group angle phi (rad, from the c22 axis); Section 3.2."""
     return _load().or_qp_group_speed(_mat_array([mat]), float(phi))
+
+
+def phase_speed(mat, th_p):
+    """Phase speed of the material's wave (qP, or SH for a material from as_sh)."""
+    return _load().or_phase_speed(_mat_array([mat]), float(th_p))
+
+
+def group_speed(mat, phi):
+    """Group speed of the material's wave along group angle phi (from the c22 axis)."""
+    return _load().or_group_speed(_mat_array([mat]), float(phi))
+
+
+def group_speed_support(mat, phi):
+    """Group speed of the material's wave by the support-function route."""
+    return _load().or_group_speed_support(_mat_array([mat]), float(phi))
+
+
+def phase_speed_deriv(mat, th_p):
+    return _load().or_phase_speed_deriv(_mat_array([mat]), float(th_p))
+
+
+def group_speed_deriv(mat, phi):
+    return _load().or_group_speed_deriv(_mat_array([mat]), float(phi))
 
 
 def qp_group_speed_support(mat, phi):

@@ -48,8 +48,8 @@ void or_stencil_partials(const or_material* m, double theta_ax, double h, const 
     double dthn = (wx * dwy - wy * dwx) / (wl * wl);
     double theta_D = theta_ax + 0.5 * M_PI;
     double thp = fmod(theta_D - theta_n + 0.5 * M_PI, M_PI);
-    double v = or_qp_phase_speed(m, thp);
-    double dv = or_qp_phase_speed_deriv(m, thp);
+    double v = or_phase_speed(m, thp);
+    double dv = or_phase_speed_deriv(m, thp);
     double dU_da = dfd / v - fd * dv / (v * v) * (-dthn);
     *dta = dU_da * da_ta;
     *dtb = 1.0 + dU_da * da_tb;
@@ -97,7 +97,7 @@ static double frozen_value(int nx, int nz, double h, const or_material* mats, co
     int di = NEIGH8[ch - 32][0], dj = NEIGH8[ch - 32][1];
     double tn = T[(int64_t)(j + dj) * nx + i + di];
     double phi = atan2((double)(-dj), (double)(-di)) - (orient[p] + 0.5 * M_PI);
-    return tn + sqrt((double)(di * di + dj * dj)) * h / or_qp_group_speed(m, phi);
+    return tn + sqrt((double)(di * di + dj * dj)) * h / or_group_speed(m, phi);
 }
 
 void or_frozen_field(int nx, int nz, double h, const or_material* mats, const uint8_t* mat_id,
@@ -127,6 +127,9 @@ int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, co
                const double* orient, int si, int sj, int R, const double* g, double* T_out,
                double* dtheta, double* dA) {
     int64_t N = (int64_t)nx * nz;
+    if (dA)   /* the stiffness partials are written for the qP wave */
+        for (int k = 0; k < n_mats; ++k)
+            if (mats[k].wave != OR_WAVE_QP) return -1;
     double* T = T_out ? T_out : malloc(sizeof(double) * (size_t)N);
     int64_t* pop = malloc(sizeof(int64_t) * (size_t)N);
     int64_t npop = or_solve_fmm(nx, nz, h, mats, n_mats, mat_id, orient, si, sj, R, T, pop, NULL);
@@ -155,9 +158,9 @@ int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, co
             int di = i - si, dj = j - sj;
             if (di == 0 && dj == 0) continue;
             double phi = atan2((double)dj, (double)di) - (orient[ps] + 0.5 * M_PI);
-            double V = or_qp_group_speed(msrc, phi);
+            double V = or_group_speed(msrc, phi);
             double r = sqrt((double)(di * di + dj * dj)) * h;
-            dtheta[ps] += l * r * or_qp_group_speed_deriv(msrc, phi) / (V * V);
+            dtheta[ps] += l * r * or_group_speed_deriv(msrc, phi) / (V * V);
             if (dA) add_ray_dA(msrc, phi, r, l, dA + 4 * ps);
             continue;
         }
@@ -181,10 +184,10 @@ int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, co
             int di = NEIGH8[ch - 32][0], dj = NEIGH8[ch - 32][1];
             int64_t pn = (int64_t)(j + dj) * nx + i + di;
             double phi = atan2((double)(-dj), (double)(-di)) - (orient[p] + 0.5 * M_PI);
-            double V = or_qp_group_speed(m, phi);
+            double V = or_group_speed(m, phi);
             double L = sqrt((double)(di * di + dj * dj)) * h;
             lam[pn] += l;
-            dtheta[p] += l * L * or_qp_group_speed_deriv(m, phi) / (V * V);
+            dtheta[p] += l * L * or_group_speed_deriv(m, phi) / (V * V);
             if (dA) add_ray_dA(m, phi, L, l, dA + 4 * p);
         }
     }

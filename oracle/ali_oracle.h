@@ -29,8 +29,13 @@
 extern "C" {
 #endif
 
+/* wave: OR_WAVE_QP (in-plane quasi-P, the paper's mode) or OR_WAVE_SH (the shear wave
+   polarised normal to the plane, Section 6's extension); one value for every material of
+   a solve. */
+enum { OR_WAVE_QP = 0, OR_WAVE_SH = 1 };
 typedef struct {
     double c11, c13, c33, c55, c44, c66, rho;
+    int32_t wave;
 } or_material;
 
 /* ---- Section 3: velocities ------------------------------------------------------- */
@@ -57,6 +62,25 @@ double or_qp_group_speed(const or_material* m, double phi);
 /* Same quantity by a second, independent route: the support function of the slowness
    curve, 1/V(phi) = max_psi cos(phi - psi) / v(psi). */
 double or_qp_group_speed_support(const or_material* m, double phi);
+
+/* SH phase speed at phase angle th_p from the c22 axis: rho v^2 = c66 cos^2 + c44 sin^2
+   (the out-of-plane entry of the Christoffel matrix), and its derivative. */
+double or_sh_phase_speed(const or_material* m, double th_p);
+double or_sh_phase_speed_deriv(const or_material* m, double th_p);
+
+/* SH group speed along group angle phi from the c22 axis: the wave surface of an
+   elliptical slowness curve is the ellipse with semi-axes sqrt(c66/rho) (c22 axis) and
+   sqrt(c44/rho) (symmetry axis); and its derivative in phi. */
+double or_sh_group_speed(const or_material* m, double phi);
+double or_sh_group_speed_deriv(const or_material* m, double phi);
+
+/* The speeds of the material's wave (qP or SH by m->wave); every solver below uses these. */
+double or_phase_speed(const or_material* m, double th_p);
+double or_phase_speed_deriv(const or_material* m, double th_p);
+double or_group_speed(const or_material* m, double phi);
+double or_group_speed_deriv(const or_material* m, double phi);
+/* support-function route for the material's wave (see or_qp_group_speed_support) */
+double or_group_speed_support(const or_material* m, double phi);
 
 /* ---- Section 4.1: stencil table --------------------------------------------------- */
 
@@ -180,8 +204,8 @@ void or_frozen_field(int nx, int nz, double h, const or_material* mats, const ui
                      const int64_t* pop, int64_t npop, double* T);
 
 /* dL/dtheta for one source given g = dL/dT at every node; writes the field to T_out
-   (nullable) and dL/dA [nz][nx][4] (A11, A13, A33, A55 of every node, A = C / rho; nullable)
-   to dA.  Returns 0, or -1 on invalid input. */
+   (nullable) and dL/dA [nz][nx][4] (A11, A13, A33, A55 of every node, A = C / rho; nullable;
+   qP only) to dA.  Returns 0, or -1 on invalid input. */
 int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, const uint8_t* mat_id,
                const double* orient, int si, int sj, int R, const double* g, double* T_out,
                double* dtheta, double* dA);

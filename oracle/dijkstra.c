@@ -62,7 +62,7 @@ double or_segment_time(int nx, int nz, double h, const or_material* mats,
         int64_t p = (int64_t)cj * nx + ci;
         const or_material* m = &mats[mat_id[p]];
         double phi = ang - (orient[p] + 0.5 * M_PI);
-        total += (tb - ta) * len * h / or_qp_group_speed(m, phi);
+        total += (tb - ta) * len * h / or_group_speed(m, phi);
     }
     free(ts);
     return total;

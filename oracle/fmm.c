@@ -90,7 +90,7 @@ double or_stencil_estimate(const or_material* m, double theta_ax, double h,
     double theta_n = atan2(yB - yE, xB - xE);
     double theta_D = theta_ax + 0.5 * M_PI;
     double thp = fmod(theta_D - theta_n + 0.5 * M_PI, M_PI);
-    double v = or_qp_phase_speed(m, thp);
+    double v = or_phase_speed(m, thp);
     return tb + fd / v;
 }
 
@@ -152,7 +152,7 @@ static double phi_core(const ctx_t* c, int i, int j, unsigned known12, int* choi
             double tn = c->T[nj * c->nx + ni];
             double phi = atan2((double)(-dj), (double)(-di)) - (th + 0.5 * M_PI);
             double dist = sqrt((double)(di * di + dj * dj)) * c->h;
-            double U = tn + dist / or_qp_group_speed(m, phi);
+            double U = tn + dist / or_group_speed(m, phi);
             if (!(U > tn)) continue;
             if (U < best_U) { best_U = U; best = 32 + k; }
         }
@@ -190,7 +190,7 @@ void or_source_box(int nx, int nz, double h, const or_material* mats, const uint
             double t = 0.0;
             if (di != 0 || dj != 0) {
                 double phi = atan2((double)dj, (double)di) - (th + 0.5 * M_PI);
-                t = sqrt((double)(di * di + dj * dj)) * h / or_qp_group_speed(m, phi);
+                t = sqrt((double)(di * di + dj * dj)) * h / or_group_speed(m, phi);
             }
             T[j * nx + i] = t;
             fixed[j * nx + i] = 1;
@@ -237,6 +237,12 @@ static int valid_inputs(int nx, int nz, double h, const or_material* mats, int n
     if (si < 0 || sj < 0 || si >= nx || sj >= nz) return 0;
     for (int k = 0; k < n_mats; ++k) {
         const or_material* m = &mats[k];
+        if (m->wave != mats[0].wave) return 0;
+        if (m->wave == OR_WAVE_SH) {
+            if (!(m->rho > 0.0 && m->c44 > 0.0 && m->c66 > 0.0)) return 0;
+            continue;
+        }
+        if (m->wave != OR_WAVE_QP) return 0;
         if (!(m->rho > 0.0 && m->c11 > 0.0 && m->c33 > 0.0 && m->c55 > 0.0)) return 0;
         if (!(m->c11 * m->c33 > m->c13 * m->c13)) return 0;
     }

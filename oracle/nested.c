@@ -103,7 +103,7 @@ int or_solve_refined(int nx, int nz, double h, const or_material* mats, int n_ma
                     double t = 0.0;
                     if (a != 0 || b != 0) {
                         double phi = atan2((double)b, (double)a) - (orient[ps] + 0.5 * M_PI);
-                        t = sqrt((double)a * a + (double)b * b) * hl / or_qp_group_speed(msrc, phi);
+                        t = sqrt((double)a * a + (double)b * b) * hl / or_group_speed(msrc, phi);
                     }
                     L->T[q] = t;
                     L->fixed[q] = 1;

@@ -128,28 +128,32 @@ double or_qp_group_speed(const or_material* m, double phi) {
     return gs;
 }
 
-double or_qp_group_speed_support(const or_material* m, double phi) {
+static double support_route(const or_material* m, double phi, double (*vphase)(const or_material*, double)) {
     /* maximise f(psi) = cos(phi - psi) / v(psi) over psi in (phi - pi/2, phi + pi/2):
        coarse scan, then golden-section refinement of the best bracket */
     const int N = 7200;
     double best = -1.0, bpsi = phi;
     for (int k = 1; k < N; ++k) {
         double psi = phi - 0.5 * M_PI + M_PI * (double)k / N;
-        double f = cos(phi - psi) / or_qp_phase_speed(m, psi);
+        double f = cos(phi - psi) / vphase(m, psi);
         if (f > best) { best = f; bpsi = psi; }
     }
     double a = bpsi - M_PI / N, b = bpsi + M_PI / N;
     const double gr = 0.5 * (sqrt(5.0) - 1.0);
     double c = b - gr * (b - a), d = a + gr * (b - a);
-    double fc = cos(phi - c) / or_qp_phase_speed(m, c);
-    double fd = cos(phi - d) / or_qp_phase_speed(m, d);
+    double fc = cos(phi - c) / vphase(m, c);
+    double fd = cos(phi - d) / vphase(m, d);
     for (int it = 0; it < 200 && (b - a) > 1e-13; ++it) {
-        if (fc > fd) { b = d; d = c; fd = fc; c = b - gr * (b - a); fc = cos(phi - c) / or_qp_phase_speed(m, c); }
-        else         { a = c; c = d; fc = fd; d = a + gr * (b - a); fd = cos(phi - d) / or_qp_phase_speed(m, d); }
+        if (fc > fd) { b = d; d = c; fd = fc; c = b - gr * (b - a); fc = cos(phi - c) / vphase(m, c); }
+        else         { a = c; c = d; fc = fd; d = a + gr * (b - a); fd = cos(phi - d) / vphase(m, d); }
     }
     double f = fc > fd ? fc : fd;
     if (best > f) f = best;
     return 1.0 / f;
+}
+
+double or_qp_group_speed_support(const or_material* m, double phi) {
+    return support_route(m, phi, or_qp_phase_speed);
 }
 
 /* d V_group / d phi by Richardson-extrapolated central differences of the exact group
@@ -201,4 +205,46 @@ void or_qp_group_speed_dA(const or_material* m, double phi, double dV[4]) {
         }
         dV[k] = (4.0 * d[1] - d[0]) / 3.0;
     }
+}
+
+/* ---- SH: the wave polarised normal to the plane ----------------------------------------
+   Its Christoffel entry is C_2j2l n_j n_l = c66 n1^2 + c44 n3^2 for the in-plane direction
+   n = (n1 across the axis, n3 along it): an elliptical slowness curve, so the wave surface
+   is an ellipse and the group speed has a closed form. */
+double or_sh_phase_speed(const or_material* m, double th_p) {
+    double c = cos(th_p), s = sin(th_p);
+    return sqrt((m->c66 * c * c + m->c44 * s * s) / m->rho);
+}
+
+double or_sh_phase_speed_deriv(const or_material* m, double th_p) {
+    double v = or_sh_phase_speed(m, th_p);
+    return (m->c44 - m->c66) * sin(2.0 * th_p) / (2.0 * m->rho * v);
+}
+
+double or_sh_group_speed(const or_material* m, double phi) {
+    double c = cos(phi), s = sin(phi);
+    return 1.0 / sqrt(c * c * m->rho / m->c66 + s * s * m->rho / m->c44);
+}
+
+double or_sh_group_speed_deriv(const or_material* m, double phi) {
+    double V = or_sh_group_speed(m, phi);
+    /* V^-2 = cos^2 rho/c66 + sin^2 rho/c44 */
+    double dinv2 = sin(2.0 * phi) * (m->rho / m->c44 - m->rho / m->c66);
+    return -0.5 * V * V * V * dinv2;
+}
+
+double or_phase_speed(const or_material* m, double th_p) {
+    return m->wave == OR_WAVE_SH ? or_sh_phase_speed(m, th_p) : or_qp_phase_speed(m, th_p);
+}
+double or_phase_speed_deriv(const or_material* m, double th_p) {
+    return m->wave == OR_WAVE_SH ? or_sh_phase_speed_deriv(m, th_p) : or_qp_phase_speed_deriv(m, th_p);
+}
+double or_group_speed(const or_material* m, double phi) {
+    return m->wave == OR_WAVE_SH ? or_sh_group_speed(m, phi) : or_qp_group_speed(m, phi);
+}
+double or_group_speed_deriv(const or_material* m, double phi) {
+    return m->wave == OR_WAVE_SH ? or_sh_group_speed_deriv(m, phi) : or_qp_group_speed_deriv(m, phi);
+}
+double or_group_speed_support(const or_material* m, double phi) {
+    return support_route(m, phi, or_phase_speed);
 }
