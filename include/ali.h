@@ -66,7 +66,19 @@ typedef struct {
     int32_t graph;           /* 1: relaxation passes are replayed from captured HIP graphs (one
                                 per argument signature, kept by the handle); 0: launched one by
                                 one; default 1                                                 */
+    int32_t wave;            /* ALI_WAVE_QP (default): the in-plane quasi-P wave of the paper;
+                                ALI_WAVE_SH: the shear wave polarised normal to the plane       */
 } ali_options;
+
+/* Wave of a call.  QP uses c11, c13, c33, c55 (needs c11, c33, c55 > 0 and
+   c11*c33 > c13^2).  SH (an extension the paper names in Section 6) uses c44 and c66: its
+   Christoffel entry is c66 n1^2 + c44 n3^2 (n1 across the axis, n3 along it), an
+   elliptical slowness curve (needs c44, c66 > 0).  The SH speeds are those of the qP wave
+   of the record c11 = c66, c33 = c44, c55 = min(c44, c66), c13 = -c55, whose in-plane
+   Christoffel matrix is diagonal with the SH entry as its larger one, so every kernel runs
+   unchanged on that record.  Rays and the orientation gradient follow the same speeds;
+   the stiffness gradient is qP only. */
+enum { ALI_WAVE_QP = 0, ALI_WAVE_SH = 1 };
 
 /* Arithmetic of the float32 entry points.  MIXED keeps travel times, scores and every
    comparison that decides a stencil in float64 and computes each stencil's wavefront /

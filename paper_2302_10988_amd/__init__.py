@@ -34,6 +34,8 @@ def default_options(**overrides):
     lib.ali_default_options(ctypes.byref(o))
     for k, v in overrides.items():
         if v is not None:
+            if k == "wave" and isinstance(v, str):
+                v = _lib.WAVE[v]
             setattr(o, k, int(v))
     return o
 
@@ -168,7 +170,9 @@ class Solver:
         c55, c44, c66 [Pa], rho [kg/m^3]); mat_id: uint8 [nz, nx] device tensor;
         orient: symmetry-axis angle [rad], float32 (float64 for precision="f64") [nz, nx];
         sources: [(i, j), ...]; arith (float32 output only): "mixed" (float64 times and
-        decisions, float32 wavefront math), "f32" or "f64".  Returns (T, stats dict)."""
+        decisions, float32 wavefront math), "f32" or "f64"; extra: other ali_options fields by
+        name (wave="sh" for the shear wave polarised normal to the plane).  Returns (T, stats
+        dict)."""
         import torch
         nz, nx = mat_id.shape
         fdt = torch.float32 if precision == "f32" else torch.float64
@@ -230,18 +234,19 @@ class Solver:
         return out, stats.as_dict()
 
     def trace_rays(self, h, mats, mat_id, orient, T, sources, receivers, window=None, sub=None,
-                   max_pts=None):
+                   max_pts=None, wave=None):
         """Ray paths from every receiver to every source through the fields T
-        [n_src, nz, nx] (float32 or float64 device tensor).  Returns (paths [n_src, n_rec,
-        max_pts, 2] float32 grid coordinates, npts [n_src, n_rec] int32 (negative: source
-        not reached), tray [n_src, n_rec] float32 seconds)."""
+        [n_src, nz, nx] (float32 or float64 device tensor); wave "qp" (default) or "sh" as
+        for the fields.  Returns (paths [n_src, n_rec, max_pts, 2] float32 grid coordinates,
+        npts [n_src, n_rec] int32 (negative: source not reached), tray [n_src, n_rec]
+        float32 seconds)."""
         import torch
         nz, nx = mat_id.shape
         m_arr, nm = _materials(mats)
         s_arr, ns = _nodes(sources)
         r_arr, nr = _nodes(receivers)
         g = _lib.Grid(int(nx), int(nz), float(h))
-        opt = default_options(ray_window=window, ray_sub=sub, ray_max_pts=max_pts)
+        opt = default_options(ray_window=window, ray_sub=sub, ray_max_pts=max_pts, wave=wave)
         dev = mat_id.device
         paths = torch.empty((ns, nr, opt.ray_max_pts, 2), dtype=torch.float32, device=dev)
         npts = torch.empty((ns, nr), dtype=torch.int32, device=dev)

@@ -36,7 +36,8 @@ class Options(ctypes.Structure):
     _fields_ = [("src_box_radius", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("inner_sweeps", ctypes.c_int32), ("band_cells", ctypes.c_int32),
                 ("ray_window", ctypes.c_int32), ("ray_max_pts", ctypes.c_int32),
-                ("arith", ctypes.c_int32), ("ray_sub", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("arith", ctypes.c_int32), ("ray_sub", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("wave", ctypes.c_int32)]
 
 MAX_LEVELS = 8
 
@@ -47,6 +48,7 @@ class Refine(ctypes.Structure):
 
 
 ARITH = {"mixed": 0, "f32": 1, "f64": 2}
+WAVE = {"qp": 0, "sh": 1}
 TUNE_CANDIDATES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4), (3, 4)]   # (band_cells, inner_sweeps)
 
 

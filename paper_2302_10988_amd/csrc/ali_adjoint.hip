@@ -688,8 +688,10 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     ali_default_options(&opt);
     if (opt_in) opt = *opt_in;
     if (!recv) return H->fail(ALI_EINVAL, "receivers are NULL");
-    ali_status st = validate_batch(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, recv);
+    ali_status st = validate_batch(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, recv, opt.wave);
     if (st != ALI_OK) return st;
+    if (d_dA && opt.wave != ALI_WAVE_QP)
+        return H->fail(ALI_EUNSUPPORTED, "the stiffness gradient is available for the qP wave only");
     if (!d_in) return H->fail(ALI_EINVAL, mode == 1 ? "d_obs is NULL" : "d_dLdT is NULL");
     if (!d_dth) return H->fail(ALI_EINVAL, "d_dLdtheta is NULL");
     int64_t n_fields64 = 0, NF = 0;

@@ -15,6 +15,7 @@ extern "C" void ali_default_options(ali_options* o) {
     o->arith = ALI_ARITH_MIXED;
     o->ray_sub = 8;
     o->graph = 1;
+    o->wave = ALI_WAVE_QP;
 }
 
 extern "C" ali_status ali_create(ali_handle** out, int device, void* hip_stream) {

@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <map>
 #include <string>
+#include <vector>
 
 #include "../../include/ali.h"
 
@@ -111,26 +112,59 @@ inline ali_status set_device(ali_handle* H) {
     return ALI_OK;
 }
 
+// one material record, checked for the wave of the call
+inline ali_status check_material(ali_handle* H, const ali_material& m, int k, int wave) {
+    const double v[7] = {m.c11, m.c13, m.c33, m.c55, m.c44, m.c66, m.rho};
+    for (double x : v)
+        if (!isfinite(x)) return H->fail(ALI_EINVAL, "material " + std::to_string(k) + " has a non-finite entry");
+    if (!(m.rho > 0.0)) return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": rho must be > 0");
+    if (wave == ALI_WAVE_SH) {
+        if (!(m.c44 > 0.0 && m.c66 > 0.0))
+            return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": c44, c66 must be > 0 (SH)");
+        return ALI_OK;
+    }
+    if (wave != ALI_WAVE_QP) return H->fail(ALI_EINVAL, "unknown wave");
+    if (!(m.c11 > 0.0 && m.c33 > 0.0 && m.c55 > 0.0))
+        return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": c11, c33, c55 must be > 0");
+    if (!(m.c11 * m.c33 > m.c13 * m.c13))
+        return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": c11*c33 must exceed c13^2");
+    return ALI_OK;
+}
+
+// The record the kernels use.  For SH: c11 = c66, c33 = c44, c55 = min(c44, c66),
+// c13 = -c55.  Its in-plane Christoffel matrix is diagonal, (c66 s^2 + c55 c^2,
+// c55 s^2 + c44 c^2) / rho for s, c of the angle from the axis, and with c55 the smaller
+// of c44, c66 the larger entry is (c66 s^2 + c44 c^2) / rho at every angle: the SH entry.
+// The qP root, its group velocity and every derivative are then those of SH.
+inline ali_material wave_record(const ali_material& m, int wave) {
+    if (wave != ALI_WAVE_SH) return m;
+    ali_material r = m;
+    r.c11 = m.c66;
+    r.c33 = m.c44;
+    r.c55 = m.c44 < m.c66 ? m.c44 : m.c66;
+    r.c13 = -r.c55;
+    return r;
+}
+
+inline std::vector<ali_material> wave_materials(const ali_material* mats, int n_mats, int wave) {
+    std::vector<ali_material> out(n_mats > 0 ? n_mats : 0);
+    for (int k = 0; k < n_mats; ++k) out[k] = wave_record(mats[k], wave);
+    return out;
+}
+
 // host-side validation shared by every entry point taking a medium
 template <typename oreal>
 inline ali_status validate_medium(ali_handle* H, const ali_grid* g, const ali_material* mats,
                                   int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient,
-                                  const ali_node* srcs, int32_t n_src) {
+                                  const ali_node* srcs, int32_t n_src, int wave = ALI_WAVE_QP) {
     if (!g) return H->fail(ALI_EINVAL, "grid is NULL");
     if (g->nx < 3 || g->nz < 3) return H->fail(ALI_EINVAL, "grid needs nx, nz >= 3");
     if ((int64_t)g->nx * g->nz > (int64_t)1 << 31) return H->fail(ALI_EINVAL, "grid too large");
     if (!(g->h > 0.0) || !isfinite(g->h)) return H->fail(ALI_EINVAL, "grid spacing h must be finite and > 0");
     if (!mats || n_mats < 1 || n_mats > 256) return H->fail(ALI_EINVAL, "need 1..256 materials");
     for (int k = 0; k < n_mats; ++k) {
-        const ali_material& m = mats[k];
-        const double v[7] = {m.c11, m.c13, m.c33, m.c55, m.c44, m.c66, m.rho};
-        for (double x : v)
-            if (!isfinite(x)) return H->fail(ALI_EINVAL, "material " + std::to_string(k) + " has a non-finite entry");
-        if (!(m.rho > 0.0)) return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": rho must be > 0");
-        if (!(m.c11 > 0.0 && m.c33 > 0.0 && m.c55 > 0.0))
-            return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": c11, c33, c55 must be > 0");
-        if (!(m.c11 * m.c33 > m.c13 * m.c13))
-            return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": c11*c33 must exceed c13^2");
+        const ali_status st = check_material(H, mats[k], k, wave);
+        if (st != ALI_OK) return st;
     }
     if (!d_mat_id || !d_orient) return H->fail(ALI_EINVAL, "medium arrays are NULL");
     if (!srcs || n_src < 1) return H->fail(ALI_EINVAL, "need at least one source");

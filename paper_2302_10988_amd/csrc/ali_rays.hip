@@ -289,7 +289,7 @@ static ali_status trace_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     ali_options opt;
     ali_default_options(&opt);
     if (opt_in) opt = *opt_in;
-    ali_status st = validate_medium(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src);
+    ali_status st = validate_medium(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt.wave);
     if (st != ALI_OK) return st;
     if (!d_T || !d_paths || !d_npts || !d_tray) return H->fail(ALI_EINVAL, "ray output or field pointer is NULL");
     if (!recv || n_recv < 1) return H->fail(ALI_EINVAL, "need at least one receiver");
@@ -303,10 +303,10 @@ static ali_status trace_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     if (set_device(H) != ALI_OK) return ALI_EDEVICE;
     hipStream_t S = H->stream;
 
+    const std::vector<ali_material> wm = wave_materials(mats, n_mats, opt.wave);
     std::vector<MatA> hm(n_mats);
     for (int k = 0; k < n_mats; ++k)
-        hm[k] = MatA{mats[k].c11 / mats[k].rho, mats[k].c13 / mats[k].rho, mats[k].c33 / mats[k].rho,
-                     mats[k].c55 / mats[k].rho};
+        hm[k] = MatA{wm[k].c11 / wm[k].rho, wm[k].c13 / wm[k].rho, wm[k].c33 / wm[k].rho, wm[k].c55 / wm[k].rho};
     std::vector<int2> hs(n_src), hr(n_recv);
     for (int k = 0; k < n_src; ++k) hs[k] = make_int2(srcs[k].i, srcs[k].j);
     for (int k = 0; k < n_recv; ++k) hr[k] = make_int2(recv[k].i, recv[k].j);

@@ -207,7 +207,7 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     if (!grid) return H->fail(ALI_EINVAL, "grid is NULL");
     if (!d_out) return H->fail(ALI_EINVAL, "d_T is NULL");
     const ali_medium mw = single_medium(grid, n_mats, n_src, 0);
-    ali_status st = validate_batch(H, &mw, 1, mats, n_mats, d_mat_id, d_orient, srcs, nullptr);
+    ali_status st = validate_batch(H, &mw, 1, mats, n_mats, d_mat_id, d_orient, srcs, nullptr, opt.wave);
     if (st != ALI_OK) return st;
     const int nl = ref.n_levels;
     if (nl < 0 || nl > ALI_MAX_LEVELS) return H->fail(ALI_EINVAL, "n_levels out of range [0, ALI_MAX_LEVELS]");
@@ -229,10 +229,10 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     const int B = 256;
 
     // material table for the straight rays (A = C / rho)
+    const std::vector<ali_material> wm = wave_materials(mats, n_mats, opt.wave);
     std::vector<MatA> hA(n_mats);
     for (int k = 0; k < n_mats; ++k)
-        hA[k] = MatA{mats[k].c11 / mats[k].rho, mats[k].c13 / mats[k].rho, mats[k].c33 / mats[k].rho,
-                     mats[k].c55 / mats[k].rho};
+        hA[k] = MatA{wm[k].c11 / wm[k].rho, wm[k].c13 / wm[k].rho, wm[k].c33 / wm[k].rho, wm[k].c55 / wm[k].rho};
     void *d_A = nullptr, *d_stop = nullptr, *d_fm = nullptr;
     if (!H->scratch("ref_A", sizeof(MatA) * n_mats, &d_A) || !H->scratch("ref_stop", sizeof(real) * n_src, &d_stop))
         return H->fail(ALI_ENOMEM, "device scratch allocation failed");

@@ -408,19 +408,12 @@ k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, co
 // ---------------------------------------------------------------------------------------
 ali_status validate_batch(ali_handle* H, const ali_medium* media, int32_t n_media, const ali_material* mats,
                           int32_t n_mats, const void* d_mat_id, const void* d_orient, const ali_node* srcs,
-                          const ali_node* recv) {
+                          const ali_node* recv, int wave) {
     if (!media || n_media < 1) return H->fail(ALI_EINVAL, "need at least one medium");
     if (!mats || n_mats < 1) return H->fail(ALI_EINVAL, "need at least one material");
     for (int k = 0; k < n_mats; ++k) {
-        const ali_material& m = mats[k];
-        const double v[7] = {m.c11, m.c13, m.c33, m.c55, m.c44, m.c66, m.rho};
-        for (double x : v)
-            if (!isfinite(x)) return H->fail(ALI_EINVAL, "material " + std::to_string(k) + " has a non-finite entry");
-        if (!(m.rho > 0.0)) return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": rho must be > 0");
-        if (!(m.c11 > 0.0 && m.c33 > 0.0 && m.c55 > 0.0))
-            return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": c11, c33, c55 must be > 0");
-        if (!(m.c11 * m.c33 > m.c13 * m.c13))
-            return H->fail(ALI_EINVAL, "material " + std::to_string(k) + ": c11*c33 must exceed c13^2");
+        const ali_status st = check_material(H, mats[k], k, wave);
+        if (st != ALI_OK) return st;
     }
     if (!d_mat_id || !d_orient) return H->fail(ALI_EINVAL, "medium arrays are NULL");
     if (!srcs) return H->fail(ALI_EINVAL, "sources are NULL");
@@ -462,8 +455,11 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
                         int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
                         const ali_node* recv, const ali_options& opt, real* d_T, ali_solve_stats* stats,
                         ForwardState<real, mreal>* fs, const uint32_t* d_fixmask) {
-    ali_status st = validate_batch(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, recv);
+    ali_status st = validate_batch(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, recv, opt.wave);
     if (st != ALI_OK) return st;
+    // the records the kernels use (for SH, the in-plane record with the SH speeds)
+    const std::vector<ali_material> wmats = wave_materials(mats, n_mats, opt.wave);
+    mats = wmats.data();
     if (!d_T) return H->fail(ALI_EINVAL, "d_T is NULL");
     if (opt.src_box_radius < 0 || opt.src_box_radius > 64) return H->fail(ALI_EINVAL, "src_box_radius out of range [0, 64]");
     if (opt.max_sweeps < 1) return H->fail(ALI_EINVAL, "max_sweeps must be >= 1");
@@ -708,7 +704,7 @@ static ali_status solve_impl(ali_handle* H, const ali_medium* media, int32_t n_m
     ali_default_options(&opt);
     if (opt_in) opt = *opt_in;
     if (!d_out) return H->fail(ALI_EINVAL, "d_T is NULL");
-    ali_status st = validate_batch(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, nullptr);
+    ali_status st = validate_batch(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, nullptr, opt.wave);
     if (st != ALI_OK) return st;
     int64_t n_fields = 0, tot = 0;
     batch_sizes(media, n_media, &n_fields, &tot);

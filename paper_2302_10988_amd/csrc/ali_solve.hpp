@@ -290,10 +290,11 @@ template <typename real, typename mreal> struct ForwardState {
     int64_t n_units = 0, field_nodes = 0;
 };
 
-// Validates a batch (media, materials, sources and, when recv != NULL, receivers).
+// Validates a batch (media, materials for the wave, sources and, when recv != NULL,
+// receivers).
 ali_status validate_batch(ali_handle* H, const ali_medium* media, int32_t n_media, const ali_material* mats,
                           int32_t n_mats, const void* d_mat_id, const void* d_orient, const ali_node* srcs,
-                          const ali_node* recv);
+                          const ali_node* recv, int wave = ALI_WAVE_QP);
 
 // Forward solve of every field of a batch into the working field d_T (fields in medium
 // order, each [nz][nx]; type real).  Validates its arguments, records H->ev0 at its start,
