@@ -86,6 +86,9 @@ def _load():
     lib.or_segment_time.restype = D
     lib.or_trace_ray.argtypes = [I, I, D, M, P, P, P, I, I, I, I, I, I, I, P, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.or_trace_ray.restype = I
+    lib.or_trace_ray_family.argtypes = [I, I, D, M, P, P, P, I, I, I, I, I, I, I, I, P, ctypes.POINTER(I),
+                                        ctypes.POINTER(D)]
+    lib.or_trace_ray_family.restype = I
     lib.or_adjoint.argtypes = [I, I, D, M, I, P, P, I, I, I, P, P, P, P]
     lib.or_adjoint.restype = I
     lib.or_qp_phase_speed_deriv.argtypes = [M, D]
@@ -292,19 +295,32 @@ def segment_time(h, mats, mat_id, orient, p0, p1):
 # ---------------------------------------------------------------------------------------
 # Section 5.1: ray tracing
 # ---------------------------------------------------------------------------------------
-def trace_ray(h, mats, mat_id, orient, T, src, start, window=4, sub=8, max_pts=4096):
-    """Ray from node `start` to the source `src` of field T.  Returns (points [n, 2] in
-    grid units (x, z), integrated time, reached flag)."""
+def trace_ray(h, mats, mat_id, orient, T, src, start, window=4, sub=8, max_pts=4096, family=-1):
+    """Ray from node `start` to the source `src` of field T; family -1 changes the plane
+    family along the ray, 0..3 fixes it (x = k, z = k, x + z = k, x - z = k).  Returns
+    (points [n, 2] in grid units (x, z), integrated time, reached flag)."""
     mat_id, orient = _medium(mat_id, orient)
     T = np.ascontiguousarray(T, dtype=np.float64)
     nz, nx = mat_id.shape
     pts = np.zeros((max_pts, 2))
     n = ctypes.c_int()
     t = ctypes.c_double()
-    st = _load().or_trace_ray(nx, nz, float(h), _mat_array(mats), _ptr(mat_id), _ptr(orient), _ptr(T),
-                              int(src[0]), int(src[1]), int(start[0]), int(start[1]), int(window),
-                              int(sub), int(max_pts), _ptr(pts), ctypes.byref(n), ctypes.byref(t))
+    st = _load().or_trace_ray_family(nx, nz, float(h), _mat_array(mats), _ptr(mat_id), _ptr(orient), _ptr(T),
+                                     int(src[0]), int(src[1]), int(start[0]), int(start[1]), int(family),
+                                     int(window), int(sub), int(max_pts), _ptr(pts), ctypes.byref(n),
+                                     ctypes.byref(t))
     return pts[: n.value].copy(), t.value, st == 0
+
+
+def trace_ray_fastest_fixed(h, mats, mat_id, orient, T, src, start, window=4, sub=8, max_pts=4096):
+    """The fastest of the four fixed-family rays (the first family wins a tie).  Returns
+    (points, time, reached, family)."""
+    best = None
+    for f in range(4):
+        pts, t, ok = trace_ray(h, mats, mat_id, orient, T, src, start, window, sub, max_pts, f)
+        if ok and (best is None or t < best[1]):
+            best = (pts, t, ok, f)
+    return best if best is not None else (np.zeros((0, 2)), float("inf"), False, -1)
 
 
 # ---------------------------------------------------------------------------------------

@@ -177,6 +177,12 @@ int or_trace_ray(int nx, int nz, double h, const or_material* mats, const uint8_
                  const double* orient, const double* T, int si, int sj, int ri, int rj,
                  int window, int sub, int max_pts, double* pts, int* n_pts, double* t_ray);
 
+/* Same with the plane family fixed for the whole ray (family 0: x = k, 1: z = k,
+   2: x + z = k, 3: x - z = k; -1: the changing family of or_trace_ray). */
+int or_trace_ray_family(int nx, int nz, double h, const or_material* mats, const uint8_t* mat_id,
+                        const double* orient, const double* T, int si, int sj, int ri, int rj, int family,
+                        int window, int sub, int max_pts, double* pts, int* n_pts, double* t_ray);
+
 /* ---- gradient with respect to orientation (frozen choices) --------------------------- */
 
 /* partial derivatives of or_stencil_estimate with respect to ta, tb, tc and theta_ax, and

@@ -1,0 +1,102 @@
+"""Pins for the oracle's fixed plane families (Section 5.1: one family of equispaced planes
+for the whole ray, each of the four tried, the fastest kept).
+
+  - structure: the interior points lie on consecutive planes of the family strictly
+    between the start and the source, in order; a start on the source's own plane gives
+    the straight segment; the fixed family through the exact gradient field still follows
+    the analytic circle of Section 5.2;
+  - homogeneous TI medium: every family that crosses the path is close to the straight
+    segment, none is faster than it, and the fastest of the four is at most each one;
+  - a family nearly parallel to the straight path is worse than one across it (the paper's
+    remark that the planes should cross the ray).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synthmedia as sm
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_gradient_ray.json")))
+FAM_N = [(1, 0), (0, 1), (1, 1), (1, -1)]
+
+
+def _plane(f, p):
+    return FAM_N[f][0] * p[0] + FAM_N[f][1] * p[1]
+
+
+@pytest.mark.parametrize("theta", [0.0, 40.0])
+def test_fixed_family_structure_and_straightness(orc, theta):
+    m = sm.homogeneous(61, 61, 1e-3, sm.TI_STEEL, theta, (10, 12))
+    src, start = (10, 12), (52, 47)
+    T = orc.solve_fmm(m.h, m.mats, m.mat_id, m.orient, src, 2)
+    straight = orc.segment_time(m.h, m.mats, m.mat_id, m.orient, start, src)
+    times = []
+    for f in range(4):
+        pts, t, ok = orc.trace_ray(m.h, m.mats, m.mat_id, m.orient, T, src, start, family=f)
+        assert ok
+        assert np.allclose(pts[0], start) and np.allclose(pts[-1], src)
+        k0, kS = _plane(f, start), _plane(f, src)
+        step = 1 if kS > k0 else -1
+        ks = [_plane(f, p) for p in pts[1:-1]]
+        assert np.allclose(ks, np.arange(k0 + step, kS, step), atol=1e-9)
+        assert len(pts) == abs(kS - k0) + 1
+        assert t >= straight * (1 - 1e-12)
+        if abs(kS - k0) >= 20:
+            # planes crossing the path: close to the straight segment (the x - z = k family
+            # meets this path at a grazing angle, 7 planes, and is about 1 % slower)
+            assert t == pytest.approx(straight, rel=1e-2)
+            a, b = np.array(start, float), np.array(src, float)
+            u = (b - a) / np.linalg.norm(b - a)
+            assert np.abs((pts - a) @ np.array([-u[1], u[0]])).max() < 1.5
+        times.append(t)
+    pts, t, ok, f = orc.trace_ray_fastest_fixed(m.h, m.mats, m.mat_id, m.orient, T, src, start)
+    assert ok and t == min(times) and f == int(np.argmin(times))
+    assert t == pytest.approx(straight, rel=5e-3)
+
+
+def test_start_on_the_source_plane(orc):
+    m = sm.homogeneous(31, 31, 1e-3, sm.TI_STEEL, 20.0, (10, 12))
+    src = (10, 12)
+    T = orc.solve_fmm(m.h, m.mats, m.mat_id, m.orient, src, 2)
+    for f, start in ((0, (10, 25)), (1, (25, 12)), (2, (14, 8)), (3, (15, 17))):
+        pts, t, ok = orc.trace_ray(m.h, m.mats, m.mat_id, m.orient, T, src, start, family=f)
+        assert ok and len(pts) == 2
+        assert t == orc.segment_time(m.h, m.mats, m.mat_id, m.orient, start, src)
+
+
+def test_fixed_family_through_exact_gradient_field(orc):
+    # x = k planes cross the circular ray of Section 5.2 everywhere (it runs left to right)
+    n = GOLD["cells"] + 1
+    g, v0, h = GOLD["g_per_cell"], GOLD["velocity_at_x0_m_per_s"], GOLD["cell_size_m"]
+    mats = [sm.isotropic(v0 + g * i, (v0 + g * i) / 1.8, 1000.0) for i in range(n)]
+    mat_id = np.tile(np.arange(n, dtype=np.uint8), (n, 1))
+    orient = np.zeros((n, n))
+    src, rec = GOLD["source_node"], GOLD["receiver_node"]
+    gg = g / h
+    J, I = np.mgrid[0:n, 0:n]
+    v = v0 + g * I
+    vr = v0 + g * rec[0]
+    Tex = np.arccosh(1 + gg * gg * ((I - rec[0]) ** 2 + (J - rec[1]) ** 2) * h * h / (2 * v * vr)) / gg
+    pts, t, ok = orc.trace_ray(h, mats, mat_id, orient, Tex, rec, src, family=0)
+    assert ok
+    cx, cz = GOLD["circle_centre"]
+    dev = np.abs(np.hypot(pts[:, 0] - cx, pts[:, 1] - cz) - GOLD["circle_radius"])
+    assert dev.max() < 0.5
+    assert t >= GOLD["true_time_discretised_s"] * (1 - 1e-6)
+    assert t == pytest.approx(GOLD["true_time_discretised_s"], rel=3e-4)
+
+
+def test_planes_across_the_ray_beat_planes_along_it(orc):
+    # a nearly horizontal path: z = k planes are crossed at a grazing angle (few points,
+    # each far from the last); x = k planes cross it squarely
+    m = sm.homogeneous(81, 41, 1e-3, sm.TI_STEEL, 25.0, (5, 15))
+    src, start = (5, 15), (75, 22)
+    T = orc.solve_fmm(m.h, m.mats, m.mat_id, m.orient, src, 2)
+    _, tx, okx = orc.trace_ray(m.h, m.mats, m.mat_id, m.orient, T, src, start, family=0)
+    pz, tz, okz = orc.trace_ray(m.h, m.mats, m.mat_id, m.orient, T, src, start, family=1)
+    assert okx and okz and len(pz) == 8
+    straight = orc.segment_time(m.h, m.mats, m.mat_id, m.orient, start, src)
+    assert tx - straight <= tz - straight + 1e-15
