@@ -68,7 +68,19 @@ typedef struct {
                                 one; default 1                                                 */
     int32_t wave;            /* ALI_WAVE_QP (default): the in-plane quasi-P wave of the paper;
                                 ALI_WAVE_SH: the shear wave polarised normal to the plane       */
+    int32_t ray_planes;      /* ray tracer plane families: ALI_RAY_CHANGING (default) or a fixed
+                                family / the fastest of the four fixed families (below)         */
 } ali_options;
+
+/* Plane families of the ray tracer (Section 5.1).  CHANGING: each step uses the family at
+   the largest angle to the last segment, candidates around the straight-ahead point, and
+   stops within 1.6 spacings of the source.  FIXED_*: one family for the whole ray
+   (x = k, z = k, x + z = k, x - z = k), its planes strictly between the receiver and the
+   source crossed in order; on each plane every grid node is costed first, then the fine
+   window (ray_window, ray_sub) around the best node; the last point joins the source.
+   FASTEST_FIXED: the four fixed families, the fastest reached ray kept. */
+enum { ALI_RAY_CHANGING = 0, ALI_RAY_FIXED_X = 1, ALI_RAY_FIXED_Z = 2, ALI_RAY_FIXED_DIAG = 3,
+       ALI_RAY_FIXED_ANTI = 4, ALI_RAY_FASTEST_FIXED = 5 };
 
 /* Wave of a call.  QP uses c11, c13, c33, c55 (needs c11, c33, c55 > 0 and
    c11*c33 > c13^2).  SH (an extension the paper names in Section 6) uses c44 and c66: its

@@ -234,10 +234,11 @@ class Solver:
         return out, stats.as_dict()
 
     def trace_rays(self, h, mats, mat_id, orient, T, sources, receivers, window=None, sub=None,
-                   max_pts=None, wave=None):
+                   max_pts=None, wave=None, planes=None):
         """Ray paths from every receiver to every source through the fields T
         [n_src, nz, nx] (float32 or float64 device tensor); wave "qp" (default) or "sh" as
-        for the fields.  Returns (paths [n_src, n_rec, max_pts, 2] float32 grid coordinates,
+        for the fields; planes "changing" (default), "x", "z", "diag", "anti" (one fixed
+        family) or "fastest" (the fastest of the four fixed families).  Returns (paths [n_src, n_rec, max_pts, 2] float32 grid coordinates,
         npts [n_src, n_rec] int32 (negative: source not reached), tray [n_src, n_rec]
         float32 seconds)."""
         import torch
@@ -246,7 +247,8 @@ class Solver:
         s_arr, ns = _nodes(sources)
         r_arr, nr = _nodes(receivers)
         g = _lib.Grid(int(nx), int(nz), float(h))
-        opt = default_options(ray_window=window, ray_sub=sub, ray_max_pts=max_pts, wave=wave)
+        opt = default_options(ray_window=window, ray_sub=sub, ray_max_pts=max_pts, wave=wave,
+                              ray_planes=_lib.RAY_PLANES[planes] if planes is not None else None)
         dev = mat_id.device
         paths = torch.empty((ns, nr, opt.ray_max_pts, 2), dtype=torch.float32, device=dev)
         npts = torch.empty((ns, nr), dtype=torch.int32, device=dev)

@@ -16,6 +16,7 @@ extern "C" void ali_default_options(ali_options* o) {
     o->ray_sub = 8;
     o->graph = 1;
     o->wave = ALI_WAVE_QP;
+    o->ray_planes = ALI_RAY_CHANGING;
 }
 
 extern "C" ali_status ali_create(ali_handle** out, int device, void* hip_stream) {

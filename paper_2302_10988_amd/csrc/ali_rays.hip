@@ -138,6 +138,16 @@ __device__ __forceinline__ void fam_node(int f, int k, int m, int& i, int& j) {
     }
 }
 
+// parameters of the grid nodes on plane k of family f
+__device__ __forceinline__ void plane_range(int nx, int nz, int f, int k, int& lo, int& hi) {
+    switch (f) {
+        case 0: lo = 0; hi = nz - 1; break;
+        case 1: lo = 0; hi = nx - 1; break;
+        case 2: lo = k - (nz - 1) > 0 ? k - (nz - 1) : 0; hi = k < nx - 1 ? k : nx - 1; break;
+        default: lo = k > 0 ? k : 0; hi = k + nz - 1 < nx - 1 ? k + nz - 1 : nx - 1; break;
+    }
+}
+
 template <typename treal>
 __device__ __forceinline__ double field_at(const treal* __restrict__ T, int nx, int nz, int i, int j) {
     if (i < 0 || j < 0 || i >= nx || j >= nz) return INFINITY;
@@ -152,7 +162,7 @@ constexpr int RAY_LDS_MATS = 4;
 template <typename treal, bool LDS_TAB>
 __global__ void __launch_bounds__(RAYS_PER_GROUP * 64)
 k_trace(RayMedium M, int n_mats, int n_rays, const treal* __restrict__ Tall, const int2* __restrict__ srcs,
-        const int2* __restrict__ recv, int n_recv, int window, int sub, int max_pts,
+        const int2* __restrict__ recv, int n_recv, int window, int sub, int max_pts, int family,
         float2* __restrict__ paths, int32_t* __restrict__ npts, float* __restrict__ tray) {
     __shared__ float s_tab[LDS_TAB ? RAY_LDS_MATS * (GT_N + 1) : 1];
     if (LDS_TAB) {
@@ -190,36 +200,85 @@ k_trace(RayMedium M, int n_mats, int n_rays, const treal* __restrict__ Tall, con
     if (lane == 0) path[0] = make_float2((float)px, (float)pz);
     ++n;
     bool reached = false;
+    // a fixed family: plane indices of the start and of S
+    int kS = 0, k0 = 0, fsgn = 1;
+    if (family >= 0) {
+        int a, b, ex, ez;
+        fam(family, a, b, ex, ez);
+        kS = a * S.x + b * S.y;
+        k0 = a * R0.x + b * R0.y;
+        fsgn = kS > k0 ? 1 : -1;
+    }
     for (int guard = 0; guard < max_pts; ++guard) {
-        if (hypot(px - S.x, pz - S.y) < 1.6) {
-            if (px != S.x || pz != S.y) {
+        int f, kk, m0;
+        if (family < 0) {
+            if (hypot(px - S.x, pz - S.y) < 1.6) {
+                if (px != S.x || pz != S.y) {
+                    keep(px, pz, (double)S.x, (double)S.y);
+                    if (lane == 0) path[n] = make_float2((float)S.x, (float)S.y);
+                    ++n;
+                }
+                reached = true;
+                break;
+            }
+            if (n + 1 >= max_pts) break;
+            // family making the largest angle with the direction of travel (first wins ties)
+            f = 0;
+            double best = 2.0;
+            const double dl = sqrt(dx * dx + dz * dz);
+            for (int q = 0; q < 4; ++q) {
+                int a, b, ex, ez;
+                fam(q, a, b, ex, ez);
+                const double c = fabs(dx * ex + dz * ez) / (dl * sqrt((double)(ex * ex + ez * ez)));
+                if (c < best) { best = c; f = q; }
+            }
+            int fnx, fnz, ex, ez;
+            fam(f, fnx, fnz, ex, ez);
+            const double dn = dx * fnx + dz * fnz;
+            const int sgn = dn > 0.0 ? 1 : -1;
+            const double ip = px * fnx + pz * fnz;
+            kk = (int)floor(ip + 0.5) + sgn;
+            const double st = (kk - ip) / dn;
+            const double xs = px + st * dx, zs = pz + st * dz;
+            m0 = (int)floor((f == 0 ? zs : xs) + 0.5);
+        } else {
+            f = family;
+            int fnx, fnz, ex, ez;
+            fam(f, fnx, fnz, ex, ez);
+            kk = (int)floor(px * fnx + pz * fnz + 0.5) + fsgn;
+            // the next plane is S's (or the start lies on it): close with S
+            if (kS == k0 || (kk - kS) * fsgn >= 0) {
                 keep(px, pz, (double)S.x, (double)S.y);
                 if (lane == 0) path[n] = make_float2((float)S.x, (float)S.y);
                 ++n;
+                reached = true;
+                break;
             }
-            reached = true;
-            break;
-        }
-        if (n + 1 >= max_pts) break;
-        // family making the largest angle with the direction of travel (first wins ties)
-        int f = 0;
-        double best = 2.0;
-        const double dl = sqrt(dx * dx + dz * dz);
-        for (int q = 0; q < 4; ++q) {
-            int a, b, ex, ez;
-            fam(q, a, b, ex, ez);
-            const double c = fabs(dx * ex + dz * ez) / (dl * sqrt((double)(ex * ex + ez * ez)));
-            if (c < best) { best = c; f = q; }
+            if (n + 1 >= max_pts) break;
+            // every grid node of the plane first (the lanes stride over them), then the
+            // fine window around the best: smallest cost, then lowest parameter
+            int lo, hi;
+            plane_range(M.nx, M.nz, f, kk, lo, hi);
+            double bc = INFINITY;
+            int bm = lo;
+            for (int mm = lo + lane; mm <= hi; mm += 64) {
+                int ci, cj;
+                fam_node(f, kk, mm, ci, cj);
+                const double tc = field_at<treal>(T, M.nx, M.nz, ci, cj);
+                if (tc < INFINITY) {
+                    const double c = segment_time(M, tab, px, pz, (double)ci, (double)cj) + tc;
+                    if (c < bc) { bc = c; bm = mm; }
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double oc = __shfl_xor(bc, off);
+                const int om = __shfl_xor(bm, off);
+                if (oc < bc || (oc == bc && om < bm)) { bc = oc; bm = om; }
+            }
+            m0 = bm;
         }
         int fnx, fnz, ex, ez;
         fam(f, fnx, fnz, ex, ez);
-        const double dn = dx * fnx + dz * fnz;
-        const int sgn = dn > 0.0 ? 1 : -1;
-        const double ip = px * fnx + pz * fnz;
-        const int kk = (int)floor(ip + 0.5) + sgn;
-        const double st = (kk - ip) / dn;
-        const double xs = px + st * dx, zs = pz + st * dz;
-        const int m0 = (int)floor((f == 0 ? zs : xs) + 0.5);
         int i00, j00;
         fam_node(f, kk, 0, i00, j00);
         // this lane's candidate (the segment walk does not wait for the field values)
@@ -281,6 +340,28 @@ k_trace(RayMedium M, int n_mats, int n_rays, const treal* __restrict__ Tall, con
     }
 }
 
+// fastest of the four fixed-family rays (reached rays only; the first family wins a tie)
+__global__ void k_pick(int n_rays, int max_pts, const float2* __restrict__ paths4, const int32_t* __restrict__ npts4,
+                       const float* __restrict__ tray4, float2* __restrict__ paths, int32_t* __restrict__ npts,
+                       float* __restrict__ tray) {
+    const int r = blockIdx.x;
+    int best = 0;
+    for (int f = 1; f < 4; ++f) {
+        const int64_t a = (int64_t)f * n_rays + r, b = (int64_t)best * n_rays + r;
+        const bool fa = npts4[a] > 0, fb = npts4[b] > 0;
+        if ((fa && !fb) || (fa && fb && tray4[a] < tray4[b])) best = f;
+    }
+    const int64_t q = (int64_t)best * n_rays + r;
+    const int32_t np = npts4[q];
+    const int cnt = np > 0 ? np : -np;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+        paths[(int64_t)r * max_pts + i] = paths4[q * max_pts + i];
+    if (threadIdx.x == 0) {
+        npts[r] = np;
+        tray[r] = tray4[q];
+    }
+}
+
 template <typename treal>
 static ali_status trace_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
                              const uint8_t* d_mat_id, const float* d_orient, const treal* d_T,
@@ -299,6 +380,8 @@ static ali_status trace_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     if (opt.ray_window < 1 || opt.ray_sub < 1 || opt.ray_window * opt.ray_sub > 32)
         return H->fail(ALI_EINVAL, "ray_window * ray_sub must be in [1, 32]");
     if (opt.ray_max_pts < 2) return H->fail(ALI_EINVAL, "ray_max_pts must be >= 2");
+    if (opt.ray_planes < ALI_RAY_CHANGING || opt.ray_planes > ALI_RAY_FASTEST_FIXED)
+        return H->fail(ALI_EINVAL, "unknown ray_planes");
     if ((int64_t)n_src * n_recv > (int64_t)1 << 30) return H->fail(ALI_EINVAL, "too many rays");
     if (set_device(H) != ALI_OK) return ALI_EDEVICE;
     hipStream_t S = H->stream;
@@ -325,14 +408,31 @@ static ali_status trace_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     RayMedium M{grid->nx, grid->nz, grid->h, d_mat_id, d_orient, (const float*)d_tab};
     const int n_rays = n_src * n_recv;
     const unsigned groups = (unsigned)((n_rays + RAYS_PER_GROUP - 1) / RAYS_PER_GROUP);
-    if (n_mats <= RAY_LDS_MATS)
-        hipLaunchKernelGGL((k_trace<treal, true>), dim3(groups), dim3(RAYS_PER_GROUP * 64), 0, S, M, n_mats, n_rays, d_T,
-                           (const int2*)d_src, (const int2*)d_rec, n_recv, opt.ray_window, opt.ray_sub,
-                           opt.ray_max_pts, (float2*)d_paths, d_npts, d_tray);
-    else
-        hipLaunchKernelGGL((k_trace<treal, false>), dim3(groups), dim3(RAYS_PER_GROUP * 64), 0, S, M, n_mats, n_rays, d_T,
-                           (const int2*)d_src, (const int2*)d_rec, n_recv, opt.ray_window, opt.ray_sub,
-                           opt.ray_max_pts, (float2*)d_paths, d_npts, d_tray);
+    auto launch = [&](int family, float2* pth, int32_t* np, float* tr) {
+        if (n_mats <= RAY_LDS_MATS)
+            hipLaunchKernelGGL((k_trace<treal, true>), dim3(groups), dim3(RAYS_PER_GROUP * 64), 0, S, M, n_mats, n_rays,
+                               d_T, (const int2*)d_src, (const int2*)d_rec, n_recv, opt.ray_window, opt.ray_sub,
+                               opt.ray_max_pts, family, pth, np, tr);
+        else
+            hipLaunchKernelGGL((k_trace<treal, false>), dim3(groups), dim3(RAYS_PER_GROUP * 64), 0, S, M, n_mats,
+                               n_rays, d_T, (const int2*)d_src, (const int2*)d_rec, n_recv, opt.ray_window,
+                               opt.ray_sub, opt.ray_max_pts, family, pth, np, tr);
+    };
+    if (opt.ray_planes == ALI_RAY_FASTEST_FIXED) {
+        void *d_p4, *d_n4, *d_t4;
+        const size_t npath = (size_t)n_rays * opt.ray_max_pts;
+        if (!H->scratch("ray_p4", sizeof(float2) * 4 * npath, &d_p4) ||
+            !H->scratch("ray_n4", sizeof(int32_t) * 4 * n_rays, &d_n4) ||
+            !H->scratch("ray_t4", sizeof(float) * 4 * n_rays, &d_t4))
+            return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+        for (int f = 0; f < 4; ++f)
+            launch(f, (float2*)d_p4 + f * npath, (int32_t*)d_n4 + (size_t)f * n_rays, (float*)d_t4 + (size_t)f * n_rays);
+        hipLaunchKernelGGL(k_pick, dim3((unsigned)n_rays), dim3(256), 0, S, n_rays, opt.ray_max_pts,
+                           (const float2*)d_p4, (const int32_t*)d_n4, (const float*)d_t4, (float2*)d_paths, d_npts,
+                           d_tray);
+    } else {
+        launch(opt.ray_planes == ALI_RAY_CHANGING ? -1 : opt.ray_planes - 1, (float2*)d_paths, d_npts, d_tray);
+    }
     HIPCK(H, hipGetLastError());
     // the host arrays above must outlive the asynchronous copies
     HIPCK(H, hipStreamSynchronize(S));
