@@ -200,9 +200,15 @@ k_trace(RayMedium M, int n_mats, int n_rays, const treal* __restrict__ Tall, con
     if (lane == 0) path[0] = make_float2((float)px, (float)pz);
     ++n;
     bool reached = false;
-    // a fixed family: plane indices of the start and of S
+    // a fixed family: plane indices of the start and of S, and a lower bound of every
+    // table slowness (interpolation stays between two entries; the margin covers rounding)
     int kS = 0, k0 = 0, fsgn = 1;
+    double minsl = 0.0;
     if (family >= 0) {
+        float ms = INFINITY;
+        for (int i = lane; i < n_mats * (GT_N + 1); i += 64) ms = fminf(ms, tab[i]);
+        for (int off = 32; off > 0; off >>= 1) ms = fminf(ms, __shfl_xor(ms, off));
+        minsl = (double)ms * (1.0 - 1e-6);
         int a, b, ex, ez;
         fam(family, a, b, ex, ez);
         kS = a * S.x + b * S.y;
@@ -256,16 +262,42 @@ k_trace(RayMedium M, int n_mats, int n_rays, const treal* __restrict__ Tall, con
             }
             if (n + 1 >= max_pts) break;
             // every grid node of the plane first (the lanes stride over them), then the
-            // fine window around the best: smallest cost, then lowest parameter
+            // fine window around the best: smallest cost, then lowest parameter.  A node's
+            // cost is at least lb = T + length at the smallest slowness of the tables, so
+            // with c* the exact cost of the node of smallest lb, only nodes with lb <= c*
+            // are walked; the others cost more than c* and cannot be the best.
             int lo, hi;
             plane_range(M.nx, M.nz, f, kk, lo, hi);
+            double blb = INFINITY;
+            int blm = lo;
+            for (int mm = lo + lane; mm <= hi; mm += 64) {
+                int ci, cj;
+                fam_node(f, kk, mm, ci, cj);
+                const double tc = field_at<treal>(T, M.nx, M.nz, ci, cj);
+                const double lb = tc + sqrt((ci - px) * (ci - px) + (cj - pz) * (cj - pz)) * M.h * minsl;
+                if (lb < blb) { blb = lb; blm = mm; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(blb, off);
+                const int om = __shfl_xor(blm, off);
+                if (ob < blb || (ob == blb && om < blm)) { blb = ob; blm = om; }
+            }
+            if (!(blb < INFINITY)) break;
+            double cstar = 0.0;
+            if (lane == 0) {
+                int ci, cj;
+                fam_node(f, kk, blm, ci, cj);
+                cstar = segment_time(M, tab, px, pz, (double)ci, (double)cj) + field_at<treal>(T, M.nx, M.nz, ci, cj);
+            }
+            cstar = __shfl(cstar, 0);
             double bc = INFINITY;
             int bm = lo;
             for (int mm = lo + lane; mm <= hi; mm += 64) {
                 int ci, cj;
                 fam_node(f, kk, mm, ci, cj);
                 const double tc = field_at<treal>(T, M.nx, M.nz, ci, cj);
-                if (tc < INFINITY) {
+                const double lb = tc + sqrt((ci - px) * (ci - px) + (cj - pz) * (cj - pz)) * M.h * minsl;
+                if (tc < INFINITY && lb <= cstar) {
                     const double c = segment_time(M, tab, px, pz, (double)ci, (double)cj) + tc;
                     if (c < bc) { bc = c; bm = mm; }
                 }

@@ -100,3 +100,27 @@ def test_planes_across_the_ray_beat_planes_along_it(orc):
     assert okx and okz and len(pz) == 8
     straight = orc.segment_time(m.h, m.mats, m.mat_id, m.orient, start, src)
     assert tx - straight <= tz - straight + 1e-15
+
+
+def test_circular_anomaly_study(orc):
+    # Section 5.3's comparison on a geometry of our choosing (the paper gives none): cubic
+    # steel, axis at 60 deg inside a circle of radius 25 cells and 15 deg outside, source
+    # and receiver on the same column (so the x = k family has no plane between them).
+    # Measured: field 1.5911e-5 s; changing family 1.5698e-5; fixed families 1.6434e-5
+    # (straight), 1.5698e-5, 1.5678e-5, 1.5746e-5; dense-graph optimum 1.5669e-5.
+    n, h, c, rad = 101, 1e-3, 50, 25
+    J, I = np.mgrid[0:n, 0:n]
+    orient = np.where((I - c) ** 2 + (J - c) ** 2 <= rad * rad, math.radians(60.0), math.radians(15.0))
+    mats, mid = [sm.CUBIC_STEEL], np.zeros((n, n), np.uint8)
+    src, rec = (50, 5), (50, 95)
+    T = orc.solve_fmm(h, mats, mid, orient, src, 2)
+    _, tc, okc = orc.trace_ray(h, mats, mid, orient, T, src, rec)
+    p0, t0, ok0 = orc.trace_ray(h, mats, mid, orient, T, src, rec, family=0)
+    _, tb, okb, fb = orc.trace_ray_fastest_fixed(h, mats, mid, orient, T, src, rec)
+    opt = orc.dijkstra_dense(h, mats, mid, orient, src, 6.0)[rec[1], rec[0]]
+    assert okc and ok0 and okb and len(p0) == 2
+    assert t0 == pytest.approx(orc.segment_time(h, mats, mid, orient, rec, src), rel=1e-15)
+    # the rays bend through the anomaly: faster than the straight segment and than the
+    # field's own estimate, within 0.3 % of the dense-graph optimum
+    assert tb <= tc < T[rec[1], rec[0]] and tc < t0
+    assert abs(tb - opt) / opt < 3e-3 and abs(tc - opt) / opt < 3e-3
