@@ -24,7 +24,7 @@ _lib = None
 
 class Material(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("c11", "c13", "c33", "c55", "c44", "c66", "rho")] + \
-               [("wave", ctypes.c_int32)]
+               [("wave", ctypes.c_int32), ("vtab", ctypes.c_int32)]
 
 
 WAVE_QP, WAVE_SH = 0, 1
@@ -33,6 +33,12 @@ WAVE_QP, WAVE_SH = 0, 1
 def as_sh(mats):
     """The same materials for the SH wave (every solver then uses the SH speeds)."""
     return [dict(m, wave=WAVE_SH) for m in mats]
+
+
+def as_table(mats):
+    """The same materials with the paper's velocity table (speeds at whole degrees,
+    linearly interpolated) in place of the run-time Christoffel speeds."""
+    return [dict(m, vtab=1) for m in mats]
 
 
 def build(force: bool = False) -> str:
@@ -123,12 +129,15 @@ def _mat_array(mats):
         if isinstance(m, dict):
             vals = [m[n] for n in ("c11", "c13", "c33", "c55", "c44", "c66", "rho")]
             wave = int(m.get("wave", WAVE_QP))
+            vtab = int(m.get("vtab", 0))
         else:
             vals = list(m)[:7]
             wave = int(list(m)[7]) if len(list(m)) > 7 else WAVE_QP
+            vtab = int(list(m)[8]) if len(list(m)) > 8 else 0
         for n, v in zip(("c11", "c13", "c33", "c55", "c44", "c66", "rho"), vals):
             setattr(arr[k], n, float(v))
         arr[k].wave = wave
+        arr[k].vtab = vtab
     return arr
 
 

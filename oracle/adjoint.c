@@ -127,6 +127,8 @@ int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, co
                const double* orient, int si, int sj, int R, const double* g, double* T_out,
                double* dtheta, double* dA) {
     int64_t N = (int64_t)nx * nz;
+    for (int k = 0; k < n_mats; ++k)   /* derivatives are of the run-time speeds */
+        if (mats[k].vtab) return -1;
     if (dA)   /* the stiffness partials are written for the qP wave */
         for (int k = 0; k < n_mats; ++k)
             if (mats[k].wave != OR_WAVE_QP) return -1;

@@ -33,9 +33,14 @@ extern "C" {
    polarised normal to the plane, Section 6's extension); one value for every material of
    a solve. */
 enum { OR_WAVE_QP = 0, OR_WAVE_SH = 1 };
+/* vtab: 0 = speeds from the Christoffel equation at run time; 1 = the paper's velocity
+   table: the phase speed from the exact speeds at whole degrees of the phase angle and the
+   group speed from those at whole degrees of the group angle, linearly interpolated
+   (Section 3.2 and Table 3's two ALI-FMM rows). */
 typedef struct {
     double c11, c13, c33, c55, c44, c66, rho;
     int32_t wave;
+    int32_t vtab;
 } or_material;
 
 /* ---- Section 3: velocities ------------------------------------------------------- */

@@ -233,14 +233,33 @@ double or_sh_group_speed_deriv(const or_material* m, double phi) {
     return -0.5 * V * V * V * dinv2;
 }
 
-double or_phase_speed(const or_material* m, double th_p) {
+static double exact_phase_speed(const or_material* m, double th_p) {
     return m->wave == OR_WAVE_SH ? or_sh_phase_speed(m, th_p) : or_qp_phase_speed(m, th_p);
+}
+static double exact_group_speed(const or_material* m, double phi) {
+    return m->wave == OR_WAVE_SH ? or_sh_group_speed(m, phi) : or_qp_group_speed(m, phi);
+}
+
+/* the velocity table: f at whole degrees of the angle, linear in between (f is pi-periodic) */
+static double table_lookup(const or_material* m, double ang, double (*f)(const or_material*, double)) {
+    double d = fmod(ang * (180.0 / M_PI), 180.0);
+    if (d < 0.0) d += 180.0;
+    double i = floor(d);
+    double w = d - i;
+    double a = f(m, i * (M_PI / 180.0));
+    if (w == 0.0) return a;
+    double b = f(m, (i + 1.0) * (M_PI / 180.0));
+    return (1.0 - w) * a + w * b;
+}
+
+double or_phase_speed(const or_material* m, double th_p) {
+    return m->vtab ? table_lookup(m, th_p, exact_phase_speed) : exact_phase_speed(m, th_p);
 }
 double or_phase_speed_deriv(const or_material* m, double th_p) {
     return m->wave == OR_WAVE_SH ? or_sh_phase_speed_deriv(m, th_p) : or_qp_phase_speed_deriv(m, th_p);
 }
 double or_group_speed(const or_material* m, double phi) {
-    return m->wave == OR_WAVE_SH ? or_sh_group_speed(m, phi) : or_qp_group_speed(m, phi);
+    return m->vtab ? table_lookup(m, phi, exact_group_speed) : exact_group_speed(m, phi);
 }
 double or_group_speed_deriv(const or_material* m, double phi) {
     return m->wave == OR_WAVE_SH ? or_sh_group_speed_deriv(m, phi) : or_qp_group_speed_deriv(m, phi);

@@ -1,0 +1,78 @@
+"""Pins for the oracle's velocity-table mode (Section 3.2: speeds from a table at whole
+degrees with linear interpolation, the variant of Table 3's first ALI-FMM row).
+
+  - at whole degrees the table speeds are the run-time speeds, in between they are the
+    chord of the two neighbouring ones;
+  - the interpolation moves a speed by at most (1 deg)^2 / 8 times its second derivative:
+    below 2e-4 relative for the steels (measured 1.6e-4); the fields move by about as much;
+  - Table 3's set-up: the table changes the mean error by at most a few percent of itself
+    (the printed rows differ by 0-4 %);
+  - the adjoint differentiates the run-time speeds only, and refuses the table.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthmedia as sm
+
+MATS = [sm.TI_STEEL, sm.CUBIC_STEEL]
+
+
+def test_table_speeds_at_and_between_whole_degrees(orc):
+    for mat in MATS:
+        for wave in (orc.WAVE_QP, orc.WAVE_SH):
+            ex = dict(mat, wave=wave)
+            tb = dict(ex, vtab=1)
+            for k in range(-200, 200, 7):
+                a = math.radians(k)
+                assert orc.phase_speed(tb, a) == pytest.approx(orc.phase_speed(ex, a), rel=1e-12)
+                assert orc.group_speed(tb, a) == pytest.approx(orc.group_speed(ex, a), rel=1e-12)
+            for k in range(0, 180, 11):
+                for w in (0.25, 0.5, 0.8):
+                    a = math.radians(k + w)
+                    lo, hi = math.radians(k), math.radians(k + 1)
+                    chord = (1 - w) * orc.phase_speed(ex, lo) + w * orc.phase_speed(ex, hi)
+                    assert orc.phase_speed(tb, a) == pytest.approx(chord, rel=1e-14)
+                    assert abs(orc.phase_speed(tb, a) / orc.phase_speed(ex, a) - 1) < 2e-4
+                    assert abs(orc.group_speed(tb, a) / orc.group_speed(ex, a) - 1) < 2e-4
+
+
+def test_table_fields_close_to_runtime_fields(orc):
+    m = sm.random_medium(37, 31, 0.2e-3, seed=4, n_mats=3)
+    src = m.sources[0]
+    a = orc.solve_fmm(m.h, m.mats, m.mat_id, m.orient, src, 2)
+    b = orc.solve_fmm(m.h, orc.as_table(m.mats), m.mat_id, m.orient, src, 2)
+    fin = a > 0
+    assert np.abs(b - a)[fin].max() / 1.0 <= 1e-3 * a[fin].max()
+    assert np.median(np.abs(b - a)[fin] / a[fin]) < 1e-4
+
+
+def test_table3_setup_table_row(orc):
+    n, h, mat = 21, 1e-3, sm.CUBIC_STEEL
+    c = n // 2
+
+    def err(mm, s, levels, half):
+        mid, ori = orc.refine_medium(np.zeros((n, n), np.uint8), np.zeros((n, n)), s)
+        T = orc.solve_refined(h / s, [mm], mid, ori, (c * s, c * s), levels, half)[::s, ::s]
+        e = []
+        for j in range(n):
+            for i in range(n):
+                if i == c and j == c:
+                    continue
+                t = math.hypot(i - c, j - c) * h / orc.qp_group_speed(mat, math.atan2(j - c, i - c) - 0.5 * math.pi)
+                e.append(abs(T[j, i] - t) / t)
+        return 100 * np.mean(e)
+
+    for s in (1, 3, 5):
+        lv = orc.PAPER_LEVELS if s == 1 else ((9, 2 * s), (3, 5 * s))
+        a = err(mat, s, lv, 0.5 * s)
+        b = err(orc.as_table([mat])[0], s, lv, 0.5 * s)
+        print("subgrid %d: run-time %.4f %%, table %.4f %%" % (s, a, b))
+        assert abs(b - a) <= 0.05 * a
+
+
+def test_adjoint_refuses_the_table(orc):
+    m = sm.random_medium(12, 12, 0.2e-3, seed=1)
+    with pytest.raises(ValueError):
+        orc.adjoint(m.h, orc.as_table(m.mats), m.mat_id, m.orient, m.sources[0], np.ones((12, 12)))
