@@ -70,7 +70,17 @@ typedef struct {
                                 ALI_WAVE_SH: the shear wave polarised normal to the plane       */
     int32_t ray_planes;      /* ray tracer plane families: ALI_RAY_CHANGING (default) or a fixed
                                 family / the fastest of the four fixed families (below)         */
+    int32_t velocity;        /* ALI_VEL_CHRISTOFFEL (default) or ALI_VEL_TABLE (below)           */
 } ali_options;
+
+/* Speeds of the solve (Section 3.2).  CHRISTOFFEL: the phase speed of every stencil and the
+   group speed of every straight ray solved at run time.  TABLE: the paper's cheaper
+   variant: per material, the exact phase speeds at whole degrees (0..90) of the angle
+   between the wavefront normal and the symmetry axis and the exact group speeds at whole
+   degrees of the group angle, linearly interpolated (tables built on the device at the
+   start of each call).  Forward solves, nested source grids and rays take either; the
+   adjoint entry points need CHRISTOFFEL (ALI_EUNSUPPORTED otherwise). */
+enum { ALI_VEL_CHRISTOFFEL = 0, ALI_VEL_TABLE = 1 };
 
 /* Plane families of the ray tracer (Section 5.1).  CHANGING: each step uses the family at
    the largest angle to the last segment, candidates around the straight-ahead point, and

@@ -36,6 +36,8 @@ def default_options(**overrides):
         if v is not None:
             if k == "wave" and isinstance(v, str):
                 v = _lib.WAVE[v]
+            if k == "velocity" and isinstance(v, str):
+                v = _lib.VELOCITY[v]
             setattr(o, k, int(v))
     return o
 
@@ -171,7 +173,8 @@ class Solver:
         orient: symmetry-axis angle [rad], float32 (float64 for precision="f64") [nz, nx];
         sources: [(i, j), ...]; arith (float32 output only): "mixed" (float64 times and
         decisions, float32 wavefront math), "f32" or "f64"; extra: other ali_options fields by
-        name (wave="sh" for the shear wave polarised normal to the plane).  Returns (T, stats
+        name (wave="sh" for the shear wave polarised normal to the plane, velocity="table" for
+        the paper's velocity table).  Returns (T, stats
         dict)."""
         import torch
         nz, nx = mat_id.shape
@@ -234,11 +237,12 @@ class Solver:
         return out, stats.as_dict()
 
     def trace_rays(self, h, mats, mat_id, orient, T, sources, receivers, window=None, sub=None,
-                   max_pts=None, wave=None, planes=None):
+                   max_pts=None, wave=None, planes=None, velocity=None):
         """Ray paths from every receiver to every source through the fields T
         [n_src, nz, nx] (float32 or float64 device tensor); wave "qp" (default) or "sh" as
         for the fields; planes "changing" (default), "x", "z", "diag", "anti" (one fixed
-        family) or "fastest" (the fastest of the four fixed families).  Returns (paths [n_src, n_rec, max_pts, 2] float32 grid coordinates,
+        family) or "fastest" (the fastest of the four fixed families); velocity
+        "christoffel" (default) or "table" as for the fields.  Returns (paths [n_src, n_rec, max_pts, 2] float32 grid coordinates,
         npts [n_src, n_rec] int32 (negative: source not reached), tray [n_src, n_rec]
         float32 seconds)."""
         import torch
@@ -247,7 +251,7 @@ class Solver:
         s_arr, ns = _nodes(sources)
         r_arr, nr = _nodes(receivers)
         g = _lib.Grid(int(nx), int(nz), float(h))
-        opt = default_options(ray_window=window, ray_sub=sub, ray_max_pts=max_pts, wave=wave,
+        opt = default_options(ray_window=window, ray_sub=sub, ray_max_pts=max_pts, wave=wave, velocity=velocity,
                               ray_planes=_lib.RAY_PLANES[planes] if planes is not None else None)
         dev = mat_id.device
         paths = torch.empty((ns, nr, opt.ray_max_pts, 2), dtype=torch.float32, device=dev)

@@ -37,7 +37,7 @@ class Options(ctypes.Structure):
                 ("inner_sweeps", ctypes.c_int32), ("band_cells", ctypes.c_int32),
                 ("ray_window", ctypes.c_int32), ("ray_max_pts", ctypes.c_int32),
                 ("arith", ctypes.c_int32), ("ray_sub", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("wave", ctypes.c_int32), ("ray_planes", ctypes.c_int32)]
+                ("wave", ctypes.c_int32), ("ray_planes", ctypes.c_int32), ("velocity", ctypes.c_int32)]
 
 MAX_LEVELS = 8
 
@@ -50,6 +50,7 @@ class Refine(ctypes.Structure):
 ARITH = {"mixed": 0, "f32": 1, "f64": 2}
 WAVE = {"qp": 0, "sh": 1}
 RAY_PLANES = {"changing": 0, "x": 1, "z": 2, "diag": 3, "anti": 4, "fastest": 5}
+VELOCITY = {"christoffel": 0, "table": 1}
 TUNE_CANDIDATES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4), (3, 4)]   # (band_cells, inner_sweeps)
 
 

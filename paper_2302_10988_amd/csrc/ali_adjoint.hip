@@ -692,6 +692,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     if (st != ALI_OK) return st;
     if (d_dA && opt.wave != ALI_WAVE_QP)
         return H->fail(ALI_EUNSUPPORTED, "the stiffness gradient is available for the qP wave only");
+    if (opt.velocity != ALI_VEL_CHRISTOFFEL)
+        return H->fail(ALI_EUNSUPPORTED, "the adjoint differentiates the run-time speeds (velocity table given)");
     if (!d_in) return H->fail(ALI_EINVAL, mode == 1 ? "d_obs is NULL" : "d_dLdT is NULL");
     if (!d_dth) return H->fail(ALI_EINVAL, "d_dLdtheta is NULL");
     int64_t n_fields64 = 0, NF = 0;

@@ -17,6 +17,7 @@ extern "C" void ali_default_options(ali_options* o) {
     o->graph = 1;
     o->wave = ALI_WAVE_QP;
     o->ray_planes = ALI_RAY_CHANGING;
+    o->velocity = ALI_VEL_CHRISTOFFEL;
 }
 
 extern "C" ali_status ali_create(ali_handle** out, int device, void* hip_stream) {

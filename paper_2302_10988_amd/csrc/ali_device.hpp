@@ -88,9 +88,18 @@ template <int S> struct Stencil {
 // mreal: type of the wavefront / phase-speed arithmetic; treal: type of travel times
 // (stored values, scores, every comparison that makes a decision)
 template <typename mreal, typename treal> struct NodeConst {
+    static constexpr bool table = false;
     mreal c2t, s2t;         // cos 2theta, sin 2theta of the symmetry axis
     mreal P, Q, R, K4;      // phase-speed constants / h^2 (K4 = 4 W^2 / h^4)
     treal fb[4];            // straight-ray times to an 8-neighbour along the 4 grid directions
+};
+
+// The velocity-table variant: the phase speed comes from the node material's table of
+// speeds / h at whole degrees (0..90) of the angle between the wavefront normal and the
+// symmetry axis, linearly interpolated.
+template <typename mreal, typename treal> struct NodeConstTab : NodeConst<mreal, treal> {
+    static constexpr bool table = true;
+    const mreal* vt;
 };
 
 // Running best candidate: rank = (class, score, table index), lexicographic.
@@ -110,8 +119,8 @@ __device__ __forceinline__ double dfma(double a, double b, double c) { return __
 // travel time from the wavefront EB to D (|FD| / v) in the math type.  The multiply-adds
 // are explicit fused operations and the build forbids implicit contraction, so every
 // kernel that evaluates an estimate rounds it the same way.
-template <typename real, typename treal>
-__device__ __forceinline__ real stencil_incr(const NodeConst<real, treal>& n, real a, int bx, int bz,
+template <typename real, typename treal, typename NC>
+__device__ __forceinline__ real stencil_incr(const NC& n, real a, int bx, int bz,
                                              int cx, int cz, int k1, int k2) {
     // w = (B - A) - a (C - A)
     const real wx = dfma(-a, real(cx), real(bx));
@@ -121,6 +130,17 @@ __device__ __forceinline__ real stencil_incr(const NodeConst<real, treal>& n, re
     const real dd = dfma(wz, wz, -(wx * wx));        // |w|^2 cos 2phi_n
     const real xz = real(-2) * wx * wz;               // |w|^2 sin 2phi_n
     const real c = dfma(dd, n.c2t, xz * n.s2t);       // |w|^2 cos 2psi
+    if constexpr (NC::table) {
+        // psi in degrees from cos 2psi, then the table (v / h) between whole degrees
+        real cc = c / w2;
+        cc = cc > real(1) ? real(1) : (cc < real(-1) ? real(-1) : cc);
+        const real deg = acos(cc) * real(28.647889756541160848);   // 90 / pi
+        int i = (int)deg;
+        i = i > 89 ? 89 : i;
+        const real fr = deg - real(i);
+        const real v = dfma(fr, n.vt[i + 1] - n.vt[i], n.vt[i]);
+        return __builtin_fabs(cr) * drsqrt(w2 * v * v);
+    }
     const real s2 = dfma(w2, w2, -(c * c));           // (|w|^2 sin 2psi)^2
     const real lin = dfma(n.Q, w2, n.R * c);
     const real G4 = dfma(n.P, w2, dfma(n.Q, c, dsqrt(dfma(lin, lin, n.K4 * s2))));   // 4 G
@@ -137,8 +157,8 @@ __device__ __forceinline__ mreal interp_weight(treal ta, treal tb, treal tc) {
 
 // Candidate of one member: estimate, causality, rank against the best so far.  Every lane
 // runs the same instructions (selects, no branches).
-template <typename mreal, typename real>
-__device__ __forceinline__ void member_candidate(const NodeConst<mreal, real>& n, const int8_t (&g)[6],
+template <typename mreal, typename real, typename NC>
+__device__ __forceinline__ void member_candidate(const NC& n, const int8_t (&g)[6],
                                                  real tA, real tB, real tC, real score, bool ok, int cls,
                                                  int ks, int idx, Best<real>& best, real& minU) {
     best.evals += ok ? 1u : 0u;
@@ -161,8 +181,8 @@ __device__ __forceinline__ void member_candidate(const NodeConst<mreal, real>& n
 // tau_A < tau_B <= tau_C unless tau_P == tau_Q; the admissible member's geometry is picked
 // by selects, so the lanes of a wave run the same instructions.  A tie evaluates member 2
 // as well, after member 1 (table order).
-template <typename mreal, typename real, int PAIR>
-__device__ __forceinline__ void eval_pair(const NodeConst<mreal, real>& n, const real (&t)[12],
+template <typename mreal, typename real, int PAIR, typename NC>
+__device__ __forceinline__ void eval_pair(const NC& n, const real (&t)[12],
                                           Best<real>& best, real& minU) {
     using S1 = Stencil<2 * PAIR>;
     using S2 = Stencil<2 * PAIR + 1>;
@@ -190,14 +210,14 @@ __device__ __forceinline__ void eval_pair(const NodeConst<mreal, real>& n, const
     }
 }
 
-template <typename mreal, typename real, int... P>
-__device__ __forceinline__ void eval_pairs(const NodeConst<mreal, real>& n, const real (&t)[12],
+template <typename mreal, typename real, typename NC, int... P>
+__device__ __forceinline__ void eval_pairs(const NC& n, const real (&t)[12],
                                            Best<real>& best, real& minU, std::integer_sequence<int, P...>) {
     (eval_pair<mreal, real, P>(n, t, best, minU), ...);
 }
 
-template <typename mreal, typename real, int K>
-__device__ __forceinline__ void eval_fallback(const NodeConst<mreal, real>& n, const real (&t)[12],
+template <typename mreal, typename real, int K, typename NC>
+__device__ __forceinline__ void eval_fallback(const NC& n, const real (&t)[12],
                                               Best<real>& best, real& minU) {
     const real tn = t[FB_SLOT[K]];
     const real U = tn + n.fb[FB_DIR[K]];
@@ -213,8 +233,8 @@ __device__ __forceinline__ void eval_fallback(const NodeConst<mreal, real>& n, c
     best.idx = better ? 32 + K : best.idx;
 }
 
-template <typename mreal, typename real, int... K>
-__device__ __forceinline__ void eval_fallbacks(const NodeConst<mreal, real>& n, const real (&t)[12],
+template <typename mreal, typename real, typename NC, int... K>
+__device__ __forceinline__ void eval_fallbacks(const NC& n, const real (&t)[12],
                                                Best<real>& best, real& minU,
                                                std::integer_sequence<int, K...>) {
     (eval_fallback<mreal, real, K>(n, t, best, minU), ...);
@@ -263,8 +283,8 @@ __device__ __forceinline__ void act_member(int ks, int cls, int idx, real score,
     }
 }
 
-template <typename mreal, typename real, int PAIR>
-__device__ __forceinline__ void act_pair(const NodeConst<mreal, real>& n, const real (&t)[12], ActBest<real>& ab) {
+template <typename mreal, typename real, int PAIR, typename NC>
+__device__ __forceinline__ void act_pair(const NC& n, const real (&t)[12], ActBest<real>& ab) {
     using S1 = Stencil<2 * PAIR>;
     using S2 = Stencil<2 * PAIR + 1>;
     const real inf = dinf<real>();
@@ -290,8 +310,8 @@ __device__ __forceinline__ void act_pair(const NodeConst<mreal, real>& n, const 
     }
 }
 
-template <typename mreal, typename real, int... P>
-__device__ __forceinline__ void act_pairs(const NodeConst<mreal, real>& n, const real (&t)[12], ActBest<real>& ab,
+template <typename mreal, typename real, typename NC, int... P>
+__device__ __forceinline__ void act_pairs(const NC& n, const real (&t)[12], ActBest<real>& ab,
                                           std::integer_sequence<int, P...>) {
     (act_pair<mreal, real, P>(n, t, ab), ...);
 }
@@ -305,8 +325,8 @@ template <typename T> __device__ __forceinline__ T pick8(const T (&v)[8], int q)
     }
 }
 
-template <typename mreal, typename real>
-__device__ __noinline__ real slow_update(const NodeConst<mreal, real> n, const real* __restrict__ lds,
+template <typename mreal, typename real, typename NC>
+__device__ __noinline__ real slow_update(const NC n, const real* __restrict__ lds,
                                          int me, int stride, int* choice) {
     const real inf = dinf<real>();
     real t[12];
@@ -369,8 +389,8 @@ __device__ __noinline__ real slow_update(const NodeConst<mreal, real> n, const r
 // reads them again from lds.
 // choice (nullable) receives the chosen candidate: table index 0..31, 32 + k for a
 // straight ray from the k-th 8-neighbour, -1 for none.
-template <typename mreal, typename real>
-__device__ __forceinline__ real local_update(const NodeConst<mreal, real>& n, const real (&t)[12],
+template <typename mreal, typename real, typename NC>
+__device__ __forceinline__ real local_update(const NC& n, const real (&t)[12],
                                              const real* __restrict__ lds, int me, int stride,
                                              unsigned& evals, int* choice = nullptr) {
     const real inf = dinf<real>();

@@ -29,12 +29,13 @@ namespace ali {
 constexpr int GT_N = 2048;                 // table intervals over [0, pi/2]
 constexpr double HALF_PI = 1.57079632679489661923;
 
-__global__ void k_gtable(const MatA* __restrict__ mats, int n_mats, float* __restrict__ tab) {
+__global__ void k_gtable(const MatA* __restrict__ mats, const double* __restrict__ gt, int n_mats,
+                         float* __restrict__ tab) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int m = blockIdx.y;
     if (q > GT_N || m >= n_mats) return;
     const double phi = HALF_PI * (double)q / GT_N;
-    tab[(int64_t)m * (GT_N + 1) + q] = (float)(1.0 / group_speed(mats[m], phi));
+    tab[(int64_t)m * (GT_N + 1) + q] = (float)(1.0 / (gt ? group_speed_tab(gt + m * VT_N, phi) : group_speed(mats[m], phi)));
 }
 
 struct RayMedium {
@@ -414,6 +415,8 @@ static ali_status trace_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     if (opt.ray_max_pts < 2) return H->fail(ALI_EINVAL, "ray_max_pts must be >= 2");
     if (opt.ray_planes < ALI_RAY_CHANGING || opt.ray_planes > ALI_RAY_FASTEST_FIXED)
         return H->fail(ALI_EINVAL, "unknown ray_planes");
+    if (opt.velocity != ALI_VEL_CHRISTOFFEL && opt.velocity != ALI_VEL_TABLE)
+        return H->fail(ALI_EINVAL, "unknown velocity mode");
     if ((int64_t)n_src * n_recv > (int64_t)1 << 30) return H->fail(ALI_EINVAL, "too many rays");
     if (set_device(H) != ALI_OK) return ALI_EDEVICE;
     hipStream_t S = H->stream;
@@ -434,8 +437,15 @@ static ali_status trace_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     HIPCK(H, hipMemcpyAsync(d_ma, hm.data(), sizeof(MatA) * n_mats, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemcpyAsync(d_src, hs.data(), sizeof(int2) * n_src, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemcpyAsync(d_rec, hr.data(), sizeof(int2) * n_recv, hipMemcpyHostToDevice, S));
+    void* d_gt = nullptr;
+    if (opt.velocity == ALI_VEL_TABLE) {
+        if (!H->scratch("ray_gt", sizeof(double) * VT_N * n_mats, &d_gt))
+            return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+        hipLaunchKernelGGL((k_vtables<double>), dim3((unsigned)n_mats), dim3(128), 0, S, (const MatA*)d_ma,
+                           (const double*)nullptr, n_mats, (double*)nullptr, (double*)d_gt);
+    }
     hipLaunchKernelGGL(k_gtable, dim3((GT_N + 1 + 255) / 256, (unsigned)n_mats), dim3(256), 0, S,
-                       (const MatA*)d_ma, n_mats, (float*)d_tab);
+                       (const MatA*)d_ma, (const double*)d_gt, n_mats, (float*)d_tab);
     HIPCK(H, hipGetLastError());
     RayMedium M{grid->nx, grid->nz, grid->h, d_mat_id, d_orient, (const float*)d_tab};
     const int n_rays = n_src * n_recv;

@@ -76,7 +76,8 @@ __device__ __forceinline__ void set_fixed(uint32_t* __restrict__ fixmask, const 
 // finest level: straight rays from the source inside |a|, |b| < half * d, +inf elsewhere
 template <typename real, typename oreal>
 __global__ void k_seed_start(const LevelDev* __restrict__ lv, int nx_w, double h_w, double half,
-                             const MatA* __restrict__ A, int n_mats, const uint8_t* __restrict__ mat_w,
+                             const MatA* __restrict__ A, const double* __restrict__ gt, int n_mats,
+                             const uint8_t* __restrict__ mat_w,
                              const oreal* __restrict__ ori_w, real* __restrict__ T, uint32_t* __restrict__ fixmask) {
     const LevelDev L = lv[blockIdx.y];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -92,7 +93,8 @@ __global__ void k_seed_start(const LevelDev* __restrict__ lv, int nx_w, double h
             const double phi = atan2((double)b, (double)a) - (double)ori_w[ps];
             // an id outside the table is reported by the solve's own check; read a valid entry
             const int mid = mat_w[ps] < n_mats ? mat_w[ps] : 0;
-            t = sqrt((double)a * a + (double)b * b) * (h_w / L.d) / group_speed(A[mid], phi);
+            const double V = gt ? group_speed_tab(gt + mid * VT_N, phi) : group_speed(A[mid], phi);
+            t = sqrt((double)a * a + (double)b * b) * (h_w / L.d) / V;
         }
         v = (real)t;
         set_fixed(fixmask, L, i, j);
@@ -237,6 +239,14 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     if (!H->scratch("ref_A", sizeof(MatA) * n_mats, &d_A) || !H->scratch("ref_stop", sizeof(real) * n_src, &d_stop))
         return H->fail(ALI_ENOMEM, "device scratch allocation failed");
     HIPCK(H, hipMemcpyAsync(d_A, hA.data(), sizeof(MatA) * n_mats, hipMemcpyHostToDevice, S));
+    // velocity-table mode: the straight rays take the group-speed table
+    void* d_gt = nullptr;
+    if (opt.velocity == ALI_VEL_TABLE) {
+        if (!H->scratch("ref_gt", sizeof(double) * VT_N * n_mats, &d_gt))
+            return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+        hipLaunchKernelGGL((k_vtables<double>), dim3((unsigned)n_mats), dim3(128), 0, S, (const MatA*)d_A,
+                           (const double*)nullptr, n_mats, (double*)nullptr, (double*)d_gt);
+    }
 
     ali_solve_stats acc{};
     acc.converged = 1;
@@ -304,7 +314,8 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
         }
         if (l == 0)
             hipLaunchKernelGGL((k_seed_start<real, oreal>), g2, dim3(B), 0, S, (const LevelDev*)d_lv, grid->nx,
-                               grid->h, ref.start_half_width, (const MatA*)d_A, n_mats, d_mat_id, d_orient, T,
+                               grid->h, ref.start_half_width, (const MatA*)d_A, (const double*)d_gt, n_mats,
+                               d_mat_id, d_orient, T,
                                (uint32_t*)d_fm);
         else
             hipLaunchKernelGGL((k_seed_transfer<real>), g2, dim3(B), 0, S, dprev, Tprev, (const real*)d_stop,

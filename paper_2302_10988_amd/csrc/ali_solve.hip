@@ -47,9 +47,12 @@ struct PrepDev {
 };
 
 template <typename mreal, typename treal, typename oreal>
+// gt_all (velocity-table mode, else NULL): group-speed tables of the device materials; the
+// node's table offset goes to geo slot 6 and the straight-ray times come from the table.
 __global__ void k_prep(const PrepDev* __restrict__ media, int m0, const MatDev<mreal>* __restrict__ mats_all,
                        const uint8_t* __restrict__ mat_id_all, const oreal* __restrict__ orient_all,
-                       mreal* __restrict__ geo_all, treal* __restrict__ fbt_all, int* __restrict__ err) {
+                       mreal* __restrict__ geo_all, treal* __restrict__ fbt_all, const double* __restrict__ gt_all,
+                       int* __restrict__ err) {
     const PrepDev md = media[m0 + blockIdx.y];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= (int64_t)md.nx * md.nz) return;
@@ -73,20 +76,23 @@ __global__ void k_prep(const PrepDev* __restrict__ media, int m0, const MatDev<m
     g[3] = mats[mid].Q;
     g[4] = mats[mid].R;
     g[5] = mats[mid].K4;
-    g[6] = mreal(0);
+    g[6] = gt_all ? (mreal)((md.mat_off + mid) * VT_N) : mreal(0);
     g[7] = mreal(0);
     // straight-ray time to an 8-neighbour along x, (1,1), z, (1,-1)
     const double quarter = 0.78539816339744830962;
     const double len[4] = {1.0, 1.41421356237309504880, 1.0, 1.41421356237309504880};
     const double ang[4] = {0.0, quarter, 2.0 * quarter, -quarter};
 #pragma unroll
-    for (int d = 0; d < 4; ++d) fbt[4 * p + d] = (treal)(len[d] * h / group_speed(m, ang[d] - th));
+    for (int d = 0; d < 4; ++d)
+        fbt[4 * p + d] = (treal)(len[d] * h / (gt_all ? group_speed_tab(gt_all + (md.mat_off + mid) * VT_N, ang[d] - th)
+                                                      : group_speed(m, ang[d] - th)));
 }
 
 // initial values of the fields f0 .. f0 + gridDim.y - 1 (all in one medium)
 template <typename real, typename mreal, typename oreal>
 __global__ void k_init(const FieldDev* __restrict__ fields, int f0, double h, const MatDev<mreal>* __restrict__ mats,
-                       int n_mats, const uint8_t* __restrict__ mat_id, const oreal* __restrict__ orient, int R,
+                       const double* __restrict__ gt, int n_mats, const uint8_t* __restrict__ mat_id,
+                       const oreal* __restrict__ orient, int R,
                        real* __restrict__ T, uint32_t* __restrict__ flags) {
     const FieldDev fd = fields[f0 + blockIdx.y];
     const int nx = fd.nx;
@@ -106,7 +112,8 @@ __global__ void k_init(const FieldDev* __restrict__ fields, int f0, double h, co
             const double phi = atan2((double)dj, (double)di) - (double)orient[ps];
             // an id outside the table is reported by k_prep; read a valid entry meanwhile
             const int mid = mat_id[ps] < n_mats ? mat_id[ps] : 0;
-            v = (real)(sqrt((double)(di * di + dj * dj)) * h / group_speed(mats[mid].A, phi));
+            const double V = gt ? group_speed_tab(gt + mid * VT_N, phi) : group_speed(mats[mid].A, phi);
+            v = (real)(sqrt((double)(di * di + dj * dj)) * h / V);
         }
     }
     T[fd.t_off + p] = v;
@@ -167,14 +174,16 @@ __device__ __forceinline__ void lds_min(double* p, double v) {
 // pass.  Each sweep packs the marked nodes into the first lanes.
 // SEEDED: the fixed nodes are the set bits of fixmask (one bit per node of each tile unit,
 // NODE_WORDS words per unit) instead of the source box of radius R.
-template <typename real, typename mreal, bool SEEDED>
+// TAB: phase speeds from the per-material tables vtab (offset in geo slot 6).
+template <typename real, typename mreal, bool SEEDED, bool TAB>
 __global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
 k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, const real* __restrict__ fbt_all,
         int R, int inner, const real* __restrict__ theta,
         real* __restrict__ T, uint32_t* __restrict__ flags, real* __restrict__ minrej,
         uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
         const uint32_t* __restrict__ count, uint32_t* __restrict__ idle,
-        unsigned long long* __restrict__ counters, const uint32_t* __restrict__ fixmask) {
+        unsigned long long* __restrict__ counters, const uint32_t* __restrict__ fixmask,
+        const mreal* __restrict__ vtab) {
     __shared__ real lt[LH * LSTRIDE];
     __shared__ uint8_t dnext[NTHREADS];
     __shared__ uint16_t clist[NTHREADS];
@@ -290,8 +299,10 @@ k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, co
                 const int nlx = node % TX, nlz = node / TX;
                 const int nme = (nlz + HALO) * LSTRIDE + (nlx + HALO);
                 const int64_t p = (int64_t)(j0 + nlz) * nx + (i0 + nlx);
-                NodeConst<mreal, real> nc;
+                using NC = typename std::conditional<TAB, NodeConstTab<mreal, real>, NodeConst<mreal, real>>::type;
+                NC nc;
                 load_node_const<real, mreal>(nc, p, geo, fbt);
+                if constexpr (TAB) nc.vt = vtab + (int)geo[GEO_N * p + 6];
                 real t[12];
 #pragma unroll
                 for (int k = 0; k < 12; ++k) t[k] = lt[nme + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]];
@@ -465,6 +476,8 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     if (opt.max_sweeps < 1) return H->fail(ALI_EINVAL, "max_sweeps must be >= 1");
     if (opt.inner_sweeps < 1 || opt.inner_sweeps > 4096) return H->fail(ALI_EINVAL, "inner_sweeps out of range [1, 4096]");
     if (opt.band_cells < 0) return H->fail(ALI_EINVAL, "band_cells must be >= 0 (0 = no band)");
+    if (opt.velocity != ALI_VEL_CHRISTOFFEL && opt.velocity != ALI_VEL_TABLE)
+        return H->fail(ALI_EINVAL, "unknown velocity mode");
     if (set_device(H) != ALI_OK) return ALI_EDEVICE;
     hipStream_t S = H->stream;
 
@@ -555,6 +568,28 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     const int B = 256;
     hipLaunchKernelGGL((k_fill<real>), dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
                        (real*)d_minrej, nunits, dinf_host<real>());
+    // velocity-table mode: per device material, phase speed / h and group speed at whole
+    // degrees (built on the device from the run-time speeds)
+    const bool tab = opt.velocity == ALI_VEL_TABLE;
+    void *d_vt = nullptr, *d_gt = nullptr;
+    std::vector<MatA> hA;
+    std::vector<double> hih;
+    if (tab) {
+        for (int m = 0; m < n_media; ++m)
+            for (int k = 0; k < media[m].n_mats; ++k) {
+                hA.push_back(hm[dev_mat_off[m] + k].A);
+                hih.push_back(1.0 / media[m].grid.h);
+            }
+        void *d_A = nullptr, *d_ih = nullptr;
+        const size_t nd = hA.size();
+        if (!H->scratch("vt_A", sizeof(MatA) * nd, &d_A) || !H->scratch("vt_ih", sizeof(double) * nd, &d_ih) ||
+            !H->scratch("vt", sizeof(mreal) * VT_N * nd, &d_vt) || !H->scratch("gt", sizeof(double) * VT_N * nd, &d_gt))
+            return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+        HIPCK(H, hipMemcpyAsync(d_A, hA.data(), sizeof(MatA) * nd, hipMemcpyHostToDevice, S));
+        HIPCK(H, hipMemcpyAsync(d_ih, hih.data(), sizeof(double) * nd, hipMemcpyHostToDevice, S));
+        hipLaunchKernelGGL((k_vtables<mreal>), dim3((unsigned)nd), dim3(128), 0, S, (const MatA*)d_A,
+                           (const double*)d_ih, (int)nd, (mreal*)d_vt, (double*)d_gt);
+    }
     // per-node constants of every medium: one launch per 65535 media
     std::vector<PrepDev> hp(n_media);
     int64_t max_nodes = 0;
@@ -571,7 +606,7 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
         const int nm = std::min(n_media - m0, 65535);
         hipLaunchKernelGGL((k_prep<mreal, real, oreal>), dim3((unsigned)((max_nodes + B - 1) / B), (unsigned)nm),
                            dim3(B), 0, S, (const PrepDev*)d_prep, m0, (const MatDev<mreal>*)d_mats, d_mat_id,
-                           d_orient, (mreal*)d_geo, (real*)d_fbt, (int*)d_err);
+                           d_orient, (mreal*)d_geo, (real*)d_fbt, (const double*)d_gt, (int*)d_err);
     }
     for (int m = 0; m < n_media; ++m) {
         const ali_medium& md = media[m];
@@ -579,7 +614,9 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
         if (!d_fixmask)
             hipLaunchKernelGGL((k_init<real, mreal, oreal>), dim3((unsigned)((N + B - 1) / B), (unsigned)md.n_src),
                                dim3(B), 0, S, (const FieldDev*)d_fields, F.medium_first_field[m], md.grid.h,
-                               (const MatDev<mreal>*)d_mats + dev_mat_off[m], md.n_mats, d_mat_id + md.node_offset,
+                               (const MatDev<mreal>*)d_mats + dev_mat_off[m],
+                               tab ? (const double*)d_gt + (size_t)VT_N * dev_mat_off[m] : (const double*)nullptr,
+                               md.n_mats, d_mat_id + md.node_offset,
                                d_orient + md.node_offset, opt.src_box_radius, d_T, (uint32_t*)d_flags);
     }
     if (d_fixmask)
@@ -612,17 +649,31 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
         uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
         uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);
-        if (d_fixmask)
-            hipLaunchKernelGGL((k_relax<real, mreal, true>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
-                               (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, -1,
+        const int R = d_fixmask ? -1 : opt.src_box_radius;
+        const mreal* vt = (const mreal*)d_vt;
+        if (d_fixmask && tab)
+            hipLaunchKernelGGL((k_relax<real, mreal, true, true>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
+                               (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, R,
                                opt.inner_sweeps, (const real*)d_theta, d_T, (uint32_t*)d_flags, (real*)d_minrej,
                                mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
-                               (unsigned long long*)d_upd, d_fixmask);
+                               (unsigned long long*)d_upd, d_fixmask, vt);
+        else if (d_fixmask)
+            hipLaunchKernelGGL((k_relax<real, mreal, true, false>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
+                               (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, R,
+                               opt.inner_sweeps, (const real*)d_theta, d_T, (uint32_t*)d_flags, (real*)d_minrej,
+                               mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
+                               (unsigned long long*)d_upd, d_fixmask, vt);
+        else if (tab)
+            hipLaunchKernelGGL((k_relax<real, mreal, false, true>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
+                               (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, R,
+                               opt.inner_sweeps, (const real*)d_theta, d_T, (uint32_t*)d_flags, (real*)d_minrej,
+                               mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
+                               (unsigned long long*)d_upd, d_fixmask, vt);
         else
-            hipLaunchKernelGGL((k_relax<real, mreal, false>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
-                               (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, opt.src_box_radius, opt.inner_sweeps, (const real*)d_theta, d_T,
+            hipLaunchKernelGGL((k_relax<real, mreal, false, false>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
+                               (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, R, opt.inner_sweeps, (const real*)d_theta, d_T,
                                (uint32_t*)d_flags, (real*)d_minrej, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)),
-                               (uint32_t*)d_idle, (unsigned long long*)d_upd, (const uint32_t*)nullptr);
+                               (uint32_t*)d_idle, (unsigned long long*)d_upd, d_fixmask, vt);
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH) + 1], S);
     };
     while (iters < opt.max_sweeps) {
@@ -631,13 +682,15 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
         if (graph) {
             // the first batch differs from the others only in the first pass (no advance)
             const int first = iters == 0 ? 1 : 0;
-            const void* kern = d_fixmask ? (const void*)&k_relax<real, mreal, true>
-                                         : (const void*)&k_relax<real, mreal, false>;
+            const void* kern = d_fixmask ? (tab ? (const void*)&k_relax<real, mreal, true, true>
+                                                : (const void*)&k_relax<real, mreal, true, false>)
+                                         : (tab ? (const void*)&k_relax<real, mreal, false, true>
+                                                : (const void*)&k_relax<real, mreal, false, false>);
             const std::string key = graph_key("relax", first, kern, d_fields, n_fields,
                                               d_flags, d_minrej, d_theta, d_step, d_list, d_count,
                                               d_marks, nunits, d_geo, d_fbt, opt.src_box_radius,
                                               opt.inner_sweeps, d_T, d_idle, d_upd, grid_relax,
-                                              (const void*)d_fixmask);
+                                              (const void*)d_fixmask, d_vt);
             HIPCK(H, hipEventRecord(H->ev2, S));
             st = launch_captured(H, key, [&](int b, hipStream_t cs) { enqueue(first ? b : PASS_BATCH + b, false, cs); });
             if (st != ALI_OK) return st;

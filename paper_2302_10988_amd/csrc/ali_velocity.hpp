@@ -116,4 +116,37 @@ __device__ inline double group_speed_dA(const MatA& m, double phi, double d[4]) 
     return spd;
 }
 
+// ---------------------------------------------------------------------------------------
+// Velocity-table mode (the paper's cheaper variant): speeds at whole degrees of the angle
+// from the symmetry axis, 0..90 (the curves are even and pi-periodic), linearly
+// interpolated.  VT_N entries per material.
+// ---------------------------------------------------------------------------------------
+constexpr int VT_N = 91;
+
+// group speed from the table gt[0..90] (group speed at whole degrees of the group angle)
+__device__ inline double group_speed_tab(const double* __restrict__ gt, double phi) {
+    const double pi = 3.14159265358979323846;
+    double a = fmod(fabs(phi), pi);
+    if (a > 0.5 * pi) a = pi - a;
+    const double deg = a * (180.0 / pi);
+    int i = (int)deg;
+    i = i > 89 ? 89 : i;
+    const double w = deg - i;
+    return w == 0.0 ? gt[i] : (1.0 - w) * gt[i] + w * gt[i + 1];
+}
+
+// tables of one material: phase speed / h (vt) and group speed (gt) at whole degrees
+template <typename mreal>
+__global__ void k_vtables(const MatA* __restrict__ A, const double* __restrict__ ih, int n, mreal* __restrict__ vt,
+                          double* __restrict__ gt) {
+    const int m = blockIdx.x;
+    const int k = threadIdx.x;
+    if (m >= n || k >= VT_N) return;
+    const double ang = k * (3.14159265358979323846 / 180.0);
+    double F, dF;
+    phase_F(A[m], ang, F, dF);
+    if (vt) vt[m * VT_N + k] = (mreal)(sqrt(F) * ih[m]);
+    if (gt) gt[m * VT_N + k] = group_speed(A[m], ang);
+}
+
 }  // namespace ali

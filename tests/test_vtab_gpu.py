@@ -1,0 +1,113 @@
+"""Velocity-table mode (ali_options.velocity = ALI_VEL_TABLE) on the GPU, through the C ABI,
+against the oracle's table mode.
+
+The GPU builds the tables on the device (phase speed / h and group speed at whole degrees
+from its own closed form and group-angle inversion) and finds each stencil's angle from
+cos 2psi with acos; the oracle interpolates its Christoffel-root speeds at whole degrees of
+its geometric angle.  Bars as for the run-time speeds: float64 fields within 1e-12 (also
+with the nested source grids and for SH), mixed within 1e-4, rays within 1e-4 in time and
+0.05 cells in path; the adjoint refuses the table.
+"""
+import numpy as np
+import pytest
+
+import synthmedia as sm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+    from paper_2302_10988_amd import Solver
+    assert torch.cuda.is_available()
+    return Solver(0)
+
+
+def _dev(m, dtype):
+    import torch
+    return torch.from_numpy(m.mat_id).cuda(), torch.from_numpy(np.ascontiguousarray(m.orient)).to(dtype).cuda()
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    assert np.array_equal(np.isfinite(a), np.isfinite(b))
+    fin = np.isfinite(b) & (b > 0)
+    return float((np.abs(a - b)[fin] / b[fin]).max())
+
+
+def _poly_dist(points, poly):
+    a, b = poly[:-1], poly[1:]
+    ab = b - a
+    L2 = np.maximum((ab ** 2).sum(1), 1e-30)
+    out = []
+    for p in points:
+        t = np.clip(((p - a) * ab).sum(1) / L2, 0, 1)
+        q = a + t[:, None] * ab
+        out.append(np.sqrt(((q - p) ** 2).sum(1)).min())
+    return np.array(out)
+
+
+@pytest.mark.parametrize("seed,wave", [(3, "qp"), (8, "qp"), (5, "sh")])
+def test_table_forward_vs_oracle(solver, orc, seed, wave):
+    import torch
+    m = sm.random_medium(45, 39, 0.2e-3, seed=seed, n_mats=3)
+    mats_or = orc.as_table(orc.as_sh(m.mats) if wave == "sh" else m.mats)
+    sources = [m.sources[0], (0, 0), (44, 38)]
+    mid, ori64 = _dev(m, torch.float64)
+    print("table forward: seed %d wave %s" % (seed, wave), flush=True)
+    T64, st = solver.solve(m.h, m.mats, mid, ori64, sources, precision="f64", velocity="table", wave=wave)
+    assert st["converged"] == 1
+    T32, _ = solver.solve(m.h, m.mats, mid, ori64.float(), sources, velocity="table", wave=wave)
+    R64, _ = solver.solve_refined(m.h, m.mats, mid, ori64, sources, precision="f64", velocity="table", wave=wave)
+    Tx, _ = solver.solve(m.h, m.mats, mid, ori64, sources, precision="f64", wave=wave)
+    for k, src in enumerate(sources):
+        ref = orc.solve_fmm(m.h, mats_or, m.mat_id, m.orient, src, 2)
+        refr = orc.solve_refined(m.h, mats_or, m.mat_id, m.orient, src)
+        e64, e32, er = _rel(T64[k].cpu().numpy(), ref), _rel(T32[k].cpu().numpy(), ref), _rel(R64[k].cpu().numpy(), refr)
+        print("  source %s: f64 %.3g, mixed %.3g, refined f64 %.3g" % (src, e64, e32, er), flush=True)
+        assert e64 <= 1e-12 and e32 <= 1e-4 and er <= 1e-12
+    # the table differs from the run-time speeds, by the interpolation error only
+    d = _rel(T64.cpu().numpy(), Tx.cpu().numpy())
+    print("  table vs run-time speeds: %.3g" % d, flush=True)
+    assert (0.0 < d < 1e-3) if wave == "qp" else (d < 1e-3)
+
+
+def test_table_rays_and_table3_setup(solver, orc):
+    import torch
+    # rays through a table-mode field
+    m = sm.weld(n=96, h=0.4e-3, seed=0)
+    mats_or = orc.as_table(m.mats)
+    sources = [(20, 0), (70, 0)]
+    receivers = [(90, 95), (5, 95), (50, 60)]
+    mid, ori = _dev(m, torch.float32)
+    T, _ = solver.solve(m.h, m.mats, mid, ori, sources, velocity="table")
+    paths, npts, tray = [x.cpu().numpy() for x in solver.trace_rays(m.h, m.mats, mid, ori, T, sources, receivers,
+                                                                    velocity="table")]
+    for a, s in enumerate(sources):
+        Tref = orc.solve_fmm(m.h, mats_or, m.mat_id, m.orient, s, 2)
+        for b, r in enumerate(receivers):
+            pts, t, ok = orc.trace_ray(m.h, mats_or, m.mat_id, m.orient, Tref, s, r)
+            assert ok and npts[a, b] > 0
+            gp = paths[a, b, : npts[a, b]].astype(np.float64)
+            dt, dp = abs(tray[a, b] - t) / t, _poly_dist(gp, pts).max()
+            print("  ray %s -> %s: time %.3g, path %.3g" % (r, s, dt, dp), flush=True)
+            assert dt <= 1e-4 and dp <= 0.05
+    # Table 3's set-up (subgrid 1): the table row
+    n, h, mat = 21, 1e-3, sm.CUBIC_STEEL
+    zi, zo = np.zeros((n, n), np.uint8), np.zeros((n, n))
+    src = (n // 2, n // 2)
+    Tt, _ = solver.solve_refined(h, [mat], torch.from_numpy(zi).cuda(), torch.from_numpy(zo).cuda(), [src],
+                                 precision="f64", velocity="table")
+    ref = orc.solve_refined(h, orc.as_table([mat]), zi, zo, src)
+    assert _rel(Tt[0].cpu().numpy(), ref) <= 1e-12
+
+
+def test_adjoint_refuses_the_table(solver):
+    import torch
+    from paper_2302_10988_amd import AliError
+    m = sm.random_medium(20, 20, 0.2e-3, seed=1)
+    mid, ori = _dev(m, torch.float32)
+    g = torch.ones((1, 1), device="cuda")
+    with pytest.raises(AliError):
+        solver.adjoint(m.h, m.mats, mid, ori, m.sources, [(19, 19)], g, velocity="table")
