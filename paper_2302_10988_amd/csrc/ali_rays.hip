@@ -160,7 +160,8 @@ __device__ __forceinline__ double field_at(const treal* __restrict__ T, int nx, 
 constexpr int RAYS_PER_GROUP = 4;
 constexpr int RAY_LDS_MATS = 4;
 
-template <typename treal, bool LDS_TAB>
+// FIXED: one plane family (family 0..3) for the whole ray; otherwise the changing family.
+template <typename treal, bool LDS_TAB, bool FIXED>
 __global__ void __launch_bounds__(RAYS_PER_GROUP * 64)
 k_trace(RayMedium M, int n_mats, int n_rays, const treal* __restrict__ Tall, const int2* __restrict__ srcs,
         const int2* __restrict__ recv, int n_recv, int window, int sub, int max_pts, int family,
@@ -205,7 +206,7 @@ k_trace(RayMedium M, int n_mats, int n_rays, const treal* __restrict__ Tall, con
     // table slowness (interpolation stays between two entries; the margin covers rounding)
     int kS = 0, k0 = 0, fsgn = 1;
     double minsl = 0.0;
-    if (family >= 0) {
+    if constexpr (FIXED) {
         float ms = INFINITY;
         for (int i = lane; i < n_mats * (GT_N + 1); i += 64) ms = fminf(ms, tab[i]);
         for (int off = 32; off > 0; off >>= 1) ms = fminf(ms, __shfl_xor(ms, off));
@@ -218,7 +219,7 @@ k_trace(RayMedium M, int n_mats, int n_rays, const treal* __restrict__ Tall, con
     }
     for (int guard = 0; guard < max_pts; ++guard) {
         int f, kk, m0;
-        if (family < 0) {
+        if constexpr (!FIXED) {
             if (hypot(px - S.x, pz - S.y) < 1.6) {
                 if (px != S.x || pz != S.y) {
                     keep(px, pz, (double)S.x, (double)S.y);
@@ -451,14 +452,15 @@ static ali_status trace_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     const int n_rays = n_src * n_recv;
     const unsigned groups = (unsigned)((n_rays + RAYS_PER_GROUP - 1) / RAYS_PER_GROUP);
     auto launch = [&](int family, float2* pth, int32_t* np, float* tr) {
-        if (n_mats <= RAY_LDS_MATS)
-            hipLaunchKernelGGL((k_trace<treal, true>), dim3(groups), dim3(RAYS_PER_GROUP * 64), 0, S, M, n_mats, n_rays,
-                               d_T, (const int2*)d_src, (const int2*)d_rec, n_recv, opt.ray_window, opt.ray_sub,
-                               opt.ray_max_pts, family, pth, np, tr);
-        else
-            hipLaunchKernelGGL((k_trace<treal, false>), dim3(groups), dim3(RAYS_PER_GROUP * 64), 0, S, M, n_mats,
-                               n_rays, d_T, (const int2*)d_src, (const int2*)d_rec, n_recv, opt.ray_window,
-                               opt.ray_sub, opt.ray_max_pts, family, pth, np, tr);
+        const bool lds = n_mats <= RAY_LDS_MATS;
+        const dim3 g(groups), b(RAYS_PER_GROUP * 64);
+#define ALI_TRACE_ARGS M, n_mats, n_rays, d_T, (const int2*)d_src, (const int2*)d_rec, n_recv, opt.ray_window, \
+                       opt.ray_sub, opt.ray_max_pts, family, pth, np, tr
+        if (family < 0 && lds) hipLaunchKernelGGL((k_trace<treal, true, false>), g, b, 0, S, ALI_TRACE_ARGS);
+        else if (family < 0) hipLaunchKernelGGL((k_trace<treal, false, false>), g, b, 0, S, ALI_TRACE_ARGS);
+        else if (lds) hipLaunchKernelGGL((k_trace<treal, true, true>), g, b, 0, S, ALI_TRACE_ARGS);
+        else hipLaunchKernelGGL((k_trace<treal, false, true>), g, b, 0, S, ALI_TRACE_ARGS);
+#undef ALI_TRACE_ARGS
     };
     if (opt.ray_planes == ALI_RAY_FASTEST_FIXED) {
         void *d_p4, *d_n4, *d_t4;
