@@ -346,6 +346,20 @@ ali_status ali_misfit_gradient_f64(ali_handle* h, const ali_grid* grid, const al
                                    const double* d_obs, const ali_options* opt, double* d_T, double* d_Trec,
                                    double* d_loss, double* d_dLdtheta, ali_adjoint_stats* stats);
 
+/* ali_misfit_gradient plus dL/dA [nz][nx][4] of every node's stiffness (as
+   ali_adjoint_stiffness; NULL is an error). */
+ali_status ali_misfit_gradient_stiffness(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                         int32_t n_mats, const uint8_t* d_mat_id, const float* d_orient,
+                                         const ali_node* srcs, int32_t n_src, const ali_node* recv, int32_t n_recv,
+                                         const float* d_obs, const ali_options* opt, float* d_T, float* d_Trec,
+                                         double* d_loss, float* d_dLdtheta, float* d_dLdA, ali_adjoint_stats* stats);
+ali_status ali_misfit_gradient_stiffness_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                             int32_t n_mats, const uint8_t* d_mat_id, const double* d_orient,
+                                             const ali_node* srcs, int32_t n_src, const ali_node* recv,
+                                             int32_t n_recv, const double* d_obs, const ali_options* opt,
+                                             double* d_T, double* d_Trec, double* d_loss, double* d_dLdtheta,
+                                             double* d_dLdA, ali_adjoint_stats* stats);
+
 /* Forward + adjoint of the travel-time misfit for many media in one call (the batched
    tomography step): for each medium m, L_m = 1/2 sum over its sources s and receivers r of
    (T_s(r) - obs)^2.
@@ -361,6 +375,14 @@ ali_status ali_misfit_gradient_batch(ali_handle* h, const ali_medium* media, int
                                      const float* d_orient, const ali_node* srcs, const ali_node* recv,
                                      const float* d_obs, const ali_options* opt, float* d_Trec,
                                      double* d_loss, float* d_dLdtheta, ali_adjoint_stats* stats);
+/* The same plus dL_m/dA of every node's stiffness, 4 values per node laid out as d_orient
+   (as ali_adjoint_stiffness; NULL is an error). */
+ali_status ali_misfit_gradient_batch_stiffness(ali_handle* h, const ali_medium* media, int32_t n_media,
+                                               const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
+                                               const float* d_orient, const ali_node* srcs, const ali_node* recv,
+                                               const float* d_obs, const ali_options* opt, float* d_Trec,
+                                               double* d_loss, float* d_dLdtheta, float* d_dLdA,
+                                               ali_adjoint_stats* stats);
 
 /* Orientation from an ncz x ncx grid of control values spanning the grid corner to corner
    (node k sits at control coordinate k (nc-1)/(n-1); linear in each direction), and its

@@ -313,9 +313,10 @@ class Solver:
 
     def misfit_gradient(self, h, mats, mat_id, orient, sources, receivers, obs, precision="f32",
                         T_out=None, src_box_radius=None, max_sweeps=None, inner_sweeps=None,
-                        band_cells=None, arith="mixed", **extra):
+                        band_cells=None, arith="mixed", stiffness=False, **extra):
         """Forward + adjoint of L = 1/2 sum (T_s(r) - obs[s, r])^2 in one call; the forward
-        fields go to T_out [n_src, nz, nx] when given.
+        fields go to T_out [n_src, nz, nx] when given.  stiffness=True returns (dLdtheta,
+        dLdA [nz, nx, 4]) in place of dLdtheta (as adjoint).
         Returns (loss float64 device scalar, Trec [n_src, n_rec], dLdtheta [nz, nx], stats)."""
         import torch
         nz, nx = mat_id.shape
@@ -333,14 +334,23 @@ class Solver:
         loss = torch.empty((), dtype=torch.float64, device=dev)
         stats = _lib.AdjointStats()
         self._sync_stream()
-        fn = self._lib.ali_misfit_gradient if precision == "f32" else self._lib.ali_misfit_gradient_f64
-        st = fn(self._h, ctypes.byref(g), m_arr, nm, _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id"),
+        args = [self._h, ctypes.byref(g), m_arr, nm, _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id"),
                 _dev_ptr(orient, fdt, (nz, nx), "orient"), s_arr, ns, r_arr, nr,
                 _dev_ptr(obs, fdt, (ns, nr), "obs"), ctypes.byref(opt),
                 _dev_ptr(T_out, fdt, (ns, nz, nx), "T_out") if T_out is not None else None, _dev_ptr(trec, fdt),
-                _dev_ptr(loss, torch.float64), _dev_ptr(dth, fdt), ctypes.byref(stats))
+                _dev_ptr(loss, torch.float64), _dev_ptr(dth, fdt)]
+        if stiffness:
+            dA = torch.empty((nz, nx, 4), dtype=fdt, device=dev)
+            fn = (self._lib.ali_misfit_gradient_stiffness if precision == "f32"
+                  else self._lib.ali_misfit_gradient_stiffness_f64)
+            st = fn(*args, _dev_ptr(dA, fdt), ctypes.byref(stats))
+            grad = (dth, dA)
+        else:
+            fn = self._lib.ali_misfit_gradient if precision == "f32" else self._lib.ali_misfit_gradient_f64
+            st = fn(*args, ctypes.byref(stats))
+            grad = dth
         self._check(st)
-        return loss, trec, dth, stats.as_dict()
+        return loss, trec, grad, stats.as_dict()
 
     def bilinear(self, ctrl, nz, nx):
         """Orientation [nz, nx] from control values ctrl [ncz, ncx] (float32 or float64
@@ -383,10 +393,11 @@ class Solver:
         self._check(st)
         return out, stats.as_dict()
 
-    def misfit_gradient_batch(self, batch, obs, orient=None, arith="mixed", **opts):
+    def misfit_gradient_batch(self, batch, obs, orient=None, arith="mixed", stiffness=False, **opts):
         """Forward + adjoint of the receiver misfit for every medium of `batch` in one call.
         obs: [n_obs] float32 device tensor (per field, its medium's receivers); orient: optional
-        replacement of the batch's orientation (same layout).  Returns (loss [n_media] float64,
+        replacement of the batch's orientation (same layout).  stiffness=True returns
+        (dLdtheta, dLdA [nodes, 4]) in place of dLdtheta.  Returns (loss [n_media] float64,
         Trec [n_obs], dLdtheta [nodes] float32, stats)."""
         import torch
         opt = default_options(arith=_lib.ARITH[arith], **opts)
@@ -397,15 +408,21 @@ class Solver:
         loss = torch.empty(batch.n_media, dtype=torch.float64, device=dev)
         stats = _lib.AdjointStats()
         self._sync_stream()
-        st = self._lib.ali_misfit_gradient_batch(self._h, batch.media, batch.n_media, batch.mats, batch.n_mats,
-                                                 _dev_ptr(batch.mat_id, torch.uint8, name="mat_id"),
-                                                 _dev_ptr(ori, torch.float32, tuple(batch.orient.shape), "orient"),
-                                                 batch.srcs, batch.recs, _dev_ptr(obs, torch.float32, (batch.n_obs,), "obs"),
-                                                 ctypes.byref(opt), _dev_ptr(trec, torch.float32),
-                                                 _dev_ptr(loss, torch.float64), _dev_ptr(dth, torch.float32),
-                                                 ctypes.byref(stats))
+        args = [self._h, batch.media, batch.n_media, batch.mats, batch.n_mats,
+                _dev_ptr(batch.mat_id, torch.uint8, name="mat_id"),
+                _dev_ptr(ori, torch.float32, tuple(batch.orient.shape), "orient"),
+                batch.srcs, batch.recs, _dev_ptr(obs, torch.float32, (batch.n_obs,), "obs"),
+                ctypes.byref(opt), _dev_ptr(trec, torch.float32),
+                _dev_ptr(loss, torch.float64), _dev_ptr(dth, torch.float32)]
+        if stiffness:
+            dA = torch.empty(tuple(batch.orient.shape) + (4,), dtype=torch.float32, device=dev)
+            st = self._lib.ali_misfit_gradient_batch_stiffness(*args, _dev_ptr(dA, torch.float32), ctypes.byref(stats))
+            grad = (dth, dA)
+        else:
+            st = self._lib.ali_misfit_gradient_batch(*args, ctypes.byref(stats))
+            grad = dth
         self._check(st)
-        return loss, trec, dth, stats.as_dict()
+        return loss, trec, grad, stats.as_dict()
 
     def autotune_batch(self, batch, arith="mixed", **opts):
         """Time the forward batch solve under each candidate schedule and return (the

@@ -119,6 +119,19 @@ SIGNATURES = {
                                                  _P, ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
                                                  ctypes.POINTER(Options), _P, _P, _P,
                                                  ctypes.POINTER(AdjointStats)]),
+    "ali_misfit_gradient_stiffness": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P,
+                                                     _P, ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
+                                                     ctypes.POINTER(Options), _P, _P, _P, _P, _P,
+                                                     ctypes.POINTER(AdjointStats)]),
+    "ali_misfit_gradient_stiffness_f64": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32,
+                                                         _P, _P, ctypes.POINTER(Node), _I32, ctypes.POINTER(Node),
+                                                         _I32, _P, ctypes.POINTER(Options), _P, _P, _P, _P, _P,
+                                                         ctypes.POINTER(AdjointStats)]),
+    "ali_misfit_gradient_batch_stiffness": (ctypes.c_int, [_P, ctypes.POINTER(Medium), _I32,
+                                                           ctypes.POINTER(Material), _I32, _P, _P,
+                                                           ctypes.POINTER(Node), ctypes.POINTER(Node), _P,
+                                                           ctypes.POINTER(Options), _P, _P, _P, _P,
+                                                           ctypes.POINTER(AdjointStats)]),
     "ali_misfit_gradient": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P, _P,
                                            ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
                                            ctypes.POINTER(Options), _P, _P, _P, _P, ctypes.POINTER(AdjointStats)]),

@@ -1088,6 +1088,50 @@ extern "C" ali_status ali_misfit_gradient_f64(ali_handle* h, const ali_grid* gri
                                                         stats);
 }
 
+extern "C" ali_status ali_misfit_gradient_stiffness(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                                    int32_t n_mats, const uint8_t* d_mat_id, const float* d_orient,
+                                                    const ali_node* srcs, int32_t n_src, const ali_node* recv,
+                                                    int32_t n_recv, const float* d_obs, const ali_options* opt,
+                                                    float* d_T, float* d_Trec, double* d_loss, float* d_dLdtheta,
+                                                    float* d_dLdA, ali_adjoint_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
+    if (!d_dLdA) return h->fail(ALI_EINVAL, "d_dLdA is NULL");
+    const ali_medium md = single_medium(grid, n_mats, n_src, n_recv);
+    return adjoint_dispatch<float, float, float>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, 1, d_obs,
+                                                 opt, d_T, d_Trec, d_loss, d_dLdtheta, d_dLdA, stats);
+}
+
+extern "C" ali_status ali_misfit_gradient_stiffness_f64(ali_handle* h, const ali_grid* grid,
+                                                        const ali_material* mats, int32_t n_mats,
+                                                        const uint8_t* d_mat_id, const double* d_orient,
+                                                        const ali_node* srcs, int32_t n_src, const ali_node* recv,
+                                                        int32_t n_recv, const double* d_obs, const ali_options* opt,
+                                                        double* d_T, double* d_Trec, double* d_loss,
+                                                        double* d_dLdtheta, double* d_dLdA,
+                                                        ali_adjoint_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
+    if (!d_dLdA) return h->fail(ALI_EINVAL, "d_dLdA is NULL");
+    const ali_medium md = single_medium(grid, n_mats, n_src, n_recv);
+    return adjoint_impl<double, double, double, double>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, 1,
+                                                        d_obs, opt, d_T, d_Trec, d_loss, d_dLdtheta, d_dLdA, stats);
+}
+
+extern "C" ali_status ali_misfit_gradient_batch_stiffness(ali_handle* h, const ali_medium* media, int32_t n_media,
+                                                          const ali_material* mats, int32_t n_mats,
+                                                          const uint8_t* d_mat_id, const float* d_orient,
+                                                          const ali_node* srcs, const ali_node* recv,
+                                                          const float* d_obs, const ali_options* opt, float* d_Trec,
+                                                          double* d_loss, float* d_dLdtheta, float* d_dLdA,
+                                                          ali_adjoint_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    if (!d_dLdA) return h->fail(ALI_EINVAL, "d_dLdA is NULL");
+    return adjoint_dispatch<float, float, float>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, recv, 1,
+                                                 d_obs, opt, (float*)nullptr, d_Trec, d_loss, d_dLdtheta, d_dLdA,
+                                                 stats);
+}
+
 extern "C" ali_status ali_misfit_gradient_batch(ali_handle* h, const ali_medium* media, int32_t n_media,
                                                 const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
                                                 const float* d_orient, const ali_node* srcs, const ali_node* recv,

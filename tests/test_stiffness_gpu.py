@@ -181,3 +181,46 @@ def test_stiffness_deterministic(solver):
     (b, gb), _ = solver.adjoint(m.h, m.mats, mid, ori, sources, receivers, dLdT, stiffness=True,
                                 inner_sweeps=3)
     assert torch.equal(a, b) and torch.equal(ga, gb)
+
+
+def test_misfit_stiffness_matches_adjoint(solver):
+    # the misfit entry point forms g = T - obs on the device; the adjoint given the same
+    # g at the receivers returns the same gradients
+    import torch
+    m = sm.random_medium(50, 44, 0.2e-3, seed=12, n_mats=3)
+    m.mats = [sm.TI_STEEL, sm.elliptic(3.6e7, 2.2e7, 1.1e7), sm.CUBIC_STEEL]
+    sources = [m.sources[0], (2, 3)]
+    receivers = [(49, 43), (0, 43), (25, 0)]
+    mid, ori = _dev(m, torch.float64)
+    obs = torch.from_numpy(np.random.default_rng(3).uniform(0, 1e-6, (2, 3))).cuda()
+    loss, trec, (dth, dA), st = solver.misfit_gradient(m.h, m.mats, mid, ori, sources, receivers, obs,
+                                                       precision="f64", stiffness=True)
+    assert st["converged"] == 1
+    (dth2, dA2), _ = solver.adjoint(m.h, m.mats, mid, ori, sources, receivers, trec - obs, precision="f64",
+                                    stiffness=True)
+    assert torch.allclose(dA, dA2, rtol=1e-12, atol=0) and torch.allclose(dth, dth2, rtol=1e-12, atol=0)
+
+
+def test_batch_stiffness_equals_per_medium(solver):
+    import torch
+    from paper_2302_10988_amd import Batch
+    media = [sm.random_medium(n, n - 6, 0.2e-3, seed=s, n_mats=2) for n, s in ((40, 1), (57, 2), (33, 3))]
+    for m in media:
+        m.sources = [m.sources[0], (1, 1)]
+        m.receivers = [(m.nx - 1, m.nz - 1), (0, m.nz - 1)]
+    b = Batch(media)
+    obs = torch.from_numpy(np.random.default_rng(7).uniform(0, 5e-6, b.n_obs).astype(np.float32)).cuda()
+    print("batch stiffness:", len(media), "media", flush=True)
+    loss, trec, (dth, dA), st = solver.misfit_gradient_batch(b, obs, stiffness=True)
+    assert st["converged"] == 1
+    off = 0
+    for k, m in enumerate(media):
+        n = len(m.sources) * len(m.receivers)
+        mid, ori = _dev(m, torch.float32)
+        _, _, (gm, am), _ = solver.misfit_gradient(m.h, m.mats, mid, ori, m.sources, m.receivers,
+                                                   obs[off:off + n].view(len(m.sources), len(m.receivers)),
+                                                   stiffness=True)
+        o = int(b.media[k].node_offset)
+        assert torch.equal(am.reshape(-1, 4), dA[o:o + m.nx * m.nz]), k
+        assert torch.equal(gm.flatten(), dth[o:o + m.nx * m.nz]), k
+        off += n
