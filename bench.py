@@ -48,7 +48,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector
 # program), per launch of the 64-field weld forward (grid 8192 x 64; the counters are split
 # by grid size), for the kernel sources with this hash.  Reported as null once the
 # sources differ.
-TRAFFIC = {"sources_sha256_16": "71720a528369df61", "fetch_bytes_per_launch": 22.89e6,
+TRAFFIC = {"sources_sha256_16": "a1b205f4979d3f5f", "fetch_bytes_per_launch": 22.89e6,
            "write_bytes_per_launch": 1.559e6}
 
 
@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--workload", default="weld512x64", choices=["weld512x64", "batch128"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the single-call timings of the other modes (nested source grids, SH, velocity "
+                         "table, stiffness gradient, fixed ray plane families)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (known bytes, to scale HBM counters)")
     return ap.parse_args()
@@ -234,6 +237,37 @@ def main():
         _, sst = solver.solve(m.h, m.mats, mid, ori, src1, out=single)
         single_ms = (time.perf_counter() - ts) * 1e3
         line["single_field_solve"] = {"ms": single_ms, "fields_per_s": 1e3 / single_ms, "passes": sst["outer_iters"]}
+
+        if not args.no_extras:
+            # the other modes on the same weld and sources: a warm-up call, then the faster of
+            # two timed calls (a mode's first calls can include one-off host work)
+            def timed(fn):
+                fn()
+                best = float("inf")
+                for _ in range(2):
+                    torch.cuda.synchronize()
+                    ts = time.perf_counter()
+                    fn()
+                    torch.cuda.synchronize()
+                    best = min(best, (time.perf_counter() - ts) * 1e3)
+                return best
+
+            srcs, recs = m.sources, m.receivers
+            xo = torch.empty_like(out)      # the step's fields in `out` stay for the check below
+            line["extras"] = {
+                "forward_box_ms": timed(lambda: solver.solve(m.h, m.mats, mid, ori, srcs, out=xo)),
+                "forward_nested_source_grids_ms": timed(lambda: solver.solve_refined(m.h, m.mats, mid, ori, srcs,
+                                                                                     out=xo)),
+                "forward_sh_ms": timed(lambda: solver.solve(m.h, m.mats, mid, ori, srcs, out=xo, wave="sh")),
+                "forward_velocity_table_ms": timed(lambda: solver.solve(m.h, m.mats, mid, ori, srcs, out=xo,
+                                                                        velocity="table")),
+                "misfit_gradient_ms": timed(lambda: solver.misfit_gradient(m.h, m.mats, mid, ori, srcs, recs, obs)),
+                "misfit_gradient_with_stiffness_ms": timed(lambda: solver.misfit_gradient(
+                    m.h, m.mats, mid, ori, srcs, recs, obs, stiffness=True)),
+                "rays_changing_family_ms": timed(lambda: solver.trace_rays(m.h, m.mats, mid, ori, out, srcs, recs)),
+                "rays_fastest_fixed_family_ms": timed(lambda: solver.trace_rays(m.h, m.mats, mid, ori, out, srcs,
+                                                                                recs, planes="fastest")),
+            }
 
     if not args.no_check:
         import oracle

@@ -14,8 +14,10 @@
 // relaxation passes queued between two host checks
 constexpr int ALI_PASS_BATCH = 16;
 // captured pass batches kept per handle (each signature includes the output pointer, so a
-// caller that passes new buffers every call would otherwise grow the cache without bound)
-constexpr size_t ALI_MAX_GRAPHS = 32;
+// caller that passes new buffers every call would otherwise grow the cache without bound).
+// A call takes two per relaxation (first batch and the rest; a nested-grid solve two per
+// level), so the bound leaves room for callers that alternate between several kinds of call.
+constexpr size_t ALI_MAX_GRAPHS = 128;
 
 struct ali_handle {
     int device = 0;

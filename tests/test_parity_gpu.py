@@ -134,9 +134,9 @@ def test_schedule_invariance(solver):
 
 def test_graph_cache_bounded_and_exact(solver):
     # in float32 arithmetic the relaxation works in the output buffer itself, so every
-    # output buffer is part of a captured batch's signature; 40 solves into fresh buffers
-    # overflow the handle's cache (32 graphs) and must release and recapture without
-    # changing a bit, graph replay or not
+    # output buffer is part of a captured batch's signature; 70 solves into fresh buffers
+    # (two graphs each) overflow the handle's cache (128 graphs) and must release and
+    # recapture without changing a bit, graph replay or not
     import torch
     m = sm.weld(96, 0.3e-3)
     mid = torch.from_numpy(m.mat_id).cuda()
@@ -145,12 +145,12 @@ def test_graph_cache_bounded_and_exact(solver):
     ref, st = solver.solve(m.h, m.mats, mid, ori, srcs, arith="f32", graph=0)
     assert st["outer_iters"] > 32      # long enough for whole captured batches
     keep = []
-    for k in range(40):
+    for k in range(70):
         out = torch.full((len(srcs), m.nz, m.nx), -1.0, device="cuda")
         keep.append(out)               # distinct live buffers, distinct signatures
         T, _ = solver.solve(m.h, m.mats, mid, ori, srcs, out=out, arith="f32")
         assert torch.equal(T, ref), k
-    print("graph cache: 40 captured signatures, all equal to the one-by-one launches", flush=True)
+    print("graph cache: 70 solves' captured signatures, all equal to the one-by-one launches", flush=True)
 
 
 # Exact ties of the discrete solution are resolved by rounding, so two correct
