@@ -258,6 +258,8 @@ def main():
                 "forward_box_ms": timed(lambda: solver.solve(m.h, m.mats, mid, ori, srcs, out=xo)),
                 "forward_nested_source_grids_ms": timed(lambda: solver.solve_refined(m.h, m.mats, mid, ori, srcs,
                                                                                      out=xo)),
+                "forward_subgrid3_ms": timed(lambda: solver.solve_refined(m.h, m.mats, mid, ori, srcs, out=xo,
+                                                                          subgrid=3)),
                 "forward_sh_ms": timed(lambda: solver.solve(m.h, m.mats, mid, ori, srcs, out=xo, wave="sh")),
                 "forward_velocity_table_ms": timed(lambda: solver.solve(m.h, m.mats, mid, ori, srcs, out=xo,
                                                                         velocity="table")),

@@ -187,10 +187,17 @@ typedef struct {
     double start_half_width;           /* straight rays on the finest grid within this many cells
                                           of the source (both directions); 0.5 = the source
                                           node's own cell; (0, radius[0] + 1]                  */
+    int32_t subgrid;                   /* whole-grid refinement s (Section 4.5's subgrid size):
+                                          0 or 1 = none; odd 3 .. 15 = the medium is refined
+                                          s-fold (every fine node takes the nearest grid node's
+                                          material and orientation), the fields are computed on
+                                          that grid and returned at the grid's own nodes; the
+                                          densities, radii and start_half_width above then count
+                                          cells of the s-fold grid                             */
 } ali_refine;
 
 /* The paper's choice: densities 27, 9, 3 out to 1, 6, 13 cells; straight rays in the source
-   node's own cell.  Host only. */
+   node's own cell; no whole-grid refinement (subgrid 1).  Host only. */
 void ali_default_refine(ali_refine* r);
 
 /* Travel-time fields with nested fine grids around every source (Section 4.4) in place of
@@ -203,8 +210,13 @@ void ali_default_refine(ali_refine* r);
    next coarser grid (the nodes that coincide with them keep their times); the grid itself
    comes last.  opt->src_box_radius is not used.  Other arguments, arithmetic, errors and
    output as ali_solve_traveltime; ref == NULL means ali_default_refine.  Scratch grows with
-   the fine grids (about 23k nodes per source by default).
-   stats->ms is the host time of the call; the other counters add up every level. */
+   the fine grids (about 23k nodes per source by default).  With ref->subgrid = s > 1 the
+   grid above is the s-fold grid (spacing h / s, sources at s i, s j) and the output holds
+   every s-th node of its fields; the scratch adds that grid's medium and fields (n_src
+   ((nx - 1) s + 1) ((nz - 1) s + 1) travel times); a subgrid that is even, above 15, or
+   makes that grid exceed 2^31 nodes is ALI_EINVAL.
+   stats->ms is the host time of the call; the other counters add up every level (on the
+   s-fold grid when subgrid > 1). */
 ali_status ali_solve_traveltime_refined(ali_handle* h, const ali_grid* grid, const ali_material* mats,
                                         int32_t n_mats, const uint8_t* d_mat_id, const float* d_orient,
                                         const ali_node* srcs, int32_t n_src, const ali_options* opt,

@@ -198,14 +198,22 @@ class Solver:
         self._check(st)
         return out, stats.as_dict()
 
-    def solve_refined(self, h, mats, mat_id, orient, sources, levels=((27, 1), (9, 6), (3, 13)),
-                      start_half_width=0.5, out=None, precision="f32", max_sweeps=None,
-                      inner_sweeps=None, band_cells=None, arith="mixed", **extra):
+    def solve_refined(self, h, mats, mat_id, orient, sources, levels=None, start_half_width=None,
+                      out=None, precision="f32", max_sweeps=None, inner_sweeps=None, band_cells=None,
+                      arith="mixed", subgrid=1, **extra):
         """Travel-time fields [n_src, nz, nx] with nested fine grids around every source
         (Section 4.4): levels = ((density, radius), ...) from the finest; straight rays on the
-        finest grid within start_half_width cells of the source.  Other arguments as solve.
-        Returns (T, stats dict)."""
+        finest grid within start_half_width cells of the source.  subgrid = s (odd) solves on
+        the s-fold refined medium and returns its fields at the given nodes (Section 4.5);
+        levels and start_half_width then count cells of that grid.  By default the paper's
+        choices: ((27, 1), (9, 6), (3, 13)) and 0.5 without a subgrid, ((9, 2 s), (3, 5 s))
+        and s / 2 with one (Table 3).  Other arguments as solve.  Returns (T, stats dict)."""
         import torch
+        s = int(subgrid)
+        if levels is None:
+            levels = ((27, 1), (9, 6), (3, 13)) if s <= 1 else ((9, 2 * s), (3, 5 * s))
+        if start_half_width is None:
+            start_half_width = 0.5 * max(s, 1)
         nz, nx = mat_id.shape
         fdt = torch.float32 if precision == "f32" else torch.float64
         m_arr, nm = _materials(mats)
@@ -222,6 +230,7 @@ class Solver:
             ref.density[k] = int(d)
             ref.radius[k] = int(r)
         ref.start_half_width = float(start_half_width)
+        ref.subgrid = s
         if out is None:
             out = torch.empty((ns, nz, nx), dtype=fdt, device=mat_id.device)
         p_id = _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id")

@@ -44,7 +44,8 @@ MAX_LEVELS = 8
 
 class Refine(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int32), ("density", ctypes.c_int32 * MAX_LEVELS),
-                ("radius", ctypes.c_int32 * MAX_LEVELS), ("start_half_width", ctypes.c_double)]
+                ("radius", ctypes.c_int32 * MAX_LEVELS), ("start_half_width", ctypes.c_double),
+                ("subgrid", ctypes.c_int32)]
 
 
 ARITH = {"mixed": 0, "f32": 1, "f64": 2}

@@ -22,6 +22,10 @@
 // would change none of the values that are handed on.
 // The working grid itself is the last level: all sources' fields in one batch, seeded
 // from the coarsest fine level.
+//
+// Section 4.5's subgrid size s (odd) refines the whole medium s-fold first (k_subgrid_medium,
+// nearest node again); the levels above then run on that grid, and k_subgrid_pick returns
+// every s-th node of its fields.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -148,6 +152,32 @@ __global__ void k_level_stop(const LevelDev* __restrict__ lv, const real* __rest
     if (threadIdx.x == 0) tstop[blockIdx.x] = red[0];
 }
 
+// the s-fold grid's medium: node (a, b) takes the material and orientation of working node
+// (nearest a / s, nearest b / s)
+template <typename oreal>
+__global__ void k_subgrid_medium(int nx, int nx_s, int64_t n_s, int s, const uint8_t* __restrict__ mat,
+                                 const oreal* __restrict__ ori, uint8_t* __restrict__ mat_s,
+                                 oreal* __restrict__ ori_s) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_s) return;
+    const int a = (int)(q % nx_s), b = (int)(q / nx_s);
+    const int64_t p = (int64_t)near_div(b, s) * nx + near_div(a, s);
+    mat_s[q] = mat[p];
+    ori_s[q] = ori[p];
+}
+
+// the fields at the working nodes: node (i, j) of field k is node (s i, s j) of the s-fold
+// field k
+template <typename outreal, typename real>
+__global__ void k_subgrid_pick(int nx, int64_t nw, int64_t n_out, int nx_s, int64_t n_s, int s,
+                               const real* __restrict__ Ts, outreal* __restrict__ out) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_out) return;
+    const int64_t k = q / nw, r = q % nw;
+    const int i = (int)(r % nx), j = (int)(r / nx);
+    out[q] = (outreal)Ts[k * n_s + (int64_t)j * s * nx_s + (int64_t)i * s];
+}
+
 // host: one level's grids (clipped to the working grid) and their offsets
 static std::vector<LevelDev> level_grids(const ali_grid& g, const ali_node* srcs, int n_src, int d, int W, int stop,
                                          std::vector<ali_medium>& media, std::vector<ali_node>& lsrc,
@@ -194,18 +224,12 @@ static void add_stats(ali_solve_stats& acc, const ali_solve_stats& s) {
     acc.converged = acc.converged && s.converged;
 }
 
+// the nested grids on one working grid (the caller's, or its s-fold refinement)
 template <typename real, typename mreal, typename oreal, typename outreal>
-static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
-                               const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs, int32_t n_src,
-                               const ali_options* opt_in, const ali_refine* ref_in, outreal* d_out,
-                               ali_solve_stats* stats) {
-    const auto t0 = std::chrono::steady_clock::now();
-    ali_options opt;
-    ali_default_options(&opt);
-    if (opt_in) opt = *opt_in;
-    ali_refine ref;
-    ali_default_refine(&ref);
-    if (ref_in) ref = *ref_in;
+static ali_status levels_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
+                              const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs, int32_t n_src,
+                              const ali_options& opt, const ali_refine& ref, outreal* d_out,
+                              ali_solve_stats* stats, std::chrono::steady_clock::time_point t0) {
     if (!grid) return H->fail(ALI_EINVAL, "grid is NULL");
     if (!d_out) return H->fail(ALI_EINVAL, "d_T is NULL");
     const ali_medium mw = single_medium(grid, n_mats, n_src, 0);
@@ -349,6 +373,63 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     return ALI_OK;
 }
 
+template <typename real, typename mreal, typename oreal, typename outreal>
+static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
+                               const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs, int32_t n_src,
+                               const ali_options* opt_in, const ali_refine* ref_in, outreal* d_out,
+                               ali_solve_stats* stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    ali_options opt;
+    ali_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    ali_refine ref;
+    ali_default_refine(&ref);
+    if (ref_in) ref = *ref_in;
+    const int s = ref.subgrid;
+    if (s == 0 || s == 1)
+        return levels_impl<real, mreal, oreal, outreal>(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt,
+                                                        ref, d_out, stats, t0);
+    if (s < 0 || s % 2 == 0 || s > 15) return H->fail(ALI_EINVAL, "subgrid must be 0, 1 or odd in [3, 15]");
+    if (!grid) return H->fail(ALI_EINVAL, "grid is NULL");
+    if (!d_out) return H->fail(ALI_EINVAL, "d_T is NULL");
+    // the caller's medium, sources included, is checked on its own grid first
+    const ali_medium mw = single_medium(grid, n_mats, n_src, 0);
+    ali_status st = validate_batch(H, &mw, 1, mats, n_mats, d_mat_id, d_orient, srcs, nullptr, opt.wave);
+    if (st != ALI_OK) return st;
+    ali_grid gs = *grid;
+    const int64_t nxs = (int64_t)(grid->nx - 1) * s + 1, nzs = (int64_t)(grid->nz - 1) * s + 1;
+    if (nxs * nzs > (int64_t)1 << 31) return H->fail(ALI_EINVAL, "the s-fold grid exceeds 2^31 nodes");
+    gs.nx = (int32_t)nxs;
+    gs.nz = (int32_t)nzs;
+    gs.h = grid->h / s;
+    std::vector<ali_node> ss(srcs, srcs + n_src);
+    for (ali_node& q : ss) {
+        q.i *= s;
+        q.j *= s;
+    }
+    if (set_device(H) != ALI_OK) return ALI_EDEVICE;
+    hipStream_t S = H->stream;
+    const int B = 256;
+    const int64_t NS = nxs * nzs, NW = (int64_t)grid->nx * grid->nz;
+    void *d_mid = nullptr, *d_ori = nullptr, *d_Ts = nullptr;
+    if (!H->scratch("sub_mid", NS, &d_mid) || !H->scratch("sub_ori", sizeof(oreal) * NS, &d_ori) ||
+        !H->scratch("sub_T", sizeof(real) * NS * n_src, &d_Ts))
+        return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+    hipLaunchKernelGGL((k_subgrid_medium<oreal>), dim3((unsigned)((NS + B - 1) / B)), dim3(B), 0, S, grid->nx,
+                       gs.nx, NS, s, d_mat_id, d_orient, (uint8_t*)d_mid, (oreal*)d_ori);
+    HIPCK(H, hipGetLastError());
+    st = levels_impl<real, mreal, oreal, real>(H, &gs, mats, n_mats, (const uint8_t*)d_mid, (const oreal*)d_ori,
+                                               ss.data(), n_src, opt, ref, (real*)d_Ts, stats, t0);
+    if (st != ALI_OK && st != ALI_ENOCONV) return st;
+    const int64_t n_out = NW * n_src;
+    hipLaunchKernelGGL((k_subgrid_pick<outreal, real>), dim3((unsigned)((n_out + B - 1) / B)), dim3(B), 0, S,
+                       grid->nx, NW, n_out, gs.nx, NS, s, (const real*)d_Ts, d_out);
+    HIPCK(H, hipGetLastError());
+    HIPCK(H, hipStreamSynchronize(S));
+    if (stats) stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+}
+
 }  // namespace ali
 
 using namespace ali;
@@ -360,6 +441,7 @@ extern "C" void ali_default_refine(ali_refine* r) {
     r->density[0] = 27; r->density[1] = 9; r->density[2] = 3;
     r->radius[0] = 1; r->radius[1] = 6; r->radius[2] = 13;
     r->start_half_width = 0.5;
+    r->subgrid = 1;
 }
 
 extern "C" ali_status ali_solve_traveltime_refined(ali_handle* h, const ali_grid* grid, const ali_material* mats,

@@ -52,7 +52,7 @@ def test_host_only_entry_points():
     r = _lib.Refine()
     lib.ali_default_refine(ctypes.byref(r))
     assert r.n_levels == 3 and list(r.density[:3]) == [27, 9, 3] and list(r.radius[:3]) == [1, 6, 13]
-    assert r.start_half_width == 0.5
+    assert r.start_half_width == 0.5 and r.subgrid == 1
     assert lib.ali_destroy(None) == _lib.ALI_EINVAL
     assert lib.ali_create(None, 0, None) == _lib.ALI_EINVAL
 
