@@ -111,8 +111,8 @@ def relax_roofline(solver, call):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the solver has no multi-GPU path; "
-              "fields shard across GPUs without communication, see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver has no multi-GPU path (independent fields "
+              "would shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
