@@ -8,7 +8,10 @@ its straight-ray fallback and its source box (Section 4.4).  Pins:
     estimate, and the shift invariance dU/dta + dU/dtb + dU/dtc = 1;
   - the adjoint against central differences of the frozen-choice field (tight), and of
     the full solver (choices free to switch) under a uniform rotation of every node;
-  - isotropic media give a zero gradient; the gradient is linear in dL/dT.
+  - isotropic media give a zero gradient; the gradient is linear in dL/dT;
+  - the ray-path gradient (the time along the traced ray, path held fixed) is a different
+    discretisation of the same derivative: projected onto a smooth control grid the two
+    agree better as the grid is refined, cosine at least 0.95 at 128 x 128.
 """
 import math
 
@@ -193,3 +196,45 @@ def test_control_gradient_vs_full_differences(orc):
             # 1e-3 rad: a switch moves single entries by a few percent
             assert cos >= 0.99, cos
             assert np.median(rel) <= 1e-2, np.median(rel)
+
+
+def test_adjoint_vs_ray_path_gradient(orc):
+    # One source, six receivers with random weights, TI steel with a smooth orientation
+    # (6 x 6 bilinear controls) on the same physical square at 32, 64 and 128 nodes per side.
+    # Both gradients are projected onto the controls (W^T G W).  Measured: cosine 0.825 /
+    # 0.898 / 0.963, norm ratio adjoint / ray 0.61 / 0.68 / 0.76: the field's discretisation
+    # error varies with the orientation, and that variation shrinks with the cell size.
+    from raypath_grad import cosine, ray_path_gradient
+    rng = np.random.default_rng(3)
+    nc = 6
+    ctrl = rng.uniform(-0.8, 0.8, size=(nc, nc))
+    src63, recs63 = (20, 0), [(5, 63), (30, 63), (50, 63), (63, 40), (63, 20), (40, 63)]
+    w = rng.normal(size=len(recs63))
+    mats = [sm.TI_STEEL]
+    cos, ratio = [], []
+    for n in (32, 64, 128):
+        h = 0.5e-3 * 64 / n
+        W = sm.bilinear_weights(n, nc)
+        th = W @ ctrl @ W.T
+        mid = np.zeros((n, n), np.uint8)
+
+        def at(p):
+            return (int(round(p[0] * (n - 1) / 63)), int(round(p[1] * (n - 1) / 63)))
+
+        src = at(src63)
+        T = orc.solve_fmm(h, mats, mid, th, src, 2)
+        g = np.zeros((n, n))
+        ray = np.zeros((n, n))
+        for r63, wk in zip(recs63, w):
+            r = at(r63)
+            g[r[1], r[0]] += wk
+            pts, t, ok = orc.trace_ray(h, mats, mid, th, T, src, r)
+            assert ok
+            ray += wk * ray_path_gradient(orc, h, mats, mid, th, pts)
+        adj = orc.adjoint(h, mats, mid, th, src, g)[1]
+        ga, gr = W.T @ adj @ W, W.T @ ray @ W
+        cos.append(cosine(ga, gr))
+        ratio.append(float(np.linalg.norm(ga) / np.linalg.norm(gr)))
+    print("control-space cosine", cos, "norm ratio", ratio)
+    assert cos[0] < cos[1] < cos[2] and cos[2] >= 0.95
+    assert ratio[0] < ratio[1] < ratio[2] <= 1.0 and ratio[2] >= 0.7
