@@ -71,6 +71,17 @@ typedef struct {
     int32_t ray_planes;      /* ray tracer plane families: ALI_RAY_CHANGING (default) or a fixed
                                 family / the fastest of the four fixed families (below)         */
     int32_t velocity;        /* ALI_VEL_CHRISTOFFEL (default) or ALI_VEL_TABLE (below)           */
+    const float* d_node_A;   /* per-node stiffness / density (device, caller-owned), NULL (default)
+                                = the material table.  Otherwise [nodes][4] float32: A11, A13, A33,
+                                A55 of every node in m^2/s^2 (A = C / rho, the layout of the
+                                stiffness gradient), nodes in the order of d_mat_id (for a batch,
+                                the media's nodes concatenated as there).  Each node needs finite
+                                A11, A33, A55 > 0 and A11 A33 > A13^2, else ALI_EINVAL after the
+                                device check.  The qP forward solves (single medium and batch) and
+                                the adjoint and misfit gradients take it; ray tracing, the nested
+                                source grids, SH and the velocity table return ALI_EUNSUPPORTED.
+                                The material table and ids must still be valid; they are then not
+                                read for the speeds.                                           */
 } ali_options;
 
 /* Speeds of the solve (Section 3.2).  CHRISTOFFEL: the phase speed of every stencil and the

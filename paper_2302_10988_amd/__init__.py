@@ -28,7 +28,7 @@ def _status_string(status):
         return "status"
 
 
-def default_options(**overrides):
+def default_options(_n_nodes=None, **overrides):
     lib = _lib.load()
     o = _lib.Options()
     lib.ali_default_options(ctypes.byref(o))
@@ -38,6 +38,17 @@ def default_options(**overrides):
                 v = _lib.WAVE[v]
             if k == "velocity" and isinstance(v, str):
                 v = _lib.VELOCITY[v]
+            if k == "node_A":
+                # per-node A11, A13, A33, A55 [.., 4] float32 device tensor, in the node order
+                # of the medium arrays (the caller keeps it alive for the call)
+                import torch
+                if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float32
+                        and v.is_contiguous() and v.dim() >= 2 and v.shape[-1] == 4):
+                    raise ValueError("node_A must be a contiguous float32 device tensor [..., 4]")
+                if _n_nodes is not None and v.numel() != 4 * _n_nodes:
+                    raise ValueError("node_A needs 4 values per node (%d nodes)" % _n_nodes)
+                o.d_node_A = v.data_ptr()
+                continue
             setattr(o, k, int(v))
     return o
 
@@ -174,8 +185,9 @@ class Solver:
         sources: [(i, j), ...]; arith (float32 output only): "mixed" (float64 times and
         decisions, float32 wavefront math), "f32" or "f64"; extra: other ali_options fields by
         name (wave="sh" for the shear wave polarised normal to the plane, velocity="table" for
-        the paper's velocity table).  Returns (T, stats
-        dict)."""
+        the paper's velocity table; node_A=[nz, nx, 4] float32 device tensor of every node's
+        A11, A13, A33, A55 = C / rho in place of the material table, also taken by adjoint,
+        misfit_gradient and the batch calls).  Returns (T, stats dict)."""
         import torch
         nz, nx = mat_id.shape
         fdt = torch.float32 if precision == "f32" else torch.float64
@@ -184,7 +196,7 @@ class Solver:
         g = _lib.Grid(int(nx), int(nz), float(h))
         opt = default_options(src_box_radius=src_box_radius, max_sweeps=max_sweeps,
                               inner_sweeps=inner_sweeps, band_cells=band_cells,
-                              arith=_lib.ARITH[arith], **extra)
+                              arith=_lib.ARITH[arith], _n_nodes=int(nx) * int(nz), **extra)
         if out is None:
             out = torch.empty((ns, nz, nx), dtype=fdt, device=mat_id.device)
         p_id = _dev_ptr(mat_id, torch.uint8, (nz, nx), "mat_id")
@@ -246,7 +258,7 @@ class Solver:
         return out, stats.as_dict()
 
     def trace_rays(self, h, mats, mat_id, orient, T, sources, receivers, window=None, sub=None,
-                   max_pts=None, wave=None, planes=None, velocity=None):
+                   max_pts=None, wave=None, planes=None, velocity=None, **extra):
         """Ray paths from every receiver to every source through the fields T
         [n_src, nz, nx] (float32 or float64 device tensor); wave "qp" (default) or "sh" as
         for the fields; planes "changing" (default), "x", "z", "diag", "anti" (one fixed
@@ -261,7 +273,7 @@ class Solver:
         r_arr, nr = _nodes(receivers)
         g = _lib.Grid(int(nx), int(nz), float(h))
         opt = default_options(ray_window=window, ray_sub=sub, ray_max_pts=max_pts, wave=wave, velocity=velocity,
-                              ray_planes=_lib.RAY_PLANES[planes] if planes is not None else None)
+                              ray_planes=_lib.RAY_PLANES[planes] if planes is not None else None, **extra)
         dev = mat_id.device
         paths = torch.empty((ns, nr, opt.ray_max_pts, 2), dtype=torch.float32, device=dev)
         npts = torch.empty((ns, nr), dtype=torch.int32, device=dev)
@@ -298,7 +310,7 @@ class Solver:
         g = _lib.Grid(int(nx), int(nz), float(h))
         opt = default_options(src_box_radius=src_box_radius, max_sweeps=max_sweeps,
                               inner_sweeps=inner_sweeps, band_cells=band_cells,
-                              arith=_lib.ARITH[arith], **extra)
+                              arith=_lib.ARITH[arith], _n_nodes=int(nx) * int(nz), **extra)
         dev = mat_id.device
         dth = torch.empty((nz, nx), dtype=fdt, device=dev)
         T = torch.empty((ns, nz, nx), dtype=fdt, device=dev) if return_T else None
@@ -336,7 +348,7 @@ class Solver:
         g = _lib.Grid(int(nx), int(nz), float(h))
         opt = default_options(src_box_radius=src_box_radius, max_sweeps=max_sweeps,
                               inner_sweeps=inner_sweeps, band_cells=band_cells,
-                              arith=_lib.ARITH[arith], **extra)
+                              arith=_lib.ARITH[arith], _n_nodes=int(nx) * int(nz), **extra)
         dev = mat_id.device
         dth = torch.empty((nz, nx), dtype=fdt, device=dev)
         trec = torch.empty((ns, nr), dtype=fdt, device=dev)
@@ -389,7 +401,7 @@ class Solver:
         """Fields of every source of every medium of `batch` in one call.  Returns (T
         [field_nodes] float32 in medium order, stats dict)."""
         import torch
-        opt = default_options(arith=_lib.ARITH[arith], **opts)
+        opt = default_options(arith=_lib.ARITH[arith], _n_nodes=batch.mat_id.numel(), **opts)
         if out is None:
             out = torch.empty(batch.field_nodes, dtype=torch.float32, device=batch.mat_id.device)
         stats = _lib.SolveStats()
@@ -409,7 +421,7 @@ class Solver:
         (dLdtheta, dLdA [nodes, 4]) in place of dLdtheta.  Returns (loss [n_media] float64,
         Trec [n_obs], dLdtheta [nodes] float32, stats)."""
         import torch
-        opt = default_options(arith=_lib.ARITH[arith], **opts)
+        opt = default_options(arith=_lib.ARITH[arith], _n_nodes=batch.mat_id.numel(), **opts)
         dev = batch.mat_id.device
         ori = batch.orient if orient is None else orient
         dth = torch.empty_like(batch.orient)
@@ -437,7 +449,7 @@ class Solver:
         """Time the forward batch solve under each candidate schedule and return (the
         fastest options as a dict, {(band_cells, inner_sweeps): ms})."""
         import torch
-        opt = default_options(arith=_lib.ARITH[arith], **opts)
+        opt = default_options(arith=_lib.ARITH[arith], _n_nodes=batch.mat_id.numel(), **opts)
         out = torch.empty(batch.field_nodes, dtype=torch.float32, device=batch.mat_id.device)
         ms = (ctypes.c_double * len(_lib.TUNE_CANDIDATES))()
         self._sync_stream()

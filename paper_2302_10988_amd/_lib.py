@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
                 ("inner_sweeps", ctypes.c_int32), ("band_cells", ctypes.c_int32),
                 ("ray_window", ctypes.c_int32), ("ray_max_pts", ctypes.c_int32),
                 ("arith", ctypes.c_int32), ("ray_sub", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("wave", ctypes.c_int32), ("ray_planes", ctypes.c_int32), ("velocity", ctypes.c_int32)]
+                ("wave", ctypes.c_int32), ("ray_planes", ctypes.c_int32), ("velocity", ctypes.c_int32),
+                ("d_node_A", ctypes.c_void_p)]
 
 MAX_LEVELS = 8
 

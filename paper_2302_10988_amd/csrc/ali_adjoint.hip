@@ -146,6 +146,7 @@ template <typename mreal, typename oreal, bool WA>
 __global__ void __launch_bounds__(NTHREADS)
 k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal>* __restrict__ mats_all,
            const uint8_t* __restrict__ mat_id_all, const oreal* __restrict__ orient_all,
+           const float* __restrict__ nodeA_all,
            const mreal* __restrict__ geo_all, const double* __restrict__ fbt_all, int R,
            const double* __restrict__ T, AdjW<mreal>* __restrict__ W, double* __restrict__ wT,
            double* __restrict__ wA, unsigned long long* __restrict__ mismatches) {
@@ -160,9 +161,16 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
     const MatDev<mreal>* __restrict__ mats = mats_all + fd.mat_off;
     const uint8_t* __restrict__ mat_id = mat_id_all + fd.node_off;
     const oreal* __restrict__ orient = orient_all + fd.node_off;
+    const float* __restrict__ nodeA = nodeA_all ? nodeA_all + 4 * fd.node_off : nullptr;
     const mreal* __restrict__ geo = geo_all + GEO_N * fd.node_off;
     const double* __restrict__ fbt = fbt_all + 4 * fd.node_off;
     const double inf = dinf<double>();
+    // stiffness / density of a node: its own (per-node mode) or its material's
+    auto stiff = [&](int64_t n) -> MatA {
+        if (nodeA) return MatA{(double)nodeA[4 * n], (double)nodeA[4 * n + 1], (double)nodeA[4 * n + 2],
+                               (double)nodeA[4 * n + 3]};
+        return mats[mat_id[n]].A;
+    };
     const int tid = threadIdx.x;
     for (int q = tid; q < LW * LH; q += NTHREADS) {
         const int li = q % LW, lj = q / LW;
@@ -192,10 +200,11 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
             const double phi = atan2((double)dj, (double)di) - (double)orient[ps];
             const double L = sqrt((double)(di * di + dj * dj)) * h;
             double dV;
-            const double V = group_speed(mats[mat_id[ps]].A, phi, &dV);
+            const MatA As = stiff(ps);
+            const double V = group_speed(As, phi, &dV);
             t = L * dV / (V * V);
             if constexpr (WA) {
-                group_speed_dA(mats[mat_id[ps]].A, phi, dA);
+                group_speed_dA(As, phi, dA);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) dA[k] *= -L / (V * V);
             }
@@ -210,7 +219,7 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
         int ch = -1;
         const double u = local_update<mreal, double>(nc, tt, lt, me, LSTRIDE, ev, &ch);
         if (!(u == tD)) atomicAdd(mismatches, 1ull);
-        const MatA& A = mats[mat_id[p]].A;
+        const MatA A = stiff(p);
         const double th = (double)orient[p];
         if (ch >= 0 && ch < 32) {
             const StGeo g = stencil_geo(ch, std::make_integer_sequence<int, 32>{});
@@ -770,13 +779,13 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     const unsigned gNF = (unsigned)((NF + B - 1) / B);
     if (d_dA)
         hipLaunchKernelGGL((k_adj_prep<mreal, oreal, true>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
-                           fs.fields, n_fields, fs.mats, d_mat_id, d_orient, fs.geo, fs.fbt, opt.src_box_radius,
-                           (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (double*)d_wA,
+                           fs.fields, n_fields, fs.mats, d_mat_id, d_orient, opt.d_node_A, fs.geo, fs.fbt,
+                           opt.src_box_radius, (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (double*)d_wA,
                            (unsigned long long*)d_cnt + 1);
     else
         hipLaunchKernelGGL((k_adj_prep<mreal, oreal, false>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
-                           fs.fields, n_fields, fs.mats, d_mat_id, d_orient, fs.geo, fs.fbt, opt.src_box_radius,
-                           (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (double*)nullptr,
+                           fs.fields, n_fields, fs.mats, d_mat_id, d_orient, opt.d_node_A, fs.geo, fs.fbt,
+                           opt.src_box_radius, (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (double*)nullptr,
                            (unsigned long long*)d_cnt + 1);
     HIPCK(H, hipGetLastError());
     hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_G, NF, 0.0);

@@ -18,6 +18,7 @@ extern "C" void ali_default_options(ali_options* o) {
     o->wave = ALI_WAVE_QP;
     o->ray_planes = ALI_RAY_CHANGING;
     o->velocity = ALI_VEL_CHRISTOFFEL;
+    o->d_node_A = nullptr;
 }
 
 extern "C" ali_status ali_create(ali_handle** out, int device, void* hip_stream) {

@@ -416,6 +416,7 @@ static ali_status trace_impl(ali_handle* H, const ali_grid* grid, const ali_mate
     if (opt.ray_max_pts < 2) return H->fail(ALI_EINVAL, "ray_max_pts must be >= 2");
     if (opt.ray_planes < ALI_RAY_CHANGING || opt.ray_planes > ALI_RAY_FASTEST_FIXED)
         return H->fail(ALI_EINVAL, "unknown ray_planes");
+    if (opt.d_node_A) return H->fail(ALI_EUNSUPPORTED, "ray tracing takes the material table, not per-node stiffness");
     if (opt.velocity != ALI_VEL_CHRISTOFFEL && opt.velocity != ALI_VEL_TABLE)
         return H->fail(ALI_EINVAL, "unknown velocity mode");
     if ((int64_t)n_src * n_recv > (int64_t)1 << 30) return H->fail(ALI_EINVAL, "too many rays");

@@ -385,6 +385,8 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     ali_refine ref;
     ali_default_refine(&ref);
     if (ref_in) ref = *ref_in;
+    if (opt.d_node_A)
+        return H->fail(ALI_EUNSUPPORTED, "the nested source grids take the material table, not per-node stiffness");
     const int s = ref.subgrid;
     if (s == 0 || s == 1)
         return levels_impl<real, mreal, oreal, outreal>(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt,

@@ -46,12 +46,30 @@ struct PrepDev {
     int n_mats, mat_off;
 };
 
+// largest qP phase speed of one stiffness over the same 181 directions as max_phase_speed
+__device__ __forceinline__ double node_vmax(const MatA& A) {
+    double v2max = 0.0;
+    for (int q = 0; q <= 180; ++q) {
+        const double psi = q * (3.14159265358979323846 / 360.0);
+        const double c = cos(2.0 * psi), sn = sin(2.0 * psi);
+        const double lin = (A.a33 - A.a11) + (A.a11 + A.a33 - 2.0 * A.a55) * c;
+        const double v2 = 0.25 * ((A.a11 + A.a33 + 2.0 * A.a55) + (A.a33 - A.a11) * c +
+                                  sqrt(lin * lin + 4.0 * (A.a13 + A.a55) * (A.a13 + A.a55) * sn * sn));
+        v2max = v2 > v2max ? v2 : v2max;
+    }
+    return sqrt(v2max);
+}
+
 template <typename mreal, typename treal, typename oreal>
 // gt_all (velocity-table mode, else NULL): group-speed tables of the device materials; the
 // node's table offset goes to geo slot 6 and the straight-ray times come from the table.
+// nodeA_all (else NULL): the per-node stiffness in place of the table (same node order as
+// the ids); each medium's largest phase speed goes to vmax_bits[medium] (positive doubles
+// order as their bit patterns, so an integer maximum finds it).
 __global__ void k_prep(const PrepDev* __restrict__ media, int m0, const MatDev<mreal>* __restrict__ mats_all,
                        const uint8_t* __restrict__ mat_id_all, const oreal* __restrict__ orient_all,
                        mreal* __restrict__ geo_all, treal* __restrict__ fbt_all, const double* __restrict__ gt_all,
+                       const float* __restrict__ nodeA_all, unsigned long long* __restrict__ vmax_bits,
                        int* __restrict__ err) {
     const PrepDev md = media[m0 + blockIdx.y];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -66,16 +84,34 @@ __global__ void k_prep(const PrepDev* __restrict__ media, int m0, const MatDev<m
     const int mid = mat_id[p];
     if (!isfinite(th)) { atomicOr(err, 1); return; }
     if (mid >= md.n_mats) { atomicOr(err, 2); return; }
-    const MatA m = mats[mid].A;
+    MatA m = mats[mid].A;
+    mreal P = mats[mid].P, Q = mats[mid].Q, R = mats[mid].R, K4 = mats[mid].K4;
+    if (nodeA_all) {
+        // the same constants as the host table, from this node's stiffness
+        const float* a = nodeA_all + 4 * (md.node_off + p);
+        m = MatA{(double)a[0], (double)a[1], (double)a[2], (double)a[3]};
+        if (!(isfinite(m.a11) && isfinite(m.a13) && isfinite(m.a33) && isfinite(m.a55) && m.a11 > 0.0 &&
+              m.a33 > 0.0 && m.a55 > 0.0 && m.a11 * m.a33 > m.a13 * m.a13)) {
+            atomicOr(err, 4);
+            return;
+        }
+        const double ih2 = 1.0 / (h * h);
+        P = (mreal)((m.a11 + m.a33 + 2.0 * m.a55) * ih2);
+        Q = (mreal)((m.a33 - m.a11) * ih2);
+        R = (mreal)((m.a11 + m.a33 - 2.0 * m.a55) * ih2);
+        const double W = (m.a13 + m.a55) * ih2;
+        K4 = (mreal)(4.0 * W * W);
+        atomicMax(&vmax_bits[m0 + blockIdx.y], (unsigned long long)__double_as_longlong(node_vmax(m)));
+    }
     double s2, c2;
     sincos(2.0 * th, &s2, &c2);
     mreal* g = geo + GEO_N * p;
     g[0] = (mreal)c2;
     g[1] = (mreal)s2;
-    g[2] = mats[mid].P;
-    g[3] = mats[mid].Q;
-    g[4] = mats[mid].R;
-    g[5] = mats[mid].K4;
+    g[2] = P;
+    g[3] = Q;
+    g[4] = R;
+    g[5] = K4;
     g[6] = gt_all ? (mreal)((md.mat_off + mid) * VT_N) : mreal(0);
     g[7] = mreal(0);
     // straight-ray time to an 8-neighbour along x, (1,1), z, (1,-1)
@@ -92,7 +128,7 @@ __global__ void k_prep(const PrepDev* __restrict__ media, int m0, const MatDev<m
 template <typename real, typename mreal, typename oreal>
 __global__ void k_init(const FieldDev* __restrict__ fields, int f0, double h, const MatDev<mreal>* __restrict__ mats,
                        const double* __restrict__ gt, int n_mats, const uint8_t* __restrict__ mat_id,
-                       const oreal* __restrict__ orient, int R,
+                       const oreal* __restrict__ orient, const float* __restrict__ nodeA, int R,
                        real* __restrict__ T, uint32_t* __restrict__ flags) {
     const FieldDev fd = fields[f0 + blockIdx.y];
     const int nx = fd.nx;
@@ -112,7 +148,10 @@ __global__ void k_init(const FieldDev* __restrict__ fields, int f0, double h, co
             const double phi = atan2((double)dj, (double)di) - (double)orient[ps];
             // an id outside the table is reported by k_prep; read a valid entry meanwhile
             const int mid = mat_id[ps] < n_mats ? mat_id[ps] : 0;
-            const double V = gt ? group_speed_tab(gt + mid * VT_N, phi) : group_speed(mats[mid].A, phi);
+            const MatA A = nodeA ? MatA{(double)nodeA[4 * ps], (double)nodeA[4 * ps + 1], (double)nodeA[4 * ps + 2],
+                                        (double)nodeA[4 * ps + 3]}
+                                 : mats[mid].A;
+            const double V = gt ? group_speed_tab(gt + mid * VT_N, phi) : group_speed(A, phi);
             v = (real)(sqrt((double)(di * di + dj * dj)) * h / V);
         }
     }
@@ -478,6 +517,8 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     if (opt.band_cells < 0) return H->fail(ALI_EINVAL, "band_cells must be >= 0 (0 = no band)");
     if (opt.velocity != ALI_VEL_CHRISTOFFEL && opt.velocity != ALI_VEL_TABLE)
         return H->fail(ALI_EINVAL, "unknown velocity mode");
+    if (opt.d_node_A && (opt.wave != ALI_WAVE_QP || opt.velocity != ALI_VEL_CHRISTOFFEL))
+        return H->fail(ALI_EUNSUPPORTED, "per-node stiffness needs the qP wave and the run-time speeds");
     if (set_device(H) != ALI_OK) return ALI_EDEVICE;
     hipStream_t S = H->stream;
 
@@ -556,8 +597,6 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     HIPCK(H, hipEventRecord(H->ev0, S));
     HIPCK(H, hipMemcpyAsync(d_mats, hm.data(), sizeof(MatDev<mreal>) * hm.size(), hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemcpyAsync(d_fields, F.hfields.data(), sizeof(FieldDev) * n_fields, hipMemcpyHostToDevice, S));
-    HIPCK(H, hipMemcpyAsync(d_theta, htheta.data(), sizeof(real) * n_fields, hipMemcpyHostToDevice, S));
-    HIPCK(H, hipMemcpyAsync(d_step, hstep.data(), sizeof(real) * n_fields, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemsetAsync(d_flags, 0, sizeof(uint32_t) * nunits, S));
     HIPCK(H, hipMemsetAsync(d_marks, 0, sizeof(uint32_t) * 2 * NODE_WORDS * nunits, S));
     HIPCK(H, hipMemsetAsync(d_upd, 0, (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), S));
@@ -598,15 +637,18 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
         hp[m] = PrepDev{md.node_offset, md.grid.nx, md.grid.nz, md.grid.h, md.n_mats, dev_mat_off[m]};
         max_nodes = std::max(max_nodes, (int64_t)md.grid.nx * md.grid.nz);
     }
-    void* d_prep = nullptr;
-    if (!H->scratch("prep", sizeof(PrepDev) * n_media, &d_prep))
+    void *d_prep = nullptr, *d_vmaxb = nullptr;
+    if (!H->scratch("prep", sizeof(PrepDev) * n_media, &d_prep) ||
+        !H->scratch("vmaxb", sizeof(unsigned long long) * n_media, &d_vmaxb))
         return H->fail(ALI_ENOMEM, "device scratch allocation failed");
     HIPCK(H, hipMemcpyAsync(d_prep, hp.data(), sizeof(PrepDev) * n_media, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemsetAsync(d_vmaxb, 0, sizeof(unsigned long long) * n_media, S));
     for (int m0 = 0; m0 < n_media; m0 += 65535) {
         const int nm = std::min(n_media - m0, 65535);
         hipLaunchKernelGGL((k_prep<mreal, real, oreal>), dim3((unsigned)((max_nodes + B - 1) / B), (unsigned)nm),
                            dim3(B), 0, S, (const PrepDev*)d_prep, m0, (const MatDev<mreal>*)d_mats, d_mat_id,
-                           d_orient, (mreal*)d_geo, (real*)d_fbt, (const double*)d_gt, (int*)d_err);
+                           d_orient, (mreal*)d_geo, (real*)d_fbt, (const double*)d_gt, opt.d_node_A,
+                           (unsigned long long*)d_vmaxb, (int*)d_err);
     }
     for (int m = 0; m < n_media; ++m) {
         const ali_medium& md = media[m];
@@ -616,8 +658,9 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
                                dim3(B), 0, S, (const FieldDev*)d_fields, F.medium_first_field[m], md.grid.h,
                                (const MatDev<mreal>*)d_mats + dev_mat_off[m],
                                tab ? (const double*)d_gt + (size_t)VT_N * dev_mat_off[m] : (const double*)nullptr,
-                               md.n_mats, d_mat_id + md.node_offset,
-                               d_orient + md.node_offset, opt.src_box_radius, d_T, (uint32_t*)d_flags);
+                               md.n_mats, d_mat_id + md.node_offset, d_orient + md.node_offset,
+                               opt.d_node_A ? opt.d_node_A + 4 * md.node_offset : (const float*)nullptr,
+                               opt.src_box_radius, d_T, (uint32_t*)d_flags);
     }
     if (d_fixmask)
         hipLaunchKernelGGL(k_seed_flags, dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
@@ -625,10 +668,29 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     HIPCK(H, hipGetLastError());
 
     int h_err = 0;
+    std::vector<unsigned long long> hvb(opt.d_node_A ? n_media : 0);
     HIPCK(H, hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, S));
+    if (opt.d_node_A)
+        HIPCK(H, hipMemcpyAsync(hvb.data(), d_vmaxb, sizeof(unsigned long long) * n_media, hipMemcpyDeviceToHost, S));
     HIPCK(H, hipStreamSynchronize(S));
     if (h_err & 1) return H->fail(ALI_EINVAL, "orientation contains NaN or Inf");
     if (h_err & 2) return H->fail(ALI_EINVAL, "material id out of range");
+    if (h_err & 4) return H->fail(ALI_EINVAL, "per-node stiffness: a node is not finite and positive definite");
+    if (opt.d_node_A) {
+        // the band steps from the nodes' own largest phase speed
+        for (int m = 0; m < n_media; ++m) {
+            double v;
+            memcpy(&v, &hvb[m], sizeof(double));
+            F.vmax[m] = v;
+            const real band = opt.band_cells > 0 ? (real)(opt.band_cells * media[m].grid.h / v) : dinf_host<real>();
+            for (int f = F.medium_first_field[m]; f < F.medium_first_field[m + 1]; ++f) {
+                hstep[f] = band;
+                htheta[f] = band;
+            }
+        }
+    }
+    HIPCK(H, hipMemcpyAsync(d_theta, htheta.data(), sizeof(real) * n_fields, hipMemcpyHostToDevice, S));
+    HIPCK(H, hipMemcpyAsync(d_step, hstep.data(), sizeof(real) * n_fields, hipMemcpyHostToDevice, S));
 
     // passes are queued in batches without host round trips; each batch ends with one
     // read of the idle flag (set by a relax launch that found an empty pass list: from
