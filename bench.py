@@ -46,10 +46,11 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector
 # HBM traffic of the relaxation kernel from two rocprofv3 --pmc runs (FETCH_SIZE, then
 # WRITE_SIZE; each scaled by the same counter on a 256 MiB device copy in the same
 # program), per launch of the 64-field weld forward (grid 8192 x 64; the counters are split
-# by grid size), for the kernel sources with this hash.  Reported as null once the
-# sources differ.
-TRAFFIC = {"sources_sha256_16": "179528ff1e8bda8c", "fetch_bytes_per_launch": 22.89e6,
-           "write_bytes_per_launch": 1.559e6}
+# by grid size), for the kernel sources with this hash, and the wave-level VALU instructions
+# of the same launches (rocprofv3 --pmc SQ_INSTS_VALU).  Reported as null once the sources
+# differ.
+TRAFFIC = {"sources_sha256_16": "e3f4d3e186980e0f", "fetch_bytes_per_launch": 22.88e6,
+           "write_bytes_per_launch": 1.559e6, "valu_wave_insts_per_launch": 5.822e6}
 
 
 def kernel_sources_hash():
@@ -96,16 +97,19 @@ def relax_roofline(solver, call):
     sec = f["relax_ms"] * 1e-3
     gbs = BYTES_PER_UPDATE * f["node_updates"] / sec / 1e9
     tflops = (OPS_PER_UPDATE * f["node_updates"] + OPS_PER_ESTIMATE * f["stencil_evals"]) / sec / 1e12
-    traffic = None
+    traffic = valu = None
     if TRAFFIC["sources_sha256_16"] == kernel_sources_hash():
         traffic = TRAFFIC["fetch_bytes_per_launch"] + TRAFFIC["write_bytes_per_launch"]
+        # per node update, in wave instructions (each covers 64 lanes)
+        valu = TRAFFIC["valu_wave_insts_per_launch"] / (f["node_updates"] / launches)
     return {"kernel": "k_relax<double,float>", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "bytes_per_update": BYTES_PER_UPDATE, "avg_launch_ms": f["relax_ms"] / launches,
             "updates_per_launch": f["node_updates"] / launches,
             "alu": {"achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": tflops / FP32_VECTOR_PEAK_TFLOPS}}
+                    "frac": tflops / FP32_VECTOR_PEAK_TFLOPS},
+            "valu_wave_insts_per_update": valu}
 
 
 def main():
