@@ -80,3 +80,16 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_options_defaults_and_node_stiffness_checks():
+    # host logic only: the defaults carry no per-node stiffness, and the binding refuses a
+    # tensor that is not a float32 device tensor of 4 values per node before any call
+    import torch
+    from paper_2302_10988_amd import default_options
+    o = default_options()
+    assert o.d_node_A is None and o.wave == 0 and o.velocity == 0
+    with pytest.raises(ValueError):
+        default_options(node_A=torch.zeros((4, 5, 4), dtype=torch.float32))       # host memory
+    with pytest.raises(ValueError):
+        default_options(node_A=[1.0, 2.0, 3.0, 4.0])
