@@ -77,9 +77,10 @@ typedef struct {
                                 stiffness gradient), nodes in the order of d_mat_id (for a batch,
                                 the media's nodes concatenated as there).  Each node needs finite
                                 A11, A33, A55 > 0 and A11 A33 > A13^2, else ALI_EINVAL after the
-                                device check.  The qP forward solves (single medium and batch) and
-                                the adjoint and misfit gradients take it; ray tracing, the nested
-                                source grids, SH and the velocity table return ALI_EUNSUPPORTED.
+                                device check.  The qP forward solves (single medium, batch, nested
+                                source grids and subgrid: fine nodes take the nearest node's) and
+                                the adjoint and misfit gradients take it; ray tracing, SH and the
+                                velocity table return ALI_EUNSUPPORTED.
                                 The material table and ids must still be valid; they are then not
                                 read for the speeds.                                           */
 } ali_options;

@@ -232,7 +232,7 @@ class Solver:
         s_arr, ns = _nodes(sources)
         g = _lib.Grid(int(nx), int(nz), float(h))
         opt = default_options(max_sweeps=max_sweeps, inner_sweeps=inner_sweeps, band_cells=band_cells,
-                              arith=_lib.ARITH[arith], **extra)
+                              arith=_lib.ARITH[arith], _n_nodes=int(nx) * int(nz), **extra)
         levels = [tuple(v) for v in levels]
         if len(levels) > _lib.MAX_LEVELS:
             raise ValueError("at most %d levels" % _lib.MAX_LEVELS)

@@ -60,8 +60,8 @@ __device__ __forceinline__ int near_div(int a, int d) {
 
 template <typename oreal>
 __global__ void k_level_medium(const LevelDev* __restrict__ lv, int nx_w, const uint8_t* __restrict__ mat_w,
-                               const oreal* __restrict__ ori_w, uint8_t* __restrict__ mat_l,
-                               oreal* __restrict__ ori_l) {
+                               const oreal* __restrict__ ori_w, const float* __restrict__ A_w,
+                               uint8_t* __restrict__ mat_l, oreal* __restrict__ ori_l, float* __restrict__ A_l) {
     const LevelDev L = lv[blockIdx.y];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= (int64_t)L.nx * L.nz) return;
@@ -69,6 +69,8 @@ __global__ void k_level_medium(const LevelDev* __restrict__ lv, int nx_w, const 
     const int64_t p = (int64_t)(L.sj + near_div(b, L.d)) * nx_w + (L.si + near_div(a, L.d));
     mat_l[L.node_off + q] = mat_w[p];
     ori_l[L.node_off + q] = ori_w[p];
+    if (A_w)
+        for (int k = 0; k < 4; ++k) A_l[4 * (L.node_off + q) + k] = A_w[4 * p + k];
 }
 
 __device__ __forceinline__ void set_fixed(uint32_t* __restrict__ fixmask, const LevelDev& L, int i, int j) {
@@ -81,8 +83,8 @@ __device__ __forceinline__ void set_fixed(uint32_t* __restrict__ fixmask, const 
 template <typename real, typename oreal>
 __global__ void k_seed_start(const LevelDev* __restrict__ lv, int nx_w, double h_w, double half,
                              const MatA* __restrict__ A, const double* __restrict__ gt, int n_mats,
-                             const uint8_t* __restrict__ mat_w,
-                             const oreal* __restrict__ ori_w, real* __restrict__ T, uint32_t* __restrict__ fixmask) {
+                             const uint8_t* __restrict__ mat_w, const oreal* __restrict__ ori_w,
+                             const float* __restrict__ A_w, real* __restrict__ T, uint32_t* __restrict__ fixmask) {
     const LevelDev L = lv[blockIdx.y];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= (int64_t)L.nx * L.nz) return;
@@ -97,7 +99,10 @@ __global__ void k_seed_start(const LevelDev* __restrict__ lv, int nx_w, double h
             const double phi = atan2((double)b, (double)a) - (double)ori_w[ps];
             // an id outside the table is reported by the solve's own check; read a valid entry
             const int mid = mat_w[ps] < n_mats ? mat_w[ps] : 0;
-            const double V = gt ? group_speed_tab(gt + mid * VT_N, phi) : group_speed(A[mid], phi);
+            const MatA As = A_w ? MatA{(double)A_w[4 * ps], (double)A_w[4 * ps + 1], (double)A_w[4 * ps + 2],
+                                       (double)A_w[4 * ps + 3]}
+                                : A[mid];
+            const double V = gt ? group_speed_tab(gt + mid * VT_N, phi) : group_speed(As, phi);
             t = sqrt((double)a * a + (double)b * b) * (h_w / L.d) / V;
         }
         v = (real)t;
@@ -156,14 +161,16 @@ __global__ void k_level_stop(const LevelDev* __restrict__ lv, const real* __rest
 // (nearest a / s, nearest b / s)
 template <typename oreal>
 __global__ void k_subgrid_medium(int nx, int nx_s, int64_t n_s, int s, const uint8_t* __restrict__ mat,
-                                 const oreal* __restrict__ ori, uint8_t* __restrict__ mat_s,
-                                 oreal* __restrict__ ori_s) {
+                                 const oreal* __restrict__ ori, const float* __restrict__ A,
+                                 uint8_t* __restrict__ mat_s, oreal* __restrict__ ori_s, float* __restrict__ A_s) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n_s) return;
     const int a = (int)(q % nx_s), b = (int)(q / nx_s);
     const int64_t p = (int64_t)near_div(b, s) * nx + near_div(a, s);
     mat_s[q] = mat[p];
     ori_s[q] = ori[p];
+    if (A)
+        for (int k = 0; k < 4; ++k) A_s[4 * q + k] = A[4 * p + k];
 }
 
 // the fields at the working nodes: node (i, j) of field k is node (s i, s j) of the s-fold
@@ -312,7 +319,9 @@ static ali_status levels_impl(ali_handle* H, const ali_grid* grid, const ali_mat
             units = (int64_t)ntx * ntz * n_src;
         }
         const std::string pp = std::to_string(l & 1);
-        void *d_lv = nullptr, *d_T = nullptr, *d_mid = nullptr, *d_ori = nullptr;
+        void *d_lv = nullptr, *d_T = nullptr, *d_mid = nullptr, *d_ori = nullptr, *d_nA = nullptr;
+        // per-node stiffness: the level grids take the nearest node's, as the material
+        ali_options lopt = opt;
         if (!H->scratch(("ref_lv" + pp).c_str(), sizeof(LevelDev) * n_src, &d_lv) ||
             !H->scratch("ref_fm", sizeof(uint32_t) * NODE_WORDS * units, &d_fm))
             return H->fail(ALI_ENOMEM, "device scratch allocation failed");
@@ -329,25 +338,26 @@ static ali_status levels_impl(ali_handle* H, const ali_grid* grid, const ali_mat
         const dim3 g2((unsigned)((maxn + B - 1) / B), (unsigned)n_src);
         if (!last) {
             if (!H->scratch(("ref_mid" + pp).c_str(), nodes, &d_mid) ||
-                !H->scratch(("ref_ori" + pp).c_str(), sizeof(oreal) * nodes, &d_ori))
+                !H->scratch(("ref_ori" + pp).c_str(), sizeof(oreal) * nodes, &d_ori) ||
+                (opt.d_node_A && !H->scratch(("ref_nA" + pp).c_str(), sizeof(float) * 4 * nodes, &d_nA)))
                 return H->fail(ALI_ENOMEM, "device scratch allocation failed");
             hipLaunchKernelGGL((k_level_medium<oreal>), g2, dim3(B), 0, S, (const LevelDev*)d_lv, grid->nx, d_mat_id,
-                               d_orient, (uint8_t*)d_mid, (oreal*)d_ori);
+                               d_orient, opt.d_node_A, (uint8_t*)d_mid, (oreal*)d_ori, (float*)d_nA);
+            lopt.d_node_A = (const float*)d_nA;
             mid = (const uint8_t*)d_mid;
             ori = (const oreal*)d_ori;
         }
         if (l == 0)
             hipLaunchKernelGGL((k_seed_start<real, oreal>), g2, dim3(B), 0, S, (const LevelDev*)d_lv, grid->nx,
                                grid->h, ref.start_half_width, (const MatA*)d_A, (const double*)d_gt, n_mats,
-                               d_mat_id, d_orient, T,
-                               (uint32_t*)d_fm);
+                               d_mat_id, d_orient, opt.d_node_A, T, (uint32_t*)d_fm);
         else
             hipLaunchKernelGGL((k_seed_transfer<real>), g2, dim3(B), 0, S, dprev, Tprev, (const real*)d_stop,
                                (const LevelDev*)d_lv, T, (uint32_t*)d_fm);
         HIPCK(H, hipGetLastError());
         ali_solve_stats ls{};
         st = solve_fields<real, mreal, oreal>(H, media.data(), (int32_t)media.size(), mats, n_mats, mid, ori,
-                                              lsrc.data(), nullptr, opt, T, &ls, nullptr, (const uint32_t*)d_fm);
+                                              lsrc.data(), nullptr, lopt, T, &ls, nullptr, (const uint32_t*)d_fm);
         if (st != ALI_OK && st != ALI_ENOCONV) return st;
         add_stats(acc, ls);
         if (!last) {
@@ -385,8 +395,6 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     ali_refine ref;
     ali_default_refine(&ref);
     if (ref_in) ref = *ref_in;
-    if (opt.d_node_A)
-        return H->fail(ALI_EUNSUPPORTED, "the nested source grids take the material table, not per-node stiffness");
     const int s = ref.subgrid;
     if (s == 0 || s == 1)
         return levels_impl<real, mreal, oreal, outreal>(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt,
@@ -413,15 +421,19 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     hipStream_t S = H->stream;
     const int B = 256;
     const int64_t NS = nxs * nzs, NW = (int64_t)grid->nx * grid->nz;
-    void *d_mid = nullptr, *d_ori = nullptr, *d_Ts = nullptr;
+    void *d_mid = nullptr, *d_ori = nullptr, *d_Ts = nullptr, *d_nA = nullptr;
     if (!H->scratch("sub_mid", NS, &d_mid) || !H->scratch("sub_ori", sizeof(oreal) * NS, &d_ori) ||
-        !H->scratch("sub_T", sizeof(real) * NS * n_src, &d_Ts))
+        !H->scratch("sub_T", sizeof(real) * NS * n_src, &d_Ts) ||
+        (opt.d_node_A && !H->scratch("sub_nA", sizeof(float) * 4 * NS, &d_nA)))
         return H->fail(ALI_ENOMEM, "device scratch allocation failed");
     hipLaunchKernelGGL((k_subgrid_medium<oreal>), dim3((unsigned)((NS + B - 1) / B)), dim3(B), 0, S, grid->nx,
-                       gs.nx, NS, s, d_mat_id, d_orient, (uint8_t*)d_mid, (oreal*)d_ori);
+                       gs.nx, NS, s, d_mat_id, d_orient, opt.d_node_A, (uint8_t*)d_mid, (oreal*)d_ori,
+                       (float*)d_nA);
     HIPCK(H, hipGetLastError());
+    ali_options sopt = opt;
+    sopt.d_node_A = (const float*)d_nA;
     st = levels_impl<real, mreal, oreal, real>(H, &gs, mats, n_mats, (const uint8_t*)d_mid, (const oreal*)d_ori,
-                                               ss.data(), n_src, opt, ref, (real*)d_Ts, stats, t0);
+                                               ss.data(), n_src, sopt, ref, (real*)d_Ts, stats, t0);
     if (st != ALI_OK && st != ALI_ENOCONV) return st;
     const int64_t n_out = NW * n_src;
     hipLaunchKernelGGL((k_subgrid_pick<outreal, real>), dim3((unsigned)((n_out + B - 1) / B)), dim3(B), 0, S,

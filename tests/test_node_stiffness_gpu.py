@@ -7,8 +7,10 @@ the material table) on the GPU, through the C ABI.
     float64 fields within 1e-12 of the oracle (which takes one material per stiffness),
     mixed within 1e-4; the orientation and stiffness gradients within 1e-9 of their
     largest entry (all nodes anisotropic, so no mirror ties);
-  - ray tracing, the nested source grids, SH and the velocity table refuse it; a node that
-    is not positive definite, and a tensor of the wrong size, are errors.
+  - the nested source grids and the subgrid take it too (fine nodes take the nearest
+    node's): equal to the table path bit for bit, and within 1e-12 of the oracle;
+  - ray tracing, SH and the velocity table refuse it; a node that is not positive
+    definite, and a tensor of the wrong size, are errors.
 """
 import numpy as np
 import pytest
@@ -147,8 +149,6 @@ def test_node_stiffness_refusals(solver):
         with pytest.raises(AliError):
             solver.solve(m.h, m.mats, mid, ori, m.sources, node_A=nodeA, **kw)
     with pytest.raises(AliError):
-        solver.solve_refined(m.h, m.mats, mid, ori, m.sources, node_A=nodeA)
-    with pytest.raises(AliError):
         solver.trace_rays(m.h, m.mats, mid, ori, T, m.sources, [(19, 17)], node_A=nodeA)
     bad = A.copy()
     bad[5, 7, 3] = -1.0                      # A55 < 0
@@ -160,3 +160,36 @@ def test_node_stiffness_refusals(solver):
         solver.solve(m.h, m.mats, mid, ori, m.sources, node_A=torch.from_numpy(bad).cuda())
     with pytest.raises(ValueError):
         solver.solve(m.h, m.mats, mid, ori, m.sources, node_A=nodeA[:10])
+
+
+def test_node_stiffness_nested_grids(solver, orc):
+    import torch
+    # the same stiffness per node and through the table: equal, with and without a subgrid
+    m = sm.random_medium(40, 34, 0.2e-3, seed=6, n_mats=3)
+    A = np.stack([_a_of(x) for x in m.mats]).astype(np.float32)
+    mats = [_mat_of(a) for a in A]
+    mid, ori = torch.from_numpy(m.mat_id).cuda(), torch.from_numpy(m.orient).cuda()
+    nodeA = torch.from_numpy(np.ascontiguousarray(A[m.mat_id])).cuda()
+    sources = [m.sources[0], (0, 0), (39, 33)]
+    print("per-node stiffness: nested grids 40 x 34", flush=True)
+    for s in (1, 3):
+        Rt, _ = solver.solve_refined(m.h, mats, mid, ori, sources, precision="f64", subgrid=s)
+        Rn, st = solver.solve_refined(m.h, mats, mid, ori, sources, precision="f64", subgrid=s, node_A=nodeA)
+        assert st["converged"] == 1 and torch.equal(Rt, Rn), s
+    # every node its own stiffness: the oracle's nested grids with one material per node
+    rng = np.random.default_rng(5)
+    A = _random_stiffness(rng, 256)
+    ids = np.arange(256, dtype=np.uint8).reshape(16, 16)
+    mm = sm.random_medium(16, 16, 0.2e-3, seed=5)
+    mats_or = [_mat_of(a) for a in A]
+    nodeA = torch.from_numpy(np.ascontiguousarray(A[ids])).cuda()
+    zeros = torch.zeros((16, 16), dtype=torch.uint8, device="cuda")
+    src = [(8, 8), (0, 3)]
+    R64, st = solver.solve_refined(mm.h, [sm.PARENT_STEEL], zeros, torch.from_numpy(mm.orient).cuda(), src,
+                                   precision="f64", node_A=nodeA)
+    assert st["converged"] == 1
+    for k, sn in enumerate(src):
+        ref = orc.solve_refined(mm.h, mats_or, ids, mm.orient, sn)
+        e = _rel(R64[k].cpu().numpy(), ref)
+        print("  source %s: f64 %.3g" % (sn, e), flush=True)
+        assert e <= 1e-12
