@@ -49,7 +49,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector
 # by grid size), for the kernel sources with this hash, and the wave-level VALU instructions
 # of the same launches (rocprofv3 --pmc SQ_INSTS_VALU).  Reported as null once the sources
 # differ.
-TRAFFIC = {"sources_sha256_16": "e3f4d3e186980e0f", "fetch_bytes_per_launch": 22.88e6,
+TRAFFIC = {"sources_sha256_16": "d4e0470f7521208c", "fetch_bytes_per_launch": 22.88e6,
            "write_bytes_per_launch": 1.559e6, "valu_wave_insts_per_launch": 5.822e6}
 
 
