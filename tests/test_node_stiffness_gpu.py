@@ -193,3 +193,42 @@ def test_node_stiffness_nested_grids(solver, orc):
         e = _rel(R64[k].cpu().numpy(), ref)
         print("  source %s: f64 %.3g" % (sn, e), flush=True)
         assert e <= 1e-12
+
+
+def test_stiffness_inversion_step_lowers_the_misfit(solver, orc):
+    # the use the per-node input is for: observations from the oracle on a true model with
+    # 256 stiffnesses scattered over the nodes, a uniform starting model, one step along
+    # -dL/dA (largest change 0.3 % of the stiffness) through per-node values; the misfit
+    # falls by the first-order prediction step |dL/dA|^2 within 10 % (the oracle's own
+    # gradient and fields give 0.980 of it on this case)
+    import torch
+    n, h = 16, 0.3e-3
+    rng = np.random.default_rng(9)
+    A_true = _random_stiffness(rng, 256)
+    ids = rng.integers(0, 256, size=(n, n)).astype(np.uint8)
+    orient = sm.f32(np.full((n, n), 0.4))
+    sources = [(2, 0), (8, 0), (13, 0)]
+    receivers = [(1, n - 1), (6, n - 1), (10, n - 1), (14, n - 1), (n - 1, 8), (0, 8)]
+    mats_true = [_mat_of(a) for a in A_true]
+    obs = np.array([[orc.solve_fmm(h, mats_true, ids, orient, s, 2)[r[1], r[0]] for r in receivers]
+                    for s in sources])
+    zeros = torch.zeros((n, n), dtype=torch.uint8, device="cuda")
+    ori = torch.from_numpy(orient).cuda()
+    A0 = np.tile(_a_of(sm.TI_STEEL).astype(np.float32), (n, n, 1))
+    dobs = torch.from_numpy(obs).cuda()
+
+    def misfit(A, grad=False):
+        out = solver.misfit_gradient(h, [sm.PARENT_STEEL], zeros, ori, sources, receivers, dobs, precision="f64",
+                                     stiffness=grad, node_A=torch.from_numpy(np.ascontiguousarray(A)).cuda())
+        return float(out[0].item()), out[2]
+
+    print("inversion step: 16 x 16, 256 true stiffnesses", flush=True)
+    L0, (_, dA) = misfit(A0, grad=True)
+    g = dA.cpu().numpy()
+    step = 0.003 * np.abs(A0).max() / np.abs(g).max()
+    A1 = (A0 - step * g).astype(np.float32)
+    L1, _ = misfit(A1)
+    pred = -step * float((g * g).sum())
+    print("  loss %.4e -> %.4e (predicted change %.3e, got %.3e)" % (L0, L1, pred, L1 - L0), flush=True)
+    assert L1 < L0
+    assert abs((L1 - L0) - pred) <= 0.1 * abs(pred)
