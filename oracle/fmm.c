@@ -198,7 +198,7 @@ void or_source_box(int nx, int nz, double h, const or_material* mats, const uint
 }
 
 /* ---- Section 2: heap Fast Marching -------------------------------------------------- */
-static int64_t g_phi_evals = 0;     /* evaluations of Phi_D in the last or_solve_fmm call */
+static _Thread_local int64_t g_phi_evals = 0;   /* evaluations of Phi_D in this thread's last or_solve_fmm call */
 int64_t or_last_phi_evals(void) { return g_phi_evals; }
 
 typedef struct { double t; int64_t idx; int64_t ver; } hent;

@@ -445,11 +445,25 @@ class Solver:
         self._check(st)
         return loss, trec, grad, stats.as_dict()
 
-    def autotune_batch(self, batch, arith="mixed", **opts):
+    def autotune_batch(self, batch, arith="mixed", cache_file=None, **opts):
         """Time the forward batch solve under each candidate schedule and return (the
-        fastest options as a dict, {(band_cells, inner_sweeps): ms})."""
+        fastest options as a dict, {(band_cells, inner_sweeps): ms}, cached).  The handle
+        keeps the choice per size bucket (a second call with a batch of the same bucket
+        times nothing); cache_file (JSON, optional) keeps it across processes under the
+        same bucket key.  cached is True when no candidate was timed."""
+        import json
+        import os
         import torch
         opt = default_options(arith=_lib.ARITH[arith], _n_nodes=batch.mat_id.numel(), **opts)
+        key = tune_bucket(batch, opt)
+        if cache_file and os.path.exists(cache_file):
+            with open(cache_file) as fh:
+                hit = json.load(fh).get(key)
+            if hit is not None:
+                for k, v in hit["choice"].items():
+                    setattr(opt, k, int(v))
+                best = {k: getattr(opt, k) for k, _ in opt._fields_}
+                return best, {tuple(c): ms for c, ms in hit["ms"]}, True
         out = torch.empty(batch.field_nodes, dtype=torch.float32, device=batch.mat_id.device)
         ms = (ctypes.c_double * len(_lib.TUNE_CANDIDATES))()
         self._sync_stream()
@@ -459,14 +473,40 @@ class Solver:
                                           ctypes.byref(opt), _dev_ptr(out, torch.float32), ms)
         self._check(st)
         best = {k: getattr(opt, k) for k, _ in opt._fields_}
-        return best, {c: ms[k] for k, c in enumerate(_lib.TUNE_CANDIDATES)}
+        times = {c: ms[k] for k, c in enumerate(_lib.TUNE_CANDIDATES)}
+        if cache_file:
+            data = {}
+            if os.path.exists(cache_file):
+                with open(cache_file) as fh:
+                    data = json.load(fh)
+            data[key] = {"choice": {k: best[k] for k in _lib.TUNE_KNOBS},
+                         "ms": [[list(c), v] for c, v in times.items()]}
+            tmp = cache_file + ".tmp%d" % os.getpid()
+            with open(tmp, "w") as fh:
+                json.dump(data, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache_file)
+        return best, times, False
 
 
-def receiver_times(solver, h, mats, mat_id, orient, sources, receivers, **opts):
-    """Travel times [n_src, n_rec] (float32) at the receivers as a differentiable function
-    of the orientation [nz, nx] (float32 device tensor).  The backward pass runs the
-    adjoint kernels (the forward fields are solved again inside it, not stored)."""
-    return _ReceiverTimes.apply(orient, solver, h, mats, mat_id, tuple(map(tuple, sources)),
+def tune_bucket(batch, opt):
+    """Size bucket of a batch for the schedule cache: powers of two of the field count, the
+    largest side and the node-fields, with the arithmetic, wave and speed mode."""
+    def p2(v):
+        return max(int(v) - 1, 0).bit_length()
+    side = max(max(nz, nx) for nz, nx in batch.shapes)
+    return "v%d:f%d:s%d:n%d:a%d:w%d:v%d:A%d" % (_lib.TUNE_VERSION, p2(batch.n_fields), p2(side),
+                                               p2(batch.field_nodes), opt.arith, opt.wave, opt.velocity,
+                                               1 if opt.d_node_A else 0)
+
+
+def receiver_times(solver, h, mats, mat_id, orient, sources, receivers, node_A=None, **opts):
+    """Travel times [n_src, n_rec] at the receivers as a differentiable function of the
+    orientation [nz, nx] (float32 device tensor; float64 solves in float64 throughout) and,
+    when given, of the per-node stiffness node_A [nz, nx, 4] (float32 device tensor of
+    A11, A13, A33, A55 = C / rho of every node, in place of the material table).  The
+    backward pass runs the adjoint kernels (the forward fields are solved again inside it,
+    not stored) and returns dL/dtheta and, when node_A requires a gradient, dL/dA."""
+    return _ReceiverTimes.apply(orient, node_A, solver, h, mats, mat_id, tuple(map(tuple, sources)),
                                 tuple(map(tuple, receivers)), opts)
 
 
@@ -481,21 +521,32 @@ def _autograd():
 
     class ReceiverTimes(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, orient, solver, h, mats, mat_id, sources, receivers, opts):
-            T, _ = solver.solve(h, mats, mat_id, orient, sources, **opts)
+        def forward(ctx, orient, node_A, solver, h, mats, mat_id, sources, receivers, opts):
+            prec = "f64" if orient.dtype == torch.float64 else "f32"
+            kw = dict(opts)
+            if node_A is not None:
+                kw["node_A"] = node_A.detach()
+            T, _ = solver.solve(h, mats, mat_id, orient.detach(), sources, precision=prec, **kw)
             rows = torch.tensor([r[1] for r in receivers], device=T.device)
             cols = torch.tensor([r[0] for r in receivers], device=T.device)
-            ctx.save_for_backward(orient)
-            ctx.args = (solver, h, mats, mat_id, sources, receivers, opts)
+            ctx.save_for_backward(orient, node_A)
+            ctx.args = (solver, h, mats, mat_id, sources, receivers, kw, prec)
             return T[:, rows, cols].contiguous()
 
         @staticmethod
         def backward(ctx, grad):
-            (orient,) = ctx.saved_tensors
-            solver, h, mats, mat_id, sources, receivers, opts = ctx.args
-            dth, _ = solver.adjoint(h, mats, mat_id, orient, sources, receivers,
-                                    grad.to(torch.float32).contiguous(), **opts)
-            return dth, None, None, None, None, None, None, None
+            orient, node_A = ctx.saved_tensors
+            solver, h, mats, mat_id, sources, receivers, kw, prec = ctx.args
+            want_A = node_A is not None and ctx.needs_input_grad[1]
+            g = grad.to(orient.dtype).contiguous()
+            res, _ = solver.adjoint(h, mats, mat_id, orient.detach(), sources, receivers, g, precision=prec,
+                                    stiffness=want_A, **kw)
+            if want_A:
+                dth, dA = res
+                dA = dA.to(node_A.dtype).view(node_A.shape)
+            else:
+                dth, dA = res, None
+            return dth, dA, None, None, None, None, None, None, None
 
     class Bilinear(torch.autograd.Function):
         @staticmethod

@@ -54,6 +54,8 @@ WAVE = {"qp": 0, "sh": 1}
 RAY_PLANES = {"changing": 0, "x": 1, "z": 2, "diag": 3, "anti": 4, "fastest": 5}
 VELOCITY = {"christoffel": 0, "table": 1}
 TUNE_CANDIDATES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4), (3, 4)]   # (band_cells, inner_sweeps)
+TUNE_KNOBS = ("band_cells", "inner_sweeps")       # the options the autotuner chooses
+TUNE_VERSION = 1                                  # bumped when the candidates or the kernels change
 
 
 class SolveStats(ctypes.Structure):

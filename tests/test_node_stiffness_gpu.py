@@ -232,3 +232,46 @@ def test_stiffness_inversion_step_lowers_the_misfit(solver, orc):
     print("  loss %.4e -> %.4e (predicted change %.3e, got %.3e)" % (L0, L1, pred, L1 - L0), flush=True)
     assert L1 < L0
     assert abs((L1 - L0) - pred) <= 0.1 * abs(pred)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_autograd_stiffness(solver, prec):
+    # receiver_times with node_A as a differentiable input: for a loss linear in the
+    # receiver times, dL/dT is the weight tensor itself, so the autograd gradients must be
+    # bitwise those of the adjoint entry point called with the same weights; a quadratic
+    # misfit must match the fused misfit call to the rounding of the residuals.
+    import torch
+    from paper_2302_10988_amd import receiver_times
+    m = sm.random_medium(64, 48, 0.2e-3, seed=6, n_mats=3)
+    rng = np.random.default_rng(6)
+    A = _random_stiffness(rng, m.nx * m.nz).reshape(m.nz, m.nx, 4)
+    mats = [_mat_of(a) for a in _random_stiffness(rng, 3)]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    mid = torch.from_numpy(m.mat_id).cuda()
+    ori = torch.from_numpy(m.orient).to(dt).cuda().requires_grad_(True)
+    nodeA = torch.from_numpy(A).cuda().requires_grad_(True)
+    sources = [m.sources[0], (2, 1), (60, 3)]
+    receivers = [(63, 47), (0, 47), (30, 47), (10, 20)]
+    W = torch.from_numpy(rng.normal(size=(3, 4))).to(dt).cuda()
+    print("autograd stiffness:", prec, flush=True)
+    Tr = receiver_times(solver, m.h, mats, mid, ori, sources, receivers, node_A=nodeA)
+    assert Tr.dtype == dt
+    (Tr * W).sum().backward()
+    (dth, dA), _ = solver.adjoint(m.h, mats, mid, ori.detach(), sources, receivers, W.contiguous(),
+                                  precision=prec, stiffness=True, node_A=nodeA.detach())
+    assert torch.equal(ori.grad, dth)
+    assert nodeA.grad.dtype == torch.float32 and nodeA.grad.shape == nodeA.shape
+    assert torch.equal(nodeA.grad, dA.to(torch.float32))
+    # quadratic misfit against the fused forward + adjoint call
+    ori.grad = None
+    nodeA.grad = None
+    obs = torch.full((3, 4), 3e-6, dtype=dt, device="cuda")
+    Tr = receiver_times(solver, m.h, mats, mid, ori, sources, receivers, node_A=nodeA)
+    (0.5 * ((Tr.double() - obs.double()) ** 2).sum()).backward()
+    _, _, (dth2, dA2), _ = solver.misfit_gradient(m.h, mats, mid, ori.detach(), sources, receivers, obs,
+                                                   precision=prec, stiffness=True, node_A=nodeA.detach())
+    tol = 1e-5 if prec == "f32" else 1e-12
+    gd = (ori.grad - dth2).abs().max().item() / dth2.abs().max().item()
+    ga = (nodeA.grad.double() - dA2.double()).abs().max().item() / dA2.abs().max().item()
+    print("  vs fused misfit: dtheta %.3g, dA %.3g" % (gd, ga), flush=True)
+    assert gd <= tol and ga <= max(tol, 1e-6)
