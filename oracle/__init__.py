@@ -24,10 +24,12 @@ _lib = None
 
 class Material(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("c11", "c13", "c33", "c55", "c44", "c66", "rho")] + \
-               [("wave", ctypes.c_int32), ("vtab", ctypes.c_int32)]
+               [("wave", ctypes.c_int32), ("vtab", ctypes.c_int32), ("grule", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 WAVE_QP, WAVE_SH = 0, 1
+GROUP_EXACT, GROUP_PAPER = 0, 1
 
 
 def as_sh(mats):
@@ -39,6 +41,28 @@ def as_table(mats):
     """The same materials with the paper's velocity table (speeds at whole degrees,
     linearly interpolated) in place of the run-time Christoffel speeds."""
     return [dict(m, vtab=1) for m in mats]
+
+
+def with_paper_group(mats):
+    """The same materials with the group speed of Section 3.2's run-time inversion (the
+    phase angle whose polarisation points along the group direction) for every straight
+    ray: a second reading of the paper's group speed, used only to test which rule the
+    printed errors of Table 3 follow."""
+    return [dict(m, grule=GROUP_PAPER) for m in mats]
+
+
+VAR_MIN_UPDATE, VAR_UNIT_SQUARES_FIRST, VAR_TRIANGLE_LITERAL, VAR_NO_CAUSALITY = 1, 2, 4, 8
+
+
+def set_reading_variant(v):
+    """Switch this thread's oracle calls to alternative readings (VAR_* bits; 0 = the
+    oracle's own readings).  Only for measuring which readings reproduce Table 3."""
+    _load().or_set_reading_variant(int(v))
+
+
+def qp_group_speed_paper(mat, phi):
+    """Section 3.2's approximate qP group speed along group angle phi (from the c22 axis)."""
+    return _load().or_qp_group_speed_paper(_mat_array([mat]), float(phi))
 
 
 def build(force: bool = False) -> str:
@@ -71,6 +95,10 @@ def _load():
     lib.or_qp_group_from_phase.argtypes = [M, D, ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.or_qp_group_speed.argtypes = [M, D]
     lib.or_qp_group_speed.restype = D
+    lib.or_set_reading_variant.argtypes = [I]
+    lib.or_set_reading_variant.restype = None
+    lib.or_qp_group_speed_paper.argtypes = [M, D]
+    lib.or_qp_group_speed_paper.restype = D
     lib.or_qp_group_speed_support.argtypes = [M, D]
     lib.or_qp_group_speed_support.restype = D
     lib.or_stencil_offsets.argtypes = [I, ctypes.POINTER(I)]
@@ -130,14 +158,17 @@ def _mat_array(mats):
             vals = [m[n] for n in ("c11", "c13", "c33", "c55", "c44", "c66", "rho")]
             wave = int(m.get("wave", WAVE_QP))
             vtab = int(m.get("vtab", 0))
+            grule = int(m.get("grule", GROUP_EXACT))
         else:
             vals = list(m)[:7]
             wave = int(list(m)[7]) if len(list(m)) > 7 else WAVE_QP
             vtab = int(list(m)[8]) if len(list(m)) > 8 else 0
+            grule = GROUP_EXACT
         for n, v in zip(("c11", "c13", "c33", "c55", "c44", "c66", "rho"), vals):
             setattr(arr[k], n, float(v))
         arr[k].wave = wave
         arr[k].vtab = vtab
+        arr[k].grule = grule
     return arr
 
 

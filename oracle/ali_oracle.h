@@ -41,7 +41,25 @@ typedef struct {
     double c11, c13, c33, c55, c44, c66, rho;
     int32_t wave;
     int32_t vtab;
+    int32_t grule;      /* group speed of the straight rays: OR_GROUP_EXACT, or OR_GROUP_PAPER
+                           for the paper's run-time inversion (Section 3.2), a second reading
+                           used only to test which rule the printed errors of Table 3 follow */
+    int32_t pad;
 } or_material;
+
+enum { OR_GROUP_EXACT = 0, OR_GROUP_PAPER = 1 };
+
+/* Alternative readings of the update and the choice, switched on per thread only by the
+   test that measures which readings reproduce the printed errors of Table 3:
+     MIN_UPDATE           a close node keeps the smaller of its old and new estimates (the
+                          usual Fast Marching rule) instead of being recomputed;
+     UNIT_SQUARES_FIRST   the side-1 squares rank before the side-sqrt(2) squares;
+     TRIANGLE_LITERAL     the first member of a triangular pair is scored with its own B and
+                          C in the second member's formula;
+     NO_CAUSALITY         a stencil estimate need not exceed tau_C. */
+enum { OR_VAR_MIN_UPDATE = 1, OR_VAR_UNIT_SQUARES_FIRST = 2, OR_VAR_TRIANGLE_LITERAL = 4,
+       OR_VAR_NO_CAUSALITY = 8 };
+void or_set_reading_variant(int v);
 
 /* ---- Section 3: velocities ------------------------------------------------------- */
 
@@ -63,6 +81,15 @@ double or_qp_group_speed_deriv(const or_material* m, double phi);
 /* qP group speed [m/s] along group angle phi [rad] from the c22 axis, by inverting the
    phase->group angle map with bisection (exact to rounding). */
 double or_qp_group_speed(const or_material* m, double phi);
+
+/* The qP group speed as Section 3.2 computes it at run time: the phase angle is the one
+   whose qP polarisation points along the group angle phi (the eigenvector condition
+   (M - lambda I) X = 0 with X along phi, solved through tan of the phase angle), the
+   eigenvalue lambda gives the phase speed v, and the group speed is v / cos(theta - phi).
+   Polarisation and group directions differ in a generally anisotropic medium, so this is
+   an approximation (up to 0.43 % faster than the exact group speed for the paper's cubic
+   steel); it is never used unless a material asks for it (grule). */
+double or_qp_group_speed_paper(const or_material* m, double phi);
 
 /* Same quantity by a second, independent route: the support function of the slowness
    curve, 1/V(phi) = max_psi cos(phi - psi) / v(psi). */

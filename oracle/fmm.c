@@ -108,13 +108,19 @@ static int in_grid(const ctx_t* c, int i, int j) {
     return i >= 0 && j >= 0 && i < c->nx && j < c->nz;
 }
 
+/* Alternative readings of Sections 2 and 4.3, for the test that measures which readings
+   reproduce the printed errors of Table 3 (never set otherwise; 0 = the readings the
+   oracle stands for).  Per thread. */
+static _Thread_local int g_variant = 0;
+void or_set_reading_variant(int v) { g_variant = v; }
+
 /* known12: bit k set <=> the k-th diamond neighbour is in the known set K. */
 static double phi_core(const ctx_t* c, int i, int j, unsigned known12, int* choice) {
     const double r2m1 = sqrt(2.0) - 1.0, two_mr2 = 2.0 - sqrt(2.0);
     int idx = j * c->nx + i;
     const or_material* m = &c->mats[c->mat_id[idx]];
     double th = c->orient[idx];
-    int best = -1, best_cls = 3;
+    int best = -1, best_cls = 4;
     double best_score = 0.0, best_U = INFINITY;
     for (int s = 0; s < 32; ++s) {
         const int* o = STENCIL[s];
@@ -125,13 +131,17 @@ static double phi_core(const ctx_t* c, int i, int j, unsigned known12, int* choi
         double ta = c->T[ja * c->nx + ia], tb = c->T[jb * c->nx + ib], tc = c->T[jc * c->nx + ic];
         if (!(ta < tb && tb <= tc)) continue;                 /* ordering, Section 4.1 */
         double U = or_stencil_estimate(m, th, c->h, o, ta, tb, tc);
-        if (!(U > tc)) continue;                              /* causality (R1) */
+        if (!(g_variant & OR_VAR_NO_CAUSALITY) && !(U > tc)) continue;   /* causality (R1) */
         int cls = s < 16 ? 0 : 1;
+        if ((g_variant & OR_VAR_UNIT_SQUARES_FIRST) && cls == 1) cls = 2;
+        if ((g_variant & OR_VAR_UNIT_SQUARES_FIRST) && s >= 8 && s < 16) cls = 1;
         double score;
-        if (cls == 0) {
+        if (s < 16) {
             score = tc - tb;                                  /* squares: tau_C - tau_B */
         } else if (s & 1) {
             /* second member of a triangular pair: tau_B closest to the isosceles value */
+            score = fabs(tb - (r2m1 * ta + two_mr2 * tc));
+        } else if (g_variant & OR_VAR_TRIANGLE_LITERAL) {
             score = fabs(tb - (r2m1 * ta + two_mr2 * tc));
         } else {
             /* first member: same calculation with B and C swapped */
@@ -290,6 +300,7 @@ static int64_t fmm_core(int nx, int nz, double h, const or_material* mats, const
             if (known[d] || fixed[d]) continue;
             double u = phi_core(&c, di, dj, known12_from_grid(&c, known, di, dj), NULL);
             ++g_phi_evals;
+            if ((g_variant & OR_VAR_MIN_UPDATE) && !(u < T[d])) continue;
             if (u != T[d]) {                                  /* R4: recompute */
                 T[d] = u;
                 ++ver[d];

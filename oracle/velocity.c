@@ -233,11 +233,31 @@ double or_sh_group_speed_deriv(const or_material* m, double phi) {
     return -0.5 * V * V * V * dinv2;
 }
 
+double or_qp_group_speed_paper(const or_material* m, double phi) {
+    /* c22, c33, c23, c44 of the paper's YZ plane are c11, c33, c13, c55 of the axis frame */
+    const double c22 = m->c11, c33 = m->c33, c23 = m->c13, c44 = m->c55;
+    const double a = reduce_quadrant(phi);
+    if (a == 0.0) return sqrt(c22 / m->rho);              /* group = phase on the axes */
+    if (a == 0.5 * M_PI) return sqrt(c33 / m->rho);
+    /* delta cos 2th + eta sin 2th + kappa = 0 with y = tan th:
+       y^2 (kappa - delta) + 2 eta y + (delta + kappa) = 0, the root of the qP mode for a
+       group angle in (0, 90) degrees */
+    const double delta = c22 + c33 - 2.0 * c44;
+    const double eta = (c23 + c44) * (tan(a) - 1.0 / tan(a));
+    const double kappa = c22 - c33;
+    const double y = (-eta - sqrt(eta * eta + delta * delta - kappa * kappa)) / (kappa - delta);
+    double th = fmod(atan(y), M_PI);
+    if (th < 0.0) th += M_PI;
+    const double lam = 0.5 * (cos(2.0 * th) * (c22 - c44) + sin(2.0 * th) * (c23 + c44) * tan(a) + (c22 + c44));
+    return sqrt(lam / m->rho) / cos(th - a);
+}
+
 static double exact_phase_speed(const or_material* m, double th_p) {
     return m->wave == OR_WAVE_SH ? or_sh_phase_speed(m, th_p) : or_qp_phase_speed(m, th_p);
 }
 static double exact_group_speed(const or_material* m, double phi) {
-    return m->wave == OR_WAVE_SH ? or_sh_group_speed(m, phi) : or_qp_group_speed(m, phi);
+    if (m->wave == OR_WAVE_SH) return or_sh_group_speed(m, phi);
+    return m->grule == OR_GROUP_PAPER ? or_qp_group_speed_paper(m, phi) : or_qp_group_speed(m, phi);
 }
 
 /* the velocity table: f at whole degrees of the angle, linear in between (f is pi-periodic) */
