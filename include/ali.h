@@ -187,6 +187,26 @@ ali_status ali_solve_traveltime_f64(ali_handle* h, const ali_grid* grid,
                                     const ali_options* opt, double* d_T,
                                     ali_solve_stats* stats);
 
+/* Allocation-free variant of ali_solve_traveltime, for callers that cannot allocate device
+   memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+   allocation.  Same arguments, computation, options, output and errors; every scratch
+   buffer is carved from one static device array of ALI_NOALLOC_SCRATCH_BYTES per device
+   (file scope in the library, held until the process ends), so the call makes no
+   hipMalloc or hipFree and calls no allocating library routine.  Passes are launched one
+   by one (opt->graph is ignored).  In the default mixed arithmetic a solve needs about
+   64 B per node plus 9 B per node and source (a 512 x 512 medium takes up to 21 sources);
+   a larger one returns ALI_EINVAL before any device work, with the needed size in
+   ali_last_error.  Every call on a device shares that device's array and it keeps the
+   last call's contents (each call clears what must start at zero): calls that overlap on
+   one device (two handles, threads or streams) race and must be serialised by the caller. */
+#define ALI_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ali_status ali_solve_traveltime_noalloc(ali_handle* h, const ali_grid* grid,
+                                        const ali_material* mats, int32_t n_mats,
+                                        const uint8_t* d_mat_id, const float* d_orient,
+                                        const ali_node* srcs, int32_t n_src,
+                                        const ali_options* opt, float* d_T,
+                                        ali_solve_stats* stats);
+
 /* ---- nested fine grids around the source (paper Section 4.4) ------------------------- */
 
 #define ALI_MAX_LEVELS 8

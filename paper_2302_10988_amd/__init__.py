@@ -176,7 +176,7 @@ class Solver:
 
     def solve(self, h, mats, mat_id, orient, sources, out=None, precision="f32",
               src_box_radius=None, max_sweeps=None, inner_sweeps=None, band_cells=None,
-              arith="mixed", **extra):
+              arith="mixed", noalloc=False, **extra):
         """Travel-time fields [n_src, nz, nx] for point sources in one medium.
 
         h: grid spacing [m]; mats: list of stiffness records (dicts with c11, c13, c33,
@@ -187,7 +187,9 @@ class Solver:
         name (wave="sh" for the shear wave polarised normal to the plane, velocity="table" for
         the paper's velocity table; node_A=[nz, nx, 4] float32 device tensor of every node's
         A11, A13, A33, A55 = C / rho in place of the material table, also taken by adjoint,
-        misfit_gradient and the batch calls).  Returns (T, stats dict)."""
+        misfit_gradient and the batch calls); noalloc=True (float32 only) calls the
+        allocation-free entry point, whose scratch is a static device array (pass `out`
+        to allocate nothing at all).  Returns (T, stats dict)."""
         import torch
         nz, nx = mat_id.shape
         fdt = torch.float32 if precision == "f32" else torch.float64
@@ -204,7 +206,10 @@ class Solver:
         p_T = _dev_ptr(out, fdt, (ns, nz, nx), "out")
         stats = _lib.SolveStats()
         self._sync_stream()
-        fn = self._lib.ali_solve_traveltime if precision == "f32" else self._lib.ali_solve_traveltime_f64
+        if noalloc and precision != "f32":
+            raise ValueError("the allocation-free entry point is float32 only")
+        fn = (self._lib.ali_solve_traveltime_noalloc if noalloc else self._lib.ali_solve_traveltime) \
+            if precision == "f32" else self._lib.ali_solve_traveltime_f64
         st = fn(self._h, ctypes.byref(g), m_arr, nm, p_id, p_or, s_arr, ns, ctypes.byref(opt),
                 p_T, ctypes.byref(stats))
         self._check(st)

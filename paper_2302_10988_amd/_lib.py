@@ -101,6 +101,9 @@ SIGNATURES = {
     "ali_solve_traveltime": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32,
                                             _P, _P, ctypes.POINTER(Node), _I32,
                                             ctypes.POINTER(Options), _P, ctypes.POINTER(SolveStats)]),
+    "ali_solve_traveltime_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32,
+                                                    _P, _P, ctypes.POINTER(Node), _I32,
+                                                    ctypes.POINTER(Options), _P, ctypes.POINTER(SolveStats)]),
     "ali_solve_traveltime_f64": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32,
                                                 _P, _P, ctypes.POINTER(Node), _I32,
                                                 ctypes.POINTER(Options), _P, ctypes.POINTER(SolveStats)]),

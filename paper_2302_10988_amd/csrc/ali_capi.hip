@@ -44,6 +44,12 @@ extern "C" ali_status ali_create(ali_handle** out, int device, void* hip_stream)
             ali_destroy(h);
             return ALI_EDEVICE;
         }
+    // the device's static scratch array (allocation-free entry point); a failed lookup
+    // leaves it unset, and only that entry point then reports the error
+    if (ali::static_scratch_address(device, &h->static_base, &h->static_bytes) != hipSuccess) {
+        h->static_base = nullptr;
+        h->static_bytes = 0;
+    }
     *out = h;
     return ALI_OK;
 }

@@ -31,13 +31,36 @@ struct ali_handle {
     std::string err;
     struct Buf { void* p = nullptr; size_t bytes = 0; };
     std::map<std::string, Buf> bufs;
+    // the device's static scratch array (address of the library's file-scope device array
+    // on this handle's device, looked up once per device at create), and the carve-up of
+    // it during an allocation-free call (arena != 0)
+    void* static_base = nullptr;
+    size_t static_bytes = 0;
+    bool arena = false;
+    size_t arena_used = 0;
+    std::map<std::string, std::pair<size_t, size_t>> arena_slots;   // name -> (offset, bytes)
 
     ali_status fail(ali_status s, const std::string& msg) {
         err = msg;
         return s;
     }
-    // device buffer `name` of at least `bytes`; contents are not preserved on growth
+    // device buffer `name` of at least `bytes`; contents are not preserved on growth.
+    // During an allocation-free call the buffer is carved from the static array instead
+    // (256-byte aligned, never hipMalloc); false if it does not fit.
     bool scratch(const char* name, size_t bytes, void** out) {
+        if (arena) {
+            auto it = arena_slots.find(name);
+            if (it != arena_slots.end() && it->second.second >= bytes) {
+                *out = (char*)static_base + it->second.first;
+                return true;
+            }
+            const size_t off = (arena_used + 255) & ~(size_t)255;
+            if (!static_base || off > static_bytes || bytes > static_bytes - off) return false;
+            arena_slots[name] = std::make_pair(off, bytes);
+            arena_used = off + bytes;
+            *out = (char*)static_base + off;
+            return true;
+        }
         Buf& b = bufs[name];
         if (b.bytes < bytes) {
             if (b.p) (void)hipFree(b.p);
@@ -62,6 +85,11 @@ struct ali_handle {
 namespace ali {
 
 constexpr int PASS_BATCH = ALI_PASS_BATCH;
+
+// Device address and size of the static scratch array of the allocation-free entry point
+// on `device` (which must be current).  The address is looked up once per device and kept
+// for the life of the process.
+hipError_t static_scratch_address(int device, void** ptr, size_t* bytes);
 
 // Enqueue `enqueue(b)` for b = 0 .. PASS_BATCH-1 on the handle's stream as one captured
 // graph, instantiated once per signature `key` (every argument the kernels receive) and

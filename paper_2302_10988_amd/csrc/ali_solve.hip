@@ -25,6 +25,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <string>
@@ -850,7 +851,71 @@ static ali_status solve_impl(ali_handle* H, const ali_medium* media, int32_t n_m
     return st;
 }
 
+// ---------------------------------------------------------------------------------------
+// allocation-free forward solve: every scratch buffer comes from one static device array
+// ---------------------------------------------------------------------------------------
+// Bytes the arena hands out for one single-medium forward solve: every scratch() request of
+// solve_impl and solve_fields, in request order, each at a 256-byte aligned offset.
+template <typename real, typename mreal>
+static size_t forward_scratch_bytes(const ali_grid& g, int n_src, int n_mats, bool table) {
+    const int64_t nodes = (int64_t)g.nx * g.nz;
+    const int64_t units = (int64_t)((g.nx + TX - 1) / TX) * ((g.nz + TZ - 1) / TZ) * n_src;
+    std::vector<size_t> req;
+    if (!std::is_same<real, float>::value) req.push_back(sizeof(real) * nodes * n_src);   // Twork
+    req.push_back(sizeof(MatDev<mreal>) * n_mats);                 // mats
+    req.push_back(sizeof(FieldDev) * n_src);                       // fields
+    req.push_back(sizeof(real) * n_src);                           // theta
+    req.push_back(sizeof(real) * n_src);                           // step
+    req.push_back(sizeof(real) * units);                           // minrej
+    req.push_back(sizeof(mreal) * GEO_N * nodes);                  // geo
+    req.push_back(sizeof(real) * 4 * nodes);                       // fbt
+    req.push_back(sizeof(uint32_t) * units);                       // flags
+    req.push_back(sizeof(PassItem) * units);                       // list
+    req.push_back(sizeof(uint32_t) * 2 * NODE_WORDS * units);      // marks
+    req.push_back(2 * sizeof(uint32_t));                           // count
+    req.push_back(sizeof(uint32_t));                               // idle
+    req.push_back((4 + 2 * STAT_SLOTS) * sizeof(unsigned long long));   // upd
+    req.push_back(sizeof(int));                                    // err
+    if (table) {
+        req.push_back(sizeof(MatA) * n_mats);                      // vt_A
+        req.push_back(sizeof(double) * n_mats);                    // vt_ih
+        req.push_back(sizeof(mreal) * VT_N * n_mats);              // vt
+        req.push_back(sizeof(double) * VT_N * n_mats);             // gt
+    }
+    req.push_back(sizeof(PrepDev));                                // prep
+    req.push_back(sizeof(unsigned long long));                     // vmaxb
+    size_t used = 0;
+    for (size_t b : req) used = ((used + 255) & ~(size_t)255) + b;
+    return used;
+}
+
 }  // namespace ali
+
+// The static scratch array: file scope, one copy per device, held until the process ends.
+// Host code never passes its name to a kernel or a copy (in host code the name stands for a
+// host-side shadow, not a device address); it uses the address hipGetSymbolAddress returns
+// on each device.
+static __device__ __align__(256) unsigned char scratch[ALI_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_SCRATCH_DEVICES] = {};
+}  // namespace
+
+hipError_t ali::static_scratch_address(int device, void** ptr, size_t* bytes) {
+    if (device < 0 || device >= MAX_SCRATCH_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    *bytes = ALI_NOALLOC_SCRATCH_BYTES;
+    return hipSuccess;
+}
 
 using namespace ali;
 
@@ -900,6 +965,43 @@ extern "C" ali_status ali_solve_batch(ali_handle* h, const ali_medium* media, in
                                       float* d_T, ali_solve_stats* stats) {
     if (!h) return ALI_EINVAL;
     return solve_dispatch<float, float>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, opt, d_T, stats);
+}
+
+extern "C" ali_status ali_solve_traveltime_noalloc(ali_handle* h, const ali_grid* grid,
+                                                   const ali_material* mats, int32_t n_mats,
+                                                   const uint8_t* d_mat_id, const float* d_orient,
+                                                   const ali_node* srcs, int32_t n_src,
+                                                   const ali_options* opt, float* d_T,
+                                                   ali_solve_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    if (!grid) return h->fail(ALI_EINVAL, "grid is NULL");
+    ali_options o;
+    ali_default_options(&o);
+    if (opt) o = *opt;
+    o.graph = 0;          // instantiating a graph may allocate
+    const ali_medium md = single_medium(grid, n_mats, n_src, 0);
+    ali_status st = validate_batch(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, nullptr, o.wave);
+    if (st != ALI_OK) return st;
+    if (!h->static_base) return h->fail(ALI_EDEVICE, "the static scratch array is not available on this device");
+    const bool table = o.velocity == ALI_VEL_TABLE;
+    size_t need = 0;
+    switch (o.arith) {
+        case ALI_ARITH_MIXED: need = forward_scratch_bytes<double, float>(*grid, n_src, n_mats, table); break;
+        case ALI_ARITH_F32: need = forward_scratch_bytes<float, float>(*grid, n_src, n_mats, table); break;
+        case ALI_ARITH_F64: need = forward_scratch_bytes<double, double>(*grid, n_src, n_mats, table); break;
+        default: return h->fail(ALI_EINVAL, "unknown arith mode");
+    }
+    if (need > h->static_bytes)
+        return h->fail(ALI_EINVAL, "this solve needs " + std::to_string(need) + " bytes of device scratch; the "
+                       "allocation-free entry point has " + std::to_string(h->static_bytes) +
+                       " (ALI_NOALLOC_SCRATCH_BYTES): use ali_solve_traveltime");
+    h->arena = true;
+    h->arena_used = 0;
+    h->arena_slots.clear();
+    st = solve_dispatch<float, float>(h, &md, 1, mats, n_mats, d_mat_id, d_orient, srcs, &o, d_T, stats);
+    h->arena = false;
+    if (st == ALI_ENOMEM) h->err = "the static scratch array was too small for this solve: " + h->err;
+    return st;
 }
 
 // candidate schedules of the autotuner: (band_cells, inner_sweeps)
