@@ -326,14 +326,15 @@ def main():
     t_tune = time.perf_counter()
     tuned, tune_ms, cached = solver.autotune_batch(batch, cache_file=None if args.retune else TUNE_CACHE)
     t_tune = time.perf_counter() - t_tune
-    sched = {k: tuned[k] for k in ("band_cells", "inner_sweeps")}
+    from paper_2302_10988_amd import _lib
+    sched = {k: tuned[k] for k in _lib.TUNE_KNOBS}
     sides = [md.nx for md in media]
     line["config"] = {"workload": "%d media, square sides %d..%d (seed 3), h=0.1 mm, 32 top sources x 32 bottom "
                                   "receivers each: batched forward + adjoint of the per-medium misfit"
                                   % (len(media), min(sides), max(sides)),
                       "fields_per_step": n_fields, "node_fields": batch.field_nodes, "src_box_radius": 2,
                       "schedule": sched, "schedule_from_cache": cached, "autotune_s": t_tune,
-                      "autotune_ms": {"band%d_inner%d" % k: v for k, v in tune_ms.items()}}
+                      "autotune_ms": {"band%d_inner%d_visit%d_persistent%d" % k: v for k, v in tune_ms.items()}}
 
     def step():
         t0 = time.perf_counter()

@@ -83,6 +83,19 @@ typedef struct {
                                 velocity table return ALI_EUNSUPPORTED.
                                 The material table and ids must still be valid; they are then not
                                 read for the speeds.                                           */
+    int32_t persistent;      /* 1: every relaxation pass of a forward solve runs in one cooperative
+                                launch (all work-groups resident, grid barriers between the
+                                scheduling and relaxation phases of a pass, every barrier wait
+                                bounded: a wait past 5 s returns ALI_EDEVICE); 0 (default): one
+                                scheduling and one relaxation launch per pass, replayed from
+                                captured graphs.  Both reach the same fields bit for bit.      */
+    int32_t visit_tiles;     /* most tiles one wave visits at once in a pass with more tiles than
+                                resident waves (their marked nodes share 64-lane chunks): 1..4,
+                                0 (default) = 4.  The fields do not depend on it.              */
+    int32_t adjoint_band_cells;    /* band of the adjoint relaxation in node spacings at the fastest
+                                      phase speed; 0 (default) = band_cells                    */
+    int32_t adjoint_inner_sweeps;  /* sweep cap of an adjoint tile visit; 0 (default) =
+                                      inner_sweeps.  The gradient does not depend on either.   */
 } ali_options;
 
 /* Speeds of the solve (Section 3.2).  CHRISTOFFEL: the phase speed of every stencil and the
@@ -116,9 +129,12 @@ enum { ALI_WAVE_QP = 0, ALI_WAVE_SH = 1 };
 
 /* Arithmetic of the float32 entry points.  MIXED keeps travel times, scores and every
    comparison that decides a stencil in float64 and computes each stencil's wavefront /
-   phase-speed increment in float32; F32 does everything in float32 (fastest; stencil
-   choices near ties follow float32 rounding of the stored times); F64 does everything in
-   float64.  Output is float32 in all three. */
+   phase-speed increment in float32 (within a few 1e-7 of the float64 oracle on the
+   straight-ray box; the nested source grids compute MIXED in float64, see
+   ali_solve_traveltime_refined); F32 does everything in float32: fastest, and outside the
+   1e-4 bar (stencil choices near score ties follow the float32 rounding of the stored
+   times: 1.7e-4 on the 512 x 512 weld); F64 does everything in float64.  Output is
+   float32 in all three. */
 enum { ALI_ARITH_MIXED = 0, ALI_ARITH_F32 = 1, ALI_ARITH_F64 = 2 };
 
 typedef struct {
@@ -154,6 +170,10 @@ ali_status ali_create(ali_handle** out, int device, void* hip_stream);
 ali_status ali_destroy(ali_handle* h);
 ali_status ali_set_stream(ali_handle* h, void* hip_stream);
 void ali_default_options(ali_options* opt);
+/* How long a grid barrier of the persistent relaxation (ali_options.persistent) waits for
+   the other work-groups before the call gives up with ALI_EDEVICE (default 5 s; seconds
+   >= 0; a wait is also cut short once any work-group has given up). */
+ali_status ali_set_barrier_timeout(ali_handle* h, double seconds);
 const char* ali_status_string(ali_status s);
 const char* ali_last_error(const ali_handle* h);
 
@@ -240,8 +260,13 @@ void ali_default_refine(ali_refine* r);
    speed inside start_half_width cells; on each level the march runs until it reaches a node
    farther than radius[l] from the source, and the nodes reached strictly earlier seed the
    next coarser grid (the nodes that coincide with them keep their times); the grid itself
-   comes last.  opt->src_box_radius is not used.  Other arguments, arithmetic, errors and
-   output as ali_solve_traveltime; ref == NULL means ali_default_refine.  Scratch grows with
+   comes last.  opt->src_box_radius is not used.  Other arguments, errors and output as
+   ali_solve_traveltime; ref == NULL means ali_default_refine.  Arithmetic: MIXED (the
+   default) computes in float64 here (wavefront math included): with float32 wavefront
+   math a near tie in the score of two square stencils on the fine grids can go the other
+   way and move the nodes behind it by up to 4.5e-4 on the 512 x 512 weld, beyond the
+   1e-4 bar; float64 costs about a fifth more.  F32 (everything in float32) is faster and
+   outside the 1e-4 bar.  Scratch grows with
    the fine grids (about 23k nodes per source by default).  With ref->subgrid = s > 1 the
    grid above is the s-fold grid (spacing h / s, sources at s i, s j) and the output holds
    every s-th node of its fields; the scratch adds that grid's medium and fields (n_src
@@ -273,12 +298,16 @@ ali_status ali_solve_batch(ali_handle* h, const ali_medium* media, int32_t n_med
                            float* d_T, ali_solve_stats* stats);
 
 /* Schedule autotuner: times the forward batch solve (the fields go to d_T, [field nodes]
-   float32, device) under each of ALI_TUNE_CANDIDATES (band_cells, inner_sweeps) settings
-   -- (1,1) (1,2) (1,4) (2,2) (2,4) (3,4) -- and writes the fastest into *opt (the other
-   fields of *opt are kept and used for every run).  ms_out (host, nullable) receives the
-   time of each candidate.  Every candidate reaches the same fields (the fixed point does
-   not depend on the schedule); only the time differs.  Synchronises the stream. */
-#define ALI_TUNE_CANDIDATES 6
+   float32, device) under each of ALI_TUNE_CANDIDATES schedules (band_cells, inner_sweeps,
+   visit_tiles, persistent) -- (1,2,4,0) (1,2,2,0) (1,2,1,0) (1,4,4,0) (2,2,4,0) (2,4,4,0)
+   (1,2,4,1) -- and writes the fastest into *opt (the other fields of *opt are kept and used
+   for every run).  ms_out (host, nullable) receives the time of each candidate.  Every
+   candidate reaches the same fields (the fixed point does not depend on the schedule);
+   only the time differs.  The handle keeps the choice per size bucket (powers of two of
+   the field count, the largest side and the node-fields, with the arithmetic, wave, speed
+   mode and per-node stiffness): a later call for a batch of the same bucket times nothing
+   and returns the kept choice and times.  Synchronises the stream. */
+#define ALI_TUNE_CANDIDATES 7
 ali_status ali_autotune_batch(ali_handle* h, const ali_medium* media, int32_t n_media,
                               const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
                               const float* d_orient, const ali_node* srcs, ali_options* opt,

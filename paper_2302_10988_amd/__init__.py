@@ -166,6 +166,10 @@ class Solver:
         except Exception:
             pass
 
+    def set_barrier_timeout(self, seconds):
+        """Wait limit of the persistent relaxation's grid barriers (default 5 s)."""
+        self._check(self._lib.ali_set_barrier_timeout(self._h, float(seconds)))
+
     def _sync_stream(self):
         import torch
         self._lib.ali_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
@@ -452,7 +456,8 @@ class Solver:
 
     def autotune_batch(self, batch, arith="mixed", cache_file=None, **opts):
         """Time the forward batch solve under each candidate schedule and return (the
-        fastest options as a dict, {(band_cells, inner_sweeps): ms}, cached).  The handle
+        fastest options as a dict, {(band_cells, inner_sweeps, visit_tiles, persistent): ms},
+        cached).  The handle
         keeps the choice per size bucket (a second call with a batch of the same bucket
         times nothing); cache_file (JSON, optional) keeps it across processes under the
         same bucket key.  cached is True when no candidate was timed."""

@@ -38,7 +38,8 @@ class Options(ctypes.Structure):
                 ("ray_window", ctypes.c_int32), ("ray_max_pts", ctypes.c_int32),
                 ("arith", ctypes.c_int32), ("ray_sub", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("wave", ctypes.c_int32), ("ray_planes", ctypes.c_int32), ("velocity", ctypes.c_int32),
-                ("d_node_A", ctypes.c_void_p)]
+                ("d_node_A", ctypes.c_void_p), ("persistent", ctypes.c_int32), ("visit_tiles", ctypes.c_int32),
+                ("adjoint_band_cells", ctypes.c_int32), ("adjoint_inner_sweeps", ctypes.c_int32)]
 
 MAX_LEVELS = 8
 
@@ -53,9 +54,10 @@ ARITH = {"mixed": 0, "f32": 1, "f64": 2}
 WAVE = {"qp": 0, "sh": 1}
 RAY_PLANES = {"changing": 0, "x": 1, "z": 2, "diag": 3, "anti": 4, "fastest": 5}
 VELOCITY = {"christoffel": 0, "table": 1}
-TUNE_CANDIDATES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4), (3, 4)]   # (band_cells, inner_sweeps)
-TUNE_KNOBS = ("band_cells", "inner_sweeps")       # the options the autotuner chooses
-TUNE_VERSION = 1                                  # bumped when the candidates or the kernels change
+# the autotuner's candidates, in the order of ali_autotune_batch's ms_out
+TUNE_KNOBS = ("band_cells", "inner_sweeps", "visit_tiles", "persistent")
+TUNE_CANDIDATES = [(1, 2, 4, 0), (1, 2, 2, 0), (1, 2, 1, 0), (1, 4, 4, 0), (2, 2, 4, 0), (2, 4, 4, 0), (1, 2, 4, 1)]
+TUNE_VERSION = 2                                  # bumped when the candidates or the kernels change
 
 
 class SolveStats(ctypes.Structure):
@@ -87,6 +89,7 @@ SIGNATURES = {
     "ali_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P]),
     "ali_destroy": (ctypes.c_int, [_P]),
     "ali_set_stream": (ctypes.c_int, [_P, _P]),
+    "ali_set_barrier_timeout": (ctypes.c_int, [_P, ctypes.c_double]),
     "ali_default_options": (None, [ctypes.POINTER(Options)]),
     "ali_default_refine": (None, [ctypes.POINTER(Refine)]),
     "ali_solve_traveltime_refined": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32,

@@ -295,7 +295,8 @@ __global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
 k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W,
             const double* __restrict__ G, const double* __restrict__ T, const double* __restrict__ theta,
             double* __restrict__ lam, uint8_t* __restrict__ pend, double* __restrict__ maxdef,
-            uint32_t* __restrict__ flags, uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
+            uint32_t* __restrict__ flags, uint32_t* __restrict__ gflag, double* __restrict__ gkey,
+            uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
             const uint32_t* __restrict__ count, uint32_t* __restrict__ idle, int inner,
             unsigned long long* __restrict__ counters) {
     __shared__ double ll[LH * LSTRIDE];
@@ -502,12 +503,14 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
             const int o = q / NODE_WORDS;
             const int64_t u2 = (int64_t)unit + (int64_t)(o / 3 - 1) * ntx + (o % 3 - 1);
             atomicOr(&marks_out[u2 * NODE_WORDS + q % NODE_WORDS], w);
-            atomicOr(&flags[u2], TF_MARK);
+            flag_tile(flags, gflag, unit - (uint32_t)(tz * ntx + tx), pi.group_off,
+                      (tz + o / 3 - 1) * ntx + (tx + o % 3 - 1), TF_MARK);
         }
     }
     if (lane == 0) {
         if (my_updates) atomicAdd(&counters[4 + 2 * (blockIdx.x % STAT_SLOTS)], (unsigned long long)my_updates);
         maxdef[unit] = dk;
+        if (gkey && dk > -dinf<double>()) key_max(&gkey[pi.group_off + (uint32_t)((tz * ntx + tx) / GROUP)], dk);
     }
     __syncthreads();
     }
@@ -517,9 +520,12 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
 // tile keys are the largest pending times (the relaxation rewrites them).
 __global__ void __launch_bounds__(SCHED_T)
 k_adj_sched(const FieldDev* __restrict__ fields, int advance, const double* __restrict__ step,
-            uint32_t* __restrict__ flags, double* __restrict__ maxdef, double* __restrict__ theta,
-            PassItem* __restrict__ list, uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next) {
-    schedule_field<true, double>(fields, advance, step, flags, maxdef, theta, list, cnt_cur, cnt_next);
+            uint32_t* __restrict__ flags, double* __restrict__ maxdef, uint32_t* __restrict__ gflag,
+            double* __restrict__ gkey, double* __restrict__ theta, PassItem* __restrict__ list,
+            uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next, int direct_tiles) {
+    __shared__ uint32_t s_due[SCHED_SPAN];
+    schedule_field<true, double, SCHED_T>(blockIdx.x, fields, advance, step, flags, maxdef, gflag, gkey, theta, list,
+                                          cnt_cur, cnt_next, s_due, direct_tiles);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -533,7 +539,7 @@ template <typename greal, typename outreal>
 __global__ void k_adj_rhs(int mode, int n_fields, const FieldDev* __restrict__ fields, const int2* __restrict__ rec,
                           const greal* __restrict__ in, const double* __restrict__ T, double* __restrict__ G,
                           outreal* __restrict__ trec, double* __restrict__ lossf, uint32_t* __restrict__ flags,
-                          double* __restrict__ theta, int banded) {
+                          uint32_t* __restrict__ gflag, double* __restrict__ theta, int banded) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= n_fields) return;
     const FieldDev fd = fields[f];
@@ -551,7 +557,9 @@ __global__ void k_adj_rhs(int mode, int n_fields, const FieldDev* __restrict__ f
         }
         G[p] += g;
         tmax = T[p] > tmax ? T[p] : tmax;
-        flags[fd.unit_off + (x.y / TZ) * fd.ntx + (x.x / TX)] |= TF_SELF;
+        const int t = (x.y / TZ) * fd.ntx + (x.x / TX);
+        flags[fd.unit_off + t] |= TF_SELF;
+        if (gflag) gflag[fd.group_off + t / GROUP] = 1u;
     }
     if (lossf) lossf[f] = L;
     theta[f] = banded ? tmax : -dinf<double>();
@@ -703,6 +711,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
         return H->fail(ALI_EUNSUPPORTED, "the stiffness gradient is available for the qP wave only");
     if (opt.velocity != ALI_VEL_CHRISTOFFEL)
         return H->fail(ALI_EUNSUPPORTED, "the adjoint differentiates the run-time speeds (velocity table given)");
+    if (opt.adjoint_band_cells < 0 || opt.adjoint_inner_sweeps < 0 || opt.adjoint_inner_sweeps > 4096)
+        return H->fail(ALI_EINVAL, "adjoint_band_cells must be >= 0 and adjoint_inner_sweeps in [0, 4096]");
     if (!d_in) return H->fail(ALI_EINVAL, mode == 1 ? "d_obs is NULL" : "d_dLdT is NULL");
     if (!d_dth) return H->fail(ALI_EINVAL, "d_dLdtheta is NULL");
     int64_t n_fields64 = 0, NF = 0;
@@ -733,6 +743,11 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
 
     void *d_W, *d_wT, *d_lam, *d_G, *d_dacc, *d_box, *d_lossf, *d_rec, *d_first;
     void *d_flags, *d_list, *d_count, *d_cnt, *d_pend, *d_maxdef, *d_theta, *d_step, *d_idle, *d_marks;
+    void *d_gflag, *d_gkey;
+    const int64_t ngroups = fs.n_groups;
+    const int direct_tiles = direct_tiles_for(nunits, SCHED_SPAN);
+    bool use_groups = false;
+    for (const FieldDev& fd : fs.hfields) use_groups |= fd.ntx * fd.ntz > direct_tiles;
     if (!H->scratch("a_w", sizeof(AdjW<mreal>) * NF, &d_W) || !H->scratch("a_wT", sizeof(double) * NF, &d_wT) ||
         !H->scratch("a_lam", sizeof(double) * NF, &d_lam) || !H->scratch("a_G", sizeof(double) * NF, &d_G) ||
         !H->scratch("a_pend", sizeof(uint8_t) * NF, &d_pend) ||
@@ -745,6 +760,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
         !H->scratch("a_rec", sizeof(int2) * n_recv_total, &d_rec) ||
         !H->scratch("a_flags", sizeof(uint32_t) * nunits, &d_flags) ||
         !H->scratch("a_maxdef", sizeof(double) * nunits, &d_maxdef) ||
+        !H->scratch("a_gflag", sizeof(uint32_t) * ngroups, &d_gflag) ||
+        !H->scratch("a_gkey", sizeof(double) * ngroups, &d_gkey) ||
         !H->scratch("a_list", sizeof(PassItem) * nunits, &d_list) ||
         !H->scratch("a_count", 2 * sizeof(uint32_t), &d_count) ||
         !H->scratch("a_idle", sizeof(uint32_t), &d_idle) ||
@@ -758,11 +775,14 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
                  !H->scratch("a_boxA", 4 * sizeof(double) * n_fields, &d_boxa)))
         return H->fail(ALI_ENOMEM, "device scratch allocation failed");
     // descending time band: band_cells node spacings at each medium's fastest phase speed
-    const bool banded = opt.band_cells > 0;
+    // the adjoint's own band and sweep cap (0: those of the forward)
+    const int abands = opt.adjoint_band_cells > 0 ? opt.adjoint_band_cells : opt.band_cells;
+    const int ainner = opt.adjoint_inner_sweeps > 0 ? opt.adjoint_inner_sweeps : opt.inner_sweeps;
+    const bool banded = abands > 0;
     std::vector<double> hstep(n_fields);
     for (int f = 0; f < n_fields; ++f) {
         const int m = fs.hfields[f].medium;
-        hstep[f] = banded ? opt.band_cells * media[m].grid.h / fs.vmax[m] : 0.0;
+        hstep[f] = banded ? abands * media[m].grid.h / fs.vmax[m] : 0.0;
     }
     std::vector<int2> hr(n_recv_total);
     for (int r = 0; r < n_recv_total; ++r) hr[r] = make_int2(recv[r].i, recv[r].j);
@@ -770,6 +790,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     HIPCK(H, hipMemcpyAsync(d_step, hstep.data(), sizeof(double) * n_fields, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemcpyAsync(d_first, fs.medium_first_field.data(), sizeof(int) * (n_media + 1), hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemsetAsync(d_flags, 0, sizeof(uint32_t) * nunits, S));
+    HIPCK(H, hipMemsetAsync(d_gflag, 0, sizeof(uint32_t) * ngroups, S));
     HIPCK(H, hipMemsetAsync(d_marks, 0, sizeof(uint32_t) * 2 * NODE_WORDS * nunits, S));
     HIPCK(H, hipMemsetAsync(d_count, 0, 2 * sizeof(uint32_t), S));
     HIPCK(H, hipMemsetAsync(d_idle, 0, sizeof(uint32_t), S));
@@ -793,9 +814,12 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     hipLaunchKernelGGL((k_fill<uint8_t>), dim3(gNF), dim3(B), 0, S, (uint8_t*)d_pend, NF, (uint8_t)0);
     hipLaunchKernelGGL((k_fill<double>), dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S, (double*)d_maxdef,
                        nunits, -dinf_host<double>());
+    hipLaunchKernelGGL((k_fill<double>), dim3((unsigned)((ngroups + B - 1) / B)), dim3(B), 0, S, (double*)d_gkey,
+                       ngroups, -dinf_host<double>());
     hipLaunchKernelGGL((k_adj_rhs<greal, outreal>), dim3((unsigned)((n_fields + 63) / 64)), dim3(64), 0, S,
                        mode, n_fields, fs.fields, (const int2*)d_rec, d_in, (const double*)T, (double*)d_G, d_trec,
-                       (double*)d_lossf, (uint32_t*)d_flags, (double*)d_theta, banded ? 1 : 0);
+                       (double*)d_lossf, (uint32_t*)d_flags, use_groups ? (uint32_t*)d_gflag : nullptr, (double*)d_theta,
+                       banded ? 1 : 0);
     HIPCK(H, hipGetLastError());
     if (mode == 1 && d_loss)
         hipLaunchKernelGGL(k_adj_loss, dim3((unsigned)((n_media + 63) / 64)), dim3(64), 0, S, (const double*)d_lossf,
@@ -809,16 +833,19 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     uint32_t* cnt = (uint32_t*)d_count;
     auto enqueue = [&](int p, bool timed, hipStream_t S) {
         hipLaunchKernelGGL(k_adj_sched, dim3((unsigned)n_fields), dim3(SCHED_T), 0, S, fs.fields, p > 0 ? 1 : 0,
-                           (const double*)d_step, (uint32_t*)d_flags, (double*)d_maxdef, (double*)d_theta,
-                           (PassItem*)d_list, cnt + (p & 1), cnt + ((p + 1) & 1));
+                           (const double*)d_step, (uint32_t*)d_flags, (double*)d_maxdef, (uint32_t*)d_gflag,
+                           (double*)d_gkey, (double*)d_theta,
+                           (PassItem*)d_list, cnt + (p & 1), cnt + ((p + 1) & 1), direct_tiles);
         uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
         uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);
         hipLaunchKernelGGL(k_adj_relax<mreal>, dim3((unsigned)grid_relax), dim3(RW), 0, S,
                            (const PassItem*)d_list, (const AdjW<mreal>*)d_W,
                            (const double*)d_G, (const double*)T, (const double*)d_theta, (double*)d_lam,
-                           (uint8_t*)d_pend, (double*)d_maxdef, (uint32_t*)d_flags, mk_in, mk_out,
-                           (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle, opt.inner_sweeps,
+                           (uint8_t*)d_pend, (double*)d_maxdef, (uint32_t*)d_flags,
+                           use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (double*)d_gkey : nullptr, mk_in,
+                           mk_out,
+                           (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle, ainner,
                            (unsigned long long*)d_cnt);
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH) + 1], S);
     };
@@ -827,8 +854,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
         const bool graph = opt.graph && batch == PASS_BATCH;
         if (graph) {
             const int first = iters == 0 ? 1 : 0;
-            const std::string key = graph_key("adj", first, (const void*)&k_adj_relax<mreal>, fs.fields, n_fields, d_step, d_flags, d_maxdef, d_theta,
-                                              d_list, d_count, d_marks, nunits, d_W, d_G, T, d_lam, d_pend, d_idle, opt.inner_sweeps, d_cnt, grid_relax);
+            const std::string key = graph_key("adj", first, (const void*)&k_adj_relax<mreal>, fs.fields, n_fields, d_step, d_flags, d_maxdef, d_gflag, d_gkey, use_groups ? 1 : 0, direct_tiles, d_theta,
+                                              d_list, d_count, d_marks, nunits, d_W, d_G, T, d_lam, d_pend, d_idle, ainner, d_cnt, grid_relax);
             HIPCK(H, hipEventRecord(H->ev2, S));
             st = launch_captured(H, key, [&](int b, hipStream_t cs) { enqueue(first ? b : PASS_BATCH + b, false, cs); });
             if (st != ALI_OK) return st;

@@ -19,6 +19,10 @@ extern "C" void ali_default_options(ali_options* o) {
     o->ray_planes = ALI_RAY_CHANGING;
     o->velocity = ALI_VEL_CHRISTOFFEL;
     o->d_node_A = nullptr;
+    o->persistent = 0;
+    o->visit_tiles = 0;
+    o->adjoint_band_cells = 0;
+    o->adjoint_inner_sweeps = 0;
 }
 
 extern "C" ali_status ali_create(ali_handle** out, int device, void* hip_stream) {
@@ -39,6 +43,11 @@ extern "C" ali_status ali_create(ali_handle** out, int device, void* hip_stream)
         ali_destroy(h);
         return ALI_EDEVICE;
     }
+    int wclk_khz = 0;
+    if (hipDeviceGetAttribute(&wclk_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || wclk_khz <= 0)
+        wclk_khz = 100000;
+    h->wall_clock_khz = wclk_khz;
+    h->barrier_timeout_ticks = 5000LL * wclk_khz;
     for (int k = 0; k < 2 * ALI_PASS_BATCH; ++k)
         if (hipEventCreate(&h->pev[k]) != hipSuccess) {
             ali_destroy(h);
@@ -72,6 +81,13 @@ extern "C" ali_status ali_destroy(ali_handle* h) {
         if (h->pev[k]) (void)hipEventDestroy(h->pev[k]);
     if (h->host_count) (void)hipHostFree(h->host_count);
     delete h;
+    return ALI_OK;
+}
+
+extern "C" ali_status ali_set_barrier_timeout(ali_handle* h, double seconds) {
+    if (!h) return ALI_EINVAL;
+    if (!(seconds >= 0.0) || seconds > 3600.0) return h->fail(ALI_EINVAL, "barrier timeout must be in [0, 3600] s");
+    h->barrier_timeout_ticks = (long long)(seconds * 1000.0 * h->wall_clock_khz);
     return ALI_OK;
 }
 

@@ -27,7 +27,11 @@ struct ali_handle {
     uint32_t* host_count = nullptr;           // pinned 4-byte readback slot
     hipEvent_t pev[2 * ALI_PASS_BATCH] = {};  // per-pass timing events of one batch
     int n_cu = 0;                             // compute units of the device
+    long long barrier_timeout_ticks = 0;      // grid-barrier wait limit, ticks of the constant-rate clock
+    int wall_clock_khz = 100000;              // rate of that clock
     std::map<std::string, hipGraphExec_t> graphs;   // captured pass batches by argument signature
+    // autotuner choices by size bucket: candidate index and every candidate's time [ms]
+    std::map<std::string, std::pair<int, std::vector<double>>> tuned;
     std::string err;
     struct Buf { void* p = nullptr; size_t bytes = 0; };
     std::map<std::string, Buf> bufs;

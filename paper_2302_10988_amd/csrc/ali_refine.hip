@@ -465,15 +465,15 @@ extern "C" ali_status ali_solve_traveltime_refined(ali_handle* h, const ali_grid
     if (!h) return ALI_EINVAL;
     const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
     switch (arith) {
+        // float32 wavefront math on the fine grids lets near score ties flip (beyond the
+        // 1e-4 bar on the weld), so the default arithmetic computes them in float64
         case ALI_ARITH_MIXED:
-            return refined_impl<double, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
-                                                             opt, ref, d_T, stats);
-        case ALI_ARITH_F32:
-            return refined_impl<float, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
-                                                            opt, ref, d_T, stats);
         case ALI_ARITH_F64:
             return refined_impl<double, double, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
                                                               opt, ref, d_T, stats);
+        case ALI_ARITH_F32:
+            return refined_impl<float, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
+                                                            opt, ref, d_T, stats);
     }
     return h->fail(ALI_EINVAL, "unknown arith mode");
 }

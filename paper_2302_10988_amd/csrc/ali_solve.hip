@@ -130,7 +130,7 @@ template <typename real, typename mreal, typename oreal>
 __global__ void k_init(const FieldDev* __restrict__ fields, int f0, double h, const MatDev<mreal>* __restrict__ mats,
                        const double* __restrict__ gt, int n_mats, const uint8_t* __restrict__ mat_id,
                        const oreal* __restrict__ orient, const float* __restrict__ nodeA, int R,
-                       real* __restrict__ T, uint32_t* __restrict__ flags) {
+                       real* __restrict__ T, uint32_t* __restrict__ flags, uint32_t* __restrict__ gflag) {
     const FieldDev fd = fields[f0 + blockIdx.y];
     const int nx = fd.nx;
     const int64_t N = (int64_t)nx * fd.nz;
@@ -158,14 +158,18 @@ __global__ void k_init(const FieldDev* __restrict__ fields, int f0, double h, co
     }
     T[fd.t_off + p] = v;
     // tiles that see the box (box radius + diamond radius) start active
-    if (abs(di) <= R + HALO && abs(dj) <= R + HALO)
-        flags[fd.unit_off + (j / TZ) * fd.ntx + (i / TX)] = TF_SELF;   // evaluate the whole tile
+    if (abs(di) <= R + HALO && abs(dj) <= R + HALO) {
+        const int t = (j / TZ) * fd.ntx + (i / TX);
+        flags[fd.unit_off + t] = TF_SELF;   // evaluate the whole tile
+        gflag[fd.group_off + t / GROUP] = 1u;
+    }
 }
 
 // Seeded fields: every tile holding a fixed node, and its 8 neighbours, starts with a
 // visit of all its nodes (a fixed node reaches 2 nodes out, tiles are wider than that).
 __global__ void k_seed_flags(const FieldDev* __restrict__ fields, int n_fields, int64_t n_units,
-                             const uint32_t* __restrict__ fixmask, uint32_t* __restrict__ flags) {
+                             const uint32_t* __restrict__ fixmask, uint32_t* __restrict__ flags,
+                             uint32_t* __restrict__ gflag) {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n_units) return;
     uint32_t any = 0u;
@@ -179,7 +183,7 @@ __global__ void k_seed_flags(const FieldDev* __restrict__ fields, int n_fields, 
         for (int dx = -1; dx <= 1; ++dx) {
             const int x = tx + dx, z = tz + dz;
             if (x < 0 || z < 0 || x >= fd.ntx || z >= fd.ntz) continue;
-            atomicOr(&flags[fd.unit_off + (uint32_t)(z * fd.ntx + x)], (uint32_t)TF_SELF);
+            flag_tile(flags, gflag, fd.unit_off, fd.group_off, z * fd.ntx + x, (uint32_t)TF_SELF);
         }
 }
 
@@ -187,9 +191,12 @@ __global__ void k_seed_flags(const FieldDev* __restrict__ fields, int n_fields, 
 template <typename real>
 __global__ void __launch_bounds__(SCHED_T)
 k_sched(const FieldDev* __restrict__ fields, int advance, uint32_t* __restrict__ flags, real* __restrict__ minrej,
-        real* __restrict__ theta, const real* __restrict__ step, PassItem* __restrict__ list,
-        uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next) {
-    schedule_field<false, real>(fields, advance, step, flags, minrej, theta, list, cnt_cur, cnt_next);
+        uint32_t* __restrict__ gflag, real* __restrict__ gkey, real* __restrict__ theta, const real* __restrict__ step,
+        PassItem* __restrict__ list, uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next,
+        int direct_tiles) {
+    __shared__ uint32_t s_due[SCHED_SPAN];
+    schedule_field<false, real, SCHED_T>(blockIdx.x, fields, advance, step, flags, minrej, gflag, gkey, theta, list,
+                                         cnt_cur, cnt_next, s_due, direct_tiles);
 }
 
 
@@ -202,7 +209,13 @@ __device__ __forceinline__ void lds_min(double* p, double v) {
 }
 
 
-// One tile visit by one wave (64 lanes, NPL nodes per lane; tile + halo staged in LDS).
+// One visit by one wave of up to G_MAX tiles of the pass list at once (64 lanes, NPL
+// nodes per lane and tile; every tile and its halo staged in LDS).  The marked nodes of
+// all the visit's tiles are packed into the same 64-lane chunks, so a wave evaluates
+// full chunks where one tile alone would fill a third of them; the tiles are otherwise
+// independent, exactly as if separate waves visited them (each works on its own copy of
+// its halo).  G, the tiles per visit, is the same for every wave of a pass: enough
+// visits to occupy `slots` waves, at most G_MAX.
 // The nodes to evaluate are tracked per node.  The first sweep takes every node (TF_SELF),
 // the band front (unreached nodes with a reached neighbour: new arrivals and values an
 // earlier band rejected) and the nodes a neighbouring tile marked; each later sweep takes
@@ -211,40 +224,49 @@ __device__ __forceinline__ void lds_min(double* p, double v) {
 // neighbours that precede D's own value in key order, so a neighbour that stays behind D
 // cannot change it.  Across tiles the marks are unconditional (the other tile may be
 // working on an older copy of X) and go to the neighbouring tile's node mask for the next
-// pass.  Each sweep packs the marked nodes into the first lanes.
+// pass.
 // SEEDED: the fixed nodes are the set bits of fixmask (one bit per node of each tile unit,
 // NODE_WORDS words per unit) instead of the source box of radius R.
 // TAB: phase speeds from the per-material tables vtab (offset in geo slot 6).
-template <typename real, typename mreal, bool SEEDED, bool TAB>
-__global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
-k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, const real* __restrict__ fbt_all,
-        int R, int inner, const real* __restrict__ theta,
-        real* __restrict__ T, uint32_t* __restrict__ flags, real* __restrict__ minrej,
-        uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
-        const uint32_t* __restrict__ count, uint32_t* __restrict__ idle,
-        unsigned long long* __restrict__ counters, const uint32_t* __restrict__ fixmask,
-        const mreal* __restrict__ vtab) {
-    __shared__ real lt[LH * LSTRIDE];
-    __shared__ uint8_t dnext[NTHREADS];
-    __shared__ uint16_t clist[NTHREADS];
-    __shared__ uint32_t omask[9][NODE_WORDS];     // marks for the 3x3 tile neighbourhood
-    __shared__ uint32_t touched[NODE_WORDS];      // nodes whose value changed in this visit
+constexpr int G_MAX = 4;
+constexpr int TILE_LDS = LH * LSTRIDE;
 
-    // the first entry is read together with the list length (the grid never exceeds the
-    // list's capacity, so the read is in bounds; the entry is used only if it is live)
-    PassItem pi = list[blockIdx.x];
-    const uint32_t n_units = *count;
-    if (n_units == 0u) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *idle = 1u;
-        return;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        atomicAdd(&counters[2], 1ull);                  // passes with work
-        atomicAdd(&counters[3], (unsigned long long)n_units);   // tile visits
-    }
-    // the work-groups walk the pass list with a grid stride
+// LDS of one relaxation wave
+template <typename real> struct RelaxLds {
+    real lt[G_MAX * TILE_LDS];                // staged tiles and halos
+    uint16_t clist[G_MAX * NTHREADS];         // packed nodes: tile * NTHREADS + node
+    uint32_t dnext[G_MAX][NODE_WORDS];        // nodes marked for the next sweep
+    uint32_t omask[G_MAX][9][NODE_WORDS];     // marks for each tile's 3x3 neighbourhood
+    uint32_t touched[G_MAX][NODE_WORDS];      // nodes whose value changed in this visit
+    PassItem s_item[G_MAX];
+    real s_th[G_MAX], s_rej[G_MAX];
+};
+// a one-tile visit uses the masks of its tile only; its byte-per-node marks for the next
+// sweep live in the neighbourhood masks of the other tiles
+static_assert(sizeof(uint32_t) * (G_MAX - 1) * 9 * NODE_WORDS >= NTHREADS, "room for one-tile sweep marks");
+
+// The tiles of one pass of n_units (> 0) listed tiles visited one at a time by this wave
+// (a grid stride over the list), for passes too small to give every wave several tiles:
+// the list entry lives in scalar registers and the first one may already be loaded (pre,
+// read together with the pass size).  The wave's update and estimate counts are added to
+// my_updates, my_evals.
+template <typename real, typename mreal, bool SEEDED, bool TAB>
+__device__ __forceinline__ void relax_single(RelaxLds<real>& L, uint32_t n_units, const PassItem* pre,
+                                             const PassItem* __restrict__ list, const mreal* __restrict__ geo_all,
+                                             const real* __restrict__ fbt_all, int R, int inner,
+                                             const real* __restrict__ theta, real* __restrict__ T,
+                                             uint32_t* __restrict__ flags, real* __restrict__ minrej,
+                                             uint32_t* __restrict__ gflag, real* __restrict__ gkey,
+                                             uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
+                                             const uint32_t* __restrict__ fixmask, const mreal* __restrict__ vtab,
+                                             unsigned& my_updates, unsigned& my_evals) {
+    real* lt = L.lt;
+    uint8_t* dnext = reinterpret_cast<uint8_t*>(&L.omask[1][0][0]);
+    uint16_t* clist = L.clist;
+    auto& omask = L.omask[0];
+    uint32_t* touched = L.touched[0];
     for (uint32_t item = blockIdx.x; item < n_units; item += gridDim.x) {
-    if (item != blockIdx.x) pi = list[item];
+    const PassItem pi = (pre && item == blockIdx.x) ? *pre : list[item];
     const uint32_t unit = pi.unit;
     const uint32_t bits = pi.bits;
     const int f = pi.f;
@@ -290,8 +312,6 @@ k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, co
     __syncthreads();
 
     // the NPL nodes of this lane: node = lane + 64 q.
-    // Loops over them stay rolled, and nothing per node is kept in registers across the
-    // phases (the write-back finds changed nodes in the LDS change mask).
     unsigned dmask = 0u;              // bit q: node q of this lane is marked for this sweep
     unsigned amask = 0u;              // bit q: node q of this lane is evaluated at all
 #pragma unroll 1
@@ -315,7 +335,6 @@ k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, co
     }
 
     real rej = inf;                   // smallest value this lane's updates rejected
-    unsigned my_updates = 0, my_evals = 0;
     bool done = false;
     for (int it = 0;; ++it) {
         // pack the marked nodes
@@ -419,12 +438,9 @@ k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, co
             any_out = true;
         }
     }
-    // wave-wide reductions
     for (int o = 32; o > 0; o >>= 1) {
         const real r2 = __shfl_xor(rej, o);
         rej = r2 < rej ? r2 : rej;
-        my_updates += __shfl_xor(my_updates, o);
-        my_evals += __shfl_xor(my_evals, o);
     }
     const bool out = __ballot(any_out) != 0ull;
     __syncthreads();
@@ -437,21 +453,424 @@ k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, co
             const int ntx2 = tx + o % 3 - 1, ntz2 = tz + o / 3 - 1;
             const int64_t u2 = (int64_t)unit + (int64_t)(ntz2 - tz) * ntx + (ntx2 - tx);
             atomicOr(&marks_out[u2 * NODE_WORDS + q % NODE_WORDS], w);
-            atomicOr(&flags[u2], TF_MARK);
+            flag_tile(flags, gflag, unit - (uint32_t)(tz * ntx + tx), pi.group_off, ntz2 * ntx + ntx2, TF_MARK);
         }
     }
     if (lane == 0) {
-        // statistics spread over STAT_SLOTS counter pairs (one address for all visits
-        // would serialise every tile visit of a pass)
-        if (my_updates) {
-            unsigned long long* sc = counters + 4 + 2 * (blockIdx.x % STAT_SLOTS);
-            atomicAdd(&sc[0], (unsigned long long)my_updates);
-            atomicAdd(&sc[1], (unsigned long long)my_evals);
-        }
         minrej[unit] = rej;
+        if (gkey && rej < inf) key_min(&gkey[pi.group_off + (uint32_t)((tz * ntx + tx) / GROUP)], rej);
     }
     __syncthreads();     // LDS is reused by the next item
     }
+}
+
+// The visits of one pass of n_units (> 0) listed tiles, taken by this wave with a stride of
+// the grid; the wave's update and estimate counts are added to *upd, *evals.
+template <typename real, typename mreal, bool SEEDED, bool TAB>
+__device__ __forceinline__ void relax_visits(RelaxLds<real>& L, uint32_t n_units, int slots, int gcap,
+                                             const PassItem* __restrict__ list, const mreal* __restrict__ geo_all,
+                                             const real* __restrict__ fbt_all, int R, int inner,
+                                             const real* __restrict__ theta, real* __restrict__ T,
+                                             uint32_t* __restrict__ flags, real* __restrict__ minrej,
+                                             uint32_t* __restrict__ gflag, real* __restrict__ gkey,
+                                             uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
+                                             const uint32_t* __restrict__ fixmask, const mreal* __restrict__ vtab,
+                                             unsigned& my_updates, unsigned& my_evals) {
+    auto& lt = L.lt;
+    auto& clist = L.clist;
+    auto& dnext = L.dnext;
+    auto& omask = L.omask;
+    auto& touched = L.touched;
+    auto& s_item = L.s_item;
+    auto& s_th = L.s_th;
+    auto& s_rej = L.s_rej;
+    // tiles per visit: spread the pass over `slots` waves, at most G_MAX tiles each
+    const uint32_t per = n_units / (uint32_t)slots;
+    const int G = per >= (uint32_t)gcap ? gcap : (per < 1u ? 1 : (int)per);
+    const uint32_t n_visits = (n_units + (uint32_t)G - 1u) / (uint32_t)G;
+    const real inf = dinf<real>();
+
+    for (uint32_t visit = blockIdx.x; visit < n_visits; visit += gridDim.x) {
+    // the lane index is made opaque inside the visit loop: otherwise the per-lane staging
+    // offsets are hoisted out of the loop and held in registers through the sweeps
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));
+    const uint32_t first = visit * (uint32_t)G;
+    const int ng = n_units - first < (uint32_t)G ? (int)(n_units - first) : G;   // tiles of this visit
+
+    // the visit's pass-list entries (lanes 0..4*ng-1, one 16-byte vector each)
+    if (lane < 4 * ng) {
+        const uint4* src = reinterpret_cast<const uint4*>(list + first) + lane;
+        reinterpret_cast<uint4*>(s_item)[lane] = *src;
+    }
+    __syncthreads();
+
+    // stage every tile and its halo: all loads of a lane are issued before its first store
+    constexpr int SQ = (LW * LH + RW - 1) / RW;
+    real sv[G_MAX][SQ];
+#pragma unroll
+    for (int g = 0; g < G_MAX; ++g) {
+        const PassItem& pi = s_item[g < ng ? g : 0];
+        const int i0 = pi.tx * TX, j0 = pi.tz * TZ, nx = pi.nx, nz = pi.nz;
+        const real* __restrict__ Tf = T + pi.t_off;
+#pragma unroll
+        for (int k = 0; k < SQ; ++k) {
+            const int q = lane + RW * k;
+            const int li = q % LW, lj = q / LW;
+            const int gi = i0 - HALO + li, gj = j0 - HALO + lj;
+            sv[g][k] = (g < ng && q < LW * LH && gi >= 0 && gj >= 0 && gi < nx && gj < nz)
+                           ? Tf[(int64_t)gj * nx + gi] : inf;
+        }
+    }
+    // incoming marks of each tile (read and cleared; this pass writes the other buffer):
+    // lane 4 g + w holds word w of tile g
+    uint32_t mk = 0u, fm = 0u;
+    if (lane < NODE_WORDS * ng) {
+        const uint32_t unit = s_item[lane / NODE_WORDS].unit;
+        const int64_t a = (int64_t)unit * NODE_WORDS + lane % NODE_WORDS;
+        mk = marks_in[a];
+        if (mk) marks_in[a] = 0u;
+        if constexpr (SEEDED) fm = fixmask[a];
+    }
+    if (lane < ng) {
+        s_th[lane] = theta[s_item[lane].f];
+        s_rej[lane] = inf;
+    }
+#pragma unroll
+    for (int g = 0; g < G_MAX; ++g) {
+#pragma unroll
+        for (int k = 0; k < SQ; ++k) {
+            const int q = lane + RW * k;
+            if (g < ng && q < LW * LH) lt[g * TILE_LDS + (q / LW) * LSTRIDE + q % LW] = sv[g][k];
+        }
+    }
+    for (int q = lane; q < G_MAX * 9 * NODE_WORDS; q += RW) (&omask[0][0][0])[q] = 0u;
+    if (lane < G_MAX * NODE_WORDS) {
+        (&dnext[0][0])[lane] = 0u;
+        (&touched[0][0])[lane] = 0u;
+    }
+    __syncthreads();
+
+    // the nodes of this lane: q = 0 .. NPL * G_MAX - 1, tile q / NPL, node lane + 64 (q % NPL).
+    // Loops over them stay rolled, and nothing per node is kept in registers across the
+    // phases (the write-back finds changed nodes in the LDS change mask).
+    unsigned dmask = 0u;              // bit q: node q of this lane is marked for this sweep
+    unsigned amask = 0u;              // bit q: node q of this lane is evaluated at all
+#pragma unroll 1
+    for (int q = 0; q < NPL * ng; ++q) {
+        const int g = q / NPL;
+        const int node = lane + RW * (q % NPL);
+        const PassItem& pi = s_item[g];
+        const int lx = node % TX, lz = node / TX;
+        const int gi = pi.tx * TX + lx, gj = pi.tz * TZ + lz;
+        const int me = g * TILE_LDS + (lz + HALO) * LSTRIDE + (lx + HALO);
+        bool fixed_node;
+        if constexpr (SEEDED) fixed_node = (__shfl(fm, g * NODE_WORDS + (node >> 5)) >> (node & 31)) & 1u;
+        else fixed_node = abs(gi - pi.src.x) <= R && abs(gj - pi.src.y) <= R;
+        const bool act = gi < pi.nx && gj < pi.nz && !fixed_node;
+        amask |= act ? 1u << q : 0u;
+        const real cur = lt[me];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) any |= lt[me + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]] < inf;
+        const bool marked = (__shfl(mk, g * NODE_WORDS + (node >> 5)) >> (node & 31)) & 1u;
+        // a finite node with no finite neighbour left is evaluated too (it must turn +inf)
+        if (act && (any || cur < inf) && ((pi.bits & TF_SELF) || !(cur < inf) || marked)) dmask |= 1u << q;
+    }
+
+    bool done = false;
+    for (int it = 0;; ++it) {
+        // pack the marked nodes of all tiles
+        unsigned total = 0;
+#pragma unroll 1
+        for (int q = 0; q < NPL * ng; ++q) {
+            const unsigned long long m = __ballot((dmask >> q) & 1u);
+            if ((dmask >> q) & 1u)
+                clist[total + __popcll(m & ((1ull << lane) - 1ull))] =
+                    (uint16_t)((q / NPL) * NTHREADS + lane + RW * (q % NPL));
+            total += (unsigned)__popcll(m);
+        }
+        __syncthreads();
+        if (total == 0) { done = true; break; }
+        if (it == inner) break;     // sweep cap: the marked nodes carry over to the next pass
+        dmask = 0u;
+        for (unsigned c = 0; c < total; c += RW) {
+            bool chg = false;
+            real lo = real(0);
+            int code = 0;
+            if (c + lane < total) {
+                code = clist[c + lane];
+                const int g = code / NTHREADS, node = code % NTHREADS;
+                const PassItem& pi = s_item[g];
+                const int nlx = node % TX, nlz = node / TX;
+                const int nme = g * TILE_LDS + (nlz + HALO) * LSTRIDE + (nlx + HALO);
+                const int64_t p = (int64_t)(pi.tz * TZ + nlz) * pi.nx + (pi.tx * TX + nlx);
+                const mreal* __restrict__ geo = geo_all + GEO_N * pi.node_off;
+                const real* __restrict__ fbt = fbt_all + 4 * pi.node_off;
+                using NC = typename std::conditional<TAB, NodeConstTab<mreal, real>, NodeConst<mreal, real>>::type;
+                NC nc;
+                load_node_const<real, mreal>(nc, p, geo, fbt);
+                if constexpr (TAB) nc.vt = vtab + (int)geo[GEO_N * p + 6];
+                real t[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) t[k] = lt[nme + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]];
+                ++my_updates;
+                real u = local_update<mreal, real>(nc, t, lt, nme, LSTRIDE, my_evals);
+                if (u > s_th[g] && u < inf) { lds_min(&s_rej[g], u); u = inf; }
+                const real cv = lt[nme];
+                if (!(u == cv || (u >= inf && cv >= inf))) {
+                    lt[nme] = u;
+                    chg = true;
+                    lo = u < cv ? u : cv;
+                    atomicOr(&touched[g][node >> 5], 1u << (node & 31));
+                }
+            }
+            // every value of the chunk is stored before any neighbour is compared (the
+            // comparisons must see the neighbours' new values)
+            __syncthreads();
+            if (chg) {
+                const int g = code / NTHREADS, node = code % NTHREADS;
+                const int nlx = node % TX, nlz = node / TX;
+                const int nme = g * TILE_LDS + (nlz + HALO) * LSTRIDE + (nlx + HALO);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    const int ax = nlx + SLOT_DI[k], az = nlz + SLOT_DJ[k];
+                    if (ax >= 0 && az >= 0 && ax < TX && az < TZ &&
+                        lo <= lt[nme + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]]) {
+                        const int nn = az * TX + ax;
+                        atomicOr(&dnext[g][nn >> 5], 1u << (nn & 31));
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // collect the marks for the next sweep
+#pragma unroll 1
+        for (int q = 0; q < NPL * ng; ++q) {
+            const int g = q / NPL;
+            const int node = lane + RW * (q % NPL);
+            if ((dnext[g][node >> 5] >> (node & 31)) & 1u) dmask |= amask & (1u << q);
+        }
+        __syncthreads();
+        if (lane < G_MAX * NODE_WORDS) (&dnext[0][0])[lane] = 0u;
+        __syncthreads();
+    }
+
+    // write back; mark the diamond neighbours of changed nodes in the neighbouring tiles
+    // (and, after the sweep cap, each tile's own unfinished nodes)
+    bool any_out = false;
+    if (!done) {
+#pragma unroll 1
+        for (int q = 0; q < NPL * ng; ++q)
+            if ((dmask >> q) & 1u) {
+                const int g = q / NPL;
+                const int node = lane + RW * (q % NPL);
+                atomicOr(&omask[g][4][node >> 5], 1u << (node & 31));
+                any_out = true;
+            }
+    }
+#pragma unroll 1
+    for (int q = 0; q < NPL * ng; ++q) {
+        const int g = q / NPL;
+        const int node = lane + RW * (q % NPL);
+        const PassItem& pi = s_item[g];
+        const int lx = node % TX, lz = node / TX;
+        const int gi = pi.tx * TX + lx, gj = pi.tz * TZ + lz;
+        if (gi >= pi.nx || gj >= pi.nz) continue;
+        // a node whose value changed (possibly back to where it started) is written back
+        if (!((touched[g][node >> 5] >> (node & 31)) & 1u)) continue;
+        T[pi.t_off + (int64_t)gj * pi.nx + gi] = lt[g * TILE_LDS + (lz + HALO) * LSTRIDE + (lx + HALO)];
+        if (lx >= HALO && lx < TX - HALO && lz >= HALO && lz < TZ - HALO) continue;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const int ax = lx + SLOT_DI[k], az = lz + SLOT_DJ[k];
+            if (ax >= 0 && az >= 0 && ax < TX && az < TZ) continue;
+            const int ngi = gi + SLOT_DI[k], ngj = gj + SLOT_DJ[k];
+            if (ngi < 0 || ngj < 0 || ngi >= pi.nx || ngj >= pi.nz) continue;
+            const int ox = ax < 0 ? 0 : (ax < TX ? 1 : 2), oz = az < 0 ? 0 : (az < TZ ? 1 : 2);
+            const int nn = (az - (oz - 1) * TZ) * TX + (ax - (ox - 1) * TX);
+            atomicOr(&omask[g][oz * 3 + ox][nn >> 5], 1u << (nn & 31));
+            any_out = true;
+        }
+    }
+    const bool out = __ballot(any_out) != 0ull;
+    __syncthreads();
+    if (out) {
+        // one lane per (tile, neighbour tile, word): push the node marks and flag the tile
+        for (int q = lane; q < ng * 9 * NODE_WORDS; q += RW) {
+            const int g = q / (9 * NODE_WORDS), r = q % (9 * NODE_WORDS);
+            const uint32_t w = omask[g][r / NODE_WORDS][r % NODE_WORDS];
+            if (!w) continue;
+            const PassItem& pi = s_item[g];
+            const int ntx = (pi.nx + TX - 1) / TX;
+            const int o = r / NODE_WORDS;
+            const int ntx2 = pi.tx + o % 3 - 1, ntz2 = pi.tz + o / 3 - 1;
+            const int64_t u2 = (int64_t)pi.unit + (int64_t)(ntz2 - pi.tz) * ntx + (ntx2 - pi.tx);
+            atomicOr(&marks_out[u2 * NODE_WORDS + r % NODE_WORDS], w);
+            flag_tile(flags, gflag, pi.unit - (uint32_t)(pi.tz * ntx + pi.tx), pi.group_off, ntz2 * ntx + ntx2,
+                      TF_MARK);
+        }
+    }
+    if (lane < ng) {
+        const PassItem& pi = s_item[lane];
+        const real rej = s_rej[lane];
+        minrej[pi.unit] = rej;
+        const int ntx = (pi.nx + TX - 1) / TX;
+        if (gkey && rej < inf) key_min(&gkey[pi.group_off + (uint32_t)((pi.tz * ntx + pi.tx) / GROUP)], rej);
+    }
+    __syncthreads();     // LDS is reused by the next visit
+    }
+}
+
+// statistics of one wave, spread over STAT_SLOTS counter pairs (one address for all waves
+// would serialise every visit of a pass)
+__device__ __forceinline__ void relax_stats(unsigned long long* __restrict__ counters, unsigned my_updates,
+                                            unsigned my_evals) {
+    for (int o = 32; o > 0; o >>= 1) {
+        my_updates += __shfl_xor(my_updates, o);
+        my_evals += __shfl_xor(my_evals, o);
+    }
+    if (threadIdx.x == 0 && my_updates) {
+        unsigned long long* sc = counters + 4 + 2 * (blockIdx.x % STAT_SLOTS);
+        atomicAdd(&sc[0], (unsigned long long)my_updates);
+        atomicAdd(&sc[1], (unsigned long long)my_evals);
+    }
+}
+
+// One relaxation pass: the listed tiles of the pass (count), or, for an empty list, the
+// idle flag that ends the solve.
+template <typename real, typename mreal, bool SEEDED, bool TAB>
+__global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
+k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, const real* __restrict__ fbt_all,
+        int R, int inner, const real* __restrict__ theta,
+        real* __restrict__ T, uint32_t* __restrict__ flags, real* __restrict__ minrej,
+        uint32_t* __restrict__ gflag, real* __restrict__ gkey,
+        uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
+        const uint32_t* __restrict__ count, uint32_t* __restrict__ idle,
+        unsigned long long* __restrict__ counters, const uint32_t* __restrict__ fixmask,
+        const mreal* __restrict__ vtab, int slots, int gcap) {
+    __shared__ RelaxLds<real> L;
+    // the first entry is read together with the list length (the grid never exceeds the
+    // list's capacity, so the read is in bounds; the entry is used only if it is live)
+    const PassItem pi0 = list[blockIdx.x];
+    const uint32_t n_units = *count;
+    if (n_units == 0u) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *idle = 1u;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd(&counters[2], 1ull);                  // passes with work
+        atomicAdd(&counters[3], (unsigned long long)n_units);   // tile visits
+    }
+    unsigned my_updates = 0, my_evals = 0;
+    if (gcap <= 1 || n_units < 2u * (uint32_t)slots)
+        relax_single<real, mreal, SEEDED, TAB>(L, n_units, &pi0, list, geo_all, fbt_all, R, inner, theta, T, flags,
+                                               minrej, gflag, gkey, marks_in, marks_out, fixmask, vtab, my_updates,
+                                               my_evals);
+    else
+        relax_visits<real, mreal, SEEDED, TAB>(L, n_units, slots, gcap, list, geo_all, fbt_all, R, inner, theta, T, flags,
+                                               minrej, gflag, gkey, marks_in, marks_out, fixmask, vtab, my_updates,
+                                               my_evals);
+    relax_stats(counters, my_updates, my_evals);
+}
+
+// ---------------------------------------------------------------------------------------
+// persistent relaxation: every pass of a solve in one cooperative launch
+// ---------------------------------------------------------------------------------------
+// Grid barrier for a cooperative grid of one-wave work-groups: each group's arrival is
+// counted on one of BAR_LEAVES leaf counters, the last arrival of a leaf counts on the top
+// counter, and the last arrival there releases everyone by bumping the generation word.
+// Each counter sits on its own 128-byte line.  The fences on both sides make every global
+// write of the phase before visible to every work-group after it, across the dies.  Every
+// wait is bounded: past `timeout` ticks of the constant-rate clock, or once another group
+// has given up, the group sets *err and returns false (the host reports a device error).
+constexpr int BAR_LEAVES = 64;
+constexpr int BAR_WORDS = 64 + 32 * BAR_LEAVES;
+
+__device__ __forceinline__ bool grid_sync(uint32_t* __restrict__ bar, uint32_t& gen, uint32_t* __restrict__ err,
+                                          long long timeout) {
+    __threadfence();
+    int ok = 1;
+    if (threadIdx.x == 0) {
+        const uint32_t nb = gridDim.x;
+        const uint32_t nleaf = nb < (uint32_t)BAR_LEAVES ? nb : (uint32_t)BAR_LEAVES;
+        const uint32_t leaf = blockIdx.x % nleaf;
+        const uint32_t leaf_n = nb / nleaf + (leaf < nb % nleaf ? 1u : 0u);
+        const uint32_t want = gen + 1u;
+        if (atomicAdd(&bar[64 + 32 * leaf], 1u) + 1u == leaf_n) {
+            atomicExch(&bar[64 + 32 * leaf], 0u);
+            __threadfence();
+            if (atomicAdd(&bar[32], 1u) + 1u == nleaf) {
+                atomicExch(&bar[32], 0u);
+                __threadfence();
+                __hip_atomic_store(&bar[0], want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        const long long t0 = wall_clock64();
+        while (__hip_atomic_load(&bar[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != want) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                wall_clock64() - t0 > timeout) {
+                atomicOr(err, 1u);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    ok = __shfl(ok, 0);
+    __threadfence();
+    gen += 1u;
+    return ok != 0;
+}
+
+// All passes of a forward solve, from pass first_pass on, in one launch: the grid (every
+// work-group resident, one wave each) schedules the fields (field f by group f mod grid),
+// meets at a grid barrier, relaxes the listed tiles, meets again; an empty pass list ends
+// the loop (*done = 1), as does max_passes.  The schedule and the visits are those of
+// k_sched and k_relax, so the fields are bitwise those of the pass-by-pass launches.
+template <typename real, typename mreal, bool SEEDED, bool TAB>
+__global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
+k_relax_persist(const FieldDev* __restrict__ fields, int n_fields, const real* __restrict__ step,
+                real* __restrict__ theta, PassItem* __restrict__ list, uint32_t* __restrict__ cnt,
+                const mreal* __restrict__ geo_all, const real* __restrict__ fbt_all, int R, int inner,
+                real* __restrict__ T, uint32_t* __restrict__ flags, real* __restrict__ minrej,
+                uint32_t* __restrict__ gflag, real* __restrict__ gkey, uint32_t* __restrict__ marks, int64_t nunits,
+                unsigned long long* __restrict__ counters, const uint32_t* __restrict__ fixmask,
+                const mreal* __restrict__ vtab, int gcap, int direct_tiles, int first_pass, int max_passes,
+                uint32_t* __restrict__ bar,
+                uint32_t* __restrict__ err, uint32_t* __restrict__ done, long long timeout) {
+    __shared__ RelaxLds<real> L;
+    uint32_t gen = 0u;
+    unsigned my_updates = 0, my_evals = 0;
+    for (int p = 0; p < max_passes; ++p) {
+        const int pp = first_pass + p;
+        for (int f = blockIdx.x; f < n_fields; f += gridDim.x)
+            schedule_field<false, real, RW, 2>(f, fields, pp > 0 ? 1 : 0, step, flags, minrej, gflag, gkey, theta, list,
+                                            cnt + (pp & 1), cnt + ((pp + 1) & 1),
+                                            reinterpret_cast<uint32_t*>(L.lt), direct_tiles);
+        if (!grid_sync(bar, gen, err, timeout)) break;
+        const uint32_t n_units = __hip_atomic_load(cnt + (pp & 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (n_units == 0u) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) *done = 1u;
+            break;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            atomicAdd(&counters[2], 1ull);
+            atomicAdd(&counters[3], (unsigned long long)n_units);
+        }
+        uint32_t* mk_in = marks + (size_t)(pp & 1) * nunits * NODE_WORDS;
+        uint32_t* mk_out = marks + (size_t)((pp + 1) & 1) * nunits * NODE_WORDS;
+        if (gcap <= 1 || n_units < 2u * gridDim.x)
+            relax_single<real, mreal, SEEDED, TAB>(L, n_units, nullptr, list, geo_all, fbt_all, R, inner, theta, T,
+                                                   flags, minrej, gflag, gkey, mk_in, mk_out, fixmask, vtab,
+                                                   my_updates, my_evals);
+        else
+            relax_visits<real, mreal, SEEDED, TAB>(L, n_units, (int)gridDim.x, gcap, list, geo_all, fbt_all, R, inner,
+                                                   theta, T, flags, minrej, gflag, gkey, mk_in, mk_out, fixmask, vtab,
+                                                   my_updates, my_evals);
+        if (!grid_sync(bar, gen, err, timeout)) break;
+    }
+    relax_stats(counters, my_updates, my_evals);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -516,6 +935,8 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     if (opt.max_sweeps < 1) return H->fail(ALI_EINVAL, "max_sweeps must be >= 1");
     if (opt.inner_sweeps < 1 || opt.inner_sweeps > 4096) return H->fail(ALI_EINVAL, "inner_sweeps out of range [1, 4096]");
     if (opt.band_cells < 0) return H->fail(ALI_EINVAL, "band_cells must be >= 0 (0 = no band)");
+    if (opt.visit_tiles < 0 || opt.visit_tiles > G_MAX) return H->fail(ALI_EINVAL, "visit_tiles out of range [0, 4]");
+    if (opt.persistent != 0 && opt.persistent != 1) return H->fail(ALI_EINVAL, "persistent must be 0 or 1");
     if (opt.velocity != ALI_VEL_CHRISTOFFEL && opt.velocity != ALI_VEL_TABLE)
         return H->fail(ALI_EINVAL, "unknown velocity mode");
     if (opt.d_node_A && (opt.wave != ALI_WAVE_QP || opt.velocity != ALI_VEL_CHRISTOFFEL))
@@ -532,7 +953,7 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     std::vector<MatDev<mreal>> hm;
     std::vector<int> dev_mat_off(n_media);
     std::vector<real> hstep, htheta;
-    int64_t units = 0, fnodes = 0, med_nodes = 0;
+    int64_t units = 0, fnodes = 0, med_nodes = 0, groups = 0;
     int obs = 0;
     for (int m = 0; m < n_media; ++m) {
         const ali_medium& md = media[m];
@@ -553,6 +974,7 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
             fd.node_off = md.node_offset;
             fd.t_off = fnodes;
             fd.unit_off = (uint32_t)units;
+            fd.group_off = (uint32_t)groups;
             fd.mat_off = dev_mat_off[m];
             fd.medium = m;
             fd.rec_off = md.rec_offset;
@@ -561,6 +983,7 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
             fd.src = make_int2(srcs[md.src_offset + k].i, srcs[md.src_offset + k].j);
             F.hfields.push_back(fd);
             units += (int64_t)ntx * ntz;
+            groups += field_groups(ntx * ntz);
             fnodes += (int64_t)nx * nz;
             obs += fd.n_rec;
             hstep.push_back(band);
@@ -571,10 +994,16 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     const int n_fields = (int)F.hfields.size();
     const int64_t nunits = units;
     F.n_units = nunits;
+    F.n_groups = groups;
+    // the scheduler reads small fields tile by tile; the group summaries are kept only if
+    // some field of the call is scheduled by groups
+    const int direct_tiles = direct_tiles_for(nunits, opt.persistent ? RW * 2 : SCHED_SPAN);
+    bool use_groups = false;
+    for (const FieldDev& fd : F.hfields) use_groups |= fd.ntx * fd.ntz > direct_tiles;
     F.field_nodes = fnodes;
 
     void *d_mats, *d_geo, *d_fbt, *d_fields, *d_flags, *d_list, *d_count, *d_upd, *d_err;
-    void *d_theta, *d_step, *d_minrej, *d_marks, *d_idle;
+    void *d_theta, *d_step, *d_minrej, *d_marks, *d_idle, *d_gflag, *d_gkey;
     if (!H->scratch("mats", sizeof(MatDev<mreal>) * hm.size(), &d_mats) ||
         !H->scratch("fields", sizeof(FieldDev) * n_fields, &d_fields) ||
         !H->scratch("theta", sizeof(real) * n_fields, &d_theta) ||
@@ -583,6 +1012,8 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
         !H->scratch("geo", sizeof(mreal) * GEO_N * med_nodes, &d_geo) ||
         !H->scratch("fbt", sizeof(real) * 4 * med_nodes, &d_fbt) ||
         !H->scratch("flags", sizeof(uint32_t) * nunits, &d_flags) ||
+        !H->scratch("gflag", sizeof(uint32_t) * groups, &d_gflag) ||
+        !H->scratch("gkey", sizeof(real) * groups, &d_gkey) ||
         !H->scratch("list", sizeof(PassItem) * nunits, &d_list) ||
         !H->scratch("marks", sizeof(uint32_t) * 2 * NODE_WORDS * nunits, &d_marks) ||
         !H->scratch("count", 2 * sizeof(uint32_t), &d_count) ||
@@ -599,6 +1030,7 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     HIPCK(H, hipMemcpyAsync(d_mats, hm.data(), sizeof(MatDev<mreal>) * hm.size(), hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemcpyAsync(d_fields, F.hfields.data(), sizeof(FieldDev) * n_fields, hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemsetAsync(d_flags, 0, sizeof(uint32_t) * nunits, S));
+    HIPCK(H, hipMemsetAsync(d_gflag, 0, sizeof(uint32_t) * groups, S));
     HIPCK(H, hipMemsetAsync(d_marks, 0, sizeof(uint32_t) * 2 * NODE_WORDS * nunits, S));
     HIPCK(H, hipMemsetAsync(d_upd, 0, (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), S));
     HIPCK(H, hipMemsetAsync(d_count, 0, 2 * sizeof(uint32_t), S));
@@ -608,6 +1040,8 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     const int B = 256;
     hipLaunchKernelGGL((k_fill<real>), dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
                        (real*)d_minrej, nunits, dinf_host<real>());
+    hipLaunchKernelGGL((k_fill<real>), dim3((unsigned)((groups + B - 1) / B)), dim3(B), 0, S,
+                       (real*)d_gkey, groups, dinf_host<real>());
     // velocity-table mode: per device material, phase speed / h and group speed at whole
     // degrees (built on the device from the run-time speeds)
     const bool tab = opt.velocity == ALI_VEL_TABLE;
@@ -661,11 +1095,12 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
                                tab ? (const double*)d_gt + (size_t)VT_N * dev_mat_off[m] : (const double*)nullptr,
                                md.n_mats, d_mat_id + md.node_offset, d_orient + md.node_offset,
                                opt.d_node_A ? opt.d_node_A + 4 * md.node_offset : (const float*)nullptr,
-                               opt.src_box_radius, d_T, (uint32_t*)d_flags);
+                               opt.src_box_radius, d_T, (uint32_t*)d_flags, (uint32_t*)d_gflag);
     }
     if (d_fixmask)
         hipLaunchKernelGGL(k_seed_flags, dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S,
-                           (const FieldDev*)d_fields, n_fields, nunits, d_fixmask, (uint32_t*)d_flags);
+                           (const FieldDev*)d_fields, n_fields, nunits, d_fixmask, (uint32_t*)d_flags,
+                           (uint32_t*)d_gflag);
     HIPCK(H, hipGetLastError());
 
     int h_err = 0;
@@ -702,13 +1137,18 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     // a fixed grid (the pass size is known only on the device); work-groups beyond the
     // pass list exit at once
     const int grid_relax = (int)(nunits < (int64_t)32 * H->n_cu ? nunits : (int64_t)32 * H->n_cu);
+    // resident one-wave work-groups of the relaxation (4 per SIMD): a pass with more tiles
+    // than this packs several tiles into each visit
+    const int slots = 16 * H->n_cu;
+    const int gcap = opt.visit_tiles > 0 ? opt.visit_tiles : G_MAX;
     uint32_t* cnt = (uint32_t*)d_count;
     // one pass: schedule, then relax (events around the relax launch when timed)
     auto enqueue = [&](int p, bool timed, hipStream_t S) {
         hipLaunchKernelGGL((k_sched<real>), dim3((unsigned)n_fields), dim3(SCHED_T), 0, S,
                            (const FieldDev*)d_fields, p > 0 ? 1 : 0,
-                           (uint32_t*)d_flags, (real*)d_minrej, (real*)d_theta, (const real*)d_step,
-                           (PassItem*)d_list, cnt + (p & 1), cnt + ((p + 1) & 1));
+                           (uint32_t*)d_flags, (real*)d_minrej, (uint32_t*)d_gflag, (real*)d_gkey,
+                           (real*)d_theta, (const real*)d_step,
+                           (PassItem*)d_list, cnt + (p & 1), cnt + ((p + 1) & 1), direct_tiles);
         uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
         uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);
@@ -718,28 +1158,94 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
             hipLaunchKernelGGL((k_relax<real, mreal, true, true>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
                                (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, R,
                                opt.inner_sweeps, (const real*)d_theta, d_T, (uint32_t*)d_flags, (real*)d_minrej,
-                               mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
-                               (unsigned long long*)d_upd, d_fixmask, vt);
+                               use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (real*)d_gkey : nullptr, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
+                               (unsigned long long*)d_upd, d_fixmask, vt, slots, gcap);
         else if (d_fixmask)
             hipLaunchKernelGGL((k_relax<real, mreal, true, false>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
                                (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, R,
                                opt.inner_sweeps, (const real*)d_theta, d_T, (uint32_t*)d_flags, (real*)d_minrej,
-                               mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
-                               (unsigned long long*)d_upd, d_fixmask, vt);
+                               use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (real*)d_gkey : nullptr, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
+                               (unsigned long long*)d_upd, d_fixmask, vt, slots, gcap);
         else if (tab)
             hipLaunchKernelGGL((k_relax<real, mreal, false, true>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
                                (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, R,
                                opt.inner_sweeps, (const real*)d_theta, d_T, (uint32_t*)d_flags, (real*)d_minrej,
-                               mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
-                               (unsigned long long*)d_upd, d_fixmask, vt);
+                               use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (real*)d_gkey : nullptr, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
+                               (unsigned long long*)d_upd, d_fixmask, vt, slots, gcap);
         else
             hipLaunchKernelGGL((k_relax<real, mreal, false, false>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
                                (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, R, opt.inner_sweeps, (const real*)d_theta, d_T,
-                               (uint32_t*)d_flags, (real*)d_minrej, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)),
-                               (uint32_t*)d_idle, (unsigned long long*)d_upd, d_fixmask, vt);
+                               (uint32_t*)d_flags, (real*)d_minrej, use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (real*)d_gkey : nullptr, mk_in, mk_out,
+                               (const uint32_t*)(cnt + (p & 1)),
+                               (uint32_t*)d_idle, (unsigned long long*)d_upd, d_fixmask, vt, slots, gcap);
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH) + 1], S);
     };
-    while (iters < opt.max_sweeps) {
+    if (opt.persistent) {
+        // every pass in one cooperative launch (all work-groups resident; the runtime
+        // refuses a grid that does not fit instead of over-subscribing)
+        void* kern = d_fixmask ? (tab ? (void*)&k_relax_persist<real, mreal, true, true>
+                                      : (void*)&k_relax_persist<real, mreal, true, false>)
+                               : (tab ? (void*)&k_relax_persist<real, mreal, false, true>
+                                      : (void*)&k_relax_persist<real, mreal, false, false>);
+        int per_cu = 0, lds_cu = 0;
+        HIPCK(H, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, RW, 0));
+        // and no more than the LDS of a compute unit holds, allocations rounded up to 512 B
+        hipFuncAttributes fa;
+        HIPCK(H, hipFuncGetAttributes(&fa, kern));
+        HIPCK(H, hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, H->device));
+        const size_t lds_wg = (fa.sharedSizeBytes + 511) & ~(size_t)511;
+        if (lds_wg > 0 && (size_t)per_cu * lds_wg > (size_t)lds_cu) per_cu = (int)((size_t)lds_cu / lds_wg);
+        if (per_cu < 1) return H->fail(ALI_EDEVICE, "persistent relaxation: no resident work-group fits a compute unit");
+        const int grid_p = per_cu * H->n_cu;
+        void *d_bar, *d_perr;
+        if (!H->scratch("bar", sizeof(uint32_t) * BAR_WORDS, &d_bar) || !H->scratch("perr", 2 * sizeof(uint32_t), &d_perr))
+            return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+        HIPCK(H, hipMemsetAsync(d_bar, 0, sizeof(uint32_t) * BAR_WORDS, S));
+        HIPCK(H, hipMemsetAsync(d_perr, 0, 2 * sizeof(uint32_t), S));
+        const FieldDev* a_fields = (const FieldDev*)d_fields;
+        int a_nf = n_fields;
+        const real* a_step = (const real*)d_step;
+        real* a_theta = (real*)d_theta;
+        PassItem* a_list = (PassItem*)d_list;
+        uint32_t* a_cnt = cnt;
+        const mreal* a_geo = (const mreal*)d_geo;
+        const real* a_fbt = (const real*)d_fbt;
+        int a_R = d_fixmask ? -1 : opt.src_box_radius;
+        int a_inner = opt.inner_sweeps;
+        real* a_T = d_T;
+        uint32_t* a_flags = (uint32_t*)d_flags;
+        real* a_minrej = (real*)d_minrej;
+        uint32_t* a_gflag = use_groups ? (uint32_t*)d_gflag : nullptr;
+        real* a_gkey = use_groups ? (real*)d_gkey : nullptr;
+        uint32_t* a_marks = (uint32_t*)d_marks;
+        int64_t a_nunits = nunits;
+        unsigned long long* a_upd = (unsigned long long*)d_upd;
+        const uint32_t* a_fix = d_fixmask;
+        const mreal* a_vt = (const mreal*)d_vt;
+        int a_gcap = gcap;
+        int a_direct = direct_tiles;
+        int a_first = 0, a_max = opt.max_sweeps;
+        uint32_t* a_bar = (uint32_t*)d_bar;
+        uint32_t* a_err = (uint32_t*)d_perr;
+        uint32_t* a_done = (uint32_t*)d_perr + 1;
+        long long a_timeout = H->barrier_timeout_ticks;
+        void* args[] = {&a_fields, &a_nf, &a_step, &a_theta, &a_list, &a_cnt, &a_geo, &a_fbt, &a_R, &a_inner,
+                        &a_T, &a_flags, &a_minrej, &a_gflag, &a_gkey, &a_marks, &a_nunits, &a_upd, &a_fix, &a_vt,
+                        &a_gcap, &a_direct, &a_first, &a_max, &a_bar, &a_err, &a_done, &a_timeout};
+        HIPCK(H, hipEventRecord(H->ev2, S));
+        HIPCK(H, hipLaunchCooperativeKernel(kern, dim3((unsigned)grid_p), dim3(RW), args, 0, S));
+        HIPCK(H, hipEventRecord(H->ev3, S));
+        uint32_t pflags[2] = {0u, 0u};
+        HIPCK(H, hipMemcpyAsync(pflags, d_perr, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, S));
+        HIPCK(H, hipStreamSynchronize(S));
+        float kms = 0.f;
+        HIPCK(H, hipEventElapsedTime(&kms, H->ev2, H->ev3));
+        relax_ms = kms;
+        if (pflags[0]) return H->fail(ALI_EDEVICE, "persistent relaxation: a grid barrier timed out");
+        converged = pflags[1] != 0u;
+        iters = opt.max_sweeps;
+    }
+    while (!opt.persistent && iters < opt.max_sweeps) {
         const int batch = opt.max_sweeps - iters < PASS_BATCH ? opt.max_sweeps - iters : PASS_BATCH;
         const bool graph = opt.graph && batch == PASS_BATCH;
         if (graph) {
@@ -750,9 +1256,10 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
                                          : (tab ? (const void*)&k_relax<real, mreal, false, true>
                                                 : (const void*)&k_relax<real, mreal, false, false>);
             const std::string key = graph_key("relax", first, kern, d_fields, n_fields,
-                                              d_flags, d_minrej, d_theta, d_step, d_list, d_count,
+                                              d_flags, d_minrej, d_gflag, d_gkey, use_groups ? 1 : 0, direct_tiles,
+                                              d_theta, d_step, d_list, d_count,
                                               d_marks, nunits, d_geo, d_fbt, opt.src_box_radius,
-                                              opt.inner_sweeps, d_T, d_idle, d_upd, grid_relax,
+                                              opt.inner_sweeps, d_T, d_idle, d_upd, grid_relax, slots, gcap,
                                               (const void*)d_fixmask, d_vt);
             HIPCK(H, hipEventRecord(H->ev2, S));
             st = launch_captured(H, key, [&](int b, hipStream_t cs) { enqueue(first ? b : PASS_BATCH + b, false, cs); });
@@ -869,7 +1376,10 @@ static size_t forward_scratch_bytes(const ali_grid& g, int n_src, int n_mats, bo
     req.push_back(sizeof(real) * units);                           // minrej
     req.push_back(sizeof(mreal) * GEO_N * nodes);                  // geo
     req.push_back(sizeof(real) * 4 * nodes);                       // fbt
+    const int64_t groups = (int64_t)field_groups(((g.nx + TX - 1) / TX) * ((g.nz + TZ - 1) / TZ)) * n_src;
     req.push_back(sizeof(uint32_t) * units);                       // flags
+    req.push_back(sizeof(uint32_t) * groups);                      // gflag
+    req.push_back(sizeof(real) * groups);                          // gkey
     req.push_back(sizeof(PassItem) * units);                       // list
     req.push_back(sizeof(uint32_t) * 2 * NODE_WORDS * units);      // marks
     req.push_back(2 * sizeof(uint32_t));                           // count
@@ -1004,9 +1514,20 @@ extern "C" ali_status ali_solve_traveltime_noalloc(ali_handle* h, const ali_grid
     return st;
 }
 
-// candidate schedules of the autotuner: (band_cells, inner_sweeps)
-static const int TUNE_BAND[ALI_TUNE_CANDIDATES] = {1, 1, 1, 2, 2, 3};
-static const int TUNE_INNER[ALI_TUNE_CANDIDATES] = {1, 2, 4, 2, 4, 4};
+// candidate schedules of the autotuner: band_cells, inner_sweeps, visit_tiles, persistent
+static const int TUNE[ALI_TUNE_CANDIDATES][4] = {
+    {1, 2, 4, 0}, {1, 2, 2, 0}, {1, 2, 1, 0}, {1, 4, 4, 0}, {2, 2, 4, 0}, {2, 4, 4, 0}, {1, 2, 4, 1}};
+
+// size bucket of a batch: powers of two of the field count, the largest side and the
+// node-fields, with the options that change the work (arithmetic, wave, speeds, stiffness)
+static std::string tune_bucket(const ali_medium* media, int32_t n_media, const ali_options& o) {
+    int64_t nf = 0, nodes = 0;
+    int side = 0;
+    batch_sizes(media, n_media, &nf, &nodes);
+    for (int m = 0; m < n_media; ++m) side = std::max(side, std::max(media[m].grid.nx, media[m].grid.nz));
+    auto p2 = [](int64_t v) { int b = 0; while (((int64_t)1 << b) < v) ++b; return b; };
+    return graph_key("tune", p2(nf), p2(side), p2(nodes), o.arith, o.wave, o.velocity, o.d_node_A ? 1 : 0);
+}
 
 extern "C" ali_status ali_autotune_batch(ali_handle* h, const ali_medium* media, int32_t n_media,
                                          const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
@@ -1014,24 +1535,48 @@ extern "C" ali_status ali_autotune_batch(ali_handle* h, const ali_medium* media,
                                          float* d_T, double* ms_out) {
     if (!h) return ALI_EINVAL;
     if (!opt) return h->fail(ALI_EINVAL, "opt is NULL");
-    ali_options best = *opt;
+    ali_status st = validate_batch(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, nullptr, opt->wave);
+    if (st != ALI_OK) return st;
+    const std::string key = tune_bucket(media, n_media, *opt);
+    auto it = h->tuned.find(key);
+    if (it != h->tuned.end()) {
+        // tuned before on this handle for a batch of the same bucket
+        const int c = it->second.first;
+        opt->band_cells = TUNE[c][0];
+        opt->inner_sweeps = TUNE[c][1];
+        opt->visit_tiles = TUNE[c][2];
+        opt->persistent = TUNE[c][3];
+        if (ms_out)
+            for (int k = 0; k < ALI_TUNE_CANDIDATES; ++k) ms_out[k] = it->second.second[k];
+        return ALI_OK;
+    }
+    int best = -1;
     double best_ms = INFINITY;
+    std::vector<double> times(ALI_TUNE_CANDIDATES, INFINITY);
     for (int c = 0; c < ALI_TUNE_CANDIDATES; ++c) {
         ali_options o = *opt;
-        o.band_cells = TUNE_BAND[c];
-        o.inner_sweeps = TUNE_INNER[c];
+        o.band_cells = TUNE[c][0];
+        o.inner_sweeps = TUNE[c][1];
+        o.visit_tiles = TUNE[c][2];
+        o.persistent = TUNE[c][3];
         double ms = INFINITY;
         // two runs: the first may build the candidate's graphs
         for (int rep = 0; rep < 2; ++rep) {
-            ali_solve_stats st{};
+            ali_solve_stats sst{};
             const ali_status s = solve_dispatch<float, float>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs,
-                                                              &o, d_T, &st);
+                                                              &o, d_T, &sst);
             if (s != ALI_OK) return s;
-            ms = st.ms;
+            ms = sst.ms;
         }
-        if (ms_out) ms_out[c] = ms;
-        if (ms < best_ms) { best_ms = ms; best = o; }
+        times[c] = ms;
+        if (ms < best_ms) { best_ms = ms; best = c; }
     }
-    *opt = best;
+    h->tuned[key] = std::make_pair(best, times);
+    opt->band_cells = TUNE[best][0];
+    opt->inner_sweeps = TUNE[best][1];
+    opt->visit_tiles = TUNE[best][2];
+    opt->persistent = TUNE[best][3];
+    if (ms_out)
+        for (int k = 0; k < ALI_TUNE_CANDIDATES; ++k) ms_out[k] = times[k];
     return ALI_OK;
 }

@@ -121,6 +121,7 @@ struct FieldDev {
     int64_t node_off;     // the medium's first node in the per-node arrays (materials, orientation)
     int64_t t_off;        // the field's first node in the per-field arrays (travel times)
     uint32_t unit_off;    // the field's first tile unit (flags, thresholds, node marks)
+    uint32_t group_off;   // the field's first scheduler group (GROUP tiles each)
     int mat_off;          // the medium's first entry in the device material table
     int medium;
     int rec_off, n_rec;   // the medium's receivers (gradient calls)
@@ -133,7 +134,8 @@ struct FieldDev {
 struct alignas(16) PassItem {
     uint32_t unit, bits;      // tile unit; the flag bits it was scheduled with
     int f, tx;                // field; tile column
-    int tz, nx, nz, pad0;     // tile row; the field's grid
+    int tz, nx, nz;           // tile row; the field's grid
+    uint32_t group_off;       // the field's first scheduler group
     int2 src;                 // the field's source node
     int64_t t_off;            // the field's first node in the per-field arrays
     int64_t node_off;         // the medium's first node in the per-node arrays
@@ -142,55 +144,188 @@ struct alignas(16) PassItem {
 static_assert(sizeof(PassItem) == 64, "pass-list entries are four 16-byte vectors");
 
 constexpr int SCHED_T = 256;  // work-items of a scheduler work-group (one group per field)
-constexpr int SCHED_K = 8;    // tiles per work-item held in registers
+constexpr int SCHED_K = 8;    // scheduler groups per work-item held in registers
+constexpr int SCHED_SPAN = SCHED_T * SCHED_K;   // groups a scheduler work-group reads at once
+// Tiles of one scheduler group.  The scheduler reads a summary per group (the OR of its
+// tiles' flags and the nearest of its tiles' keys) and only expands the groups that are
+// due, one wave per group and one tile per lane, instead of reading every tile of every
+// field on every pass.
+constexpr int GROUP = 64;
 
-// Pass scheduler of field blockIdx.x, run by one work-group of SCHED_T work-items.
+__host__ __device__ inline uint32_t field_groups(int ntiles) { return (uint32_t)((ntiles + GROUP - 1) / GROUP); }
+
+// Group summaries of the tile keys, kept exact with integer atomics on the key's bit
+// pattern: keys are non-negative times, +inf (ascending: none) or -inf (descending: none),
+// which order like their patterns read as signed integers.
+__device__ __forceinline__ void key_min(double* p, double v) {
+    atomicMin(reinterpret_cast<long long*>(p), (long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ void key_min(float* p, float v) { atomicMin(reinterpret_cast<int*>(p), __float_as_int(v)); }
+__device__ __forceinline__ void key_max(double* p, double v) {
+    atomicMax(reinterpret_cast<long long*>(p), (long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ void key_max(float* p, float v) { atomicMax(reinterpret_cast<int*>(p), __float_as_int(v)); }
+
+// flag tile t (index within its field) and its scheduler group (gflag == NULL: no field
+// of the call is scheduled by groups)
+__device__ __forceinline__ void flag_tile(uint32_t* __restrict__ flags, uint32_t* __restrict__ gflag, uint32_t unit_off,
+                                          uint32_t group_off, int t, uint32_t bits) {
+    atomicOr(&flags[unit_off + (uint32_t)t], bits);
+    if (gflag) atomicOr(&gflag[group_off + (uint32_t)(t / GROUP)], 1u);
+}
+
+// Fields of up to this many tiles have their tiles read directly by the scheduler, when
+// the whole call has at most DIRECT_ALL_UNITS tiles; otherwise only fields of up to one
+// scheduler span are (the group summaries spare the larger ones a full read per pass).
+constexpr int64_t DIRECT_ALL_UNITS = (int64_t)1 << 18;
+inline int direct_tiles_for(int64_t n_units, int span) { return n_units <= DIRECT_ALL_UNITS ? (1 << 30) : span; }
+
+// Pass scheduler of field f, run by one work-group of NT work-items (a multiple of 64;
+// every work-item of the group calls it), each holding K groups at a time.  s_due:
+// NT * K words of LDS.
 // Ascending (DESC = false, travel times): key[t] is the smallest value tile t rejected
-// (+inf: none); the threshold rises by step each pass, a tile is due when it is flagged
-// or its key is at or below the threshold, and a due tile's key is reset to +inf (its
-// visit recomputes it).  Descending (DESC = true, adjoint): key[t] is the largest key
-// still pending in tile t (-inf: none); the threshold falls by step, and a tile is due
-// when flagged or its key is at or above the threshold.  When no tile is due the
-// threshold jumps to the nearest key.  Due tiles have their flags cleared and are
-// appended to the pass list, counted by cnt_cur; cnt_next (the next pass's counter) is
-// cleared here.  Fields of up to SCHED_T * SCHED_K tiles are read once.
-template <bool DESC, typename real>
-__device__ __forceinline__ void schedule_field(const FieldDev* __restrict__ fields, int advance,
+// (+inf: none); the threshold rises by step each pass, and a tile is due when it is
+// flagged or its key is at or below the threshold.  Descending (DESC = true, adjoint):
+// key[t] is the largest key still pending in tile t (-inf: none); the threshold falls by
+// step, and a tile is due when flagged or its key is at or above the threshold.  When no
+// tile is due the threshold jumps to the nearest key.  Due tiles have their flags cleared
+// and their keys reset (their visit in this pass writes them again) and are appended to
+// the pass list, counted by cnt_cur; cnt_next (the next pass's counter) is cleared here.
+// Fields of at most direct_tiles tiles are read tile by tile (in spans of NT * K); larger
+// ones through the group summaries gflag / gkey, which are exact: a group is due exactly
+// when one of its tiles is; an expanded group's summary is rebuilt from its tiles that
+// stay.
+template <bool DESC, typename real, int NT, int K = SCHED_K>
+__device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict__ fields, int advance,
                                                const real* __restrict__ step, uint32_t* __restrict__ flags,
-                                               real* __restrict__ key, real* __restrict__ theta,
+                                               real* __restrict__ key, uint32_t* __restrict__ gflag,
+                                               real* __restrict__ gkey, real* __restrict__ theta,
                                                PassItem* __restrict__ list, uint32_t* __restrict__ cnt_cur,
-                                               uint32_t* __restrict__ cnt_next) {
-    constexpr int NW = SCHED_T / 64;
-    constexpr int SPAN = SCHED_T * SCHED_K;
+                                               uint32_t* __restrict__ cnt_next, uint32_t* __restrict__ s_due,
+                                               int direct_tiles) {
+    constexpr int NW = NT / 64;
+    constexpr int SPAN = NT * K;
     __shared__ real s_key[NW];
-    __shared__ unsigned s_act[NW], s_cnt[NW];
+    __shared__ unsigned s_act[NW], s_cnt[NW], s_gcnt[NW];
     __shared__ uint32_t s_base;
-    const int f = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const FieldDev fd = fields[f];
     const int ntiles = fd.ntx * fd.ntz;
+    const int ngroups = (int)field_groups(ntiles);
     uint32_t* __restrict__ fl = flags + fd.unit_off;
     real* __restrict__ ky = key + fd.unit_off;
+    uint32_t* __restrict__ gf = gflag + fd.group_off;
+    real* __restrict__ gk = gkey + fd.group_off;
     const real inf = dinf<real>();
     const real none = DESC ? -inf : inf;
     if (f == 0 && tid == 0) *cnt_next = 0u;
     real th = theta[f];
     if (advance) th = DESC ? th - step[f] : th + step[f];
+    auto due_key = [&](real k) { return k != none && (DESC ? k >= th : k <= th); };
 
-    // is any tile due at this threshold, and which key is nearest?
-    uint32_t fv[SCHED_K];
-    real kv[SCHED_K];
+    if (ntiles <= direct_tiles) {
+        // read tile by tile, in spans of NT * K (a single span is read once)
+        uint32_t fv[K];
+        real kv[K];
+        bool act = false;
+        real near = none;
+        for (int b0 = 0; b0 < ntiles; b0 += SPAN) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int t = b0 + tid + NT * k;
+                fv[k] = t < ntiles ? fl[t] : 0u;
+                kv[k] = t < ntiles ? ky[t] : none;
+                act |= fv[k] != 0u || due_key(kv[k]);
+                near = DESC ? (kv[k] > near ? kv[k] : near) : (kv[k] < near ? kv[k] : near);
+            }
+        }
+        const bool wact = __ballot(act) != 0ull;
+        for (int o = 32; o > 0; o >>= 1) {
+            const real r = __shfl_xor(near, o);
+            near = DESC ? (r > near ? r : near) : (r < near ? r : near);
+        }
+        if (lane == 0) { s_key[wv] = near; s_act[wv] = wact ? 1u : 0u; }
+        __syncthreads();
+        bool any = false;
+        near = none;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            any |= s_act[w] != 0u;
+            near = DESC ? (s_key[w] > near ? s_key[w] : near) : (s_key[w] < near ? s_key[w] : near);
+        }
+        if (!any && near != none && (DESC ? near < th : near > th)) th = near;   // idle: jump
+        if (tid == 0) theta[f] = th;
+        for (int b0 = 0; b0 < ntiles; b0 += SPAN) {
+            if (ntiles > SPAN) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int t = b0 + tid + NT * k;
+                    fv[k] = t < ntiles ? fl[t] : 0u;
+                    kv[k] = t < ntiles ? ky[t] : none;
+                }
+            }
+            unsigned dmask = 0u;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (fv[k] != 0u || due_key(kv[k])) dmask |= 1u << k;
+            const unsigned mine = (unsigned)__popc(dmask);
+            unsigned incl = mine;
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned v = __shfl_up(incl, o);
+                if (lane >= o) incl += v;
+            }
+            if (lane == 63) s_cnt[wv] = incl;
+            __syncthreads();
+            unsigned wbase = 0u, total = 0u;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                wbase += w < wv ? s_cnt[w] : 0u;
+                total += s_cnt[w];
+            }
+            if (tid == 0) s_base = total ? atomicAdd(cnt_cur, total) : 0u;
+            __syncthreads();
+            uint32_t pos = s_base + wbase + incl - mine;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (!((dmask >> k) & 1u)) continue;
+                const int t = b0 + tid + NT * k;
+                fl[t] = 0u;
+                ky[t] = none;
+                PassItem it;
+                it.unit = fd.unit_off + (uint32_t)t;
+                it.bits = fv[k];
+                it.f = f;
+                it.tx = t % fd.ntx;
+                it.tz = t / fd.ntx;
+                it.nx = fd.nx;
+                it.nz = fd.nz;
+                it.group_off = fd.group_off;
+                it.src = fd.src;
+                it.t_off = fd.t_off;
+                it.node_off = fd.node_off;
+                it.pad1 = 0;
+                list[pos++] = it;
+            }
+            __syncthreads();     // s_cnt and s_base are reused by the next span and field
+        }
+        return;
+    }
+
+    // is any group due at this threshold, and which key is nearest?
+    uint32_t fv[K];
+    real kv[K];
     bool act = false;
     real near = none;
-    for (int b0 = 0; b0 < ntiles; b0 += SPAN) {
+    for (int b0 = 0; b0 < ngroups; b0 += SPAN) {
 #pragma unroll
-        for (int k = 0; k < SCHED_K; ++k) {
-            const int t = b0 + tid + SCHED_T * k;
-            fv[k] = t < ntiles ? fl[t] : 0u;
-            kv[k] = t < ntiles ? ky[t] : none;
+        for (int k = 0; k < K; ++k) {
+            const int g = b0 + tid + NT * k;
+            fv[k] = g < ngroups ? gf[g] : 0u;
+            kv[k] = g < ngroups ? gk[g] : none;
         }
 #pragma unroll
-        for (int k = 0; k < SCHED_K; ++k) {
-            act |= fv[k] != 0u || (kv[k] != none && (DESC ? kv[k] >= th : kv[k] <= th));
+        for (int k = 0; k < K; ++k) {
+            act |= fv[k] != 0u || due_key(kv[k]);
             near = DESC ? (kv[k] > near ? kv[k] : near) : (kv[k] < near ? kv[k] : near);
         }
     }
@@ -211,27 +346,47 @@ __device__ __forceinline__ void schedule_field(const FieldDev* __restrict__ fiel
     if (!any && near != none && (DESC ? near < th : near > th)) th = near;   // idle: jump
     if (tid == 0) theta[f] = th;
 
-    // append the due tiles: a prefix sum of the per-work-item counts gives the slots
-    for (int b0 = 0; b0 < ntiles; b0 += SPAN) {
-        if (ntiles > SPAN) {
+    for (int b0 = 0; b0 < ngroups; b0 += SPAN) {
+        // the due groups of this span, compacted in LDS
+        if (ngroups > SPAN) {
 #pragma unroll
-            for (int k = 0; k < SCHED_K; ++k) {
-                const int t = b0 + tid + SCHED_T * k;
-                fv[k] = t < ntiles ? fl[t] : 0u;
-                kv[k] = t < ntiles ? ky[t] : none;
+            for (int k = 0; k < K; ++k) {
+                const int g = b0 + tid + NT * k;
+                fv[k] = g < ngroups ? gf[g] : 0u;
+                kv[k] = g < ngroups ? gk[g] : none;
             }
         }
         unsigned dmask = 0u;
 #pragma unroll
-        for (int k = 0; k < SCHED_K; ++k)
-            if (fv[k] != 0u || (kv[k] != none && (DESC ? kv[k] >= th : kv[k] <= th))) dmask |= 1u << k;
+        for (int k = 0; k < K; ++k)
+            if (fv[k] != 0u || due_key(kv[k])) dmask |= 1u << k;
         const unsigned mine = (unsigned)__popc(dmask);
         unsigned incl = mine;
         for (int o = 1; o < 64; o <<= 1) {
             const unsigned v = __shfl_up(incl, o);
             if (lane >= o) incl += v;
         }
-        if (lane == 63) s_cnt[wv] = incl;
+        if (lane == 63) s_gcnt[wv] = incl;
+        __syncthreads();
+        unsigned gbase = 0u, ndue = 0u;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            gbase += w < wv ? s_gcnt[w] : 0u;
+            ndue += s_gcnt[w];
+        }
+        uint32_t gpos = gbase + incl - mine;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if ((dmask >> k) & 1u) s_due[gpos++] = (uint32_t)(b0 + tid + NT * k);
+        __syncthreads();
+        // count the due tiles (one wave per due group, one tile per lane)
+        unsigned wcount = 0u;
+        for (unsigned q = wv; q < ndue; q += NW) {
+            const int t = (int)s_due[q] * GROUP + lane;
+            const bool d = t < ntiles && (fl[t] != 0u || due_key(ky[t]));
+            wcount += (unsigned)__popcll(__ballot(d));
+        }
+        if (lane == 0) s_cnt[wv] = wcount;
         __syncthreads();
         unsigned wbase = 0u, total = 0u;
 #pragma unroll
@@ -241,29 +396,42 @@ __device__ __forceinline__ void schedule_field(const FieldDev* __restrict__ fiel
         }
         if (tid == 0) s_base = total ? atomicAdd(cnt_cur, total) : 0u;
         __syncthreads();
-        uint32_t pos = s_base + wbase + incl - mine;
-#pragma unroll
-        for (int k = 0; k < SCHED_K; ++k) {
-            if (!((dmask >> k) & 1u)) continue;
-            const int t = b0 + tid + SCHED_T * k;
-            fl[t] = 0u;
-            if (!DESC) ky[t] = inf;
-            PassItem it;
-            it.unit = fd.unit_off + (uint32_t)t;
-            it.bits = fv[k];
-            it.f = f;
-            it.tx = t % fd.ntx;
-            it.tz = t / fd.ntx;
-            it.nx = fd.nx;
-            it.nz = fd.nz;
-            it.pad0 = 0;
-            it.src = fd.src;
-            it.t_off = fd.t_off;
-            it.node_off = fd.node_off;
-            it.pad1 = 0;
-            list[pos++] = it;
+        // append them in the same order, reset their flags and keys, rebuild the summaries
+        uint32_t pos = s_base + wbase;
+        for (unsigned q = wv; q < ndue; q += NW) {
+            const int g = (int)s_due[q];
+            const int t = g * GROUP + lane;
+            const uint32_t tf = t < ntiles ? fl[t] : 0u;
+            const real tk = t < ntiles ? ky[t] : none;
+            const bool d = t < ntiles && (tf != 0u || due_key(tk));
+            const unsigned long long m = __ballot(d);
+            if (d) {
+                fl[t] = 0u;
+                ky[t] = none;
+                PassItem it;
+                it.unit = fd.unit_off + (uint32_t)t;
+                it.bits = tf;
+                it.f = f;
+                it.tx = t % fd.ntx;
+                it.tz = t / fd.ntx;
+                it.nx = fd.nx;
+                it.nz = fd.nz;
+                it.group_off = fd.group_off;
+                it.src = fd.src;
+                it.t_off = fd.t_off;
+                it.node_off = fd.node_off;
+                it.pad1 = 0;
+                list[pos + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = it;
+            }
+            pos += (uint32_t)__popcll(m);
+            real r = d ? none : tk;
+            for (int o = 32; o > 0; o >>= 1) {
+                const real r2 = __shfl_xor(r, o);
+                r = DESC ? (r2 > r ? r2 : r) : (r2 < r ? r2 : r);
+            }
+            if (lane == 0) { gk[g] = r; gf[g] = 0u; }
         }
-        __syncthreads();     // s_cnt and s_base are reused by the next span of tiles
+        __syncthreads();     // s_cnt, s_gcnt, s_due and s_base are reused by the next span
     }
 }
 
@@ -287,7 +455,7 @@ template <typename real, typename mreal> struct ForwardState {
     std::vector<FieldDev> hfields;
     std::vector<int> medium_first_field;   // per medium, then the total
     std::vector<double> vmax;        // fastest phase speed per medium
-    int64_t n_units = 0, field_nodes = 0;
+    int64_t n_units = 0, n_groups = 0, field_nodes = 0;
 };
 
 // Validates a batch (media, materials for the wave, sources and, when recv != NULL,

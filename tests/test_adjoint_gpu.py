@@ -12,8 +12,10 @@ Bars:
     >= 0.99999 and every entry within 1e-4 of the largest.
   - the tomography misfit over a 32 x 32 bilinear control grid (256 x 256 nodes, 32
     sources, 32 receivers): control gradient against the oracle, and against central
-    differences of the GPU forward solve with steps 1e-6 rad (tight) and 1e-3 rad
-    (stencil switches move single entries, so the bar is on the median and the cosine);
+    differences of the GPU forward solve: step 1e-6 rad on 48 controls (tight), step
+    1e-3 rad on all 1024 (the controls whose step crosses a stencil switch, found by a
+    second difference at half the step, are held only through the median over all; the
+    cosine bar applies to the others);
   - the GPU gradient against the ray-path gradient along the GPU's own rays (a different
     discretisation of the same derivative): projected onto 6 x 6 smooth controls, cosine
     at least 0.95 on a 128 x 128 medium, and the same as the oracle's pair within 1e-3.
@@ -164,7 +166,7 @@ def test_misfit_gradient_tomography(solver, orc):
     assert abs(loss.item() - ref_loss) <= 1e-3 * ref_loss
     assert c >= 0.9999
     assert np.abs(gc - gref).max() <= 1e-3 * np.abs(gref).max()
-    # central differences of the GPU forward (float64) on a sample of controls
+    # central differences of the GPU forward (float64): a sample of controls at 1e-6 rad, all at 1e-3
     rng = np.random.default_rng(0)
     sample = rng.choice(nc * nc, 48, replace=False)
     mid64 = torch.from_numpy(m.mat_id).cuda()
@@ -178,27 +180,46 @@ def test_misfit_gradient_tomography(solver, orc):
         return 0.5 * float(((T[:, rows, cols] - obs_d) ** 2).sum().item())
 
     base = m.controls.astype(np.float32).astype(np.float64)
-    ga = gc.flat[sample]
-    for e in (1e-6, 1e-3):
-        fd = []
-        for q in sample:
+
+    def central(qs, e):
+        out = []
+        for q in qs:
             cp, cm = base.copy(), base.copy()
             cp.flat[q] += e
             cm.flat[q] -= e
-            fd.append((loss_at(cp) - loss_at(cm)) / (2 * e))
-        fd = np.array(fd)
-        rel = np.abs(ga - fd) / np.abs(fd).max()
-        print("central differences, step %g (48 controls): cos %.6f, median rel %.3g, max rel %.3g"
-              % (e, _cos(ga, fd), np.median(rel), rel.max()), flush=True)
-        if e < 1e-4:
-            # no stencil switch within the step: the discrete map is differentiated exactly
-            assert _cos(ga, fd) >= 0.99999
-            assert rel.max() <= 1e-3
-        else:
-            # the choice by score makes T piecewise smooth with small jumps, so a 1e-3 rad
-            # step across a switch moves single entries
-            assert _cos(ga, fd) >= 0.98
-            assert np.median(rel) <= 1e-2
+            out.append((loss_at(cp) - loss_at(cm)) / (2 * e))
+        return np.array(out)
+
+    # step 1e-6 rad on the sample: no stencil switch within the step, so the discrete map
+    # is differentiated exactly
+    ga = gc.flat[sample]
+    fd = central(sample, 1e-6)
+    rel = np.abs(ga - fd) / np.abs(fd).max()
+    print("central differences, step 1e-6 (48 controls): cos %.6f, median rel %.3g, max rel %.3g"
+          % (_cos(ga, fd), np.median(rel), rel.max()), flush=True)
+    assert _cos(ga, fd) >= 0.99999
+    assert rel.max() <= 1e-3
+    # step 1e-3 rad (the configuration's) on all 1024 controls.  The choice by score makes
+    # T piecewise smooth with small jumps; a step across a jump gives a difference that
+    # grows like 1/step, and with 256 x 256 nodes under every control about half of the
+    # steps cross one.  Such controls are found by a second difference at half the step
+    # (a smooth entry agrees to O(step^2)); the cosine bar holds on the others, the median
+    # bar over all, both scaled by the largest gradient entry.
+    qs = np.arange(nc * nc)
+    ga = gc.flat[qs]
+    f1, f2 = central(qs, 1e-3), central(qs, 5e-4)
+    scale = np.abs(ga).max()
+    smooth = np.abs(f1 - f2) <= 0.05 * np.abs(f1) + 1e-3 * scale
+    rel = np.abs(ga - f1) / scale
+    cs = _cos(ga[smooth], f1[smooth])
+    print("central differences, step 1e-3 (1024 controls): %d cross a stencil switch; on the others cos %.6f, "
+          "median rel %.3g, max rel %.3g; median rel over all %.3g"
+          % ((~smooth).sum(), cs, np.median(rel[smooth]), rel[smooth].max(), np.median(rel)), flush=True)
+    # measured: 457 of 1024 steps cross a switch; cosine 0.99907 on the others, median
+    # 1.1e-3 there and 4.8e-3 over all
+    assert smooth.sum() >= 0.4 * len(qs)
+    assert cs >= 0.98
+    assert np.median(rel) <= 1e-2
 
 
 def test_bilinear_against_matrices(solver):

@@ -6,16 +6,17 @@ the FP64 oracle.
     and for a second level set, sources in the interior and at the edges (clipped fine
     grids), heterogeneous media;
   - without fine grids the seeded path reproduces the straight-ray box solve bitwise;
-  - mixed arithmetic: within 1e-4 relative (the float32 contract) on the 128 x 128 weld; on
-    the 512 x 512 weld a float32 near-tie flip is measured, so the bar there is on the bulk;
+  - the float32 entry point's default arithmetic (float64 on the nested grids): within
+    1e-4 relative (the float32 contract) on the 128 x 128 weld and on four sources of the
+    512 x 512 weld; pure float32 is reported, not held to the bar;
   - Table 3's set-up (cubic steel, 21 x 21, orientation 0, subgrid sizes 1, 3 and 5 through
     the library's whole-grid refinement): the GPU field equals the oracle's and its error
     is the oracle's, below the printed one;
   - whole-grid refinement (subgrid s = 3, 5) on heterogeneous media: the returned fields
     equal every s-th node of the oracle's solve on its own s-fold medium (float64 within
     1e-12, mixed within 1e-4); an even or too large s is refused;
-  - the 512 x 512 weld with 64 sources: two whole fields against the oracle (float64
-    element-wise, mixed on the bulk).
+  - the 512 x 512 weld with 64 sources: four whole fields against the oracle (float64
+    element-wise, the float32 entry point at 1e-4).
 """
 import math
 
@@ -72,10 +73,12 @@ def test_no_levels_is_the_box_solve(solver):
     m = sm.random_medium(60, 44, 0.2e-3, seed=4, n_mats=3)
     sources = [m.sources[0], (2, 40)]
     mid, ori = _dev(m, torch.float32)
+    # the refined entry point's default arithmetic is float64 (the box solve's F64)
     for R in (0, 2):
-        a, _ = solver.solve_refined(m.h, m.mats, mid, ori, sources, levels=(), start_half_width=R + 0.5)
-        b, _ = solver.solve(m.h, m.mats, mid, ori, sources, src_box_radius=R)
-        assert torch.equal(a, b), R
+        for ar, br in (("mixed", "f64"), ("f64", "f64"), ("f32", "f32")):
+            a, _ = solver.solve_refined(m.h, m.mats, mid, ori, sources, levels=(), start_half_width=R + 0.5, arith=ar)
+            b, _ = solver.solve(m.h, m.mats, mid, ori, sources, src_box_radius=R, arith=br)
+            assert torch.equal(a, b), (R, ar)
 
 
 def test_refined_mixed_vs_oracle(solver, orc):
@@ -151,13 +154,13 @@ def test_subgrid_refusals(solver):
 
 
 def test_refined_weld_full_size(solver, orc):
-    # float64: element-wise parity.  Mixed arithmetic: the stencil choice ranks squares by
-    # the score tau_C - tau_B, not by value, so a near tie in score between two stencils
-    # whose estimates differ by ~1e-6 goes either way with float32 increments.  For the
-    # last source one such flip on the top surface inside the weld, 254 cells from the
-    # source, moves the nodes behind it by up to 4.5e-4 (4.5 % of the nodes above 1e-5).
-    # The bar is therefore on the bulk: median within 1e-6, 90 % within 1e-5, all 1e-3.
+    # float64: element-wise parity.  The float32 entry point's default arithmetic computes
+    # the nested grids in float64 too (with float32 wavefront math a near tie in the score
+    # of two square stencils went the other way for source (508, 0) and moved the nodes
+    # behind it by 4.5e-4), so it is held to the 1e-4 bar on four sources across the top,
+    # that one included; pure float32 is reported, not held to it.
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     m = sm.weld_multi()
     mid, ori = _dev(m, torch.float64)
     print("refined weld %d x %d, %d sources" % (m.nx, m.nz, len(m.sources)), flush=True)
@@ -165,16 +168,20 @@ def test_refined_weld_full_size(solver, orc):
     assert st["converged"] == 1
     T32, st = solver.solve_refined(m.h, m.mats, mid, ori.float(), m.sources)
     assert st["converged"] == 1 and torch.isfinite(T32).all()
-    for k in (0, len(m.sources) - 1):
-        ref = orc.solve_refined(m.h, m.mats, m.mat_id, m.orient, m.sources[k])
+    Tf32, st = solver.solve_refined(m.h, m.mats, mid, ori.float(), m.sources, arith="f32")
+    assert st["converged"] == 1
+    ks = (0, 21, 42, 63)
+    with ThreadPoolExecutor(len(ks)) as pool:
+        refs = list(pool.map(lambda k: orc.solve_refined(m.h, m.mats, m.mat_id, m.orient, m.sources[k]), ks))
+    for k, ref in zip(ks, refs):
         err = _rel(T64[k].cpu().numpy(), ref)
-        got = T32[k].cpu().numpy().astype(np.float64)
         fin = ref > 0
-        rel = np.abs(got - ref)[fin] / ref[fin]
-        print("  source %s: f64 max rel err %.3g; mixed max %.3g, median %.3g, above 1e-5: %.2f %%"
-              % (m.sources[k], err, rel.max(), np.median(rel), 100 * (rel > 1e-5).mean()), flush=True)
+        rel = np.abs(T32[k].cpu().numpy().astype(np.float64) - ref)[fin] / ref[fin]
+        r32 = np.abs(Tf32[k].cpu().numpy().astype(np.float64) - ref)[fin] / ref[fin]
+        print("  source %s: f64 max rel err %.3g; default float32 entry max %.3g; pure f32 max %.3g"
+              % (m.sources[k], err, rel.max(), r32.max()), flush=True)
         assert err <= 1e-12
-        assert np.median(rel) <= 1e-6 and (rel > 1e-5).mean() <= 0.1 and rel.max() <= 1e-3
+        assert rel.max() <= 1e-4
 
 
 def test_refined_errors(solver):
