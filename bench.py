@@ -53,8 +53,8 @@ VECTOR_PEAK_TFLOPS = 78.6
 # program), per launch of the batch128 forward (all launches of one forward, averaged),
 # for the kernel sources with this hash, and the wave-level VALU instructions of the same
 # launches (rocprofv3 --pmc SQ_INSTS_VALU).  Reported as null once the sources differ.
-TRAFFIC = {"sources_sha256_16": None, "fetch_bytes_per_launch": None,
-           "write_bytes_per_launch": None, "valu_wave_insts_per_launch": None}
+TRAFFIC = {"sources_sha256_16": "acf8f5dc377bd4bb", "fetch_bytes_per_launch": 1075972301,
+           "write_bytes_per_launch": 102788915, "valu_wave_insts_per_launch": 2.278e8}
 
 TUNE_CACHE = os.path.join(ROOT, "paper_2302_10988_amd", "tuned_schedules.json")
 
@@ -346,15 +346,15 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    tot = dict(node_updates=0, stencil_evals=0, outer_iters=0, nodes=0)
-    adj = dict(lambda_updates=0, outer_iters=0, ms=0.0, fwd_ms=0.0)
+    tot = dict(node_updates=0, stencil_evals=0, outer_iters=0, nodes=0, tile_visits=0)
+    adj = dict(lambda_updates=0, outer_iters=0, ms=0.0, fwd_ms=0.0, tile_visits=0)
     t0 = time.perf_counter()
     for k in range(args.steps):
         (loss, trec, dth, st), tfa = step()
         f = st["forward"]
         for key in tot:
             tot[key] += f[key]
-        for key in ("lambda_updates", "outer_iters", "ms"):
+        for key in ("lambda_updates", "outer_iters", "ms", "tile_visits"):
             adj[key] += st[key]
         adj["fwd_ms"] += f["ms"]
         log("step %d done, %d + %d passes, forward %.1f ms, forward+adjoint %.1f ms"
@@ -374,6 +374,10 @@ def main():
         "relax_passes_per_step": tot["outer_iters"] / args.steps,
         "adjoint_lambda_updates_per_node": adj["lambda_updates"] / max(tot["nodes"], 1),
         "adjoint_passes_per_step": adj["outer_iters"] / args.steps,
+        "tile_visits_per_pass": tot["tile_visits"] / max(tot["outer_iters"], 1),
+        "updates_per_tile_visit": tot["node_updates"] / max(tot["tile_visits"], 1),
+        "adjoint_tile_visits_per_pass": adj["tile_visits"] / max(adj["outer_iters"], 1),
+        "adjoint_updates_per_tile_visit": adj["lambda_updates"] / max(adj["tile_visits"], 1),
     })
     trec_np = trec.cpu().numpy().astype(np.float64)
 
