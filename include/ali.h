@@ -88,7 +88,11 @@ typedef struct {
                                 scheduling and relaxation phases of a pass, every barrier wait
                                 bounded: a wait past 5 s returns ALI_EDEVICE); 0 (default): one
                                 scheduling and one relaxation launch per pass, replayed from
-                                captured graphs.  Both reach the same fields bit for bit.      */
+                                captured graphs.  Both reach the same fields bit for bit.  The
+                                cooperative launch needs the device's cooperative-launch
+                                resources: while another process holds them (one that has made
+                                such a launch) the runtime refuses it and the call returns
+                                ALI_EDEVICE, naming the refused launch in ali_last_error.      */
     int32_t visit_tiles;     /* most tiles one wave visits at once in a pass with more tiles than
                                 resident waves (their marked nodes share 64-lane chunks): 1..4,
                                 0 (default) = 4.  The fields do not depend on it.              */
@@ -301,8 +305,9 @@ ali_status ali_solve_batch(ali_handle* h, const ali_medium* media, int32_t n_med
    float32, device) under each of ALI_TUNE_CANDIDATES schedules (band_cells, inner_sweeps,
    visit_tiles, persistent) -- (1,2,4,0) (1,2,2,0) (1,2,1,0) (1,4,4,0) (2,2,4,0) (2,4,4,0)
    (1,2,4,1) -- and writes the fastest into *opt (the other fields of *opt are kept and used
-   for every run).  ms_out (host, nullable) receives the time of each candidate.  Every
-   candidate reaches the same fields (the fixed point does not depend on the schedule);
+   for every run).  ms_out (host, nullable) receives the time of each candidate; a
+   persistent candidate whose cooperative launch the runtime refuses is left out (+inf).
+   Every candidate reaches the same fields (the fixed point does not depend on the schedule);
    only the time differs.  The handle keeps the choice per size bucket (powers of two of
    the field count, the largest side and the node-fields, with the arithmetic, wave, speed
    mode and per-node stiffness): a later call for a batch of the same bucket times nothing

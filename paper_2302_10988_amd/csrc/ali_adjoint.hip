@@ -321,7 +321,8 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
         atomicAdd(&counters[2], 1ull);
         atomicAdd(&counters[3], (unsigned long long)n_units);
     }
-    for (uint32_t item = blockIdx.x; item < n_units; item += gridDim.x) {
+    const XcdRange xr = xcd_range(n_units);
+    for (uint32_t item = xr.begin; item < xr.end; item += xr.stride) {
     if (item != blockIdx.x) pi = list[item];
     // opaque inside the item loop, so that per-lane staging offsets are not hoisted out of
     // it and held in registers through the sweeps

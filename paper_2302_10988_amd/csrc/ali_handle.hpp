@@ -29,6 +29,7 @@ struct ali_handle {
     int n_cu = 0;                             // compute units of the device
     long long barrier_timeout_ticks = 0;      // grid-barrier wait limit, ticks of the constant-rate clock
     int wall_clock_khz = 100000;              // rate of that clock
+    bool coop_refused = false;                // the runtime refused the last cooperative launch
     std::map<std::string, hipGraphExec_t> graphs;   // captured pass batches by argument signature
     // autotuner choices by size bucket: candidate index and every candidate's time [ms]
     std::map<std::string, std::pair<int, std::vector<double>>> tuned;
@@ -79,11 +80,16 @@ struct ali_handle {
     }
 };
 
+// A failed runtime call is reported through the handle; the runtime's last-error state is
+// cleared, so that the failure (a refused cooperative launch, say) is not reported again by
+// the error check of a later, unrelated call.
 #define HIPCK(H, call)                                                                 \
     do {                                                                               \
         hipError_t e_ = (call);                                                        \
-        if (e_ != hipSuccess)                                                          \
+        if (e_ != hipSuccess) {                                                        \
+            (void)hipGetLastError();                                                   \
             return (H)->fail(ALI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+        }                                                                              \
     } while (0)
 
 namespace ali {

@@ -235,15 +235,56 @@ constexpr int TILE_LDS = LH * LSTRIDE;
 template <typename real> struct RelaxLds {
     real lt[G_MAX * TILE_LDS];                // staged tiles and halos
     uint16_t clist[G_MAX * NTHREADS];         // packed nodes: tile * NTHREADS + node
-    uint32_t dnext[G_MAX][NODE_WORDS];        // nodes marked for the next sweep
-    uint32_t omask[G_MAX][9][NODE_WORDS];     // marks for each tile's 3x3 neighbourhood
+    uint8_t dnext[G_MAX][NTHREADS];           // one byte per node: marked for the next sweep
+    uint32_t own[G_MAX][NODE_WORDS];          // nodes left marked at the sweep cap
     uint32_t touched[G_MAX][NODE_WORDS];      // nodes whose value changed in this visit
     PassItem s_item[G_MAX];
     real s_th[G_MAX], s_rej[G_MAX];
 };
-// a one-tile visit uses the masks of its tile only; its byte-per-node marks for the next
-// sweep live in the neighbourhood masks of the other tiles
-static_assert(sizeof(uint32_t) * (G_MAX - 1) * 9 * NODE_WORDS >= NTHREADS, "room for one-tile sweep marks");
+
+// Marks that one tile (tx, tz) of an nx x nz field sends to its neighbouring tile
+// (tx + ox, tz + oz), (ox, oz) != (0, 0): the diamond neighbours (offsets (di, dj) with
+// 1 <= |di| + |dj| <= 2) of its changed nodes tw that fall in that tile and inside the
+// grid.  Node masks hold node lz * TX + lx at bit (node & 31) of word node >> 5, so word w
+// is rows 2w and 2w + 1 of the tile, 16 bits each.  Computed on whole rows: each row sits
+// in bits 16..31 of a 64-bit window whose bits 0..15 and 32..47 are the same row of the
+// tiles to the left and right, spread sideways by up to two columns and then down and up
+// by the remaining reach of the diamond.
+__device__ __forceinline__ void cross_marks(const uint32_t (&tw)[NODE_WORDS], int tx, int tz, int nx, int nz,
+                                            int ox, int oz, uint32_t (&out)[NODE_WORDS]) {
+    static_assert(TX == 16 && TZ == 8 && HALO == 2 && NODE_WORDS == 4, "row layout of the node masks");
+    uint64_t h0[TZ], h1[TZ], h2[TZ];          // the row spread by 0, <= 1 and <= 2 columns
+#pragma unroll
+    for (int r = 0; r < TZ; ++r) {
+        const uint64_t w = (uint64_t)((tw[r >> 1] >> ((r & 1) * 16)) & 0xFFFFu) << 16;
+        h0[r] = w;
+        h1[r] = w | (w << 1) | (w >> 1);
+        h2[r] = h1[r] | (w << 2) | (w >> 2);
+    }
+    // rows -2, -1 (the tiles above), 8, 9 (below) and 0..7 (beside) of the spread set
+    const uint64_t up2 = h0[0], up1 = h1[0] | h0[1];
+    const uint64_t dn8 = h1[TZ - 1] | h0[TZ - 2], dn9 = h0[TZ - 1];
+    const int shift = 16 * (ox + 1);
+    const int ncols = nx - (tx + ox) * TX, nrows = nz - (tz + oz) * TZ;
+    const bool exists = tx + ox >= 0 && tz + oz >= 0 && ncols > 0 && nrows > 0;
+    const uint32_t colmask = ncols >= TX ? 0xFFFFu : (ncols > 0 ? (1u << ncols) - 1u : 0u);
+#pragma unroll
+    for (int w = 0; w < NODE_WORDS; ++w) out[w] = 0u;
+#pragma unroll
+    for (int R = 0; R < TZ; ++R) {
+        uint64_t mid = h2[R];
+        if (R >= 1) mid |= h1[R - 1];
+        if (R + 1 < TZ) mid |= h1[R + 1];
+        if (R >= 2) mid |= h0[R - 2];
+        if (R + 2 < TZ) mid |= h0[R + 2];
+        const uint64_t above = R == TZ - 2 ? up2 : (R == TZ - 1 ? up1 : 0ull);
+        const uint64_t below = R == 0 ? dn8 : (R == 1 ? dn9 : 0ull);
+        const uint64_t d = oz < 0 ? above : (oz > 0 ? below : mid);
+        uint32_t bits = (uint32_t)(d >> shift) & colmask;
+        bits = (exists && R < nrows) ? bits : 0u;
+        out[R >> 1] |= bits << (16 * (R & 1));
+    }
+}
 
 // The tiles of one pass of n_units (> 0) listed tiles visited one at a time by this wave
 // (a grid stride over the list), for passes too small to give every wave several tiles:
@@ -261,11 +302,11 @@ __device__ __forceinline__ void relax_single(RelaxLds<real>& L, uint32_t n_units
                                              const uint32_t* __restrict__ fixmask, const mreal* __restrict__ vtab,
                                              unsigned& my_updates, unsigned& my_evals) {
     real* lt = L.lt;
-    uint8_t* dnext = reinterpret_cast<uint8_t*>(&L.omask[1][0][0]);
+    uint8_t* dnext = L.dnext[0];
     uint16_t* clist = L.clist;
-    auto& omask = L.omask[0];
     uint32_t* touched = L.touched[0];
-    for (uint32_t item = blockIdx.x; item < n_units; item += gridDim.x) {
+    const XcdRange xr = xcd_range(n_units);
+    for (uint32_t item = xr.begin; item < xr.end; item += xr.stride) {
     const PassItem pi = (pre && item == blockIdx.x) ? *pre : list[item];
     const uint32_t unit = pi.unit;
     const uint32_t bits = pi.bits;
@@ -305,7 +346,6 @@ __device__ __forceinline__ void relax_single(RelaxLds<real>& L, uint32_t n_units
         const int q = lane + RW * k;
         if (q < LW * LH) lt[(q / LW) * LSTRIDE + q % LW] = sv[k];
     }
-    for (int q = lane; q < 9 * NODE_WORDS; q += RW) omask[q / NODE_WORDS][q % NODE_WORDS] = 0u;
     for (int q = lane; q < NTHREADS; q += RW) dnext[q] = 0;
     if (lane < NODE_WORDS) touched[lane] = 0u;
     const int2 s = pi.src;
@@ -404,57 +444,53 @@ __device__ __forceinline__ void relax_single(RelaxLds<real>& L, uint32_t n_units
         __syncthreads();
     }
 
-    // write back; mark the diamond neighbours of changed nodes in the neighbouring tiles
-    // (and, after the sweep cap, this tile's own unfinished nodes)
-    bool any_out = false;
-    if (!done) {
-#pragma unroll 1
-        for (int q = 0; q < NPL; ++q)
-            if ((dmask >> q) & 1u) {
-                const int node = lane + RW * q;
-                atomicOr(&omask[4][node >> 5], 1u << (node & 31));
-                any_out = true;
-            }
-    }
+    // write back the changed nodes
 #pragma unroll 1
     for (int q = 0; q < NPL; ++q) {
         const int node = lane + RW * q;
-        const int lx = node % TX, lz = node / TX;
-        const int gi = i0 + lx, gj = j0 + lz;
-        if (gi >= nx || gj >= nz) continue;
-        // a node whose value changed (possibly back to where it started) is written back
+        // a node whose value changed (possibly back to where it started) is written back;
+        // only nodes inside the grid are ever evaluated
         if (!((touched[node >> 5] >> (node & 31)) & 1u)) continue;
-        Tf[(int64_t)gj * nx + gi] = lt[(lz + HALO) * LSTRIDE + (lx + HALO)];
-        if (lx >= HALO && lx < TX - HALO && lz >= HALO && lz < TZ - HALO) continue;
+        const int lx = node % TX, lz = node / TX;
+        Tf[(int64_t)(j0 + lz) * nx + (i0 + lx)] = lt[(lz + HALO) * LSTRIDE + (lx + HALO)];
+    }
+    // after the sweep cap, the tile's own unfinished nodes carry over to the next pass
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const int ax = lx + SLOT_DI[k], az = lz + SLOT_DJ[k];
-            if (ax >= 0 && az >= 0 && ax < TX && az < TZ) continue;
-            const int ngi = gi + SLOT_DI[k], ngj = gj + SLOT_DJ[k];
-            if (ngi < 0 || ngj < 0 || ngi >= nx || ngj >= nz) continue;
-            const int ox = ax < 0 ? 0 : (ax < TX ? 1 : 2), oz = az < 0 ? 0 : (az < TZ ? 1 : 2);
-            const int nn = (az - (oz - 1) * TZ) * TX + (ax - (ox - 1) * TX);
-            atomicOr(&omask[oz * 3 + ox][nn >> 5], 1u << (nn & 31));
-            any_out = true;
+    for (int q = 0; q < NPL; ++q) {
+        const unsigned long long m = done ? 0ull : __ballot((dmask >> q) & 1u);
+        if (lane == 0) {
+            L.own[0][2 * q] = (uint32_t)m;
+            L.own[0][2 * q + 1] = (uint32_t)(m >> 32);
         }
     }
     for (int o = 32; o > 0; o >>= 1) {
         const real r2 = __shfl_xor(rej, o);
         rej = r2 < rej ? r2 : rej;
     }
-    const bool out = __ballot(any_out) != 0ull;
     __syncthreads();
-    if (out) {
-        // one lane per (neighbour tile, word): push the node marks and flag the tile
-        for (int q = lane; q < 9 * NODE_WORDS; q += RW) {
-            const uint32_t w = omask[q / NODE_WORDS][q % NODE_WORDS];
-            if (!w) continue;
-            const int o = q / NODE_WORDS;
-            const int ntx2 = tx + o % 3 - 1, ntz2 = tz + o / 3 - 1;
-            const int64_t u2 = (int64_t)unit + (int64_t)(ntz2 - tz) * ntx + (ntx2 - tx);
-            atomicOr(&marks_out[u2 * NODE_WORDS + q % NODE_WORDS], w);
-            flag_tile(flags, gflag, unit - (uint32_t)(tz * ntx + tx), pi.group_off, ntz2 * ntx + ntx2, TF_MARK);
+    // lane o < 9: the marks for neighbourhood slot o (4: the tile itself); push the node
+    // marks and flag the tile
+    if (lane < 9) {
+        const int ox = lane % 3 - 1, oz = lane / 3 - 1;
+        uint32_t w[NODE_WORDS];
+        if (lane == 4) {
+#pragma unroll
+            for (int k = 0; k < NODE_WORDS; ++k) w[k] = L.own[0][k];
+        } else {
+            uint32_t tw[NODE_WORDS];
+#pragma unroll
+            for (int k = 0; k < NODE_WORDS; ++k) tw[k] = touched[k];
+            cross_marks(tw, tx, tz, nx, nz, ox, oz, w);
         }
+        const int64_t u2 = (int64_t)unit + (int64_t)oz * ntx + ox;
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < NODE_WORDS; ++k)
+            if (w[k]) {
+                atomicOr(&marks_out[u2 * NODE_WORDS + k], w[k]);
+                any = true;
+            }
+        if (any) flag_tile(flags, gflag, unit - (uint32_t)(tz * ntx + tx), pi.group_off, (tz + oz) * ntx + tx + ox, TF_MARK);
     }
     if (lane == 0) {
         minrej[unit] = rej;
@@ -479,7 +515,6 @@ __device__ __forceinline__ void relax_visits(RelaxLds<real>& L, uint32_t n_units
     auto& lt = L.lt;
     auto& clist = L.clist;
     auto& dnext = L.dnext;
-    auto& omask = L.omask;
     auto& touched = L.touched;
     auto& s_item = L.s_item;
     auto& s_th = L.s_th;
@@ -490,20 +525,27 @@ __device__ __forceinline__ void relax_visits(RelaxLds<real>& L, uint32_t n_units
     const uint32_t n_visits = (n_units + (uint32_t)G - 1u) / (uint32_t)G;
     const real inf = dinf<real>();
 
-    for (uint32_t visit = blockIdx.x; visit < n_visits; visit += gridDim.x) {
+    static_assert(sizeof(PassItem) == 4 * sizeof(uint4), "a pass-list entry is four 16-byte vectors");
+    const XcdRange xr = xcd_range(n_visits);
+    // the pass-list entries of a visit (lanes 0..4*ng-1, one 16-byte vector each): the
+    // first visit's are read here, each later visit's while the one before it runs
+    uint4 nitem = make_uint4(0u, 0u, 0u, 0u);
+    auto fetch = [&](uint32_t v) {
+        const uint32_t f0 = v * (uint32_t)G;
+        const int n = n_units - f0 < (uint32_t)G ? (int)(n_units - f0) : G;
+        if ((int)threadIdx.x < 4 * n) nitem = reinterpret_cast<const uint4*>(list + f0)[threadIdx.x];
+    };
+    if (xr.begin < xr.end) fetch(xr.begin);
+    for (uint32_t visit = xr.begin; visit < xr.end; visit += xr.stride) {
     // the lane index is made opaque inside the visit loop: otherwise the per-lane staging
     // offsets are hoisted out of the loop and held in registers through the sweeps
     int lane = threadIdx.x;
     asm volatile("" : "+v"(lane));
     const uint32_t first = visit * (uint32_t)G;
     const int ng = n_units - first < (uint32_t)G ? (int)(n_units - first) : G;   // tiles of this visit
-
-    // the visit's pass-list entries (lanes 0..4*ng-1, one 16-byte vector each)
-    if (lane < 4 * ng) {
-        const uint4* src = reinterpret_cast<const uint4*>(list + first) + lane;
-        reinterpret_cast<uint4*>(s_item)[lane] = *src;
-    }
+    if (lane < 4 * ng) reinterpret_cast<uint4*>(s_item)[lane] = nitem;
     __syncthreads();
+    if (visit + xr.stride < xr.end) fetch(visit + xr.stride);
 
     // stage every tile and its halo: all loads of a lane are issued before its first store
     constexpr int SQ = (LW * LH + RW - 1) / RW;
@@ -544,11 +586,9 @@ __device__ __forceinline__ void relax_visits(RelaxLds<real>& L, uint32_t n_units
             if (g < ng && q < LW * LH) lt[g * TILE_LDS + (q / LW) * LSTRIDE + q % LW] = sv[g][k];
         }
     }
-    for (int q = lane; q < G_MAX * 9 * NODE_WORDS; q += RW) (&omask[0][0][0])[q] = 0u;
-    if (lane < G_MAX * NODE_WORDS) {
-        (&dnext[0][0])[lane] = 0u;
-        (&touched[0][0])[lane] = 0u;
-    }
+    static_assert(sizeof(L.dnext) == RW * sizeof(uint64_t), "one 8-byte word of sweep marks per lane");
+    reinterpret_cast<uint64_t*>(&dnext[0][0])[lane] = 0ull;
+    if (lane < G_MAX * NODE_WORDS) (&touched[0][0])[lane] = 0u;
     __syncthreads();
 
     // the nodes of this lane: q = 0 .. NPL * G_MAX - 1, tile q / NPL, node lane + 64 (q % NPL).
@@ -636,80 +676,75 @@ __device__ __forceinline__ void relax_visits(RelaxLds<real>& L, uint32_t n_units
                 for (int k = 0; k < 12; ++k) {
                     const int ax = nlx + SLOT_DI[k], az = nlz + SLOT_DJ[k];
                     if (ax >= 0 && az >= 0 && ax < TX && az < TZ &&
-                        lo <= lt[nme + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]]) {
-                        const int nn = az * TX + ax;
-                        atomicOr(&dnext[g][nn >> 5], 1u << (nn & 31));
-                    }
+                        lo <= lt[nme + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]])
+                        dnext[g][az * TX + ax] = 1;
                 }
             }
             __syncthreads();
         }
-        // collect the marks for the next sweep
+        // collect (and clear) the marks for the next sweep: every node's byte is read by
+        // the lane that owns the node
 #pragma unroll 1
         for (int q = 0; q < NPL * ng; ++q) {
             const int g = q / NPL;
             const int node = lane + RW * (q % NPL);
-            if ((dnext[g][node >> 5] >> (node & 31)) & 1u) dmask |= amask & (1u << q);
+            if (dnext[g][node]) {
+                dnext[g][node] = 0;
+                dmask |= amask & (1u << q);
+            }
         }
-        __syncthreads();
-        if (lane < G_MAX * NODE_WORDS) (&dnext[0][0])[lane] = 0u;
         __syncthreads();
     }
 
-    // write back; mark the diamond neighbours of changed nodes in the neighbouring tiles
-    // (and, after the sweep cap, each tile's own unfinished nodes)
-    bool any_out = false;
-    if (!done) {
-#pragma unroll 1
-        for (int q = 0; q < NPL * ng; ++q)
-            if ((dmask >> q) & 1u) {
-                const int g = q / NPL;
-                const int node = lane + RW * (q % NPL);
-                atomicOr(&omask[g][4][node >> 5], 1u << (node & 31));
-                any_out = true;
-            }
-    }
+    // write back the changed nodes (only nodes inside the grid are ever evaluated)
 #pragma unroll 1
     for (int q = 0; q < NPL * ng; ++q) {
         const int g = q / NPL;
         const int node = lane + RW * (q % NPL);
+        if (!((touched[g][node >> 5] >> (node & 31)) & 1u)) continue;
         const PassItem& pi = s_item[g];
         const int lx = node % TX, lz = node / TX;
-        const int gi = pi.tx * TX + lx, gj = pi.tz * TZ + lz;
-        if (gi >= pi.nx || gj >= pi.nz) continue;
-        // a node whose value changed (possibly back to where it started) is written back
-        if (!((touched[g][node >> 5] >> (node & 31)) & 1u)) continue;
-        T[pi.t_off + (int64_t)gj * pi.nx + gi] = lt[g * TILE_LDS + (lz + HALO) * LSTRIDE + (lx + HALO)];
-        if (lx >= HALO && lx < TX - HALO && lz >= HALO && lz < TZ - HALO) continue;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const int ax = lx + SLOT_DI[k], az = lz + SLOT_DJ[k];
-            if (ax >= 0 && az >= 0 && ax < TX && az < TZ) continue;
-            const int ngi = gi + SLOT_DI[k], ngj = gj + SLOT_DJ[k];
-            if (ngi < 0 || ngj < 0 || ngi >= pi.nx || ngj >= pi.nz) continue;
-            const int ox = ax < 0 ? 0 : (ax < TX ? 1 : 2), oz = az < 0 ? 0 : (az < TZ ? 1 : 2);
-            const int nn = (az - (oz - 1) * TZ) * TX + (ax - (ox - 1) * TX);
-            atomicOr(&omask[g][oz * 3 + ox][nn >> 5], 1u << (nn & 31));
-            any_out = true;
+        T[pi.t_off + (int64_t)(pi.tz * TZ + lz) * pi.nx + (pi.tx * TX + lx)] =
+            lt[g * TILE_LDS + (lz + HALO) * LSTRIDE + (lx + HALO)];
+    }
+    // after the sweep cap, each tile's own unfinished nodes carry over to the next pass
+#pragma unroll 1
+    for (int q = 0; q < NPL * ng; ++q) {
+        const unsigned long long m = done ? 0ull : __ballot((dmask >> q) & 1u);
+        if (lane == 0) {
+            L.own[q / NPL][2 * (q % NPL)] = (uint32_t)m;
+            L.own[q / NPL][2 * (q % NPL) + 1] = (uint32_t)(m >> 32);
         }
     }
-    const bool out = __ballot(any_out) != 0ull;
     __syncthreads();
-    if (out) {
-        // one lane per (tile, neighbour tile, word): push the node marks and flag the tile
-        for (int q = lane; q < ng * 9 * NODE_WORDS; q += RW) {
-            const int g = q / (9 * NODE_WORDS), r = q % (9 * NODE_WORDS);
-            const uint32_t w = omask[g][r / NODE_WORDS][r % NODE_WORDS];
-            if (!w) continue;
-            const PassItem& pi = s_item[g];
-            const int ntx = (pi.nx + TX - 1) / TX;
-            const int o = r / NODE_WORDS;
-            const int ntx2 = pi.tx + o % 3 - 1, ntz2 = pi.tz + o / 3 - 1;
-            const int64_t u2 = (int64_t)pi.unit + (int64_t)(ntz2 - pi.tz) * ntx + (ntx2 - pi.tx);
-            atomicOr(&marks_out[u2 * NODE_WORDS + r % NODE_WORDS], w);
-            flag_tile(flags, gflag, pi.unit - (uint32_t)(pi.tz * ntx + pi.tx), pi.group_off, ntz2 * ntx + ntx2,
-                      TF_MARK);
+    // lane 9 g + o: the marks of tile g for its neighbourhood slot o (4: the tile itself);
+    // push the node marks and flag the tile
+    if (lane < 9 * ng) {
+        const int g = lane / 9, o = lane % 9;
+        const int ox = o % 3 - 1, oz = o / 3 - 1;
+        const PassItem& pi = s_item[g];
+        const int ntx = (pi.nx + TX - 1) / TX;
+        uint32_t w[NODE_WORDS];
+        if (o == 4) {
+#pragma unroll
+            for (int k = 0; k < NODE_WORDS; ++k) w[k] = L.own[g][k];
+        } else {
+            uint32_t tw[NODE_WORDS];
+#pragma unroll
+            for (int k = 0; k < NODE_WORDS; ++k) tw[k] = touched[g][k];
+            cross_marks(tw, pi.tx, pi.tz, pi.nx, pi.nz, ox, oz, w);
         }
+        const int64_t u2 = (int64_t)pi.unit + (int64_t)oz * ntx + ox;
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < NODE_WORDS; ++k)
+            if (w[k]) {
+                atomicOr(&marks_out[u2 * NODE_WORDS + k], w[k]);
+                any = true;
+            }
+        if (any)
+            flag_tile(flags, gflag, pi.unit - (uint32_t)(pi.tz * ntx + pi.tx), pi.group_off,
+                      (pi.tz + oz) * ntx + pi.tx + ox, TF_MARK);
     }
     if (lane < ng) {
         const PassItem& pi = s_item[lane];
@@ -1233,7 +1268,14 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
                         &a_T, &a_flags, &a_minrej, &a_gflag, &a_gkey, &a_marks, &a_nunits, &a_upd, &a_fix, &a_vt,
                         &a_gcap, &a_direct, &a_first, &a_max, &a_bar, &a_err, &a_done, &a_timeout};
         HIPCK(H, hipEventRecord(H->ev2, S));
-        HIPCK(H, hipLaunchCooperativeKernel(kern, dim3((unsigned)grid_p), dim3(RW), args, 0, S));
+        const hipError_t le = hipLaunchCooperativeKernel(kern, dim3((unsigned)grid_p), dim3(RW), args, 0, S);
+        if (le != hipSuccess) {
+            // e.g. while another process holds the device's cooperative-launch resources
+            (void)hipGetLastError();
+            H->coop_refused = true;
+            return H->fail(ALI_EDEVICE, std::string("hipLaunchCooperativeKernel refused the persistent relaxation: ") +
+                                            hipGetErrorString(le));
+        }
         HIPCK(H, hipEventRecord(H->ev3, S));
         uint32_t pflags[2] = {0u, 0u};
         HIPCK(H, hipMemcpyAsync(pflags, d_perr, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, S));
@@ -1560,11 +1602,14 @@ extern "C" ali_status ali_autotune_batch(ali_handle* h, const ali_medium* media,
         o.visit_tiles = TUNE[c][2];
         o.persistent = TUNE[c][3];
         double ms = INFINITY;
-        // two runs: the first may build the candidate's graphs
+        // two runs: the first may build the candidate's graphs.  A persistent candidate whose
+        // cooperative launch the runtime refuses is left out (time +inf).
+        h->coop_refused = false;
         for (int rep = 0; rep < 2; ++rep) {
             ali_solve_stats sst{};
             const ali_status s = solve_dispatch<float, float>(h, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs,
                                                               &o, d_T, &sst);
+            if (s != ALI_OK && o.persistent && h->coop_refused) { ms = INFINITY; break; }
             if (s != ALI_OK) return s;
             ms = sst.ms;
         }

@@ -27,6 +27,23 @@ constexpr int NPL = NTHREADS / RW;            // nodes per lane
 constexpr int NODE_WORDS = NTHREADS / 32;     // 32-bit words of a per-tile node mask
 constexpr int STAT_SLOTS = 256;               // spread of the statistics counters
 
+// Work-group IDs go round-robin over the 8 dies (XCDs) of the chip, each with its own L2.
+// A relaxation launch hands its n list entries (visits) out so that every die works
+// through one contiguous eighth of the list: consecutive entries are neighbouring tiles
+// of one field, whose halos overlap, so they meet in the same L2 instead of being
+// fetched once per die.  Work-group b runs on die b % 8 and takes the entries
+// begin, begin + stride, ... below end.  A grid that is not a multiple of 8 falls back to a
+// plain grid stride.
+constexpr uint32_t N_XCD = 8;
+struct XcdRange { uint32_t begin, end, stride; };
+__device__ __forceinline__ XcdRange xcd_range(uint32_t n) {
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    if (nb % N_XCD != 0u) return XcdRange{b, n, nb};
+    const uint32_t x = b % N_XCD, per = (n + N_XCD - 1u) / N_XCD;
+    const uint32_t lo = x * per, hi = lo + per < n ? lo + per : n;
+    return XcdRange{lo + b / N_XCD, hi, nb / N_XCD};
+}
+
 // per-node constants of the relaxation: GEO_N values of the math type per node, namely
 // cos 2theta, sin 2theta of the symmetry axis and P, Q, R, K4 of the node's material (two
 // unused), so that a node's constants come in two aligned vector loads with no table

