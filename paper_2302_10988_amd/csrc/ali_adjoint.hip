@@ -830,7 +830,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     int iters = 0;
     bool converged = false;
     double relax_ms = 0.0;
-    const int grid_relax = (int)(nunits < (int64_t)32 * H->n_cu ? nunits : (int64_t)32 * H->n_cu);
+    // far more work-groups than are resident (see the forward relaxation)
+    const int grid_relax = (int)(nunits < (int64_t)128 * H->n_cu ? nunits : (int64_t)128 * H->n_cu);
     uint32_t* cnt = (uint32_t*)d_count;
     auto enqueue = [&](int p, bool timed, hipStream_t S) {
         hipLaunchKernelGGL(k_adj_sched, dim3((unsigned)n_fields), dim3(SCHED_T), 0, S, fs.fields, p > 0 ? 1 : 0,

@@ -20,7 +20,7 @@ namespace ali {
 // for slightly more redundant forward updates (5.65 against 5.42 per node).
 constexpr int TX = 16, TZ = 8, HALO = 2;
 constexpr int LW = TX + 2 * HALO, LH = TZ + 2 * HALO;
-constexpr int LSTRIDE = LW + 1;
+constexpr int LSTRIDE = LW;                  // LDS row stride of a staged tile (rows contiguous)
 constexpr int NTHREADS = TX * TZ;             // nodes of a tile
 constexpr int RW = 64;                        // one wave per tile visit
 constexpr int NPL = NTHREADS / RW;            // nodes per lane
