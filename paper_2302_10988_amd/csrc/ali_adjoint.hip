@@ -41,6 +41,11 @@ __host__ __device__ constexpr uint16_t make_code(int kind, unsigned a, unsigned 
     return (uint16_t)(((unsigned)kind << 12) | (c << 8) | (b << 4) | a);
 }
 constexpr uint16_t CODE_NONE = make_code(K_NONE, NO_SLOT, NO_SLOT, NO_SLOT);
+// the kind takes bits 12..13; bit 14 marks a node whose right-hand side g may be nonzero
+// (a receiver), so that the relaxation reads g only there
+constexpr unsigned CODE_KIND_MASK = 0x3u;
+constexpr unsigned CODE_RHS = 1u << 14;
+__host__ __device__ constexpr int code_kind(unsigned code) { return (int)((code >> 12) & CODE_KIND_MASK); }
 
 struct StGeo { int sa, sb, sc, bx, bz, cx, cz, k1, k2; };
 
@@ -304,7 +309,9 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
     __shared__ uint16_t lc[LH * LSTRIDE];
     __shared__ uint8_t dnext[NTHREADS];
     __shared__ uint8_t lpend[NTHREADS];
-    __shared__ double ltn[NTHREADS], lgn[NTHREADS];   // own nodes: travel time, right-hand side
+    // own nodes' travel times for the band test, rounded up to float32 (the band only
+    // orders the evaluations; every use of the time in the schedule reads this value)
+    __shared__ float ltn[NTHREADS];
     __shared__ uint16_t clist[NTHREADS];
     __shared__ uint32_t omask[9][NODE_WORDS];
     __shared__ uint32_t touched[NODE_WORDS];      // nodes whose lambda changed in this visit
@@ -360,10 +367,10 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
         if (mk) marks_in[(int64_t)unit * NODE_WORDS + lane] = 0u;
     }
     const double th = theta[f];
-    // the tile's own nodes: pending state, travel time (band test) and right-hand side,
-    // read with the halo instead of at every evaluation
+    // the tile's own nodes: pending state and travel time (band test), read with the halo
+    // instead of at every evaluation
     uint8_t pdv[NPL];
-    double tv[NPL], gv[NPL];
+    double tv[NPL];
 #pragma unroll
     for (int q = 0; q < NPL; ++q) {
         const int node = lane + RW * q;
@@ -372,7 +379,6 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
         const int64_t p = fo + (int64_t)gj * nx + gi;
         pdv[q] = in ? pend[p] : 0;
         tv[q] = in ? T[p] : 0.0;
-        gv[q] = in ? G[p] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < SQ; ++k) {
@@ -393,8 +399,7 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
         const bool valid = gi < nx && gj < nz;
         const uint8_t pd = pdv[q];
         lpend[node] = pd;
-        ltn[node] = tv[q];
-        lgn[node] = gv[q];
+        ltn[node] = __double2float_ru(tv[q]);
         pmask |= pd ? 1u << q : 0u;
         const bool marked = (__shfl(mk, (node >> 5)) >> (node & 31)) & 1u;
         vmask |= valid ? 1u << q : 0u;
@@ -428,7 +433,9 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
                 lpend[node] = ready ? 0 : 1;
                 if (ready) {
                     ++my_updates;
-                    const double v = pull_lambda(lgn[node], nme, ll, lc, la, lb, lcw);
+                    // the right-hand side: nonzero only at receivers, which the code flags
+                    const double g0 = (lc[nme] & CODE_RHS) ? G[fo + (int64_t)(j0 + nlz) * nx + (i0 + nlx)] : 0.0;
+                    const double v = pull_lambda(g0, nme, ll, lc, la, lb, lcw);
                     if (v != ll[nme]) {
                         ll[nme] = v;
                         atomicOr(&touched[node >> 5], 1u << (node & 31));
@@ -540,7 +547,8 @@ template <typename greal, typename outreal>
 __global__ void k_adj_rhs(int mode, int n_fields, const FieldDev* __restrict__ fields, const int2* __restrict__ rec,
                           const greal* __restrict__ in, const double* __restrict__ T, double* __restrict__ G,
                           outreal* __restrict__ trec, double* __restrict__ lossf, uint32_t* __restrict__ flags,
-                          uint32_t* __restrict__ gflag, double* __restrict__ theta, int banded) {
+                          uint32_t* __restrict__ gflag, double* __restrict__ theta, int banded,
+                          uint32_t* __restrict__ wcode, int wstride) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= n_fields) return;
     const FieldDev fd = fields[f];
@@ -557,6 +565,7 @@ __global__ void k_adj_rhs(int mode, int n_fields, const FieldDev* __restrict__ f
             if (trec) trec[fd.obs_off + r] = (outreal)t;
         }
         G[p] += g;
+        wcode[p * wstride] |= CODE_RHS;
         tmax = T[p] > tmax ? T[p] : tmax;
         const int t = (x.y / TZ) * fd.ntx + (x.x / TX);
         flags[fd.unit_off + t] |= TF_SELF;
@@ -589,7 +598,7 @@ __global__ void k_adj_grad(int64_t N, int f0, int f1, const FieldDev* __restrict
     double s = 0.0;
     for (int f = f0; f < f1; ++f) {
         const int64_t q = fields[f].t_off + p;
-        const int kind = (int)(W[q].code >> 12);
+        const int kind = code_kind(W[q].code);
         if (kind == K_STENCIL || kind == K_FALLBACK) s += lam[q] * wT[q];
     }
     dth[p] = s;
@@ -605,7 +614,7 @@ __global__ void k_adj_grad_a(int64_t N, int f0, int f1, const FieldDev* __restri
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     for (int f = f0; f < f1; ++f) {
         const int64_t q = fields[f].t_off + p;
-        const int kind = (int)(W[q].code >> 12);
+        const int kind = code_kind(W[q].code);
         if (kind == K_STENCIL || kind == K_FALLBACK) {
             const double l = lam[q];
             s0 += l * wA[4 * q + 0];
@@ -820,7 +829,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     hipLaunchKernelGGL((k_adj_rhs<greal, outreal>), dim3((unsigned)((n_fields + 63) / 64)), dim3(64), 0, S,
                        mode, n_fields, fs.fields, (const int2*)d_rec, d_in, (const double*)T, (double*)d_G, d_trec,
                        (double*)d_lossf, (uint32_t*)d_flags, use_groups ? (uint32_t*)d_gflag : nullptr, (double*)d_theta,
-                       banded ? 1 : 0);
+                       banded ? 1 : 0, &((AdjW<mreal>*)d_W)->code, (int)(sizeof(AdjW<mreal>) / sizeof(uint32_t)));
     HIPCK(H, hipGetLastError());
     if (mode == 1 && d_loss)
         hipLaunchKernelGGL(k_adj_loss, dim3((unsigned)((n_media + 63) / 64)), dim3(64), 0, S, (const double*)d_lossf,

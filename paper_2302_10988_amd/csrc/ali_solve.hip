@@ -586,8 +586,9 @@ __device__ __forceinline__ void relax_visits(RelaxLds<real>& L, uint32_t n_units
             if (g < ng && q < LW * LH) lt[g * TILE_LDS + (q / LW) * LSTRIDE + q % LW] = sv[g][k];
         }
     }
-    static_assert(sizeof(L.dnext) == RW * sizeof(uint64_t), "one 8-byte word of sweep marks per lane");
-    reinterpret_cast<uint64_t*>(&dnext[0][0])[lane] = 0ull;
+    static_assert(sizeof(L.dnext) % sizeof(uint64_t) == 0 && sizeof(L.dnext) <= RW * sizeof(uint64_t),
+                  "at most one 8-byte word of sweep marks per lane");
+    if (lane < (int)(sizeof(L.dnext) / sizeof(uint64_t))) reinterpret_cast<uint64_t*>(&dnext[0][0])[lane] = 0ull;
     if (lane < G_MAX * NODE_WORDS) (&touched[0][0])[lane] = 0u;
     __syncthreads();
 
