@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "ali_solve.hpp"
+#include "ali_marks.hpp"
 
 namespace ali {
 
@@ -242,49 +243,8 @@ template <typename real> struct RelaxLds {
     real s_th[G_MAX], s_rej[G_MAX];
 };
 
-// Marks that one tile (tx, tz) of an nx x nz field sends to its neighbouring tile
-// (tx + ox, tz + oz), (ox, oz) != (0, 0): the diamond neighbours (offsets (di, dj) with
-// 1 <= |di| + |dj| <= 2) of its changed nodes tw that fall in that tile and inside the
-// grid.  Node masks hold node lz * TX + lx at bit (node & 31) of word node >> 5, so word w
-// is rows 2w and 2w + 1 of the tile, 16 bits each.  Computed on whole rows: each row sits
-// in bits 16..31 of a 64-bit window whose bits 0..15 and 32..47 are the same row of the
-// tiles to the left and right, spread sideways by up to two columns and then down and up
-// by the remaining reach of the diamond.
-__device__ __forceinline__ void cross_marks(const uint32_t (&tw)[NODE_WORDS], int tx, int tz, int nx, int nz,
-                                            int ox, int oz, uint32_t (&out)[NODE_WORDS]) {
-    static_assert(TX == 16 && TZ == 8 && HALO == 2 && NODE_WORDS == 4, "row layout of the node masks");
-    uint64_t h0[TZ], h1[TZ], h2[TZ];          // the row spread by 0, <= 1 and <= 2 columns
-#pragma unroll
-    for (int r = 0; r < TZ; ++r) {
-        const uint64_t w = (uint64_t)((tw[r >> 1] >> ((r & 1) * 16)) & 0xFFFFu) << 16;
-        h0[r] = w;
-        h1[r] = w | (w << 1) | (w >> 1);
-        h2[r] = h1[r] | (w << 2) | (w >> 2);
-    }
-    // rows -2, -1 (the tiles above), 8, 9 (below) and 0..7 (beside) of the spread set
-    const uint64_t up2 = h0[0], up1 = h1[0] | h0[1];
-    const uint64_t dn8 = h1[TZ - 1] | h0[TZ - 2], dn9 = h0[TZ - 1];
-    const int shift = 16 * (ox + 1);
-    const int ncols = nx - (tx + ox) * TX, nrows = nz - (tz + oz) * TZ;
-    const bool exists = tx + ox >= 0 && tz + oz >= 0 && ncols > 0 && nrows > 0;
-    const uint32_t colmask = ncols >= TX ? 0xFFFFu : (ncols > 0 ? (1u << ncols) - 1u : 0u);
-#pragma unroll
-    for (int w = 0; w < NODE_WORDS; ++w) out[w] = 0u;
-#pragma unroll
-    for (int R = 0; R < TZ; ++R) {
-        uint64_t mid = h2[R];
-        if (R >= 1) mid |= h1[R - 1];
-        if (R + 1 < TZ) mid |= h1[R + 1];
-        if (R >= 2) mid |= h0[R - 2];
-        if (R + 2 < TZ) mid |= h0[R + 2];
-        const uint64_t above = R == TZ - 2 ? up2 : (R == TZ - 1 ? up1 : 0ull);
-        const uint64_t below = R == 0 ? dn8 : (R == 1 ? dn9 : 0ull);
-        const uint64_t d = oz < 0 ? above : (oz > 0 ? below : mid);
-        uint32_t bits = (uint32_t)(d >> shift) & colmask;
-        bits = (exists && R < nrows) ? bits : 0u;
-        out[R >> 1] |= bits << (16 * (R & 1));
-    }
-}
+static_assert(TX == MARK_TX && TZ == MARK_TZ && NODE_WORDS == MARK_WORDS && HALO == 2,
+              "the cross-tile marks are written for 16 x 8 tiles and the diamond of radius 2");
 
 // The tiles of one pass of n_units (> 0) listed tiles visited one at a time by this wave
 // (a grid stride over the list), for passes too small to give every wave several tiles:
