@@ -241,6 +241,8 @@ template <typename real> struct RelaxLds {
     uint32_t touched[G_MAX][NODE_WORDS];      // nodes whose value changed in this visit
     PassItem s_item[G_MAX];
     real s_th[G_MAX], s_rej[G_MAX];
+    real s_lo[G_MAX];                         // smallest old or new value of a change in the tile
+    uint32_t incm[G_MAX][NODE_WORDS];         // nodes whose value went up in this visit
 };
 
 static_assert(TX == MARK_TX && TZ == MARK_TZ && NODE_WORDS == MARK_WORDS && HALO == 2,
@@ -537,6 +539,7 @@ __device__ __forceinline__ void relax_visits(RelaxLds<real>& L, uint32_t n_units
     if (lane < ng) {
         s_th[lane] = theta[s_item[lane].f];
         s_rej[lane] = inf;
+        L.s_lo[lane] = inf;
     }
 #pragma unroll
     for (int g = 0; g < G_MAX; ++g) {
@@ -549,7 +552,10 @@ __device__ __forceinline__ void relax_visits(RelaxLds<real>& L, uint32_t n_units
     static_assert(sizeof(L.dnext) % sizeof(uint64_t) == 0 && sizeof(L.dnext) <= RW * sizeof(uint64_t),
                   "at most one 8-byte word of sweep marks per lane");
     if (lane < (int)(sizeof(L.dnext) / sizeof(uint64_t))) reinterpret_cast<uint64_t*>(&dnext[0][0])[lane] = 0ull;
-    if (lane < G_MAX * NODE_WORDS) (&touched[0][0])[lane] = 0u;
+    if (lane < G_MAX * NODE_WORDS) {
+        (&touched[0][0])[lane] = 0u;
+        (&L.incm[0][0])[lane] = 0u;
+    }
     __syncthreads();
 
     // the nodes of this lane: q = 0 .. NPL * G_MAX - 1, tile q / NPL, node lane + 64 (q % NPL).
@@ -624,6 +630,8 @@ __device__ __forceinline__ void relax_visits(RelaxLds<real>& L, uint32_t n_units
                     chg = true;
                     lo = u < cv ? u : cv;
                     atomicOr(&touched[g][node >> 5], 1u << (node & 31));
+                    lds_min(&L.s_lo[g], lo);
+                    if (u > cv) atomicOr(&L.incm[g][node >> 5], 1u << (node & 31));
                 }
             }
             // every value of the chunk is stored before any neighbour is compared (the
@@ -687,13 +695,34 @@ __device__ __forceinline__ void relax_visits(RelaxLds<real>& L, uint32_t n_units
         const int ntx = (pi.nx + TX - 1) / TX;
         uint32_t w[NODE_WORDS];
         if (o == 4) {
+            // unfinished nodes, and nodes whose value went up: a neighbouring tile may have
+            // skipped marking them against their lower staged value (below)
 #pragma unroll
-            for (int k = 0; k < NODE_WORDS; ++k) w[k] = L.own[g][k];
+            for (int k = 0; k < NODE_WORDS; ++k) w[k] = L.own[g][k] | L.incm[g][k];
         } else {
             uint32_t tw[NODE_WORDS];
 #pragma unroll
             for (int k = 0; k < NODE_WORDS; ++k) tw[k] = touched[g][k];
             cross_marks(tw, pi.tx, pi.tz, pi.nx, pi.nz, ox, oz, w);
+            // The causal filter across tiles, on this visit's staged copy of the neighbour:
+            // a node D whose copy lies below every old and new value of the tile's changes
+            // cannot depend on them.  If D's own tile raised D during this pass (the copy is
+            // then out of date), that tile marks D itself for the next pass (above); a D that
+            // went down or stayed keeps the argument.
+            const real lo_t = L.s_lo[g];
+#pragma unroll
+            for (int k = 0; k < NODE_WORDS; ++k) {
+                uint32_t m = w[k], keep = 0u;
+                while (m) {
+                    const int b = __builtin_ctz(m);
+                    m &= m - 1u;
+                    const int nn = 32 * k + b;   // node of the neighbouring tile
+                    const int ax = nn % TX + TX * ox, az = nn / TX + TZ * oz;
+                    const real td = lt[g * TILE_LDS + (az + HALO) * LSTRIDE + (ax + HALO)];
+                    if (!(td < lo_t)) keep |= 1u << b;
+                }
+                w[k] = keep;
+            }
         }
         const int64_t u2 = (int64_t)pi.unit + (int64_t)oz * ntx + ox;
         bool any = false;
