@@ -302,8 +302,8 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
             double* __restrict__ lam, uint8_t* __restrict__ pend, double* __restrict__ maxdef,
             uint32_t* __restrict__ flags, uint32_t* __restrict__ gflag, double* __restrict__ gkey,
             uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
-            const uint32_t* __restrict__ count, uint32_t* __restrict__ idle, int inner,
-            unsigned long long* __restrict__ counters) {
+            const uint32_t* __restrict__ count, const uint32_t* __restrict__ part_base, uint32_t* __restrict__ idle,
+            int inner, unsigned long long* __restrict__ counters) {
     __shared__ double ll[LH * LSTRIDE];
     __shared__ wreal la[LH * LSTRIDE], lb[LH * LSTRIDE], lcw[LH * LSTRIDE];
     __shared__ uint16_t lc[LH * LSTRIDE];
@@ -315,22 +315,27 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
     __shared__ uint16_t clist[NTHREADS];
     __shared__ uint32_t omask[9][NODE_WORDS];
     __shared__ uint32_t touched[NODE_WORDS];      // nodes whose lambda changed in this visit
+    __shared__ ListMap s_map;                     // where the pass's list entries sit
 
-    // the first entry is read together with the list length (in bounds: the grid never
-    // exceeds the list's capacity; the entry is used only if it is live)
-    PassItem pi = list[blockIdx.x];
-    const uint32_t n_units = *count;
+    const ListMap map = read_list_map(count, part_base);
+    const uint32_t n_units = map.pre[LIST_PARTS];
     if (n_units == 0u) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *idle = 1u;
         return;
     }
+    put_list_map(s_map, map);
+    __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         atomicAdd(&counters[2], 1ull);
         atomicAdd(&counters[3], (unsigned long long)n_units);
     }
     const XcdRange xr = xcd_range(n_units);
+    // the slot of the first entry from the map in registers, each later one looked up in
+    // the LDS copy while the entry before it is visited
+    uint32_t slot = xr.begin < xr.end ? list_slot_reg(map, xr.begin) : 0u;
     for (uint32_t item = xr.begin; item < xr.end; item += xr.stride) {
-    if (item != blockIdx.x) pi = list[item];
+    const PassItem pi = list[slot];
+    if (item + xr.stride < xr.end) slot = __builtin_amdgcn_readfirstlane(list_slot(s_map, item + xr.stride));
     // opaque inside the item loop, so that per-lane staging offsets are not hoisted out of
     // it and held in registers through the sweeps
     int lane = threadIdx.x;
@@ -530,10 +535,11 @@ __global__ void __launch_bounds__(SCHED_T)
 k_adj_sched(const FieldDev* __restrict__ fields, int advance, const double* __restrict__ step,
             uint32_t* __restrict__ flags, double* __restrict__ maxdef, uint32_t* __restrict__ gflag,
             double* __restrict__ gkey, double* __restrict__ theta, PassItem* __restrict__ list,
-            uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next, int direct_tiles) {
+            uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next, const uint32_t* __restrict__ part_base,
+            int direct_tiles) {
     __shared__ uint32_t s_due[SCHED_SPAN];
     schedule_field<true, double, SCHED_T>(blockIdx.x, fields, advance, step, flags, maxdef, gflag, gkey, theta, list,
-                                          cnt_cur, cnt_next, s_due, direct_tiles);
+                                          cnt_cur, cnt_next, part_base, s_due, direct_tiles);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -773,7 +779,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
         !H->scratch("a_gflag", sizeof(uint32_t) * ngroups, &d_gflag) ||
         !H->scratch("a_gkey", sizeof(double) * ngroups, &d_gkey) ||
         !H->scratch("a_list", sizeof(PassItem) * nunits, &d_list) ||
-        !H->scratch("a_count", 2 * sizeof(uint32_t), &d_count) ||
+        !H->scratch("a_count", sizeof(uint32_t) * CNT_WORDS, &d_count) ||
         !H->scratch("a_idle", sizeof(uint32_t), &d_idle) ||
         !H->scratch("a_marks", sizeof(uint32_t) * 2 * NODE_WORDS * nunits, &d_marks) ||
         !H->scratch("a_cnt", (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), &d_cnt))
@@ -802,7 +808,10 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     HIPCK(H, hipMemsetAsync(d_flags, 0, sizeof(uint32_t) * nunits, S));
     HIPCK(H, hipMemsetAsync(d_gflag, 0, sizeof(uint32_t) * ngroups, S));
     HIPCK(H, hipMemsetAsync(d_marks, 0, sizeof(uint32_t) * 2 * NODE_WORDS * nunits, S));
-    HIPCK(H, hipMemsetAsync(d_count, 0, 2 * sizeof(uint32_t), S));
+    HIPCK(H, hipMemsetAsync(d_count, 0, sizeof(uint32_t) * CNT_WORDS, S));
+    const std::vector<uint32_t> part_base = list_part_base(fs.hfields);
+    HIPCK(H, hipMemcpyAsync((uint32_t*)d_count + 2 * CNT_BLOCK, part_base.data(), sizeof(uint32_t) * LIST_PARTS,
+                            hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemsetAsync(d_idle, 0, sizeof(uint32_t), S));
     HIPCK(H, hipMemsetAsync(d_cnt, 0, (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), S));
 
@@ -846,7 +855,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
         hipLaunchKernelGGL(k_adj_sched, dim3((unsigned)n_fields), dim3(SCHED_T), 0, S, fs.fields, p > 0 ? 1 : 0,
                            (const double*)d_step, (uint32_t*)d_flags, (double*)d_maxdef, (uint32_t*)d_gflag,
                            (double*)d_gkey, (double*)d_theta,
-                           (PassItem*)d_list, cnt + (p & 1), cnt + ((p + 1) & 1), direct_tiles);
+                           (PassItem*)d_list, cnt + (p & 1) * CNT_BLOCK, cnt + ((p + 1) & 1) * CNT_BLOCK,
+                           (const uint32_t*)(cnt + 2 * CNT_BLOCK), direct_tiles);
         uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
         uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);
@@ -856,7 +866,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
                            (uint8_t*)d_pend, (double*)d_maxdef, (uint32_t*)d_flags,
                            use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (double*)d_gkey : nullptr, mk_in,
                            mk_out,
-                           (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle, ainner,
+                           (const uint32_t*)(cnt + (p & 1) * CNT_BLOCK), (const uint32_t*)(cnt + 2 * CNT_BLOCK),
+                           (uint32_t*)d_idle, ainner,
                            (unsigned long long*)d_cnt);
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH) + 1], S);
     };

@@ -194,10 +194,10 @@ __global__ void __launch_bounds__(SCHED_T)
 k_sched(const FieldDev* __restrict__ fields, int advance, uint32_t* __restrict__ flags, real* __restrict__ minrej,
         uint32_t* __restrict__ gflag, real* __restrict__ gkey, real* __restrict__ theta, const real* __restrict__ step,
         PassItem* __restrict__ list, uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next,
-        int direct_tiles) {
+        const uint32_t* __restrict__ part_base, int direct_tiles) {
     __shared__ uint32_t s_due[SCHED_SPAN];
     schedule_field<false, real, SCHED_T>(blockIdx.x, fields, advance, step, flags, minrej, gflag, gkey, theta, list,
-                                         cnt_cur, cnt_next, s_due, direct_tiles);
+                                         cnt_cur, cnt_next, part_base, s_due, direct_tiles);
 }
 
 
@@ -243,6 +243,7 @@ template <typename real> struct RelaxLds {
     real s_th[G_MAX], s_rej[G_MAX];
     real s_lo[G_MAX];                         // smallest old or new value of a change in the tile
     uint32_t incm[G_MAX][NODE_WORDS];         // nodes whose value went up in this visit
+    ListMap map;                              // where the pass's list entries sit
 };
 
 static_assert(TX == MARK_TX && TZ == MARK_TZ && NODE_WORDS == MARK_WORDS && HALO == 2,
@@ -250,11 +251,10 @@ static_assert(TX == MARK_TX && TZ == MARK_TZ && NODE_WORDS == MARK_WORDS && HALO
 
 // The tiles of one pass of n_units (> 0) listed tiles visited one at a time by this wave
 // (a grid stride over the list), for passes too small to give every wave several tiles:
-// the list entry lives in scalar registers and the first one may already be loaded (pre,
-// read together with the pass size).  The wave's update and estimate counts are added to
-// my_updates, my_evals.
+// the list entry lives in scalar registers.  The wave's update and estimate counts are
+// added to my_updates, my_evals.
 template <typename real, typename mreal, bool SEEDED, bool TAB>
-__device__ __forceinline__ void relax_single(RelaxLds<real>& L, uint32_t n_units, const PassItem* pre,
+__device__ __forceinline__ void relax_single(RelaxLds<real>& L, uint32_t n_units, const ListMap& map,
                                              const PassItem* __restrict__ list, const mreal* __restrict__ geo_all,
                                              const real* __restrict__ fbt_all, int R, int inner,
                                              const real* __restrict__ theta, real* __restrict__ T,
@@ -268,8 +268,12 @@ __device__ __forceinline__ void relax_single(RelaxLds<real>& L, uint32_t n_units
     uint16_t* clist = L.clist;
     uint32_t* touched = L.touched[0];
     const XcdRange xr = xcd_range(n_units);
+    // the slot of the first entry from the map in registers, each later one looked up in
+    // the LDS copy while the entry before it is visited
+    uint32_t slot = xr.begin < xr.end ? list_slot_reg(map, xr.begin) : 0u;
     for (uint32_t item = xr.begin; item < xr.end; item += xr.stride) {
-    const PassItem pi = (pre && item == blockIdx.x) ? *pre : list[item];
+    const PassItem pi = list[slot];
+    if (item + xr.stride < xr.end) slot = __builtin_amdgcn_readfirstlane(list_slot(L.map, item + xr.stride));
     const uint32_t unit = pi.unit;
     const uint32_t bits = pi.bits;
     const int f = pi.f;
@@ -495,7 +499,8 @@ __device__ __forceinline__ void relax_visits(RelaxLds<real>& L, uint32_t n_units
     auto fetch = [&](uint32_t v) {
         const uint32_t f0 = v * (uint32_t)G;
         const int n = n_units - f0 < (uint32_t)G ? (int)(n_units - f0) : G;
-        if ((int)threadIdx.x < 4 * n) nitem = reinterpret_cast<const uint4*>(list + f0)[threadIdx.x];
+        if ((int)threadIdx.x < 4 * n)
+            nitem = reinterpret_cast<const uint4*>(list + list_slot(L.map, f0 + threadIdx.x / 4u))[threadIdx.x % 4u];
     };
     if (xr.begin < xr.end) fetch(xr.begin);
     for (uint32_t visit = xr.begin; visit < xr.end; visit += xr.stride) {
@@ -771,25 +776,25 @@ k_relax(const PassItem* __restrict__ list, const mreal* __restrict__ geo_all, co
         real* __restrict__ T, uint32_t* __restrict__ flags, real* __restrict__ minrej,
         uint32_t* __restrict__ gflag, real* __restrict__ gkey,
         uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
-        const uint32_t* __restrict__ count, uint32_t* __restrict__ idle,
+        const uint32_t* __restrict__ count, const uint32_t* __restrict__ part_base, uint32_t* __restrict__ idle,
         unsigned long long* __restrict__ counters, const uint32_t* __restrict__ fixmask,
         const mreal* __restrict__ vtab, int slots, int gcap) {
     __shared__ RelaxLds<real> L;
-    // the first entry is read together with the list length (the grid never exceeds the
-    // list's capacity, so the read is in bounds; the entry is used only if it is live)
-    const PassItem pi0 = list[blockIdx.x];
-    const uint32_t n_units = *count;
+    const ListMap map = read_list_map(count, part_base);
+    const uint32_t n_units = map.pre[LIST_PARTS];
     if (n_units == 0u) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *idle = 1u;
         return;
     }
+    put_list_map(L.map, map);
+    __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         atomicAdd(&counters[2], 1ull);                  // passes with work
         atomicAdd(&counters[3], (unsigned long long)n_units);   // tile visits
     }
     unsigned my_updates = 0, my_evals = 0;
     if (gcap <= 1 || n_units < 2u * (uint32_t)slots)
-        relax_single<real, mreal, SEEDED, TAB>(L, n_units, &pi0, list, geo_all, fbt_all, R, inner, theta, T, flags,
+        relax_single<real, mreal, SEEDED, TAB>(L, n_units, map, list, geo_all, fbt_all, R, inner, theta, T, flags,
                                                minrej, gflag, gkey, marks_in, marks_out, fixmask, vtab, my_updates,
                                                my_evals);
     else
@@ -871,14 +876,17 @@ k_relax_persist(const FieldDev* __restrict__ fields, int n_fields, const real* _
         const int pp = first_pass + p;
         for (int f = blockIdx.x; f < n_fields; f += gridDim.x)
             schedule_field<false, real, RW, 2>(f, fields, pp > 0 ? 1 : 0, step, flags, minrej, gflag, gkey, theta, list,
-                                            cnt + (pp & 1), cnt + ((pp + 1) & 1),
-                                            reinterpret_cast<uint32_t*>(L.lt), direct_tiles);
+                                            cnt + (pp & 1) * CNT_BLOCK, cnt + ((pp + 1) & 1) * CNT_BLOCK,
+                                            cnt + 2 * CNT_BLOCK, reinterpret_cast<uint32_t*>(L.lt), direct_tiles);
         if (!grid_sync(bar, gen, err, timeout)) break;
-        const uint32_t n_units = __hip_atomic_load(cnt + (pp & 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const ListMap map = read_list_map<true>(cnt + (pp & 1) * CNT_BLOCK, cnt + 2 * CNT_BLOCK);
+        const uint32_t n_units = map.pre[LIST_PARTS];
         if (n_units == 0u) {
             if (blockIdx.x == 0 && threadIdx.x == 0) *done = 1u;
             break;
         }
+        put_list_map(L.map, map);
+        __syncthreads();
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             atomicAdd(&counters[2], 1ull);
             atomicAdd(&counters[3], (unsigned long long)n_units);
@@ -886,7 +894,7 @@ k_relax_persist(const FieldDev* __restrict__ fields, int n_fields, const real* _
         uint32_t* mk_in = marks + (size_t)(pp & 1) * nunits * NODE_WORDS;
         uint32_t* mk_out = marks + (size_t)((pp + 1) & 1) * nunits * NODE_WORDS;
         if (gcap <= 1 || n_units < 2u * gridDim.x)
-            relax_single<real, mreal, SEEDED, TAB>(L, n_units, nullptr, list, geo_all, fbt_all, R, inner, theta, T,
+            relax_single<real, mreal, SEEDED, TAB>(L, n_units, map, list, geo_all, fbt_all, R, inner, theta, T,
                                                    flags, minrej, gflag, gkey, mk_in, mk_out, fixmask, vtab,
                                                    my_updates, my_evals);
         else
@@ -1017,6 +1025,7 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     }
     F.medium_first_field.push_back((int)F.hfields.size());
     const int n_fields = (int)F.hfields.size();
+    for (int f = 0; f < n_fields; ++f) F.hfields[f].part = list_part_of(f, n_fields);
     const int64_t nunits = units;
     F.n_units = nunits;
     F.n_groups = groups;
@@ -1041,7 +1050,7 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
         !H->scratch("gkey", sizeof(real) * groups, &d_gkey) ||
         !H->scratch("list", sizeof(PassItem) * nunits, &d_list) ||
         !H->scratch("marks", sizeof(uint32_t) * 2 * NODE_WORDS * nunits, &d_marks) ||
-        !H->scratch("count", 2 * sizeof(uint32_t), &d_count) ||
+        !H->scratch("count", sizeof(uint32_t) * CNT_WORDS, &d_count) ||
         !H->scratch("idle", sizeof(uint32_t), &d_idle) ||
         !H->scratch("upd", (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), &d_upd) ||
         !H->scratch("err", sizeof(int), &d_err))
@@ -1058,7 +1067,10 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     HIPCK(H, hipMemsetAsync(d_gflag, 0, sizeof(uint32_t) * groups, S));
     HIPCK(H, hipMemsetAsync(d_marks, 0, sizeof(uint32_t) * 2 * NODE_WORDS * nunits, S));
     HIPCK(H, hipMemsetAsync(d_upd, 0, (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), S));
-    HIPCK(H, hipMemsetAsync(d_count, 0, 2 * sizeof(uint32_t), S));
+    HIPCK(H, hipMemsetAsync(d_count, 0, sizeof(uint32_t) * CNT_WORDS, S));
+    F.part_base = list_part_base(F.hfields);
+    HIPCK(H, hipMemcpyAsync((uint32_t*)d_count + 2 * CNT_BLOCK, F.part_base.data(), sizeof(uint32_t) * LIST_PARTS,
+                            hipMemcpyHostToDevice, S));
     HIPCK(H, hipMemsetAsync(d_idle, 0, sizeof(uint32_t), S));
     HIPCK(H, hipMemsetAsync(d_err, 0, sizeof(int), S));
 
@@ -1177,7 +1189,8 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
                            (const FieldDev*)d_fields, p > 0 ? 1 : 0,
                            (uint32_t*)d_flags, (real*)d_minrej, (uint32_t*)d_gflag, (real*)d_gkey,
                            (real*)d_theta, (const real*)d_step,
-                           (PassItem*)d_list, cnt + (p & 1), cnt + ((p + 1) & 1), direct_tiles);
+                           (PassItem*)d_list, cnt + (p & 1) * CNT_BLOCK, cnt + ((p + 1) & 1) * CNT_BLOCK,
+                           (const uint32_t*)(cnt + 2 * CNT_BLOCK), direct_tiles);
         uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
         uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);
@@ -1187,25 +1200,25 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
             hipLaunchKernelGGL((k_relax<real, mreal, true, true>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
                                (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, R,
                                opt.inner_sweeps, (const real*)d_theta, d_T, (uint32_t*)d_flags, (real*)d_minrej,
-                               use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (real*)d_gkey : nullptr, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
+                               use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (real*)d_gkey : nullptr, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1) * CNT_BLOCK), (const uint32_t*)(cnt + 2 * CNT_BLOCK), (uint32_t*)d_idle,
                                (unsigned long long*)d_upd, d_fixmask, vt, slots, gcap);
         else if (d_fixmask)
             hipLaunchKernelGGL((k_relax<real, mreal, true, false>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
                                (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, R,
                                opt.inner_sweeps, (const real*)d_theta, d_T, (uint32_t*)d_flags, (real*)d_minrej,
-                               use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (real*)d_gkey : nullptr, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
+                               use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (real*)d_gkey : nullptr, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1) * CNT_BLOCK), (const uint32_t*)(cnt + 2 * CNT_BLOCK), (uint32_t*)d_idle,
                                (unsigned long long*)d_upd, d_fixmask, vt, slots, gcap);
         else if (tab)
             hipLaunchKernelGGL((k_relax<real, mreal, false, true>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
                                (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, R,
                                opt.inner_sweeps, (const real*)d_theta, d_T, (uint32_t*)d_flags, (real*)d_minrej,
-                               use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (real*)d_gkey : nullptr, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1)), (uint32_t*)d_idle,
+                               use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (real*)d_gkey : nullptr, mk_in, mk_out, (const uint32_t*)(cnt + (p & 1) * CNT_BLOCK), (const uint32_t*)(cnt + 2 * CNT_BLOCK), (uint32_t*)d_idle,
                                (unsigned long long*)d_upd, d_fixmask, vt, slots, gcap);
         else
             hipLaunchKernelGGL((k_relax<real, mreal, false, false>), dim3((unsigned)grid_relax), dim3(RW), 0, S,
                                (const PassItem*)d_list, (const mreal*)d_geo, (const real*)d_fbt, R, opt.inner_sweeps, (const real*)d_theta, d_T,
                                (uint32_t*)d_flags, (real*)d_minrej, use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (real*)d_gkey : nullptr, mk_in, mk_out,
-                               (const uint32_t*)(cnt + (p & 1)),
+                               (const uint32_t*)(cnt + (p & 1) * CNT_BLOCK), (const uint32_t*)(cnt + 2 * CNT_BLOCK),
                                (uint32_t*)d_idle, (unsigned long long*)d_upd, d_fixmask, vt, slots, gcap);
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH) + 1], S);
     };
@@ -1418,7 +1431,7 @@ static size_t forward_scratch_bytes(const ali_grid& g, int n_src, int n_mats, bo
     req.push_back(sizeof(real) * groups);                          // gkey
     req.push_back(sizeof(PassItem) * units);                       // list
     req.push_back(sizeof(uint32_t) * 2 * NODE_WORDS * units);      // marks
-    req.push_back(2 * sizeof(uint32_t));                           // count
+    req.push_back(sizeof(uint32_t) * CNT_WORDS);                   // count
     req.push_back(sizeof(uint32_t));                               // idle
     req.push_back((4 + 2 * STAT_SLOTS) * sizeof(unsigned long long));   // upd
     req.push_back(sizeof(int));                                    // err

@@ -144,6 +144,7 @@ struct FieldDev {
     int rec_off, n_rec;   // the medium's receivers (gradient calls)
     int obs_off;          // the field's first entry in per-receiver arrays
     int2 src;
+    int part;             // the field's pass-list region
 };
 
 // One entry of a pass list: what a tile visit needs before its first load of field
@@ -159,6 +160,98 @@ struct alignas(16) PassItem {
     int64_t pad1;
 };
 static_assert(sizeof(PassItem) == 64, "pass-list entries are four 16-byte vectors");
+
+// The pass list is kept in LIST_PARTS regions: the fields are split into LIST_PARTS runs of
+// consecutive fields (FieldDev::part), and each run appends its due tiles to its own
+// region, reserving slots on the region's own counter.  A device-scope atomic on one
+// address is served one at a time (~8 ns each): with one counter the reservations of a
+// 4096-field batch queue behind each other, with 8 counters (each on its own 4 KiB page)
+// only behind those of the same run.  Region r starts at slot part_base[r] of the list
+// array (the tiles of the fields of the runs before it, so it can never overflow) and
+// holds that pass's count of it.  The readers take the regions as one list, in region
+// order (entry v of the pass is in region r when pre[r] <= v < pre[r + 1], pre being the
+// running sum of the counts), so the list keeps its field order: the relaxation gives each
+// die one contiguous eighth of it, and the fields of one medium, which share the per-node
+// records, stay on one die's L2 (regions by field number mod 8 spread every medium over
+// all dies and made the batch relaxation 1.6 % slower).
+// The counter buffer of a solve holds CNT_WORDS words: the counters of even passes at
+// word r * CNT_GAP, those of odd passes CNT_BLOCK words further, then the region offsets.
+constexpr int LIST_PARTS = 8;
+constexpr int CNT_GAP = 1024;
+constexpr int CNT_BLOCK = LIST_PARTS * CNT_GAP;
+constexpr int CNT_WORDS = 2 * CNT_BLOCK + LIST_PARTS;
+
+// region of field f of n: LIST_PARTS runs of consecutive fields
+inline int list_part_of(int64_t f, int64_t n) { return (int)(f * LIST_PARTS / n); }
+
+// first slot of every list region for the fields of a call (FieldDev::part set)
+inline std::vector<uint32_t> list_part_base(const std::vector<FieldDev>& fields) {
+    std::vector<uint32_t> cap(LIST_PARTS, 0u), base(LIST_PARTS, 0u);
+    for (size_t f = 0; f < fields.size(); ++f)
+        cap[fields[f].part] += (uint32_t)(fields[f].ntx * fields[f].ntz);
+    for (int r = 1; r < LIST_PARTS; ++r) base[r] = base[r - 1] + cap[r - 1];
+    return base;
+}
+
+// Where one pass's entries sit: pre[r] entries precede region r (pre[LIST_PARTS]: all of
+// them), base[r] is region r's first slot.  Read by each relaxation work-group at its start
+// into scalar registers (uniform values), and copied to LDS for the lookups of later entries.
+struct ListMap {
+    uint32_t pre[LIST_PARTS + 1];
+    uint32_t base[LIST_PARTS];
+};
+
+// The map of one pass from its counters (cnt: that pass's counter block) and the region
+// offsets.  COHERENT: device-scope loads of the counters (a reader in the same launch as
+// the schedulers).
+template <bool COHERENT = false>
+__device__ __forceinline__ ListMap read_list_map(const uint32_t* __restrict__ cnt,
+                                                 const uint32_t* __restrict__ part_base) {
+    ListMap m;
+    m.pre[0] = 0u;
+#pragma unroll
+    for (int r = 0; r < LIST_PARTS; ++r) {
+        uint32_t c;
+        if constexpr (COHERENT)
+            c = __builtin_amdgcn_readfirstlane(__hip_atomic_load(const_cast<uint32_t*>(cnt) + r * CNT_GAP,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        else
+            c = cnt[r * CNT_GAP];
+        m.base[r] = part_base[r];
+        m.pre[r + 1] = m.pre[r] + c;
+    }
+    return m;
+}
+
+// copy of the map in LDS, written by one lane (the work-group synchronises before reading it)
+__device__ __forceinline__ void put_list_map(ListMap& dst, const ListMap& m) {
+    if ((threadIdx.x & 63u) == 0u) {
+#pragma unroll
+        for (int r = 0; r < LIST_PARTS; ++r) {
+            dst.pre[r] = m.pre[r];
+            dst.base[r] = m.base[r];
+        }
+        dst.pre[LIST_PARTS] = m.pre[LIST_PARTS];
+    }
+}
+
+// slot in the list array of entry v (< pre[LIST_PARTS]) of the pass, from the LDS copy
+__device__ __forceinline__ uint32_t list_slot(const ListMap& m, uint32_t v) {
+    int r = 0;
+#pragma unroll
+    for (int q = 1; q < LIST_PARTS; ++q) r += v >= m.pre[q] ? 1 : 0;
+    return m.base[r] + (v - m.pre[r]);
+}
+
+// the same from the map in registers: selects only (an indexed register array would be
+// moved to scratch memory)
+__device__ __forceinline__ uint32_t list_slot_reg(const ListMap& m, uint32_t v) {
+    uint32_t s = m.base[0] + v;
+#pragma unroll
+    for (int q = 1; q < LIST_PARTS; ++q)
+        if (v >= m.pre[q]) s = m.base[q] + (v - m.pre[q]);
+    return s;
+}
 
 constexpr int SCHED_T = 256;  // work-items of a scheduler work-group (one group per field)
 constexpr int SCHED_K = 8;    // scheduler groups per work-item held in registers
@@ -207,7 +300,8 @@ inline int direct_tiles_for(int64_t n_units, int span) { return n_units <= DIREC
 // step, and a tile is due when flagged or its key is at or above the threshold.  When no
 // tile is due the threshold jumps to the nearest key.  Due tiles have their flags cleared
 // and their keys reset (their visit in this pass writes them again) and are appended to
-// the pass list, counted by cnt_cur; cnt_next (the next pass's counter) is cleared here.
+// the field's region of the pass list (part_base), counted by the region's counter in the
+// block cnt_cur; the block cnt_next (the next pass's counters) is cleared here.
 // Fields of at most direct_tiles tiles are read tile by tile (in spans of NT * K); larger
 // ones through the group summaries gflag / gkey, which are exact: a group is due exactly
 // when one of its tiles is; an expanded group's summary is rebuilt from its tiles that
@@ -218,7 +312,8 @@ __device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict
                                                real* __restrict__ key, uint32_t* __restrict__ gflag,
                                                real* __restrict__ gkey, real* __restrict__ theta,
                                                PassItem* __restrict__ list, uint32_t* __restrict__ cnt_cur,
-                                               uint32_t* __restrict__ cnt_next, uint32_t* __restrict__ s_due,
+                                               uint32_t* __restrict__ cnt_next,
+                                               const uint32_t* __restrict__ part_base, uint32_t* __restrict__ s_due,
                                                int direct_tiles) {
     constexpr int NW = NT / 64;
     constexpr int SPAN = NT * K;
@@ -235,7 +330,9 @@ __device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict
     real* __restrict__ gk = gkey + fd.group_off;
     const real inf = dinf<real>();
     const real none = DESC ? -inf : inf;
-    if (f == 0 && tid == 0) *cnt_next = 0u;
+    if (f == 0 && tid < LIST_PARTS) cnt_next[tid * CNT_GAP] = 0u;
+    uint32_t* __restrict__ rcnt = cnt_cur + fd.part * CNT_GAP;   // the field's region
+    PassItem* __restrict__ rlist = list + part_base[fd.part];
     real th = theta[f];
     if (advance) th = DESC ? th - step[f] : th + step[f];
     auto due_key = [&](real k) { return k != none && (DESC ? k >= th : k <= th); };
@@ -299,7 +396,7 @@ __device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict
                 wbase += w < wv ? s_cnt[w] : 0u;
                 total += s_cnt[w];
             }
-            if (tid == 0) s_base = total ? atomicAdd(cnt_cur, total) : 0u;
+            if (tid == 0) s_base = total ? atomicAdd(rcnt, total) : 0u;
             __syncthreads();
             uint32_t pos = s_base + wbase + incl - mine;
 #pragma unroll
@@ -321,7 +418,7 @@ __device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict
                 it.t_off = fd.t_off;
                 it.node_off = fd.node_off;
                 it.pad1 = 0;
-                list[pos++] = it;
+                rlist[pos++] = it;
             }
             __syncthreads();     // s_cnt and s_base are reused by the next span and field
         }
@@ -411,7 +508,7 @@ __device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict
             wbase += w < wv ? s_cnt[w] : 0u;
             total += s_cnt[w];
         }
-        if (tid == 0) s_base = total ? atomicAdd(cnt_cur, total) : 0u;
+        if (tid == 0) s_base = total ? atomicAdd(rcnt, total) : 0u;
         __syncthreads();
         // append them in the same order, reset their flags and keys, rebuild the summaries
         uint32_t pos = s_base + wbase;
@@ -438,7 +535,7 @@ __device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict
                 it.t_off = fd.t_off;
                 it.node_off = fd.node_off;
                 it.pad1 = 0;
-                list[pos + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = it;
+                rlist[pos + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = it;
             }
             pos += (uint32_t)__popcll(m);
             real r = d ? none : tk;
@@ -470,6 +567,7 @@ template <typename real, typename mreal> struct ForwardState {
     const real* fbt = nullptr;       // [medium nodes][4] straight-ray times to 8-neighbours
     const FieldDev* fields = nullptr;
     std::vector<FieldDev> hfields;
+    std::vector<uint32_t> part_base;       // first slot of every pass-list region
     std::vector<int> medium_first_field;   // per medium, then the total
     std::vector<double> vmax;        // fastest phase speed per medium
     int64_t n_units = 0, n_groups = 0, field_nodes = 0;
