@@ -147,8 +147,10 @@ __device__ void stencil_partials_A(const NodeD& n, const StGeo& g, double ta, do
 // ---------------------------------------------------------------------------------------
 // WA: also write dU/dA of every node (4 float64 per node and field, wA[4 q + k]); for a
 // source-box node that is the derivative with respect to the source node's stiffness.
+// Four waves per SIMD (128 registers): left to itself the compiler takes 149 and runs
+// three, and the kernel waits on its dependent float64 chains, not on memory.
 template <typename mreal, typename oreal, bool WA>
-__global__ void __launch_bounds__(NTHREADS)
+__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(4)))
 k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal>* __restrict__ mats_all,
            const uint8_t* __restrict__ mat_id_all, const oreal* __restrict__ orient_all,
            const float* __restrict__ nodeA_all,
