@@ -370,7 +370,7 @@ typedef struct {
      d_dLdtheta     [nz][nx] output (device), summed over all sources
    opt->arith must be ALI_ARITH_MIXED (float32 wavefront math in the forward, float64
    derivatives) or ALI_ARITH_F64; ALI_ARITH_F32 returns ALI_EUNSUPPORTED.  Every receiver
-   must be reached by every source.  Scratch: about 58 bytes per node and source.
+   must be reached by every source.  Scratch: about 62 bytes per node and source.
    Synchronises the stream. */
 ali_status ali_adjoint(ali_handle* h, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
                        const uint8_t* d_mat_id, const float* d_orient, const ali_node* srcs, int32_t n_src,

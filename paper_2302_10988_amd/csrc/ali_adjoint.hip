@@ -13,7 +13,8 @@
 //   1. forward solve (float64 travel times), kept on the device;
 //   2. k_adj_prep: re-derive each node's choice with the forward's own local update on
 //      the final field, and its partial derivatives in float64 (hand-differentiated
-//      estimate formula); one record per node and field;
+//      estimate formula); one record per node and field, and the node's band time (its
+//      travel time rounded up to float32, the only form in which the relaxation reads it);
 //   3. k_adj_relax: tiled relaxation of the lambda equation.  Each evaluation recomputes
 //      lambda(X) from scratch as a sum in a fixed order, so the end state (no value
 //      changes) is the exact solution and independent of the schedule; on a DAG the
@@ -156,7 +157,7 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
            const float* __restrict__ nodeA_all,
            const mreal* __restrict__ geo_all, const double* __restrict__ fbt_all, int R,
            const double* __restrict__ T, AdjW<mreal>* __restrict__ W, double* __restrict__ wT,
-           double* __restrict__ wA, unsigned long long* __restrict__ mismatches) {
+           float* __restrict__ Tb, double* __restrict__ wA, unsigned long long* __restrict__ mismatches) {
     __shared__ double lt[LH * LSTRIDE];
     const uint32_t unit = blockIdx.x;
     const FieldDev fd = fields[field_of_unit(fields, n_fields, unit)];
@@ -264,6 +265,7 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
     w.code = cd;
     W[q] = w;
     wT[q] = t;
+    Tb[q] = __double2float_ru(tD);
     if constexpr (WA) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) wA[4 * q + k] = dA[k];
@@ -300,7 +302,7 @@ __device__ __forceinline__ double pull_lambda(double gsum, int me, const double*
 template <typename wreal>
 __global__ void __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(4)))
 k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W,
-            const double* __restrict__ G, const double* __restrict__ T, const double* __restrict__ theta,
+            const double* __restrict__ G, const float* __restrict__ Tb, const double* __restrict__ theta,
             double* __restrict__ lam, uint8_t* __restrict__ pend, double* __restrict__ maxdef,
             uint32_t* __restrict__ flags, uint32_t* __restrict__ gflag, double* __restrict__ gkey,
             uint32_t* __restrict__ marks_in, uint32_t* __restrict__ marks_out,
@@ -374,10 +376,10 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
         if (mk) marks_in[(int64_t)unit * NODE_WORDS + lane] = 0u;
     }
     const double th = theta[f];
-    // the tile's own nodes: pending state and travel time (band test), read with the halo
-    // instead of at every evaluation
+    // the tile's own nodes: pending state and band time, read with the halo instead of at
+    // every evaluation
     uint8_t pdv[NPL];
-    double tv[NPL];
+    float tv[NPL];
 #pragma unroll
     for (int q = 0; q < NPL; ++q) {
         const int node = lane + RW * q;
@@ -385,7 +387,7 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
         const bool in = gi < nx && gj < nz;
         const int64_t p = fo + (int64_t)gj * nx + gi;
         pdv[q] = in ? pend[p] : 0;
-        tv[q] = in ? T[p] : 0.0;
+        tv[q] = in ? Tb[p] : 0.0f;
     }
 #pragma unroll
     for (int k = 0; k < SQ; ++k) {
@@ -406,7 +408,7 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
         const bool valid = gi < nx && gj < nz;
         const uint8_t pd = pdv[q];
         lpend[node] = pd;
-        ltn[node] = __double2float_ru(tv[q]);
+        ltn[node] = tv[q];
         pmask |= pd ? 1u << q : 0u;
         const bool marked = (__shfl(mk, (node >> 5)) >> (node & 31)) & 1u;
         vmask |= valid ? 1u << q : 0u;
@@ -759,7 +761,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     HIPCK(H, hipEventRecord(H->ev4, S));
     const int64_t nunits = fs.n_units;
 
-    void *d_W, *d_wT, *d_lam, *d_G, *d_dacc, *d_box, *d_lossf, *d_rec, *d_first;
+    void *d_W, *d_wT, *d_Tb, *d_lam, *d_G, *d_dacc, *d_box, *d_lossf, *d_rec, *d_first;
     void *d_flags, *d_list, *d_count, *d_cnt, *d_pend, *d_maxdef, *d_theta, *d_step, *d_idle, *d_marks;
     void *d_gflag, *d_gkey;
     const int64_t ngroups = fs.n_groups;
@@ -767,6 +769,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     bool use_groups = false;
     for (const FieldDev& fd : fs.hfields) use_groups |= fd.ntx * fd.ntz > direct_tiles;
     if (!H->scratch("a_w", sizeof(AdjW<mreal>) * NF, &d_W) || !H->scratch("a_wT", sizeof(double) * NF, &d_wT) ||
+        !H->scratch("a_tb", sizeof(float) * NF, &d_Tb) ||
         !H->scratch("a_lam", sizeof(double) * NF, &d_lam) || !H->scratch("a_G", sizeof(double) * NF, &d_G) ||
         !H->scratch("a_pend", sizeof(uint8_t) * NF, &d_pend) ||
         !H->scratch("a_dth", sizeof(double) * med_nodes, &d_dacc) ||
@@ -822,12 +825,14 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     if (d_dA)
         hipLaunchKernelGGL((k_adj_prep<mreal, oreal, true>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
                            fs.fields, n_fields, fs.mats, d_mat_id, d_orient, opt.d_node_A, fs.geo, fs.fbt,
-                           opt.src_box_radius, (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (double*)d_wA,
+                           opt.src_box_radius, (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (float*)d_Tb,
+                           (double*)d_wA,
                            (unsigned long long*)d_cnt + 1);
     else
         hipLaunchKernelGGL((k_adj_prep<mreal, oreal, false>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
                            fs.fields, n_fields, fs.mats, d_mat_id, d_orient, opt.d_node_A, fs.geo, fs.fbt,
-                           opt.src_box_radius, (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (double*)nullptr,
+                           opt.src_box_radius, (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (float*)d_Tb,
+                           (double*)nullptr,
                            (unsigned long long*)d_cnt + 1);
     HIPCK(H, hipGetLastError());
     hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_G, NF, 0.0);
@@ -864,7 +869,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);
         hipLaunchKernelGGL(k_adj_relax<mreal>, dim3((unsigned)grid_relax), dim3(RW), 0, S,
                            (const PassItem*)d_list, (const AdjW<mreal>*)d_W,
-                           (const double*)d_G, (const double*)T, (const double*)d_theta, (double*)d_lam,
+                           (const double*)d_G, (const float*)d_Tb, (const double*)d_theta, (double*)d_lam,
                            (uint8_t*)d_pend, (double*)d_maxdef, (uint32_t*)d_flags,
                            use_groups ? (uint32_t*)d_gflag : nullptr, use_groups ? (double*)d_gkey : nullptr, mk_in,
                            mk_out,
