@@ -23,6 +23,7 @@
 //      (deterministic), plus the source-box terms; k_adj_grad_a / k_adj_box_a do the same
 //      for dL/dA = lambda(D) dU_D/dA_D, whose partials k_adj_prep writes when asked.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 #include <string>
@@ -564,6 +565,12 @@ __global__ void k_adj_rhs(int mode, int n_fields, const FieldDev* __restrict__ f
     const FieldDev fd = fields[f];
     double L = 0.0;
     double tmax = -dinf<double>();
+    // G is read only where the code carries CODE_RHS, so only the receiver nodes are
+    // cleared (receivers on one node add up)
+    for (int r = 0; r < fd.n_rec; ++r) {
+        const int2 x = rec[fd.rec_off + r];
+        G[fd.t_off + (int64_t)x.y * fd.nx + x.x] = 0.0;
+    }
     for (int r = 0; r < fd.n_rec; ++r) {
         const int2 x = rec[fd.rec_off + r];
         const int64_t p = fd.t_off + (int64_t)x.y * fd.nx + x.x;
@@ -691,25 +698,44 @@ __global__ void k_adj_box_a(const FieldDev* __restrict__ fields, int R, const do
     if (threadIdx.x < 4) boxsum[4 * f + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// one work-item adds the stiffness box terms at the source nodes in field order
-__global__ void k_adj_box_add_a(int n_fields, const FieldDev* __restrict__ fields,
-                                const double* __restrict__ boxsum, double* __restrict__ dA) {
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (int f = 0; f < n_fields; ++f) {
-            const FieldDev& fd = fields[f];
-            const int64_t p = fd.node_off + (int64_t)fd.src.y * fd.nx + fd.src.x;
-            for (int c = 0; c < 4; ++c) dA[4 * p + c] += boxsum[4 * f + c];
-        }
+// The box terms are added at the source nodes in field order: one work-item per medium
+// when the media's node ranges are disjoint (each node then sees its terms in field order),
+// else one work-item for all (media may share nodes).
+__device__ __forceinline__ bool box_add_range(int n_media, const int* __restrict__ first, bool disjoint, int& f0,
+                                              int& f1) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (disjoint) {
+        if (m >= n_media) return false;
+        f0 = first[m];
+        f1 = first[m + 1];
+        return true;
+    }
+    f0 = 0;
+    f1 = first[n_media];
+    return m == 0;
 }
 
-// one work-item adds the box terms at the source nodes in field order
-__global__ void k_adj_box_add(int n_fields, const FieldDev* __restrict__ fields, const double* __restrict__ boxsum,
+__global__ void k_adj_box_add_a(int n_media, const int* __restrict__ first, int disjoint,
+                                const FieldDev* __restrict__ fields, const double* __restrict__ boxsum,
+                                double* __restrict__ dA) {
+    int f0, f1;
+    if (!box_add_range(n_media, first, disjoint != 0, f0, f1)) return;
+    for (int f = f0; f < f1; ++f) {
+        const FieldDev& fd = fields[f];
+        const int64_t p = fd.node_off + (int64_t)fd.src.y * fd.nx + fd.src.x;
+        for (int c = 0; c < 4; ++c) dA[4 * p + c] += boxsum[4 * f + c];
+    }
+}
+
+__global__ void k_adj_box_add(int n_media, const int* __restrict__ first, int disjoint,
+                              const FieldDev* __restrict__ fields, const double* __restrict__ boxsum,
                               double* __restrict__ dth) {
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (int f = 0; f < n_fields; ++f) {
-            const FieldDev& fd = fields[f];
-            dth[fd.node_off + (int64_t)fd.src.y * fd.nx + fd.src.x] += boxsum[f];
-        }
+    int f0, f1;
+    if (!box_add_range(n_media, first, disjoint != 0, f0, f1)) return;
+    for (int f = f0; f < f1; ++f) {
+        const FieldDev& fd = fields[f];
+        dth[fd.node_off + (int64_t)fd.src.y * fd.nx + fd.src.x] += boxsum[f];
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -743,6 +769,15 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     for (int m = 0; m < n_media; ++m) {
         med_nodes = std::max(med_nodes, media[m].node_offset + (int64_t)media[m].grid.nx * media[m].grid.nz);
         n_recv_total = std::max(n_recv_total, media[m].rec_offset + media[m].n_rec);
+    }
+    // do the media's node ranges overlap? (the box terms are then added by one work-item)
+    bool disjoint = true;
+    {
+        std::vector<std::pair<int64_t, int64_t>> rng(n_media);
+        for (int m = 0; m < n_media; ++m)
+            rng[m] = std::make_pair(media[m].node_offset, media[m].node_offset + (int64_t)media[m].grid.nx * media[m].grid.nz);
+        std::sort(rng.begin(), rng.end());
+        for (int m = 1; m < n_media; ++m) disjoint &= rng[m].first >= rng[m - 1].second;
     }
 
     // forward fields in float64: the caller's buffer when it is float64, else scratch
@@ -835,7 +870,6 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
                            (double*)nullptr,
                            (unsigned long long*)d_cnt + 1);
     HIPCK(H, hipGetLastError());
-    hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_G, NF, 0.0);
     hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_lam, NF, 0.0);
     hipLaunchKernelGGL((k_fill<uint8_t>), dim3(gNF), dim3(B), 0, S, (uint8_t*)d_pend, NF, (uint8_t)0);
     hipLaunchKernelGGL((k_fill<double>), dim3((unsigned)((nunits + B - 1) / B)), dim3(B), 0, S, (double*)d_maxdef,
@@ -920,8 +954,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     }
     hipLaunchKernelGGL(k_adj_box, dim3((unsigned)n_fields), dim3(256), 0, S, fs.fields, opt.src_box_radius,
                        (const double*)d_wT, (const double*)d_lam, (double*)d_box);
-    hipLaunchKernelGGL(k_adj_box_add, dim3(1), dim3(64), 0, S, n_fields, fs.fields, (const double*)d_box,
-                       (double*)d_dacc);
+    hipLaunchKernelGGL(k_adj_box_add, dim3((unsigned)((n_media + 63) / 64)), dim3(64), 0, S, n_media,
+                       (const int*)d_first, disjoint ? 1 : 0, fs.fields, (const double*)d_box, (double*)d_dacc);
     for (int m = 0; m < n_media; ++m) {
         const int64_t N = (int64_t)media[m].grid.nx * media[m].grid.nz;
         hipLaunchKernelGGL((k_convert<outreal, double>), dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, S,
@@ -938,7 +972,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
         }
         hipLaunchKernelGGL(k_adj_box_a, dim3((unsigned)n_fields), dim3(256), 0, S, fs.fields, opt.src_box_radius,
                            (const double*)d_wA, (const double*)d_lam, (double*)d_boxa);
-        hipLaunchKernelGGL(k_adj_box_add_a, dim3(1), dim3(64), 0, S, n_fields, fs.fields, (const double*)d_boxa,
+        hipLaunchKernelGGL(k_adj_box_add_a, dim3((unsigned)((n_media + 63) / 64)), dim3(64), 0, S, n_media,
+                           (const int*)d_first, disjoint ? 1 : 0, fs.fields, (const double*)d_boxa,
                            (double*)d_aacc);
         for (int m = 0; m < n_media; ++m) {
             const int64_t N4 = 4 * (int64_t)media[m].grid.nx * media[m].grid.nz;
