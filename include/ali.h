@@ -424,6 +424,31 @@ ali_status ali_misfit_gradient_f64(ali_handle* h, const ali_grid* grid, const al
                                    const double* d_obs, const ali_options* opt, double* d_T, double* d_Trec,
                                    double* d_loss, double* d_dLdtheta, ali_adjoint_stats* stats);
 
+/* ali_misfit_gradient of the forward on the medium refined s-fold (Section 4.5's subgrid
+   size s; the forward of ali_solve_traveltime_refined with ref->subgrid = s and no nested
+   source grids): the ((nx - 1) s + 1) x ((nz - 1) s + 1) grid of spacing h / s whose nodes
+   take the material and orientation of the nearest node, the sources and receivers on its
+   nodes (s i, s j) and the straight-ray source box of opt->src_box_radius fine nodes.  Each
+   node's orientation reaches the fine nodes nearest to it, so d_dLdtheta [nz][nx] is the
+   s-fold grid's gradient summed over those nodes (the chain rule through the refinement).
+     subgrid        1 (ali_misfit_gradient itself) or odd in [3, 15]; else ALI_EINVAL
+     d_T            [n_src][nz][nx] the s-fold fields at the nodes (device, nullable)
+   Every other argument as ali_misfit_gradient; opt->d_node_A returns ALI_EUNSUPPORTED.
+   Scratch: that of ali_misfit_gradient on the s-fold grid plus 9 bytes per fine node
+   (float64 entry: 17) and, with d_T, one travel time per fine node and source.
+   Synchronises the stream. */
+ali_status ali_misfit_gradient_subgrid(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                       int32_t n_mats, const uint8_t* d_mat_id, const float* d_orient,
+                                       const ali_node* srcs, int32_t n_src, const ali_node* recv, int32_t n_recv,
+                                       const float* d_obs, const ali_options* opt, int32_t subgrid, float* d_T,
+                                       float* d_Trec, double* d_loss, float* d_dLdtheta, ali_adjoint_stats* stats);
+ali_status ali_misfit_gradient_subgrid_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                           int32_t n_mats, const uint8_t* d_mat_id, const double* d_orient,
+                                           const ali_node* srcs, int32_t n_src, const ali_node* recv,
+                                           int32_t n_recv, const double* d_obs, const ali_options* opt,
+                                           int32_t subgrid, double* d_T, double* d_Trec, double* d_loss,
+                                           double* d_dLdtheta, ali_adjoint_stats* stats);
+
 /* ali_misfit_gradient plus dL/dA [nz][nx][4] of every node's stiffness (as
    ali_adjoint_stiffness; NULL is an error). */
 ali_status ali_misfit_gradient_stiffness(ali_handle* h, const ali_grid* grid, const ali_material* mats,

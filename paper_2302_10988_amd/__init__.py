@@ -343,10 +343,12 @@ class Solver:
 
     def misfit_gradient(self, h, mats, mat_id, orient, sources, receivers, obs, precision="f32",
                         T_out=None, src_box_radius=None, max_sweeps=None, inner_sweeps=None,
-                        band_cells=None, arith="mixed", stiffness=False, **extra):
+                        band_cells=None, arith="mixed", stiffness=False, subgrid=1, **extra):
         """Forward + adjoint of L = 1/2 sum (T_s(r) - obs[s, r])^2 in one call; the forward
         fields go to T_out [n_src, nz, nx] when given.  stiffness=True returns (dLdtheta,
-        dLdA [nz, nx, 4]) in place of dLdtheta (as adjoint).
+        dLdA [nz, nx, 4]) in place of dLdtheta (as adjoint).  subgrid = s (odd) runs the
+        forward and adjoint on the medium refined s-fold and sums the gradient back onto the
+        nodes (ali_misfit_gradient_subgrid; orientation only).
         Returns (loss float64 device scalar, Trec [n_src, n_rec], dLdtheta [nz, nx], stats)."""
         import torch
         nz, nx = mat_id.shape
@@ -369,6 +371,14 @@ class Solver:
                 _dev_ptr(obs, fdt, (ns, nr), "obs"), ctypes.byref(opt),
                 _dev_ptr(T_out, fdt, (ns, nz, nx), "T_out") if T_out is not None else None, _dev_ptr(trec, fdt),
                 _dev_ptr(loss, torch.float64), _dev_ptr(dth, fdt)]
+        if subgrid != 1:
+            if stiffness:
+                raise ValueError("the subgrid misfit gradient differentiates orientation only")
+            fn = (self._lib.ali_misfit_gradient_subgrid if precision == "f32"
+                  else self._lib.ali_misfit_gradient_subgrid_f64)
+            st = fn(*args[:12], int(subgrid), *args[12:], ctypes.byref(stats))
+            self._check(st)
+            return loss, trec, dth, stats.as_dict()
         if stiffness:
             dA = torch.empty((nz, nx, 4), dtype=fdt, device=dev)
             fn = (self._lib.ali_misfit_gradient_stiffness if precision == "f32"

@@ -149,6 +149,14 @@ SIGNATURES = {
                                                ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
                                                ctypes.POINTER(Options), _P, _P, _P, _P,
                                                ctypes.POINTER(AdjointStats)]),
+    "ali_misfit_gradient_subgrid": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P, _P,
+                                                   ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
+                                                   ctypes.POINTER(Options), _I32, _P, _P, _P, _P,
+                                                   ctypes.POINTER(AdjointStats)]),
+    "ali_misfit_gradient_subgrid_f64": (ctypes.c_int, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Material), _I32, _P,
+                                                       _P, ctypes.POINTER(Node), _I32, ctypes.POINTER(Node), _I32, _P,
+                                                       ctypes.POINTER(Options), _I32, _P, _P, _P, _P,
+                                                       ctypes.POINTER(AdjointStats)]),
     "ali_solve_batch": (ctypes.c_int, [_P, ctypes.POINTER(Medium), _I32, ctypes.POINTER(Material), _I32, _P, _P,
                                        ctypes.POINTER(Node), ctypes.POINTER(Options), _P, ctypes.POINTER(SolveStats)]),
     "ali_misfit_gradient_batch": (ctypes.c_int, [_P, ctypes.POINTER(Medium), _I32, ctypes.POINTER(Material), _I32,

@@ -444,6 +444,83 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     return st;
 }
 
+// dL/dtheta of the working grid from the s-fold grid's: every fine node takes the
+// orientation of its nearest working node, so a working node's derivative is the sum over
+// the fine nodes within (s - 1) / 2 of its position (s odd: the nearest node is unique),
+// added row by row in a fixed order
+template <typename outreal>
+__global__ void k_subgrid_sum(int nx, int nz, int nx_s, int nz_s, int s, const outreal* __restrict__ g_s,
+                              outreal* __restrict__ g) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)nx * nz) return;
+    const int i = (int)(p % nx), j = (int)(p / nx), r = (s - 1) / 2;
+    const int a0 = i * s - r < 0 ? 0 : i * s - r, a1 = i * s + r < nx_s - 1 ? i * s + r : nx_s - 1;
+    const int b0 = j * s - r < 0 ? 0 : j * s - r, b1 = j * s + r < nz_s - 1 ? j * s + r : nz_s - 1;
+    double acc = 0.0;
+    for (int b = b0; b <= b1; ++b)
+        for (int a = a0; a <= a1; ++a) acc += (double)g_s[(int64_t)b * nx_s + a];
+    g[p] = (outreal)acc;
+}
+
+// The misfit gradient of the forward on the s-fold grid (Section 4.5's subgrid size with the
+// straight-ray source box counted in fine nodes): the fine medium is built as for the
+// refined forward, the single-medium misfit gradient `grad` runs on it with the sources and
+// receivers on the nodes (s i, s j), and its dL/dtheta is summed back onto the working nodes.
+template <typename oreal, typename outreal, typename F>
+static ali_status subgrid_gradient_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
+                                        const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
+                                        int32_t n_src, const ali_node* recv, int32_t n_recv, const outreal* d_obs,
+                                        const ali_options* opt_in, int32_t s, outreal* d_T, outreal* d_Trec,
+                                        double* d_loss, outreal* d_dth, ali_adjoint_stats* stats, F grad) {
+    if (!grid) return H->fail(ALI_EINVAL, "grid is NULL");
+    if (s == 1)
+        return grad(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, recv, n_recv, d_obs, opt_in, d_T, d_Trec,
+                    d_loss, d_dth, stats);
+    if (s < 3 || s % 2 == 0 || s > 15) return H->fail(ALI_EINVAL, "subgrid must be 1 or odd in [3, 15]");
+    ali_options opt;
+    ali_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (opt.d_node_A) return H->fail(ALI_EUNSUPPORTED, "the subgrid misfit gradient takes per-material stiffness only");
+    if (!d_dth) return H->fail(ALI_EINVAL, "d_dLdtheta is NULL");
+    // the caller's medium, sources and receivers are checked on its own grid first
+    const ali_medium mw = single_medium(grid, n_mats, n_src, n_recv);
+    ali_status st = validate_batch(H, &mw, 1, mats, n_mats, d_mat_id, d_orient, srcs, recv, opt.wave);
+    if (st != ALI_OK) return st;
+    const int64_t nxs = (int64_t)(grid->nx - 1) * s + 1, nzs = (int64_t)(grid->nz - 1) * s + 1;
+    if (nxs * nzs > (int64_t)1 << 31) return H->fail(ALI_EINVAL, "the s-fold grid exceeds 2^31 nodes");
+    ali_grid gs = *grid;
+    gs.nx = (int32_t)nxs;
+    gs.nz = (int32_t)nzs;
+    gs.h = grid->h / s;
+    std::vector<ali_node> ss(srcs, srcs + n_src), rs(recv, recv + n_recv);
+    for (ali_node& q : ss) { q.i *= s; q.j *= s; }
+    for (ali_node& q : rs) { q.i *= s; q.j *= s; }
+    if (set_device(H) != ALI_OK) return ALI_EDEVICE;
+    hipStream_t S = H->stream;
+    const int B = 256;
+    const int64_t NS = nxs * nzs, NW = (int64_t)grid->nx * grid->nz;
+    void *d_mid = nullptr, *d_ori = nullptr, *d_gs = nullptr, *d_Ts = nullptr;
+    if (!H->scratch("sg_mid", NS, &d_mid) || !H->scratch("sg_ori", sizeof(oreal) * NS, &d_ori) ||
+        !H->scratch("sg_dth", sizeof(outreal) * NS, &d_gs) ||
+        (d_T && !H->scratch("sg_T", sizeof(outreal) * NS * n_src, &d_Ts)))
+        return H->fail(ALI_ENOMEM, "device scratch allocation failed");
+    hipLaunchKernelGGL((k_subgrid_medium<oreal>), dim3((unsigned)((NS + B - 1) / B)), dim3(B), 0, S, grid->nx,
+                       gs.nx, NS, s, d_mat_id, d_orient, (const float*)nullptr, (uint8_t*)d_mid, (oreal*)d_ori,
+                       (float*)nullptr);
+    HIPCK(H, hipGetLastError());
+    st = grad(H, &gs, mats, n_mats, (const uint8_t*)d_mid, (const oreal*)d_ori, ss.data(), n_src, rs.data(), n_recv,
+              d_obs, &opt, (outreal*)d_Ts, d_Trec, d_loss, (outreal*)d_gs, stats);
+    if (st != ALI_OK && st != ALI_ENOCONV) return st;
+    hipLaunchKernelGGL((k_subgrid_sum<outreal>), dim3((unsigned)((NW + B - 1) / B)), dim3(B), 0, S, grid->nx,
+                       grid->nz, gs.nx, gs.nz, s, (const outreal*)d_gs, d_dth);
+    if (d_T)
+        hipLaunchKernelGGL((k_subgrid_pick<outreal, outreal>), dim3((unsigned)((NW * n_src + B - 1) / B)), dim3(B), 0,
+                           S, grid->nx, NW, NW * n_src, gs.nx, NS, s, (const outreal*)d_Ts, d_T);
+    HIPCK(H, hipGetLastError());
+    HIPCK(H, hipStreamSynchronize(S));
+    return st;
+}
+
 }  // namespace ali
 
 using namespace ali;
@@ -485,4 +562,28 @@ extern "C" ali_status ali_solve_traveltime_refined_f64(ali_handle* h, const ali_
     if (!h) return ALI_EINVAL;
     return refined_impl<double, double, double, double>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt,
                                                         ref, d_T, stats);
+}
+
+extern "C" ali_status ali_misfit_gradient_subgrid(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                                  int32_t n_mats, const uint8_t* d_mat_id, const float* d_orient,
+                                                  const ali_node* srcs, int32_t n_src, const ali_node* recv,
+                                                  int32_t n_recv, const float* d_obs, const ali_options* opt,
+                                                  int32_t subgrid, float* d_T, float* d_Trec, double* d_loss,
+                                                  float* d_dLdtheta, ali_adjoint_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    return subgrid_gradient_impl<float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, recv, n_recv,
+                                               d_obs, opt, subgrid, d_T, d_Trec, d_loss, d_dLdtheta, stats,
+                                               ali_misfit_gradient);
+}
+
+extern "C" ali_status ali_misfit_gradient_subgrid_f64(ali_handle* h, const ali_grid* grid, const ali_material* mats,
+                                                      int32_t n_mats, const uint8_t* d_mat_id, const double* d_orient,
+                                                      const ali_node* srcs, int32_t n_src, const ali_node* recv,
+                                                      int32_t n_recv, const double* d_obs, const ali_options* opt,
+                                                      int32_t subgrid, double* d_T, double* d_Trec, double* d_loss,
+                                                      double* d_dLdtheta, ali_adjoint_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    return subgrid_gradient_impl<double, double>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, recv,
+                                                 n_recv, d_obs, opt, subgrid, d_T, d_Trec, d_loss, d_dLdtheta, stats,
+                                                 ali_misfit_gradient_f64);
 }
