@@ -12,7 +12,9 @@
  *     dL/dtheta_D += lambda(D) dU_D/dtheta_D.
  * The local partials differentiate the paper's geometric formulas (point E, foot point F,
  * |FD|, normal direction, phase speed at theta') by hand; the group-speed derivative used
- * by straight rays is a Richardson-extrapolated central difference.
+ * by straight rays is a Richardson-extrapolated central difference.  With the velocity
+ * table (Sections 3.2, 4.2) the speeds are the table's piecewise-linear interpolants, and
+ * their derivatives the slopes of the whole-degree intervals (velocity.c: table_slope).
  *
  * The same reverse pass also gives dL/dA for the density-normalised stiffness A = C / rho
  * of every node (A11, A13, A33, A55): a stencil estimate depends on A_D through the phase
@@ -127,11 +129,9 @@ int or_adjoint(int nx, int nz, double h, const or_material* mats, int n_mats, co
                const double* orient, int si, int sj, int R, const double* g, double* T_out,
                double* dtheta, double* dA) {
     int64_t N = (int64_t)nx * nz;
-    for (int k = 0; k < n_mats; ++k)   /* derivatives are of the run-time speeds */
-        if (mats[k].vtab) return -1;
-    if (dA)   /* the stiffness partials are written for the qP wave */
+    if (dA)   /* the stiffness partials are written for the qP wave's run-time speeds */
         for (int k = 0; k < n_mats; ++k)
-            if (mats[k].wave != OR_WAVE_QP) return -1;
+            if (mats[k].wave != OR_WAVE_QP || mats[k].vtab) return -1;
     double* T = T_out ? T_out : malloc(sizeof(double) * (size_t)N);
     int64_t* pop = malloc(sizeof(int64_t) * (size_t)N);
     int64_t npop = or_solve_fmm(nx, nz, h, mats, n_mats, mat_id, orient, si, sj, R, T, pop, NULL);

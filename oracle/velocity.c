@@ -272,16 +272,28 @@ static double table_lookup(const or_material* m, double ang, double (*f)(const o
     return (1.0 - w) * a + w * b;
 }
 
+/* derivative of the table's interpolant in the angle [per radian]: the slope of the
+   whole-degree interval the angle lies in (at a whole degree, the interval above it, as
+   table_lookup reads it) */
+static double table_slope(const or_material* m, double ang, double (*f)(const or_material*, double)) {
+    double d = fmod(ang * (180.0 / M_PI), 180.0);
+    if (d < 0.0) d += 180.0;
+    double i = floor(d);
+    return (f(m, (i + 1.0) * (M_PI / 180.0)) - f(m, i * (M_PI / 180.0))) * (180.0 / M_PI);
+}
+
 double or_phase_speed(const or_material* m, double th_p) {
     return m->vtab ? table_lookup(m, th_p, exact_phase_speed) : exact_phase_speed(m, th_p);
 }
 double or_phase_speed_deriv(const or_material* m, double th_p) {
+    if (m->vtab) return table_slope(m, th_p, exact_phase_speed);
     return m->wave == OR_WAVE_SH ? or_sh_phase_speed_deriv(m, th_p) : or_qp_phase_speed_deriv(m, th_p);
 }
 double or_group_speed(const or_material* m, double phi) {
     return m->vtab ? table_lookup(m, phi, exact_group_speed) : exact_group_speed(m, phi);
 }
 double or_group_speed_deriv(const or_material* m, double phi) {
+    if (m->vtab) return table_slope(m, phi, exact_group_speed);
     return m->wave == OR_WAVE_SH ? or_sh_group_speed_deriv(m, phi) : or_qp_group_speed_deriv(m, phi);
 }
 double or_group_speed_support(const or_material* m, double phi) {
