@@ -90,9 +90,3 @@ def test_table3_table_row_above_runtime_row(orc):
         # the printed table row itself, to the same factor as the run-time row
         lo, hi = (1.05, 1.16) if s == 1 else (1.02, 1.10)
         assert lo <= tb[s] / table3.PRINTED_TABLE[s] <= hi
-
-
-def test_adjoint_refuses_the_table(orc):
-    m = sm.random_medium(12, 12, 0.2e-3, seed=1)
-    with pytest.raises(ValueError):
-        orc.adjoint(m.h, orc.as_table(m.mats), m.mat_id, m.orient, m.sources[0], np.ones((12, 12)))
