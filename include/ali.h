@@ -363,7 +363,10 @@ typedef struct {
        dL/dtheta(D) = sum over sources of lambda(D) dU_D/dtheta(D)
    plus, for the source box, lambda times the derivative of the straight-ray time with
    respect to the source node's orientation.  The result is the exact derivative of the
-   discrete map wherever no stencil choice switches.
+   discrete map wherever no stencil choice switches.  With the velocity table
+   (opt->velocity = ALI_VEL_TABLE, Sections 3.2 and 4.2) the speeds are the table's
+   piecewise-linear interpolants and their derivatives the slopes of the whole-degree
+   intervals (the map has kinks at whole degrees as well).
      recv[n_recv]   receiver nodes (host), inside the grid
      d_dLdT         [n_src][n_recv] dL/dT at the receivers (device)
      d_T            [n_src][nz][nx] forward fields out (device, nullable)
@@ -392,8 +395,9 @@ ali_status ali_adjoint_f64(ali_handle* h, const ali_grid* grid, const ali_materi
    source node.
      d_dLdA         [nz][nx][4] output (device), summed over all sources; NULL is an error
    Gradients w.r.t. C and rho follow by the chain rule: dL/dC = dL/dA / rho and
-   dL/drho = -sum_k A_k dL/dA_k / rho.  Every other argument, the arithmetic, errors and
-   synchronisation as ali_adjoint.  Scratch: 40 more bytes per node and source. */
+   dL/drho = -sum_k A_k dL/dA_k / rho.  The velocity table returns ALI_EUNSUPPORTED.  Every
+   other argument, the arithmetic, errors and synchronisation as ali_adjoint.  Scratch: 40
+   more bytes per node and source. */
 ali_status ali_adjoint_stiffness(ali_handle* h, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
                                  const uint8_t* d_mat_id, const float* d_orient, const ali_node* srcs,
                                  int32_t n_src, const ali_node* recv, int32_t n_recv, const float* d_dLdT,

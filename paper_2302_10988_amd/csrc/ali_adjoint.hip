@@ -144,21 +144,82 @@ __device__ void stencil_partials_A(const NodeD& n, const StGeo& g, double ta, do
     d[3] = k * (2.0 * (gP - gR) + gW);
 }
 
+// The same partials with the velocity table (Sections 3.2 and 4.2): v is the node
+// material's table of phase speed / h at whole degrees of psi, the angle between the
+// wavefront normal and the symmetry axis folded into [0, 90] degrees, linear in between;
+// its derivative is the slope of the interval psi lies in.  cos 2psi' = c / |w|^2 and
+// sin 2psi' = s / |w|^2 for psi' = phi_n - theta (phi_n the normal's direction), and
+// 2 psi = |2 psi'| folded, so d(2 psi) = sign(s) d(2 psi').
+template <typename mreal>
+__device__ void stencil_partials_tab(const NodeD& n, const StGeo& g, const mreal* __restrict__ vt, double ta,
+                                     double tb, double tc, double& dA, double& dB, double& dC, double& dT) {
+    constexpr double DEG = 57.295779513082320877;   // degrees per radian
+    const double Dl = tc - ta;
+    const double a = (tb - ta) / Dl;
+    const double wx = g.bx - a * g.cx, wz = g.bz - a * g.cz;
+    const double cr = g.k1 - a * g.k2;
+    const double w2 = wx * wx + wz * wz;
+    const double dd = wz * wz - wx * wx;
+    const double xz = -2.0 * wx * wz;
+    const double c = dd * n.c2t + xz * n.s2t;
+    const double sn = xz * n.c2t - dd * n.s2t;
+    double cc = c / w2;
+    cc = cc > 1.0 ? 1.0 : (cc < -1.0 ? -1.0 : cc);
+    const double deg = 0.5 * DEG * acos(cc);
+    int i = (int)deg;
+    i = i > 89 ? 89 : i;
+    const double v0 = (double)vt[i], v1 = (double)vt[i + 1];
+    const double v = v0 + (deg - i) * (v1 - v0);
+    const double slope = v1 - v0;                        // dv / dpsi, per degree
+    const double inc = fabs(cr) / (sqrt(w2) * v);
+    const double sg = sn >= 0.0 ? 1.0 : -1.0;
+    // d/da: the normal turns with a, d(2 phi_n) = (dd dxz - xz ddd) / |w|^4
+    const double dwx = -(double)g.cx, dwz = -(double)g.cz, dcr = -(double)g.k2;
+    const double dw2 = 2.0 * (wx * dwx + wz * dwz);
+    const double ddd = 2.0 * (wz * dwz - wx * dwx);
+    const double dxz = -2.0 * (dwx * wz + wx * dwz);
+    const double dpsi_da = 0.5 * DEG * sg * (dd * dxz - xz * ddd) / (w2 * w2);
+    const double dinc = inc * (dcr / cr - 0.5 * dw2 / w2 - slope * dpsi_da / v);
+    dA = dinc * (a - 1.0) / Dl;
+    dB = 1.0 + dinc / Dl;
+    dC = -dinc * a / Dl;
+    // d/dtheta at fixed a: d(2 psi') = -2 dtheta
+    dT = inc * slope * sg * DEG / v;
+}
+
+// group speed from the table gt (whole degrees of the group angle folded into [0, 90],
+// linear in between; as group_speed_tab) and its derivative in phi
+__device__ inline double group_speed_tab_d(const double* __restrict__ gt, double phi, double* dV) {
+    const double pi = 3.14159265358979323846;
+    double a = fmod(fabs(phi), pi);
+    double da = phi >= 0.0 ? 1.0 : -1.0;
+    if (a > 0.5 * pi) { a = pi - a; da = -da; }
+    const double deg = a * (180.0 / pi);
+    int i = (int)deg;
+    i = i > 89 ? 89 : i;
+    const double w = deg - i;
+    *dV = (gt[i + 1] - gt[i]) * (180.0 / pi) * da;
+    return w == 0.0 ? gt[i] : (1.0 - w) * gt[i] + w * gt[i + 1];
+}
+
 // ---------------------------------------------------------------------------------------
 // step 2: choices and partial derivatives, one work-group per (tile, field)
 // ---------------------------------------------------------------------------------------
 // WA: also write dU/dA of every node (4 float64 per node and field, wA[4 q + k]); for a
 // source-box node that is the derivative with respect to the source node's stiffness.
+// TAB: the velocity table (vtab: the forward's phase-speed tables, the node's offset in geo
+// slot 6; gtab: the group-speed tables, VT_N per device material).
 // Four waves per SIMD (128 registers): left to itself the compiler takes 149 and runs
 // three, and the kernel waits on its dependent float64 chains, not on memory.
-template <typename mreal, typename oreal, bool WA>
+template <typename mreal, typename oreal, bool WA, bool TAB>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(4)))
 k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal>* __restrict__ mats_all,
            const uint8_t* __restrict__ mat_id_all, const oreal* __restrict__ orient_all,
            const float* __restrict__ nodeA_all,
            const mreal* __restrict__ geo_all, const double* __restrict__ fbt_all, int R,
            const double* __restrict__ T, AdjW<mreal>* __restrict__ W, double* __restrict__ wT,
-           float* __restrict__ Tb, double* __restrict__ wA, unsigned long long* __restrict__ mismatches) {
+           float* __restrict__ Tb, double* __restrict__ wA, const mreal* __restrict__ vtab,
+           const double* __restrict__ gtab, unsigned long long* __restrict__ mismatches) {
     __shared__ double lt[LH * LSTRIDE];
     const uint32_t unit = blockIdx.x;
     const FieldDev fd = fields[field_of_unit(fields, n_fields, unit)];
@@ -210,7 +271,8 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
             const double L = sqrt((double)(di * di + dj * dj)) * h;
             double dV;
             const MatA As = stiff(ps);
-            const double V = group_speed(As, phi, &dV);
+            const double V = TAB ? group_speed_tab_d(gtab + (fd.mat_off + mat_id[ps]) * VT_N, phi, &dV)
+                                 : group_speed(As, phi, &dV);
             t = L * dV / (V * V);
             if constexpr (WA) {
                 group_speed_dA(As, phi, dA);
@@ -219,8 +281,10 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
             }
         }
     } else if (tD < inf) {
-        NodeConst<mreal, double> nc;
+        using NC = typename std::conditional<TAB, NodeConstTab<mreal, double>, NodeConst<mreal, double>>::type;
+        NC nc;
         load_node_const<double, mreal>(nc, p, geo, fbt);
+        if constexpr (TAB) nc.vt = vtab + (int)geo[GEO_N * p + 6];
         double tt[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) tt[k] = lt[me + SLOT_DJ[k] * LSTRIDE + SLOT_DI[k]];
@@ -240,7 +304,8 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
             nd.R = (A.a11 + A.a33 - 2.0 * A.a55) * ih2;
             nd.W = (A.a13 + A.a55) * ih2;
             nd.K4 = 4.0 * nd.W * nd.W;
-            stencil_partials(nd, g, tt[g.sa], tt[g.sb], tt[g.sc], a, b, c, t);
+            if constexpr (TAB) stencil_partials_tab(nd, g, nc.vt, tt[g.sa], tt[g.sb], tt[g.sc], a, b, c, t);
+            else stencil_partials(nd, g, tt[g.sa], tt[g.sb], tt[g.sc], a, b, c, t);
             if constexpr (WA) stencil_partials_A(nd, g, tt[g.sa], tt[g.sb], tt[g.sc], ih2, dA);
             cd = make_code(K_STENCIL, (unsigned)g.sa, (unsigned)g.sb, (unsigned)g.sc);
         } else if (ch >= 32) {
@@ -250,7 +315,8 @@ k_adj_prep(const FieldDev* __restrict__ fields, int n_fields, const MatDev<mreal
             const double ang = d == 0 ? 0.0 : d == 1 ? quarter : d == 2 ? 2.0 * quarter : -quarter;
             const double len = (d & 1) ? 1.41421356237309504880 : 1.0;
             double dV;
-            const double V = group_speed(A, ang - th, &dV);
+            const double V = TAB ? group_speed_tab_d(gtab + (fd.mat_off + mat_id[p]) * VT_N, ang - th, &dV)
+                                 : group_speed(A, ang - th, &dV);
             a = 1.0;
             t = len * h * dV / (V * V);
             if constexpr (WA) {
@@ -755,8 +821,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     if (st != ALI_OK) return st;
     if (d_dA && opt.wave != ALI_WAVE_QP)
         return H->fail(ALI_EUNSUPPORTED, "the stiffness gradient is available for the qP wave only");
-    if (opt.velocity != ALI_VEL_CHRISTOFFEL)
-        return H->fail(ALI_EUNSUPPORTED, "the adjoint differentiates the run-time speeds (velocity table given)");
+    if (opt.velocity != ALI_VEL_CHRISTOFFEL && d_dA)
+        return H->fail(ALI_EUNSUPPORTED, "the stiffness gradient differentiates the run-time speeds (velocity table given)");
     if (opt.adjoint_band_cells < 0 || opt.adjoint_inner_sweeps < 0 || opt.adjoint_inner_sweeps > 4096)
         return H->fail(ALI_EINVAL, "adjoint_band_cells must be >= 0 and adjoint_inner_sweeps in [0, 4096]");
     if (!d_in) return H->fail(ALI_EINVAL, mode == 1 ? "d_obs is NULL" : "d_dLdT is NULL");
@@ -858,16 +924,21 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     const int B = 256;
     const unsigned gNF = (unsigned)((NF + B - 1) / B);
     if (d_dA)
-        hipLaunchKernelGGL((k_adj_prep<mreal, oreal, true>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
+        hipLaunchKernelGGL((k_adj_prep<mreal, oreal, true, false>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
                            fs.fields, n_fields, fs.mats, d_mat_id, d_orient, opt.d_node_A, fs.geo, fs.fbt,
                            opt.src_box_radius, (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (float*)d_Tb,
-                           (double*)d_wA,
+                           (double*)d_wA, (const mreal*)nullptr, (const double*)nullptr,
                            (unsigned long long*)d_cnt + 1);
-    else
-        hipLaunchKernelGGL((k_adj_prep<mreal, oreal, false>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
+    else if (fs.vt)
+        hipLaunchKernelGGL((k_adj_prep<mreal, oreal, false, true>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
                            fs.fields, n_fields, fs.mats, d_mat_id, d_orient, opt.d_node_A, fs.geo, fs.fbt,
                            opt.src_box_radius, (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (float*)d_Tb,
-                           (double*)nullptr,
+                           (double*)nullptr, fs.vt, fs.gt, (unsigned long long*)d_cnt + 1);
+    else
+        hipLaunchKernelGGL((k_adj_prep<mreal, oreal, false, false>), dim3((unsigned)nunits), dim3(NTHREADS), 0, S,
+                           fs.fields, n_fields, fs.mats, d_mat_id, d_orient, opt.d_node_A, fs.geo, fs.fbt,
+                           opt.src_box_radius, (const double*)T, (AdjW<mreal>*)d_W, (double*)d_wT, (float*)d_Tb,
+                           (double*)nullptr, (const mreal*)nullptr, (const double*)nullptr,
                            (unsigned long long*)d_cnt + 1);
     HIPCK(H, hipGetLastError());
     hipLaunchKernelGGL((k_fill<double>), dim3(gNF), dim3(B), 0, S, (double*)d_lam, NF, 0.0);

@@ -1101,6 +1101,8 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
         hipLaunchKernelGGL((k_vtables<mreal>), dim3((unsigned)nd), dim3(128), 0, S, (const MatA*)d_A,
                            (const double*)d_ih, (int)nd, (mreal*)d_vt, (double*)d_gt);
     }
+    F.vt = (const mreal*)d_vt;
+    F.gt = (const double*)d_gt;
     // per-node constants of every medium: one launch per 65535 media
     std::vector<PrepDev> hp(n_media);
     int64_t max_nodes = 0;

@@ -565,6 +565,8 @@ template <typename real, typename mreal> struct ForwardState {
     const MatDev<mreal>* mats = nullptr;
     const mreal* geo = nullptr;      // [medium nodes][2] cos 2theta, sin 2theta
     const real* fbt = nullptr;       // [medium nodes][4] straight-ray times to 8-neighbours
+    const mreal* vt = nullptr;       // velocity-table mode: phase speed / h tables of the device materials
+    const double* gt = nullptr;      // and their group-speed tables (VT_N entries each), else NULL
     const FieldDev* fields = nullptr;
     std::vector<FieldDev> hfields;
     std::vector<uint32_t> part_base;       // first slot of every pass-list region
