@@ -2,9 +2,10 @@
 // host code carries AddressSanitizer and UndefinedBehaviorSanitizer (device code is built
 // as usual).  Without a GPU it checks the calls that need none and that ali_create fails
 // cleanly; with one it runs forward solves (mixed, float64, allocation-free, persistent,
-// nested source grids, batch), gradients, rays, the autotuner and error paths, and checks
-// each status.  Exits 0 when every status is the expected one; the sanitizers abort on
-// the first host memory or undefined-behaviour error.
+// nested source grids, batch), gradients (also on the refined medium and with the velocity
+// table), rays, the autotuner and error paths, and checks each status.  Exits 0 when every
+// status is the expected one; the sanitizers abort on the first host memory or
+// undefined-behaviour error.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
@@ -121,6 +122,18 @@ int main() {
                              d_dth, d_dA, &ast));
     OK(ali_misfit_gradient(h, &g, mats.data(), 2, d_id, d_th, src.data(), 2, rec.data(), 3, d_obs, nullptr, nullptr,
                            d_trec, d_loss, d_dth, &ast));
+    // the same on the 3-fold refined medium, and the gradient with the velocity table
+    float* d_Tsub = dev(std::vector<float>(2 * N));
+    CHECK(d_Tsub);
+    OK(ali_misfit_gradient_subgrid(h, &g, mats.data(), 2, d_id, d_th, src.data(), 2, rec.data(), 3, d_obs, nullptr, 3,
+                                   d_Tsub, d_trec, d_loss, d_dth, &ast));
+    CHECK(ali_misfit_gradient_subgrid(h, &g, mats.data(), 2, d_id, d_th, src.data(), 2, rec.data(), 3, d_obs, nullptr,
+                                      4, nullptr, d_trec, d_loss, d_dth, &ast) == ALI_EINVAL);
+    ali_options otab = o;
+    otab.velocity = ALI_VEL_TABLE;
+    OK(ali_adjoint(h, &g, mats.data(), 2, d_id, d_th, src.data(), 2, rec.data(), 3, d_g, &otab, nullptr, d_dth, &ast));
+    CHECK(ali_adjoint_stiffness(h, &g, mats.data(), 2, d_id, d_th, src.data(), 2, rec.data(), 3, d_g, &otab, nullptr,
+                                d_dth, d_dA, &ast) == ALI_EUNSUPPORTED);
 
     // a batch of two media (the second a copy of the first), its gradient and the autotuner
     std::vector<ali_medium> media(2);
@@ -158,7 +171,8 @@ int main() {
     CHECK(ali_solve_traveltime(h, &g, mats.data(), 2, d_id, d_th, src.data(), 2, &badopt, d_T, &st) == ALI_EINVAL);
 
     for (void* p : {(void*)d_id, (void*)d_th, (void*)d_th64, (void*)d_T, (void*)d_T64, (void*)d_paths, (void*)d_np,
-                    (void*)d_tr, (void*)d_g, (void*)d_obs, (void*)d_dth, (void*)d_dA, (void*)d_trec, (void*)d_loss})
+                    (void*)d_tr, (void*)d_g, (void*)d_obs, (void*)d_dth, (void*)d_dA, (void*)d_trec, (void*)d_loss,
+                    (void*)d_Tsub})
         (void)hipFree(p);
     const ali_status ds = ali_destroy(h);
     g_handle = nullptr;
