@@ -607,10 +607,10 @@ k_adj_sched(const FieldDev* __restrict__ fields, int advance, const double* __re
             uint32_t* __restrict__ flags, double* __restrict__ maxdef, uint32_t* __restrict__ gflag,
             double* __restrict__ gkey, double* __restrict__ theta, PassItem* __restrict__ list,
             uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next, const uint32_t* __restrict__ part_base,
-            int direct_tiles) {
+            uint32_t* __restrict__ done, int direct_tiles) {
     __shared__ uint32_t s_due[SCHED_SPAN];
     schedule_field<true, double, SCHED_T>(blockIdx.x, fields, advance, step, flags, maxdef, gflag, gkey, theta, list,
-                                          cnt_cur, cnt_next, part_base, s_due, direct_tiles);
+                                          cnt_cur, cnt_next, part_base, done, s_due, direct_tiles);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -885,7 +885,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
         !H->scratch("a_gflag", sizeof(uint32_t) * ngroups, &d_gflag) ||
         !H->scratch("a_gkey", sizeof(double) * ngroups, &d_gkey) ||
         !H->scratch("a_list", sizeof(PassItem) * nunits, &d_list) ||
-        !H->scratch("a_count", sizeof(uint32_t) * CNT_WORDS, &d_count) ||
+        !H->scratch("a_count", sizeof(uint32_t) * (CNT_WORDS + n_fields), &d_count) ||
         !H->scratch("a_idle", sizeof(uint32_t), &d_idle) ||
         !H->scratch("a_marks", sizeof(uint32_t) * 2 * NODE_WORDS * nunits, &d_marks) ||
         !H->scratch("a_cnt", (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), &d_cnt))
@@ -914,7 +914,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     HIPCK(H, hipMemsetAsync(d_flags, 0, sizeof(uint32_t) * nunits, S));
     HIPCK(H, hipMemsetAsync(d_gflag, 0, sizeof(uint32_t) * ngroups, S));
     HIPCK(H, hipMemsetAsync(d_marks, 0, sizeof(uint32_t) * 2 * NODE_WORDS * nunits, S));
-    HIPCK(H, hipMemsetAsync(d_count, 0, sizeof(uint32_t) * CNT_WORDS, S));
+    HIPCK(H, hipMemsetAsync(d_count, 0, sizeof(uint32_t) * (CNT_WORDS + n_fields), S));
     const std::vector<uint32_t> part_base = list_part_base(fs.hfields);
     HIPCK(H, hipMemcpyAsync((uint32_t*)d_count + 2 * CNT_BLOCK, part_base.data(), sizeof(uint32_t) * LIST_PARTS,
                             hipMemcpyHostToDevice, S));
@@ -968,7 +968,7 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
                            (const double*)d_step, (uint32_t*)d_flags, (double*)d_maxdef, (uint32_t*)d_gflag,
                            (double*)d_gkey, (double*)d_theta,
                            (PassItem*)d_list, cnt + (p & 1) * CNT_BLOCK, cnt + ((p + 1) & 1) * CNT_BLOCK,
-                           (const uint32_t*)(cnt + 2 * CNT_BLOCK), direct_tiles);
+                           (const uint32_t*)(cnt + 2 * CNT_BLOCK), cnt + 2 * CNT_BLOCK + LIST_PARTS, direct_tiles);
         uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
         uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);

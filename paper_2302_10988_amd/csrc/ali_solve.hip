@@ -194,10 +194,10 @@ __global__ void __launch_bounds__(SCHED_T)
 k_sched(const FieldDev* __restrict__ fields, int advance, uint32_t* __restrict__ flags, real* __restrict__ minrej,
         uint32_t* __restrict__ gflag, real* __restrict__ gkey, real* __restrict__ theta, const real* __restrict__ step,
         PassItem* __restrict__ list, uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next,
-        const uint32_t* __restrict__ part_base, int direct_tiles) {
+        const uint32_t* __restrict__ part_base, uint32_t* __restrict__ done, int direct_tiles) {
     __shared__ uint32_t s_due[SCHED_SPAN];
     schedule_field<false, real, SCHED_T>(blockIdx.x, fields, advance, step, flags, minrej, gflag, gkey, theta, list,
-                                         cnt_cur, cnt_next, part_base, s_due, direct_tiles);
+                                         cnt_cur, cnt_next, part_base, done, s_due, direct_tiles);
 }
 
 
@@ -877,7 +877,8 @@ k_relax_persist(const FieldDev* __restrict__ fields, int n_fields, const real* _
         for (int f = blockIdx.x; f < n_fields; f += gridDim.x)
             schedule_field<false, real, RW, 2>(f, fields, pp > 0 ? 1 : 0, step, flags, minrej, gflag, gkey, theta, list,
                                             cnt + (pp & 1) * CNT_BLOCK, cnt + ((pp + 1) & 1) * CNT_BLOCK,
-                                            cnt + 2 * CNT_BLOCK, reinterpret_cast<uint32_t*>(L.lt), direct_tiles);
+                                            cnt + 2 * CNT_BLOCK, cnt + 2 * CNT_BLOCK + LIST_PARTS,
+                                            reinterpret_cast<uint32_t*>(L.lt), direct_tiles);
         if (!grid_sync(bar, gen, err, timeout)) break;
         const ListMap map = read_list_map<true>(cnt + (pp & 1) * CNT_BLOCK, cnt + 2 * CNT_BLOCK);
         const uint32_t n_units = map.pre[LIST_PARTS];
@@ -1050,7 +1051,7 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
         !H->scratch("gkey", sizeof(real) * groups, &d_gkey) ||
         !H->scratch("list", sizeof(PassItem) * nunits, &d_list) ||
         !H->scratch("marks", sizeof(uint32_t) * 2 * NODE_WORDS * nunits, &d_marks) ||
-        !H->scratch("count", sizeof(uint32_t) * CNT_WORDS, &d_count) ||
+        !H->scratch("count", sizeof(uint32_t) * (CNT_WORDS + n_fields), &d_count) ||
         !H->scratch("idle", sizeof(uint32_t), &d_idle) ||
         !H->scratch("upd", (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), &d_upd) ||
         !H->scratch("err", sizeof(int), &d_err))
@@ -1067,7 +1068,7 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     HIPCK(H, hipMemsetAsync(d_gflag, 0, sizeof(uint32_t) * groups, S));
     HIPCK(H, hipMemsetAsync(d_marks, 0, sizeof(uint32_t) * 2 * NODE_WORDS * nunits, S));
     HIPCK(H, hipMemsetAsync(d_upd, 0, (4 + 2 * STAT_SLOTS) * sizeof(unsigned long long), S));
-    HIPCK(H, hipMemsetAsync(d_count, 0, sizeof(uint32_t) * CNT_WORDS, S));
+    HIPCK(H, hipMemsetAsync(d_count, 0, sizeof(uint32_t) * (CNT_WORDS + n_fields), S));
     F.part_base = list_part_base(F.hfields);
     HIPCK(H, hipMemcpyAsync((uint32_t*)d_count + 2 * CNT_BLOCK, F.part_base.data(), sizeof(uint32_t) * LIST_PARTS,
                             hipMemcpyHostToDevice, S));
@@ -1192,7 +1193,7 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
                            (uint32_t*)d_flags, (real*)d_minrej, (uint32_t*)d_gflag, (real*)d_gkey,
                            (real*)d_theta, (const real*)d_step,
                            (PassItem*)d_list, cnt + (p & 1) * CNT_BLOCK, cnt + ((p + 1) & 1) * CNT_BLOCK,
-                           (const uint32_t*)(cnt + 2 * CNT_BLOCK), direct_tiles);
+                           (const uint32_t*)(cnt + 2 * CNT_BLOCK), cnt + 2 * CNT_BLOCK + LIST_PARTS, direct_tiles);
         uint32_t* mk_in = (uint32_t*)d_marks + (size_t)(p & 1) * nunits * NODE_WORDS;
         uint32_t* mk_out = (uint32_t*)d_marks + (size_t)((p + 1) & 1) * nunits * NODE_WORDS;
         if (timed) (void)hipEventRecord(H->pev[2 * (p % PASS_BATCH)], S);
@@ -1433,7 +1434,7 @@ static size_t forward_scratch_bytes(const ali_grid& g, int n_src, int n_mats, bo
     req.push_back(sizeof(real) * groups);                          // gkey
     req.push_back(sizeof(PassItem) * units);                       // list
     req.push_back(sizeof(uint32_t) * 2 * NODE_WORDS * units);      // marks
-    req.push_back(sizeof(uint32_t) * CNT_WORDS);                   // count
+    req.push_back(sizeof(uint32_t) * (CNT_WORDS + n_src));         // count, finished fields
     req.push_back(sizeof(uint32_t));                               // idle
     req.push_back((4 + 2 * STAT_SLOTS) * sizeof(unsigned long long));   // upd
     req.push_back(sizeof(int));                                    // err

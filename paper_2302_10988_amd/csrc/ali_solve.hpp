@@ -175,7 +175,8 @@ static_assert(sizeof(PassItem) == 64, "pass-list entries are four 16-byte vector
 // records, stay on one die's L2 (regions by field number mod 8 spread every medium over
 // all dies and made the batch relaxation 1.6 % slower).
 // The counter buffer of a solve holds CNT_WORDS words: the counters of even passes at
-// word r * CNT_GAP, those of odd passes CNT_BLOCK words further, then the region offsets.
+// word r * CNT_GAP, those of odd passes CNT_BLOCK words further, then the region offsets;
+// one word per field follows them (the field has finished).
 constexpr int LIST_PARTS = 8;
 constexpr int CNT_GAP = 1024;
 constexpr int CNT_BLOCK = LIST_PARTS * CNT_GAP;
@@ -301,7 +302,9 @@ inline int direct_tiles_for(int64_t n_units, int span) { return n_units <= DIREC
 // tile is due the threshold jumps to the nearest key.  Due tiles have their flags cleared
 // and their keys reset (their visit in this pass writes them again) and are appended to
 // the field's region of the pass list (part_base), counted by the region's counter in the
-// block cnt_cur; the block cnt_next (the next pass's counters) is cleared here.
+// block cnt_cur; the block cnt_next (the next pass's counters) is cleared here.  A field
+// with nothing flagged and no pending key sets done[f] (cleared by the caller before the
+// first pass) and is skipped from then on.
 // Fields of at most direct_tiles tiles are read tile by tile (in spans of NT * K); larger
 // ones through the group summaries gflag / gkey, which are exact: a group is due exactly
 // when one of its tiles is; an expanded group's summary is rebuilt from its tiles that
@@ -313,14 +316,18 @@ __device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict
                                                real* __restrict__ gkey, real* __restrict__ theta,
                                                PassItem* __restrict__ list, uint32_t* __restrict__ cnt_cur,
                                                uint32_t* __restrict__ cnt_next,
-                                               const uint32_t* __restrict__ part_base, uint32_t* __restrict__ s_due,
-                                               int direct_tiles) {
+                                               const uint32_t* __restrict__ part_base, uint32_t* __restrict__ done,
+                                               uint32_t* __restrict__ s_due, int direct_tiles) {
     constexpr int NW = NT / 64;
     constexpr int SPAN = NT * K;
     __shared__ real s_key[NW];
     __shared__ unsigned s_act[NW], s_cnt[NW], s_gcnt[NW];
     __shared__ uint32_t s_base;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (f == 0 && tid < LIST_PARTS) cnt_next[tid * CNT_GAP] = 0u;
+    // a field that had nothing flagged and no pending key has finished: only its own tile
+    // visits could bring new work, and it has none
+    if (done[f]) return;
     const FieldDev fd = fields[f];
     const int ntiles = fd.ntx * fd.ntz;
     const int ngroups = (int)field_groups(ntiles);
@@ -330,7 +337,6 @@ __device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict
     real* __restrict__ gk = gkey + fd.group_off;
     const real inf = dinf<real>();
     const real none = DESC ? -inf : inf;
-    if (f == 0 && tid < LIST_PARTS) cnt_next[tid * CNT_GAP] = 0u;
     uint32_t* __restrict__ rcnt = cnt_cur + fd.part * CNT_GAP;   // the field's region
     PassItem* __restrict__ rlist = list + part_base[fd.part];
     real th = theta[f];
@@ -368,6 +374,7 @@ __device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict
             near = DESC ? (s_key[w] > near ? s_key[w] : near) : (s_key[w] < near ? s_key[w] : near);
         }
         if (!any && near != none && (DESC ? near < th : near > th)) th = near;   // idle: jump
+        if (!any && near == none && tid == 0) done[f] = 1u;
         if (tid == 0) theta[f] = th;
         for (int b0 = 0; b0 < ntiles; b0 += SPAN) {
             if (ntiles > SPAN) {
@@ -458,6 +465,7 @@ __device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict
         near = DESC ? (s_key[w] > near ? s_key[w] : near) : (s_key[w] < near ? s_key[w] : near);
     }
     if (!any && near != none && (DESC ? near < th : near > th)) th = near;   // idle: jump
+    if (!any && near == none && tid == 0) done[f] = 1u;
     if (tid == 0) theta[f] = th;
 
     for (int b0 = 0; b0 < ngroups; b0 += SPAN) {
