@@ -257,6 +257,8 @@ __device__ __forceinline__ uint32_t list_slot_reg(const ListMap& m, uint32_t v) 
 constexpr int SCHED_T = 256;  // work-items of a scheduler work-group (one group per field)
 constexpr int SCHED_K = 8;    // scheduler groups per work-item held in registers
 constexpr int SCHED_SPAN = SCHED_T * SCHED_K;   // groups a scheduler work-group reads at once
+// due groups a scheduler wave expands at once (batch step: 2 and 4 save 0.9 %, 8 nothing)
+constexpr int SCHED_UNROLL = 2;
 // Tiles of one scheduler group.  The scheduler reads a summary per group (the OR of its
 // tiles' flags and the nearest of its tiles' keys) and only expands the groups that are
 // due, one wave per group and one tile per lane, instead of reading every tile of every
@@ -501,12 +503,22 @@ __device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict
         for (int k = 0; k < K; ++k)
             if ((dmask >> k) & 1u) s_due[gpos++] = (uint32_t)(b0 + tid + NT * k);
         __syncthreads();
-        // count the due tiles (one wave per due group, one tile per lane)
+        // count the due tiles (one wave per due group, one tile per lane; each wave loads
+        // the flags and keys of SCHED_UNROLL of its groups before it uses any of them)
+        constexpr int U = SCHED_UNROLL;
         unsigned wcount = 0u;
-        for (unsigned q = wv; q < ndue; q += NW) {
-            const int t = (int)s_due[q] * GROUP + lane;
-            const bool d = t < ntiles && (fl[t] != 0u || due_key(ky[t]));
-            wcount += (unsigned)__popcll(__ballot(d));
+        for (unsigned q = wv; q < ndue; q += U * NW) {
+            uint32_t fu[U];
+            real ku[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const unsigned qu = q + (unsigned)(u * NW);
+                const int t = qu < ndue ? (int)s_due[qu] * GROUP + lane : ntiles;
+                fu[u] = t < ntiles ? fl[t] : 0u;
+                ku[u] = t < ntiles ? ky[t] : none;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) wcount += (unsigned)__popcll(__ballot(fu[u] != 0u || due_key(ku[u])));
         }
         if (lane == 0) s_cnt[wv] = wcount;
         __syncthreads();
@@ -520,38 +532,52 @@ __device__ __forceinline__ void schedule_field(int f, const FieldDev* __restrict
         __syncthreads();
         // append them in the same order, reset their flags and keys, rebuild the summaries
         uint32_t pos = s_base + wbase;
-        for (unsigned q = wv; q < ndue; q += NW) {
-            const int g = (int)s_due[q];
-            const int t = g * GROUP + lane;
-            const uint32_t tf = t < ntiles ? fl[t] : 0u;
-            const real tk = t < ntiles ? ky[t] : none;
-            const bool d = t < ntiles && (tf != 0u || due_key(tk));
-            const unsigned long long m = __ballot(d);
-            if (d) {
-                fl[t] = 0u;
-                ky[t] = none;
-                PassItem it;
-                it.unit = fd.unit_off + (uint32_t)t;
-                it.bits = tf;
-                it.f = f;
-                it.tx = t % fd.ntx;
-                it.tz = t / fd.ntx;
-                it.nx = fd.nx;
-                it.nz = fd.nz;
-                it.group_off = fd.group_off;
-                it.src = fd.src;
-                it.t_off = fd.t_off;
-                it.node_off = fd.node_off;
-                it.pad1 = 0;
-                rlist[pos + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = it;
+        for (unsigned q = wv; q < ndue; q += U * NW) {
+            uint32_t fu[U];
+            real ku[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const unsigned qu = q + (unsigned)(u * NW);
+                const int t = qu < ndue ? (int)s_due[qu] * GROUP + lane : ntiles;
+                fu[u] = t < ntiles ? fl[t] : 0u;
+                ku[u] = t < ntiles ? ky[t] : none;
             }
-            pos += (uint32_t)__popcll(m);
-            real r = d ? none : tk;
-            for (int o = 32; o > 0; o >>= 1) {
-                const real r2 = __shfl_xor(r, o);
-                r = DESC ? (r2 > r ? r2 : r) : (r2 < r ? r2 : r);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const unsigned qu = q + (unsigned)(u * NW);
+                if (qu >= ndue) break;
+                const int g = (int)s_due[qu];
+                const int t = g * GROUP + lane;
+                const uint32_t tf = fu[u];
+                const real tk = ku[u];
+                const bool d = t < ntiles && (tf != 0u || due_key(tk));
+                const unsigned long long m = __ballot(d);
+                if (d) {
+                    fl[t] = 0u;
+                    ky[t] = none;
+                    PassItem it;
+                    it.unit = fd.unit_off + (uint32_t)t;
+                    it.bits = tf;
+                    it.f = f;
+                    it.tx = t % fd.ntx;
+                    it.tz = t / fd.ntx;
+                    it.nx = fd.nx;
+                    it.nz = fd.nz;
+                    it.group_off = fd.group_off;
+                    it.src = fd.src;
+                    it.t_off = fd.t_off;
+                    it.node_off = fd.node_off;
+                    it.pad1 = 0;
+                    rlist[pos + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = it;
+                }
+                pos += (uint32_t)__popcll(m);
+                real r = d ? none : tk;
+                for (int o = 32; o > 0; o >>= 1) {
+                    const real r2 = __shfl_xor(r, o);
+                    r = DESC ? (r2 > r ? r2 : r) : (r2 < r ? r2 : r);
+                }
+                if (lane == 0) { gk[g] = r; gf[g] = 0u; }
             }
-            if (lane == 0) { gk[g] = r; gf[g] = 0u; }
         }
         __syncthreads();     // s_cnt, s_gcnt, s_due and s_base are reused by the next span
     }
