@@ -53,8 +53,8 @@ VECTOR_PEAK_TFLOPS = 78.6
 # program), per launch of the batch128 forward (all launches of one forward, averaged),
 # for the kernel sources with this hash, and the wave-level VALU instructions of the same
 # launches (rocprofv3 --pmc SQ_INSTS_VALU).  Reported as null once the sources differ.
-TRAFFIC = {"sources_sha256_16": "07200906cb392e6d", "fetch_bytes_per_launch": 858803601,
-           "write_bytes_per_launch": 84414873, "valu_wave_insts_per_launch": 1.916e8}
+TRAFFIC = {"sources_sha256_16": "26dd42100321a18b", "fetch_bytes_per_launch": 859807831,
+           "write_bytes_per_launch": 84428288, "valu_wave_insts_per_launch": 1.912e8}
 
 TUNE_CACHE = os.path.join(ROOT, "paper_2302_10988_amd", "tuned_schedules.json")
 

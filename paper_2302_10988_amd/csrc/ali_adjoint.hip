@@ -601,15 +601,16 @@ k_adj_relax(const PassItem* __restrict__ list, const AdjW<wreal>* __restrict__ W
 }
 
 // Scheduler of one adjoint pass (descending thresholds), one work-group per field; the
-// tile keys are the largest pending times (the relaxation rewrites them).
+// tile keys are the largest pending times (the relaxation rewrites them).  K as in k_sched.
+template <int K>
 __global__ void __launch_bounds__(SCHED_T)
 k_adj_sched(const FieldDev* __restrict__ fields, int advance, const double* __restrict__ step,
             uint32_t* __restrict__ flags, double* __restrict__ maxdef, uint32_t* __restrict__ gflag,
             double* __restrict__ gkey, double* __restrict__ theta, PassItem* __restrict__ list,
             uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next, const uint32_t* __restrict__ part_base,
             uint32_t* __restrict__ done, int direct_tiles) {
-    __shared__ uint32_t s_due[SCHED_SPAN];
-    schedule_field<true, double, SCHED_T>(blockIdx.x, fields, advance, step, flags, maxdef, gflag, gkey, theta, list,
+    __shared__ uint32_t s_due[SCHED_T * K];
+    schedule_field<true, double, SCHED_T, K>(blockIdx.x, fields, advance, step, flags, maxdef, gflag, gkey, theta, list,
                                           cnt_cur, cnt_next, part_base, done, s_due, direct_tiles);
 }
 
@@ -866,7 +867,8 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     void *d_flags, *d_list, *d_count, *d_cnt, *d_pend, *d_maxdef, *d_theta, *d_step, *d_idle, *d_marks;
     void *d_gflag, *d_gkey;
     const int64_t ngroups = fs.n_groups;
-    const int direct_tiles = direct_tiles_for(nunits, SCHED_SPAN);
+    const int sched_k = sched_k_for(nunits);
+    const int direct_tiles = direct_tiles_for(nunits, SCHED_T * sched_k);
     bool use_groups = false;
     for (const FieldDev& fd : fs.hfields) use_groups |= fd.ntx * fd.ntz > direct_tiles;
     if (!H->scratch("a_w", sizeof(AdjW<mreal>) * NF, &d_W) || !H->scratch("a_wT", sizeof(double) * NF, &d_wT) ||
@@ -963,8 +965,9 @@ static ali_status adjoint_impl(ali_handle* H, const ali_medium* media, int32_t n
     // far more work-groups than are resident (see the forward relaxation)
     const int grid_relax = (int)(nunits < (int64_t)128 * H->n_cu ? nunits : (int64_t)128 * H->n_cu);
     uint32_t* cnt = (uint32_t*)d_count;
+    auto* const ksched = sched_k == SCHED_K ? &k_adj_sched<SCHED_K> : &k_adj_sched<SCHED_K_LARGE>;
     auto enqueue = [&](int p, bool timed, hipStream_t S) {
-        hipLaunchKernelGGL(k_adj_sched, dim3((unsigned)n_fields), dim3(SCHED_T), 0, S, fs.fields, p > 0 ? 1 : 0,
+        hipLaunchKernelGGL(ksched, dim3((unsigned)n_fields), dim3(SCHED_T), 0, S, fs.fields, p > 0 ? 1 : 0,
                            (const double*)d_step, (uint32_t*)d_flags, (double*)d_maxdef, (uint32_t*)d_gflag,
                            (double*)d_gkey, (double*)d_theta,
                            (PassItem*)d_list, cnt + (p & 1) * CNT_BLOCK, cnt + ((p + 1) & 1) * CNT_BLOCK,

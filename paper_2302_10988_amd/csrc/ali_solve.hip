@@ -188,15 +188,16 @@ __global__ void k_seed_flags(const FieldDev* __restrict__ fields, int n_fields, 
         }
 }
 
-// Scheduler of one relaxation pass (ascending thresholds), one work-group per field.
-template <typename real>
+// Scheduler of one relaxation pass (ascending thresholds), one work-group per field, each
+// work-item holding K groups or tiles at a time.
+template <typename real, int K>
 __global__ void __launch_bounds__(SCHED_T)
 k_sched(const FieldDev* __restrict__ fields, int advance, uint32_t* __restrict__ flags, real* __restrict__ minrej,
         uint32_t* __restrict__ gflag, real* __restrict__ gkey, real* __restrict__ theta, const real* __restrict__ step,
         PassItem* __restrict__ list, uint32_t* __restrict__ cnt_cur, uint32_t* __restrict__ cnt_next,
         const uint32_t* __restrict__ part_base, uint32_t* __restrict__ done, int direct_tiles) {
-    __shared__ uint32_t s_due[SCHED_SPAN];
-    schedule_field<false, real, SCHED_T>(blockIdx.x, fields, advance, step, flags, minrej, gflag, gkey, theta, list,
+    __shared__ uint32_t s_due[SCHED_T * K];
+    schedule_field<false, real, SCHED_T, K>(blockIdx.x, fields, advance, step, flags, minrej, gflag, gkey, theta, list,
                                          cnt_cur, cnt_next, part_base, done, s_due, direct_tiles);
 }
 
@@ -1032,7 +1033,8 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     F.n_groups = groups;
     // the scheduler reads small fields tile by tile; the group summaries are kept only if
     // some field of the call is scheduled by groups
-    const int direct_tiles = direct_tiles_for(nunits, opt.persistent ? RW * 2 : SCHED_SPAN);
+    const int sched_k = sched_k_for(nunits);
+    const int direct_tiles = direct_tiles_for(nunits, opt.persistent ? RW * 2 : SCHED_T * sched_k);
     bool use_groups = false;
     for (const FieldDev& fd : F.hfields) use_groups |= fd.ntx * fd.ntz > direct_tiles;
     F.field_nodes = fnodes;
@@ -1187,8 +1189,9 @@ ali_status solve_fields(ali_handle* H, const ali_medium* media, int32_t n_media,
     const int gcap = opt.visit_tiles > 0 ? opt.visit_tiles : G_MAX;
     uint32_t* cnt = (uint32_t*)d_count;
     // one pass: schedule, then relax (events around the relax launch when timed)
+    auto* const ksched = sched_k == SCHED_K ? &k_sched<real, SCHED_K> : &k_sched<real, SCHED_K_LARGE>;
     auto enqueue = [&](int p, bool timed, hipStream_t S) {
-        hipLaunchKernelGGL((k_sched<real>), dim3((unsigned)n_fields), dim3(SCHED_T), 0, S,
+        hipLaunchKernelGGL(ksched, dim3((unsigned)n_fields), dim3(SCHED_T), 0, S,
                            (const FieldDev*)d_fields, p > 0 ? 1 : 0,
                            (uint32_t*)d_flags, (real*)d_minrej, (uint32_t*)d_gflag, (real*)d_gkey,
                            (real*)d_theta, (const real*)d_step,

@@ -256,7 +256,12 @@ __device__ __forceinline__ uint32_t list_slot_reg(const ListMap& m, uint32_t v) 
 
 constexpr int SCHED_T = 256;  // work-items of a scheduler work-group (one group per field)
 constexpr int SCHED_K = 8;    // scheduler groups per work-item held in registers
-constexpr int SCHED_SPAN = SCHED_T * SCHED_K;   // groups a scheduler work-group reads at once
+// the same in calls of more than DIRECT_ALL_UNITS tiles, where only fields of one span are
+// read tile by tile: fewer registers (more resident scheduler work-groups) pay there
+// (batch of 128 media: step 1.260 -> 1.249 s; 2 the same), while a smaller call, read tile
+// by tile, would need two spans for fields of 1025-2048 tiles (64 fields of 512 x 512:
+// forward +2.8 % with 4)
+constexpr int SCHED_K_LARGE = 4;
 // due groups a scheduler wave expands at once (batch step: 2 and 4 save 0.9 %, 8 nothing)
 constexpr int SCHED_UNROLL = 2;
 // Tiles of one scheduler group.  The scheduler reads a summary per group (the OR of its
@@ -292,6 +297,7 @@ __device__ __forceinline__ void flag_tile(uint32_t* __restrict__ flags, uint32_t
 // scheduler span are (the group summaries spare the larger ones a full read per pass).
 constexpr int64_t DIRECT_ALL_UNITS = (int64_t)1 << 18;
 inline int direct_tiles_for(int64_t n_units, int span) { return n_units <= DIRECT_ALL_UNITS ? (1 << 30) : span; }
+inline int sched_k_for(int64_t n_units) { return n_units <= DIRECT_ALL_UNITS ? SCHED_K : SCHED_K_LARGE; }
 
 // Pass scheduler of field f, run by one work-group of NT work-items (a multiple of 64;
 // every work-item of the group calls it), each holding K groups at a time.  s_due:
