@@ -401,9 +401,24 @@ def main():
                                   "fields_per_s": 1e3 / single_ms, "passes": sst["outer_iters"]}
 
     if not args.no_extras:
+        log("batch forward modes (extras)")
+        bo = torch.empty(batch.field_nodes, dtype=torch.float32, device=dev)
+
+        def once(fn):
+            fn()            # the first call captures the pass graphs of new shapes
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - ts) * 1e3
+
+        batch_modes = {"forward_box": once(lambda: solver.solve_batch(batch, out=bo, **sched)),
+                       "forward_nested_source_grids": once(lambda: solver.solve_batch_refined(batch, out=bo,
+                                                                                             **sched))}
+        del bo
         log("weld figures (extras)")
         res, _ = weld_step_figures(solver, dev, 3, 1, True, not args.no_check)
-        line["extras"] = {"weld512x64": res}
+        line["extras"] = {"weld512x64": res, "batch_forward_modes_ms": batch_modes}
 
     if not args.no_check:
         import oracle

@@ -301,6 +301,25 @@ ali_status ali_solve_batch(ali_handle* h, const ali_medium* media, int32_t n_med
                            const float* d_orient, const ali_node* srcs, const ali_options* opt,
                            float* d_T, ali_solve_stats* stats);
 
+/* ali_solve_batch with the nested fine grids of ali_solve_traveltime_refined (Section 4.4)
+   around every source of every medium: each level's grids, one per field, take the material
+   and orientation of their own medium's nearest nodes and the materials of its range, and
+   all of them relax in one call per level; the last level is the batch itself.  Media,
+   layout, output and errors as ali_solve_batch; refinement, arithmetic and statistics as
+   ali_solve_traveltime_refined (stats add up every level), except that ref->subgrid must
+   be 0 or 1 (the s-fold medium is offered for one medium at a time; other values return
+   ALI_EUNSUPPORTED).  Every field equals that of ali_solve_traveltime_refined on its own
+   medium and source.  Scratch: the fine grids of all fields (about 23k nodes per field by
+   default) besides that of ali_solve_batch. */
+ali_status ali_solve_batch_refined(ali_handle* h, const ali_medium* media, int32_t n_media,
+                                   const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
+                                   const float* d_orient, const ali_node* srcs, const ali_options* opt,
+                                   const ali_refine* ref, float* d_T, ali_solve_stats* stats);
+ali_status ali_solve_batch_refined_f64(ali_handle* h, const ali_medium* media, int32_t n_media,
+                                       const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
+                                       const double* d_orient, const ali_node* srcs, const ali_options* opt,
+                                       const ali_refine* ref, double* d_T, ali_solve_stats* stats);
+
 /* Schedule autotuner: times the forward batch solve (the fields go to d_T, [field nodes]
    float32, device) under each of ALI_TUNE_CANDIDATES schedules (band_cells, inner_sweeps,
    visit_tiles, persistent) -- (1,2,4,0) (1,2,2,0) (1,2,1,0) (1,4,4,0) (2,2,4,0) (2,4,4,0)

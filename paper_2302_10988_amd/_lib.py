@@ -159,6 +159,12 @@ SIGNATURES = {
                                                        ctypes.POINTER(AdjointStats)]),
     "ali_solve_batch": (ctypes.c_int, [_P, ctypes.POINTER(Medium), _I32, ctypes.POINTER(Material), _I32, _P, _P,
                                        ctypes.POINTER(Node), ctypes.POINTER(Options), _P, ctypes.POINTER(SolveStats)]),
+    "ali_solve_batch_refined": (ctypes.c_int, [_P, ctypes.POINTER(Medium), _I32, ctypes.POINTER(Material), _I32,
+                                               _P, _P, ctypes.POINTER(Node), ctypes.POINTER(Options),
+                                               ctypes.POINTER(Refine), _P, ctypes.POINTER(SolveStats)]),
+    "ali_solve_batch_refined_f64": (ctypes.c_int, [_P, ctypes.POINTER(Medium), _I32, ctypes.POINTER(Material),
+                                                   _I32, _P, _P, ctypes.POINTER(Node), ctypes.POINTER(Options),
+                                                   ctypes.POINTER(Refine), _P, ctypes.POINTER(SolveStats)]),
     "ali_misfit_gradient_batch": (ctypes.c_int, [_P, ctypes.POINTER(Medium), _I32, ctypes.POINTER(Material), _I32,
                                                  _P, _P, ctypes.POINTER(Node), ctypes.POINTER(Node), _P,
                                                  ctypes.POINTER(Options), _P, _P, _P, ctypes.POINTER(AdjointStats)]),

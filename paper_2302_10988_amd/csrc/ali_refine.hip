@@ -50,6 +50,11 @@ struct LevelDev {
     int64_t t_off;            // first node in the level's field array
     uint32_t unit_off;        // first tile unit
     int ntx;
+    // the source's working medium: its first node, row length, spacing and materials
+    int64_t w_node;
+    int nx_w;
+    int mat_off, n_mats;
+    double h_w;
 };
 
 // nearest multiple index of a / d for odd d (a half never occurs)
@@ -59,14 +64,14 @@ __device__ __forceinline__ int near_div(int a, int d) {
 }
 
 template <typename oreal>
-__global__ void k_level_medium(const LevelDev* __restrict__ lv, int nx_w, const uint8_t* __restrict__ mat_w,
+__global__ void k_level_medium(const LevelDev* __restrict__ lv, const uint8_t* __restrict__ mat_w,
                                const oreal* __restrict__ ori_w, const float* __restrict__ A_w,
                                uint8_t* __restrict__ mat_l, oreal* __restrict__ ori_l, float* __restrict__ A_l) {
     const LevelDev L = lv[blockIdx.y];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= (int64_t)L.nx * L.nz) return;
     const int a = L.a_lo + (int)(q % L.nx), b = L.b_lo + (int)(q / L.nx);
-    const int64_t p = (int64_t)(L.sj + near_div(b, L.d)) * nx_w + (L.si + near_div(a, L.d));
+    const int64_t p = L.w_node + (int64_t)(L.sj + near_div(b, L.d)) * L.nx_w + (L.si + near_div(a, L.d));
     mat_l[L.node_off + q] = mat_w[p];
     ori_l[L.node_off + q] = ori_w[p];
     if (A_w)
@@ -81,9 +86,8 @@ __device__ __forceinline__ void set_fixed(uint32_t* __restrict__ fixmask, const 
 
 // finest level: straight rays from the source inside |a|, |b| < half * d, +inf elsewhere
 template <typename real, typename oreal>
-__global__ void k_seed_start(const LevelDev* __restrict__ lv, int nx_w, double h_w, double half,
-                             const MatA* __restrict__ A, const double* __restrict__ gt, int n_mats,
-                             const uint8_t* __restrict__ mat_w, const oreal* __restrict__ ori_w,
+__global__ void k_seed_start(const LevelDev* __restrict__ lv, double half, const MatA* __restrict__ A,
+                             const double* __restrict__ gt, const uint8_t* __restrict__ mat_w, const oreal* __restrict__ ori_w,
                              const float* __restrict__ A_w, real* __restrict__ T, uint32_t* __restrict__ fixmask) {
     const LevelDev L = lv[blockIdx.y];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -95,15 +99,15 @@ __global__ void k_seed_start(const LevelDev* __restrict__ lv, int nx_w, double h
     if (fabs((double)a) < lim && fabs((double)b) < lim) {
         double t = 0.0;
         if (a != 0 || b != 0) {
-            const int64_t ps = (int64_t)L.sj * nx_w + L.si;
+            const int64_t ps = L.w_node + (int64_t)L.sj * L.nx_w + L.si;
             const double phi = atan2((double)b, (double)a) - (double)ori_w[ps];
             // an id outside the table is reported by the solve's own check; read a valid entry
-            const int mid = mat_w[ps] < n_mats ? mat_w[ps] : 0;
+            const int mid = L.mat_off + (mat_w[ps] < L.n_mats ? mat_w[ps] : 0);
             const MatA As = A_w ? MatA{(double)A_w[4 * ps], (double)A_w[4 * ps + 1], (double)A_w[4 * ps + 2],
                                        (double)A_w[4 * ps + 3]}
                                 : A[mid];
             const double V = gt ? group_speed_tab(gt + mid * VT_N, phi) : group_speed(As, phi);
-            t = sqrt((double)a * a + (double)b * b) * (h_w / L.d) / V;
+            t = sqrt((double)a * a + (double)b * b) * (L.h_w / L.d) / V;
         }
         v = (real)t;
         set_fixed(fixmask, L, i, j);
@@ -185,39 +189,56 @@ __global__ void k_subgrid_pick(int nx, int64_t nw, int64_t n_out, int nx_s, int6
     out[q] = (outreal)Ts[k * n_s + (int64_t)j * s * nx_s + (int64_t)i * s];
 }
 
-// host: one level's grids (clipped to the working grid) and their offsets
-static std::vector<LevelDev> level_grids(const ali_grid& g, const ali_node* srcs, int n_src, int d, int W, int stop,
-                                         std::vector<ali_medium>& media, std::vector<ali_node>& lsrc,
-                                         double h_w, int n_mats) {
-    std::vector<LevelDev> lv(n_src);
-    media.assign(n_src, ali_medium{});
-    lsrc.assign(n_src, ali_node{});
+// the working medium of every field of a batch (fields in medium order, then source order)
+static LevelDev working_level(const ali_medium& m, const ali_node& src) {
+    LevelDev L{};
+    L.si = src.i; L.sj = src.j;
+    L.w_node = m.node_offset;
+    L.nx_w = m.grid.nx;
+    L.mat_off = m.mat_offset;
+    L.n_mats = m.n_mats;
+    L.h_w = m.grid.h;
+    return L;
+}
+
+// host: one level's grids (clipped to each field's working grid) and their offsets; one
+// level medium per field
+static std::vector<LevelDev> level_grids(const ali_medium* bm, int n_bm, const ali_node* srcs, int d, int W,
+                                         int stop, std::vector<ali_medium>& media, std::vector<ali_node>& lsrc) {
+    std::vector<LevelDev> lv;
+    media.clear();
+    lsrc.clear();
     int64_t node = 0;
     uint32_t unit = 0;
-    for (int k = 0; k < n_src; ++k) {
-        LevelDev& L = lv[k];
-        const int si = srcs[k].i, sj = srcs[k].j;
-        L.si = si; L.sj = sj; L.d = d; L.stop = stop;
-        L.a_lo = std::max(-W, -si * d);
-        const int a_hi = std::min(W, (g.nx - 1 - si) * d);
-        L.b_lo = std::max(-W, -sj * d);
-        const int b_hi = std::min(W, (g.nz - 1 - sj) * d);
-        L.nx = a_hi - L.a_lo + 1;
-        L.nz = b_hi - L.b_lo + 1;
-        L.node_off = node;
-        L.t_off = node;              // one field per level medium
-        L.unit_off = unit;
-        L.ntx = (L.nx + TX - 1) / TX;
-        ali_medium& m = media[k];
-        m.grid.nx = L.nx; m.grid.nz = L.nz; m.grid.h = h_w / d;
-        m.mat_offset = 0; m.n_mats = n_mats;
-        m.node_offset = node;
-        m.src_offset = k; m.n_src = 1;
-        m.rec_offset = 0; m.n_rec = 0;
-        lsrc[k].i = -L.a_lo;
-        lsrc[k].j = -L.b_lo;
-        node += (int64_t)L.nx * L.nz;
-        unit += (uint32_t)(L.ntx * ((L.nz + TZ - 1) / TZ));
+    for (int m = 0; m < n_bm; ++m) {
+        const ali_grid& g = bm[m].grid;
+        for (int k = 0; k < bm[m].n_src; ++k) {
+            const ali_node& sn = srcs[bm[m].src_offset + k];
+            LevelDev L = working_level(bm[m], sn);
+            const int si = sn.i, sj = sn.j;
+            L.d = d; L.stop = stop;
+            L.a_lo = std::max(-W, -si * d);
+            const int a_hi = std::min(W, (g.nx - 1 - si) * d);
+            L.b_lo = std::max(-W, -sj * d);
+            const int b_hi = std::min(W, (g.nz - 1 - sj) * d);
+            L.nx = a_hi - L.a_lo + 1;
+            L.nz = b_hi - L.b_lo + 1;
+            L.node_off = node;
+            L.t_off = node;              // one field per level medium
+            L.unit_off = unit;
+            L.ntx = (L.nx + TX - 1) / TX;
+            ali_medium lm{};
+            lm.grid.nx = L.nx; lm.grid.nz = L.nz; lm.grid.h = g.h / d;
+            lm.mat_offset = bm[m].mat_offset; lm.n_mats = bm[m].n_mats;
+            lm.node_offset = node;
+            lm.src_offset = (int32_t)lv.size(); lm.n_src = 1;
+            lm.rec_offset = 0; lm.n_rec = 0;
+            media.push_back(lm);
+            lsrc.push_back(ali_node{-L.a_lo, -L.b_lo});
+            lv.push_back(L);
+            node += (int64_t)L.nx * L.nz;
+            unit += (uint32_t)(L.ntx * ((L.nz + TZ - 1) / TZ));
+        }
     }
     return lv;
 }
@@ -231,17 +252,19 @@ static void add_stats(ali_solve_stats& acc, const ali_solve_stats& s) {
     acc.converged = acc.converged && s.converged;
 }
 
-// the nested grids on one working grid (the caller's, or its s-fold refinement)
+// the nested grids of every source of a batch of working grids (a caller's medium or its
+// s-fold refinement, or the media of a batch); one relaxation per level for all fields
 template <typename real, typename mreal, typename oreal, typename outreal>
-static ali_status levels_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
-                              const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs, int32_t n_src,
+static ali_status levels_impl(ali_handle* H, const ali_medium* bm, int32_t n_bm, const ali_material* mats,
+                              int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
                               const ali_options& opt, const ali_refine& ref, outreal* d_out,
                               ali_solve_stats* stats, std::chrono::steady_clock::time_point t0) {
-    if (!grid) return H->fail(ALI_EINVAL, "grid is NULL");
     if (!d_out) return H->fail(ALI_EINVAL, "d_T is NULL");
-    const ali_medium mw = single_medium(grid, n_mats, n_src, 0);
-    ali_status st = validate_batch(H, &mw, 1, mats, n_mats, d_mat_id, d_orient, srcs, nullptr, opt.wave);
+    ali_status st = validate_batch(H, bm, n_bm, mats, n_mats, d_mat_id, d_orient, srcs, nullptr, opt.wave);
     if (st != ALI_OK) return st;
+    int64_t n_fields64 = 0, NF = 0;
+    batch_sizes(bm, n_bm, &n_fields64, &NF);
+    const int n_src = (int)n_fields64;      // one level grid per field
     const int nl = ref.n_levels;
     if (nl < 0 || nl > ALI_MAX_LEVELS) return H->fail(ALI_EINVAL, "n_levels out of range [0, ALI_MAX_LEVELS]");
     if (!(ref.start_half_width > 0.0) || !(ref.start_half_width <= 64.0))
@@ -281,7 +304,23 @@ static ali_status levels_impl(ali_handle* H, const ali_grid* grid, const ali_mat
 
     ali_solve_stats acc{};
     acc.converged = 1;
-    const int64_t NW = (int64_t)grid->nx * grid->nz;
+    // the working level: the batch's own fields
+    std::vector<LevelDev> wl;
+    {
+        const std::vector<uint32_t> uoff = unit_offsets(bm, n_bm);
+        int64_t t = 0;
+        for (int m = 0; m < n_bm; ++m)
+            for (int k = 0; k < bm[m].n_src; ++k) {
+                LevelDev L = working_level(bm[m], srcs[bm[m].src_offset + k]);
+                L.d = 1; L.stop = -1;
+                L.a_lo = -L.si; L.b_lo = -L.sj; L.nx = bm[m].grid.nx; L.nz = bm[m].grid.nz;
+                L.node_off = bm[m].node_offset; L.t_off = t;
+                L.unit_off = uoff[wl.size()];
+                L.ntx = (L.nx + TX - 1) / TX;
+                wl.push_back(L);
+                t += (int64_t)L.nx * L.nz;
+            }
+    }
     constexpr bool same_out = std::is_same<real, outreal>::value;
     std::vector<LevelDev> prev;
     const real* Tprev = nullptr;
@@ -297,26 +336,16 @@ static ali_status levels_impl(ali_handle* H, const ali_grid* grid, const ali_mat
         real* T = nullptr;
         int64_t nodes = 0, units = 0;
         if (!last) {
-            lv = level_grids(*grid, srcs, n_src, d, ref.radius[l] * d + 2, ref.radius[l] * d, media, lsrc,
-                             grid->h, n_mats);
+            lv = level_grids(bm, n_bm, srcs, d, ref.radius[l] * d + 2, ref.radius[l] * d, media, lsrc);
             nodes = lv.back().node_off + (int64_t)lv.back().nx * lv.back().nz;
             units = unit_offsets(media.data(), n_src).back();
         } else {
-            // the working grid: every source's field in one medium
-            media.assign(1, mw);
-            lsrc.assign(srcs, srcs + n_src);
-            lv.resize(n_src);
-            const int ntx = (grid->nx + TX - 1) / TX, ntz = (grid->nz + TZ - 1) / TZ;
-            for (int k = 0; k < n_src; ++k) {
-                LevelDev& L = lv[k];
-                L.si = srcs[k].i; L.sj = srcs[k].j; L.d = 1; L.stop = -1;
-                L.a_lo = -L.si; L.b_lo = -L.sj; L.nx = grid->nx; L.nz = grid->nz;
-                L.node_off = 0; L.t_off = (int64_t)k * NW;
-                L.unit_off = (uint32_t)((int64_t)k * ntx * ntz);
-                L.ntx = ntx;
-            }
-            nodes = NW * n_src;
-            units = (int64_t)ntx * ntz * n_src;
+            // the working grids: the batch's media and sources as given
+            media.assign(bm, bm + n_bm);
+            lsrc.clear();
+            lv = wl;
+            nodes = NF;
+            units = unit_offsets(bm, n_bm).back();
         }
         const std::string pp = std::to_string(l & 1);
         void *d_lv = nullptr, *d_T = nullptr, *d_mid = nullptr, *d_ori = nullptr, *d_nA = nullptr;
@@ -341,23 +370,24 @@ static ali_status levels_impl(ali_handle* H, const ali_grid* grid, const ali_mat
                 !H->scratch(("ref_ori" + pp).c_str(), sizeof(oreal) * nodes, &d_ori) ||
                 (opt.d_node_A && !H->scratch(("ref_nA" + pp).c_str(), sizeof(float) * 4 * nodes, &d_nA)))
                 return H->fail(ALI_ENOMEM, "device scratch allocation failed");
-            hipLaunchKernelGGL((k_level_medium<oreal>), g2, dim3(B), 0, S, (const LevelDev*)d_lv, grid->nx, d_mat_id,
+            hipLaunchKernelGGL((k_level_medium<oreal>), g2, dim3(B), 0, S, (const LevelDev*)d_lv, d_mat_id,
                                d_orient, opt.d_node_A, (uint8_t*)d_mid, (oreal*)d_ori, (float*)d_nA);
             lopt.d_node_A = (const float*)d_nA;
             mid = (const uint8_t*)d_mid;
             ori = (const oreal*)d_ori;
         }
         if (l == 0)
-            hipLaunchKernelGGL((k_seed_start<real, oreal>), g2, dim3(B), 0, S, (const LevelDev*)d_lv, grid->nx,
-                               grid->h, ref.start_half_width, (const MatA*)d_A, (const double*)d_gt, n_mats,
-                               d_mat_id, d_orient, opt.d_node_A, T, (uint32_t*)d_fm);
+            hipLaunchKernelGGL((k_seed_start<real, oreal>), g2, dim3(B), 0, S, (const LevelDev*)d_lv,
+                               ref.start_half_width, (const MatA*)d_A, (const double*)d_gt, d_mat_id, d_orient,
+                               opt.d_node_A, T, (uint32_t*)d_fm);
         else
             hipLaunchKernelGGL((k_seed_transfer<real>), g2, dim3(B), 0, S, dprev, Tprev, (const real*)d_stop,
                                (const LevelDev*)d_lv, T, (uint32_t*)d_fm);
         HIPCK(H, hipGetLastError());
         ali_solve_stats ls{};
         st = solve_fields<real, mreal, oreal>(H, media.data(), (int32_t)media.size(), mats, n_mats, mid, ori,
-                                              lsrc.data(), nullptr, lopt, T, &ls, nullptr, (const uint32_t*)d_fm);
+                                              last ? srcs : lsrc.data(), nullptr, lopt, T, &ls, nullptr,
+                                              (const uint32_t*)d_fm);
         if (st != ALI_OK && st != ALI_ENOCONV) return st;
         add_stats(acc, ls);
         if (!last) {
@@ -376,7 +406,7 @@ static ali_status levels_impl(ali_handle* H, const ali_grid* grid, const ali_mat
     HIPCK(H, hipStreamSynchronize(S));
     if (stats) {
         *stats = acc;
-        stats->nodes = NW * n_src;
+        stats->nodes = NF;
         stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     if (!acc.converged) return H->fail(ALI_ENOCONV, "relaxation reached max_sweeps");
@@ -396,11 +426,13 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     ali_default_refine(&ref);
     if (ref_in) ref = *ref_in;
     const int s = ref.subgrid;
-    if (s == 0 || s == 1)
-        return levels_impl<real, mreal, oreal, outreal>(H, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt,
-                                                        ref, d_out, stats, t0);
-    if (s < 0 || s % 2 == 0 || s > 15) return H->fail(ALI_EINVAL, "subgrid must be 0, 1 or odd in [3, 15]");
     if (!grid) return H->fail(ALI_EINVAL, "grid is NULL");
+    if (s == 0 || s == 1) {
+        const ali_medium mw = single_medium(grid, n_mats, n_src, 0);
+        return levels_impl<real, mreal, oreal, outreal>(H, &mw, 1, mats, n_mats, d_mat_id, d_orient, srcs, opt, ref,
+                                                        d_out, stats, t0);
+    }
+    if (s < 0 || s % 2 == 0 || s > 15) return H->fail(ALI_EINVAL, "subgrid must be 0, 1 or odd in [3, 15]");
     if (!d_out) return H->fail(ALI_EINVAL, "d_T is NULL");
     // the caller's medium, sources included, is checked on its own grid first
     const ali_medium mw = single_medium(grid, n_mats, n_src, 0);
@@ -432,8 +464,9 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     HIPCK(H, hipGetLastError());
     ali_options sopt = opt;
     sopt.d_node_A = (const float*)d_nA;
-    st = levels_impl<real, mreal, oreal, real>(H, &gs, mats, n_mats, (const uint8_t*)d_mid, (const oreal*)d_ori,
-                                               ss.data(), n_src, sopt, ref, (real*)d_Ts, stats, t0);
+    const ali_medium ms = single_medium(&gs, n_mats, n_src, 0);
+    st = levels_impl<real, mreal, oreal, real>(H, &ms, 1, mats, n_mats, (const uint8_t*)d_mid, (const oreal*)d_ori,
+                                               ss.data(), sopt, ref, (real*)d_Ts, stats, t0);
     if (st != ALI_OK && st != ALI_ENOCONV) return st;
     const int64_t n_out = NW * n_src;
     hipLaunchKernelGGL((k_subgrid_pick<outreal, real>), dim3((unsigned)((n_out + B - 1) / B)), dim3(B), 0, S,
@@ -521,6 +554,25 @@ static ali_status subgrid_gradient_impl(ali_handle* H, const ali_grid* grid, con
     return st;
 }
 
+// a batch of media: the nested grids of every field, one relaxation per level for all of them
+template <typename real, typename mreal, typename oreal, typename outreal>
+static ali_status batch_refined_impl(ali_handle* H, const ali_medium* media, int32_t n_media,
+                                     const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
+                                     const oreal* d_orient, const ali_node* srcs, const ali_options* opt_in,
+                                     const ali_refine* ref_in, outreal* d_out, ali_solve_stats* stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    ali_options opt;
+    ali_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    ali_refine ref;
+    ali_default_refine(&ref);
+    if (ref_in) ref = *ref_in;
+    if (ref.subgrid != 0 && ref.subgrid != 1)
+        return H->fail(ALI_EUNSUPPORTED, "batch calls take subgrid 0 or 1 (the s-fold medium is a single-medium option)");
+    return levels_impl<real, mreal, oreal, outreal>(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, opt,
+                                                    ref, d_out, stats, t0);
+}
+
 }  // namespace ali
 
 using namespace ali;
@@ -562,6 +614,34 @@ extern "C" ali_status ali_solve_traveltime_refined_f64(ali_handle* h, const ali_
     if (!h) return ALI_EINVAL;
     return refined_impl<double, double, double, double>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt,
                                                         ref, d_T, stats);
+}
+
+extern "C" ali_status ali_solve_batch_refined(ali_handle* h, const ali_medium* media, int32_t n_media,
+                                              const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
+                                              const float* d_orient, const ali_node* srcs, const ali_options* opt,
+                                              const ali_refine* ref, float* d_T, ali_solve_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
+    switch (arith) {
+        case ALI_ARITH_MIXED:   // the fine grids in float64, as in ali_solve_traveltime_refined
+        case ALI_ARITH_F64:
+            return batch_refined_impl<double, double, float, float>(h, media, n_media, mats, n_mats, d_mat_id,
+                                                                    d_orient, srcs, opt, ref, d_T, stats);
+        case ALI_ARITH_F32:
+            return batch_refined_impl<float, float, float, float>(h, media, n_media, mats, n_mats, d_mat_id,
+                                                                  d_orient, srcs, opt, ref, d_T, stats);
+    }
+    return h->fail(ALI_EINVAL, "unknown arith mode");
+}
+
+extern "C" ali_status ali_solve_batch_refined_f64(ali_handle* h, const ali_medium* media, int32_t n_media,
+                                                  const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
+                                                  const double* d_orient, const ali_node* srcs,
+                                                  const ali_options* opt, const ali_refine* ref, double* d_T,
+                                                  ali_solve_stats* stats) {
+    if (!h) return ALI_EINVAL;
+    return batch_refined_impl<double, double, double, double>(h, media, n_media, mats, n_mats, d_mat_id, d_orient,
+                                                              srcs, opt, ref, d_T, stats);
 }
 
 extern "C" ali_status ali_misfit_gradient_subgrid(ali_handle* h, const ali_grid* grid, const ali_material* mats,
