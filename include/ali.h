@@ -266,11 +266,12 @@ void ali_default_refine(ali_refine* r);
    next coarser grid (the nodes that coincide with them keep their times); the grid itself
    comes last.  opt->src_box_radius is not used.  Other arguments, errors and output as
    ali_solve_traveltime; ref == NULL means ali_default_refine.  Arithmetic: MIXED (the
-   default) computes in float64 here (wavefront math included): with float32 wavefront
-   math a near tie in the score of two square stencils on the fine grids can go the other
-   way and move the nodes behind it by up to 4.5e-4 on the 512 x 512 weld, beyond the
-   1e-4 bar; float64 costs about a fifth more.  F32 (everything in float32) is faster and
-   outside the 1e-4 bar.  Scratch grows with
+   default) computes the fine grids in float64 (wavefront math included): with float32
+   wavefront math a near tie in the score of two square stencils on a fine grid can go the
+   other way and move the nodes behind it by up to 4.5e-4 on the 512 x 512 weld, beyond
+   the 1e-4 bar; the grid itself is solved in the mixed arithmetic of ali_solve_traveltime.
+   F64 computes everything in float64; F32 (everything in float32) is faster and outside
+   the 1e-4 bar.  Scratch grows with
    the fine grids (about 23k nodes per source by default).  With ref->subgrid = s > 1 the
    grid above is the s-fold grid (spacing h / s, sources at s i, s j) and the output holds
    every s-th node of its fields; the scratch adds that grid's medium and fields (n_src

@@ -254,7 +254,8 @@ static void add_stats(ali_solve_stats& acc, const ali_solve_stats& s) {
 
 // the nested grids of every source of a batch of working grids (a caller's medium or its
 // s-fold refinement, or the media of a batch); one relaxation per level for all fields
-template <typename real, typename mreal, typename oreal, typename outreal>
+// mreal: the wavefront math of the fine grids; wmreal: that of the working grid
+template <typename real, typename mreal, typename wmreal, typename oreal, typename outreal>
 static ali_status levels_impl(ali_handle* H, const ali_medium* bm, int32_t n_bm, const ali_material* mats,
                               int32_t n_mats, const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs,
                               const ali_options& opt, const ali_refine& ref, outreal* d_out,
@@ -385,9 +386,11 @@ static ali_status levels_impl(ali_handle* H, const ali_medium* bm, int32_t n_bm,
                                (const LevelDev*)d_lv, T, (uint32_t*)d_fm);
         HIPCK(H, hipGetLastError());
         ali_solve_stats ls{};
-        st = solve_fields<real, mreal, oreal>(H, media.data(), (int32_t)media.size(), mats, n_mats, mid, ori,
-                                              last ? srcs : lsrc.data(), nullptr, lopt, T, &ls, nullptr,
-                                              (const uint32_t*)d_fm);
+        st = last ? solve_fields<real, wmreal, oreal>(H, media.data(), (int32_t)media.size(), mats, n_mats, mid, ori,
+                                                      srcs, nullptr, lopt, T, &ls, nullptr, (const uint32_t*)d_fm)
+                  : solve_fields<real, mreal, oreal>(H, media.data(), (int32_t)media.size(), mats, n_mats, mid, ori,
+                                                     lsrc.data(), nullptr, lopt, T, &ls, nullptr,
+                                                     (const uint32_t*)d_fm);
         if (st != ALI_OK && st != ALI_ENOCONV) return st;
         add_stats(acc, ls);
         if (!last) {
@@ -413,7 +416,7 @@ static ali_status levels_impl(ali_handle* H, const ali_medium* bm, int32_t n_bm,
     return ALI_OK;
 }
 
-template <typename real, typename mreal, typename oreal, typename outreal>
+template <typename real, typename mreal, typename wmreal, typename oreal, typename outreal>
 static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_material* mats, int32_t n_mats,
                                const uint8_t* d_mat_id, const oreal* d_orient, const ali_node* srcs, int32_t n_src,
                                const ali_options* opt_in, const ali_refine* ref_in, outreal* d_out,
@@ -429,8 +432,8 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     if (!grid) return H->fail(ALI_EINVAL, "grid is NULL");
     if (s == 0 || s == 1) {
         const ali_medium mw = single_medium(grid, n_mats, n_src, 0);
-        return levels_impl<real, mreal, oreal, outreal>(H, &mw, 1, mats, n_mats, d_mat_id, d_orient, srcs, opt, ref,
-                                                        d_out, stats, t0);
+        return levels_impl<real, mreal, wmreal, oreal, outreal>(H, &mw, 1, mats, n_mats, d_mat_id, d_orient, srcs,
+                                                                opt, ref, d_out, stats, t0);
     }
     if (s < 0 || s % 2 == 0 || s > 15) return H->fail(ALI_EINVAL, "subgrid must be 0, 1 or odd in [3, 15]");
     if (!d_out) return H->fail(ALI_EINVAL, "d_T is NULL");
@@ -465,8 +468,9 @@ static ali_status refined_impl(ali_handle* H, const ali_grid* grid, const ali_ma
     ali_options sopt = opt;
     sopt.d_node_A = (const float*)d_nA;
     const ali_medium ms = single_medium(&gs, n_mats, n_src, 0);
-    st = levels_impl<real, mreal, oreal, real>(H, &ms, 1, mats, n_mats, (const uint8_t*)d_mid, (const oreal*)d_ori,
-                                               ss.data(), sopt, ref, (real*)d_Ts, stats, t0);
+    st = levels_impl<real, mreal, wmreal, oreal, real>(H, &ms, 1, mats, n_mats, (const uint8_t*)d_mid,
+                                                       (const oreal*)d_ori, ss.data(), sopt, ref, (real*)d_Ts, stats,
+                                                       t0);
     if (st != ALI_OK && st != ALI_ENOCONV) return st;
     const int64_t n_out = NW * n_src;
     hipLaunchKernelGGL((k_subgrid_pick<outreal, real>), dim3((unsigned)((n_out + B - 1) / B)), dim3(B), 0, S,
@@ -555,7 +559,7 @@ static ali_status subgrid_gradient_impl(ali_handle* H, const ali_grid* grid, con
 }
 
 // a batch of media: the nested grids of every field, one relaxation per level for all of them
-template <typename real, typename mreal, typename oreal, typename outreal>
+template <typename real, typename mreal, typename wmreal, typename oreal, typename outreal>
 static ali_status batch_refined_impl(ali_handle* H, const ali_medium* media, int32_t n_media,
                                      const ali_material* mats, int32_t n_mats, const uint8_t* d_mat_id,
                                      const oreal* d_orient, const ali_node* srcs, const ali_options* opt_in,
@@ -569,8 +573,8 @@ static ali_status batch_refined_impl(ali_handle* H, const ali_medium* media, int
     if (ref_in) ref = *ref_in;
     if (ref.subgrid != 0 && ref.subgrid != 1)
         return H->fail(ALI_EUNSUPPORTED, "batch calls take subgrid 0 or 1 (the s-fold medium is a single-medium option)");
-    return levels_impl<real, mreal, oreal, outreal>(H, media, n_media, mats, n_mats, d_mat_id, d_orient, srcs, opt,
-                                                    ref, d_out, stats, t0);
+    return levels_impl<real, mreal, wmreal, oreal, outreal>(H, media, n_media, mats, n_mats, d_mat_id, d_orient,
+                                                            srcs, opt, ref, d_out, stats, t0);
 }
 
 }  // namespace ali
@@ -595,14 +599,17 @@ extern "C" ali_status ali_solve_traveltime_refined(ali_handle* h, const ali_grid
     const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
     switch (arith) {
         // float32 wavefront math on the fine grids lets near score ties flip (beyond the
-        // 1e-4 bar on the weld), so the default arithmetic computes them in float64
+        // 1e-4 bar on the weld), so the default arithmetic computes them in float64; the
+        // grid itself keeps the mixed arithmetic of ali_solve_traveltime
         case ALI_ARITH_MIXED:
+            return refined_impl<double, double, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs,
+                                                                     n_src, opt, ref, d_T, stats);
         case ALI_ARITH_F64:
-            return refined_impl<double, double, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
-                                                              opt, ref, d_T, stats);
+            return refined_impl<double, double, double, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs,
+                                                                      n_src, opt, ref, d_T, stats);
         case ALI_ARITH_F32:
-            return refined_impl<float, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src,
-                                                            opt, ref, d_T, stats);
+            return refined_impl<float, float, float, float, float>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs,
+                                                                   n_src, opt, ref, d_T, stats);
     }
     return h->fail(ALI_EINVAL, "unknown arith mode");
 }
@@ -612,8 +619,8 @@ extern "C" ali_status ali_solve_traveltime_refined_f64(ali_handle* h, const ali_
                                                        const ali_node* srcs, int32_t n_src, const ali_options* opt,
                                                        const ali_refine* ref, double* d_T, ali_solve_stats* stats) {
     if (!h) return ALI_EINVAL;
-    return refined_impl<double, double, double, double>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs, n_src, opt,
-                                                        ref, d_T, stats);
+    return refined_impl<double, double, double, double, double>(h, grid, mats, n_mats, d_mat_id, d_orient, srcs,
+                                                                n_src, opt, ref, d_T, stats);
 }
 
 extern "C" ali_status ali_solve_batch_refined(ali_handle* h, const ali_medium* media, int32_t n_media,
@@ -623,13 +630,15 @@ extern "C" ali_status ali_solve_batch_refined(ali_handle* h, const ali_medium* m
     if (!h) return ALI_EINVAL;
     const int arith = opt ? opt->arith : ALI_ARITH_MIXED;
     switch (arith) {
-        case ALI_ARITH_MIXED:   // the fine grids in float64, as in ali_solve_traveltime_refined
+        case ALI_ARITH_MIXED:   // the fine grids in float64 (see ali_solve_traveltime_refined)
+            return batch_refined_impl<double, double, float, float, float>(h, media, n_media, mats, n_mats, d_mat_id,
+                                                                           d_orient, srcs, opt, ref, d_T, stats);
         case ALI_ARITH_F64:
-            return batch_refined_impl<double, double, float, float>(h, media, n_media, mats, n_mats, d_mat_id,
-                                                                    d_orient, srcs, opt, ref, d_T, stats);
+            return batch_refined_impl<double, double, double, float, float>(h, media, n_media, mats, n_mats, d_mat_id,
+                                                                            d_orient, srcs, opt, ref, d_T, stats);
         case ALI_ARITH_F32:
-            return batch_refined_impl<float, float, float, float>(h, media, n_media, mats, n_mats, d_mat_id,
-                                                                  d_orient, srcs, opt, ref, d_T, stats);
+            return batch_refined_impl<float, float, float, float, float>(h, media, n_media, mats, n_mats, d_mat_id,
+                                                                         d_orient, srcs, opt, ref, d_T, stats);
     }
     return h->fail(ALI_EINVAL, "unknown arith mode");
 }
@@ -640,7 +649,7 @@ extern "C" ali_status ali_solve_batch_refined_f64(ali_handle* h, const ali_mediu
                                                   const ali_options* opt, const ali_refine* ref, double* d_T,
                                                   ali_solve_stats* stats) {
     if (!h) return ALI_EINVAL;
-    return batch_refined_impl<double, double, double, double>(h, media, n_media, mats, n_mats, d_mat_id, d_orient,
+    return batch_refined_impl<double, double, double, double, double>(h, media, n_media, mats, n_mats, d_mat_id, d_orient,
                                                               srcs, opt, ref, d_T, stats);
 }
 

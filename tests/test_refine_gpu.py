@@ -6,7 +6,8 @@ the FP64 oracle.
     and for a second level set, sources in the interior and at the edges (clipped fine
     grids), heterogeneous media;
   - without fine grids the seeded path reproduces the straight-ray box solve bitwise;
-  - the float32 entry point's default arithmetic (float64 on the nested grids): within
+  - the float32 entry point's default arithmetic (float64 on the fine grids, mixed on the
+    grid itself): within
     1e-4 relative (the float32 contract) on the 128 x 128 weld and on four sources of the
     512 x 512 weld; pure float32 is reported, not held to the bar;
   - Table 3's set-up (cubic steel, 21 x 21, orientation 0, subgrid sizes 1, 3 and 5 through
@@ -73,9 +74,10 @@ def test_no_levels_is_the_box_solve(solver):
     m = sm.random_medium(60, 44, 0.2e-3, seed=4, n_mats=3)
     sources = [m.sources[0], (2, 40)]
     mid, ori = _dev(m, torch.float32)
-    # the refined entry point's default arithmetic is float64 (the box solve's F64)
+    # without fine grids the refined entry points solve the grid itself in the caller's
+    # arithmetic, as the box solve does
     for R in (0, 2):
-        for ar, br in (("mixed", "f64"), ("f64", "f64"), ("f32", "f32")):
+        for ar, br in (("mixed", "mixed"), ("f64", "f64"), ("f32", "f32")):
             a, _ = solver.solve_refined(m.h, m.mats, mid, ori, sources, levels=(), start_half_width=R + 0.5, arith=ar)
             b, _ = solver.solve(m.h, m.mats, mid, ori, sources, src_box_radius=R, arith=br)
             assert torch.equal(a, b), (R, ar)
@@ -155,10 +157,11 @@ def test_subgrid_refusals(solver):
 
 def test_refined_weld_full_size(solver, orc):
     # float64: element-wise parity.  The float32 entry point's default arithmetic computes
-    # the nested grids in float64 too (with float32 wavefront math a near tie in the score
-    # of two square stencils went the other way for source (508, 0) and moved the nodes
-    # behind it by 4.5e-4), so it is held to the 1e-4 bar on four sources across the top,
-    # that one included; pure float32 is reported, not held to it.
+    # the fine grids in float64 (with float32 wavefront math a near tie in the score of two
+    # square stencils on a fine grid went the other way for source (508, 0) and moved the
+    # nodes behind it by 4.5e-4) and the grid itself in mixed arithmetic, and is held to
+    # the 1e-4 bar on four sources across the top, that one included; pure float32 is
+    # reported, not held to it.
     import torch
     from concurrent.futures import ThreadPoolExecutor
     m = sm.weld_multi()
