@@ -93,3 +93,42 @@ def test_batch_refined_errors(solver):
     # densities that do not divide each other are refused before any device work
     with pytest.raises(AliError):
         solver.solve_batch_refined(b, levels=((9, 2), (5, 5)))
+
+
+def test_batch_refined_node_stiffness(solver):
+    # per-node stiffness equal to every node's material: the same fields as the material
+    # table (the level grids take the stiffness of their own medium's nearest nodes, and
+    # the straight rays that of their source node)
+    import torch
+    from paper_2302_10988_amd import Batch
+    ms = media()
+    for m in ms:
+        A = np.stack([np.array([x["c11"], x["c13"], x["c33"], x["c55"]]) / x["rho"] for x in m.mats])
+        A = A.astype(np.float32)
+        # density 1, so the table's C / rho is the float32 value itself
+        m.mats = [dict(c11=float(a[0]), c13=float(a[1]), c33=float(a[2]), c55=float(a[3]), c44=float(a[3]),
+                       c66=float(a[3]), rho=1.0) for a in A]
+        m.nodeA = A[m.mat_id].reshape(-1, 4)
+    b = Batch(ms)
+    nodeA = torch.from_numpy(np.ascontiguousarray(np.concatenate([m.nodeA for m in ms]))).cuda()
+    print("batch refined, per-node stiffness:", len(ms), "media", flush=True)
+    Tt, _ = solver.solve_batch_refined(b)
+    Tn, st = solver.solve_batch_refined(b, node_A=nodeA)
+    assert st["converged"] == 1 and torch.equal(Tt, Tn)
+
+
+@pytest.mark.parametrize("opt", [{"velocity": "table"}, {"wave": "sh"}])
+def test_batch_refined_modes_equal_per_medium(solver, opt):
+    # the velocity table (each medium's materials in its own range of the table) and the SH
+    # wave reach the level grids of a batch as they reach those of one medium
+    import torch
+    from paper_2302_10988_amd import Batch
+    ms = media()
+    b = Batch(ms)
+    print("batch refined:", opt, flush=True)
+    T, st = solver.solve_batch_refined(b, **opt)
+    assert st["converged"] == 1
+    for m, Tb in zip(ms, b.fields(T)):
+        mid, ori = _dev(m)
+        Tm, _ = solver.solve_refined(m.h, m.mats, mid, ori, m.sources, **opt)
+        assert torch.equal(Tm, Tb), (m.name, opt, (Tm - Tb).abs().max().item())
