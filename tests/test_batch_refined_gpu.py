@@ -132,3 +132,28 @@ def test_batch_refined_modes_equal_per_medium(solver, opt):
         mid, ori = _dev(m)
         Tm, _ = solver.solve_refined(m.h, m.mats, mid, ori, m.sources, **opt)
         assert torch.equal(Tm, Tb), (m.name, opt, (Tm - Tb).abs().max().item())
+
+
+def test_batch_refined_f64_equals_per_medium(solver):
+    # the float64 entry point through the C ABI: float64 orientation and output
+    import torch
+    from paper_2302_10988_amd import Batch, _lib, _refine, default_options
+    ms = media()
+    b = Batch(ms)
+    ori64 = b.orient.double().contiguous()
+    out = torch.empty(b.field_nodes, dtype=torch.float64, device="cuda")
+    opt = default_options()
+    stats = _lib.SolveStats()
+    ref = _refine(((27, 1), (9, 6), (3, 13)), 0.5, 1)
+    print("batch refined f64:", len(ms), "media", flush=True)
+    solver._sync_stream()
+    st = solver._lib.ali_solve_batch_refined_f64(solver._h, b.media, b.n_media, b.mats, b.n_mats,
+                                                 b.mat_id.data_ptr(), ori64.data_ptr(), b.srcs, ctypes.byref(opt),
+                                                 ctypes.byref(ref), out.data_ptr(), ctypes.byref(stats))
+    torch.cuda.synchronize()
+    assert st == 0 and stats.converged == 1
+    for m, Tb in zip(ms, b.fields(out)):
+        mid, _ = _dev(m)
+        ori = torch.from_numpy(np.ascontiguousarray(m.orient)).float().double().cuda()
+        Tm, _ = solver.solve_refined(m.h, m.mats, mid, ori, m.sources, precision="f64")
+        assert torch.equal(Tm, Tb), (m.name, (Tm - Tb).abs().max().item())
