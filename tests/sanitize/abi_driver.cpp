@@ -2,7 +2,7 @@
 // host code carries AddressSanitizer and UndefinedBehaviorSanitizer (device code is built
 // as usual).  Without a GPU it checks the calls that need none and that ali_create fails
 // cleanly; with one it runs forward solves (mixed, float64, allocation-free, persistent,
-// nested source grids, batch), gradients (also on the refined medium and with the velocity
+// nested source grids, batch, batch with nested grids), gradients (also on the refined medium and with the velocity
 // table), rays, the autotuner and error paths, and checks each status.  Exits 0 when every
 // status is the expected one; the sanitizers abort on the first host memory or
 // undefined-behaviour error.
@@ -148,6 +148,13 @@ int main() {
         media[m].n_rec = 3;
     }
     OK(ali_solve_batch(h, media.data(), 2, mats.data(), 2, d_id, d_th, src.data(), nullptr, d_T, &st));
+    OK(ali_solve_batch_refined(h, media.data(), 2, mats.data(), 2, d_id, d_th, src.data(), nullptr, nullptr, d_T,
+                               &st));
+    ali_refine r3;
+    ali_default_refine(&r3);
+    r3.subgrid = 3;
+    CHECK(ali_solve_batch_refined(h, media.data(), 2, mats.data(), 2, d_id, d_th, src.data(), nullptr, &r3, d_T,
+                                  &st) == ALI_EUNSUPPORTED);
     OK(ali_misfit_gradient_batch(h, media.data(), 2, mats.data(), 2, d_id, d_th, src.data(), rec.data(), d_obs,
                                  nullptr, d_trec, d_loss, d_dth, &ast));
     ali_options tuned = o;
