@@ -189,7 +189,8 @@ __global__ void k_subgrid_pick(int nx, int64_t nw, int64_t n_out, int nx_s, int6
     out[q] = (outreal)Ts[k * n_s + (int64_t)j * s * nx_s + (int64_t)i * s];
 }
 
-// the working medium of every field of a batch (fields in medium order, then source order)
+// the level record of a field of medium m with its source and its working medium filled in
+// (the batch's fields come in medium order, then source order)
 static LevelDev working_level(const ali_medium& m, const ali_node& src) {
     LevelDev L{};
     L.si = src.i; L.sj = src.j;
